@@ -1,0 +1,86 @@
+"""Planted mistakes in the oracle (on the CPU only): each mutant must make at
+least one pin fail, which shows that the pins can see that kind of error."""
+
+import numpy as np
+import pytest
+
+from oracle import ckks as C
+from tests import test_oracle_ring as TR
+from tests import test_oracle_scheme as TS
+
+
+def _tiny():
+    P = C.Params(**TS.TINY)
+    import synth as S
+    return P, S.key_draws(3, P.n, P.q)
+
+
+def _expect_fail(fn, *args):
+    with pytest.raises(AssertionError):
+        fn(*args)
+
+
+def test_mutant_rescale_without_rounding_offset(monkeypatch):
+    real = C.rescale
+    monkeypatch.setattr(C, "rescale", lambda P, x, mode="round": real(P, x, mode="floor"))
+    _expect_fail(TR.test_rescale_matches_bigint_division, "round")
+
+
+def test_mutant_automorphism_without_sign(monkeypatch):
+    def bad(a, kappa, mods, n):
+        out = np.empty_like(a)
+        for j in range(n):
+            out[:, (j * kappa) % (2 * n) % n] = a[:, j]
+        return out
+    monkeypatch.setattr(C, "automorphism", bad)
+    _expect_fail(TR.test_automorphism_is_substitution, 3)
+
+
+def test_mutant_tensor_dropped_cross_term(monkeypatch):
+    def bad(params, x, y):
+        mods = params.q[:x.level]
+        return (C.ring_mul(params, x.c0, y.c0, mods), C.ring_mul(params, x.c0, y.c1, mods),
+                C.ring_mul(params, x.c1, y.c1, mods))
+    monkeypatch.setattr(C, "tensor", bad)
+    _expect_fail(TS.test_tensor_exact, _tiny())
+
+
+def test_mutant_gadget_on_wrong_digit(monkeypatch):
+    real = C.switch_key
+
+    def bad(params, s, s_prime, a, e):
+        k = real(params, s, s_prime, a, e)
+        k.b = k.b[::-1]
+        k.a = k.a[::-1]
+        return k
+    monkeypatch.setattr(C, "switch_key", bad)
+    _expect_fail(TS.test_switch_key_gadget_exact, _tiny(), "relin")
+
+
+def test_mutant_moddown_missing_inverse(monkeypatch):
+    def bad(params, acc, level):
+        qs = params.q[:level]
+        conv = C.base_convert(acc[level:], params.p, qs, params.n)
+        return C.sub(acc[:level], conv, qs)
+    monkeypatch.setattr(C, "mod_down", bad)
+    _expect_fail(TS.test_key_switch_error_bound, _tiny(), 3)
+
+
+def test_mutant_encode_wrong_generator(monkeypatch):
+    def bad(n, n_slots):
+        e = np.empty(n_slots, dtype=np.int64)
+        x = 1
+        for j in range(n_slots):
+            e[j] = x
+            x = x * 3 % (2 * n)
+        return e
+    monkeypatch.setattr(C, "slot_exponents", bad)
+    _expect_fail(TS.test_c1_rotate, TS.c1_env(), 3)
+
+
+def test_mutant_decrypt_sign(monkeypatch):
+    def bad(params, s, ct):
+        mods = params.q[:ct.level]
+        return C.sub(ct.c0, C.ring_mul(params, ct.c1, C.rns_from_int(s, mods), mods), mods)
+    monkeypatch.setattr(C, "decrypt", bad)
+    _expect_fail(TS.test_encrypt_decrypt_exact, _tiny())
