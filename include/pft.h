@@ -1,0 +1,185 @@
+/*
+ * pft.h -- C ABI of libpft: RNS-CKKS primitives of PrivFT (arXiv:1908.06972)
+ * as HIP kernels for AMD Instinct MI355X (gfx950).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Status: every int-returning call returns PFT_OK (0) or a negative PFT_E*
+ *   code; pft_last_error() then returns a message (thread-local, owned by
+ *   the library, valid until the next failing call on that thread).
+ * Ring: R_q = Z_q[X]/(X^N+1), N = 2^log_n, residues are uint64 < q < 2^60
+ *   (Sec. 3.4, the CKKS levelled scheme).  The chain q_0 > q_1 > ... > q_{L-1}
+ *   is strictly descending so that the prime dropped by RESCALE is the
+ *   smallest (Sec. 5.1, the paragraph before Eq. (1)); K special primes
+ *   p_0..p_{K-1} follow for key switching.
+ * Level: a ciphertext at level l uses q_0..q_{l-1} (1 <= l <= L).
+ * Device layout: a ciphertext is [2][level][N] uint64 in device memory, limb
+ *   i of both polynomials reduced mod q_i, in the NTT domain: entry k of a
+ *   limb holds the evaluation at psi^(2*brv(k)+1), psi the primitive 2N-th
+ *   root g^((q-1)/2N) with g the smallest quadratic non-residue.  Host-side
+ *   import/export and decrypt outputs use coefficient form.
+ * Memory: ciphertext and plaintext storage is caller-owned device memory
+ *   (e.g. torch tensors); the library never frees it.  Keys, tables and
+ *   scratch are library-owned and freed with their context.
+ * Streams: a context enqueues all work on the HIP stream given at creation;
+ *   calls that return host data synchronize that stream.  A context is not
+ *   thread-safe; use one per host thread/stream.
+ * Randomness: KEYGEN and ENC take their random polynomials as arguments
+ *   (ternary secret, Gaussian errors, uniform masks), so results are a pure
+ *   function of the inputs.
+ */
+#ifndef PFT_H
+#define PFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    PFT_OK = 0,
+    PFT_EINVAL = -1,  /* bad pointer, size or shape */
+    PFT_EPARAM = -2,  /* parameter set unsupported or primes not found */
+    PFT_ELEVEL = -3,  /* level mismatch or level out of range */
+    PFT_ESCALE = -4,  /* scales differ by more than 2^-40 (relative) */
+    PFT_ENOKEY = -5,  /* missing public/relinearisation/rotation key */
+    PFT_ENOMEM = -6,  /* device allocation failed */
+    PFT_EHIP = -7     /* a HIP runtime call failed; message has the HIP error */
+};
+
+typedef struct pft_params pft_params; /* opaque, host */
+typedef struct pft_ctx pft_ctx;       /* opaque, owns device tables and keys */
+
+/* SETUP (Sec. 3.4; parameter guidance Sec. 6.4).  Primes are the largest
+ * primes = 1 mod 2N of the given bit sizes: q_0 has q0_bits bits, q_1..q_{L-1}
+ * the next L-1 largest with q_bits bits (descending), the K special primes
+ * the largest unused with p_bits bits.  All bit sizes must be <= 60.
+ * 10 <= log_n <= 16, 1 <= dnum <= n_q, n_p >= 1. */
+typedef struct pft_param_spec {
+    uint32_t log_n;
+    uint32_t n_q;     /* L */
+    uint32_t q0_bits;
+    uint32_t q_bits;
+    uint32_t n_p;     /* K */
+    uint32_t p_bits;
+    uint32_t dnum;    /* digits of hybrid key switching, alpha = ceil(L/dnum) */
+    uint32_t reserved;
+    double scale;     /* default encoding scale Delta */
+} pft_param_spec;
+
+int pft_params_create(const pft_param_spec* spec, pft_params** out);
+void pft_params_destroy(pft_params* params);
+/* Copies q_0..q_{L-1} and p_0..p_{K-1} (host arrays of L and K entries). */
+int pft_params_moduli(const pft_params* params, uint64_t* q, uint64_t* p);
+/* N, L, K, dnum, alpha in that order (host array of 5). */
+int pft_params_dims(const pft_params* params, uint32_t* dims);
+
+const char* pft_last_error(void);
+
+/* One context per device and stream.  stream may be NULL (the null stream). */
+int pft_ctx_create(const pft_params* params, int device, void* hip_stream, pft_ctx** out);
+void pft_ctx_destroy(pft_ctx* ctx);
+int pft_ctx_synchronize(pft_ctx* ctx);
+
+/* ---- ciphertexts ------------------------------------------------------- */
+typedef struct pft_ct {
+    uint64_t* data;   /* device, >= 2*level*N uint64, layout [2][level][N], NTT domain */
+    uint32_t level;
+    uint32_t reserved;
+    double scale;
+} pft_ct;
+
+/* Plaintext already in the NTT domain on the device: [level][N]. */
+typedef struct pft_pt {
+    uint64_t* data;
+    uint32_t level;
+    uint32_t reserved;
+    double scale;
+} pft_pt;
+
+/* ---- KEYGEN (Sec. 3.4), randomness supplied by the caller (host memory) --
+ * s: ternary secret, N int64 in {-1,0,1}.  Must be called first. */
+int pft_set_secret(pft_ctx* ctx, const int64_t* s);
+/* Public key b = -a s + e over q_0..q_{L-1}.  a: [L][N] uniform residues in
+ * coefficient form (a[i][k] < q_i); e: [N] small errors. */
+int pft_gen_public_key(pft_ctx* ctx, const uint64_t* a, const int64_t* e);
+/* Switching keys of hybrid key switching (the paper cites key switching for
+ * relinearisation and rotation, Sec. 3.4 and its footnote).  For each digit
+ * j < dnum: a[j]: [L+K][N] uniform residues in coefficient form (rows 0..L-1
+ * mod q_i, rows L..L+K-1 mod p_k), e[j]: [N] errors.  The key is
+ * b_j = -a_j s + e_j + [limb in digit j] (P mod q_limb) s' on all L+K limbs,
+ * with s' = s^2 (relinearisation) or s(X^kappa), kappa = 5^step mod 2N
+ * (rotation of the slots by `step` to the left).  Keys stay in device memory. */
+int pft_gen_relin_key(pft_ctx* ctx, const uint64_t* a, const int64_t* e);
+int pft_gen_rotation_key(pft_ctx* ctx, int32_t step, const uint64_t* a, const int64_t* e);
+/* Number of device bytes held by keys and tables. */
+int pft_ctx_device_bytes(const pft_ctx* ctx, uint64_t* bytes);
+
+/* ---- ENC / DEC (Sec. 3.4) ---------------------------------------------
+ * ENC of the integer plaintext m ([N] int64, host) at `level`:
+ * (b v + e0 + m, a v + e1) with v ternary, e0/e1 errors ([N] int64, host).
+ * out->data must be caller-allocated device memory of 2*level*N uint64;
+ * the call sets out->level and out->scale. */
+int pft_encrypt(pft_ctx* ctx, const int64_t* m, uint32_t level, double scale,
+                const int64_t* v, const int64_t* e0, const int64_t* e1, pft_ct* out);
+/* DEC: c0 + c1 s mod q_i, written to host memory [level][N] in coefficient
+ * form.  Synchronizes the context stream. */
+int pft_decrypt(pft_ctx* ctx, const pft_ct* ct, uint64_t* out);
+/* Coefficient-form transfer of a whole ciphertext, host [2][level][N].
+ * export synchronizes; import sets ct->level/scale from the arguments. */
+int pft_ct_export(pft_ctx* ctx, const pft_ct* ct, uint64_t* host);
+int pft_ct_import(pft_ctx* ctx, const uint64_t* host, uint32_t level, double scale, pft_ct* ct);
+/* Integer plaintext polynomial m ([N] int64, host) to an NTT-domain
+ * plaintext at `level` (pt->data: caller device memory of level*N). */
+int pft_pt_from_coeffs(pft_ctx* ctx, const int64_t* m, uint32_t level, double scale, pft_pt* pt);
+
+/* ---- homomorphic operations (Sec. 3.4), all asynchronous ----------------
+ * Batched forms take arrays of n descriptors; every element is independent.
+ * out may alias an input for add/add_plain/mul_plain/rescale-free ops, not
+ * for mul_relin or rotate. */
+int pft_add(pft_ctx* ctx, const pft_ct* a, const pft_ct* b, pft_ct* out);           /* HADD */
+int pft_add_plain(pft_ctx* ctx, const pft_ct* a, const pft_pt* p, pft_ct* out);     /* HADDPLAIN */
+int pft_mul_plain(pft_ctx* ctx, const pft_ct* a, const pft_pt* p, pft_ct* out);     /* HMULPLAIN */
+/* HMUL followed by relinearisation (Table 2's HMUL+REL), no rescale. */
+int pft_mul_relin(pft_ctx* ctx, const pft_ct* a, const pft_ct* b, pft_ct* out);
+int pft_mul_relin_batch(pft_ctx* ctx, uint32_t n, const pft_ct* a, const pft_ct* b, pft_ct* out);
+/* RESCALE by q_{level-1} (Sec. 5.1, Eq. (1) and Alg. 3).  mode 0 rounds
+ * (adds (q-1)/2 before the exact division, the RESCALE of Sec. 3.4), mode 1
+ * floors (Alg. 3 as printed).  out->data needs 2*(level-1)*N uint64 and must
+ * not alias in. */
+int pft_rescale(pft_ctx* ctx, const pft_ct* in, uint32_t mode, pft_ct* out);
+int pft_rescale_batch(pft_ctx* ctx, uint32_t n, const pft_ct* in, uint32_t mode, pft_ct* out);
+/* Keep limbs 0..level-1 (exact).  out may alias in. */
+int pft_mod_drop(pft_ctx* ctx, const pft_ct* in, uint32_t level, pft_ct* out);
+/* ROTATE (Sec. 3.4): X -> X^kappa, kappa = 5^step mod 2N, then key switching
+ * with the rotation key of `step` (PFT_ENOKEY if absent).  Slot j of the
+ * result holds slot j+step of the input. */
+int pft_rotate(pft_ctx* ctx, const pft_ct* in, int32_t step, pft_ct* out);
+int pft_rotate_batch(pft_ctx* ctx, uint32_t n, const pft_ct* in, int32_t step, pft_ct* out);
+/* TotalSum (Sec. 4.1, Alg. 2): ct += ROTATE(ct, 2^i) for i < log2(n_slots);
+ * needs the rotation keys 1, 2, 4, ..., n_slots/2.  out may alias in. */
+int pft_total_sum(pft_ctx* ctx, const pft_ct* in, uint32_t n_slots, pft_ct* out);
+
+/* ---- transforms on raw RNS polynomials ---------------------------------
+ * data: device [n_polys][n_limbs][N], limb i of every polynomial mod q_i
+ * (n_limbs <= L).  Forward maps coefficient form to the NTT domain of the
+ * header comment, inverse maps back.  In place. */
+int pft_ntt_forward(pft_ctx* ctx, uint64_t* data, uint32_t n_polys, uint32_t n_limbs);
+int pft_ntt_inverse(pft_ctx* ctx, uint64_t* data, uint32_t n_polys, uint32_t n_limbs);
+
+/* ---- client-side ENCODE / DECODE on the host (Sec. 3.4; CPU per Sec. 5.1)
+ * encode: slots z_j = re[j] + i im[j], j < n_slots <= N/2, to the integer
+ * polynomial round((2 scale/N) Re sum_j z_j zeta^(-(5^j) k)), zeta = e^{i pi/N};
+ * PFT_EINVAL if a coefficient would exceed 2^62 in magnitude.
+ * decode: residues [level][N] (coefficient form, e.g. from pft_decrypt),
+ * centred CRT lift, then z_j = (1/scale) sum_k mu_k zeta^((5^j) k). */
+int pft_encode(const pft_params* params, const double* re, const double* im, uint32_t n_slots,
+               double scale, int64_t* out);
+int pft_decode(const pft_params* params, const uint64_t* residues, uint32_t level, double scale,
+               uint32_t n_slots, double* re, double* im);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PFT_H */

@@ -1,0 +1,262 @@
+"""Python front end of libpft: Params / Context / Ciphertext.
+
+Marshalling only: device buffers are torch tensors on the GPU (int64 storage
+of uint64 residues), every computation is a libpft call on torch's current
+HIP stream.
+"""
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import native as N
+
+
+class Params:
+    """SETUP (Sec. 3.4): ring degree, prime chain, special primes, dnum, scale."""
+
+    def __init__(self, log_n, n_q, q0_bits, q_bits, n_p, p_bits, dnum, scale):
+        lib = N.load()
+        spec = N.ParamSpec(log_n, n_q, q0_bits, q_bits, n_p, p_bits, dnum, 0, float(scale))
+        h = ctypes.c_void_p()
+        N.check(lib.pft_params_create(ctypes.byref(spec), ctypes.byref(h)))
+        self.handle = h
+        self.log_n = log_n
+        self.n = 1 << log_n
+        self.L = n_q
+        self.K = n_p
+        self.dnum = dnum
+        self.scale = float(scale)
+        q = np.zeros(n_q, dtype=np.uint64)
+        p = np.zeros(n_p, dtype=np.uint64)
+        N.check(lib.pft_params_moduli(h, N.u64p(q), N.u64p(p)))
+        self.q = [int(x) for x in q]
+        self.p = [int(x) for x in p]
+        dims = np.zeros(5, dtype=np.uint32)
+        N.check(lib.pft_params_dims(h, dims.ctypes.data_as(N._u32p)))
+        self.alpha = int(dims[4])
+
+    @classmethod
+    def from_config(cls, cfg):
+        return cls(cfg.log_n, cfg.n_q, cfg.q0_bits, cfg.q_bits, cfg.n_p, cfg.p_bits, cfg.dnum, cfg.scale)
+
+    def key_moduli(self):
+        return self.q + self.p
+
+    def __del__(self):
+        if getattr(self, "handle", None) is not None and N._lib is not None:
+            N._lib.pft_params_destroy(self.handle)
+            self.handle = None
+
+    # client-side ENCODE / DECODE on the host
+    def encode(self, z, scale=None) -> np.ndarray:
+        z = np.asarray(z, dtype=np.complex128)
+        re = np.ascontiguousarray(z.real)
+        im = np.ascontiguousarray(z.imag)
+        out = np.empty(self.n, dtype=np.int64)
+        N.check(N.load().pft_encode(self.handle, N.dblp(re), N.dblp(im), len(z),
+                                    float(self.scale if scale is None else scale), N.i64p(out)))
+        return out
+
+    def decode(self, residues, scale, n_slots=None) -> np.ndarray:
+        res = np.ascontiguousarray(residues, dtype=np.uint64)
+        n_slots = self.n // 2 if n_slots is None else n_slots
+        re = np.empty(n_slots)
+        im = np.empty(n_slots)
+        N.check(N.load().pft_decode(self.handle, N.u64p(res), res.shape[0], float(scale), n_slots,
+                                    N.dblp(re), N.dblp(im)))
+        return re + 1j * im
+
+
+class Ciphertext:
+    """[2][level][N] residues in the NTT domain, in a torch tensor on the GPU."""
+
+    def __init__(self, data: torch.Tensor, level: int, scale: float):
+        self.data = data
+        self.level = level
+        self.scale = scale
+
+    def desc(self) -> N.CtDesc:
+        return N.CtDesc(self.data.data_ptr(), self.level, 0, self.scale)
+
+    def sync_from(self, d: N.CtDesc):
+        self.level = d.level
+        self.scale = d.scale
+        return self
+
+
+class Plaintext(Ciphertext):
+    """[level][N] NTT-domain plaintext on the GPU."""
+
+
+def _i64(a):
+    return np.ascontiguousarray(a, dtype=np.int64)
+
+
+def _u64(a):
+    return np.ascontiguousarray(a, dtype=np.uint64)
+
+
+class Context:
+    def __init__(self, params: Params, device: int = 0):
+        self.params = params
+        self.device = torch.device("cuda", device)
+        self.lib = N.load()
+        h = ctypes.c_void_p()
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        N.check(self.lib.pft_ctx_create(params.handle, device, ctypes.c_void_p(stream), ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            self.lib.pft_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
+
+    def synchronize(self):
+        N.check(self.lib.pft_ctx_synchronize(self.handle))
+
+    def device_bytes(self) -> int:
+        b = ctypes.c_uint64()
+        N.check(self.lib.pft_ctx_device_bytes(self.handle, ctypes.byref(b)))
+        return b.value
+
+    # ---- buffers
+    def empty_ct(self, level: int, scale: float = 0.0) -> Ciphertext:
+        t = torch.empty((2, level, self.params.n), dtype=torch.int64, device=self.device)
+        return Ciphertext(t, level, scale)
+
+    def empty_pt(self, level: int) -> Plaintext:
+        t = torch.empty((level, self.params.n), dtype=torch.int64, device=self.device)
+        return Plaintext(t, level, 0.0)
+
+    # ---- KEYGEN (randomness as arguments)
+    def set_secret(self, s):
+        N.check(self.lib.pft_set_secret(self.handle, N.i64p(_i64(s))))
+
+    def gen_public_key(self, a, e):
+        N.check(self.lib.pft_gen_public_key(self.handle, N.u64p(_u64(a)), N.i64p(_i64(e))))
+
+    def gen_relin_key(self, a, e):
+        N.check(self.lib.pft_gen_relin_key(self.handle, N.u64p(_u64(a)), N.i64p(_i64(e))))
+
+    def gen_rotation_key(self, step, a, e):
+        N.check(self.lib.pft_gen_rotation_key(self.handle, int(step), N.u64p(_u64(a)), N.i64p(_i64(e))))
+
+    # ---- ENC / DEC
+    def encrypt(self, m, level, scale, v, e0, e1) -> Ciphertext:
+        ct = self.empty_ct(level)
+        d = ct.desc()
+        N.check(self.lib.pft_encrypt(self.handle, N.i64p(_i64(m)), level, float(scale), N.i64p(_i64(v)),
+                                     N.i64p(_i64(e0)), N.i64p(_i64(e1)), ctypes.byref(d)))
+        return ct.sync_from(d)
+
+    def decrypt(self, ct: Ciphertext) -> np.ndarray:
+        out = np.empty((ct.level, self.params.n), dtype=np.uint64)
+        d = ct.desc()
+        N.check(self.lib.pft_decrypt(self.handle, ctypes.byref(d), N.u64p(out)))
+        return out
+
+    def export(self, ct: Ciphertext) -> np.ndarray:
+        out = np.empty((2, ct.level, self.params.n), dtype=np.uint64)
+        d = ct.desc()
+        N.check(self.lib.pft_ct_export(self.handle, ctypes.byref(d), N.u64p(out)))
+        return out
+
+    def import_(self, host, level, scale) -> Ciphertext:
+        ct = self.empty_ct(level)
+        d = ct.desc()
+        N.check(self.lib.pft_ct_import(self.handle, N.u64p(_u64(host)), level, float(scale), ctypes.byref(d)))
+        return ct.sync_from(d)
+
+    def plaintext(self, m, level, scale) -> Plaintext:
+        pt = self.empty_pt(level)
+        d = pt.desc()
+        N.check(self.lib.pft_pt_from_coeffs(self.handle, N.i64p(_i64(m)), level, float(scale), ctypes.byref(d)))
+        return pt.sync_from(d)
+
+    # ---- homomorphic operations
+    def _binary(self, fn, a, b, out):
+        da, db, do = a.desc(), b.desc(), out.desc()
+        N.check(fn(self.handle, ctypes.byref(da), ctypes.byref(db), ctypes.byref(do)))
+        return out.sync_from(do)
+
+    def add(self, a, b, out=None):
+        return self._binary(self.lib.pft_add, a, b, out or self.empty_ct(a.level))
+
+    def add_plain(self, a, p, out=None):
+        return self._binary(self.lib.pft_add_plain, a, p, out or self.empty_ct(a.level))
+
+    def mul_plain(self, a, p, out=None):
+        return self._binary(self.lib.pft_mul_plain, a, p, out or self.empty_ct(a.level))
+
+    def mul_relin(self, a, b, out=None):
+        return self._binary(self.lib.pft_mul_relin, a, b, out or self.empty_ct(a.level))
+
+    def _arr(self, cts):
+        arr = (N.CtDesc * len(cts))()
+        for i, c in enumerate(cts):
+            arr[i] = c.desc()
+        return arr
+
+    def mul_relin_batch(self, a, b, out=None):
+        out = out or [self.empty_ct(x.level) for x in a]
+        A, B, O = self._arr(a), self._arr(b), self._arr(out)
+        N.check(self.lib.pft_mul_relin_batch(self.handle, len(a), A, B, O))
+        return [o.sync_from(O[i]) for i, o in enumerate(out)]
+
+    def rescale(self, a, mode=0, out=None):
+        out = out or self.empty_ct(a.level - 1)
+        da, do = a.desc(), out.desc()
+        N.check(self.lib.pft_rescale(self.handle, ctypes.byref(da), mode, ctypes.byref(do)))
+        return out.sync_from(do)
+
+    def rescale_batch(self, a, mode=0, out=None):
+        out = out or [self.empty_ct(x.level - 1) for x in a]
+        A, O = self._arr(a), self._arr(out)
+        N.check(self.lib.pft_rescale_batch(self.handle, len(a), A, mode, O))
+        return [o.sync_from(O[i]) for i, o in enumerate(out)]
+
+    def mod_drop(self, a, level, out=None):
+        out = out or self.empty_ct(level)
+        da, do = a.desc(), out.desc()
+        N.check(self.lib.pft_mod_drop(self.handle, ctypes.byref(da), level, ctypes.byref(do)))
+        return out.sync_from(do)
+
+    def rotate(self, a, step, out=None):
+        out = out or self.empty_ct(a.level)
+        da, do = a.desc(), out.desc()
+        N.check(self.lib.pft_rotate(self.handle, ctypes.byref(da), int(step), ctypes.byref(do)))
+        return out.sync_from(do)
+
+    def rotate_batch(self, a, step, out=None):
+        out = out or [self.empty_ct(x.level) for x in a]
+        A, O = self._arr(a), self._arr(out)
+        N.check(self.lib.pft_rotate_batch(self.handle, len(a), A, int(step), O))
+        return [o.sync_from(O[i]) for i, o in enumerate(out)]
+
+    def total_sum(self, a, n_slots, out=None):
+        out = out or self.empty_ct(a.level)
+        da, do = a.desc(), out.desc()
+        N.check(self.lib.pft_total_sum(self.handle, ctypes.byref(da), n_slots, ctypes.byref(do)))
+        return out.sync_from(do)
+
+    def ntt_forward(self, data: torch.Tensor, n_limbs: int):
+        n_polys = data.numel() // (n_limbs * self.params.n)
+        N.check(self.lib.pft_ntt_forward(self.handle, ctypes.c_void_p(data.data_ptr()), n_polys, n_limbs))
+
+    def ntt_inverse(self, data: torch.Tensor, n_limbs: int):
+        n_polys = data.numel() // (n_limbs * self.params.n)
+        N.check(self.lib.pft_ntt_inverse(self.handle, ctypes.c_void_p(data.data_ptr()), n_polys, n_limbs))
+
+
+def to_device_u64(a: np.ndarray, device) -> torch.Tensor:
+    """Host uint64 array -> GPU int64 tensor with the same bits."""
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint64).view(np.int64)).to(device)
+
+
+def to_host_u64(t: torch.Tensor) -> np.ndarray:
+    return t.detach().cpu().numpy().view(np.uint64)

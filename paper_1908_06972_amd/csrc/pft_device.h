@@ -1,0 +1,110 @@
+// pft_device.h -- device-side data structures and 64-bit modular arithmetic
+// for gfx950.  Residues are uint64 below primes q < 2^60.
+//
+// Three reductions are used, chosen per operand kind:
+//   * Shoup (constant multiplier w with w' = floor(w 2^64 / q)): twiddles and
+//     per-prime constants; result in [0, 2q) before the optional final
+//     subtraction.
+//   * Montgomery REDC (R = 2^64) for sums of products whose constant factor
+//     was stored pre-multiplied by R: base-conversion matrices, switching keys.
+//   * Barrett (mu = floor(2^(2b)/q), b = bit length of q) for products of two
+//     variable residues (the HMUL tensor, NTT-domain plaintext products).
+// All three are built from 64x64 products that the compiler lowers to
+// v_mul_lo_u32 / v_mul_hi_u32 / v_mad_u64_u32, which issue at full rate on
+// gfx950.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define PFT_MAX_POLYS 64
+
+struct DevMod {
+    uint64_t q;
+    uint64_t two_q;
+    uint64_t mu;          // floor(2^(2b) / q)
+    uint64_t mont_neg_qinv;  // -q^-1 mod 2^64
+    uint64_t n_inv, n_inv_sh;      // N^-1 mod q and its Shoup companion
+    uint64_t last_inv, last_inv_sh; // psi^-brv(1) * N^-1: fused last inverse stage
+    uint32_t bits;
+    uint32_t pad;
+};
+
+struct TwPair {
+    uint64_t w;
+    uint64_t wp;  // floor(w * 2^64 / q)
+};
+
+// A set of RNS polynomials processed by one launch.  Limb i (0 <= i <
+// n_limbs) of polynomial p sits at row r(i) = i + (i >= gap_at ? gap_len : 0)
+// of ptr[p] (rows are N words apart); row r is reduced modulo modulus index
+// r < split ? off0 + r : off1 + (r - split).
+struct PolyBatch {
+    uint64_t* ptr[PFT_MAX_POLYS];
+    uint32_t n_polys;
+    uint32_t n_limbs;
+    uint32_t gap_at, gap_len;
+    uint32_t split, off0, off1;
+    uint32_t pad;
+};
+
+__device__ __forceinline__ uint32_t pb_row(const PolyBatch& b, uint32_t i) {
+    return i + (i >= b.gap_at ? b.gap_len : 0u);
+}
+__device__ __forceinline__ uint32_t pb_mod(const PolyBatch& b, uint32_t row) {
+    return row < b.split ? b.off0 + row : b.off1 + (row - b.split);
+}
+
+__device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) { return __umul64hi(a, b); }
+
+// a*w mod q in [0, 2q) for any a < 2^64 (Shoup).
+__device__ __forceinline__ uint64_t shoup_lazy(uint64_t a, uint64_t w, uint64_t wp, uint64_t q) {
+    return a * w - mulhi64(a, wp) * q;
+}
+__device__ __forceinline__ uint64_t shoup(uint64_t a, uint64_t w, uint64_t wp, uint64_t q) {
+    uint64_t r = shoup_lazy(a, w, wp, q);
+    return r >= q ? r - q : r;
+}
+
+// (hi:lo) * 2^-64 mod q for hi:lo < q * 2^64; result in [0, q).
+__device__ __forceinline__ uint64_t mont_redc(uint64_t lo, uint64_t hi, uint64_t q, uint64_t neg_qinv) {
+    uint64_t m = lo * neg_qinv;
+    uint64_t r = hi + mulhi64(m, q) + (lo != 0 ? 1u : 0u);
+    return r >= q ? r - q : r;
+}
+
+// 128-bit accumulator helpers
+struct Acc128 {
+    uint64_t lo, hi;
+};
+__device__ __forceinline__ void mac128(Acc128& acc, uint64_t a, uint64_t b) {
+    uint64_t lo = a * b;
+    uint64_t hi = mulhi64(a, b);
+    acc.lo += lo;
+    acc.hi += hi + (acc.lo < lo ? 1u : 0u);
+}
+
+// a*b mod q for a, b < q (Barrett, HAC 14.42 with base 2).
+__device__ __forceinline__ uint64_t mul_barrett(uint64_t a, uint64_t b, const DevMod& m) {
+    uint64_t lo = a * b, hi = mulhi64(a, b);
+    uint32_t bits = m.bits;
+    uint64_t x1 = (lo >> (bits - 1)) | (hi << (65 - bits));
+    uint64_t plo = x1 * m.mu, phi = mulhi64(x1, m.mu);
+    uint64_t qh = (plo >> (bits + 1)) | (phi << (63 - bits));
+    uint64_t r = lo - qh * m.q;
+    if (r >= m.q) r -= m.q;
+    if (r >= m.q) r -= m.q;
+    return r;
+}
+
+__device__ __forceinline__ uint64_t add_mod(uint64_t a, uint64_t b, uint64_t q) {
+    uint64_t r = a + b;
+    return r >= q ? r - q : r;
+}
+__device__ __forceinline__ uint64_t sub_mod(uint64_t a, uint64_t b, uint64_t q) {
+    return a >= b ? a - b : a + q - b;
+}
+
+// index of the bit-reversal of k over log_n bits
+__device__ __forceinline__ uint32_t brev_n(uint32_t k, uint32_t log_n) {
+    return __brev(k) >> (32 - log_n);
+}

@@ -1,0 +1,250 @@
+"""Bit-exact parity of the HIP path (through the C ABI) with the oracle.
+
+Every ciphertext the library produces is exported in coefficient form and
+compared residue by residue with the oracle's result on the same seeded
+draws.  Levels are chosen so that the last key-switching digit is both full
+and ragged (level not a multiple of alpha)."""
+
+import numpy as np
+import pytest
+
+import synth as S
+from oracle import _ring
+from oracle import ckks as C
+from tests.gpu_env import World
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+# ---------------------------------------------------------------------------
+# the transform (row a1/a2): forward/inverse NTT against the oracle definition
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("log_n", [12, 13, 14, 15, 16])
+def test_ntt_forward_inverse(torch_cuda, log_n):
+    import paper_1908_06972_amd.ckks as L
+    lp = L.Params(log_n, 5, 60, 50, 1, 60, 2, 2 ** 40)
+    op = C.Params(log_n, 5, 60, 50, 1, 60, 2, 2 ** 40)
+    assert lp.q == op.q
+    ctx = L.Context(lp)
+    n, n_polys, n_limbs = 1 << log_n, 3, 5
+    g = np.random.default_rng(log_n)
+    host = np.stack([np.stack([g.integers(0, q, n, dtype=np.uint64) for q in op.q]) for _ in range(n_polys)])
+    dev = L.to_device_u64(host, ctx.device)
+    ctx.ntt_forward(dev, n_limbs)
+    fwd = L.to_host_u64(dev)
+    for p in range(n_polys):
+        for i, q in enumerate(op.q):
+            want = np.empty(n, dtype=np.uint64)
+            _ring.lib().or_ntt_fast(_ring.ptr(np.ascontiguousarray(host[p, i])), _ring.ptr(want), n, q,
+                                    op.psi[q])
+            assert np.array_equal(fwd[p, i], want), (p, i)
+    ctx.ntt_inverse(dev, n_limbs)
+    assert np.array_equal(L.to_host_u64(dev), host)
+
+
+def test_ntt_extreme_values(torch_cuda):
+    """All-zero, all q-1 and a single spike: exercises the lazy ranges."""
+    import paper_1908_06972_amd.ckks as L
+    lp = L.Params(16, 2, 60, 60, 1, 60, 1, 2 ** 40)
+    op = C.Params(16, 2, 60, 60, 1, 60, 1, 2 ** 40)
+    ctx = L.Context(lp)
+    n = 1 << 16
+    host = np.zeros((3, 2, n), dtype=np.uint64)
+    for i, q in enumerate(op.q):
+        host[1, i] = q - 1
+        host[2, i, 12345] = q - 1
+    dev = L.to_device_u64(host, ctx.device)
+    ctx.ntt_forward(dev, 2)
+    fwd = L.to_host_u64(dev)
+    for p in range(3):
+        for i, q in enumerate(op.q):
+            want = np.empty(n, dtype=np.uint64)
+            _ring.lib().or_ntt_fast(_ring.ptr(np.ascontiguousarray(host[p, i])), _ring.ptr(want), n, q, op.psi[q])
+            assert np.array_equal(fwd[p, i], want)
+    ctx.ntt_inverse(dev, 2)
+    assert np.array_equal(L.to_host_u64(dev), host)
+
+
+# ---------------------------------------------------------------------------
+# worlds per configuration
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def c1(torch_cuda):
+    return World(S.CONFIGS["C1"], seed=1, rot_steps=(1, 2, -1, 5))
+
+
+@pytest.fixture(scope="module")
+def c2(torch_cuda):
+    return World(S.CONFIGS["C2"], seed=2, rot_steps=(1, 3))
+
+
+@pytest.fixture(scope="module")
+def c3(torch_cuda):
+    return World(S.CONFIGS["C3"], seed=3, rot_steps=(1,))
+
+
+def _world(request, name):
+    return request.getfixturevalue(name)
+
+
+@pytest.mark.parametrize("name,levels", [("c1", (2, 1)), ("c2", (8, 5, 3, 1)), ("c3", (24, 23))])
+def test_encrypt_decrypt_parity(request, name, levels):
+    w = _world(request, name)
+    m = w.random_plain(11)
+    for lvl in levels:
+        g, o = w.encrypt_pair(m, lvl, 100 + lvl)
+        w.assert_same(g, o)
+        assert np.array_equal(w.ctx.decrypt(g), C.decrypt(w.op, w.kd.s, o))
+
+
+@pytest.mark.parametrize("name,levels", [("c1", (2, 1)), ("c2", (8, 7, 4, 3)), ("c3", (24, 19))])
+def test_mul_relin_parity(request, name, levels):
+    w = _world(request, name)
+    for lvl in levels:
+        ga, oa = w.encrypt_pair(w.random_plain(21), lvl, 200 + lvl)
+        gb, ob = w.encrypt_pair(w.random_plain(22), lvl, 300 + lvl)
+        w.assert_same(w.ctx.mul_relin(ga, gb), C.hmul_relin(w.op, oa, ob, w.rlk))
+
+
+@pytest.mark.parametrize("name,levels", [("c1", (2,)), ("c2", (8, 3, 2)), ("c3", (24, 13))])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_rescale_parity(request, name, levels, mode):
+    w = _world(request, name)
+    for lvl in levels:
+        g, o = w.encrypt_pair(w.random_plain(31), lvl, 400 + lvl)
+        w.assert_same(w.ctx.rescale(g, mode=mode), C.rescale(w.op, o, mode="round" if mode == 0 else "floor"))
+
+
+@pytest.mark.parametrize("name,steps,levels", [("c1", (1, -1, 5), (2, 1)), ("c2", (1, 3), (8, 5)),
+                                               ("c3", (1,), (24,))])
+def test_rotate_parity(request, name, steps, levels):
+    w = _world(request, name)
+    for lvl in levels:
+        g, o = w.encrypt_pair(w.random_plain(41), lvl, 500 + lvl)
+        for st in steps:
+            w.assert_same(w.ctx.rotate(g, st), C.rotate(w.op, o, st, w.rot[st]))
+
+
+def test_total_sum_parity(c1):
+    w = c1
+    g, o = w.encrypt_pair(w.random_plain(51), 2, 600)
+    keys = {s: w.rot[s] for s in (1, 2)}
+    w.assert_same(w.ctx.total_sum(g, 4), C.total_sum(w.op, o, 4, keys))
+
+
+def test_plain_ops_parity(c2):
+    w = c2
+    lvl = 6
+    g, o = w.encrypt_pair(w.random_plain(61), lvl, 700)
+    g2, o2 = w.encrypt_pair(w.random_plain(62), lvl, 701)
+    m = w.random_plain(63, bound=2 ** 30)
+    pt = w.ctx.plaintext(m, lvl, 2.0 ** 30)
+    w.assert_same(w.ctx.add(g, g2), C.hadd(w.op, o, o2))
+    w.assert_same(w.ctx.mul_plain(g, pt), C.hmul_plain(w.op, o, m, 2.0 ** 30))
+    pt_s = w.ctx.plaintext(m, lvl, w.op.scale)
+    w.assert_same(w.ctx.add_plain(g, pt_s), C.hadd_plain(w.op, o, m))
+    w.assert_same(w.ctx.mod_drop(g, 3), C.mod_drop(w.op, o, 3))
+
+
+def test_import_export_roundtrip(c2):
+    w = c2
+    g = np.random.default_rng(5)
+    host = np.stack([np.stack([g.integers(0, q, w.n, dtype=np.uint64) for q in w.op.q[:4]]) for _ in range(2)])
+    ct = w.ctx.import_(host, 4, 1.0)
+    assert np.array_equal(w.ctx.export(ct), host)
+
+
+def test_batch_equals_singles(c2):
+    w = c2
+    cts = [w.encrypt_pair(w.random_plain(70 + i), lvl, 800 + i) for i, lvl in enumerate((8, 6, 5))]
+    others = [w.encrypt_pair(w.random_plain(80 + i), lvl, 900 + i) for i, lvl in enumerate((8, 6, 5))]
+    batch = w.ctx.mul_relin_batch([c[0] for c in cts], [c[0] for c in others])
+    for (ga, oa), (gb, ob), gbat in zip(cts, others, batch):
+        w.assert_same(gbat, C.hmul_relin(w.op, oa, ob, w.rlk))
+
+
+def test_chain_parity_c2(c2):
+    """encrypt -> HMult+relin -> rescale -> rotate -> HMult+relin -> rescale."""
+    w = c2
+    ga, oa = w.encrypt_pair(w.random_plain(91), 8, 1001)
+    gb, ob = w.encrypt_pair(w.random_plain(92), 8, 1002)
+    g = w.ctx.rescale(w.ctx.mul_relin(ga, gb))
+    o = C.rescale(w.op, C.hmul_relin(w.op, oa, ob, w.rlk))
+    g = w.ctx.rotate(g, 3)
+    o = C.rotate(w.op, o, 3, w.rot[3])
+    g2, o2 = w.encrypt_pair(w.random_plain(93), 7, 1003)
+    g = w.ctx.rescale(w.ctx.mul_relin(g, g2))
+    o = C.rescale(w.op, C.hmul_relin(w.op, o, o2, w.rlk))
+    w.assert_same(g, o)
+
+
+def test_slots_c1(c1):
+    """Decoded slots of encrypt -> HMult+relin -> rescale -> decrypt, each side
+    encoding z1, z2 with its own encoder: both track z1*z2 within the noise
+    bound, so they agree with each other within twice that bound."""
+    from tests import noise
+    w = c1
+    n = w.n
+    z1 = S.slots_uniform(S.rng(101), n // 2)
+    z2 = S.slots_uniform(S.rng(102), n // 2)
+    d1, d2 = S.enc_draws(1001, n), S.enc_draws(1002, n)
+    g1 = w.ctx.encrypt(w.lp.encode(z1), 2, w.op.scale, d1.v, d1.e0, d1.e1)
+    g2 = w.ctx.encrypt(w.lp.encode(z2), 2, w.op.scale, d2.v, d2.e0, d2.e1)
+    gp = w.ctx.rescale(w.ctx.mul_relin(g1, g2))
+    lib_slots = w.lp.decode(w.ctx.decrypt(gp), gp.scale)
+    o1 = C.encrypt(w.op, w.pk, C.encode(z1, n, w.op.scale), 2, d1.v, d1.e0, d1.e1, w.op.scale)
+    o2 = C.encrypt(w.op, w.pk, C.encode(z2, n, w.op.scale), 2, d2.v, d2.e0, d2.e1, w.op.scale)
+    op_ = C.rescale(w.op, C.hmul_relin(w.op, o1, o2, w.rlk))
+    ora_slots = C.decode(C.decrypt(w.op, w.kd.s, op_), w.op.q[:1], n, op_.scale, n // 2)
+    h = 2 * n / 3
+    fresh = noise.fresh(n, h, h, w.op.scale) + n / w.op.scale
+    bound = 2 * np.sqrt(2) * fresh + noise.rescale_round(n, h, gp.scale) + 1e-6
+    assert np.max(np.abs(lib_slots - z1 * z2)) <= bound
+    assert np.max(np.abs(ora_slots - z1 * z2)) <= bound
+    assert np.max(np.abs(lib_slots - ora_slots)) <= 2 * bound
+
+
+def test_slots_c3_within_2_20(c3):
+    """At the large ring (scale 2^50) the decoded product agrees with the
+    oracle's decoded product within 2^-20."""
+    w = c3
+    n = w.n
+    z1 = S.slots_unit(S.rng(303), n // 2)
+    z2 = S.slots_unit(S.rng(304), n // 2)
+    d1, d2 = S.enc_draws(3001, n), S.enc_draws(3002, n)
+    g1 = w.ctx.encrypt(w.lp.encode(z1), 24, w.op.scale, d1.v, d1.e0, d1.e1)
+    g2 = w.ctx.encrypt(w.lp.encode(z2), 24, w.op.scale, d2.v, d2.e0, d2.e1)
+    gp = w.ctx.rescale(w.ctx.mul_relin(g1, g2))
+    lib_slots = w.lp.decode(w.ctx.decrypt(gp), gp.scale)
+    o1 = C.encrypt(w.op, w.pk, C.encode(z1, n, w.op.scale), 24, d1.v, d1.e0, d1.e1, w.op.scale)
+    o2 = C.encrypt(w.op, w.pk, C.encode(z2, n, w.op.scale), 24, d2.v, d2.e0, d2.e1, w.op.scale)
+    op_ = C.rescale(w.op, C.hmul_relin(w.op, o1, o2, w.rlk))
+    ora_slots = C.decode(C.decrypt(w.op, w.kd.s, op_), w.op.q[:23], n, op_.scale, n // 2)
+    assert np.max(np.abs(lib_slots - ora_slots)) <= 2.0 ** -20
+    assert np.max(np.abs(lib_slots - z1 * z2)) <= 2.0 ** -20
+
+
+def test_errors(c1):
+    import paper_1908_06972_amd.native as N
+    w = c1
+    g, _ = w.encrypt_pair(w.random_plain(1), 2, 1)
+    h, _ = w.encrypt_pair(w.random_plain(2), 1, 2)
+    with pytest.raises(N.PftError) as e:
+        w.ctx.rotate(g, 7)
+    assert e.value.code == N.PFT_ENOKEY
+    with pytest.raises(N.PftError) as e:
+        w.ctx.add(g, h)
+    assert e.value.code == N.PFT_ELEVEL
+    with pytest.raises(N.PftError) as e:
+        w.ctx.rescale(h)
+    assert e.value.code == N.PFT_ELEVEL
+    with pytest.raises(N.PftError) as e:
+        w.ctx.mul_relin(g, g, out=g)
+    assert e.value.code == N.PFT_EINVAL
