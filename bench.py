@@ -1,0 +1,293 @@
+#!/usr/bin/env python3
+"""Throughput of the CKKS hot path on one MI355X.
+
+Workload (the large-ring configuration the headline metric is quoted on):
+N = 2^16, L = 24 ciphertext primes (60-bit q_0, then 50-bit), K = 6 special
+60-bit primes, dnum = 4, scale 2^50; a batch of 16 ciphertexts with
+unit-modulus complex slots.  One step = for every ciphertext of the batch a
+depth-8 chain c <- RESCALE(HMult+relin(c, c)) (levels 24 -> 16) followed by
+rotate-and-sum over all 2^15 slots (15 rotations + 15 additions).  That is
+128 HMult+relin, 128 RESCALE and 240 ROTATE per step; inputs are resident in
+HBM before the timed region starts.
+
+`value` is whole-job HMult+relin/s: 128 * steps / timed seconds (the time
+includes the rescales and rotations of the job).  Rates of the individual
+operations, timed separately on the same data, are reported under
+"breakdown"; the dominant kernel family's per-launch time is measured with
+HIP events on the stream the kernels run on and reported under "roofline".
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch B]
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, AMD published
+ALU_PEAK_GOPS = 256 * 64 * 2.4  # int32 VALU lane-ops/s in G: 256 CUs x 64 lanes x 2.4 GHz
+FAMILIES = ["ntt_fwd_pass", "ntt_inv_pass", "modup_bconv", "key_inner_product", "moddown_bconv",
+            "moddown_final", "tensor", "automorphism", "rescale", "elementwise"]
+KERNEL_NAMES = {0: "k_ntt_pass<8, false>", 1: "k_ntt_pass<8, true>", 2: "k_modup", 3: "k_key_inner",
+                4: "k_moddown_conv", 5: "k_moddown_final", 6: "k_tensor", 7: "k_automorphism",
+                8: "k_rescale_expand/k_rescale_final"}
+CHAIN_DEPTH = 8
+ROT_SLOTS = 1 << 15
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=int(os.environ.get("WORLD_SIZE", "1")))
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=0,
+                    help="run only this many untimed steps (for rocprofv3) and exit")
+    return ap.parse_args()
+
+
+def prof_read(ctx, kid):
+    import ctypes
+    from paper_1908_06972_amd import native as N
+    ms, cnt, by, op = ctypes.c_double(), ctypes.c_uint64(), ctypes.c_double(), ctypes.c_double()
+    N.check(ctx.lib.pft_prof_read(ctx.handle, kid, ctypes.byref(ms), ctypes.byref(cnt), ctypes.byref(by),
+                                  ctypes.byref(op)))
+    return ms.value, cnt.value, by.value, op.value
+
+
+def prof_enable(ctx, mask):
+    from paper_1908_06972_amd import native as N
+    N.check(ctx.lib.pft_prof_enable(ctx.handle, mask))
+
+
+def setup(batch):
+    import numpy as np
+
+    import synth as S
+    from paper_1908_06972_amd import ckks as L
+
+    cfg = S.CONFIGS["C3"]
+    lp = L.Params.from_config(cfg)
+    ctx = L.Context(lp, 0)
+    n = lp.n
+    t0 = time.time()
+    kd = S.key_draws(1, n, lp.q)
+    ctx.set_secret(kd.s)
+    ctx.gen_public_key(kd.pk_a, kd.pk_e)
+    a, e = S.switch_key_draws(1, 0, n, lp.key_moduli(), lp.dnum)
+    ctx.gen_relin_key(a, e)
+    steps = [1 << i for i in range(15)]
+    for st in steps:
+        a, e = S.switch_key_draws(1, 1000 + st, n, lp.key_moduli(), lp.dnum)
+        ctx.gen_rotation_key(st, a, e)
+    del a, e
+    log("keys: rlk + %d rotation keys resident, %.2f GiB device, %.1fs" % (len(steps), ctx.device_bytes() / 2 ** 30,
+                                                                            time.time() - t0))
+    cts = []
+    for i in range(batch):
+        z = S.slots_unit(S.rng(303 + i), n // 2)
+        d = S.enc_draws(3000 + i, n)
+        cts.append(ctx.encrypt(lp.encode(z), lp.L, lp.scale, d.v, d.e0, d.e1))
+    ctx.synchronize()
+    return lp, ctx, kd, cts
+
+
+def job_step(ctx, cts):
+    """One step of the workload over the batch; returns the final ciphertexts."""
+    cur = cts
+    for _ in range(CHAIN_DEPTH):
+        cur = ctx.rescale_batch(ctx.mul_relin_batch(cur, cur))
+    return ctx.total_sum_batch(cur, ROT_SLOTS)
+
+
+def timed(fn, reps, sync):
+    sync()
+    t = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    sync()
+    return (time.perf_counter() - t) / reps
+
+
+def cpu_baseline():
+    """The oracle (never tuned) on a bounded sample of the same job: two
+    HMult+relin, two RESCALE and two ROTATE of one N = 2^16, L = 24
+    ciphertext, extrapolated to the job's operation counts."""
+    import numpy as np
+
+    import synth as S
+    from oracle import ckks as C
+
+    cfg = S.CONFIGS["C3"]
+    P = C.Params.from_config(cfg)
+    C.set_mul_mode(1)
+    n = P.n
+    kd = S.key_draws(1, n, P.q)
+    pk = C.public_key(P, kd.s, kd.pk_a, kd.pk_e)
+    a, e = S.switch_key_draws(1, 0, n, P.key_moduli(), P.dnum)
+    rlk = C.relin_key(P, kd.s, a, e)
+    a, e = S.switch_key_draws(1, 1001, n, P.key_moduli(), P.dnum)
+    rk = C.rotation_key(P, kd.s, 1, a, e)
+    m = S.plaintext_coeffs(S.rng(5), n, 2 ** 50)
+    d = S.enc_draws(3000, n)
+    ct = C.encrypt(P, pk, m, P.L, d.v, d.e0, d.e1, P.scale)
+    th = tr = tt = 0.0
+    for _ in range(2):
+        t = time.perf_counter()
+        pr = C.hmul_relin(P, ct, ct, rlk)
+        th += time.perf_counter() - t
+        t = time.perf_counter()
+        ct = C.rescale(P, pr)
+        tr += time.perf_counter() - t
+        t = time.perf_counter()
+        rot = C.rotate(P, ct, 1, rk)
+        C.hadd(P, ct, rot)
+        tt += time.perf_counter() - t
+    th, tr, tt = th / 2, tr / 2, tt / 2
+    per_ct = CHAIN_DEPTH * (th + tr) + 15 * tt
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": CHAIN_DEPTH / per_ct,
+        "unit": "HMult+relin/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": "2 HMult+relin, 2 RESCALE, 2 ROTATE+HADD of one N=2^16 L=24 ciphertext (oracle, %d OpenMP "
+                  "threads); whole-job rate = 8 / (8 (t_hmult + t_rescale) + 15 t_rotate_add) with t_hmult=%.3fs "
+                  "t_rescale=%.3fs t_rotate_add=%.3fs" % (threads, th, tr, tt),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (DESIGN.md describes how the "
+              "work would shard); rerun with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+
+    lp, ctx, kd, cts = setup(args.batch)
+    sync = torch.cuda.synchronize
+
+    if args.profile_steps:
+        for i in range(args.profile_steps):
+            job_step(ctx, cts)
+            sync()
+            log("profile step %d done" % i)
+        return
+
+    # rank kernel families over one untimed step
+    prof_enable(ctx, (1 << len(FAMILIES)) - 1)
+    job_step(ctx, cts)
+    sync()
+    totals = {k: prof_read(ctx, k) for k in range(len(FAMILIES))}
+    prof_enable(ctx, 0)
+    step_total = sum(v[0] for v in totals.values())
+    dom = max(totals, key=lambda k: totals[k][0])
+    log("kernel families over one step: " + ", ".join(
+        "%s %.1fms (%d)" % (FAMILIES[k], v[0], v[1]) for k, v in sorted(totals.items(), key=lambda kv: -kv[1][0])
+        if v[1]))
+
+    for i in range(args.warmup):
+        job_step(ctx, cts)
+        sync()
+        log("warmup step %d done" % i)
+
+    # timed region: only the dominant family is bracketed with events
+    prof_enable(ctx, 1 << dom)
+    sync()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        job_step(ctx, cts)
+        sync()
+        log("timed step %d done" % i)
+    sync()
+    elapsed = time.perf_counter() - t0
+    d_ms, d_cnt, d_bytes, d_ops = prof_read(ctx, dom)
+    prof_enable(ctx, 0)
+
+    hmults = args.batch * CHAIN_DEPTH * args.steps
+    ms_per_step = 1000.0 * elapsed / args.steps
+    value = hmults / elapsed
+
+    # separately timed per-operation rates at level 24 on the same batch
+    reps = 3
+    t_mul = timed(lambda: ctx.mul_relin_batch(cts, cts), reps, sync)
+    t_rot = timed(lambda: ctx.rotate_batch(cts, 1), reps, sync)
+    t_rs = timed(lambda: ctx.rescale_batch(cts), reps, sync)
+    polys = torch.empty((2 * args.batch, lp.L, lp.n), dtype=torch.int64, device="cuda")
+    for i, c in enumerate(cts):
+        polys[2 * i:2 * i + 2].copy_(c.data)
+    t_ntt = timed(lambda: ctx.ntt_forward(polys, lp.L), reps, sync)
+    t_intt = timed(lambda: ctx.ntt_inverse(polys, lp.L), reps, sync)
+    breakdown = {
+        "hmult_relin_per_s": args.batch / t_mul,
+        "rotate_per_s": args.batch / t_rot,
+        "rescale_per_s": args.batch / t_rs,
+        "ntt_per_s": 2 * args.batch / t_ntt,
+        "intt_per_s": 2 * args.batch / t_intt,
+        "limb_ntt_per_s": 2 * args.batch * lp.L / t_ntt,
+        "note": "level 24, batch of %d, per-operation loops after the timed region; ntt = forward NTT of one "
+                "24-limb polynomial" % args.batch,
+    }
+
+    avg_ms = d_ms / max(d_cnt, 1)
+    gbs = d_bytes / (d_ms * 1e-3) / 1e9 if d_ms > 0 else 0.0
+    roofline = {
+        "kernel": KERNEL_NAMES.get(dom, FAMILIES[dom]),
+        "family": FAMILIES[dom],
+        "bound": "hbm",
+        "achieved": round(gbs, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(gbs / HBM_PEAK_GBS, 4),
+        "traffic": None,
+        "avg_launch_us": round(1000.0 * avg_ms, 2),
+        "launches": d_cnt,
+        "alg_bytes_per_launch": d_bytes / max(d_cnt, 1),
+        "alg_ops_per_launch": d_ops / max(d_cnt, 1),
+        "share_of_step": round(totals[dom][0] / step_total, 3) if step_total else None,
+    }
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle sample)...")
+        cpu = cpu_baseline()
+
+    out = {
+        "metric": "HMult+relin/s and NTT/s at N=2^16,L=24; p50/p99 encrypted-inference latency",
+        "value": round(value, 2),
+        "unit": "HMult+relin/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "large ring: N=2^16, L=24 (+K=6, dnum=4), scale 2^50, batch %d; depth-8 "
+                               "HMult+relin+rescale chain then rotate-and-sum over 2^15 slots" % args.batch,
+                   "global_batch": args.batch, "log_n": 16, "levels": lp.L, "special_primes": lp.K, "dnum": lp.dnum},
+        "breakdown": breakdown,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

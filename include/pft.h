@@ -136,8 +136,10 @@ int pft_pt_from_coeffs(pft_ctx* ctx, const int64_t* m, uint32_t level, double sc
 
 /* ---- homomorphic operations (Sec. 3.4), all asynchronous ----------------
  * Batched forms take arrays of n descriptors; every element is independent.
- * out may alias an input for add/add_plain/mul_plain/rescale-free ops, not
- * for mul_relin or rotate. */
+ * Elements of equal level are processed together, up to 64 per launch, so
+ * that one launch fills the GPU and reads each key once per batch.
+ * out may alias an input for add, add_plain, mul_plain, mod_drop and
+ * total_sum, not for mul_relin, rescale or rotate. */
 int pft_add(pft_ctx* ctx, const pft_ct* a, const pft_ct* b, pft_ct* out);           /* HADD */
 int pft_add_plain(pft_ctx* ctx, const pft_ct* a, const pft_pt* p, pft_ct* out);     /* HADDPLAIN */
 int pft_mul_plain(pft_ctx* ctx, const pft_ct* a, const pft_pt* p, pft_ct* out);     /* HMULPLAIN */
@@ -160,6 +162,7 @@ int pft_rotate_batch(pft_ctx* ctx, uint32_t n, const pft_ct* in, int32_t step, p
 /* TotalSum (Sec. 4.1, Alg. 2): ct += ROTATE(ct, 2^i) for i < log2(n_slots);
  * needs the rotation keys 1, 2, 4, ..., n_slots/2.  out may alias in. */
 int pft_total_sum(pft_ctx* ctx, const pft_ct* in, uint32_t n_slots, pft_ct* out);
+int pft_total_sum_batch(pft_ctx* ctx, uint32_t n, const pft_ct* in, uint32_t n_slots, pft_ct* out);
 
 /* ---- transforms on raw RNS polynomials ---------------------------------
  * data: device [n_polys][n_limbs][N], limb i of every polynomial mod q_i
@@ -167,6 +170,20 @@ int pft_total_sum(pft_ctx* ctx, const pft_ct* in, uint32_t n_slots, pft_ct* out)
  * header comment, inverse maps back.  In place. */
 int pft_ntt_forward(pft_ctx* ctx, uint64_t* data, uint32_t n_polys, uint32_t n_limbs);
 int pft_ntt_inverse(pft_ctx* ctx, uint64_t* data, uint32_t n_polys, uint32_t n_limbs);
+
+/* ---- per-kernel timing ------------------------------------------------
+ * pft_prof_enable brackets every launch of the selected kernel families
+ * (bit k of mask = family k; 0 turns timing off) with HIP events recorded on
+ * the context stream, and clears previous records.  pft_prof_read
+ * synchronizes and returns, for family `kid`, the summed event time, the
+ * number of launches, and the summed algorithmic HBM bytes and algorithmic
+ * operations (butterflies for the transforms, 64-bit modular multiply-adds
+ * otherwise) of those launches.  Families: 0 forward NTT pass, 1 inverse NTT
+ * pass, 2 ModUp base conversion, 3 key inner product, 4 ModDown base
+ * conversion, 5 ModDown final scaling, 6 HMUL tensor, 7 automorphism,
+ * 8 rescale, 9 other elementwise. */
+int pft_prof_enable(pft_ctx* ctx, uint32_t mask);
+int pft_prof_read(pft_ctx* ctx, uint32_t kid, double* total_ms, uint64_t* launches, double* bytes, double* ops);
 
 /* ---- client-side ENCODE / DECODE on the host (Sec. 3.4; CPU per Sec. 5.1)
  * encode: slots z_j = re[j] + i im[j], j < n_slots <= N/2, to the integer

@@ -244,6 +244,12 @@ class Context:
         N.check(self.lib.pft_total_sum(self.handle, ctypes.byref(da), n_slots, ctypes.byref(do)))
         return out.sync_from(do)
 
+    def total_sum_batch(self, a, n_slots, out=None):
+        out = out or [self.empty_ct(x.level) for x in a]
+        A, O = self._arr(a), self._arr(out)
+        N.check(self.lib.pft_total_sum_batch(self.handle, len(a), A, n_slots, O))
+        return [o.sync_from(O[i]) for i, o in enumerate(out)]
+
     def ntt_forward(self, data: torch.Tensor, n_limbs: int):
         n_polys = data.numel() // (n_limbs * self.params.n)
         N.check(self.lib.pft_ntt_forward(self.handle, ctypes.c_void_p(data.data_ptr()), n_polys, n_limbs))

@@ -144,7 +144,52 @@ struct SwitchKeyDev {
     uint64_t* data = nullptr;  // [dnum][2][L+K][N], NTT domain, times 2^64 mod m
 };
 
+// HIP-event bracketing of kernel families on the context stream.
+struct EventProf : ProfHook {
+    hipStream_t st = nullptr;
+    uint32_t mask = 0;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    struct Rec {
+        int kid;
+        hipEvent_t a, b;
+        double bytes, ops;
+    };
+    std::vector<Rec> recs;
+    hipEvent_t open[PK_COUNT] = {};
+    hipEvent_t get() {
+        if (used == pool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+    bool on(int kid) const { return (mask >> kid) & 1u; }
+    void begin(int kid) override {
+        if (!on(kid)) return;
+        open[kid] = get();
+        if (open[kid]) (void)hipEventRecord(open[kid], st);
+    }
+    void end(int kid, double bytes, double ops) override {
+        if (!on(kid) || !open[kid]) return;
+        hipEvent_t b = get();
+        if (!b) return;
+        (void)hipEventRecord(b, st);
+        recs.push_back(Rec{kid, open[kid], b, bytes, ops});
+        open[kid] = nullptr;
+    }
+    void reset() {
+        recs.clear();
+        used = 0;
+    }
+    ~EventProf() override {
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    }
+};
+
 struct pft_ctx {
+    EventProf prof;
     const pft_params* P = nullptr;
     int device = 0;
     hipStream_t stream = nullptr;
@@ -155,7 +200,8 @@ struct pft_ctx {
     TwPair* to_mont = nullptr;       // [L+K]: 2^64 mod m as Shoup pairs
     std::vector<void*> allocs;
     uint64_t device_bytes = 0;
-    uint64_t* s = nullptr;   // [L+K][N] secret, NTT domain
+    uint64_t* s = nullptr;        // [L+K][N] secret, NTT domain
+    uint64_t* s_prime = nullptr;  // [L+K][N] scratch for s^2 / s(X^kappa) during key generation
     uint64_t* pk = nullptr;  // [2][L][N] (b, a), NTT domain
     SwitchKeyDev rlk;
     std::map<int32_t, SwitchKeyDev> rot;  // keyed by step mod N/2
@@ -301,6 +347,7 @@ extern "C" int pft_ctx_create(const pft_params* P, int device, void* stream, pft
     c->P = P;
     c->device = device;
     c->stream = (hipStream_t)stream;
+    c->prof.st = c->stream;
     int r = build_tables(c);
     if (r) {
         pft_ctx_destroy(c);
@@ -332,41 +379,83 @@ extern "C" int pft_ctx_device_bytes(const pft_ctx* c, uint64_t* bytes) {
 }
 
 // ---------------------------------------------------------------------------
-// batch descriptors
+// launch descriptors
 // ---------------------------------------------------------------------------
-// n_polys polynomials of n_limbs consecutive rows starting at row `first`,
-// rows [0, split) mod q_row, rows >= split mod p_(row - split).
-static PolyBatch pb_make(const pft_params* P, std::initializer_list<uint64_t*> ptrs, uint32_t n_limbs,
-                         uint32_t first = 0, uint32_t split = ~0u) {
-    PolyBatch b{};
+// Up to eight polynomials of n_limbs rows starting at row `first`; rows below
+// `split` are q-limbs, the others special limbs.
+static SmallBatch sb(const pft_params* P, std::initializer_list<uint64_t*> ptrs, uint32_t n_limbs, uint32_t first = 0,
+                     uint32_t split = ~0u) {
+    SmallBatch b{};
     uint32_t i = 0;
     for (uint64_t* p : ptrs) b.ptr[i++] = p;
     b.n_polys = i;
     b.n_limbs = n_limbs;
-    b.gap_at = 0;
-    b.gap_len = first;
+    b.first = first;
     b.split = split;
     b.off0 = 0;
     b.off1 = P->L;
     return b;
 }
 
-static PolyBatch pb_rows(const pft_params* P, uint64_t* base, uint32_t n_polys, uint32_t rows_per_poly,
-                         uint32_t n_limbs, uint32_t split = ~0u) {
-    PolyBatch b{};
+// n_polys consecutive [rows_per_poly][N] blocks starting at base.
+static SmallBatch sb_rows(const pft_params* P, uint64_t* base, uint32_t n_polys, uint32_t rows_per_poly,
+                          uint32_t n_limbs, uint32_t split = ~0u) {
+    SmallBatch b{};
     for (uint32_t i = 0; i < n_polys; ++i) b.ptr[i] = base + ((size_t)i * rows_per_poly << P->log_n);
     b.n_polys = n_polys;
     b.n_limbs = n_limbs;
-    b.gap_at = 0;
-    b.gap_len = 0;
+    b.first = 0;
     b.split = split;
     b.off0 = 0;
     b.off1 = P->L;
     return b;
 }
 
-static void ntt(pft_ctx* c, const PolyBatch& b, bool inverse) {
-    launch_ntt(b, c->tabs, c->P->log_n, inverse, c->stream);
+static ProfHook* hook(pft_ctx* c) { return c->prof.mask ? &c->prof : nullptr; }
+
+// One transform job: a polynomial whose n_limbs limbs sit at rows
+// i + (i >= gap_at ? gap_len : 0) of ptr.
+struct NttJob {
+    uint64_t* ptr;
+    uint32_t gap_at, gap_len;
+};
+
+static void ntt_jobs(pft_ctx* c, const std::vector<NttJob>& jobs, uint32_t n_limbs, uint32_t split, bool inverse,
+                     uint32_t off0 = 0) {
+    const pft_params* P = c->P;
+    for (size_t s = 0; s < jobs.size(); s += PFT_MAX_POLYS) {
+        PolyBatch b{};
+        const uint32_t np = (uint32_t)std::min<size_t>(PFT_MAX_POLYS, jobs.size() - s);
+        for (uint32_t i = 0; i < np; ++i) {
+            b.ptr[i] = jobs[s + i].ptr;
+            b.gap_at[i] = (uint8_t)std::min<uint32_t>(jobs[s + i].gap_at, 255u);
+            b.gap_len[i] = (uint8_t)jobs[s + i].gap_len;
+        }
+        b.n_polys = np;
+        b.n_limbs = n_limbs;
+        b.split = split;
+        b.off0 = off0;
+        b.off1 = P->L;
+        launch_ntt(b, c->tabs, P->log_n, inverse, c->stream, hook(c));
+    }
+}
+
+// Transform of n_polys consecutive [rows_per_poly][N] blocks, limbs 0..n_limbs-1.
+static void ntt_rows(pft_ctx* c, uint64_t* base, uint32_t n_polys, uint32_t rows_per_poly, uint32_t n_limbs,
+                     bool inverse, uint32_t split = ~0u) {
+    std::vector<NttJob> jobs;
+    for (uint32_t i = 0; i < n_polys; ++i)
+        jobs.push_back(NttJob{base + ((size_t)i * rows_per_poly << c->P->log_n), 255u, 0u});
+    ntt_jobs(c, jobs, n_limbs, split, inverse);
+}
+
+// Runs f (one kernel launch) bracketed by profiling events when enabled.
+template <typename F>
+static void timed(pft_ctx* c, int kid, double bytes, double ops, F&& f) {
+    ProfHook* h = hook(c);
+    if (h) h->begin(kid);
+    f();
+    if (h) h->end(kid, bytes, ops);
 }
 
 // ---------------------------------------------------------------------------
@@ -398,13 +487,13 @@ extern "C" int pft_set_secret(pft_ctx* c, const int64_t* s) {
     if (!c || !s) return fail(PFT_EINVAL, "null argument");
     const pft_params* P = c->P;
     if (!check_ternary(s, P->n)) return fail(PFT_EINVAL, "secret must be ternary");
+    const uint32_t R = P->L + P->K;
     int r;
-    if (!c->s && (r = dalloc(c, &c->s, (size_t)(P->L + P->K) * P->n * 8))) return r;
+    if (!c->s && (r = dalloc(c, &c->s, (size_t)R * P->n * 8))) return r;
     if ((r = ensure_ws(c, (size_t)P->n * 8))) return r;
     if ((r = upload_i64(c, (int64_t*)c->ws, s, P->n))) return r;
-    PolyBatch b = pb_rows(P, c->s, 1, P->L + P->K, P->L + P->K, P->L);
-    launch_int_to_rns((const int64_t*)c->ws, b, c->tabs, P->log_n, c->stream);
-    ntt(c, b, false);
+    launch_int_to_rns((const int64_t*)c->ws, sb(P, {c->s}, R, 0, P->L), c->tabs, P->log_n, c->stream);
+    ntt_rows(c, c->s, 1, R, R, false, P->L);
     HIPCK(hipStreamSynchronize(c->stream));
     return PFT_OK;
 }
@@ -422,14 +511,11 @@ extern "C" int pft_gen_public_key(pft_ctx* c, const uint64_t* a, const int64_t* 
     int64_t* e_raw = (int64_t*)(c->ws + nL);
     uint64_t* pa = c->pk + nL;
     if ((r = upload_u64(c, pa, a, nL)) || (r = upload_i64(c, e_raw, e, P->n))) return r;
-    PolyBatch A = pb_rows(P, pa, 1, P->L, P->L);
-    ntt(c, A, false);
-    PolyBatch E = pb_rows(P, e_rns, 1, P->L, P->L);
-    launch_int_to_rns(e_raw, E, c->tabs, P->log_n, c->stream);
-    ntt(c, E, false);
+    ntt_rows(c, pa, 1, P->L, P->L, false);
+    launch_int_to_rns(e_raw, sb(P, {e_rns}, P->L), c->tabs, P->log_n, c->stream);
+    ntt_rows(c, e_rns, 1, P->L, P->L, false);
     // b = -(a s) + e
-    PolyBatch S = pb_rows(P, c->s, 1, P->L, P->L);
-    PolyBatch B = pb_rows(P, c->pk, 1, P->L, P->L);
+    SmallBatch A = sb(P, {pa}, P->L), S = sb(P, {c->s}, P->L), E = sb(P, {e_rns}, P->L), B = sb(P, {c->pk}, P->L);
     launch_ew(EW_NEG_MULADD, B, A, &S, &E, c->tabs, P->log_n, c->stream);
     HIPCK(hipStreamSynchronize(c->stream));
     return PFT_OK;
@@ -450,26 +536,23 @@ static int gen_switch_key(pft_ctx* c, const uint64_t* s_prime, const uint64_t* a
     uint64_t* e_rns = c->ws;
     int64_t* e_raw = (int64_t*)(c->ws + nR);
     uint64_t* gs = c->ws + nR + P->n;  // gadget * s'
-    PolyBatch S = pb_rows(P, c->s, 1, R, R, P->L);
+    const SmallBatch S = sb(P, {c->s}, R, 0, P->L);
     for (uint32_t j = 0; j < P->dnum; ++j) {
         uint64_t* kb = dst->data + (size_t)(2 * j) * nR;
         uint64_t* ka = dst->data + (size_t)(2 * j + 1) * nR;
         if ((r = upload_u64(c, ka, a + (size_t)j * nR, nR)) || (r = upload_i64(c, e_raw, e + (size_t)j * P->n, P->n)))
             return r;
-        PolyBatch A = pb_rows(P, ka, 1, R, R, P->L);
-        ntt(c, A, false);
-        PolyBatch E = pb_rows(P, e_rns, 1, R, R, P->L);
-        launch_int_to_rns(e_raw, E, c->tabs, P->log_n, c->stream);
-        ntt(c, E, false);
-        PolyBatch B = pb_rows(P, kb, 1, R, R, P->L);
+        ntt_rows(c, ka, 1, R, R, false, P->L);
+        launch_int_to_rns(e_raw, sb(P, {e_rns}, R, 0, P->L), c->tabs, P->log_n, c->stream);
+        ntt_rows(c, e_rns, 1, R, R, false, P->L);
+        const SmallBatch A = sb(P, {ka}, R, 0, P->L), E = sb(P, {e_rns}, R, 0, P->L), B = sb(P, {kb}, R, 0, P->L);
         launch_ew(EW_NEG_MULADD, B, A, &S, &E, c->tabs, P->log_n, c->stream);  // b = -a s + e
         // + (P mod q_t) s' on the q-limbs of digit j
         const uint32_t i0 = j * P->alpha, i1 = std::min(i0 + P->alpha, P->L);
         if (i0 < i1) {
-            PolyBatch Sp = pb_make(P, {(uint64_t*)s_prime}, i1 - i0, i0);
-            PolyBatch G = pb_make(P, {gs}, i1 - i0, i0);
+            const SmallBatch Sp = sb(P, {(uint64_t*)s_prime}, i1 - i0, i0), G = sb(P, {gs}, i1 - i0, i0);
             launch_mul_const(G, Sp, c->gadget + i0, c->tabs, P->log_n, c->stream);
-            PolyBatch Bd = pb_make(P, {kb}, i1 - i0, i0);
+            const SmallBatch Bd = sb(P, {kb}, i1 - i0, i0);
             launch_ew(EW_ADD, Bd, Bd, &G, nullptr, c->tabs, P->log_n, c->stream);
         }
         // store both halves times 2^64 (Montgomery form) for the inner product
@@ -485,13 +568,11 @@ extern "C" int pft_gen_relin_key(pft_ctx* c, const uint64_t* a, const int64_t* e
     if (!c->s) return fail(PFT_ENOKEY, "set the secret first");
     const pft_params* P = c->P;
     const uint32_t R = P->L + P->K;
-    uint64_t* s2;
     int r;
-    if ((r = dalloc(c, &s2, (size_t)R * P->n * 8))) return r;  // kept: small, freed with ctx
-    PolyBatch S = pb_rows(P, c->s, 1, R, R, P->L);
-    PolyBatch S2 = pb_rows(P, s2, 1, R, R, P->L);
+    if (!c->s_prime && (r = dalloc(c, &c->s_prime, (size_t)R * P->n * 8))) return r;
+    const SmallBatch S = sb(P, {c->s}, R, 0, P->L), S2 = sb(P, {c->s_prime}, R, 0, P->L);
     launch_ew(EW_MUL, S2, S, &S, nullptr, c->tabs, P->log_n, c->stream);
-    return gen_switch_key(c, s2, a, e, &c->rlk);
+    return gen_switch_key(c, c->s_prime, a, e, &c->rlk);
 }
 
 static uint64_t galois_element(int32_t step, uint32_t n) {
@@ -505,17 +586,23 @@ static int32_t norm_step(int32_t step, uint32_t n) {
     return (int32_t)((((int64_t)step % half) + half) % half);
 }
 
+static ItemPtrs one_item(uint64_t* p) {
+    ItemPtrs ip{};
+    ip.p[0] = p;
+    return ip;
+}
+
 extern "C" int pft_gen_rotation_key(pft_ctx* c, int32_t step, const uint64_t* a, const int64_t* e) {
     if (!c || !a || !e) return fail(PFT_EINVAL, "null argument");
     if (!c->s) return fail(PFT_ENOKEY, "set the secret first");
     const pft_params* P = c->P;
     const uint32_t R = P->L + P->K;
-    uint64_t* srot;
     int r;
-    if ((r = dalloc(c, &srot, (size_t)R * P->n * 8))) return r;
-    launch_automorphism(c->s, srot, 1, R, galois_element(step, P->n), P->log_n, c->stream);
+    if (!c->s_prime && (r = dalloc(c, &c->s_prime, (size_t)R * P->n * 8))) return r;
+    launch_automorphism_b(1, one_item(c->s), R, WsRef{c->s_prime, 0}, 0, galois_element(step, P->n), P->log_n,
+                          c->stream);
     SwitchKeyDev& k = c->rot[norm_step(step, P->n)];
-    return gen_switch_key(c, srot, a, e, &k);
+    return gen_switch_key(c, c->s_prime, a, e, &k);
 }
 
 // ---------------------------------------------------------------------------
@@ -546,14 +633,12 @@ extern "C" int pft_encrypt(pft_ctx* c, const int64_t* m, uint32_t level, double 
     if ((r = upload_i64(c, raw, m, n)) || (r = upload_i64(c, raw + n, v, n)) || (r = upload_i64(c, raw + 2 * n, e0, n)) ||
         (r = upload_i64(c, raw + 3 * n, e1, n)))
         return r;
-    PolyBatch all = pb_make(P, {M, V, E0, E1}, level);
-    launch_int_to_rns(raw, all, c->tabs, P->log_n, c->stream);
-    ntt(c, all, false);
+    launch_int_to_rns(raw, sb(P, {M, V, E0, E1}, level), c->tabs, P->log_n, c->stream);
+    ntt_rows(c, M, 4, level, level, false);
     const size_t nL = (size_t)P->L * n;
-    PolyBatch Bk = pb_make(P, {c->pk}, level), Ak = pb_make(P, {c->pk + nL}, level);
-    PolyBatch Vb = pb_make(P, {V}, level);
-    PolyBatch C0 = pb_make(P, {out->data}, level), C1 = pb_make(P, {out->data + nl}, level);
-    PolyBatch E0b = pb_make(P, {E0}, level), E1b = pb_make(P, {E1}, level), Mb = pb_make(P, {M}, level);
+    const SmallBatch Bk = sb(P, {c->pk}, level), Ak = sb(P, {c->pk + nL}, level), Vb = sb(P, {V}, level);
+    const SmallBatch C0 = sb(P, {out->data}, level), C1 = sb(P, {out->data + nl}, level);
+    const SmallBatch E0b = sb(P, {E0}, level), E1b = sb(P, {E1}, level), Mb = sb(P, {M}, level);
     launch_ew(EW_MULADD, C0, Bk, &Vb, &E0b, c->tabs, P->log_n, c->stream);  // b v + e0
     launch_ew(EW_ADD, C0, C0, &Mb, nullptr, c->tabs, P->log_n, c->stream);  // + m
     launch_ew(EW_MULADD, C1, Ak, &Vb, &E1b, c->tabs, P->log_n, c->stream);  // a v + e1
@@ -571,11 +656,10 @@ extern "C" int pft_decrypt(pft_ctx* c, const pft_ct* ct, uint64_t* out) {
     const pft_params* P = c->P;
     const size_t nl = (size_t)ct->level * P->n;
     if ((r = ensure_ws(c, nl * 8))) return r;
-    PolyBatch Mu = pb_make(P, {c->ws}, ct->level);
-    PolyBatch C0 = pb_make(P, {ct->data}, ct->level), C1 = pb_make(P, {ct->data + nl}, ct->level);
-    PolyBatch S = pb_make(P, {c->s}, ct->level);
+    const SmallBatch Mu = sb(P, {c->ws}, ct->level), C0 = sb(P, {ct->data}, ct->level);
+    const SmallBatch C1 = sb(P, {ct->data + nl}, ct->level), S = sb(P, {c->s}, ct->level);
     launch_ew(EW_MULADD, Mu, C1, &S, &C0, c->tabs, P->log_n, c->stream);
-    ntt(c, Mu, true);
+    ntt_rows(c, c->ws, 1, ct->level, ct->level, true);
     HIPCK(hipMemcpyAsync(out, c->ws, nl * 8, hipMemcpyDeviceToHost, c->stream));
     HIPCK(hipStreamSynchronize(c->stream));
     return PFT_OK;
@@ -589,7 +673,7 @@ extern "C" int pft_ct_export(pft_ctx* c, const pft_ct* ct, uint64_t* host) {
     const size_t nl = (size_t)ct->level * P->n;
     if ((r = ensure_ws(c, 2 * nl * 8))) return r;
     HIPCK(hipMemcpyAsync(c->ws, ct->data, 2 * nl * 8, hipMemcpyDeviceToDevice, c->stream));
-    ntt(c, pb_rows(P, c->ws, 2, ct->level, ct->level), true);
+    ntt_rows(c, c->ws, 2, ct->level, ct->level, true);
     HIPCK(hipMemcpyAsync(host, c->ws, 2 * nl * 8, hipMemcpyDeviceToHost, c->stream));
     HIPCK(hipStreamSynchronize(c->stream));
     return PFT_OK;
@@ -604,7 +688,7 @@ extern "C" int pft_ct_import(pft_ctx* c, const uint64_t* host, uint32_t level, d
             return fail(PFT_EINVAL, "residues must be < q_i");
     const size_t nl = (size_t)level * P->n;
     HIPCK(hipMemcpyAsync(ct->data, host, 2 * nl * 8, hipMemcpyHostToDevice, c->stream));
-    ntt(c, pb_rows(P, ct->data, 2, level, level), false);
+    ntt_rows(c, ct->data, 2, level, level, false);
     ct->level = level;
     ct->scale = scale;
     HIPCK(hipStreamSynchronize(c->stream));
@@ -618,9 +702,8 @@ extern "C" int pft_pt_from_coeffs(pft_ctx* c, const int64_t* m, uint32_t level, 
     int r;
     if ((r = ensure_ws(c, (size_t)P->n * 8))) return r;
     if ((r = upload_i64(c, (int64_t*)c->ws, m, P->n))) return r;
-    PolyBatch b = pb_make(P, {pt->data}, level);
-    launch_int_to_rns((const int64_t*)c->ws, b, c->tabs, P->log_n, c->stream);
-    ntt(c, b, false);
+    launch_int_to_rns((const int64_t*)c->ws, sb(P, {pt->data}, level), c->tabs, P->log_n, c->stream);
+    ntt_rows(c, pt->data, 1, level, level, false);
     pt->level = level;
     pt->scale = scale;
     HIPCK(hipStreamSynchronize(c->stream));
@@ -635,38 +718,39 @@ static bool scales_match(double a, double b) { return std::fabs(a - b) <= std::l
 extern "C" int pft_add(pft_ctx* c, const pft_ct* a, const pft_ct* b, pft_ct* out) {
     int r;
     if (!c) return fail(PFT_EINVAL, "null ctx");
-    if ((r = check_ct(c, a)) || (r = check_ct(c, b)) || (r = check_ct(c, out))) return r;
+    if ((r = check_ct(c, a)) || (r = check_ct(c, b))) return r;
+    if (!out || !out->data) return fail(PFT_EINVAL, "null output");
     if (a->level != b->level) return fail(PFT_ELEVEL, "HADD needs equal levels (%u vs %u)", a->level, b->level);
     if (!scales_match(a->scale, b->scale)) return fail(PFT_ESCALE, "HADD needs equal scales");
     const pft_params* P = c->P;
     const uint32_t l = a->level;
-    PolyBatch O = pb_rows(P, out->data, 2, l, l), A = pb_rows(P, a->data, 2, l, l), B = pb_rows(P, b->data, 2, l, l);
+    const SmallBatch O = sb_rows(P, out->data, 2, l, l), A = sb_rows(P, a->data, 2, l, l),
+                     B = sb_rows(P, b->data, 2, l, l);
     launch_ew(EW_ADD, O, A, &B, nullptr, c->tabs, P->log_n, c->stream);
     out->level = l;
     out->scale = a->scale;
     return PFT_OK;
 }
 
-static int check_pt(const pft_ctx* c, const pft_pt* p, uint32_t level) {
+static int check_pt(const pft_pt* p, uint32_t level) {
     if (!p || !p->data) return fail(PFT_EINVAL, "null plaintext");
     if (p->level < level) return fail(PFT_ELEVEL, "plaintext level %u below ciphertext level %u", p->level, level);
-    (void)c;
     return PFT_OK;
 }
 
 extern "C" int pft_add_plain(pft_ctx* c, const pft_ct* a, const pft_pt* p, pft_ct* out) {
     int r;
     if (!c) return fail(PFT_EINVAL, "null ctx");
-    if ((r = check_ct(c, a)) || (r = check_ct(c, out)) || (r = check_pt(c, p, a->level))) return r;
+    if ((r = check_ct(c, a)) || (r = check_pt(p, a->level))) return r;
+    if (!out || !out->data) return fail(PFT_EINVAL, "null output");
     if (!scales_match(a->scale, p->scale)) return fail(PFT_ESCALE, "HADDPLAIN needs equal scales");
     const pft_params* P = c->P;
     const uint32_t l = a->level;
     const size_t nl = (size_t)l * P->n;
-    PolyBatch O0 = pb_make(P, {out->data}, l), A0 = pb_make(P, {a->data}, l), Pt = pb_make(P, {p->data}, l);
+    const SmallBatch O0 = sb(P, {out->data}, l), A0 = sb(P, {a->data}, l), Pt = sb(P, {p->data}, l);
     launch_ew(EW_ADD, O0, A0, &Pt, nullptr, c->tabs, P->log_n, c->stream);
-    if (out->data != a->data) {
+    if (out->data != a->data)
         HIPCK(hipMemcpyAsync(out->data + nl, a->data + nl, nl * 8, hipMemcpyDeviceToDevice, c->stream));
-    }
     out->level = l;
     out->scale = a->scale;
     return PFT_OK;
@@ -675,11 +759,12 @@ extern "C" int pft_add_plain(pft_ctx* c, const pft_ct* a, const pft_pt* p, pft_c
 extern "C" int pft_mul_plain(pft_ctx* c, const pft_ct* a, const pft_pt* p, pft_ct* out) {
     int r;
     if (!c) return fail(PFT_EINVAL, "null ctx");
-    if ((r = check_ct(c, a)) || (r = check_ct(c, out)) || (r = check_pt(c, p, a->level))) return r;
+    if ((r = check_ct(c, a)) || (r = check_pt(p, a->level))) return r;
+    if (!out || !out->data) return fail(PFT_EINVAL, "null output");
     const pft_params* P = c->P;
     const uint32_t l = a->level;
-    PolyBatch O = pb_rows(P, out->data, 2, l, l), A = pb_rows(P, a->data, 2, l, l);
-    PolyBatch Pt = pb_make(P, {p->data, p->data}, l);
+    const SmallBatch O = sb_rows(P, out->data, 2, l, l), A = sb_rows(P, a->data, 2, l, l);
+    const SmallBatch Pt = sb(P, {p->data, p->data}, l);
     launch_ew(EW_MUL, O, A, &Pt, nullptr, c->tabs, P->log_n, c->stream);
     out->level = l;
     out->scale = a->scale * p->scale;
@@ -689,74 +774,140 @@ extern "C" int pft_mul_plain(pft_ctx* c, const pft_ct* a, const pft_pt* p, pft_c
 extern "C" int pft_mod_drop(pft_ctx* c, const pft_ct* in, uint32_t level, pft_ct* out) {
     int r;
     if (!c) return fail(PFT_EINVAL, "null ctx");
-    if ((r = check_ct(c, in)) || !out || !out->data) return r ? r : fail(PFT_EINVAL, "null output");
+    if ((r = check_ct(c, in))) return r;
+    if (!out || !out->data) return fail(PFT_EINVAL, "null output");
     if (level < 1 || level > in->level) return fail(PFT_ELEVEL, "mod_drop to %u from %u", level, in->level);
     const pft_params* P = c->P;
     const size_t lo = (size_t)level * P->n, li = (size_t)in->level * P->n;
-    // [2][level][N] from [2][in_level][N]; poly 1 moves down when levels differ
-    HIPCK(hipMemcpyAsync(out->data, in->data, lo * 8, hipMemcpyDeviceToDevice, c->stream));
-    if (out->data != in->data || level != in->level)
+    if (out->data == in->data) {
+        // in place: poly 1 moves down from row in_level to row level; go
+        // through the workspace because the two ranges may overlap
+        if (level != in->level) {
+            if ((r = ensure_ws(c, lo * 8))) return r;
+            HIPCK(hipMemcpyAsync(c->ws, in->data + li, lo * 8, hipMemcpyDeviceToDevice, c->stream));
+            HIPCK(hipMemcpyAsync(out->data + lo, c->ws, lo * 8, hipMemcpyDeviceToDevice, c->stream));
+        }
+    } else {
+        HIPCK(hipMemcpyAsync(out->data, in->data, lo * 8, hipMemcpyDeviceToDevice, c->stream));
         HIPCK(hipMemcpyAsync(out->data + lo, in->data + li, lo * 8, hipMemcpyDeviceToDevice, c->stream));
+    }
     out->level = level;
     out->scale = in->scale;
     return PFT_OK;
 }
 
-// Scratch needed by one key switch at `level`.
-static size_t ks_ws_words(const pft_params* P, uint32_t level) {
-    const uint32_t beta = (level + P->alpha - 1) / P->alpha;
-    const size_t rows = level + P->K;
-    return ((size_t)level + beta * rows + 2 * rows + 2 * (size_t)level) << P->log_n;
+// ---- batched hybrid key switching ---------------------------------------
+// Per-item workspace words after the op's own prefix.
+struct KsLayout {
+    uint32_t level, beta, rows;
+    uint64_t off_dcoef, off_ext, off_acc, off_conv, end;
+};
+
+static KsLayout ks_layout(const pft_params* P, uint32_t level, uint64_t base) {
+    KsLayout k{};
+    k.level = level;
+    k.beta = (level + P->alpha - 1) / P->alpha;
+    k.rows = level + P->K;
+    const uint64_t n = P->n;
+    k.off_dcoef = base;
+    k.off_ext = k.off_dcoef + level * n;
+    k.off_acc = k.off_ext + (uint64_t)k.beta * k.rows * n;
+    k.off_conv = k.off_acc + 2ull * k.rows * n;
+    k.end = k.off_conv + 2ull * level * n;
+    return k;
 }
 
-// Hybrid key switching of d (NTT domain, [level][N]) with `key`; writes
-// out[2][level][N] = ModDown(sum_j ModUp_j(d) * key_j) + (add0, add1).
-// ws must hold ks_ws_words(level) words.
-static void key_switch(pft_ctx* c, const uint64_t* d_ntt, const SwitchKeyDev& key, uint32_t level,
-                       const uint64_t* add0, const uint64_t* add1, uint64_t* out, uint64_t* ws) {
+static ItemPtrs ws_items(WsRef ws, uint32_t n, uint64_t off = 0) {
+    ItemPtrs ip{};
+    for (uint32_t z = 0; z < n; ++z) ip.p[z] = ws.base + z * ws.stride + off;
+    return ip;
+}
+
+// Key switching of d (NTT domain, [level][N] at ws_z + off_d) for n items:
+// out_z = ModDown(sum_j ModUp_j(d) key_j) + (ws rows at off_add0/off_add1).
+static void key_switch_b(pft_ctx* c, uint32_t n, WsRef ws, const KsLayout& K, uint64_t off_d,
+                         const SwitchKeyDev& key, uint64_t off_add0, uint64_t off_add1, const ItemPtrs& out) {
     const pft_params* P = c->P;
-    const uint32_t lg = P->log_n, K = P->K, A = P->alpha;
-    const uint32_t beta = (level + A - 1) / A, rows = level + K;
-    uint64_t* d_coef = ws;
-    uint64_t* ext = d_coef + ((size_t)level << lg);
-    uint64_t* acc = ext + ((size_t)beta * rows << lg);
-    uint64_t* conv = acc + ((size_t)2 * rows << lg);
-    (void)hipMemcpyAsync(d_coef, d_ntt, ((size_t)level << lg) * 8, hipMemcpyDeviceToDevice, c->stream);
-    ntt(c, pb_make(P, {d_coef}, level), true);
-    launch_modup(d_coef, ext, level, c->kc, c->tabs, lg, c->stream);
-    for (uint32_t j = 0; j < beta; ++j) {
-        const uint32_t i0 = j * A, na = std::min(i0 + A, level) - i0;
-        PolyBatch b{};
-        b.ptr[0] = ext + ((size_t)j * rows << lg);
-        b.n_polys = 1;
-        b.n_limbs = rows - na;
-        b.gap_at = i0;
-        b.gap_len = na;
-        b.split = level;
-        b.off0 = 0;
-        b.off1 = P->L;
-        ntt(c, b, false);
+    const uint32_t lg = P->log_n, A = P->alpha, level = K.level, rows = K.rows, beta = K.beta;
+    const double N = (double)P->n;
+    // d -> coefficient form
+    launch_copy_rows_b(n, ws_items(ws, n), off_d, ws_items(ws, n), K.off_dcoef, level, lg, c->stream);
+    {
+        std::vector<NttJob> jobs;
+        for (uint32_t z = 0; z < n; ++z) jobs.push_back(NttJob{ws.base + z * ws.stride + K.off_dcoef, 255u, 0u});
+        ntt_jobs(c, jobs, level, ~0u, true);
     }
-    launch_key_inner(d_ntt, ext, key.data, acc, level, c->kc, c->tabs, lg, c->stream);
+    // ModUp base conversion
+    {
+        double rd = 0, wr = 0, macs = 0;
+        for (uint32_t j = 0; j < beta; ++j) {
+            const uint32_t na = std::min(j * A + A, level) - j * A;
+            rd += na;
+            wr += rows - na;
+            macs += (double)(rows - na) * na + na;
+        }
+        timed(c, PK_MODUP, 8.0 * N * (rd + wr) * n, N * macs * n,
+              [&] { launch_modup_b(n, ws, K.off_dcoef, K.off_ext, level, c->kc, c->tabs, lg, c->stream); });
+    }
+    // ModUp transforms: all digits of all items, full digits and the ragged
+    // last digit in separate launches (different limb counts)
+    {
+        std::vector<NttJob> full, last;
+        uint32_t na_last = 0;
+        for (uint32_t z = 0; z < n; ++z)
+            for (uint32_t j = 0; j < beta; ++j) {
+                const uint32_t i0 = j * A, na = std::min(i0 + A, level) - i0;
+                NttJob job{ws.base + z * ws.stride + K.off_ext + ((uint64_t)j * rows << lg), i0, na};
+                (na == A ? full : last).push_back(job);
+                if (na != A) na_last = na;
+            }
+        if (!full.empty()) ntt_jobs(c, full, rows - A, level, false);
+        if (!last.empty()) ntt_jobs(c, last, rows - na_last, level, false);
+    }
+    // key inner product over level + K rows
+    timed(c, PK_KEY_INNER, 8.0 * N * ((double)beta * rows * 3 + 2.0 * rows) * n, 2.0 * N * beta * rows * n, [&] {
+        launch_key_inner_b(n, ws, off_d, K.off_ext, K.off_acc, key.data, level, c->kc, c->tabs, lg, c->stream);
+    });
     // ModDown: special rows of both accumulators to coefficient form
-    PolyBatch sp = pb_make(P, {acc, acc + ((size_t)rows << lg)}, K, level, level);
-    ntt(c, sp, true);
-    launch_moddown_conv(acc, conv, level, c->kc, c->tabs, lg, c->stream);
-    ntt(c, pb_rows(P, conv, 2, level, level), false);
-    launch_moddown_final(acc, conv, add0, add1, out, level, c->kc, c->tabs, lg, c->stream);
+    {
+        std::vector<NttJob> jobs;
+        for (uint32_t z = 0; z < n; ++z)
+            for (uint32_t b = 0; b < 2; ++b)
+                jobs.push_back(NttJob{ws.base + z * ws.stride + K.off_acc + ((uint64_t)b * rows << lg), 0u, level});
+        ntt_jobs(c, jobs, P->K, level, true);
+    }
+    timed(c, PK_MODDOWN_CONV, 8.0 * N * (2.0 * P->K + 2.0 * level) * n, 2.0 * N * P->K * level * n,
+          [&] { launch_moddown_conv_b(n, ws, K.off_acc, K.off_conv, level, c->kc, c->tabs, lg, c->stream); });
+    {
+        std::vector<NttJob> jobs;
+        for (uint32_t z = 0; z < n; ++z)
+            for (uint32_t b = 0; b < 2; ++b)
+                jobs.push_back(NttJob{ws.base + z * ws.stride + K.off_conv + ((uint64_t)b * level << lg), 255u, 0u});
+        ntt_jobs(c, jobs, level, ~0u, false);
+    }
+    const double adds = (off_add0 != PFT_NO_OFFSET) + (off_add1 != PFT_NO_OFFSET);
+    timed(c, PK_MODDOWN_FINAL, 8.0 * N * level * (6.0 + adds) * n, 2.0 * N * level * n, [&] {
+        launch_moddown_final_b(n, ws, K.off_acc, K.off_conv, off_add0, off_add1, out, level, c->kc, c->tabs, lg,
+                               c->stream);
+    });
 }
 
-static int mul_relin_one(pft_ctx* c, const pft_ct* a, const pft_ct* b, pft_ct* out) {
-    const pft_params* P = c->P;
-    const uint32_t l = a->level, lg = P->log_n;
-    const size_t nl = (size_t)l << lg;
-    int r;
-    if ((r = ensure_ws(c, (3 * nl + ks_ws_words(P, l)) * 8))) return r;
-    uint64_t *d0 = c->ws, *d1 = d0 + nl, *d2 = d1 + nl, *ws = d2 + nl;
-    launch_tensor(a->data, b->data, d0, d1, d2, l, c->tabs, lg, c->stream);
-    key_switch(c, d2, c->rlk, l, d0, d1, out->data, ws);
-    out->level = l;
-    out->scale = a->scale * b->scale;
+// Items of one batched call grouped into launches of at most PFT_MAX_ITEMS
+// ciphertexts of equal level.
+template <typename F>
+static int for_level_groups(uint32_t n, const pft_ct* in, F&& f) {
+    std::vector<uint32_t> idx(n);
+    for (uint32_t i = 0; i < n; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](uint32_t x, uint32_t y) { return in[x].level > in[y].level; });
+    size_t s = 0;
+    while (s < n) {
+        size_t e = s;
+        while (e < n && e - s < PFT_MAX_ITEMS && in[idx[e]].level == in[idx[s]].level) ++e;
+        std::vector<uint32_t> grp(idx.begin() + s, idx.begin() + e);
+        int r = f(grp);
+        if (r) return r;
+        s = e;
+    }
     return PFT_OK;
 }
 
@@ -769,37 +920,34 @@ extern "C" int pft_mul_relin_batch(pft_ctx* c, uint32_t n, const pft_ct* a, cons
     if (!c->rlk.data) return fail(PFT_ENOKEY, "no relinearisation key");
     int r;
     for (uint32_t i = 0; i < n; ++i) {
-        if ((r = check_ct(c, &a[i])) || (r = check_ct(c, &b[i])) || (r = check_ct(c, &out[i]))) return r;
+        if ((r = check_ct(c, &a[i])) || (r = check_ct(c, &b[i]))) return r;
+        if (!out[i].data) return fail(PFT_EINVAL, "null output");
         if (a[i].level != b[i].level) return fail(PFT_ELEVEL, "HMUL needs equal levels");
         if (out[i].data == a[i].data || out[i].data == b[i].data) return fail(PFT_EINVAL, "output aliases an input");
     }
-    for (uint32_t i = 0; i < n; ++i)
-        if ((r = mul_relin_one(c, &a[i], &b[i], &out[i]))) return r;
-    return PFT_OK;
-}
-
-static int rescale_one(pft_ctx* c, const pft_ct* in, uint32_t mode, pft_ct* out) {
     const pft_params* P = c->P;
-    const uint32_t l = in->level, lg = P->log_n;
-    const size_t n = (size_t)1 << lg;
-    int r;
-    if ((r = ensure_ws(c, (2 * n + 2 * (size_t)(l - 1) * n) * 8))) return r;
-    uint64_t* last = c->ws;
-    uint64_t* tmp = last + 2 * n;
-    HIPCK(hipMemcpyAsync(last, in->data + (size_t)(l - 1) * n, n * 8, hipMemcpyDeviceToDevice, c->stream));
-    HIPCK(hipMemcpyAsync(last + n, in->data + (size_t)(2 * l - 1) * n, n * 8, hipMemcpyDeviceToDevice, c->stream));
-    PolyBatch Lb = pb_make(P, {last, last + n}, 1, l - 1);
-    Lb.gap_len = 0;
-    Lb.off0 = l - 1;  // both rows are limb l-1
-    Lb.split = ~0u;
-    ntt(c, Lb, true);
-    launch_rescale_expand(last, tmp, l, mode, c->tabs, lg, c->stream);
-    ntt(c, pb_rows(P, tmp, 2, l - 1, l - 1), false);
-    launch_rescale_final(in->data, tmp, out->data, l, c->rescale_qinv + (size_t)(l - 1) * P->L, c->tabs, lg,
-                         c->stream);
-    out->level = l - 1;
-    out->scale = in->scale / (double)P->q[l - 1];
-    return PFT_OK;
+    return for_level_groups(n, a, [&](const std::vector<uint32_t>& g) -> int {
+        const uint32_t l = a[g[0]].level, cnt = (uint32_t)g.size();
+        const uint64_t nl = (uint64_t)l * P->n;
+        const KsLayout K = ks_layout(P, l, 3 * nl);
+        int rr;
+        if ((rr = ensure_ws(c, (size_t)cnt * K.end * 8))) return rr;
+        const WsRef ws{c->ws, K.end};
+        ItemPtrs A{}, B{}, O{};
+        for (uint32_t z = 0; z < cnt; ++z) {
+            A.p[z] = a[g[z]].data;
+            B.p[z] = b[g[z]].data;
+            O.p[z] = out[g[z]].data;
+        }
+        timed(c, PK_TENSOR, 8.0 * nl * 7 * cnt, 4.0 * nl * cnt,
+              [&] { launch_tensor_b(cnt, A, B, ws, 0, l, c->tabs, P->log_n, c->stream); });
+        key_switch_b(c, cnt, ws, K, 2 * nl, c->rlk, 0, nl, O);
+        for (uint32_t z = 0; z < cnt; ++z) {
+            out[g[z]].level = l;
+            out[g[z]].scale = a[g[z]].scale * b[g[z]].scale;
+        }
+        return PFT_OK;
+    });
 }
 
 extern "C" int pft_rescale(pft_ctx* c, const pft_ct* in, uint32_t mode, pft_ct* out) {
@@ -816,23 +964,44 @@ extern "C" int pft_rescale_batch(pft_ctx* c, uint32_t n, const pft_ct* in, uint3
         if (!out[i].data) return fail(PFT_EINVAL, "null output");
         if (out[i].data == in[i].data) return fail(PFT_EINVAL, "rescale output aliases its input");
     }
-    for (uint32_t i = 0; i < n; ++i)
-        if ((r = rescale_one(c, &in[i], mode, &out[i]))) return r;
-    return PFT_OK;
-}
-
-static int rotate_one(pft_ctx* c, const pft_ct* in, const SwitchKeyDev& key, uint64_t kappa, pft_ct* out) {
     const pft_params* P = c->P;
-    const uint32_t l = in->level, lg = P->log_n;
-    const size_t nl = (size_t)l << lg;
-    int r;
-    if ((r = ensure_ws(c, (2 * nl + ks_ws_words(P, l)) * 8))) return r;
-    uint64_t* rot = c->ws;  // [2][l][N]: c0(X^kappa), c1(X^kappa)
-    launch_automorphism(in->data, rot, 2, l, kappa, lg, c->stream);
-    key_switch(c, rot + nl, key, l, rot, nullptr, out->data, rot + 2 * nl);
-    out->level = l;
-    out->scale = in->scale;
-    return PFT_OK;
+    const uint32_t lg = P->log_n;
+    return for_level_groups(n, in, [&](const std::vector<uint32_t>& g) -> int {
+        const uint32_t l = in[g[0]].level, cnt = (uint32_t)g.size();
+        const uint64_t N = P->n;
+        const uint64_t off_last = 0, off_tmp = 2 * N, words = 2 * N + 2 * (uint64_t)(l - 1) * N;
+        int rr;
+        if ((rr = ensure_ws(c, (size_t)cnt * words * 8))) return rr;
+        const WsRef ws{c->ws, words};
+        ItemPtrs I{}, O{};
+        for (uint32_t z = 0; z < cnt; ++z) {
+            I.p[z] = in[g[z]].data;
+            O.p[z] = out[g[z]].data;
+        }
+        // limb l-1 of both polynomials -> coefficient form
+        launch_copy_rows_b(cnt, I, (uint64_t)(l - 1) * N, ws_items(ws, cnt), off_last, 1, lg, c->stream);
+        launch_copy_rows_b(cnt, I, (uint64_t)(2 * l - 1) * N, ws_items(ws, cnt), off_last + N, 1, lg, c->stream);
+        std::vector<NttJob> jl, jt;
+        for (uint32_t z = 0; z < cnt; ++z)
+            for (uint32_t b = 0; b < 2; ++b) {
+                jl.push_back(NttJob{ws.base + z * ws.stride + off_last + b * N, 255u, 0u});
+                jt.push_back(NttJob{ws.base + z * ws.stride + off_tmp + b * (l - 1) * N, 255u, 0u});
+            }
+        ntt_jobs(c, jl, 1, ~0u, true, l - 1);  // modulus of row 0 is q_{l-1}
+        const double nd = (double)N;
+        timed(c, PK_RESCALE, 8.0 * nd * (2.0 + 2.0 * (l - 1)) * cnt, 0,
+              [&] { launch_rescale_expand_b(cnt, ws, off_last, off_tmp, l, mode, c->tabs, lg, c->stream); });
+        ntt_jobs(c, jt, l - 1, ~0u, false);
+        timed(c, PK_RESCALE, 8.0 * nd * 6.0 * (l - 1) * cnt, 2.0 * nd * (l - 1) * cnt, [&] {
+            launch_rescale_final_b(cnt, I, ws, off_tmp, O, l, c->rescale_qinv + (size_t)(l - 1) * P->L, c->tabs, lg,
+                                   c->stream);
+        });
+        for (uint32_t z = 0; z < cnt; ++z) {
+            out[g[z]].level = l - 1;
+            out[g[z]].scale = in[g[z]].scale / (double)P->q[l - 1];
+        }
+        return PFT_OK;
+    });
 }
 
 static const SwitchKeyDev* find_rot(pft_ctx* c, int32_t step) {
@@ -850,43 +1019,82 @@ extern "C" int pft_rotate_batch(pft_ctx* c, uint32_t n, const pft_ct* in, int32_
     if (!key) return fail(PFT_ENOKEY, "no rotation key for step %d", step);
     int r;
     for (uint32_t i = 0; i < n; ++i) {
-        if ((r = check_ct(c, &in[i])) || (r = check_ct(c, &out[i]))) return r;
+        if ((r = check_ct(c, &in[i]))) return r;
+        if (!out[i].data) return fail(PFT_EINVAL, "null output");
         if (out[i].data == in[i].data) return fail(PFT_EINVAL, "rotate output aliases its input");
     }
-    const uint64_t kappa = galois_element(step, c->P->n);
-    for (uint32_t i = 0; i < n; ++i)
-        if ((r = rotate_one(c, &in[i], *key, kappa, &out[i]))) return r;
-    return PFT_OK;
+    const pft_params* P = c->P;
+    const uint64_t kappa = galois_element(step, P->n);
+    return for_level_groups(n, in, [&](const std::vector<uint32_t>& g) -> int {
+        const uint32_t l = in[g[0]].level, cnt = (uint32_t)g.size();
+        const uint64_t nl = (uint64_t)l * P->n;
+        const KsLayout K = ks_layout(P, l, 2 * nl);
+        int rr;
+        if ((rr = ensure_ws(c, (size_t)cnt * K.end * 8))) return rr;
+        const WsRef ws{c->ws, K.end};
+        ItemPtrs I{}, O{};
+        for (uint32_t z = 0; z < cnt; ++z) {
+            I.p[z] = in[g[z]].data;
+            O.p[z] = out[g[z]].data;
+        }
+        timed(c, PK_AUTOMORPHISM, 8.0 * 4 * nl * cnt, 0,
+              [&] { launch_automorphism_b(cnt, I, 2 * l, ws, 0, kappa, P->log_n, c->stream); });
+        key_switch_b(c, cnt, ws, K, nl, *key, 0, PFT_NO_OFFSET, O);
+        for (uint32_t z = 0; z < cnt; ++z) {
+            out[g[z]].level = l;
+            out[g[z]].scale = in[g[z]].scale;
+        }
+        return PFT_OK;
+    });
 }
 
 extern "C" int pft_total_sum(pft_ctx* c, const pft_ct* in, uint32_t n_slots, pft_ct* out) {
-    if (!c) return fail(PFT_EINVAL, "null ctx");
+    return pft_total_sum_batch(c, 1, in, n_slots, out);
+}
+
+extern "C" int pft_total_sum_batch(pft_ctx* c, uint32_t n, const pft_ct* in, uint32_t n_slots, pft_ct* out) {
+    if (!c || !in || !out) return fail(PFT_EINVAL, "null argument");
     int r;
-    if ((r = check_ct(c, in)) || (r = check_ct(c, out))) return r;
+    for (uint32_t i = 0; i < n; ++i) {
+        if ((r = check_ct(c, &in[i]))) return r;
+        if (!out[i].data) return fail(PFT_EINVAL, "null output");
+    }
     if (n_slots < 1 || n_slots > c->P->n / 2 || (n_slots & (n_slots - 1)))
         return fail(PFT_EINVAL, "n_slots must be a power of two <= N/2");
     for (uint32_t s = 1; s < n_slots; s <<= 1)
         if (!find_rot(c, (int32_t)s)) return fail(PFT_ENOKEY, "no rotation key for step %u", s);
     const pft_params* P = c->P;
-    const uint32_t l = in->level, lg = P->log_n;
-    const size_t nl = (size_t)l << lg;
-    if ((r = ensure_ws(c, (4 * nl + ks_ws_words(P, l)) * 8))) return r;
-    uint64_t* cur = c->ws;           // [2][l][N]
-    uint64_t* rot = cur + 2 * nl;    // [2][l][N]
-    uint64_t* ws = rot + 2 * nl;
-    HIPCK(hipMemcpyAsync(cur, in->data, 2 * nl * 8, hipMemcpyDeviceToDevice, c->stream));
-    PolyBatch Cur = pb_rows(P, cur, 2, l, l);
-    for (uint32_t s = 1; s < n_slots; s <<= 1) {
-        // rot = ROTATE(cur, s); cur = cur + rot
-        launch_automorphism(cur, rot, 2, l, galois_element((int32_t)s, P->n), lg, c->stream);
-        key_switch(c, rot + nl, *find_rot(c, (int32_t)s), l, rot, nullptr, rot, ws);
-        PolyBatch Rot = pb_rows(P, rot, 2, l, l);
-        launch_ew(EW_ADD, Cur, Cur, &Rot, nullptr, c->tabs, lg, c->stream);
-    }
-    HIPCK(hipMemcpyAsync(out->data, cur, 2 * nl * 8, hipMemcpyDeviceToDevice, c->stream));
-    out->level = l;
-    out->scale = in->scale;
-    return PFT_OK;
+    const uint32_t lg = P->log_n;
+    return for_level_groups(n, in, [&](const std::vector<uint32_t>& g) -> int {
+        const uint32_t l = in[g[0]].level, cnt = (uint32_t)g.size();
+        const uint64_t nl = (uint64_t)l * P->n;
+        const uint64_t off_cur = 0, off_rot = 2 * nl;
+        const KsLayout K = ks_layout(P, l, 4 * nl);
+        int rr;
+        if ((rr = ensure_ws(c, (size_t)cnt * K.end * 8))) return rr;
+        const WsRef ws{c->ws, K.end};
+        ItemPtrs I{}, O{};
+        for (uint32_t z = 0; z < cnt; ++z) {
+            I.p[z] = in[g[z]].data;
+            O.p[z] = out[g[z]].data;
+        }
+        launch_copy_rows_b(cnt, I, 0, ws_items(ws, cnt), off_cur, 2 * l, lg, c->stream);
+        const ItemPtrs CUR = ws_items(ws, cnt, off_cur), ROT = ws_items(ws, cnt, off_rot);
+        for (uint32_t s = 1; s < n_slots; s <<= 1) {
+            // rot = ROTATE(cur, s); cur = cur + rot   (Alg. 2)
+            const uint64_t kappa = galois_element((int32_t)s, P->n);
+            timed(c, PK_AUTOMORPHISM, 8.0 * 4 * nl * cnt, 0,
+                  [&] { launch_automorphism_b(cnt, CUR, 2 * l, ws, off_rot, kappa, lg, c->stream); });
+            key_switch_b(c, cnt, ws, K, off_rot + nl, *find_rot(c, (int32_t)s), off_rot, PFT_NO_OFFSET, ROT);
+            launch_add_ct_b(cnt, ws, off_cur, off_rot, off_cur, l, c->tabs, lg, c->stream);
+        }
+        launch_copy_rows_b(cnt, CUR, 0, O, 0, 2 * l, lg, c->stream);
+        for (uint32_t z = 0; z < cnt; ++z) {
+            out[g[z]].level = l;
+            out[g[z]].scale = in[g[z]].scale;
+        }
+        return PFT_OK;
+    });
 }
 
 // ---------------------------------------------------------------------------
@@ -895,11 +1103,7 @@ extern "C" int pft_total_sum(pft_ctx* c, const pft_ct* in, uint32_t n_slots, pft
 static int raw_ntt(pft_ctx* c, uint64_t* data, uint32_t n_polys, uint32_t n_limbs, bool inv) {
     if (!c || !data) return fail(PFT_EINVAL, "null argument");
     if (n_limbs < 1 || n_limbs > c->P->L) return fail(PFT_EINVAL, "n_limbs must be in 1..L");
-    const pft_params* P = c->P;
-    for (uint32_t p0 = 0; p0 < n_polys; p0 += PFT_MAX_POLYS) {
-        const uint32_t np = std::min<uint32_t>(PFT_MAX_POLYS, n_polys - p0);
-        ntt(c, pb_rows(P, data + ((size_t)p0 * n_limbs << P->log_n), np, n_limbs, n_limbs), inv);
-    }
+    ntt_rows(c, data, n_polys, n_limbs, n_limbs, inv);
     return PFT_OK;
 }
 
@@ -1001,5 +1205,39 @@ extern "C" int pft_decode(const pft_params* P, const uint64_t* res, uint32_t lev
         im[j] = M[e].imag() / scale;
         e = e * 5 % (2 * n);
     }
+    return PFT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// per-kernel-family timing (HIP events on the context stream)
+// ---------------------------------------------------------------------------
+extern "C" int pft_prof_enable(pft_ctx* c, uint32_t mask) {
+    if (!c) return fail(PFT_EINVAL, "null ctx");
+    HIPCK(hipStreamSynchronize(c->stream));
+    c->prof.reset();
+    c->prof.mask = mask & ((1u << PK_COUNT) - 1u);
+    return PFT_OK;
+}
+
+extern "C" int pft_prof_read(pft_ctx* c, uint32_t kid, double* total_ms, uint64_t* launches, double* bytes,
+                             double* ops) {
+    if (!c || !total_ms || !launches || !bytes || !ops) return fail(PFT_EINVAL, "null argument");
+    if (kid >= PK_COUNT) return fail(PFT_EINVAL, "kernel family %u out of range", kid);
+    HIPCK(hipStreamSynchronize(c->stream));
+    double ms = 0, by = 0, op = 0;
+    uint64_t cnt = 0;
+    for (const auto& r : c->prof.recs) {
+        if (r.kid != (int)kid) continue;
+        float t = 0;
+        HIPCK(hipEventElapsedTime(&t, r.a, r.b));
+        ms += t;
+        by += r.bytes;
+        op += r.ops;
+        ++cnt;
+    }
+    *total_ms = ms;
+    *launches = cnt;
+    *bytes = by;
+    *ops = op;
     return PFT_OK;
 }

@@ -160,7 +160,7 @@ __global__ __launch_bounds__(256) void k_ntt_pass(PolyBatch b, const DevMod* __r
     const uint32_t job = blockIdx.y;
     const uint32_t limb = job / b.n_polys;
     const uint32_t poly = job - limb * b.n_polys;
-    const uint32_t row = pb_row(b, limb);
+    const uint32_t row = pb_row(b, poly, limb);
     const uint32_t mi = pb_mod(b, row);
     uint64_t* __restrict__ data = b.ptr[poly] + ((size_t)row << log_n);
     const DevMod md = mods[mi];
@@ -224,35 +224,43 @@ __global__ __launch_bounds__(256) void k_ntt_pass(PolyBatch b, const DevMod* __r
 
 template <int LOG_M, bool INV>
 void launch_pass(const PolyBatch& b, const DevTables& t, uint32_t log_n, uint32_t s0, bool final_pass,
-                 hipStream_t st) {
+                 hipStream_t st, ProfHook* g_prof) {
     const uint32_t jobs = b.n_polys * b.n_limbs;
     dim3 grid((1u << log_n) / 4096u, jobs);
+    const int kid = INV ? PK_NTT_INV : PK_NTT_FWD;
+    if (g_prof) g_prof->begin(kid);
     hipLaunchKernelGGL((k_ntt_pass<LOG_M, INV>), grid, dim3(256), 0, st, b, t.mods, INV ? t.tw_inv : t.tw_fwd,
                        log_n, s0, (uint32_t)final_pass);
+    if (g_prof) {
+        const double elems = (double)jobs * (double)(1u << log_n);
+        // read + write every residue once; N/2 butterflies per stage
+        g_prof->end(kid, 16.0 * elems, 0.5 * elems * LOG_M);
+    }
 }
 
 }  // namespace
 
 bool ntt_supported(uint32_t log_n) { return log_n >= 12 && log_n <= 16; }
 
-void launch_ntt(const PolyBatch& b, const DevTables& t, uint32_t log_n, bool inverse, hipStream_t st) {
+void launch_ntt(const PolyBatch& b, const DevTables& t, uint32_t log_n, bool inverse, hipStream_t st,
+                ProfHook* prof) {
     if (b.n_polys == 0 || b.n_limbs == 0) return;
     if (!inverse) {
         switch (log_n) {
-            case 12: launch_pass<12, false>(b, t, 12, 0, true, st); break;
-            case 13: launch_pass<7, false>(b, t, 13, 0, false, st); launch_pass<6, false>(b, t, 13, 7, true, st); break;
-            case 14: launch_pass<7, false>(b, t, 14, 0, false, st); launch_pass<7, false>(b, t, 14, 7, true, st); break;
-            case 15: launch_pass<8, false>(b, t, 15, 0, false, st); launch_pass<7, false>(b, t, 15, 8, true, st); break;
-            case 16: launch_pass<8, false>(b, t, 16, 0, false, st); launch_pass<8, false>(b, t, 16, 8, true, st); break;
+            case 12: launch_pass<12, false>(b, t, 12, 0, true, st, prof); break;
+            case 13: launch_pass<7, false>(b, t, 13, 0, false, st, prof); launch_pass<6, false>(b, t, 13, 7, true, st, prof); break;
+            case 14: launch_pass<7, false>(b, t, 14, 0, false, st, prof); launch_pass<7, false>(b, t, 14, 7, true, st, prof); break;
+            case 15: launch_pass<8, false>(b, t, 15, 0, false, st, prof); launch_pass<7, false>(b, t, 15, 8, true, st, prof); break;
+            case 16: launch_pass<8, false>(b, t, 16, 0, false, st, prof); launch_pass<8, false>(b, t, 16, 8, true, st, prof); break;
             default: break;
         }
     } else {
         switch (log_n) {
-            case 12: launch_pass<12, true>(b, t, 12, 0, true, st); break;
-            case 13: launch_pass<6, true>(b, t, 13, 7, false, st); launch_pass<7, true>(b, t, 13, 0, true, st); break;
-            case 14: launch_pass<7, true>(b, t, 14, 7, false, st); launch_pass<7, true>(b, t, 14, 0, true, st); break;
-            case 15: launch_pass<7, true>(b, t, 15, 8, false, st); launch_pass<8, true>(b, t, 15, 0, true, st); break;
-            case 16: launch_pass<8, true>(b, t, 16, 8, false, st); launch_pass<8, true>(b, t, 16, 0, true, st); break;
+            case 12: launch_pass<12, true>(b, t, 12, 0, true, st, prof); break;
+            case 13: launch_pass<6, true>(b, t, 13, 7, false, st, prof); launch_pass<7, true>(b, t, 13, 0, true, st, prof); break;
+            case 14: launch_pass<7, true>(b, t, 14, 7, false, st, prof); launch_pass<7, true>(b, t, 14, 0, true, st, prof); break;
+            case 15: launch_pass<7, true>(b, t, 15, 8, false, st, prof); launch_pass<8, true>(b, t, 15, 0, true, st, prof); break;
+            case 16: launch_pass<8, true>(b, t, 16, 8, false, st, prof); launch_pass<8, true>(b, t, 16, 0, true, st, prof); break;
             default: break;
         }
     }

@@ -16,7 +16,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#define PFT_MAX_POLYS 64
+#define PFT_MAX_POLYS 128  // polynomials per NTT launch
+#define PFT_MAX_ITEMS 64   // ciphertexts per batched launch
+#define PFT_SMALL_POLYS 8  // operands of the small elementwise kernels
 
 struct DevMod {
     uint64_t q;
@@ -34,25 +36,43 @@ struct TwPair {
     uint64_t wp;  // floor(w * 2^64 / q)
 };
 
-// A set of RNS polynomials processed by one launch.  Limb i (0 <= i <
-// n_limbs) of polynomial p sits at row r(i) = i + (i >= gap_at ? gap_len : 0)
+// A set of RNS polynomials processed by one NTT launch.  Limb i (0 <= i <
+// n_limbs) of polynomial p sits at row r = i + (i >= gap_at[p] ? gap_len[p] : 0)
 // of ptr[p] (rows are N words apart); row r is reduced modulo modulus index
 // r < split ? off0 + r : off1 + (r - split).
 struct PolyBatch {
     uint64_t* ptr[PFT_MAX_POLYS];
+    uint8_t gap_at[PFT_MAX_POLYS];
+    uint8_t gap_len[PFT_MAX_POLYS];
     uint32_t n_polys;
     uint32_t n_limbs;
-    uint32_t gap_at, gap_len;
     uint32_t split, off0, off1;
-    uint32_t pad;
 };
 
-__device__ __forceinline__ uint32_t pb_row(const PolyBatch& b, uint32_t i) {
-    return i + (i >= b.gap_at ? b.gap_len : 0u);
+__device__ __forceinline__ uint32_t pb_row(const PolyBatch& b, uint32_t p, uint32_t i) {
+    return i + (i >= b.gap_at[p] ? (uint32_t)b.gap_len[p] : 0u);
 }
 __device__ __forceinline__ uint32_t pb_mod(const PolyBatch& b, uint32_t row) {
     return row < b.split ? b.off0 + row : b.off1 + (row - b.split);
 }
+
+// Up to eight polynomials of n_limbs consecutive rows starting at row
+// `first`, same modulus rule as PolyBatch (small elementwise launches).
+struct SmallBatch {
+    uint64_t* ptr[PFT_SMALL_POLYS];
+    uint32_t n_polys;
+    uint32_t n_limbs;
+    uint32_t first;
+    uint32_t split, off0, off1;
+};
+__device__ __forceinline__ uint32_t sb_mod(const SmallBatch& b, uint32_t row) {
+    return row < b.split ? b.off0 + row : b.off1 + (row - b.split);
+}
+
+// Per-ciphertext device pointers of a batched launch.
+struct ItemPtrs {
+    uint64_t* p[PFT_MAX_ITEMS];
+};
 
 __device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) { return __umul64hi(a, b); }
 

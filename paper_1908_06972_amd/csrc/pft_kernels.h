@@ -12,40 +12,50 @@ struct DevTables {
     TwPair* tw_inv;   // [L+K][N]: psi^-brv(k)
 };
 
+// Optional per-launch timing: begin/end bracket one kernel launch with HIP
+// events on the launch stream and record its algorithmic traffic and work.
+enum ProfKernel : int {
+    PK_NTT_FWD = 0, PK_NTT_INV = 1, PK_MODUP = 2, PK_KEY_INNER = 3, PK_MODDOWN_CONV = 4,
+    PK_MODDOWN_FINAL = 5, PK_TENSOR = 6, PK_AUTOMORPHISM = 7, PK_RESCALE = 8, PK_ELEMENTWISE = 9, PK_COUNT = 10
+};
+struct ProfHook {
+    virtual void begin(int kid) = 0;
+    virtual void end(int kid, double bytes, double ops) = 0;
+    virtual ~ProfHook() {}
+};
+
 bool ntt_supported(uint32_t log_n);
-void launch_ntt(const PolyBatch& b, const DevTables& t, uint32_t log_n, bool inverse, hipStream_t st);
+void launch_ntt(const PolyBatch& b, const DevTables& t, uint32_t log_n, bool inverse, hipStream_t st,
+                ProfHook* prof = nullptr);
 
 // ---- elementwise kernels (ckks.hip) --------------------------------------
-// Signed small/integer polynomial x ([N] int64, device) reduced into every
-// limb of `out`.
-void launch_int_to_rns(const int64_t* x, const PolyBatch& out, const DevTables& t, uint32_t log_n, hipStream_t st);
+// Signed integer polynomials x ([n_polys][N] int64, device) reduced into
+// every limb of `out` (polynomial p from x + p N).
+void launch_int_to_rns(const int64_t* x, const SmallBatch& out, const DevTables& t, uint32_t log_n, hipStream_t st);
 
-// Limb-wise ops on NTT-domain data.  Each operand is a PolyBatch with the
-// same shape; modulus mapping taken from `out`.
+// Limb-wise ops on NTT-domain data.  Operands share the shape of `out`; the
+// modulus mapping is taken from `out`.
 enum EwOp : uint32_t {
-    EW_ADD = 0,       // out = a + b
-    EW_SUB = 1,       // out = a - b
-    EW_MUL = 2,       // out = a * b
-    EW_MULADD = 3,    // out = a * b + c
+    EW_ADD = 0,         // out = a + b
+    EW_SUB = 1,         // out = a - b
+    EW_MUL = 2,         // out = a * b
+    EW_MULADD = 3,      // out = a * b + c
     EW_NEG_MULADD = 4,  // out = -(a * b) + c
-    EW_COPY = 5,      // out = a
+    EW_COPY = 5,        // out = a
 };
-void launch_ew(EwOp op, const PolyBatch& out, const PolyBatch& a, const PolyBatch* b, const PolyBatch* c,
+void launch_ew(EwOp op, const SmallBatch& out, const SmallBatch& a, const SmallBatch* b, const SmallBatch* c,
                const DevTables& t, uint32_t log_n, hipStream_t st);
-// out = a * const_r (Shoup) per limb, consts indexed by limb: (w, w') pairs on device
-void launch_mul_const(const PolyBatch& out, const PolyBatch& a, const TwPair* consts, const DevTables& t,
+// out = a * consts[limb] (Shoup pairs on the device)
+void launch_mul_const(const SmallBatch& out, const SmallBatch& a, const TwPair* consts, const DevTables& t,
                       uint32_t log_n, hipStream_t st);
 
-// HMUL tensor: d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1 over `level` limbs.
-void launch_tensor(const uint64_t* a, const uint64_t* b, uint64_t* d0, uint64_t* d1, uint64_t* d2, uint32_t level,
-                   const DevTables& t, uint32_t log_n, hipStream_t st);
+// ---- batched kernels: item z uses pointers [z] and workspace base + z*stride
+struct WsRef {
+    uint64_t* base;
+    uint64_t stride;  // words
+};
+#define PFT_NO_OFFSET (~0ull)
 
-// NTT-domain automorphism X -> X^kappa: out[k] = in[perm(k)] for n_limbs of
-// n_polys polynomials of a [n_polys][level][N] array.
-void launch_automorphism(const uint64_t* in, uint64_t* out, uint32_t n_polys, uint32_t level, uint64_t kappa,
-                         uint32_t log_n, hipStream_t st);
-
-// Key switching pieces.
 struct KsConsts {
     const TwPair* modup_hatinv;   // [L][dnum][alpha]   indexed by (level-1, j, ii)
     const uint64_t* modup_c;      // [L][dnum][alpha][L+K] Montgomery form, row = target row
@@ -54,25 +64,33 @@ struct KsConsts {
     const TwPair* down_pinv;      // [L]
     uint32_t L, K, dnum, alpha;
 };
-// ModUp base conversion: d_coef [level][N] -> ext [beta][level+K][N]
-// (coefficient form; rows inside digit j of ext_j are left untouched).
-void launch_modup(const uint64_t* d_coef, uint64_t* ext, uint32_t level, const KsConsts& kc, const DevTables& t,
-                  uint32_t log_n, hipStream_t st);
-// acc [2][level+K][N] = sum_j ext_j (or d_ntt on digit rows) * key_j (Montgomery)
-void launch_key_inner(const uint64_t* d_ntt, const uint64_t* ext, const uint64_t* key, uint64_t* acc, uint32_t level,
-                      const KsConsts& kc, const DevTables& t, uint32_t log_n, hipStream_t st);
-// ModDown conversion: acc special rows (coefficient form) -> conv [2][level][N] coefficient form
-void launch_moddown_conv(const uint64_t* acc, uint64_t* conv, uint32_t level, const KsConsts& kc, const DevTables& t,
-                         uint32_t log_n, hipStream_t st);
-// out_b[i] = (acc_b[i] - conv_b[i]) P^-1 + add_b[i]   (add may be null; add1 null -> no add on poly 1)
-void launch_moddown_final(const uint64_t* acc, const uint64_t* conv, const uint64_t* add0, const uint64_t* add1,
-                          uint64_t* out, uint32_t level, const KsConsts& kc, const DevTables& t, uint32_t log_n,
-                          hipStream_t st);
 
-// Rescale: last (coefficient form, [2][N]) -> tmp [2][level-1][N] holding
-// ((r + h) mod q_last) - h reduced mod q_k (h = (q_last-1)/2 or 0).
-void launch_rescale_expand(const uint64_t* last, uint64_t* tmp, uint32_t level, uint32_t mode, const DevTables& t,
+// d [3][level][N] at ws_z + off_d from ciphertexts a_z, b_z.
+void launch_tensor_b(uint32_t n, const ItemPtrs& a, const ItemPtrs& b, WsRef ws, uint64_t off_d, uint32_t level,
+                     const DevTables& t, uint32_t log_n, hipStream_t st);
+void launch_copy_rows_b(uint32_t n, const ItemPtrs& src, uint64_t src_off, const ItemPtrs& dst, uint64_t dst_off,
+                        uint32_t rows, uint32_t log_n, hipStream_t st);
+// NTT-domain X -> X^kappa of `rows` rows of in_z into ws_z + off_out.
+void launch_automorphism_b(uint32_t n, const ItemPtrs& in, uint32_t rows, WsRef ws, uint64_t off_out, uint64_t kappa,
                            uint32_t log_n, hipStream_t st);
-// out_b[k] = (c_b[k] - tmp_b[k]) * q_last^-1 (consts [level-1] pairs)
-void launch_rescale_final(const uint64_t* c, const uint64_t* tmp, uint64_t* out, uint32_t level,
-                          const TwPair* qinv, const DevTables& t, uint32_t log_n, hipStream_t st);
+// ModUp base conversion: d (coefficient form) -> ext [beta][level+K][N].
+void launch_modup_b(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, uint32_t level, const KsConsts& kc,
+                    const DevTables& t, uint32_t log_n, hipStream_t st);
+// acc [2][level+K][N] = sum_j x_j * key_j  (key: [dnum][2][L+K][N], Montgomery form)
+void launch_key_inner_b(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, uint64_t off_acc, const uint64_t* key,
+                        uint32_t level, const KsConsts& kc, const DevTables& t, uint32_t log_n, hipStream_t st);
+// acc special rows (coefficient form) -> conv [2][level][N] (coefficient form)
+void launch_moddown_conv_b(uint32_t n, WsRef ws, uint64_t off_acc, uint64_t off_conv, uint32_t level,
+                           const KsConsts& kc, const DevTables& t, uint32_t log_n, hipStream_t st);
+// out_z[b][i] = (acc_b[i] - conv_b[i]) P^-1 (+ ws rows at off_add_b unless PFT_NO_OFFSET)
+void launch_moddown_final_b(uint32_t n, WsRef ws, uint64_t off_acc, uint64_t off_conv, uint64_t off_add0,
+                            uint64_t off_add1, const ItemPtrs& out, uint32_t level, const KsConsts& kc,
+                            const DevTables& t, uint32_t log_n, hipStream_t st);
+// RESCALE pieces (see ckks.hip)
+void launch_rescale_expand_b(uint32_t n, WsRef ws, uint64_t off_last, uint64_t off_tmp, uint32_t level, uint32_t mode,
+                             const DevTables& t, uint32_t log_n, hipStream_t st);
+void launch_rescale_final_b(uint32_t n, const ItemPtrs& c, WsRef ws, uint64_t off_tmp, const ItemPtrs& out,
+                            uint32_t level, const TwPair* qinv, const DevTables& t, uint32_t log_n, hipStream_t st);
+// ws_z[off_out] = ws_z[off_a] + ws_z[off_b] over [2][level][N]
+void launch_add_ct_b(uint32_t n, WsRef ws, uint64_t off_a, uint64_t off_b, uint64_t off_out, uint32_t level,
+                     const DevTables& t, uint32_t log_n, hipStream_t st);

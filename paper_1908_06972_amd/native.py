@@ -77,8 +77,12 @@ SIGNATURES = [
     ("pft_rotate_batch", [_vp, ctypes.c_uint32, ctypes.POINTER(CtDesc), ctypes.c_int32, ctypes.POINTER(CtDesc)],
      ctypes.c_int),
     ("pft_total_sum", [_vp, ctypes.POINTER(CtDesc), ctypes.c_uint32, ctypes.POINTER(CtDesc)], ctypes.c_int),
+    ("pft_total_sum_batch", [_vp, ctypes.c_uint32, ctypes.POINTER(CtDesc), ctypes.c_uint32, ctypes.POINTER(CtDesc)],
+     ctypes.c_int),
     ("pft_ntt_forward", [_vp, _vp, ctypes.c_uint32, ctypes.c_uint32], ctypes.c_int),
     ("pft_ntt_inverse", [_vp, _vp, ctypes.c_uint32, ctypes.c_uint32], ctypes.c_int),
+    ("pft_prof_enable", [_vp, ctypes.c_uint32], ctypes.c_int),
+    ("pft_prof_read", [_vp, ctypes.c_uint32, _dblp, _u64p, _dblp, _dblp], ctypes.c_int),
     ("pft_encode", [_vp, _dblp, _dblp, ctypes.c_uint32, ctypes.c_double, _i64p], ctypes.c_int),
     ("pft_decode", [_vp, _u64p, ctypes.c_uint32, ctypes.c_double, ctypes.c_uint32, _dblp, _dblp], ctypes.c_int),
 ]

@@ -139,6 +139,29 @@ def test_total_sum_parity(c1):
     w.assert_same(w.ctx.total_sum(g, 4), C.total_sum(w.op, o, 4, keys))
 
 
+def test_batched_ops_mixed_levels(c2):
+    """Batched HMult+relin, rescale, rotate and TotalSum over ciphertexts of
+    mixed levels (3..8) equal the oracle element by element."""
+    w = c2
+    lv = [8, 3, 6, 8, 5, 4, 7, 3]
+    a = [w.encrypt_pair(w.random_plain(1100 + i), l, 1200 + i) for i, l in enumerate(lv)]
+    b = [w.encrypt_pair(w.random_plain(1300 + i), l, 1400 + i) for i, l in enumerate(lv)]
+    prod = w.ctx.mul_relin_batch([x[0] for x in a], [x[0] for x in b])
+    oprod = [C.hmul_relin(w.op, x[1], y[1], w.rlk) for x, y in zip(a, b)]
+    for g, o in zip(prod, oprod):
+        w.assert_same(g, o)
+    rs = w.ctx.rescale_batch(prod)
+    ors = [C.rescale(w.op, o) for o in oprod]
+    for g, o in zip(rs, ors):
+        w.assert_same(g, o)
+    rot = w.ctx.rotate_batch(rs, 3)
+    for g, o in zip(rot, ors):
+        w.assert_same(g, C.rotate(w.op, o, 3, w.rot[3]))
+    ts = w.ctx.total_sum_batch(rs[:3], 2)
+    for g, o in zip(ts, ors[:3]):
+        w.assert_same(g, C.total_sum(w.op, o, 2, {1: w.rot[1]}))
+
+
 def test_plain_ops_parity(c2):
     w = c2
     lvl = 6
