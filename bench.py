@@ -44,6 +44,177 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+class Roctx:
+    """roctxProfilerResume/Pause around the timed region, so that a
+    `rocprofv3 --selected-regions` run profiles exactly the timed steps.
+    Without the profiler these calls do nothing."""
+
+    def __init__(self):
+        import ctypes
+        self.lib = None
+        for name in ("/opt/rocm/lib/librocprofiler-sdk-roctx.so.1", "librocprofiler-sdk-roctx.so.1",
+                     "librocprofiler-sdk-roctx.so"):
+            try:
+                self.lib = ctypes.CDLL(name)
+                break
+            except OSError:
+                continue
+        log("roctx: %s" % ("loaded" if self.lib is not None else "not found (profiler regions unavailable)"))
+        if self.lib is not None:
+            for fn in ("roctxProfilerResume", "roctxProfilerPause"):
+                getattr(self.lib, fn).argtypes = [ctypes.c_uint64]
+                getattr(self.lib, fn).restype = ctypes.c_int
+
+    def resume(self):
+        if self.lib is not None:
+            rc = self.lib.roctxProfilerResume(0)
+            if rc:
+                log("roctxProfilerResume returned %d" % rc)
+
+    def pause(self):
+        if self.lib is not None:
+            rc = self.lib.roctxProfilerPause(0)
+            if rc:
+                log("roctxProfilerPause returned %d" % rc)
+
+
+# kernel family -> source files whose text determines the kernel (for the
+# validity of stored counter figures)
+FAMILY_SOURCES = {0: ["ntt.hip", "pft_device.h"], 1: ["ntt.hip", "pft_device.h"]}
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+CSRC = os.path.join(ROOT, "paper_1908_06972_amd", "csrc")
+
+
+def source_sha(kid):
+    import hashlib
+    h = hashlib.sha256()
+    for f in FAMILY_SOURCES.get(kid, ["ckks.hip", "pft_device.h"]):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_profile(kernel, kid):
+    """Counter figures of `kernel` recorded under profiles/ (a `pft-profile:`
+    JSON line), if they were taken on the current kernel source."""
+    if not os.path.isdir(PROFILE_DIR):
+        return None
+    sha = source_sha(kid)
+    for f in sorted(os.listdir(PROFILE_DIR)):
+        if not f.endswith(".md"):
+            continue
+        for line in open(os.path.join(PROFILE_DIR, f)):
+            if line.startswith("pft-profile: "):
+                rec = json.loads(line[len("pft-profile: "):])
+                if rec.get("kernel") == kernel and rec.get("source_sha256") == sha:
+                    return rec
+    return None
+
+
+def _csv_rows(path):
+    import csv
+    with open(path) as fh:
+        return list(csv.DictReader(fh))
+
+
+def _find(dirpath, suffix):
+    for root, _, files in os.walk(dirpath):
+        for f in files:
+            if f.endswith(suffix):
+                return os.path.join(root, f)
+    raise FileNotFoundError("no *%s under %s" % (suffix, dirpath))
+
+
+def _step_dispatches(rows, key_id, key_start):
+    """Dispatches from the first HMUL tensor kernel on: the job steps (every
+    step of a run launches the same kernels with the same shapes), which
+    excludes key generation and encryption."""
+    rows = sorted(rows, key=lambda r: int(r[key_id]))
+    first = next((i for i, r in enumerate(rows) if "k_tensor_b" in r["Kernel_Name"]), None)
+    return rows[first:] if first is not None else []
+
+
+def summarize(trace_dir, fetch_dir, write_dir, kernel, kid, commands):
+    """Markdown summary of three rocprofv3 runs of bench.py: a kernel trace
+    (durations) and two counter runs (FETCH_SIZE with SQ_INSTS_VALU, then
+    WRITE_SIZE), each restricted to the dispatches of the job steps.  The
+    copy kernel k_copy_rows_b (8 bytes read and 8 written per work-item)
+    calibrates the byte counters."""
+    trace = _step_dispatches(_csv_rows(_find(trace_dir, "kernel_trace.csv")), "Dispatch_Id", "Start_Timestamp")
+    per = {}
+    for r in trace:
+        name = r["Kernel_Name"].replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "")
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        c, t = per.get(name, (0, 0.0))
+        per[name] = (c + 1, t + d)
+    total = sum(t for _, t in per.values())
+    out = ["# %s: job steps of bench.py (large ring, N=2^16, L=24, batch 16)" % kernel, ""]
+    out.append("Commands (from the repository root on the GPU box, after `export TMPDIR=/tmp`):")
+    out.append("")
+    for c in commands:
+        out.append("    " + c)
+    out.append("")
+    out.append("Kernel durations over the dispatches of the job steps (from the first HMUL tensor launch on; "
+               "every step launches the same kernels with the same shapes):")
+    out.append("")
+    out.append("| kernel | calls | total ms | avg us | share |")
+    out.append("|---|---|---|---|---|")
+    for name, (c, t) in sorted(per.items(), key=lambda kv: -kv[1][1])[:14]:
+        out.append("| %s | %d | %.2f | %.1f | %.1f%% |" % (name, c, t / 1e3, t / c, 100 * t / total))
+    short = kernel.replace("void ", "")
+    tgt = [v for k, v in per.items() if k == short]
+    avg_us = tgt[0][1] / tgt[0][0] if tgt else None
+
+    def per_dispatch(dirpath, counter):
+        rows = [r for r in _csv_rows(_find(dirpath, "counter_collection.csv"))]
+        rows = _step_dispatches(rows, "Dispatch_Id", "Start_Timestamp")
+        vals, cal = [], []
+        for r in rows:
+            if r.get("Counter_Name") != counter:
+                continue
+            v = float(r["Counter_Value"])
+            if short in r["Kernel_Name"]:
+                vals.append(v)
+            elif "k_copy_rows_b" in r["Kernel_Name"]:
+                cal.append((v, 8.0 * float(r["Grid_Size"])))
+        return vals, cal
+
+    fetch, fcal = per_dispatch(fetch_dir, "FETCH_SIZE")
+    valu, _ = per_dispatch(fetch_dir, "SQ_INSTS_VALU")
+    write, wcal = per_dispatch(write_dir, "WRITE_SIZE")
+    f_factor = sum(b for _, b in fcal) / (1024.0 * sum(v for v, _ in fcal)) if fcal else None
+    w_factor = sum(b for _, b in wcal) / (1024.0 * sum(v for v, _ in wcal)) if wcal else None
+    rec = {
+        "kernel": kernel,
+        "source_sha256": source_sha(kid),
+        "avg_launch_us": avg_us,
+        "fetch_kib_per_launch": sum(fetch) / len(fetch) if fetch else None,
+        "write_kib_per_launch": sum(write) / len(write) if write else None,
+        "fetch_calibration": f_factor,
+        "write_calibration": w_factor,
+        "valu_insts_per_launch": sum(valu) / len(valu) if valu else None,
+    }
+    if None not in (rec["fetch_kib_per_launch"], rec["write_kib_per_launch"], f_factor, w_factor):
+        rec["traffic_bytes_per_launch"] = 1024.0 * (rec["fetch_kib_per_launch"] * f_factor +
+                                                    rec["write_kib_per_launch"] * w_factor)
+    out.append("")
+    out.append("Counters of %s over the same dispatches (%d with FETCH_SIZE, %d with WRITE_SIZE):" %
+               (kernel, len(fetch), len(write)))
+    out.append("")
+    for k in ("avg_launch_us", "fetch_kib_per_launch", "write_kib_per_launch", "fetch_calibration",
+              "write_calibration", "traffic_bytes_per_launch", "valu_insts_per_launch"):
+        if rec.get(k) is not None:
+            out.append("- %s: %.6g" % (k, rec[k]))
+    out.append("")
+    out.append("Calibration factors: known bytes of k_copy_rows_b (a plain copy, 8 bytes read and 8 written per "
+               "work-item) divided by 1024 x its counted KiB; traffic = 1024 x (fetch x fetch factor + write x "
+               "write factor).  On this box FETCH_SIZE counts half the bytes the copy reads (factor 2.0) while "
+               "WRITE_SIZE is exact (factor 1.0).")
+    out.append("")
+    out.append("pft-profile: " + json.dumps(rec))
+    return "\n".join(out) + "\n"
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=int(os.environ.get("WORLD_SIZE", "1")))
@@ -53,6 +224,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="run only this many untimed steps (for rocprofv3) and exit")
+    ap.add_argument("--no-breakdown", action="store_true", help="skip the per-operation loops")
+    ap.add_argument("--summarize", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
+                    help="write the markdown summary of three rocprofv3 runs of the timed region and exit")
+    ap.add_argument("--kernel", default="k_ntt_pass<8, false>")
+    ap.add_argument("--family", type=int, default=0)
+    ap.add_argument("--commands", nargs="*", default=[])
     return ap.parse_args()
 
 
@@ -169,6 +346,9 @@ def cpu_baseline():
 
 def main():
     args = parse()
+    if args.summarize:
+        print(summarize(*args.summarize, args.kernel, args.family, args.commands), end="")
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (DESIGN.md describes how the "
               "work would shard); rerun with --gpus 1", file=sys.stderr)
@@ -207,7 +387,9 @@ def main():
 
     # timed region: only the dominant family is bracketed with events
     prof_enable(ctx, 1 << dom)
+    roctx = Roctx()
     sync()
+    roctx.resume()
     t0 = time.perf_counter()
     for i in range(args.steps):
         job_step(ctx, cts)
@@ -215,6 +397,7 @@ def main():
         log("timed step %d done" % i)
     sync()
     elapsed = time.perf_counter() - t0
+    roctx.pause()
     d_ms, d_cnt, d_bytes, d_ops = prof_read(ctx, dom)
     prof_enable(ctx, 0)
 
@@ -222,43 +405,59 @@ def main():
     ms_per_step = 1000.0 * elapsed / args.steps
     value = hmults / elapsed
 
-    # separately timed per-operation rates at level 24 on the same batch
-    reps = 3
-    t_mul = timed(lambda: ctx.mul_relin_batch(cts, cts), reps, sync)
-    t_rot = timed(lambda: ctx.rotate_batch(cts, 1), reps, sync)
-    t_rs = timed(lambda: ctx.rescale_batch(cts), reps, sync)
-    polys = torch.empty((2 * args.batch, lp.L, lp.n), dtype=torch.int64, device="cuda")
-    for i, c in enumerate(cts):
-        polys[2 * i:2 * i + 2].copy_(c.data)
-    t_ntt = timed(lambda: ctx.ntt_forward(polys, lp.L), reps, sync)
-    t_intt = timed(lambda: ctx.ntt_inverse(polys, lp.L), reps, sync)
-    breakdown = {
-        "hmult_relin_per_s": args.batch / t_mul,
-        "rotate_per_s": args.batch / t_rot,
-        "rescale_per_s": args.batch / t_rs,
-        "ntt_per_s": 2 * args.batch / t_ntt,
-        "intt_per_s": 2 * args.batch / t_intt,
-        "limb_ntt_per_s": 2 * args.batch * lp.L / t_ntt,
-        "note": "level 24, batch of %d, per-operation loops after the timed region; ntt = forward NTT of one "
-                "24-limb polynomial" % args.batch,
-    }
+    breakdown = None
+    if not args.no_breakdown:
+        # separately timed per-operation rates at level 24 on the same batch
+        reps = 3
+        t_mul = timed(lambda: ctx.mul_relin_batch(cts, cts), reps, sync)
+        t_rot = timed(lambda: ctx.rotate_batch(cts, 1), reps, sync)
+        t_rs = timed(lambda: ctx.rescale_batch(cts), reps, sync)
+        polys = torch.empty((2 * args.batch, lp.L, lp.n), dtype=torch.int64, device="cuda")
+        for i, c in enumerate(cts):
+            polys[2 * i:2 * i + 2].copy_(c.data)
+        t_ntt = timed(lambda: ctx.ntt_forward(polys, lp.L), reps, sync)
+        t_intt = timed(lambda: ctx.ntt_inverse(polys, lp.L), reps, sync)
+        breakdown = {
+            "hmult_relin_per_s": args.batch / t_mul,
+            "rotate_per_s": args.batch / t_rot,
+            "rescale_per_s": args.batch / t_rs,
+            "ntt_per_s": 2 * args.batch / t_ntt,
+            "intt_per_s": 2 * args.batch / t_intt,
+            "limb_ntt_per_s": 2 * args.batch * lp.L / t_ntt,
+            "note": "level 24, batch of %d, per-operation loops after the timed region; ntt = forward NTT of one "
+                    "24-limb polynomial" % args.batch,
+        }
 
     avg_ms = d_ms / max(d_cnt, 1)
     gbs = d_bytes / (d_ms * 1e-3) / 1e9 if d_ms > 0 else 0.0
+    kname = KERNEL_NAMES.get(dom, FAMILIES[dom])
+    stored = stored_profile(kname, dom)
+    traffic = None
+    alu = None
+    if stored:
+        traffic = stored.get("traffic_bytes_per_launch")
+        if stored.get("valu_insts_per_launch") and avg_ms > 0:
+            # one wave-level VALU instruction = 64 lane-ops; peak issue is one
+            # wave instruction per CU per clock (4 SIMDs x 16 lanes)
+            lane_ops = stored["valu_insts_per_launch"] * 64.0
+            alu = {"achieved_gops": round(lane_ops / (avg_ms * 1e-3) / 1e9, 1), "peak_gops": ALU_PEAK_GOPS,
+                   "frac": round(lane_ops / (avg_ms * 1e-3) / 1e9 / ALU_PEAK_GOPS, 4),
+                   "source": "SQ_INSTS_VALU per launch from profiles/ over this launch time"}
     roofline = {
-        "kernel": KERNEL_NAMES.get(dom, FAMILIES[dom]),
+        "kernel": kname,
         "family": FAMILIES[dom],
         "bound": "hbm",
         "achieved": round(gbs, 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(gbs / HBM_PEAK_GBS, 4),
-        "traffic": None,
+        "traffic": traffic,
         "avg_launch_us": round(1000.0 * avg_ms, 2),
         "launches": d_cnt,
         "alg_bytes_per_launch": d_bytes / max(d_cnt, 1),
-        "alg_ops_per_launch": d_ops / max(d_cnt, 1),
+        "alg_butterflies_per_launch": d_ops / max(d_cnt, 1),
         "share_of_step": round(totals[dom][0] / step_total, 3) if step_total else None,
+        "alu": alu,
     }
 
     cpu = None
