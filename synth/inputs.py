@@ -18,7 +18,7 @@ ERR_BOUND = 19
 __all__ = [
     "rng", "ternary", "gaussian", "uniform_mod", "slots_uniform", "slots_unit",
     "plaintext_coeffs", "KeyDraws", "key_draws", "EncDraws", "enc_draws",
-    "switch_key_draws", "SIGMA", "ERR_BOUND",
+    "switch_key_draws", "SIGMA", "ERR_BOUND", "bow_documents", "bow_weights",
 ]
 
 
@@ -98,3 +98,28 @@ class EncDraws:
 def enc_draws(seed: int, n: int) -> EncDraws:
     g = rng(seed)
     return EncDraws(ternary(g, n), gaussian(g, n), gaussian(g, n))
+
+
+def bow_documents(seed: int, n_docs: int, vocab: int, w_min: int = 50, w_max: int = 500):
+    """Bag-of-words count vectors: per document a length w ~ U{w_min..w_max},
+    w tokens drawn as Zipf ranks r in 1..vocab with P(r) proportional to 1/r
+    (inverse-CDF sampling), mapped to word indices through a fixed seeded
+    permutation of the vocabulary.  Returns (counts [n_docs, vocab] int64,
+    w [n_docs] int64)."""
+    g = rng(seed)
+    perm = np.random.default_rng([seed, 7]).permutation(vocab)
+    cdf = np.cumsum(1.0 / np.arange(1, vocab + 1))
+    cdf /= cdf[-1]
+    counts = np.zeros((n_docs, vocab), dtype=np.int64)
+    lengths = g.integers(w_min, w_max + 1, size=n_docs)
+    for d in range(n_docs):
+        ranks = np.searchsorted(cdf, g.random(int(lengths[d])), side="right")
+        np.add.at(counts[d], perm[np.minimum(ranks, vocab - 1)], 1)
+    return counts, lengths.astype(np.int64)
+
+
+def bow_weights(seed: int, vocab: int, dim: int, classes: int, sigma: float = 0.1):
+    """Embedding H [vocab, dim] and classifier O [dim, classes], entries
+    N(0, sigma^2) in fp64."""
+    g = rng(seed)
+    return g.normal(0.0, sigma, (vocab, dim)), g.normal(0.0, sigma, (dim, classes))
