@@ -164,6 +164,44 @@ int pft_rotate_batch(pft_ctx* ctx, uint32_t n, const pft_ct* in, int32_t step, p
 int pft_total_sum(pft_ctx* ctx, const pft_ct* in, uint32_t n_slots, pft_ct* out);
 int pft_total_sum_batch(pft_ctx* ctx, uint32_t n, const pft_ct* in, uint32_t n_slots, pft_ct* out);
 
+/* ---- constant multiplication -------------------------------------------
+ * out = in * m with the integer constant m = round(value * q_{level-1})
+ * (half away from zero), i.e. HMULPLAIN by the constant plaintext whose
+ * slots all equal `value` at scale q_{level-1}; out->scale = in->scale *
+ * q_{level-1}, so a following RESCALE restores in->scale.  |value| < 4.
+ * Used for the 1/w average of Sec. 4.1.  Synchronizes (per-call constants). */
+int pft_mul_const(pft_ctx* ctx, const pft_ct* in, double value, pft_ct* out);
+int pft_mul_const_batch(pft_ctx* ctx, uint32_t n, const pft_ct* in, const double* values, pft_ct* out);
+
+/* ---- PtMatVec: plaintext matrix x encrypted vector (Sec. 4.1, v H and h O)
+ * Matrix M (n_o x n_in*n_i, row-major doubles) acting on an input split over
+ * n_in ciphertexts whose t = N/2 slots hold a vector periodic with period
+ * n_i (n_o | n_i | t, powers of two).  Diagonal method, baby-step/giant-step
+ * form with b = 2^ceil(log2(n_o)/2) baby steps and G = n_o/b giant steps:
+ *   D^c_i[k] = M[k mod n_o][c n_i + (k+i) mod n_i],   i = g b + r,
+ *   P^c_{g,r} = D^c_{gb+r} rotated right by g b (pre-rotated, encoded at
+ *               scale q_{level-1}),
+ *   u = sum_g ROTATE(sum_c sum_r P^c_{g,r} * ROTATE(v_c, r), g b),
+ *   y = u + ROTATE(u, n_o) + ... (steps n_o 2^s while n_o 2^s < n_i),
+ * so slot k of y holds (M v)_{k mod n_o}.  Rotation keys for 1..b-1, g b and
+ * n_o 2^s must exist.  No rescale: y->scale = v->scale * pt_scale.
+ * pft_ptmat_create encodes the pre-rotated diagonals on the host (encoder of
+ * pft_encode) at scale q_{level-1}; pft_ptmat_create_from_coeffs takes the
+ * integer plaintexts P^c_{g,r} directly, layout [n_in][G][b][N] int64.
+ * The matrix lives in device memory of its context until the context is
+ * destroyed. */
+typedef struct pft_ptmat pft_ptmat;
+int pft_ptmat_create(pft_ctx* ctx, const double* M, uint32_t n_o, uint32_t n_i, uint32_t n_in, uint32_t level,
+                     pft_ptmat** out);
+int pft_ptmat_create_from_coeffs(pft_ctx* ctx, const int64_t* coeffs, uint32_t n_o, uint32_t n_i, uint32_t n_in,
+                                 uint32_t level, double pt_scale, pft_ptmat** out);
+/* n_o, n_i, n_in, level, b, G (host array of 6). */
+int pft_ptmat_info(const pft_ptmat* m, uint32_t* info);
+void pft_ptmat_destroy(pft_ptmat* m);
+/* in: n_docs * n_in ciphertexts, document-major, all at the matrix level;
+ * out: n_docs ciphertexts (caller memory, 2*level*N each). */
+int pft_ptmatvec(pft_ctx* ctx, const pft_ptmat* m, uint32_t n_docs, const pft_ct* in, pft_ct* out);
+
 /* ---- transforms on raw RNS polynomials ---------------------------------
  * data: device [n_polys][n_limbs][N], limb i of every polynomial mod q_i
  * (n_limbs <= L).  Forward maps coefficient form to the NTT domain of the

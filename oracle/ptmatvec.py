@@ -118,10 +118,13 @@ def ptmatvec(params, inputs, plains, n_o, n_i, rot_keys, pt_scale):
 
 
 def constant_plain(params, value, level):
-    """Integer constant polynomial round(value * q_{level-1}) (every slot
-    equals value at scale q_{level-1}) and that scale."""
-    q = params.q[level - 1]
-    return np.array([int(round(value * q))] + [0] * (params.n - 1), dtype=np.int64), float(q)
+    """Integer constant polynomial round(value * q_{level-1}), the product
+    taken in double precision and rounded half away from zero (every slot
+    equals value at scale q_{level-1}), and that scale."""
+    qs = float(params.q[level - 1])
+    x = value * qs
+    m = int(np.floor(x + 0.5)) if x >= 0 else -int(np.floor(-x + 0.5))  # round half away from zero
+    return np.array([m] + [0] * (params.n - 1), dtype=np.int64), qs
 
 
 def inference_plain(v, H, O, w):

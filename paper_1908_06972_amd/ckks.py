@@ -250,6 +250,37 @@ class Context:
         N.check(self.lib.pft_total_sum_batch(self.handle, len(a), A, n_slots, O))
         return [o.sync_from(O[i]) for i, o in enumerate(out)]
 
+    def mul_const_batch(self, a, values, out=None):
+        out = out or [self.empty_ct(x.level) for x in a]
+        A, O = self._arr(a), self._arr(out)
+        vals = np.ascontiguousarray(values, dtype=np.float64)
+        N.check(self.lib.pft_mul_const_batch(self.handle, len(a), A, N.dblp(vals), O))
+        return [o.sync_from(O[i]) for i, o in enumerate(out)]
+
+    def ptmat(self, M, n_o, n_i, n_in, level):
+        """Plaintext matrix from doubles (library encoder)."""
+        h = ctypes.c_void_p()
+        Mc = np.ascontiguousarray(M, dtype=np.float64)
+        assert Mc.shape == (n_o, n_in * n_i)
+        N.check(self.lib.pft_ptmat_create(self.handle, N.dblp(Mc), n_o, n_i, n_in, level, ctypes.byref(h)))
+        return PtMat(self, h)
+
+    def ptmat_from_coeffs(self, coeffs, n_o, n_i, n_in, level, pt_scale):
+        """Plaintext matrix from integer plaintexts [n_in][G][b][N]."""
+        h = ctypes.c_void_p()
+        c = np.ascontiguousarray(coeffs, dtype=np.int64)
+        N.check(self.lib.pft_ptmat_create_from_coeffs(self.handle, N.i64p(c), n_o, n_i, n_in, level,
+                                                      float(pt_scale), ctypes.byref(h)))
+        return PtMat(self, h)
+
+    def ptmatvec(self, mat, inputs, out=None):
+        """inputs: list over documents of lists of n_in ciphertexts."""
+        flat = [c for doc in inputs for c in doc]
+        out = out or [self.empty_ct(doc[0].level) for doc in inputs]
+        A, O = self._arr(flat), self._arr(out)
+        N.check(self.lib.pft_ptmatvec(self.handle, mat.handle, len(inputs), A, O))
+        return [o.sync_from(O[i]) for i, o in enumerate(out)]
+
     def ntt_forward(self, data: torch.Tensor, n_limbs: int):
         n_polys = data.numel() // (n_limbs * self.params.n)
         N.check(self.lib.pft_ntt_forward(self.handle, ctypes.c_void_p(data.data_ptr()), n_polys, n_limbs))
@@ -257,6 +288,20 @@ class Context:
     def ntt_inverse(self, data: torch.Tensor, n_limbs: int):
         n_polys = data.numel() // (n_limbs * self.params.n)
         N.check(self.lib.pft_ntt_inverse(self.handle, ctypes.c_void_p(data.data_ptr()), n_polys, n_limbs))
+
+
+class PtMat:
+    def __init__(self, ctx, handle):
+        self.ctx = ctx
+        self.handle = handle
+        info = np.zeros(6, dtype=np.uint32)
+        N.check(ctx.lib.pft_ptmat_info(handle, info.ctypes.data_as(N._u32p)))
+        self.n_o, self.n_i, self.n_in, self.level, self.b, self.G = (int(x) for x in info)
+
+    def __del__(self):
+        if getattr(self, "handle", None) is not None and N._lib is not None:
+            N._lib.pft_ptmat_destroy(self.handle)
+            self.handle = None
 
 
 def to_device_u64(a: np.ndarray, device) -> torch.Tensor:

@@ -205,8 +205,12 @@ struct pft_ctx {
     uint64_t* pk = nullptr;  // [2][L][N] (b, a), NTT domain
     SwitchKeyDev rlk;
     std::map<int32_t, SwitchKeyDev> rot;  // keyed by step mod N/2
-    uint64_t* ws = nullptr;
+    uint64_t* ws = nullptr;  // scratch of one operation (key switching etc.)
     size_t ws_bytes = 0;
+    uint64_t* aux = nullptr;  // buffers of composite operations (PtMatVec) that call other operations
+    size_t aux_bytes = 0;
+    TwPair* cbuf = nullptr;  // per-call constants (e.g. 1/w per document)
+    size_t cbuf_n = 0;
 };
 
 template <typename T>
@@ -239,6 +243,20 @@ static int ensure_ws(pft_ctx* c, size_t bytes) {
     hipError_t e = hipMalloc(&c->ws, bytes);
     if (e != hipSuccess) return fail(PFT_ENOMEM, "workspace hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
     c->ws_bytes = bytes;
+    return PFT_OK;
+}
+
+static int ensure_aux(pft_ctx* c, size_t bytes) {
+    if (c->aux_bytes >= bytes) return PFT_OK;
+    if (c->aux) {
+        HIPCK(hipStreamSynchronize(c->stream));
+        HIPCK(hipFree(c->aux));
+        c->aux = nullptr;
+        c->aux_bytes = 0;
+    }
+    hipError_t e = hipMalloc(&c->aux, bytes);
+    if (e != hipSuccess) return fail(PFT_ENOMEM, "aux hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    c->aux_bytes = bytes;
     return PFT_OK;
 }
 
@@ -363,6 +381,8 @@ extern "C" void pft_ctx_destroy(pft_ctx* c) {
     (void)hipStreamSynchronize(c->stream);
     for (void* p : c->allocs) (void)hipFree(p);
     if (c->ws) (void)hipFree(c->ws);
+    if (c->aux) (void)hipFree(c->aux);
+    if (c->cbuf) (void)hipFree(c->cbuf);
     delete c;
 }
 
@@ -1095,6 +1115,283 @@ extern "C" int pft_total_sum_batch(pft_ctx* c, uint32_t n, const pft_ct* in, uin
         }
         return PFT_OK;
     });
+}
+
+// ---------------------------------------------------------------------------
+// constant multiplication and PtMatVec (Sec. 4.1: v H and h O by HMULPLAIN,
+// HADD and ROTATE; diagonal method in baby-step/giant-step form)
+// ---------------------------------------------------------------------------
+static int64_t round_half_away(double x) { return (int64_t)(x >= 0 ? std::floor(x + 0.5) : -std::floor(-x + 0.5)); }
+
+extern "C" int pft_mul_const_batch(pft_ctx* c, uint32_t n, const pft_ct* in, const double* values, pft_ct* out) {
+    if (!c || !in || !values || !out) return fail(PFT_EINVAL, "null argument");
+    int r;
+    for (uint32_t i = 0; i < n; ++i) {
+        if ((r = check_ct(c, &in[i]))) return r;
+        if (!out[i].data) return fail(PFT_EINVAL, "null output");
+        if (!(std::fabs(values[i]) < 4.0)) return fail(PFT_EINVAL, "constant must satisfy |value| < 4");
+    }
+    const pft_params* P = c->P;
+    return for_level_groups(n, in, [&](const std::vector<uint32_t>& g) -> int {
+        const uint32_t l = in[g[0]].level, cnt = (uint32_t)g.size();
+        const double qs = (double)P->q[l - 1];
+        std::vector<TwPair> consts((size_t)cnt * l);
+        for (uint32_t z = 0; z < cnt; ++z) {
+            const int64_t m = round_half_away(values[g[z]] * qs);
+            for (uint32_t i = 0; i < l; ++i) {
+                const uint64_t q = P->q[i];
+                const uint64_t v = m >= 0 ? (uint64_t)m % q : (q - ((0ull - (uint64_t)m) % q)) % q;
+                consts[(size_t)z * l + i] = pair(v, q);
+            }
+        }
+        if (c->cbuf_n < consts.size()) {
+            HIPCK(hipStreamSynchronize(c->stream));
+            if (c->cbuf) HIPCK(hipFree(c->cbuf));
+            c->cbuf = nullptr;
+            HIPCK(hipMalloc(&c->cbuf, consts.size() * sizeof(TwPair)));
+            c->cbuf_n = consts.size();
+        }
+        HIPCK(hipMemcpyAsync(c->cbuf, consts.data(), consts.size() * sizeof(TwPair), hipMemcpyHostToDevice,
+                             c->stream));
+        ItemPtrs I{}, O{};
+        for (uint32_t z = 0; z < cnt; ++z) {
+            I.p[z] = in[g[z]].data;
+            O.p[z] = out[g[z]].data;
+        }
+        launch_scale_const_b(cnt, I, O, c->cbuf, l, c->tabs, P->log_n, c->stream);
+        // the constants are a pageable host vector: wait before it goes away
+        HIPCK(hipStreamSynchronize(c->stream));
+        for (uint32_t z = 0; z < cnt; ++z) {
+            out[g[z]].level = l;
+            out[g[z]].scale = in[g[z]].scale * qs;
+        }
+        return PFT_OK;
+    });
+}
+
+extern "C" int pft_mul_const(pft_ctx* c, const pft_ct* in, double value, pft_ct* out) {
+    return pft_mul_const_batch(c, 1, in, &value, out);
+}
+
+struct pft_ptmat {
+    pft_ctx* ctx = nullptr;
+    uint32_t n_o = 0, n_i = 0, n_in = 0, level = 0, b = 0, G = 0;
+    double pt_scale = 0;
+    uint64_t* pt = nullptr;  // [G][n_in * b][level][N], NTT domain, times 2^64 mod q
+};
+
+static void bsgs_plan(uint32_t n_o, uint32_t* b, uint32_t* G) {
+    uint32_t lg = 0;
+    while ((1u << lg) < n_o) ++lg;
+    *b = 1u << ((lg + 1) / 2);
+    *G = n_o / *b;
+}
+
+static int ptmat_check(const pft_ctx* c, uint32_t n_o, uint32_t n_i, uint32_t n_in, uint32_t level) {
+    const uint32_t t = c->P->n / 2;
+    if (!n_o || (n_o & (n_o - 1)) || !n_i || (n_i & (n_i - 1)) || n_i > t || n_o > n_i)
+        return fail(PFT_EINVAL, "need powers of two n_o <= n_i <= N/2");
+    if (n_in < 1 || n_in > 64) return fail(PFT_EINVAL, "n_in must be in 1..64");
+    if (level < 2 || level > c->P->L) return fail(PFT_ELEVEL, "plaintext matrix level must be in 2..L");
+    return PFT_OK;
+}
+
+// coeffs: [n_in][G][b][N] integer plaintexts of the pre-rotated diagonals.
+static int ptmat_upload(pft_ctx* c, pft_ptmat* m, const int64_t* coeffs) {
+    const pft_params* P = c->P;
+    const uint32_t J = m->n_in * m->b, l = m->level;
+    const size_t N = P->n, words = (size_t)m->G * J * l * N;
+    int r;
+    if ((r = dalloc(c, &m->pt, words * 8))) return r;
+    if ((r = ensure_ws(c, (size_t)J * N * 8))) return r;
+    for (uint32_t g = 0; g < m->G; ++g) {
+        for (uint32_t cc = 0; cc < m->n_in; ++cc)
+            for (uint32_t rr = 0; rr < m->b; ++rr) {
+                const int64_t* src = coeffs + (((size_t)cc * m->G + g) * m->b + rr) * N;
+                if ((r = upload_i64(c, (int64_t*)c->ws + ((size_t)cc * m->b + rr) * N, src, N))) return r;
+            }
+        uint64_t* dst = m->pt + (size_t)g * J * l * N;
+        for (uint32_t j0 = 0; j0 < J; j0 += PFT_SMALL_POLYS) {
+            const uint32_t nj = std::min<uint32_t>(PFT_SMALL_POLYS, J - j0);
+            SmallBatch out = sb_rows(P, dst + (size_t)j0 * l * N, nj, l, l);
+            launch_int_to_rns((const int64_t*)c->ws + (size_t)j0 * N, out, c->tabs, P->log_n, c->stream);
+            launch_mul_const(out, out, c->to_mont, c->tabs, P->log_n, c->stream);  // [0, q) kept; NTT below
+        }
+        ntt_rows(c, dst, J, l, l, false);
+        HIPCK(hipStreamSynchronize(c->stream));  // the staged host rows are reused for the next g
+    }
+    return PFT_OK;
+}
+
+extern "C" int pft_ptmat_create_from_coeffs(pft_ctx* c, const int64_t* coeffs, uint32_t n_o, uint32_t n_i,
+                                            uint32_t n_in, uint32_t level, double pt_scale, pft_ptmat** out) {
+    if (!c || !coeffs || !out) return fail(PFT_EINVAL, "null argument");
+    int r;
+    if ((r = ptmat_check(c, n_o, n_i, n_in, level))) return r;
+    auto* m = new pft_ptmat();
+    m->ctx = c;
+    m->n_o = n_o;
+    m->n_i = n_i;
+    m->n_in = n_in;
+    m->level = level;
+    m->pt_scale = pt_scale;
+    bsgs_plan(n_o, &m->b, &m->G);
+    if ((r = ptmat_upload(c, m, coeffs))) {
+        delete m;
+        return r;
+    }
+    *out = m;
+    return PFT_OK;
+}
+
+extern "C" int pft_ptmat_create(pft_ctx* c, const double* M, uint32_t n_o, uint32_t n_i, uint32_t n_in,
+                                uint32_t level, pft_ptmat** out) {
+    if (!c || !M || !out) return fail(PFT_EINVAL, "null argument");
+    int r;
+    if ((r = ptmat_check(c, n_o, n_i, n_in, level))) return r;
+    const pft_params* P = c->P;
+    const uint32_t t = P->n / 2, cols = n_in * n_i;
+    uint32_t b, G;
+    bsgs_plan(n_o, &b, &G);
+    const double pt_scale = (double)P->q[level - 1];
+    std::vector<int64_t> coeffs((size_t)n_in * G * b * P->n);
+    std::vector<double> diag(t), zero(t, 0.0);
+    for (uint32_t cc = 0; cc < n_in; ++cc)
+        for (uint32_t g = 0; g < G; ++g)
+            for (uint32_t rr = 0; rr < b; ++rr) {
+                const uint32_t i = g * b + rr;
+                // P^c_{g,r}[k] = D^c_i[(k - g b) mod t], D^c_i[k] = M[k mod n_o][c n_i + (k + i) mod n_i]
+                for (uint32_t k = 0; k < t; ++k) {
+                    const uint32_t kk = (k + t - (g * b) % t) % t;
+                    diag[k] = M[(size_t)(kk % n_o) * cols + (size_t)cc * n_i + (kk + i) % n_i];
+                }
+                int64_t* dst = coeffs.data() + (((size_t)cc * G + g) * b + rr) * P->n;
+                if ((r = pft_encode(P, diag.data(), zero.data(), t, pt_scale, dst))) return r;
+            }
+    return pft_ptmat_create_from_coeffs(c, coeffs.data(), n_o, n_i, n_in, level, pt_scale, out);
+}
+
+extern "C" void pft_ptmat_destroy(pft_ptmat* m) { delete m; }  // device rows are freed with the context
+
+extern "C" int pft_ptmat_info(const pft_ptmat* m, uint32_t* info) {
+    if (!m || !info) return fail(PFT_EINVAL, "null argument");
+    info[0] = m->n_o;
+    info[1] = m->n_i;
+    info[2] = m->n_in;
+    info[3] = m->level;
+    info[4] = m->b;
+    info[5] = m->G;
+    return PFT_OK;
+}
+
+static std::vector<uint32_t> ptmat_steps(const pft_ptmat* m) {
+    std::vector<uint32_t> st;
+    for (uint32_t r = 1; r < m->b; ++r) st.push_back(r);
+    for (uint32_t g = 1; g < m->G; ++g) st.push_back(g * m->b);
+    for (uint32_t s = m->n_o; s < m->n_i; s <<= 1) st.push_back(s);
+    return st;
+}
+
+static std::vector<pft_ct> cts_at(uint64_t* base, size_t stride, uint64_t off, uint32_t n, uint32_t level,
+                                  double scale) {
+    std::vector<pft_ct> v(n);
+    for (uint32_t z = 0; z < n; ++z) v[z] = pft_ct{base + z * stride + off, level, 0, scale};
+    return v;
+}
+
+extern "C" int pft_ptmatvec(pft_ctx* c, const pft_ptmat* m, uint32_t n_docs, const pft_ct* in, pft_ct* out) {
+    if (!c || !m || !in || !out) return fail(PFT_EINVAL, "null argument");
+    if (m->ctx != c) return fail(PFT_EINVAL, "plaintext matrix belongs to another context");
+    const pft_params* P = c->P;
+    const uint32_t l = m->level, J = m->n_in * m->b, lg = P->log_n;
+    int r;
+    for (uint32_t z = 0; z < n_docs; ++z) {
+        if (!out[z].data) return fail(PFT_EINVAL, "null output");
+        for (uint32_t cc = 0; cc < m->n_in; ++cc) {
+            const pft_ct& x = in[(size_t)z * m->n_in + cc];
+            if ((r = check_ct(c, &x))) return r;
+            if (x.level != l) return fail(PFT_ELEVEL, "input level %u differs from the matrix level %u", x.level, l);
+            if (!scales_match(x.scale, in[0].scale)) return fail(PFT_ESCALE, "inputs need equal scales");
+        }
+    }
+    for (uint32_t st : ptmat_steps(m))
+        if (!find_rot(c, (int32_t)st)) return fail(PFT_ENOKEY, "no rotation key for step %u", st);
+    if (n_docs == 0) return PFT_OK;
+    const double scale = in[0].scale;
+    const uint64_t ct_words = 2ull * l * P->n;
+    // per document: baby[n_in][b] | acc | tot | tmp
+    const uint64_t off_baby = 0, off_acc = (uint64_t)J * ct_words, off_tot = off_acc + ct_words,
+                   off_tmp = off_tot + ct_words, stride = off_tmp + ct_words;
+    if ((r = ensure_aux(c, (size_t)n_docs * stride * 8))) return r;
+    uint64_t* A = c->aux;
+    // inputs -> baby[c][0]
+    for (uint32_t z0 = 0; z0 < n_docs * m->n_in; z0 += PFT_MAX_ITEMS) {
+        const uint32_t cnt = std::min<uint32_t>(PFT_MAX_ITEMS, n_docs * m->n_in - z0);
+        ItemPtrs I{}, O{};
+        for (uint32_t u = 0; u < cnt; ++u) {
+            const uint32_t z = (z0 + u) / m->n_in, cc = (z0 + u) % m->n_in;
+            I.p[u] = in[z0 + u].data;
+            O.p[u] = A + z * stride + off_baby + (uint64_t)cc * m->b * ct_words;
+        }
+        launch_copy_rows_b(cnt, I, 0, O, 0, 2 * l, lg, c->stream);
+    }
+    // baby steps: baby[c][r] = ROTATE(baby[c][0], r)
+    for (uint32_t rr = 1; rr < m->b; ++rr) {
+        std::vector<pft_ct> src, dst;
+        for (uint32_t z = 0; z < n_docs; ++z)
+            for (uint32_t cc = 0; cc < m->n_in; ++cc) {
+                const uint64_t base = z * stride + off_baby + (uint64_t)cc * m->b * ct_words;
+                src.push_back(pft_ct{A + base, l, 0, scale});
+                dst.push_back(pft_ct{A + base + rr * ct_words, l, 0, scale});
+            }
+        if ((r = pft_rotate_batch(c, (uint32_t)src.size(), src.data(), (int32_t)rr, dst.data()))) return r;
+    }
+    // giant steps: tot = sum_g ROTATE(sum_{c,r} P_{g,c,r} baby[c][r], g b)
+    const WsRef ws{A, stride};
+    for (uint32_t g = 0; g < m->G; ++g) {
+        const uint64_t* ptg = m->pt + (size_t)g * J * l * P->n;
+        for (uint32_t z0 = 0; z0 < n_docs; z0 += 65535) {
+            const uint32_t cnt = std::min<uint32_t>(65535, n_docs - z0);
+            const WsRef w{A + z0 * stride, stride};
+            timed(c, PK_ELEMENTWISE, 8.0 * (double)cnt * ct_words * (J + 1) + 8.0 * J * l * P->n,
+                  (double)cnt * ct_words * J, [&] {
+                      launch_pt_dot_b(cnt, w, off_baby, ct_words, ptg, J, g == 0 ? off_tot : off_acc, l, c->tabs, lg,
+                                      c->stream);
+                  });
+        }
+        if (g == 0) continue;
+        std::vector<pft_ct> src = cts_at(A, stride, off_acc, n_docs, l, scale * m->pt_scale);
+        std::vector<pft_ct> dst = cts_at(A, stride, off_tmp, n_docs, l, scale * m->pt_scale);
+        if ((r = pft_rotate_batch(c, n_docs, src.data(), (int32_t)(g * m->b), dst.data()))) return r;
+        for (uint32_t z0 = 0; z0 < n_docs; z0 += 65535) {
+            const uint32_t cnt = std::min<uint32_t>(65535, n_docs - z0);
+            launch_add_ct_b(cnt, WsRef{A + z0 * stride, stride}, off_tot, off_tmp, off_tot, l, c->tabs, lg, c->stream);
+        }
+    }
+    // rotate-and-sum over the n_i / n_o blocks
+    for (uint32_t s = m->n_o; s < m->n_i; s <<= 1) {
+        std::vector<pft_ct> src = cts_at(A, stride, off_tot, n_docs, l, scale * m->pt_scale);
+        std::vector<pft_ct> dst = cts_at(A, stride, off_tmp, n_docs, l, scale * m->pt_scale);
+        if ((r = pft_rotate_batch(c, n_docs, src.data(), (int32_t)s, dst.data()))) return r;
+        for (uint32_t z0 = 0; z0 < n_docs; z0 += 65535) {
+            const uint32_t cnt = std::min<uint32_t>(65535, n_docs - z0);
+            launch_add_ct_b(cnt, WsRef{A + z0 * stride, stride}, off_tot, off_tmp, off_tot, l, c->tabs, lg, c->stream);
+        }
+    }
+    for (uint32_t z0 = 0; z0 < n_docs; z0 += PFT_MAX_ITEMS) {
+        const uint32_t cnt = std::min<uint32_t>(PFT_MAX_ITEMS, n_docs - z0);
+        ItemPtrs I{}, O{};
+        for (uint32_t u = 0; u < cnt; ++u) {
+            I.p[u] = A + (z0 + u) * stride + off_tot;
+            O.p[u] = out[z0 + u].data;
+        }
+        launch_copy_rows_b(cnt, I, 0, O, 0, 2 * l, lg, c->stream);
+    }
+    for (uint32_t z = 0; z < n_docs; ++z) {
+        out[z].level = l;
+        out[z].scale = scale * m->pt_scale;
+    }
+    return PFT_OK;
 }
 
 // ---------------------------------------------------------------------------

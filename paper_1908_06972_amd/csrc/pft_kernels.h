@@ -94,3 +94,9 @@ void launch_rescale_final_b(uint32_t n, const ItemPtrs& c, WsRef ws, uint64_t of
 // ws_z[off_out] = ws_z[off_a] + ws_z[off_b] over [2][level][N]
 void launch_add_ct_b(uint32_t n, WsRef ws, uint64_t off_a, uint64_t off_b, uint64_t off_out, uint32_t level,
                      const DevTables& t, uint32_t log_n, hipStream_t st);
+// PtMatVec inner sums: acc_z = sum_j baby_{z,j} * pt_j (pt in Montgomery form)
+void launch_pt_dot_b(uint32_t n, WsRef ws, uint64_t off_baby, uint64_t ct_words, const uint64_t* pt, uint32_t J,
+                     uint64_t off_acc, uint32_t level, const DevTables& t, uint32_t log_n, hipStream_t st);
+// out_z = in_z * consts[z][limb] (integer constant polynomial)
+void launch_scale_const_b(uint32_t n, const ItemPtrs& in, const ItemPtrs& out, const TwPair* consts, uint32_t level,
+                          const DevTables& t, uint32_t log_n, hipStream_t st);

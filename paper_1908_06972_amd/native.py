@@ -79,6 +79,16 @@ SIGNATURES = [
     ("pft_total_sum", [_vp, ctypes.POINTER(CtDesc), ctypes.c_uint32, ctypes.POINTER(CtDesc)], ctypes.c_int),
     ("pft_total_sum_batch", [_vp, ctypes.c_uint32, ctypes.POINTER(CtDesc), ctypes.c_uint32, ctypes.POINTER(CtDesc)],
      ctypes.c_int),
+    ("pft_mul_const", [_vp, ctypes.POINTER(CtDesc), ctypes.c_double, ctypes.POINTER(CtDesc)], ctypes.c_int),
+    ("pft_mul_const_batch", [_vp, ctypes.c_uint32, ctypes.POINTER(CtDesc), _dblp, ctypes.POINTER(CtDesc)],
+     ctypes.c_int),
+    ("pft_ptmat_create", [_vp, _dblp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                          ctypes.POINTER(_vp)], ctypes.c_int),
+    ("pft_ptmat_create_from_coeffs", [_vp, _i64p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                      ctypes.c_uint32, ctypes.c_double, ctypes.POINTER(_vp)], ctypes.c_int),
+    ("pft_ptmat_info", [_vp, _u32p], ctypes.c_int),
+    ("pft_ptmat_destroy", [_vp], None),
+    ("pft_ptmatvec", [_vp, _vp, ctypes.c_uint32, ctypes.POINTER(CtDesc), ctypes.POINTER(CtDesc)], ctypes.c_int),
     ("pft_ntt_forward", [_vp, _vp, ctypes.c_uint32, ctypes.c_uint32], ctypes.c_int),
     ("pft_ntt_inverse", [_vp, _vp, ctypes.c_uint32, ctypes.c_uint32], ctypes.c_int),
     ("pft_prof_enable", [_vp, ctypes.c_uint32], ctypes.c_int),
