@@ -253,9 +253,10 @@ def setup(batch):
     import synth as S
     from paper_1908_06972_amd import ckks as L
 
+    import torch
     cfg = S.CONFIGS["C3"]
     lp = L.Params.from_config(cfg)
-    ctx = L.Context(lp, 0)
+    ctx = L.Context(lp, 0, stream=torch.cuda.Stream())  # a non-null stream: graphs can be captured on it
     n = lp.n
     t0 = time.time()
     kd = S.key_draws(1, n, lp.q)
@@ -280,11 +281,41 @@ def setup(batch):
 
 
 def job_step(ctx, cts):
-    """One step of the workload over the batch; returns the final ciphertexts."""
+    """One step of the workload over the batch, eager calls with fresh
+    output buffers; returns the final ciphertexts."""
     cur = cts
     for _ in range(CHAIN_DEPTH):
         cur = ctx.rescale_batch(ctx.mul_relin_batch(cur, cur))
     return ctx.total_sum_batch(cur, ROT_SLOTS)
+
+
+class GraphStep:
+    """The same step with preallocated buffers, captured once in a HIP graph
+    and replayed: one graph launch per step instead of ~1000 kernel launches."""
+
+    def __init__(self, ctx, cts):
+        self.ctx, self.cts = ctx, cts
+        self.muls, self.rss = [], []
+        level = cts[0].level
+        for _ in range(CHAIN_DEPTH):
+            self.muls.append([ctx.empty_ct(level) for _ in cts])
+            self.rss.append([ctx.empty_ct(level - 1) for _ in cts])
+            level -= 1
+        self.out = [ctx.empty_ct(level) for _ in cts]
+        self.run()  # eager once: sizes the scratch the capture will use
+        ctx.synchronize()
+        self.graph = ctx.capture(self.run)
+
+    def run(self):
+        cur = self.cts
+        for d in range(CHAIN_DEPTH):
+            self.ctx.mul_relin_batch(cur, cur, out=self.muls[d])
+            self.ctx.rescale_batch(self.muls[d], out=self.rss[d])
+            cur = self.rss[d]
+        self.ctx.total_sum_batch(cur, ROT_SLOTS, out=self.out)
+
+    def launch(self):
+        self.graph.launch()
 
 
 def timed(fn, reps, sync):
@@ -385,7 +416,8 @@ def main():
         sync()
         log("warmup step %d done" % i)
 
-    # timed region: only the dominant family is bracketed with events
+    # timed region: batched eager launches; only the dominant kernel family
+    # is bracketed with HIP events (on the context stream)
     prof_enable(ctx, 1 << dom)
     roctx = Roctx()
     sync()
@@ -407,14 +439,28 @@ def main():
 
     breakdown = None
     if not args.no_breakdown:
+        # the same step captured once in a HIP graph and replayed; its output
+        # must equal the eager step's output bit for bit
+        gstep = GraphStep(ctx, cts)
+        ref = job_step(ctx, cts)
+        gstep.launch()
+        sync()
+        identical = all(torch.equal(a.data, b.data) for a, b in zip(ref, gstep.out))
+        if not identical:
+            print("graph replay differs from the eager step", file=sys.stderr)
+            sys.exit(1)
+        t_graph = timed(gstep.launch, max(1, args.steps), sync)
+        gstep.graph.close()
         # separately timed per-operation rates at level 24 on the same batch
         reps = 3
         t_mul = timed(lambda: ctx.mul_relin_batch(cts, cts), reps, sync)
         t_rot = timed(lambda: ctx.rotate_batch(cts, 1), reps, sync)
         t_rs = timed(lambda: ctx.rescale_batch(cts), reps, sync)
+        t_single = timed(lambda: [ctx.mul_relin(c, c) for c in cts], 1, sync)
         polys = torch.empty((2 * args.batch, lp.L, lp.n), dtype=torch.int64, device="cuda")
         for i, c in enumerate(cts):
             polys[2 * i:2 * i + 2].copy_(c.data)
+        sync()
         t_ntt = timed(lambda: ctx.ntt_forward(polys, lp.L), reps, sync)
         t_intt = timed(lambda: ctx.ntt_inverse(polys, lp.L), reps, sync)
         breakdown = {
@@ -424,8 +470,13 @@ def main():
             "ntt_per_s": 2 * args.batch / t_ntt,
             "intt_per_s": 2 * args.batch / t_intt,
             "limb_ntt_per_s": 2 * args.batch * lp.L / t_ntt,
+            "unbatched_hmult_relin_per_s": args.batch / t_single,
+            "graph_ms_per_step": 1000.0 * t_graph,
+            "graph_hmult_relin_per_s": args.batch * CHAIN_DEPTH / t_graph,
+            "graph_equals_eager": identical,
             "note": "level 24, batch of %d, per-operation loops after the timed region; ntt = forward NTT of one "
-                    "24-limb polynomial" % args.batch,
+                    "24-limb polynomial; unbatched = one mul_relin call per ciphertext; graph = the timed step "
+                    "replayed from one HIP graph" % args.batch,
         }
 
     avg_ms = d_ms / max(d_cnt, 1)

@@ -209,6 +209,23 @@ int pft_ptmatvec(pft_ctx* ctx, const pft_ptmat* m, uint32_t n_docs, const pft_ct
 int pft_ntt_forward(pft_ctx* ctx, uint64_t* data, uint32_t n_polys, uint32_t n_limbs);
 int pft_ntt_inverse(pft_ctx* ctx, uint64_t* data, uint32_t n_polys, uint32_t n_limbs);
 
+/* ---- HIP graphs ----------------------------------------------------------
+ * pft_graph_begin starts a capture on the context stream (which must not be
+ * the null stream); every following call on the context is recorded instead
+ * of run, until pft_graph_end, which instantiates the graph.  pft_graph_launch
+ * replays it on the context stream: same kernels, same device buffers (the
+ * descriptors' data pointers and levels are baked in).  Calls that move host
+ * data, synchronize, or would grow the library scratch fail with PFT_EINVAL /
+ * PFT_ENOMEM while a capture is open; pft_ctx_reserve sizes the scratch
+ * (bytes of the per-operation workspace and of the composite-operation
+ * buffers) beforehand.  A graph must be destroyed before its context. */
+typedef struct pft_graph pft_graph;
+int pft_ctx_reserve(pft_ctx* ctx, uint64_t ws_bytes, uint64_t aux_bytes);
+int pft_graph_begin(pft_ctx* ctx);
+int pft_graph_end(pft_ctx* ctx, pft_graph** out);
+int pft_graph_launch(pft_ctx* ctx, pft_graph* graph);
+void pft_graph_destroy(pft_graph* graph);
+
 /* ---- per-kernel timing ------------------------------------------------
  * pft_prof_enable brackets every launch of the selected kernel families
  * (bit k of mask = family k; 0 turns timing off) with HIP events recorded on

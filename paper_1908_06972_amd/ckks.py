@@ -99,12 +99,15 @@ def _u64(a):
 
 
 class Context:
-    def __init__(self, params: Params, device: int = 0):
+    def __init__(self, params: Params, device: int = 0, stream=None):
+        """stream: a torch.cuda.Stream to run on (default: torch's current
+        stream).  Graph capture needs a stream other than the null stream."""
         self.params = params
         self.device = torch.device("cuda", device)
         self.lib = N.load()
         h = ctypes.c_void_p()
-        stream = torch.cuda.current_stream(self.device).cuda_stream
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        stream = self.stream.cuda_stream
         N.check(self.lib.pft_ctx_create(params.handle, device, ctypes.c_void_p(stream), ctypes.byref(h)))
         self.handle = h
 
@@ -119,6 +122,25 @@ class Context:
     def synchronize(self):
         N.check(self.lib.pft_ctx_synchronize(self.handle))
 
+    def reserve(self, ws_bytes, aux_bytes=0):
+        N.check(self.lib.pft_ctx_reserve(self.handle, int(ws_bytes), int(aux_bytes)))
+
+    def capture(self, fn):
+        """Record the libpft calls made by fn() into a HIP graph (fn must pass
+        preallocated outputs: nothing may allocate while capturing)."""
+        N.check(self.lib.pft_graph_begin(self.handle))
+        try:
+            fn()
+        except Exception:
+            h = ctypes.c_void_p()
+            self.lib.pft_graph_end(self.handle, ctypes.byref(h))
+            if h.value:
+                self.lib.pft_graph_destroy(h)
+            raise
+        h = ctypes.c_void_p()
+        N.check(self.lib.pft_graph_end(self.handle, ctypes.byref(h)))
+        return Graph(self, h)
+
     def device_bytes(self) -> int:
         b = ctypes.c_uint64()
         N.check(self.lib.pft_ctx_device_bytes(self.handle, ctypes.byref(b)))
@@ -126,11 +148,14 @@ class Context:
 
     # ---- buffers
     def empty_ct(self, level: int, scale: float = 0.0) -> Ciphertext:
-        t = torch.empty((2, level, self.params.n), dtype=torch.int64, device=self.device)
+        # allocated on the context stream, so the caching allocator orders reuse with its work
+        with torch.cuda.stream(self.stream):
+            t = torch.empty((2, level, self.params.n), dtype=torch.int64, device=self.device)
         return Ciphertext(t, level, scale)
 
     def empty_pt(self, level: int) -> Plaintext:
-        t = torch.empty((level, self.params.n), dtype=torch.int64, device=self.device)
+        with torch.cuda.stream(self.stream):
+            t = torch.empty((level, self.params.n), dtype=torch.int64, device=self.device)
         return Plaintext(t, level, 0.0)
 
     # ---- KEYGEN (randomness as arguments)
@@ -288,6 +313,23 @@ class Context:
     def ntt_inverse(self, data: torch.Tensor, n_limbs: int):
         n_polys = data.numel() // (n_limbs * self.params.n)
         N.check(self.lib.pft_ntt_inverse(self.handle, ctypes.c_void_p(data.data_ptr()), n_polys, n_limbs))
+
+
+class Graph:
+    def __init__(self, ctx, handle):
+        self.ctx = ctx
+        self.handle = handle
+
+    def launch(self):
+        N.check(self.ctx.lib.pft_graph_launch(self.ctx.handle, self.handle))
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and N._lib is not None:
+            N._lib.pft_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
 
 
 class PtMat:

@@ -211,6 +211,9 @@ struct pft_ctx {
     size_t aux_bytes = 0;
     TwPair* cbuf = nullptr;  // per-call constants (e.g. 1/w per document)
     size_t cbuf_n = 0;
+    bool capturing = false;  // a HIP graph capture is open on the stream
+    int live_graphs = 0;     // graphs may reference ws/aux: grow by retiring, never free
+    std::vector<void*> retired;
 };
 
 template <typename T>
@@ -234,9 +237,15 @@ static int upload(pft_ctx* c, T** dst, const std::vector<T>& src) {
 
 static int ensure_ws(pft_ctx* c, size_t bytes) {
     if (c->ws_bytes >= bytes) return PFT_OK;
+    if (c->capturing)
+        return fail(PFT_ENOMEM, "workspace of %zu bytes needed during graph capture; call pft_ctx_reserve first",
+                    bytes);
     if (c->ws) {
         HIPCK(hipStreamSynchronize(c->stream));
-        HIPCK(hipFree(c->ws));
+        if (c->live_graphs)
+            c->retired.push_back(c->ws);
+        else
+            HIPCK(hipFree(c->ws));
         c->ws = nullptr;
         c->ws_bytes = 0;
     }
@@ -248,9 +257,15 @@ static int ensure_ws(pft_ctx* c, size_t bytes) {
 
 static int ensure_aux(pft_ctx* c, size_t bytes) {
     if (c->aux_bytes >= bytes) return PFT_OK;
+    if (c->capturing)
+        return fail(PFT_ENOMEM, "aux buffer of %zu bytes needed during graph capture; call pft_ctx_reserve first",
+                    bytes);
     if (c->aux) {
         HIPCK(hipStreamSynchronize(c->stream));
-        HIPCK(hipFree(c->aux));
+        if (c->live_graphs)
+            c->retired.push_back(c->aux);
+        else
+            HIPCK(hipFree(c->aux));
         c->aux = nullptr;
         c->aux_bytes = 0;
     }
@@ -383,11 +398,13 @@ extern "C" void pft_ctx_destroy(pft_ctx* c) {
     if (c->ws) (void)hipFree(c->ws);
     if (c->aux) (void)hipFree(c->aux);
     if (c->cbuf) (void)hipFree(c->cbuf);
+    for (void* p : c->retired) (void)hipFree(p);
     delete c;
 }
 
 extern "C" int pft_ctx_synchronize(pft_ctx* c) {
     if (!c) return fail(PFT_EINVAL, "null ctx");
+    if (c->capturing) return fail(PFT_EINVAL, "cannot synchronize during graph capture");
     HIPCK(hipStreamSynchronize(c->stream));
     return PFT_OK;
 }
@@ -505,6 +522,7 @@ static bool check_uniform(const uint64_t* a, const std::vector<uint64_t>& mods, 
 
 extern "C" int pft_set_secret(pft_ctx* c, const int64_t* s) {
     if (!c || !s) return fail(PFT_EINVAL, "null argument");
+    if (c->capturing) return fail(PFT_EINVAL, "host transfers cannot be captured in a graph");
     const pft_params* P = c->P;
     if (!check_ternary(s, P->n)) return fail(PFT_EINVAL, "secret must be ternary");
     const uint32_t R = P->L + P->K;
@@ -520,6 +538,7 @@ extern "C" int pft_set_secret(pft_ctx* c, const int64_t* s) {
 
 extern "C" int pft_gen_public_key(pft_ctx* c, const uint64_t* a, const int64_t* e) {
     if (!c || !a || !e) return fail(PFT_EINVAL, "null argument");
+    if (c->capturing) return fail(PFT_EINVAL, "host transfers cannot be captured in a graph");
     const pft_params* P = c->P;
     if (!c->s) return fail(PFT_ENOKEY, "set the secret first");
     if (!check_uniform(a, P->q, P->L, P->n)) return fail(PFT_EINVAL, "mask residues must be < q_i");
@@ -585,6 +604,7 @@ static int gen_switch_key(pft_ctx* c, const uint64_t* s_prime, const uint64_t* a
 
 extern "C" int pft_gen_relin_key(pft_ctx* c, const uint64_t* a, const int64_t* e) {
     if (!c || !a || !e) return fail(PFT_EINVAL, "null argument");
+    if (c->capturing) return fail(PFT_EINVAL, "host transfers cannot be captured in a graph");
     if (!c->s) return fail(PFT_ENOKEY, "set the secret first");
     const pft_params* P = c->P;
     const uint32_t R = P->L + P->K;
@@ -614,6 +634,7 @@ static ItemPtrs one_item(uint64_t* p) {
 
 extern "C" int pft_gen_rotation_key(pft_ctx* c, int32_t step, const uint64_t* a, const int64_t* e) {
     if (!c || !a || !e) return fail(PFT_EINVAL, "null argument");
+    if (c->capturing) return fail(PFT_EINVAL, "host transfers cannot be captured in a graph");
     if (!c->s) return fail(PFT_ENOKEY, "set the secret first");
     const pft_params* P = c->P;
     const uint32_t R = P->L + P->K;
@@ -637,6 +658,7 @@ static int check_ct(const pft_ctx* c, const pft_ct* ct) {
 extern "C" int pft_encrypt(pft_ctx* c, const int64_t* m, uint32_t level, double scale, const int64_t* v,
                            const int64_t* e0, const int64_t* e1, pft_ct* out) {
     if (!c || !m || !v || !e0 || !e1 || !out || !out->data) return fail(PFT_EINVAL, "null argument");
+    if (c->capturing) return fail(PFT_EINVAL, "host transfers cannot be captured in a graph");
     const pft_params* P = c->P;
     if (!c->pk) return fail(PFT_ENOKEY, "no public key");
     if (level < 1 || level > P->L) return fail(PFT_ELEVEL, "level %u out of range", level);
@@ -670,6 +692,7 @@ extern "C" int pft_encrypt(pft_ctx* c, const int64_t* m, uint32_t level, double 
 
 extern "C" int pft_decrypt(pft_ctx* c, const pft_ct* ct, uint64_t* out) {
     if (!c || !out) return fail(PFT_EINVAL, "null argument");
+    if (c->capturing) return fail(PFT_EINVAL, "host transfers cannot be captured in a graph");
     int r;
     if ((r = check_ct(c, ct))) return r;
     if (!c->s) return fail(PFT_ENOKEY, "no secret");
@@ -687,6 +710,7 @@ extern "C" int pft_decrypt(pft_ctx* c, const pft_ct* ct, uint64_t* out) {
 
 extern "C" int pft_ct_export(pft_ctx* c, const pft_ct* ct, uint64_t* host) {
     if (!c || !host) return fail(PFT_EINVAL, "null argument");
+    if (c->capturing) return fail(PFT_EINVAL, "host transfers cannot be captured in a graph");
     int r;
     if ((r = check_ct(c, ct))) return r;
     const pft_params* P = c->P;
@@ -701,6 +725,7 @@ extern "C" int pft_ct_export(pft_ctx* c, const pft_ct* ct, uint64_t* host) {
 
 extern "C" int pft_ct_import(pft_ctx* c, const uint64_t* host, uint32_t level, double scale, pft_ct* ct) {
     if (!c || !host || !ct || !ct->data) return fail(PFT_EINVAL, "null argument");
+    if (c->capturing) return fail(PFT_EINVAL, "host transfers cannot be captured in a graph");
     const pft_params* P = c->P;
     if (level < 1 || level > P->L) return fail(PFT_ELEVEL, "level %u out of range", level);
     for (uint32_t b = 0; b < 2; ++b)
@@ -717,6 +742,7 @@ extern "C" int pft_ct_import(pft_ctx* c, const uint64_t* host, uint32_t level, d
 
 extern "C" int pft_pt_from_coeffs(pft_ctx* c, const int64_t* m, uint32_t level, double scale, pft_pt* pt) {
     if (!c || !m || !pt || !pt->data) return fail(PFT_EINVAL, "null argument");
+    if (c->capturing) return fail(PFT_EINVAL, "host transfers cannot be captured in a graph");
     const pft_params* P = c->P;
     if (level < 1 || level > P->L) return fail(PFT_ELEVEL, "level %u out of range", level);
     int r;
@@ -1125,6 +1151,7 @@ static int64_t round_half_away(double x) { return (int64_t)(x >= 0 ? std::floor(
 
 extern "C" int pft_mul_const_batch(pft_ctx* c, uint32_t n, const pft_ct* in, const double* values, pft_ct* out) {
     if (!c || !in || !values || !out) return fail(PFT_EINVAL, "null argument");
+    if (c->capturing) return fail(PFT_EINVAL, "mul_const copies host constants and cannot be captured");
     int r;
     for (uint32_t i = 0; i < n; ++i) {
         if ((r = check_ct(c, &in[i]))) return r;
@@ -1159,8 +1186,6 @@ extern "C" int pft_mul_const_batch(pft_ctx* c, uint32_t n, const pft_ct* in, con
             O.p[z] = out[g[z]].data;
         }
         launch_scale_const_b(cnt, I, O, c->cbuf, l, c->tabs, P->log_n, c->stream);
-        // the constants are a pageable host vector: wait before it goes away
-        HIPCK(hipStreamSynchronize(c->stream));
         for (uint32_t z = 0; z < cnt; ++z) {
             out[g[z]].level = l;
             out[g[z]].scale = in[g[z]].scale * qs;
@@ -1510,6 +1535,7 @@ extern "C" int pft_decode(const pft_params* P, const uint64_t* res, uint32_t lev
 // ---------------------------------------------------------------------------
 extern "C" int pft_prof_enable(pft_ctx* c, uint32_t mask) {
     if (!c) return fail(PFT_EINVAL, "null ctx");
+    if (c->capturing) return fail(PFT_EINVAL, "timing cannot change during graph capture");
     HIPCK(hipStreamSynchronize(c->stream));
     c->prof.reset();
     c->prof.mask = mask & ((1u << PK_COUNT) - 1u);
@@ -1537,4 +1563,69 @@ extern "C" int pft_prof_read(pft_ctx* c, uint32_t kid, double* total_ms, uint64_
     *bytes = by;
     *ops = op;
     return PFT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// HIP graphs: capture a sequence of calls on the context stream, replay it
+// ---------------------------------------------------------------------------
+struct pft_graph {
+    pft_ctx* ctx = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" int pft_ctx_reserve(pft_ctx* c, uint64_t ws_bytes, uint64_t aux_bytes) {
+    if (!c) return fail(PFT_EINVAL, "null ctx");
+    if (c->capturing) return fail(PFT_EINVAL, "cannot reserve during graph capture");
+    int r;
+    if ((r = ensure_ws(c, ws_bytes)) || (r = ensure_aux(c, aux_bytes))) return r;
+    return PFT_OK;
+}
+
+extern "C" int pft_graph_begin(pft_ctx* c) {
+    if (!c) return fail(PFT_EINVAL, "null ctx");
+    if (c->capturing) return fail(PFT_EINVAL, "a capture is already open");
+    if (!c->stream) return fail(PFT_EINVAL, "graph capture needs a context created on a non-null stream");
+    if (c->prof.mask) return fail(PFT_EINVAL, "disable kernel timing before capturing");
+    HIPCK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+    c->capturing = true;
+    return PFT_OK;
+}
+
+extern "C" int pft_graph_end(pft_ctx* c, pft_graph** out) {
+    if (!c || !out) return fail(PFT_EINVAL, "null argument");
+    if (!c->capturing) return fail(PFT_EINVAL, "no capture is open");
+    c->capturing = false;
+    auto* g = new pft_graph();
+    hipError_t e = hipStreamEndCapture(c->stream, &g->graph);
+    if (e != hipSuccess) {
+        delete g;
+        return fail(PFT_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    }
+    e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g->graph);
+        delete g;
+        return fail(PFT_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    g->ctx = c;
+    ++c->live_graphs;
+    *out = g;
+    return PFT_OK;
+}
+
+extern "C" int pft_graph_launch(pft_ctx* c, pft_graph* g) {
+    if (!c || !g) return fail(PFT_EINVAL, "null argument");
+    if (g->ctx != c) return fail(PFT_EINVAL, "graph belongs to another context");
+    if (c->capturing) return fail(PFT_EINVAL, "cannot launch a graph during capture");
+    HIPCK(hipGraphLaunch(g->exec, c->stream));
+    return PFT_OK;
+}
+
+extern "C" void pft_graph_destroy(pft_graph* g) {
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->ctx) --g->ctx->live_graphs;
+    delete g;
 }

@@ -91,6 +91,11 @@ SIGNATURES = [
     ("pft_ptmatvec", [_vp, _vp, ctypes.c_uint32, ctypes.POINTER(CtDesc), ctypes.POINTER(CtDesc)], ctypes.c_int),
     ("pft_ntt_forward", [_vp, _vp, ctypes.c_uint32, ctypes.c_uint32], ctypes.c_int),
     ("pft_ntt_inverse", [_vp, _vp, ctypes.c_uint32, ctypes.c_uint32], ctypes.c_int),
+    ("pft_ctx_reserve", [_vp, ctypes.c_uint64, ctypes.c_uint64], ctypes.c_int),
+    ("pft_graph_begin", [_vp], ctypes.c_int),
+    ("pft_graph_end", [_vp, ctypes.POINTER(_vp)], ctypes.c_int),
+    ("pft_graph_launch", [_vp, _vp], ctypes.c_int),
+    ("pft_graph_destroy", [_vp], None),
     ("pft_prof_enable", [_vp, ctypes.c_uint32], ctypes.c_int),
     ("pft_prof_read", [_vp, ctypes.c_uint32, _dblp, _u64p, _dblp, _dblp], ctypes.c_int),
     ("pft_encode", [_vp, _dblp, _dblp, ctypes.c_uint32, ctypes.c_double, _i64p], ctypes.c_int),

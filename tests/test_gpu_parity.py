@@ -271,3 +271,44 @@ def test_errors(c1):
     with pytest.raises(N.PftError) as e:
         w.ctx.mul_relin(g, g, out=g)
     assert e.value.code == N.PFT_EINVAL
+
+
+def test_graph_replay_matches_eager(torch_cuda):
+    """HMult+relin -> rescale -> rotate captured in a HIP graph: every replay,
+    with other work on the stream in between, equals the eager result."""
+    import paper_1908_06972_amd.ckks as L
+    torch = torch_cuda
+    cfg = S.CONFIGS["C2"]
+    lp = L.Params.from_config(cfg)
+    side = torch.cuda.Stream()
+    ctx = L.Context(lp, stream=side)
+    n = lp.n
+    kd = S.key_draws(2, n, lp.q)
+    ctx.set_secret(kd.s)
+    ctx.gen_public_key(kd.pk_a, kd.pk_e)
+    a, e = S.switch_key_draws(2, 0, n, lp.key_moduli(), lp.dnum)
+    ctx.gen_relin_key(a, e)
+    a, e = S.switch_key_draws(2, 1003, n, lp.key_moduli(), lp.dnum)
+    ctx.gen_rotation_key(3, a, e)
+    d1, d2 = S.enc_draws(61, n), S.enc_draws(62, n)
+    ga = ctx.encrypt(S.plaintext_coeffs(S.rng(63), n, 2 ** 40), 8, lp.scale, d1.v, d1.e0, d1.e1)
+    gb = ctx.encrypt(S.plaintext_coeffs(S.rng(64), n, 2 ** 40), 8, lp.scale, d2.v, d2.e0, d2.e1)
+    eager = ctx.export(ctx.rotate(ctx.rescale(ctx.mul_relin(ga, gb)), 3))
+    m_out, r_out, rot_out = ctx.empty_ct(8), ctx.empty_ct(7), ctx.empty_ct(7)
+
+    def chain():
+        ctx.mul_relin(ga, gb, out=m_out)
+        ctx.rescale(m_out, out=r_out)
+        ctx.rotate(r_out, 3, out=rot_out)
+
+    graph = ctx.capture(chain)
+    for rep in range(3):
+        with torch.cuda.stream(side):
+            rot_out.data.zero_()
+            m_out.data.fill_(rep)
+        ctx.rescale(ctx.mul_relin(gb, ga))  # unrelated eager work on the same stream
+        graph.launch()
+        ctx.synchronize()
+        assert np.array_equal(ctx.export(rot_out), eager), rep
+    graph.close()
+    ctx.close()
