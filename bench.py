@@ -225,6 +225,8 @@ def parse():
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="run only this many untimed steps (for rocprofv3) and exit")
     ap.add_argument("--no-breakdown", action="store_true", help="skip the per-operation loops")
+    ap.add_argument("--serve-requests", type=int, default=1000,
+                    help="requests of the serving measurement (0 skips it)")
     ap.add_argument("--summarize", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="write the markdown summary of three rocprofv3 runs of the timed region and exit")
     ap.add_argument("--kernel", default="k_ntt_pass<8, false>")
@@ -316,6 +318,43 @@ class GraphStep:
 
     def launch(self):
         self.graph.launch()
+
+
+SERVING_MIX = {"N=2^14": 3, "N=2^15": 2, "N=2^16": 1}
+
+
+def serving_bench(n_requests, rate=200.0, level=4, pool=16, budget_gib=16):
+    """Poisson stream of encrypted bag-of-words inferences (vocabulary 32768,
+    embedding 64, 8 classes) over three parameter sets in the ratio 3:2:1
+    (N = 2^14 / 2^15 / 2^16 with the batched / bag-of-words / large-ring
+    prime chains), inputs encrypted at level 4 (depth 3), keys resident.
+    Served twice on the same trace: continuous batching (one stream per
+    parameter set, overlapping) and a plain per-op server (one request at a
+    time, arrival order)."""
+    import synth as S
+    from paper_1908_06972_amd.serving import GpuExecutor, Scheduler, build_sets, poisson_trace
+
+    specs = {"N=2^14": S.CONFIGS["C2"], "N=2^15": S.CONFIGS["C4"], "N=2^16": S.CONFIGS["C3"]}
+    H, O = S.bow_weights(404, 32768, 64, 8)
+    t0 = time.time()
+    sets, policies, words, _ = build_sets(specs, H, O, pool_size=pool, level=level, draws=S)
+    key_bytes = sum(ctx.device_bytes() for ctx, _, _ in sets.values())
+    log("serving: 3 parameter sets ready in %.1fs, %.2f GiB resident" % (time.time() - t0, key_bytes / 2 ** 30))
+    ex = GpuExecutor(sets)
+    warm = Scheduler(ex, policies, budget_gib << 30).run(poisson_trace(1, 12, 1000.0, SERVING_MIX,
+                                                                       {k: pool for k in specs}, words))
+    assert warm.completed == 12
+    out = {"rate_req_per_s": rate, "requests": n_requests, "mix": "3:2:1 over N=2^14/2^15/2^16", "level": level,
+           "vocab": 32768, "dim": 64, "classes": 8, "hbm_budget_gib": budget_gib,
+           "resident_gib": round(key_bytes / 2 ** 30, 3)}
+    for mode, cont in (("continuous", True), ("per_op", False)):
+        trace = poisson_trace(505, n_requests, rate, SERVING_MIX, {k: pool for k in specs}, words)
+        st = Scheduler(ex, policies, budget_gib << 30, continuous=cont).run(trace)
+        out[mode] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.summary().items()}
+        log("serving %s: %s" % (mode, out[mode]))
+    for ctx, _, _ in sets.values():
+        ctx.synchronize()
+    return out
 
 
 def timed(fn, reps, sync):
@@ -511,6 +550,9 @@ def main():
         "alu": alu,
     }
 
+    serving = None
+    if args.serve_requests > 0:
+        serving = serving_bench(args.serve_requests)
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample)...")
@@ -535,6 +577,7 @@ def main():
         "breakdown": breakdown,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 
