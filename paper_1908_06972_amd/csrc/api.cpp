@@ -275,7 +275,19 @@ static int ensure_aux(pft_ctx* c, size_t bytes) {
     return PFT_OK;
 }
 
+// Limbs whose NTT runs in fp64 (exact for q < 2^50).
+static bool ntt_fp(uint64_t q) { return bit_length(q) <= 50; }
+static uint64_t dbits(double v) {
+    uint64_t u;
+    memcpy(&u, &v, sizeof u);
+    return u;
+}
 static TwPair pair(uint64_t w, uint64_t q) { return TwPair{w, shoup_companion(w, q)}; }
+// NTT twiddle in the form the limb's butterflies use.
+static TwPair twiddle(uint64_t w, uint64_t q) {
+    if (ntt_fp(q)) return TwPair{dbits((double)w), dbits((double)w / (double)q)};
+    return pair(w, q);
+}
 
 static int build_tables(pft_ctx* c) {
     const pft_params* P = c->P;
@@ -292,8 +304,8 @@ static int build_tables(pft_ctx* c) {
         }
         for (uint32_t k = 0; k < n; ++k) {
             const uint32_t r = bitrev(k, lg);
-            fw[(size_t)m * n + k] = pair(pw[r], q);
-            iw[(size_t)m * n + k] = pair(ipw[r], q);
+            fw[(size_t)m * n + k] = twiddle(pw[r], q);
+            iw[(size_t)m * n + k] = twiddle(ipw[r], q);
         }
         DevMod& d = mods[m];
         d.q = q;
@@ -307,6 +319,13 @@ static int build_tables(pft_ctx* c) {
         d.n_inv_sh = shoup_companion(d.n_inv, q);
         d.last_inv = mulmod(ipw[n / 2], d.n_inv, q);  // psi^-brv(1) = psi^-(N/2)
         d.last_inv_sh = shoup_companion(d.last_inv, q);
+        d.fp = ntt_fp(q) ? 1u : 0u;
+        d.qd = (double)q;
+        d.qinv = 1.0 / (double)q;
+        d.n_inv_d = (double)d.n_inv;
+        d.n_inv_q = (double)d.n_inv / (double)q;
+        d.last_inv_d = (double)d.last_inv;
+        d.last_inv_q = (double)d.last_inv / (double)q;
     }
     int r;
     if ((r = upload(c, &c->tabs.mods, mods)) || (r = upload(c, &c->tabs.tw_fwd, fw)) ||

@@ -19,13 +19,20 @@
 // the sub-problem itself).
 //   N = 2^12: one pass of 12 stages.   N = 2^13: 7 + 6.   N = 2^14: 7 + 7.
 //   N = 2^15: 8 + 7.                   N = 2^16: 8 + 8.
-// Butterflies keep residues lazily reduced (forward in [0, 4q), inverse in
-// [0, 2q)); q < 2^60 leaves headroom.  Outputs of a full transform are in
-// [0, q).
+// Arithmetic, chosen per limb (uniform within a workgroup):
+//   * q < 2^50: fp64.  A residue fits the 53-bit significand, and MI355X issues
+//     fp64 FMA at the full VALU rate, so an exact product modulo q costs six
+//     fp64 instructions instead of some twenty 32-bit integer ones (bounds at
+//     fmulmod below).
+//   * otherwise (q < 2^60): 64-bit integer Shoup butterflies kept lazily
+//     reduced (forward in [0, 4q), inverse in [0, 2q)).
+// Inputs below 4q are accepted; outputs of a full transform are in [0, q).
 #include "pft_device.h"
 #include "pft_kernels.h"
 
 namespace {
+
+// ---- integer butterflies (any q < 2^60)
 
 // Harvey forward butterfly: X, Y in [0, 4q) -> X + WY, X - WY in [0, 4q).
 __device__ __forceinline__ void fwd_bfly(uint64_t& X, uint64_t& Y, uint64_t w, uint64_t wp, uint64_t q,
@@ -46,6 +53,63 @@ __device__ __forceinline__ void inv_bfly(uint64_t& X, uint64_t& Y, uint64_t w, u
     Y = v;
 }
 
+// ---- fp64 butterflies (q < 2^50)
+//
+// A residue is held as an integer-valued double of either sign; every value
+// stays an integer below 2^53 in magnitude, so sums and differences are exact.
+// fmulmod(a, w) returns a w - k q with k = rint(fl(a fl(w/q))): the product
+// a w is split exactly into hi + lo (hi = fl(a w), lo = fma(a, w, -hi)); then
+// fma(-k, q, hi) is exact because the true value is an integer of magnitude
+// below 2^53, and adding lo is exact for the same reason.  The quotient is off
+// from a w / q by at most 1/2 + |a| 2^-52 (two roundings), so with |a| <= c q
+// and q < 2^50 the result lies within (1/2 + c/4) q of zero.  freduce(x) =
+// x - rint(x/q) q lies within q/2 (+ a vanishing error) for the magnitudes
+// used here.  Forward: inputs within B q give outputs within (1 + B/4) q, so
+// B stays below 4/3 after the first stage (inputs below 4q are accepted).
+// Inverse: inputs within B q give outputs within max(1/2, 1/2 + B/2) q, so B
+// stays at most 1 (inputs below 4q accepted).  All magnitudes stay below
+// 8q < 2^53.
+__device__ __forceinline__ double as_f(uint64_t v) { return __builtin_bit_cast(double, v); }
+__device__ __forceinline__ uint64_t as_u(double v) { return __builtin_bit_cast(uint64_t, v); }
+
+__device__ __forceinline__ double fmulmod(double a, double w, double wq, double q) {
+#pragma clang fp contract(off)
+    const double hi = a * w;
+    const double lo = __builtin_fma(a, w, -hi);
+    const double k = __builtin_rint(a * wq);
+    return __builtin_fma(-k, q, hi) + lo;
+}
+__device__ __forceinline__ double freduce(double x, double q, double qinv) {
+#pragma clang fp contract(off)
+    return __builtin_fma(-__builtin_rint(x * qinv), q, x);
+}
+__device__ __forceinline__ void fwd_bfly_fp(uint64_t& X, uint64_t& Y, const TwPair& tp, double q, double qinv) {
+#pragma clang fp contract(off)
+    const double x = freduce(as_f(X), q, qinv);
+    const double t = fmulmod(as_f(Y), as_f(tp.w), as_f(tp.wp), q);
+    X = as_u(x + t);
+    Y = as_u(x - t);
+}
+__device__ __forceinline__ void inv_bfly_fp(uint64_t& X, uint64_t& Y, const TwPair& tp, double q, double qinv) {
+#pragma clang fp contract(off)
+    const double x = as_f(X), y = as_f(Y);
+    X = as_u(freduce(x + y, q, qinv));
+    Y = as_u(fmulmod(x - y, as_f(tp.w), as_f(tp.wp), q));
+}
+// u64 below 2^52 -> double: the bits of 2^52 + v, minus 2^52.
+__device__ __forceinline__ uint64_t fp_from_u64(uint64_t v) {
+#pragma clang fp contract(off)
+    return as_u(as_f(v | 0x4330000000000000ull) - 4503599627370496.0);
+}
+// double residue -> canonical u64 in [0, q): reduce to within q/2, lift the
+// negative half by q, then read the mantissa of 2^52 + r.
+__device__ __forceinline__ uint64_t fp_to_u64(uint64_t v, double q, double qinv) {
+#pragma clang fp contract(off)
+    double r = freduce(as_f(v), q, qinv);
+    r = r < 0.0 ? r + q : r;
+    return as_u(r + 4503599627370496.0) & 0x000FFFFFFFFFFFFFull;
+}
+
 template <int LOG_M, int PH>
 struct Phase {
     static constexpr int HB = LOG_M - 1 - 4 * PH;           // highest stage bit of this phase
@@ -56,11 +120,12 @@ struct Phase {
     }
 };
 
-template <int LOG_M, int PH, bool INV>
+template <int LOG_M, int PH, bool INV, bool FP, bool FOLD>
 __device__ __forceinline__ void run_phase(uint64_t (&x)[16], uint32_t l, uint32_t high, uint32_t s0,
-                                          const TwPair* __restrict__ twt, const DevMod& md, bool fold_last) {
+                                          const TwPair* __restrict__ twt, const DevMod& md) {
     using Ph = Phase<LOG_M, PH>;
     const uint64_t q = md.q, two_q = md.two_q;
+    const double qd = md.qd, qinv = md.qinv;
     if constexpr (!INV) {
 #pragma unroll
         for (int bit = Ph::HB; bit >= Ph::LB; --bit) {
@@ -73,7 +138,10 @@ __device__ __forceinline__ void run_phase(uint64_t (&x)[16], uint32_t l, uint32_
                 const uint32_t r = Ph::r_of(l, e);
                 const uint32_t i = (high << spp) | (r >> (bit + 1));
                 const TwPair tp = twt[(1u << s) + i];
-                fwd_bfly(x[e], x[e | (1 << pos)], tp.w, tp.wp, q, two_q);
+                if constexpr (FP)
+                    fwd_bfly_fp(x[e], x[e | (1 << pos)], tp, qd, qinv);
+                else
+                    fwd_bfly(x[e], x[e | (1 << pos)], tp.w, tp.wp, q, two_q);
             }
         }
     } else {
@@ -82,16 +150,22 @@ __device__ __forceinline__ void run_phase(uint64_t (&x)[16], uint32_t l, uint32_
             const int spp = LOG_M - 1 - bit;
             const uint32_t s = s0 + spp;
             const int pos = bit - Ph::WLO;
-            if (PH == 0 && bit == Ph::HB && fold_last) {
-                // stage 0 with N^-1 folded in: outputs fully reduced
+            if (FOLD && PH == 0 && bit == Ph::HB) {
+                // stage 0 with N^-1 folded in (integer path: outputs fully reduced)
 #pragma unroll
                 for (int e = 0; e < 16; ++e) {
                     if (e & (1 << pos)) continue;
                     uint64_t X = x[e], Y = x[e | (1 << pos)];
-                    uint64_t u = X + Y;
-                    u = u >= two_q ? u - two_q : u;
-                    x[e] = shoup(u, md.n_inv, md.n_inv_sh, q);
-                    x[e | (1 << pos)] = shoup(X + two_q - Y, md.last_inv, md.last_inv_sh, q);
+                    if constexpr (FP) {
+                        const double a = as_f(X), b2 = as_f(Y);
+                        x[e] = as_u(fmulmod(a + b2, md.n_inv_d, md.n_inv_q, qd));
+                        x[e | (1 << pos)] = as_u(fmulmod(a - b2, md.last_inv_d, md.last_inv_q, qd));
+                    } else {
+                        uint64_t u = X + Y;
+                        u = u >= two_q ? u - two_q : u;
+                        x[e] = shoup(u, md.n_inv, md.n_inv_sh, q);
+                        x[e | (1 << pos)] = shoup(X + two_q - Y, md.last_inv, md.last_inv_sh, q);
+                    }
                 }
             } else {
 #pragma unroll
@@ -100,61 +174,90 @@ __device__ __forceinline__ void run_phase(uint64_t (&x)[16], uint32_t l, uint32_
                     const uint32_t r = Ph::r_of(l, e);
                     const uint32_t i = (high << spp) | (r >> (bit + 1));
                     const TwPair tp = twt[(1u << s) + i];
-                    inv_bfly(x[e], x[e | (1 << pos)], tp.w, tp.wp, q, two_q);
+                    if constexpr (FP)
+                        inv_bfly_fp(x[e], x[e | (1 << pos)], tp, qd, qinv);
+                    else
+                        inv_bfly(x[e], x[e | (1 << pos)], tp.w, tp.wp, q, two_q);
                 }
             }
         }
     }
 }
 
+// LDS word of element r of sub-problem c: c S + r + P (r >> 4).  The address
+// is affine in the register index e of every arrangement (so ds_read/ds_write
+// take immediate offsets), and (S, P) are chosen per M so that each access
+// pattern of the pass -- a register phase's arrangement under either lane
+// mapping, and the staging order -- spreads the 64 lanes of a wave over the
+// LDS banks with at most 1.5x the conflict-free number of cycles (1x for most).
+template <int LOG_M> struct LdsPad;
+template <> struct LdsPad<6> { static constexpr uint32_t S = 67, P = 0; };
+template <> struct LdsPad<7> { static constexpr uint32_t S = 137, P = 1; };
+template <> struct LdsPad<8> { static constexpr uint32_t S = 274, P = 1; };
+template <> struct LdsPad<12> { static constexpr uint32_t S = 4352, P = 1; };
+template <int LOG_M>
+constexpr uint32_t lds_words() { return (4096u >> LOG_M) * LdsPad<LOG_M>::S; }
+template <int LOG_M>
+__device__ __forceinline__ uint32_t lds_at(uint32_t c, uint32_t r) {
+    return c * LdsPad<LOG_M>::S + r + LdsPad<LOG_M>::P * (r >> 4);
+}
+
 template <int LOG_M, int PH>
 __device__ __forceinline__ void lds_read(uint64_t (&x)[16], const uint64_t* lds, uint32_t c, uint32_t l) {
-    constexpr int LDSW = (1 << LOG_M) + 1;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) x[e] = lds[c * LDSW + Phase<LOG_M, PH>::r_of(l, e)];
+    for (int e = 0; e < 16; ++e) x[e] = lds[lds_at<LOG_M>(c, Phase<LOG_M, PH>::r_of(l, e))];
 }
 template <int LOG_M, int PH>
 __device__ __forceinline__ void lds_write(const uint64_t (&x)[16], uint64_t* lds, uint32_t c, uint32_t l) {
-    constexpr int LDSW = (1 << LOG_M) + 1;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) lds[c * LDSW + Phase<LOG_M, PH>::r_of(l, e)] = x[e];
+    for (int e = 0; e < 16; ++e) lds[lds_at<LOG_M>(c, Phase<LOG_M, PH>::r_of(l, e))] = x[e];
 }
 
-template <int LOG_M, bool INV, int PH>
-__device__ __forceinline__ void phases_fwd(uint64_t (&x)[16], uint64_t* lds, uint32_t c, uint32_t l, uint32_t high,
+// The register phases of one pass in execution order (forward: 0, 1, ...;
+// inverse: the reverse), with an LDS exchange between consecutive phases.
+// Each thread writes back to the words it read last, so one barrier per
+// exchange suffices.
+template <int LOG_M, bool INV, bool FP, bool FOLD, int K>
+__device__ __forceinline__ void run_phases(uint64_t (&x)[16], uint64_t* lds, uint32_t c, uint32_t l, uint32_t high,
                                            uint32_t s0, const TwPair* __restrict__ twt, const DevMod& md) {
     constexpr int NPH = (LOG_M + 3) / 4;
-    if constexpr (PH < NPH) {
-        lds_read<LOG_M, PH>(x, lds, c, l);
-        run_phase<LOG_M, PH, false>(x, l, high, s0, twt, md, false);
-        lds_write<LOG_M, PH>(x, lds, c, l);
-        __syncthreads();
-        phases_fwd<LOG_M, INV, PH + 1>(x, lds, c, l, high, s0, twt, md);
+    if constexpr (K < NPH) {
+        constexpr int PH = INV ? NPH - 1 - K : K;
+        if constexpr (K > 0) {
+            constexpr int PREV = INV ? PH + 1 : PH - 1;
+            lds_write<LOG_M, PREV>(x, lds, c, l);
+            __syncthreads();
+            lds_read<LOG_M, PH>(x, lds, c, l);
+        }
+        run_phase<LOG_M, PH, INV, FP, FOLD>(x, l, high, s0, twt, md);
+        run_phases<LOG_M, INV, FP, FOLD, K + 1>(x, lds, c, l, high, s0, twt, md);
     }
 }
 
-template <int LOG_M, int PH>
-__device__ __forceinline__ void phases_inv(uint64_t (&x)[16], uint64_t* lds, uint32_t c, uint32_t l, uint32_t high,
-                                           uint32_t s0, const TwPair* __restrict__ twt, const DevMod& md,
-                                           bool fold_last) {
-    if constexpr (PH >= 0) {
-        lds_read<LOG_M, PH>(x, lds, c, l);
-        run_phase<LOG_M, PH, true>(x, l, high, s0, twt, md, fold_last);
-        lds_write<LOG_M, PH>(x, lds, c, l);
-        __syncthreads();
-        phases_inv<LOG_M, PH - 1>(x, lds, c, l, high, s0, twt, md, fold_last);
-    }
-}
-
-template <int LOG_M, bool INV>
+// One pass over stages s0 .. s0 + LOG_M - 1 of a 4096-element tile.
+// COL (stages below log_n - LOG_M leave low index bits: the M elements of a
+// sub-problem are 2^lbits apart): consecutive lanes take consecutive
+// sub-problems, so every register arrangement is a coalesced global access
+// and the pass loads and stores directly.  Row passes (lbits = 0, each
+// sub-problem contiguous): consecutive lanes walk along a sub-problem; a side
+// whose arrangement gives runs shorter than 16 words goes through LDS in
+// address order instead.
+// Limbs with DevMod::fp run the fp64 butterflies: the first pass of a
+// transform converts its u64 input, later passes exchange the doubles through
+// HBM, and the final pass writes canonical u64.  Integer limbs keep u64.
+template <int LOG_M, bool INV, bool COL, bool FINAL>
 __global__ __launch_bounds__(256) void k_ntt_pass(PolyBatch b, const DevMod* __restrict__ mods,
                                                   const TwPair* __restrict__ tw, uint32_t log_n, uint32_t s0,
-                                                  uint32_t final_pass) {
+                                                  uint32_t first_pass) {
     constexpr int M = 1 << LOG_M;
     constexpr int T = M / 16;
     constexpr int C = 256 / T;
-    constexpr int LDSW = M + 1;
-    __shared__ uint64_t lds[C * LDSW];
+    constexpr int NPH = (LOG_M + 3) / 4;
+    constexpr int PH_IN = INV ? NPH - 1 : 0;
+    constexpr int PH_OUT = INV ? 0 : NPH - 1;
+    constexpr bool DIRECT_IN = COL || Phase<LOG_M, PH_IN>::WLO >= 4;
+    constexpr bool DIRECT_OUT = COL || Phase<LOG_M, PH_OUT>::WLO >= 4;
+    __shared__ uint64_t lds[lds_words<LOG_M>()];
 
     const uint32_t tid = threadIdx.x;
     const uint32_t job = blockIdx.y;
@@ -164,61 +267,72 @@ __global__ __launch_bounds__(256) void k_ntt_pass(PolyBatch b, const DevMod* __r
     const uint32_t mi = pb_mod(b, row);
     uint64_t* __restrict__ data = b.ptr[poly] + ((size_t)row << log_n);
     const DevMod md = mods[mi];
+    const bool fp = md.fp != 0;
     const TwPair* __restrict__ twt = tw + ((size_t)mi << log_n);
 
     const uint32_t lbits = log_n - s0 - LOG_M;
     const uint32_t lmask = (1u << lbits) - 1u;
     const uint32_t sp0 = blockIdx.x * C;
-
-    // coalesced global -> LDS
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        const uint32_t idx = tid + 256u * k;
-        uint32_t c, r;
-        if (lbits > 0) {
-            c = idx % C;
-            r = idx / C;
-        } else {
-            c = idx / M;
-            r = idx % M;
-        }
-        const uint32_t sp = sp0 + c;
-        const size_t j = ((((size_t)(sp >> lbits) << LOG_M) | r) << lbits) | (sp & lmask);
-        lds[c * LDSW + r] = data[j];
-    }
-    __syncthreads();
-
-    const uint32_t c = tid / T, l = tid % T;
+    const uint32_t c = COL ? tid % C : tid / T;
+    const uint32_t l = COL ? tid / C : tid % T;
     const uint32_t high = (sp0 + c) >> lbits;
+    // global index of element r of the workgroup's sub-problem cc
+    auto gidx = [&](uint32_t cc, uint32_t r) -> size_t {
+        const uint32_t sp = sp0 + cc;
+        return ((((size_t)(sp >> lbits) << LOG_M) | r) << lbits) | (sp & lmask);
+    };
+
     uint64_t x[16];
-    if constexpr (!INV) {
-        phases_fwd<LOG_M, INV, 0>(x, lds, c, l, high, s0, twt, md);
+    const bool convert_in = fp && first_pass;
+    if constexpr (DIRECT_IN) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const uint64_t v = data[gidx(c, Phase<LOG_M, PH_IN>::r_of(l, e))];
+            x[e] = convert_in ? fp_from_u64(v) : v;
+        }
     } else {
-        constexpr int NPH = (LOG_M + 3) / 4;
-        phases_inv<LOG_M, NPH - 1>(x, lds, c, l, high, s0, twt, md, final_pass != 0 && s0 == 0);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const uint32_t idx = tid + 256u * k;
+            const uint32_t cc = idx / M, r = idx % M;
+            const uint64_t v = data[gidx(cc, r)];
+            lds[lds_at<LOG_M>(cc, r)] = convert_in ? fp_from_u64(v) : v;
+        }
+        __syncthreads();
+        lds_read<LOG_M, PH_IN>(x, lds, c, l);
     }
 
-    // LDS -> global, coalesced
+    // the final inverse pass (s0 = 0) folds N^-1 into stage 0
+    if (fp)
+        run_phases<LOG_M, INV, true, FINAL, 0>(x, lds, c, l, high, s0, twt, md);
+    else
+        run_phases<LOG_M, INV, false, FINAL, 0>(x, lds, c, l, high, s0, twt, md);
+
     const uint64_t q = md.q, two_q = md.two_q;
+    const double qd = md.qd, qinv = md.qinv;
+    auto finish = [&](uint64_t v) -> uint64_t {
+        if constexpr (FINAL) {
+            if (fp) {
+                v = fp_to_u64(v, qd, qinv);
+            } else if constexpr (!INV) {
+                v = v >= two_q ? v - two_q : v;
+                v = v >= q ? v - q : v;
+            }
+        }
+        return v;
+    };
+    if constexpr (DIRECT_OUT) {
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        const uint32_t idx = tid + 256u * k;
-        uint32_t cc, r;
-        if (lbits > 0) {
-            cc = idx % C;
-            r = idx / C;
-        } else {
-            cc = idx / M;
-            r = idx % M;
+        for (int e = 0; e < 16; ++e) data[gidx(c, Phase<LOG_M, PH_OUT>::r_of(l, e))] = finish(x[e]);
+    } else {
+        lds_write<LOG_M, PH_OUT>(x, lds, c, l);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const uint32_t idx = tid + 256u * k;
+            const uint32_t cc = idx / M, r = idx % M;
+            data[gidx(cc, r)] = finish(lds[lds_at<LOG_M>(cc, r)]);
         }
-        const uint32_t sp = sp0 + cc;
-        const size_t j = ((((size_t)(sp >> lbits) << LOG_M) | r) << lbits) | (sp & lmask);
-        uint64_t v = lds[cc * LDSW + r];
-        if (!INV && final_pass) {
-            v = v >= two_q ? v - two_q : v;
-            v = v >= q ? v - q : v;
-        }
-        data[j] = v;
     }
 }
 
@@ -228,9 +342,25 @@ void launch_pass(const PolyBatch& b, const DevTables& t, uint32_t log_n, uint32_
     const uint32_t jobs = b.n_polys * b.n_limbs;
     dim3 grid((1u << log_n) / 4096u, jobs);
     const int kid = INV ? PK_NTT_INV : PK_NTT_FWD;
+    // the first pass executed: s0 = 0 going forward, the top window going back
+    const uint32_t first_pass = INV ? (s0 + LOG_M == log_n) : (s0 == 0);
+    const TwPair* tw = INV ? t.tw_inv : t.tw_fwd;
     if (g_prof) g_prof->begin(kid);
-    hipLaunchKernelGGL((k_ntt_pass<LOG_M, INV>), grid, dim3(256), 0, st, b, t.mods, INV ? t.tw_inv : t.tw_fwd,
-                       log_n, s0, (uint32_t)final_pass);
+    // column pass when low index bits remain below the window; the final
+    // pass is the row pass going forward and the s0 = 0 pass going back
+    const bool col = s0 + LOG_M < log_n;
+    if (col && final_pass)
+        hipLaunchKernelGGL((k_ntt_pass<LOG_M, INV, true, true>), grid, dim3(256), 0, st, b, t.mods, tw, log_n, s0,
+                           first_pass);
+    else if (col)
+        hipLaunchKernelGGL((k_ntt_pass<LOG_M, INV, true, false>), grid, dim3(256), 0, st, b, t.mods, tw, log_n,
+                           s0, first_pass);
+    else if (final_pass)
+        hipLaunchKernelGGL((k_ntt_pass<LOG_M, INV, false, true>), grid, dim3(256), 0, st, b, t.mods, tw, log_n,
+                           s0, first_pass);
+    else
+        hipLaunchKernelGGL((k_ntt_pass<LOG_M, INV, false, false>), grid, dim3(256), 0, st, b, t.mods, tw, log_n,
+                           s0, first_pass);
     if (g_prof) {
         const double elems = (double)jobs * (double)(1u << log_n);
         // read + write every residue once; N/2 butterflies per stage

@@ -28,12 +28,19 @@ struct DevMod {
     uint64_t n_inv, n_inv_sh;      // N^-1 mod q and its Shoup companion
     uint64_t last_inv, last_inv_sh; // psi^-brv(1) * N^-1: fused last inverse stage
     uint32_t bits;
-    uint32_t pad;
+    uint32_t fp;          // 1 if q < 2^50: the NTT runs its butterflies in fp64
+    // fp64 forms for the NTT when fp != 0: q, 1/q, and each constant c with
+    // its quotient c/q, all rounded to nearest (c < q < 2^50 is exact).
+    double qd, qinv;
+    double n_inv_d, n_inv_q;
+    double last_inv_d, last_inv_q;
 };
 
+// One twiddle.  Integer limbs: w and its Shoup companion floor(w 2^64 / q).
+// fp64 limbs (DevMod::fp): the bit patterns of the doubles w and w/q.
 struct TwPair {
     uint64_t w;
-    uint64_t wp;  // floor(w * 2^64 / q)
+    uint64_t wp;
 };
 
 // A set of RNS polynomials processed by one NTT launch.  Limb i (0 <= i <
