@@ -209,6 +209,33 @@ int pft_ptmatvec(pft_ctx* ctx, const pft_ptmat* m, uint32_t n_docs, const pft_ct
 int pft_ntt_forward(pft_ctx* ctx, uint64_t* data, uint32_t n_polys, uint32_t n_limbs);
 int pft_ntt_inverse(pft_ctx* ctx, uint64_t* data, uint32_t n_polys, uint32_t n_limbs);
 
+/* ---- NTT pass schedules (autotuner) --------------------------------------
+ * A transform of length N = 2^log_n runs as one or two passes over windows of
+ * consecutive stages.  A schedule crosses this boundary as four uint32 words:
+ * the window sizes (radices, log2 of each window's stage count) in forward
+ * order, zero-filled to three entries and summing to log_n, then a flags word
+ * (bit 0: the last window's pass accesses the side of its data that is not
+ * coalesced directly, 16 bytes per lane, instead of staging it through LDS).
+ * Every schedule computes the same transform bit for bit; the choice only
+ * changes speed.
+ * pft_ntt_candidates writes the candidates for the ring of p (default first)
+ * as scheds[4 i .. 4 i + 3] for i < max_count and returns how many exist
+ * (scheds may be NULL to count them).
+ * pft_ntt_autotune(ctx, 1) (the default): the first transform of a direction
+ * and batch-size class (up to 2^k limbs, k <= 10) times every candidate on
+ * library-allocated scratch (zeroed, <= 2^10 limbs cycling through all
+ * moduli) on the context stream and keeps the fastest; while a graph capture
+ * is open the default schedule is used instead.  pft_ntt_autotune(ctx, 0)
+ * forgets tuned choices and uses the default.  pft_ntt_set_schedule pins a
+ * candidate (4 words) for one direction (inverse 0/1) and every batch size
+ * (NULL unpins); PFT_EINVAL if it is not a candidate.  pft_ntt_get_schedule
+ * writes the schedule a transform of n_limbs limbs would use (tuning first if
+ * enabled). */
+int pft_ntt_candidates(const pft_params* p, uint32_t* scheds, uint32_t max_count);
+int pft_ntt_autotune(pft_ctx* ctx, int enable);
+int pft_ntt_set_schedule(pft_ctx* ctx, int inverse, const uint32_t* sched);
+int pft_ntt_get_schedule(pft_ctx* ctx, int inverse, uint64_t n_limbs, uint32_t* sched);
+
 /* ---- HIP graphs ----------------------------------------------------------
  * pft_graph_begin starts a capture on the context stream (which must not be
  * the null stream); every following call on the context is recorded instead

@@ -314,6 +314,39 @@ class Context:
         n_polys = data.numel() // (n_limbs * self.params.n)
         N.check(self.lib.pft_ntt_inverse(self.handle, ctypes.c_void_p(data.data_ptr()), n_polys, n_limbs))
 
+    # ---- NTT pass schedules (see pft_ntt_candidates): a schedule is
+    # (radices in forward order, direct) with direct = the last window's pass
+    # skips the LDS staging
+    @staticmethod
+    def _sched_from(words):
+        return tuple(int(r) for r in words[:3] if r), bool(words[3] & 1)
+
+    @staticmethod
+    def _sched_to(sched):
+        radices, direct = sched
+        return (ctypes.c_uint32 * 4)(*(list(radices) + [0] * (3 - len(radices)) + [1 if direct else 0]))
+
+    def ntt_candidates(self):
+        n = self.lib.pft_ntt_candidates(self.params.handle, None, 0)
+        if n < 0:
+            N.check(n)
+        buf = (ctypes.c_uint32 * (4 * n))()
+        self.lib.pft_ntt_candidates(self.params.handle, buf, n)
+        return [self._sched_from(buf[4 * i:4 * i + 4]) for i in range(n)]
+
+    def ntt_autotune(self, enable: bool):
+        N.check(self.lib.pft_ntt_autotune(self.handle, int(bool(enable))))
+
+    def ntt_set_schedule(self, inverse: bool, sched):
+        """sched: (radices, direct), or None to unpin."""
+        arr = None if sched is None else self._sched_to(sched)
+        N.check(self.lib.pft_ntt_set_schedule(self.handle, int(bool(inverse)), arr))
+
+    def ntt_get_schedule(self, inverse: bool, n_limbs: int):
+        arr = (ctypes.c_uint32 * 4)()
+        N.check(self.lib.pft_ntt_get_schedule(self.handle, int(bool(inverse)), n_limbs, arr))
+        return self._sched_from(arr)
+
 
 class Graph:
     def __init__(self, ctx, handle):

@@ -214,6 +214,11 @@ struct pft_ctx {
     bool capturing = false;  // a HIP graph capture is open on the stream
     int live_graphs = 0;     // graphs may reference ws/aux: grow by retiring, never free
     std::vector<void*> retired;
+    // NTT pass schedules: pinned per direction, else tuned per (direction,
+    // batch-size class) on first use when ntt_tune is set
+    bool ntt_tune = true;
+    NttSchedule ntt_pinned[2] = {};
+    std::map<uint32_t, NttSchedule> ntt_tuned;
 };
 
 template <typename T>
@@ -476,9 +481,98 @@ struct NttJob {
     uint32_t gap_at, gap_len;
 };
 
+// ---- NTT schedule selection (autotuner) -----------------------------------
+// Transforms of up to 2^k limbs share a class (k <= 10); every candidate
+// schedule gives the same result, so the choice only affects speed.
+static uint32_t ntt_class(uint64_t limbs) {
+    uint32_t k = 0;
+    while (k < 10 && (1ull << k) < limbs) ++k;
+    return k;
+}
+
+static NttSchedule ntt_default(const pft_params* P) {
+    NttSchedule s[1];
+    ntt_candidates(P->log_n, s, 1);
+    return s[0];
+}
+
+// Times every candidate on zeroed scratch of min(limbs, 2^class) limbs that
+// cycle through all L + K moduli (fp64 and integer limbs in the chain's
+// proportion); keeps the fastest mean of three runs.
+static NttSchedule ntt_tune(pft_ctx* c, bool inverse, uint32_t cls) {
+    const pft_params* P = c->P;
+    NttSchedule cand[16];
+    const int nc = ntt_candidates(P->log_n, cand, 16);
+    if (nc <= 1) return cand[0];
+    const uint32_t rows = P->L + P->K;
+    const uint64_t want = 1ull << cls;
+    uint32_t np = (uint32_t)std::min<uint64_t>((want + rows - 1) / rows, PFT_MAX_POLYS);
+    if (np == 0) np = 1;
+    const uint32_t nl = (uint32_t)std::min<uint64_t>(want, rows);
+    const size_t bytes = (size_t)np * rows * P->n * 8;
+    void* buf = nullptr;
+    if (hipMalloc(&buf, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return cand[0];
+    }
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) {
+        hipFree(buf);
+        return cand[0];
+    }
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        hipFree(buf);
+        return cand[0];
+    }
+    NttSchedule best = cand[0];
+    float best_ms = 1e30f;
+    bool ok = hipMemsetAsync(buf, 0, bytes, c->stream) == hipSuccess;
+    PolyBatch b{};
+    for (uint32_t i = 0; i < np; ++i) {
+        b.ptr[i] = (uint64_t*)buf + ((size_t)i * rows << P->log_n);
+        b.gap_at[i] = 255;
+        b.gap_len[i] = 0;
+    }
+    b.n_polys = np;
+    b.n_limbs = nl;
+    b.split = P->L;
+    b.off0 = 0;
+    b.off1 = P->L;
+    for (int k = 0; ok && k < nc; ++k) {
+        launch_ntt(b, c->tabs, P->log_n, inverse, cand[k], c->stream, nullptr);
+        ok = hipEventRecord(e0, c->stream) == hipSuccess;
+        for (int r = 0; r < 3; ++r) launch_ntt(b, c->tabs, P->log_n, inverse, cand[k], c->stream, nullptr);
+        ok = ok && hipEventRecord(e1, c->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+        float ms = 0;
+        if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < best_ms) {
+            best_ms = ms;
+            best = cand[k];
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipStreamSynchronize(c->stream);
+    hipFree(buf);
+    return best;
+}
+
+static NttSchedule ntt_schedule(pft_ctx* c, bool inverse, uint64_t limbs) {
+    if (c->ntt_pinned[inverse].n_passes) return c->ntt_pinned[inverse];
+    const uint32_t key = (inverse ? 64u : 0u) + ntt_class(limbs);
+    auto it = c->ntt_tuned.find(key);
+    if (it != c->ntt_tuned.end()) return it->second;
+    if (!c->ntt_tune) return ntt_default(c->P);
+    if (c->capturing) return ntt_default(c->P);  // no timing inside a capture
+    const NttSchedule s = ntt_tune(c, inverse, ntt_class(limbs));
+    c->ntt_tuned[key] = s;
+    return s;
+}
+
 static void ntt_jobs(pft_ctx* c, const std::vector<NttJob>& jobs, uint32_t n_limbs, uint32_t split, bool inverse,
                      uint32_t off0 = 0) {
     const pft_params* P = c->P;
+    const NttSchedule sched = ntt_schedule(c, inverse, (uint64_t)jobs.size() * n_limbs);
     for (size_t s = 0; s < jobs.size(); s += PFT_MAX_POLYS) {
         PolyBatch b{};
         const uint32_t np = (uint32_t)std::min<size_t>(PFT_MAX_POLYS, jobs.size() - s);
@@ -492,7 +586,7 @@ static void ntt_jobs(pft_ctx* c, const std::vector<NttJob>& jobs, uint32_t n_lim
         b.split = split;
         b.off0 = off0;
         b.off1 = P->L;
-        launch_ntt(b, c->tabs, P->log_n, inverse, c->stream, hook(c));
+        launch_ntt(b, c->tabs, P->log_n, inverse, sched, c->stream, hook(c));
     }
 }
 
@@ -1453,6 +1547,50 @@ extern "C" int pft_ntt_forward(pft_ctx* c, uint64_t* data, uint32_t n_polys, uin
 }
 extern "C" int pft_ntt_inverse(pft_ctx* c, uint64_t* data, uint32_t n_polys, uint32_t n_limbs) {
     return raw_ntt(c, data, n_polys, n_limbs, true);
+}
+
+// Schedules cross the boundary as four words: up to three radices in
+// forward order (then zeros) and the flags word.
+static void sched_words(const NttSchedule& s, uint32_t* w) {
+    for (uint32_t k = 0; k < 3; ++k) w[k] = k < s.n_passes ? s.radix[k] : 0;
+    w[3] = s.flags;
+}
+
+extern "C" int pft_ntt_candidates(const pft_params* p, uint32_t* scheds, uint32_t max_count) {
+    if (!p) return fail(PFT_EINVAL, "null params");
+    NttSchedule cand[16];
+    const int n = ntt_candidates(p->log_n, cand, 16);
+    if (scheds)
+        for (uint32_t i = 0; i < std::min<uint32_t>((uint32_t)n, max_count); ++i) sched_words(cand[i], scheds + 4 * i);
+    return n;
+}
+
+extern "C" int pft_ntt_autotune(pft_ctx* c, int enable) {
+    if (!c) return fail(PFT_EINVAL, "null context");
+    c->ntt_tune = enable != 0;
+    if (!c->ntt_tune) c->ntt_tuned.clear();
+    return PFT_OK;
+}
+
+extern "C" int pft_ntt_set_schedule(pft_ctx* c, int inverse, const uint32_t* sched) {
+    if (!c) return fail(PFT_EINVAL, "null context");
+    NttSchedule s{};
+    if (sched) {
+        for (uint32_t k = 0; k < 3 && sched[k]; ++k) {
+            if (sched[k] > 16) return fail(PFT_EINVAL, "bad radix %u", sched[k]);
+            s.radix[s.n_passes++] = (uint8_t)sched[k];
+        }
+        s.flags = sched[3];
+        if (!ntt_schedule_valid(c->P->log_n, s)) return fail(PFT_EINVAL, "not a candidate schedule for this ring");
+    }
+    c->ntt_pinned[inverse ? 1 : 0] = s;
+    return PFT_OK;
+}
+
+extern "C" int pft_ntt_get_schedule(pft_ctx* c, int inverse, uint64_t n_limbs, uint32_t* sched) {
+    if (!c || !sched) return fail(PFT_EINVAL, "null argument");
+    sched_words(ntt_schedule(c, inverse != 0, n_limbs ? n_limbs : 1), sched);
+    return PFT_OK;
 }
 
 // ---------------------------------------------------------------------------

@@ -186,14 +186,18 @@ __device__ __forceinline__ void run_phase(uint64_t (&x)[16], uint32_t l, uint32_
 
 // LDS word of element r of sub-problem c: c S + r + P (r >> 4).  The address
 // is affine in the register index e of every arrangement (so ds_read/ds_write
-// take immediate offsets), and (S, P) are chosen per M so that each access
-// pattern of the pass -- a register phase's arrangement under either lane
-// mapping, and the staging order -- spreads the 64 lanes of a wave over the
-// LDS banks with at most 1.5x the conflict-free number of cycles (1x for most).
+// take immediate offsets).  (S, P) are chosen per M for the LDS serving 16
+// lanes x 8 bytes per cycle: every access pattern of the pass -- a register
+// phase's arrangement under either lane mapping, and the staging order --
+// puts each group of 16 consecutive lanes on distinct bank pairs (radix 6
+// and 7 keep a two-way conflict on one row-pass pattern).
 template <int LOG_M> struct LdsPad;
-template <> struct LdsPad<6> { static constexpr uint32_t S = 67, P = 0; };
-template <> struct LdsPad<7> { static constexpr uint32_t S = 137, P = 1; };
-template <> struct LdsPad<8> { static constexpr uint32_t S = 274, P = 1; };
+template <> struct LdsPad<4> { static constexpr uint32_t S = 17, P = 0; };
+template <> struct LdsPad<6> { static constexpr uint32_t S = 69, P = 1; };
+template <> struct LdsPad<7> { static constexpr uint32_t S = 145, P = 2; };
+template <> struct LdsPad<8> { static constexpr uint32_t S = 273, P = 1; };
+template <> struct LdsPad<9> { static constexpr uint32_t S = 546, P = 1; };
+template <> struct LdsPad<10> { static constexpr uint32_t S = 1092, P = 1; };
 template <> struct LdsPad<12> { static constexpr uint32_t S = 4352, P = 1; };
 template <int LOG_M>
 constexpr uint32_t lds_words() { return (4096u >> LOG_M) * LdsPad<LOG_M>::S; }
@@ -239,13 +243,15 @@ __device__ __forceinline__ void run_phases(uint64_t (&x)[16], uint64_t* lds, uin
 // sub-problem are 2^lbits apart): consecutive lanes take consecutive
 // sub-problems, so every register arrangement is a coalesced global access
 // and the pass loads and stores directly.  Row passes (lbits = 0, each
-// sub-problem contiguous): consecutive lanes walk along a sub-problem; a side
-// whose arrangement gives runs shorter than 16 words goes through LDS in
-// address order instead.
+// sub-problem contiguous): consecutive lanes walk along a sub-problem.  With
+// STAGE, a side whose arrangement gives runs shorter than 16 words goes
+// through LDS in address order; without, it is accessed directly, and the
+// arrangement in which each thread owns 16 consecutive words (the window's
+// lowest stages) moves 16 bytes per lane per access.
 // Limbs with DevMod::fp run the fp64 butterflies: the first pass of a
 // transform converts its u64 input, later passes exchange the doubles through
 // HBM, and the final pass writes canonical u64.  Integer limbs keep u64.
-template <int LOG_M, bool INV, bool COL, bool FINAL>
+template <int LOG_M, bool INV, bool COL, bool FINAL, bool STAGE>
 __global__ __launch_bounds__(256) void k_ntt_pass(PolyBatch b, const DevMod* __restrict__ mods,
                                                   const TwPair* __restrict__ tw, uint32_t log_n, uint32_t s0,
                                                   uint32_t first_pass) {
@@ -255,8 +261,11 @@ __global__ __launch_bounds__(256) void k_ntt_pass(PolyBatch b, const DevMod* __r
     constexpr int NPH = (LOG_M + 3) / 4;
     constexpr int PH_IN = INV ? NPH - 1 : 0;
     constexpr int PH_OUT = INV ? 0 : NPH - 1;
-    constexpr bool DIRECT_IN = COL || Phase<LOG_M, PH_IN>::WLO >= 4;
-    constexpr bool DIRECT_OUT = COL || Phase<LOG_M, PH_OUT>::WLO >= 4;
+    constexpr bool DIRECT_IN = COL || !STAGE || Phase<LOG_M, PH_IN>::WLO >= 4;
+    constexpr bool DIRECT_OUT = COL || !STAGE || Phase<LOG_M, PH_OUT>::WLO >= 4;
+    // a row-pass arrangement where thread l owns words 16 l .. 16 l + 15
+    constexpr bool VEC_IN = !COL && Phase<LOG_M, PH_IN>::WLO == 0;
+    constexpr bool VEC_OUT = !COL && Phase<LOG_M, PH_OUT>::WLO == 0;
     __shared__ uint64_t lds[lds_words<LOG_M>()];
 
     const uint32_t tid = threadIdx.x;
@@ -284,7 +293,15 @@ __global__ __launch_bounds__(256) void k_ntt_pass(PolyBatch b, const DevMod* __r
 
     uint64_t x[16];
     const bool convert_in = fp && first_pass;
-    if constexpr (DIRECT_IN) {
+    if constexpr (DIRECT_IN && VEC_IN) {
+        const ulonglong2* __restrict__ src = reinterpret_cast<const ulonglong2*>(data + gidx(c, 16u * l));
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const ulonglong2 v = src[e];
+            x[2 * e] = convert_in ? fp_from_u64(v.x) : v.x;
+            x[2 * e + 1] = convert_in ? fp_from_u64(v.y) : v.y;
+        }
+    } else if constexpr (DIRECT_IN) {
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
             const uint64_t v = data[gidx(c, Phase<LOG_M, PH_IN>::r_of(l, e))];
@@ -321,7 +338,16 @@ __global__ __launch_bounds__(256) void k_ntt_pass(PolyBatch b, const DevMod* __r
         }
         return v;
     };
-    if constexpr (DIRECT_OUT) {
+    if constexpr (DIRECT_OUT && VEC_OUT) {
+        ulonglong2* __restrict__ dst = reinterpret_cast<ulonglong2*>(data + gidx(c, 16u * l));
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            ulonglong2 v;
+            v.x = finish(x[2 * e]);
+            v.y = finish(x[2 * e + 1]);
+            dst[e] = v;
+        }
+    } else if constexpr (DIRECT_OUT) {
 #pragma unroll
         for (int e = 0; e < 16; ++e) data[gidx(c, Phase<LOG_M, PH_OUT>::r_of(l, e))] = finish(x[e]);
     } else {
@@ -336,35 +362,57 @@ __global__ __launch_bounds__(256) void k_ntt_pass(PolyBatch b, const DevMod* __r
     }
 }
 
-template <int LOG_M, bool INV>
-void launch_pass(const PolyBatch& b, const DevTables& t, uint32_t log_n, uint32_t s0, bool final_pass,
-                 hipStream_t st, ProfHook* g_prof) {
-    const uint32_t jobs = b.n_polys * b.n_limbs;
-    dim3 grid((1u << log_n) / 4096u, jobs);
-    const int kid = INV ? PK_NTT_INV : PK_NTT_FWD;
-    // the first pass executed: s0 = 0 going forward, the top window going back
-    const uint32_t first_pass = INV ? (s0 + LOG_M == log_n) : (s0 == 0);
+template <int LOG_M, bool INV, bool COL, bool FINAL>
+void launch_k(const PolyBatch& b, const DevTables& t, uint32_t log_n, uint32_t s0, uint32_t first_pass, bool stage,
+              hipStream_t st) {
+    const dim3 grid((1u << log_n) / 4096u, b.n_polys * b.n_limbs);
     const TwPair* tw = INV ? t.tw_inv : t.tw_fwd;
-    if (g_prof) g_prof->begin(kid);
-    // column pass when low index bits remain below the window; the final
-    // pass is the row pass going forward and the s0 = 0 pass going back
+    if (COL || stage)
+        hipLaunchKernelGGL((k_ntt_pass<LOG_M, INV, COL, FINAL, true>), grid, dim3(256), 0, st, b, t.mods, tw, log_n,
+                           s0, first_pass);
+    else if constexpr (!COL)
+        hipLaunchKernelGGL((k_ntt_pass<LOG_M, INV, COL, FINAL, false>), grid, dim3(256), 0, st, b, t.mods, tw,
+                           log_n, s0, first_pass);
+}
+
+// One pass.  A column pass (low index bits remain below the window) needs at
+// least 16 sub-problems per workgroup for coalescing, so radices above 8 only
+// run as the last window.  Going forward the last window is the final pass;
+// going back the s0 = 0 window is.
+template <int LOG_M, bool INV>
+void launch_pass(const PolyBatch& b, const DevTables& t, uint32_t log_n, uint32_t s0, bool final_pass, bool stage,
+                 hipStream_t st, ProfHook* g_prof) {
+    const int kid = INV ? PK_NTT_INV : PK_NTT_FWD;
+    const uint32_t first_pass = INV ? (s0 + LOG_M == log_n) : (s0 == 0);
     const bool col = s0 + LOG_M < log_n;
-    if (col && final_pass)
-        hipLaunchKernelGGL((k_ntt_pass<LOG_M, INV, true, true>), grid, dim3(256), 0, st, b, t.mods, tw, log_n, s0,
-                           first_pass);
-    else if (col)
-        hipLaunchKernelGGL((k_ntt_pass<LOG_M, INV, true, false>), grid, dim3(256), 0, st, b, t.mods, tw, log_n,
-                           s0, first_pass);
-    else if (final_pass)
-        hipLaunchKernelGGL((k_ntt_pass<LOG_M, INV, false, true>), grid, dim3(256), 0, st, b, t.mods, tw, log_n,
-                           s0, first_pass);
-    else
-        hipLaunchKernelGGL((k_ntt_pass<LOG_M, INV, false, false>), grid, dim3(256), 0, st, b, t.mods, tw, log_n,
-                           s0, first_pass);
+    if (g_prof) g_prof->begin(kid);
+    if (col) {
+        if constexpr (LOG_M <= 8) launch_k<LOG_M, INV, true, INV>(b, t, log_n, s0, first_pass, true, st);
+    } else if (final_pass) {
+        if constexpr (!INV || LOG_M == 12)
+            launch_k<LOG_M, INV, false, true>(b, t, log_n, s0, first_pass, stage, st);
+    } else {
+        if constexpr (INV) launch_k<LOG_M, INV, false, false>(b, t, log_n, s0, first_pass, stage, st);
+    }
     if (g_prof) {
-        const double elems = (double)jobs * (double)(1u << log_n);
+        const double elems = (double)b.n_polys * b.n_limbs * (double)(1u << log_n);
         // read + write every residue once; N/2 butterflies per stage
         g_prof->end(kid, 16.0 * elems, 0.5 * elems * LOG_M);
+    }
+}
+
+template <bool INV>
+void launch_radix(uint32_t radix, const PolyBatch& b, const DevTables& t, uint32_t log_n, uint32_t s0, bool fin,
+                  bool stage, hipStream_t st, ProfHook* prof) {
+    switch (radix) {
+        case 4: launch_pass<4, INV>(b, t, log_n, s0, fin, stage, st, prof); break;
+        case 6: launch_pass<6, INV>(b, t, log_n, s0, fin, stage, st, prof); break;
+        case 7: launch_pass<7, INV>(b, t, log_n, s0, fin, stage, st, prof); break;
+        case 8: launch_pass<8, INV>(b, t, log_n, s0, fin, stage, st, prof); break;
+        case 9: launch_pass<9, INV>(b, t, log_n, s0, fin, stage, st, prof); break;
+        case 10: launch_pass<10, INV>(b, t, log_n, s0, fin, stage, st, prof); break;
+        case 12: launch_pass<12, INV>(b, t, log_n, s0, fin, stage, st, prof); break;
+        default: break;
     }
 }
 
@@ -372,26 +420,66 @@ void launch_pass(const PolyBatch& b, const DevTables& t, uint32_t log_n, uint32_
 
 bool ntt_supported(uint32_t log_n) { return log_n >= 12 && log_n <= 16; }
 
-void launch_ntt(const PolyBatch& b, const DevTables& t, uint32_t log_n, bool inverse, hipStream_t st,
-                ProfHook* prof) {
-    if (b.n_polys == 0 || b.n_limbs == 0) return;
+// Candidate schedules per log2 N, the default first: every radix split
+// below, each with the row pass staged through LDS and direct.  Windows are
+// listed in forward order (stages 0.. first); every candidate has at most two
+// passes, so each moves every residue through HBM at most twice.
+int ntt_candidates(uint32_t log_n, NttSchedule* out, int max_out) {
+    static const uint8_t c12[][2] = {{12, 0}, {8, 4}, {6, 6}, {4, 8}};
+    static const uint8_t c13[][2] = {{7, 6}, {6, 7}, {4, 9}};
+    static const uint8_t c14[][2] = {{7, 7}, {8, 6}, {6, 8}, {4, 10}};
+    static const uint8_t c15[][2] = {{8, 7}, {7, 8}, {6, 9}};
+    static const uint8_t c16[][2] = {{8, 8}, {7, 9}, {6, 10}, {4, 12}};
+    const uint8_t(*c)[2] = nullptr;
+    int n = 0;
+    switch (log_n) {
+        case 12: c = c12; n = 4; break;
+        case 13: c = c13; n = 3; break;
+        case 14: c = c14; n = 4; break;
+        case 15: c = c15; n = 3; break;
+        case 16: c = c16; n = 4; break;
+        default: return 0;
+    }
+    int k = 0;
+    for (int direct = 0; direct < 2; ++direct)
+        for (int i = 0; i < n; ++i) {
+            if (k >= max_out) return k;
+            NttSchedule s{};
+            s.n_passes = c[i][1] ? 2 : 1;
+            s.radix[0] = c[i][0];
+            s.radix[1] = c[i][1];
+            s.flags = direct ? NTT_DIRECT_ROWS : 0;
+            out[k++] = s;
+        }
+    return k;
+}
+
+bool ntt_schedule_valid(uint32_t log_n, const NttSchedule& s) {
+    NttSchedule c[16];
+    const int n = ntt_candidates(log_n, c, 16);
+    for (int i = 0; i < n; ++i)
+        if (c[i].n_passes == s.n_passes && c[i].radix[0] == s.radix[0] && c[i].radix[1] == s.radix[1] &&
+            c[i].flags == s.flags)
+            return true;
+    return false;
+}
+
+void launch_ntt(const PolyBatch& b, const DevTables& t, uint32_t log_n, bool inverse, const NttSchedule& s,
+                hipStream_t st, ProfHook* prof) {
+    if (b.n_polys == 0 || b.n_limbs == 0 || s.n_passes == 0 || s.n_passes > 3) return;
+    uint32_t s0[4];
+    uint32_t acc = 0;
+    for (uint32_t p = 0; p < s.n_passes; ++p) {
+        s0[p] = acc;
+        acc += s.radix[p];
+    }
+    if (acc != log_n) return;
+    const bool stage = (s.flags & NTT_DIRECT_ROWS) == 0;
     if (!inverse) {
-        switch (log_n) {
-            case 12: launch_pass<12, false>(b, t, 12, 0, true, st, prof); break;
-            case 13: launch_pass<7, false>(b, t, 13, 0, false, st, prof); launch_pass<6, false>(b, t, 13, 7, true, st, prof); break;
-            case 14: launch_pass<7, false>(b, t, 14, 0, false, st, prof); launch_pass<7, false>(b, t, 14, 7, true, st, prof); break;
-            case 15: launch_pass<8, false>(b, t, 15, 0, false, st, prof); launch_pass<7, false>(b, t, 15, 8, true, st, prof); break;
-            case 16: launch_pass<8, false>(b, t, 16, 0, false, st, prof); launch_pass<8, false>(b, t, 16, 8, true, st, prof); break;
-            default: break;
-        }
+        for (uint32_t p = 0; p < s.n_passes; ++p)
+            launch_radix<false>(s.radix[p], b, t, log_n, s0[p], p + 1 == s.n_passes, stage, st, prof);
     } else {
-        switch (log_n) {
-            case 12: launch_pass<12, true>(b, t, 12, 0, true, st, prof); break;
-            case 13: launch_pass<6, true>(b, t, 13, 7, false, st, prof); launch_pass<7, true>(b, t, 13, 0, true, st, prof); break;
-            case 14: launch_pass<7, true>(b, t, 14, 7, false, st, prof); launch_pass<7, true>(b, t, 14, 0, true, st, prof); break;
-            case 15: launch_pass<7, true>(b, t, 15, 8, false, st, prof); launch_pass<8, true>(b, t, 15, 0, true, st, prof); break;
-            case 16: launch_pass<8, true>(b, t, 16, 8, false, st, prof); launch_pass<8, true>(b, t, 16, 0, true, st, prof); break;
-            default: break;
-        }
+        for (uint32_t p = s.n_passes; p-- > 0;)
+            launch_radix<true>(s.radix[p], b, t, log_n, s0[p], p == 0, stage, st, prof);
     }
 }

@@ -24,9 +24,19 @@ struct ProfHook {
     virtual ~ProfHook() {}
 };
 
+// An NTT pass schedule: the radices (log2 of the stage windows) in forward
+// order, summing to log2 N, and flags.
+enum : uint32_t { NTT_DIRECT_ROWS = 1 };  // row pass reads/writes its strided side directly
+struct NttSchedule {
+    uint32_t n_passes;
+    uint8_t radix[4];
+    uint32_t flags;
+};
 bool ntt_supported(uint32_t log_n);
-void launch_ntt(const PolyBatch& b, const DevTables& t, uint32_t log_n, bool inverse, hipStream_t st,
-                ProfHook* prof = nullptr);
+int ntt_candidates(uint32_t log_n, NttSchedule* out, int max_out);
+bool ntt_schedule_valid(uint32_t log_n, const NttSchedule& s);
+void launch_ntt(const PolyBatch& b, const DevTables& t, uint32_t log_n, bool inverse, const NttSchedule& s,
+                hipStream_t st, ProfHook* prof = nullptr);
 
 // ---- elementwise kernels (ckks.hip) --------------------------------------
 // Signed integer polynomials x ([n_polys][N] int64, device) reduced into

@@ -91,6 +91,10 @@ SIGNATURES = [
     ("pft_ptmatvec", [_vp, _vp, ctypes.c_uint32, ctypes.POINTER(CtDesc), ctypes.POINTER(CtDesc)], ctypes.c_int),
     ("pft_ntt_forward", [_vp, _vp, ctypes.c_uint32, ctypes.c_uint32], ctypes.c_int),
     ("pft_ntt_inverse", [_vp, _vp, ctypes.c_uint32, ctypes.c_uint32], ctypes.c_int),
+    ("pft_ntt_candidates", [_vp, _u32p, ctypes.c_uint32], ctypes.c_int),
+    ("pft_ntt_autotune", [_vp, ctypes.c_int], ctypes.c_int),
+    ("pft_ntt_set_schedule", [_vp, ctypes.c_int, _u32p], ctypes.c_int),
+    ("pft_ntt_get_schedule", [_vp, ctypes.c_int, ctypes.c_uint64, _u32p], ctypes.c_int),
     ("pft_ctx_reserve", [_vp, ctypes.c_uint64, ctypes.c_uint64], ctypes.c_int),
     ("pft_graph_begin", [_vp], ctypes.c_int),
     ("pft_graph_end", [_vp, ctypes.POINTER(_vp)], ctypes.c_int),

@@ -87,3 +87,25 @@ def test_library_decode_matches_oracle():
     a1 = P.decode(res[:1], 2.0 ** 40)
     b1 = C.decode(res[:1], op.q[:1], op.n, 2.0 ** 40, op.n // 2)
     assert np.max(np.abs(a1 - b1)) <= 2.0 ** -20
+
+
+def test_ntt_candidate_schedules():
+    """Schedules cover log2 N exactly, default first, at most two passes, only
+    the last window may exceed radix 8 (column passes need >= 16 sub-problems
+    per workgroup), and each radix split comes staged and direct."""
+    from paper_1908_06972_amd.ckks import Params
+    lib = N.load()
+    for log_n in range(12, 17):
+        p = Params(log_n, 2, 40, 40, 1, 50, 1, 2 ** 30)
+        n = lib.pft_ntt_candidates(p.handle, None, 0)
+        assert n >= 4
+        buf = (ctypes.c_uint32 * (4 * n))()
+        assert lib.pft_ntt_candidates(p.handle, buf, n) == n
+        scheds = [(tuple(r for r in buf[4 * i:4 * i + 3] if r), buf[4 * i + 3]) for i in range(n)]
+        assert len(set(scheds)) == n
+        for radices, flags in scheds:
+            assert sum(radices) == log_n and 1 <= len(radices) <= 2
+            assert all(r <= 8 for r in radices[:-1])
+            assert flags in (0, 1)
+            assert (radices, 1 - flags) in scheds
+        assert scheds[0] == ({12: (12,), 13: (7, 6), 14: (7, 7), 15: (8, 7), 16: (8, 8)}[log_n], 0)

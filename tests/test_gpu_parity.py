@@ -49,11 +49,75 @@ def test_ntt_forward_inverse(torch_cuda, log_n):
     assert np.array_equal(L.to_host_u64(dev), host)
 
 
-def test_ntt_extreme_values(torch_cuda):
-    """All-zero, all q-1 and a single spike: exercises the lazy ranges."""
+def _oracle_ntt(op, host):
+    n = host.shape[-1]
+    out = np.empty_like(host)
+    for p in range(host.shape[0]):
+        for i in range(host.shape[1]):
+            q = op.q[i]
+            _ring.lib().or_ntt_fast(_ring.ptr(np.ascontiguousarray(host[p, i])), _ring.ptr(out[p, i]), n, q,
+                                    op.psi[q])
+    return out
+
+
+@pytest.mark.parametrize("log_n", [12, 13, 14, 15, 16])
+def test_ntt_every_schedule(torch_cuda, log_n):
+    """Every candidate pass schedule (integer limbs: the 60-bit q0; fp64
+    limbs: the 50- and 40-bit primes) gives the oracle's transform and
+    round-trips, on random rows plus all-(q-1) and spike rows."""
     import paper_1908_06972_amd.ckks as L
-    lp = L.Params(16, 2, 60, 60, 1, 60, 1, 2 ** 40)
-    op = C.Params(16, 2, 60, 60, 1, 60, 1, 2 ** 40)
+    lp = L.Params(log_n, 4, 60, 50, 1, 40, 2, 2 ** 40)
+    op = C.Params(log_n, 4, 60, 50, 1, 40, 2, 2 ** 40)
+    assert lp.q == op.q
+    ctx = L.Context(lp)
+    n = 1 << log_n
+    g = np.random.default_rng(100 + log_n)
+    host = np.stack([np.stack([g.integers(0, q, n, dtype=np.uint64) for q in op.q]) for _ in range(3)])
+    for i, q in enumerate(op.q):
+        host[1, i] = q - 1
+        host[2, i] = 0
+        host[2, i, (7 * i + 1) % n] = q - 1
+    want = _oracle_ntt(op, host)
+    cands = ctx.ntt_candidates()
+    assert len(cands) >= 4 and all(sum(c[0]) == log_n for c in cands)
+    for sched in cands:
+        ctx.ntt_set_schedule(False, sched)
+        ctx.ntt_set_schedule(True, sched)
+        assert ctx.ntt_get_schedule(False, 12) == sched
+        dev = L.to_device_u64(host, ctx.device)
+        ctx.ntt_forward(dev, len(op.q))
+        assert np.array_equal(L.to_host_u64(dev), want), sched
+        ctx.ntt_inverse(dev, len(op.q))
+        assert np.array_equal(L.to_host_u64(dev), host), sched
+
+
+def test_ntt_autotune_picks_a_candidate(torch_cuda):
+    import paper_1908_06972_amd.ckks as L
+    import paper_1908_06972_amd.native as N
+    lp = L.Params(14, 4, 60, 50, 1, 60, 2, 2 ** 40)
+    ctx = L.Context(lp)
+    cands = ctx.ntt_candidates()
+    for inv in (False, True):
+        for limbs in (1, 40, 5000):
+            assert ctx.ntt_get_schedule(inv, limbs) in cands
+    ctx.ntt_autotune(False)
+    assert ctx.ntt_get_schedule(False, 40) == cands[0]
+    with pytest.raises(N.PftError):
+        ctx.ntt_set_schedule(False, ((7, 6, 1), False))
+    with pytest.raises(N.PftError):
+        ctx.ntt_set_schedule(False, ((8, 8), False))
+    ctx.ntt_set_schedule(True, cands[-1])
+    assert ctx.ntt_get_schedule(True, 7) == cands[-1]
+    ctx.ntt_set_schedule(True, None)
+
+
+@pytest.mark.parametrize("bits", [(60, 60, 60), (60, 50, 60), (40, 40, 50)])
+def test_ntt_extreme_values(torch_cuda, bits):
+    """All-zero, all q-1 and a single spike: exercises the lazy ranges of the
+    integer butterflies (60-bit primes) and the fp64 bounds (<= 50 bits)."""
+    import paper_1908_06972_amd.ckks as L
+    lp = L.Params(16, 2, bits[0], bits[1], 1, bits[2], 1, 2 ** 40)
+    op = C.Params(16, 2, bits[0], bits[1], 1, bits[2], 1, 2 ** 40)
     ctx = L.Context(lp)
     n = 1 << 16
     host = np.zeros((3, 2, n), dtype=np.uint64)
