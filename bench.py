@@ -33,9 +33,17 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, AMD published
 ALU_PEAK_GOPS = 256 * 64 * 2.4  # int32 VALU lane-ops/s in G: 256 CUs x 64 lanes x 2.4 GHz
 FAMILIES = ["ntt_fwd_pass", "ntt_inv_pass", "modup_bconv", "key_inner_product", "moddown_bconv",
             "moddown_final", "tensor", "automorphism", "rescale", "elementwise"]
-KERNEL_NAMES = {0: "k_ntt_pass<8, false>", 1: "k_ntt_pass<8, true>", 2: "k_modup", 3: "k_key_inner",
-                4: "k_moddown_conv", 5: "k_moddown_final", 6: "k_tensor", 7: "k_automorphism",
-                8: "k_rescale_expand/k_rescale_final"}
+KERNEL_NAMES = {2: "k_modup_b", 3: "k_key_inner_b", 4: "k_moddown_conv_b", 5: "k_moddown_final_b", 6: "k_tensor_b",
+                7: "k_automorphism_b", 8: "k_rescale_expand_b/k_rescale_final_b"}
+
+
+def kernel_name(kid, variant):
+    """Demangled kernel name of one instantiation (see pft_prof_read_variants)."""
+    if kid in (0, 1) and variant:
+        v = variant - 1
+        b = lambda x: "true" if x else "false"  # noqa: E731
+        return "k_ntt_pass<%d, %s, %s, %s, %s>" % (v & 31, b(kid == 1), b(v & 32), b(v & 64), b(v & 128))
+    return KERNEL_NAMES.get(kid, FAMILIES[kid])
 CHAIN_DEPTH = 8
 ROT_SLOTS = 1 << 15
 
@@ -229,10 +237,30 @@ def parse():
                     help="requests of the serving measurement (0 skips it)")
     ap.add_argument("--summarize", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="write the markdown summary of three rocprofv3 runs of the timed region and exit")
-    ap.add_argument("--kernel", default="k_ntt_pass<8, false>")
+    ap.add_argument("--kernel", default="k_ntt_pass<8, false, true, false, true>",
+                    help="kernel the --summarize counters are collected for (the roofline kernel bench prints)")
     ap.add_argument("--family", type=int, default=0)
     ap.add_argument("--commands", nargs="*", default=[])
     return ap.parse_args()
+
+
+def prof_top_variant(ctx, kid):
+    """(variant, total ms, launches, bytes, ops) of the instantiation of
+    family kid with the largest total time since prof_enable."""
+    import ctypes
+    from paper_1908_06972_amd import native as N
+    n = 16
+    var = (ctypes.c_uint32 * n)()
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_uint64 * n)()
+    by = (ctypes.c_double * n)()
+    op = (ctypes.c_double * n)()
+    k = ctx.lib.pft_prof_read_variants(ctx.handle, kid, n, var, ms, cnt, by, op)
+    if k < 0:
+        N.check(k)
+    if k == 0:
+        return 0, 0.0, 0, 0.0, 0.0
+    return var[0], ms[0], cnt[0], by[0], op[0]
 
 
 def prof_read(ctx, kid):
@@ -469,7 +497,8 @@ def main():
     sync()
     elapsed = time.perf_counter() - t0
     roctx.pause()
-    d_ms, d_cnt, d_bytes, d_ops = prof_read(ctx, dom)
+    dom_ms = prof_read(ctx, dom)[0]
+    variant, d_ms, d_cnt, d_bytes, d_ops = prof_top_variant(ctx, dom)
     prof_enable(ctx, 0)
 
     hmults = args.batch * CHAIN_DEPTH * args.steps
@@ -520,7 +549,7 @@ def main():
 
     avg_ms = d_ms / max(d_cnt, 1)
     gbs = d_bytes / (d_ms * 1e-3) / 1e9 if d_ms > 0 else 0.0
-    kname = KERNEL_NAMES.get(dom, FAMILIES[dom])
+    kname = kernel_name(dom, variant)
     stored = stored_profile(kname, dom)
     traffic = None
     alu = None
@@ -547,6 +576,7 @@ def main():
         "alg_bytes_per_launch": d_bytes / max(d_cnt, 1),
         "alg_butterflies_per_launch": d_ops / max(d_cnt, 1),
         "share_of_step": round(totals[dom][0] / step_total, 3) if step_total else None,
+        "kernel_share_of_family": round(d_ms / dom_ms, 3) if dom_ms else None,
         "alu": alu,
     }
 

@@ -236,6 +236,44 @@ int pft_ntt_autotune(pft_ctx* ctx, int enable);
 int pft_ntt_set_schedule(pft_ctx* ctx, int inverse, const uint32_t* sched);
 int pft_ntt_get_schedule(pft_ctx* ctx, int inverse, uint64_t n_limbs, uint32_t* sched);
 
+/* ---- op-list executor ---------------------------------------------------
+ * pft_exec_batch runs n_ops operations on the ciphertexts cts[0..n_cts) with
+ * the result of issuing them one at a time, in list order, through the
+ * single-op calls (bit for bit; the descriptors' level and scale of every
+ * output are updated as those calls would).  op.a / op.b / op.out index cts:
+ *   PFT_OP_NTT, PFT_OP_INTT   forward / inverse transform of both polynomials
+ *                             of cts[a] in place (raw RNS polynomials, as
+ *                             pft_ntt_forward/inverse); b, out unused
+ *   PFT_OP_ADD                cts[out] = cts[a] + cts[b]            (pft_add)
+ *   PFT_OP_MUL_RELIN          cts[out] = HMUL+relin(cts[a], cts[b]) (out distinct)
+ *   PFT_OP_RESCALE            cts[out] = RESCALE(cts[a]), op.mode as pft_rescale
+ *   PFT_OP_ROTATE             cts[out] = ROTATE(cts[a], op.step)    (out distinct)
+ * Output buffers are caller-owned and sized for their level.  The list is
+ * split into dependency waves (an op waits for every earlier op that writes
+ * what it touches or reads what it writes); inside a wave, ops of equal kind,
+ * input level and step/mode run as one batched call, and the groups of a wave
+ * run concurrently on side streams forked from the context stream (joined
+ * before the next wave), each with its own library workspace, so ciphertexts
+ * of different levels share the device.  Captured between pft_graph_begin and
+ * pft_graph_end, the list becomes one graph with a branch per group (run it
+ * once eagerly first so the workspaces exist).  Errors: PFT_EINVAL (bad
+ * index, kind, aliasing, timing enabled), PFT_ELEVEL (operand levels), any
+ * error of the single-op calls; work of earlier waves may have been issued. */
+enum { PFT_OP_NTT = 1, PFT_OP_INTT = 2, PFT_OP_ADD = 3, PFT_OP_MUL_RELIN = 4, PFT_OP_RESCALE = 5, PFT_OP_ROTATE = 6 };
+typedef struct pft_op {
+    uint32_t kind;
+    uint32_t a, b, out;
+    int32_t step;   /* PFT_OP_ROTATE */
+    uint32_t mode;  /* PFT_OP_RESCALE */
+} pft_op;
+int pft_exec_batch(pft_ctx* ctx, pft_ct* cts, uint32_t n_cts, const pft_op* ops, uint32_t n_ops);
+/* The plan pft_exec_batch would follow, on the host only: for input levels
+ * levels[0..n_cts), writes each op's wave and its group index within the
+ * wave (either array may be NULL) and returns the number of waves, or the
+ * error pft_exec_batch would return for the list. */
+int pft_exec_plan(const pft_op* ops, uint32_t n_ops, const uint32_t* levels, uint32_t n_cts, uint32_t* wave,
+                  uint32_t* group);
+
 /* ---- HIP graphs ----------------------------------------------------------
  * pft_graph_begin starts a capture on the context stream (which must not be
  * the null stream); every following call on the context is recorded instead
@@ -266,6 +304,14 @@ void pft_graph_destroy(pft_graph* graph);
  * 8 rescale, 9 other elementwise. */
 int pft_prof_enable(pft_ctx* ctx, uint32_t mask);
 int pft_prof_read(pft_ctx* ctx, uint32_t kid, double* total_ms, uint64_t* launches, double* bytes, double* ops);
+/* Per-instantiation totals of family kid since pft_prof_enable, largest total
+ * time first: up to max_count entries of (variant, ms, launches, algorithmic
+ * bytes, ops); returns the number of distinct variants.  variant 0: the
+ * family's single kernel; NTT passes (families 0 and 1): 1 + (radix | 32 if a
+ * column pass | 64 if the transform's final pass | 128 if staged), naming
+ * k_ntt_pass<radix, inverse, column, final, staged>.  Any output may be NULL. */
+int pft_prof_read_variants(pft_ctx* ctx, uint32_t kid, uint32_t max_count, uint32_t* variants, double* total_ms,
+                           uint64_t* launches, double* bytes, double* ops);
 
 /* ---- client-side ENCODE / DECODE on the host (Sec. 3.4; CPU per Sec. 5.1)
  * encode: slots z_j = re[j] + i im[j], j < n_slots <= N/2, to the integer

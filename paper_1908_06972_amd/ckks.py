@@ -257,6 +257,23 @@ class Context:
         N.check(self.lib.pft_rotate(self.handle, ctypes.byref(da), int(step), ctypes.byref(do)))
         return out.sync_from(do)
 
+    def exec_batch(self, cts, ops):
+        """Run an op list (see pft_exec_batch) over the ciphertexts `cts`.
+        ops: tuples (kind, a, b, out, step, mode) with kind one of
+        'ntt', 'intt', 'add', 'mul_relin', 'rescale', 'rotate' and a/b/out
+        indices into cts (unused fields may be 0).  Output ciphertexts must be
+        allocated for their level; levels and scales are updated in place."""
+        kinds = {"ntt": N.PFT_OP_NTT, "intt": N.PFT_OP_INTT, "add": N.PFT_OP_ADD, "mul_relin": N.PFT_OP_MUL_RELIN,
+                 "rescale": N.PFT_OP_RESCALE, "rotate": N.PFT_OP_ROTATE}
+        C = self._arr(cts)
+        O = (N.OpDesc * len(ops))()
+        for i, (kind, a, b, out, step, mode) in enumerate(ops):
+            O[i] = N.OpDesc(kinds[kind], a, b, out, int(step), mode)
+        N.check(self.lib.pft_exec_batch(self.handle, C, len(cts), O, len(ops)))
+        for i, c in enumerate(cts):
+            c.sync_from(C[i])
+        return cts
+
     def rotate_batch(self, a, step, out=None):
         out = out or [self.empty_ct(x.level) for x in a]
         A, O = self._arr(a), self._arr(out)

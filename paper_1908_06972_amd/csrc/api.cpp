@@ -152,6 +152,7 @@ struct EventProf : ProfHook {
     size_t used = 0;
     struct Rec {
         int kid;
+        uint32_t variant;
         hipEvent_t a, b;
         double bytes, ops;
     };
@@ -171,12 +172,12 @@ struct EventProf : ProfHook {
         open[kid] = get();
         if (open[kid]) (void)hipEventRecord(open[kid], st);
     }
-    void end(int kid, double bytes, double ops) override {
+    void end(int kid, double bytes, double ops, uint32_t variant) override {
         if (!on(kid) || !open[kid]) return;
         hipEvent_t b = get();
         if (!b) return;
         (void)hipEventRecord(b, st);
-        recs.push_back(Rec{kid, open[kid], b, bytes, ops});
+        recs.push_back(Rec{kid, variant, open[kid], b, bytes, ops});
         open[kid] = nullptr;
     }
     void reset() {
@@ -219,6 +220,11 @@ struct pft_ctx {
     bool ntt_tune = true;
     NttSchedule ntt_pinned[2] = {};
     std::map<uint32_t, NttSchedule> ntt_tuned;
+    // op-list executor: side streams and their workspaces (branch k > 0;
+    // branch 0 is the context stream with ws)
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> side_ev;
+    std::vector<std::pair<uint64_t*, size_t>> side_ws;
 };
 
 template <typename T>
@@ -423,6 +429,13 @@ extern "C" void pft_ctx_destroy(pft_ctx* c) {
     if (c->aux) (void)hipFree(c->aux);
     if (c->cbuf) (void)hipFree(c->cbuf);
     for (void* p : c->retired) (void)hipFree(p);
+    for (hipStream_t st : c->side) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+    }
+    for (hipEvent_t e : c->side_ev) (void)hipEventDestroy(e);
+    for (auto& w : c->side_ws)
+        if (w.first) (void)hipFree(w.first);
     delete c;
 }
 
@@ -1720,6 +1733,229 @@ extern "C" int pft_prof_read(pft_ctx* c, uint32_t kid, double* total_ms, uint64_
     *bytes = by;
     *ops = op;
     return PFT_OK;
+}
+
+extern "C" int pft_prof_read_variants(pft_ctx* c, uint32_t kid, uint32_t max_count, uint32_t* variants,
+                                      double* total_ms, uint64_t* launches, double* bytes, double* ops) {
+    if (!c) return fail(PFT_EINVAL, "null ctx");
+    if (kid >= PK_COUNT) return fail(PFT_EINVAL, "kernel family %u out of range", kid);
+    HIPCK(hipStreamSynchronize(c->stream));
+    struct Acc {
+        double ms = 0, by = 0, op = 0;
+        uint64_t n = 0;
+    };
+    std::map<uint32_t, Acc> acc;
+    for (const auto& r : c->prof.recs) {
+        if (r.kid != (int)kid) continue;
+        float t = 0;
+        HIPCK(hipEventElapsedTime(&t, r.a, r.b));
+        Acc& a = acc[r.variant];
+        a.ms += t;
+        a.by += r.bytes;
+        a.op += r.ops;
+        ++a.n;
+    }
+    std::vector<std::pair<uint32_t, Acc>> v(acc.begin(), acc.end());
+    std::stable_sort(v.begin(), v.end(), [](const std::pair<uint32_t, Acc>& x, const std::pair<uint32_t, Acc>& y) {
+        return x.second.ms > y.second.ms;
+    });
+    for (uint32_t i = 0; i < std::min<uint32_t>((uint32_t)v.size(), max_count); ++i) {
+        if (variants) variants[i] = v[i].first;
+        if (total_ms) total_ms[i] = v[i].second.ms;
+        if (launches) launches[i] = v[i].second.n;
+        if (bytes) bytes[i] = v[i].second.by;
+        if (ops) ops[i] = v[i].second.op;
+    }
+    return (int)v.size();
+}
+
+// ---------------------------------------------------------------------------
+// Op-list executor
+// ---------------------------------------------------------------------------
+// The list runs as if each op were issued alone, in order.  Plan: op j joins
+// wave 1 + max(wave of every earlier op sharing a ciphertext with j where
+// either writes it); within a wave, ops of equal (kind, input level,
+// step/mode) form one group, executed as one batched call (one fused launch
+// per stage for the whole group).  Groups of a wave are independent, so each
+// runs on its own stream (the context stream and side streams forked from it
+// with an event, joined back before the next wave) with its own workspace;
+// ciphertexts of different levels therefore occupy the device together.
+// Inside pft_graph_begin/end the side streams join the capture, so the whole
+// list becomes one graph with a parallel branch per group.
+namespace {
+struct ExecGroup {
+    uint32_t kind, level, mode;
+    int32_t step;
+    std::vector<uint32_t> ops;
+};
+}  // namespace
+
+static int exec_group(pft_ctx* c, pft_ct* cts, const pft_op* ops, const ExecGroup& g) {
+    const uint32_t n = (uint32_t)g.ops.size();
+    std::vector<pft_ct> a(n), b(n), o(n);
+    for (uint32_t i = 0; i < n; ++i) {
+        const pft_op& op = ops[g.ops[i]];
+        a[i] = cts[op.a];
+        b[i] = cts[op.kind == PFT_OP_ADD || op.kind == PFT_OP_MUL_RELIN ? op.b : op.a];
+        o[i] = cts[op.out];
+    }
+    int r = PFT_OK;
+    switch (g.kind) {
+        case PFT_OP_NTT:
+        case PFT_OP_INTT: {
+            std::vector<NttJob> jobs;
+            for (uint32_t i = 0; i < n; ++i)
+                for (uint32_t p = 0; p < 2; ++p)
+                    jobs.push_back(NttJob{a[i].data + ((size_t)p * g.level << c->P->log_n), 255u, 0u});
+            ntt_jobs(c, jobs, g.level, ~0u, g.kind == PFT_OP_INTT);
+            return PFT_OK;
+        }
+        case PFT_OP_ADD:
+            for (uint32_t i = 0; i < n && !r; ++i) r = pft_add(c, &a[i], &b[i], &o[i]);
+            break;
+        case PFT_OP_MUL_RELIN: r = pft_mul_relin_batch(c, n, a.data(), b.data(), o.data()); break;
+        case PFT_OP_RESCALE: r = pft_rescale_batch(c, n, a.data(), g.mode, o.data()); break;
+        case PFT_OP_ROTATE: r = pft_rotate_batch(c, n, a.data(), g.step, o.data()); break;
+        default: return fail(PFT_EINVAL, "unknown op kind %u", g.kind);
+    }
+    if (r) return r;
+    for (uint32_t i = 0; i < n; ++i) {
+        cts[ops[g.ops[i]].out].level = o[i].level;
+        cts[ops[g.ops[i]].out].scale = o[i].scale;
+    }
+    return PFT_OK;
+}
+
+static int side_branch(pft_ctx* c, size_t k) {
+    while (c->side.size() < k) {
+        hipStream_t st;
+        HIPCK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        c->side.push_back(st);
+        hipEvent_t e;
+        HIPCK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        c->side_ev.push_back(e);
+        c->side_ws.push_back({nullptr, 0});
+    }
+    return PFT_OK;
+}
+
+// Waves and groups of an op list given the input levels (shared by
+// pft_exec_plan and pft_exec_batch).  Returns the number of waves or an error.
+static int plan_ops(const pft_op* ops, uint32_t n_ops, const uint32_t* levels, uint32_t n_cts,
+                    std::vector<std::vector<ExecGroup>>& plan) {
+    std::vector<uint32_t> lvl(levels, levels + n_cts);
+    std::vector<uint32_t> wave(n_ops, 0), in_level(n_ops, 0);
+    std::vector<int64_t> last_write(n_cts, -1), last_read_wave(n_cts, 0);
+    uint32_t n_waves = 0;
+    for (uint32_t j = 0; j < n_ops; ++j) {
+        const pft_op& op = ops[j];
+        const bool two = op.kind == PFT_OP_ADD || op.kind == PFT_OP_MUL_RELIN;
+        const bool in_place = op.kind == PFT_OP_NTT || op.kind == PFT_OP_INTT;
+        if (op.kind < PFT_OP_NTT || op.kind > PFT_OP_ROTATE) return fail(PFT_EINVAL, "op %u: unknown kind %u", j, op.kind);
+        if (op.a >= n_cts || (two && op.b >= n_cts) || (!in_place && op.out >= n_cts))
+            return fail(PFT_EINVAL, "op %u: ciphertext index out of range", j);
+        const uint32_t out = in_place ? op.a : op.out;
+        if (two && lvl[op.a] != lvl[op.b]) return fail(PFT_ELEVEL, "op %u: operands at different levels", j);
+        if ((op.kind == PFT_OP_MUL_RELIN || op.kind == PFT_OP_ROTATE) && (out == op.a || (two && out == op.b)))
+            return fail(PFT_EINVAL, "op %u: output aliases an input", j);
+        if (op.kind == PFT_OP_RESCALE && lvl[op.a] < 2) return fail(PFT_ELEVEL, "op %u: rescale needs level >= 2", j);
+        in_level[j] = lvl[op.a];
+        // after every earlier writer of what j touches and every earlier
+        // reader of what j writes
+        uint32_t w = 0;
+        const uint32_t reads[2] = {op.a, two ? op.b : op.a};
+        for (uint32_t r : reads)
+            if (last_write[r] >= 0) w = std::max<uint32_t>(w, wave[last_write[r]] + 1);
+        if (last_write[out] >= 0) w = std::max<uint32_t>(w, wave[last_write[out]] + 1);
+        w = std::max<uint32_t>(w, (uint32_t)last_read_wave[out]);
+        wave[j] = w;
+        n_waves = std::max(n_waves, w + 1);
+        for (uint32_t r : reads) last_read_wave[r] = std::max<int64_t>(last_read_wave[r], w + 1);
+        last_write[out] = j;
+        lvl[out] = op.kind == PFT_OP_RESCALE ? lvl[op.a] - 1 : lvl[op.a];
+    }
+    plan.assign(n_waves, {});
+    for (uint32_t j = 0; j < n_ops; ++j) {
+        const pft_op& op = ops[j];
+        const uint32_t mode = op.kind == PFT_OP_RESCALE ? op.mode : 0;
+        const int32_t step = op.kind == PFT_OP_ROTATE ? op.step : 0;
+        auto& gs = plan[wave[j]];
+        auto it = std::find_if(gs.begin(), gs.end(), [&](const ExecGroup& g) {
+            return g.kind == op.kind && g.level == in_level[j] && g.mode == mode && g.step == step;
+        });
+        if (it == gs.end()) {
+            gs.push_back(ExecGroup{op.kind, in_level[j], mode, step, {}});
+            it = gs.end() - 1;
+        }
+        it->ops.push_back(j);
+    }
+    return (int)n_waves;
+}
+
+extern "C" int pft_exec_plan(const pft_op* ops, uint32_t n_ops, const uint32_t* levels, uint32_t n_cts,
+                             uint32_t* wave, uint32_t* group) {
+    if ((!ops && n_ops) || (!levels && n_cts)) return fail(PFT_EINVAL, "null argument");
+    std::vector<std::vector<ExecGroup>> plan;
+    const int nw = plan_ops(ops, n_ops, levels, n_cts, plan);
+    if (nw < 0) return nw;
+    for (uint32_t w = 0; w < plan.size(); ++w)
+        for (uint32_t g = 0; g < plan[w].size(); ++g)
+            for (uint32_t j : plan[w][g].ops) {
+                if (wave) wave[j] = w;
+                if (group) group[j] = g;
+            }
+    return nw;
+}
+
+extern "C" int pft_exec_batch(pft_ctx* c, pft_ct* cts, uint32_t n_cts, const pft_op* ops, uint32_t n_ops) {
+    if (!c || (!cts && n_cts) || (!ops && n_ops)) return fail(PFT_EINVAL, "null argument");
+    if (c->prof.mask) return fail(PFT_EINVAL, "disable kernel timing before pft_exec_batch");
+    std::vector<uint32_t> levels(n_cts);
+    for (uint32_t i = 0; i < n_cts; ++i) levels[i] = cts[i].level;
+    std::vector<std::vector<ExecGroup>> plan;
+    const int nw = plan_ops(ops, n_ops, levels.data(), n_cts, plan);
+    if (nw < 0) return nw;
+    const uint32_t n_waves = (uint32_t)nw;
+    size_t max_groups = 0;
+    for (auto& gs : plan) max_groups = std::max(max_groups, gs.size());
+    int r;
+    if ((r = side_branch(c, max_groups > 0 ? max_groups - 1 : 0))) return r;
+
+    const hipStream_t main = c->stream;
+    hipEvent_t fork = nullptr;
+    HIPCK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    r = PFT_OK;
+    for (uint32_t w = 0; w < n_waves && !r; ++w) {
+        const auto& gs = plan[w];
+        if (gs.size() > 1) {
+            if (hipEventRecord(fork, main) != hipSuccess) r = fail(PFT_EHIP, "hipEventRecord failed");
+            for (size_t k = 1; k < gs.size() && !r; ++k)
+                if (hipStreamWaitEvent(c->side[k - 1], fork, 0) != hipSuccess) r = fail(PFT_EHIP, "fork failed");
+        }
+        for (size_t k = 0; k < gs.size() && !r; ++k) {
+            if (k == 0) {
+                r = exec_group(c, cts, ops, gs[k]);
+                continue;
+            }
+            // run on side stream k-1 with its own workspace
+            uint64_t* const mws = c->ws;
+            const size_t mbytes = c->ws_bytes;
+            c->stream = c->prof.st = c->side[k - 1];
+            c->ws = c->side_ws[k - 1].first;
+            c->ws_bytes = c->side_ws[k - 1].second;
+            r = exec_group(c, cts, ops, gs[k]);
+            c->side_ws[k - 1] = {c->ws, c->ws_bytes};
+            c->stream = c->prof.st = main;
+            c->ws = mws;
+            c->ws_bytes = mbytes;
+            if (!r && hipEventRecord(c->side_ev[k - 1], c->side[k - 1]) != hipSuccess)
+                r = fail(PFT_EHIP, "hipEventRecord failed");
+        }
+        for (size_t k = 1; k < gs.size(); ++k)
+            if (hipStreamWaitEvent(main, c->side_ev[k - 1], 0) != hipSuccess && !r) r = fail(PFT_EHIP, "join failed");
+    }
+    (void)hipEventDestroy(fork);
+    return r;
 }
 
 // ---------------------------------------------------------------------------

@@ -385,6 +385,7 @@ void launch_pass(const PolyBatch& b, const DevTables& t, uint32_t log_n, uint32_
     const int kid = INV ? PK_NTT_INV : PK_NTT_FWD;
     const uint32_t first_pass = INV ? (s0 + LOG_M == log_n) : (s0 == 0);
     const bool col = s0 + LOG_M < log_n;
+    const bool staged = col || stage;
     if (g_prof) g_prof->begin(kid);
     if (col) {
         if constexpr (LOG_M <= 8) launch_k<LOG_M, INV, true, INV>(b, t, log_n, s0, first_pass, true, st);
@@ -397,7 +398,8 @@ void launch_pass(const PolyBatch& b, const DevTables& t, uint32_t log_n, uint32_
     if (g_prof) {
         const double elems = (double)b.n_polys * b.n_limbs * (double)(1u << log_n);
         // read + write every residue once; N/2 butterflies per stage
-        g_prof->end(kid, 16.0 * elems, 0.5 * elems * LOG_M);
+        const uint32_t variant = 1u + (LOG_M | (col ? 32u : 0u) | (final_pass ? 64u : 0u) | (staged ? 128u : 0u));
+        g_prof->end(kid, 16.0 * elems, 0.5 * elems * LOG_M, variant);
     }
 }
 

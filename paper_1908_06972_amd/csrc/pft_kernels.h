@@ -18,9 +18,11 @@ enum ProfKernel : int {
     PK_NTT_FWD = 0, PK_NTT_INV = 1, PK_MODUP = 2, PK_KEY_INNER = 3, PK_MODDOWN_CONV = 4,
     PK_MODDOWN_FINAL = 5, PK_TENSOR = 6, PK_AUTOMORPHISM = 7, PK_RESCALE = 8, PK_ELEMENTWISE = 9, PK_COUNT = 10
 };
+// variant: which instantiation of the family ran (0 for single-kernel
+// families; NTT passes: 1 + (radix | col << 5 | final << 6 | staged << 7)).
 struct ProfHook {
     virtual void begin(int kid) = 0;
-    virtual void end(int kid, double bytes, double ops) = 0;
+    virtual void end(int kid, double bytes, double ops, uint32_t variant = 0) = 0;
     virtual ~ProfHook() {}
 };
 

@@ -42,6 +42,14 @@ class CtDesc(ctypes.Structure):
 
 PtDesc = CtDesc  # same layout: pft_pt
 
+
+class OpDesc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_uint32), ("a", ctypes.c_uint32), ("b", ctypes.c_uint32), ("out", ctypes.c_uint32),
+                ("step", ctypes.c_int32), ("mode", ctypes.c_uint32)]
+
+
+PFT_OP_NTT, PFT_OP_INTT, PFT_OP_ADD, PFT_OP_MUL_RELIN, PFT_OP_RESCALE, PFT_OP_ROTATE = 1, 2, 3, 4, 5, 6
+
 # (name, argtypes, restype) of every exported symbol declared in include/pft.h
 SIGNATURES = [
     ("pft_params_create", [ctypes.POINTER(ParamSpec), ctypes.POINTER(_vp)], ctypes.c_int),
@@ -95,6 +103,9 @@ SIGNATURES = [
     ("pft_ntt_autotune", [_vp, ctypes.c_int], ctypes.c_int),
     ("pft_ntt_set_schedule", [_vp, ctypes.c_int, _u32p], ctypes.c_int),
     ("pft_ntt_get_schedule", [_vp, ctypes.c_int, ctypes.c_uint64, _u32p], ctypes.c_int),
+    ("pft_exec_batch", [_vp, ctypes.POINTER(CtDesc), ctypes.c_uint32, ctypes.POINTER(OpDesc), ctypes.c_uint32],
+     ctypes.c_int),
+    ("pft_exec_plan", [ctypes.POINTER(OpDesc), ctypes.c_uint32, _u32p, ctypes.c_uint32, _u32p, _u32p], ctypes.c_int),
     ("pft_ctx_reserve", [_vp, ctypes.c_uint64, ctypes.c_uint64], ctypes.c_int),
     ("pft_graph_begin", [_vp], ctypes.c_int),
     ("pft_graph_end", [_vp, ctypes.POINTER(_vp)], ctypes.c_int),
@@ -102,6 +113,8 @@ SIGNATURES = [
     ("pft_graph_destroy", [_vp], None),
     ("pft_prof_enable", [_vp, ctypes.c_uint32], ctypes.c_int),
     ("pft_prof_read", [_vp, ctypes.c_uint32, _dblp, _u64p, _dblp, _dblp], ctypes.c_int),
+    ("pft_prof_read_variants", [_vp, ctypes.c_uint32, ctypes.c_uint32, _u32p, _dblp, _u64p, _dblp, _dblp],
+     ctypes.c_int),
     ("pft_encode", [_vp, _dblp, _dblp, ctypes.c_uint32, ctypes.c_double, _i64p], ctypes.c_int),
     ("pft_decode", [_vp, _u64p, ctypes.c_uint32, ctypes.c_double, ctypes.c_uint32, _dblp, _dblp], ctypes.c_int),
 ]

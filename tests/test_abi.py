@@ -109,3 +109,48 @@ def test_ntt_candidate_schedules():
             assert flags in (0, 1)
             assert (radices, 1 - flags) in scheds
         assert scheds[0] == ({12: (12,), 13: (7, 6), 14: (7, 7), 15: (8, 7), 16: (8, 8)}[log_n], 0)
+
+
+def _plan(ops, levels):
+    n = len(ops)
+    O = (N.OpDesc * max(n, 1))()
+    for i, (kind, a, b, out, step, mode) in enumerate(ops):
+        O[i] = N.OpDesc(kind, a, b, out, step, mode)
+    L = (ctypes.c_uint32 * max(len(levels), 1))(*levels)
+    w = (ctypes.c_uint32 * max(n, 1))()
+    g = (ctypes.c_uint32 * max(n, 1))()
+    nw = N.load().pft_exec_plan(O, n, L, len(levels), w, g)
+    return nw, list(w)[:n], list(g)[:n]
+
+
+def test_exec_plan_waves_and_groups():
+    """Independent ops share wave 0; equal (kind, level, step) share a group;
+    read-after-write, write-after-read and write-after-write each start a later
+    wave; rescale lowers the simulated level of its output."""
+    MUL, RS, ROT, ADD, NTT = N.PFT_OP_MUL_RELIN, N.PFT_OP_RESCALE, N.PFT_OP_ROTATE, N.PFT_OP_ADD, N.PFT_OP_NTT
+    levels = [5, 5, 4, 4, 5, 5, 4, 4, 0, 0, 0, 0]
+    ops = [(MUL, 0, 1, 8, 0, 0),      # wave 0, level 5
+           (MUL, 2, 3, 9, 0, 0),      # wave 0, level 4 -> other group
+           (MUL, 4, 5, 10, 0, 0),     # wave 0, same group as op 0
+           (RS, 8, 0, 11, 0, 0),      # reads 8 (written by op 0) -> wave 1
+           (ROT, 11, 0, 0, 3, 0),     # writes 0, read by op 0 (WAR) and reads 11 (RAW) -> wave 2
+           (NTT, 6, 0, 0, 0, 0),      # independent, in place -> wave 0
+           (ADD, 6, 7, 9, 0, 0)]      # reads 6 (written by op 5), writes 9 (written by op 1) -> wave 1
+    nw, w, g = _plan(ops, levels)
+    assert nw == 3
+    assert w == [0, 0, 0, 1, 2, 0, 1]
+    assert g[0] == g[2] != g[1]
+    assert len({g[0], g[1], g[5]}) == 3
+    assert g[3] != g[6]
+
+
+def test_exec_plan_rejects_bad_lists():
+    MUL, RS, ROT = N.PFT_OP_MUL_RELIN, N.PFT_OP_RESCALE, N.PFT_OP_ROTATE
+    assert _plan([(MUL, 0, 1, 2, 0, 0)], [3, 4, 0])[0] == N.PFT_ELEVEL
+    assert _plan([(ROT, 0, 0, 0, 1, 0)], [3])[0] == N.PFT_EINVAL
+    assert _plan([(RS, 0, 0, 1, 0, 0)], [1, 0])[0] == N.PFT_ELEVEL
+    assert _plan([(99, 0, 0, 0, 0, 0)], [3])[0] == N.PFT_EINVAL
+    assert _plan([(MUL, 0, 1, 5, 0, 0)], [3, 3])[0] == N.PFT_EINVAL
+    # a rescale chain: the simulated level drops, so the second rescale of a
+    # level-2 input fails
+    assert _plan([(RS, 0, 0, 1, 0, 0), (RS, 1, 0, 2, 0, 0)], [2, 0, 0])[0] == N.PFT_ELEVEL

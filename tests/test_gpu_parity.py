@@ -16,13 +16,6 @@ from tests.gpu_env import World
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module")
-def torch_cuda():
-    import torch
-    assert torch.cuda.is_available(), "GPU tests need a GPU"
-    return torch
-
-
 # ---------------------------------------------------------------------------
 # the transform (row a1/a2): forward/inverse NTT against the oracle definition
 # ---------------------------------------------------------------------------
