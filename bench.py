@@ -134,12 +134,17 @@ def _find(dirpath, suffix):
 
 
 def _step_dispatches(rows, key_id, key_start):
-    """Dispatches from the first HMUL tensor kernel on: the job steps (every
-    step of a run launches the same kernels with the same shapes), which
-    excludes key generation and encryption."""
+    """Dispatches of the job steps after the first one: from the first HMUL
+    tensor kernel of the second step on (a step launches CHAIN_DEPTH tensor
+    kernels).  This excludes key generation, encryption and the first step,
+    during which the NTT autotuner times its candidates; every later step
+    launches the same kernels with the same shapes."""
     rows = sorted(rows, key=lambda r: int(r[key_id]))
-    first = next((i for i, r in enumerate(rows) if "k_tensor_b" in r["Kernel_Name"]), None)
-    return rows[first:] if first is not None else []
+    tensors = sorted({int(r[key_id]) for r in rows if "k_tensor_b" in r["Kernel_Name"]})
+    if len(tensors) <= CHAIN_DEPTH:
+        return []
+    first = tensors[CHAIN_DEPTH]
+    return [r for r in rows if int(r[key_id]) >= first]
 
 
 def summarize(trace_dir, fetch_dir, write_dir, kernel, kid, commands):
@@ -162,13 +167,18 @@ def summarize(trace_dir, fetch_dir, write_dir, kernel, kid, commands):
     for c in commands:
         out.append("    " + c)
     out.append("")
-    out.append("Kernel durations over the dispatches of the job steps (from the first HMUL tensor launch on; "
-               "every step launches the same kernels with the same shapes):")
+    out.append("Kernel durations over the dispatches of the job steps after the first (the first settles the NTT "
+               "autotuner; every later step launches the same kernels with the same shapes):")
     out.append("")
     out.append("| kernel | calls | total ms | avg us | share |")
     out.append("|---|---|---|---|---|")
     for name, (c, t) in sorted(per.items(), key=lambda kv: -kv[1][1])[:14]:
         out.append("| %s | %d | %.2f | %.1f | %.1f%% |" % (name, c, t / 1e3, t / c, 100 * t / total))
+    if kernel == "auto":
+        kernel = max(per, key=lambda k: per[k][1])
+        out[0] = "# %s: job steps of bench.py (large ring, N=2^16, L=24, batch 16)" % kernel
+        if kernel.startswith("k_ntt_pass<"):
+            kid = 1 if kernel.split(",")[1].strip() == "true" else 0
     short = kernel.replace("void ", "")
     tgt = [v for k, v in per.items() if k == short]
     avg_us = tgt[0][1] / tgt[0][0] if tgt else None
@@ -237,10 +247,12 @@ def parse():
                     help="requests of the serving measurement (0 skips it)")
     ap.add_argument("--summarize", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="write the markdown summary of three rocprofv3 runs of the timed region and exit")
-    ap.add_argument("--kernel", default="k_ntt_pass<8, false, true, false, true>",
-                    help="kernel the --summarize counters are collected for (the roofline kernel bench prints)")
+    ap.add_argument("--kernel", default="auto",
+                    help="kernel the --summarize counters are collected for; auto = the longest in the trace")
     ap.add_argument("--family", type=int, default=0)
     ap.add_argument("--commands", nargs="*", default=[])
+    ap.add_argument("--tuning-in", help="JSON table of NTT schedules (from --tuning-out) to use instead of tuning")
+    ap.add_argument("--tuning-out", help="write the NTT schedules the run used (JSON)")
     return ap.parse_args()
 
 
@@ -386,6 +398,9 @@ def serving_bench(n_requests, rate=200.0, level=4, pool=16, budget_gib=16):
 
 
 def timed(fn, reps, sync):
+    """Mean seconds per call of fn over reps calls, after one untimed call
+    (which also lets the NTT autotuner settle the call's batch classes)."""
+    fn()
     sync()
     t = time.perf_counter()
     for _ in range(reps):
@@ -458,12 +473,25 @@ def main():
 
     lp, ctx, kd, cts = setup(args.batch)
     sync = torch.cuda.synchronize
+    if args.tuning_in:
+        with open(args.tuning_in) as fh:
+            ctx.ntt_tuning_import([(e[0], e[1], (tuple(e[2]), e[3])) for e in json.load(fh)])
+        log("NTT schedules imported from %s" % args.tuning_in)
+
+    def save_tuning():
+        table = [[inv, cls, list(sched[0]), sched[1]] for inv, cls, sched in ctx.ntt_tuning_export()]
+        if args.tuning_out:
+            with open(args.tuning_out, "w") as fh:
+                json.dump(table, fh)
+        return table
 
     if args.profile_steps:
-        for i in range(args.profile_steps):
+        # one settling step (autotuner), then the profiled steps
+        for i in range(1 + args.profile_steps):
             job_step(ctx, cts)
             sync()
             log("profile step %d done" % i)
+        save_tuning()
         return
 
     # rank kernel families over one untimed step
@@ -580,6 +608,7 @@ def main():
         "alu": alu,
     }
 
+    tuning = save_tuning()
     serving = None
     if args.serve_requests > 0:
         serving = serving_bench(args.serve_requests)
@@ -603,7 +632,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "large ring: N=2^16, L=24 (+K=6, dnum=4), scale 2^50, batch %d; depth-8 "
                                "HMult+relin+rescale chain then rotate-and-sum over 2^15 slots" % args.batch,
-                   "global_batch": args.batch, "log_n": 16, "levels": lp.L, "special_primes": lp.K, "dnum": lp.dnum},
+                   "global_batch": args.batch, "log_n": 16, "levels": lp.L, "special_primes": lp.K, "dnum": lp.dnum,
+                   "ntt_schedules": [{"inverse": bool(i), "class": c, "radices": r, "direct_rows": bool(d)}
+                                     for i, c, r, d in tuning]},
         "breakdown": breakdown,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -235,6 +235,12 @@ int pft_ntt_candidates(const pft_params* p, uint32_t* scheds, uint32_t max_count
 int pft_ntt_autotune(pft_ctx* ctx, int enable);
 int pft_ntt_set_schedule(pft_ctx* ctx, int inverse, const uint32_t* sched);
 int pft_ntt_get_schedule(pft_ctx* ctx, int inverse, uint64_t n_limbs, uint32_t* sched);
+/* The tuned table as entries of six words (inverse 0/1, batch-size class
+ * 0..10, the four schedule words): export writes up to max_count entries and
+ * returns how many exist; import validates every entry (PFT_EINVAL, nothing
+ * changed) and then sets them, so a later run can reuse earlier choices. */
+int pft_ntt_tuning_export(pft_ctx* ctx, uint32_t* entries, uint32_t max_count);
+int pft_ntt_tuning_import(pft_ctx* ctx, const uint32_t* entries, uint32_t count);
 
 /* ---- op-list executor ---------------------------------------------------
  * pft_exec_batch runs n_ops operations on the ciphertexts cts[0..n_cts) with

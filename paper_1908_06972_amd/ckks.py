@@ -359,6 +359,24 @@ class Context:
         arr = None if sched is None else self._sched_to(sched)
         N.check(self.lib.pft_ntt_set_schedule(self.handle, int(bool(inverse)), arr))
 
+    def ntt_tuning_export(self):
+        """Tuned choices: list of (inverse, class, (radices, direct))."""
+        n = self.lib.pft_ntt_tuning_export(self.handle, None, 0)
+        if n < 0:
+            N.check(n)
+        buf = (ctypes.c_uint32 * (6 * max(n, 1)))()
+        self.lib.pft_ntt_tuning_export(self.handle, buf, n)
+        return [(bool(buf[6 * i]), int(buf[6 * i + 1]), self._sched_from(buf[6 * i + 2:6 * i + 6])) for i in range(n)]
+
+    def ntt_tuning_import(self, table):
+        buf = (ctypes.c_uint32 * (6 * max(len(table), 1)))()
+        for i, (inv, cls, sched) in enumerate(table):
+            buf[6 * i] = int(bool(inv))
+            buf[6 * i + 1] = int(cls)
+            for k, w in enumerate(self._sched_to(sched)):
+                buf[6 * i + 2 + k] = w
+        N.check(self.lib.pft_ntt_tuning_import(self.handle, buf, len(table)))
+
     def ntt_get_schedule(self, inverse: bool, n_limbs: int):
         arr = (ctypes.c_uint32 * 4)()
         N.check(self.lib.pft_ntt_get_schedule(self.handle, int(bool(inverse)), n_limbs, arr))

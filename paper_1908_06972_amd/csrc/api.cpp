@@ -511,7 +511,8 @@ static NttSchedule ntt_default(const pft_params* P) {
 
 // Times every candidate on zeroed scratch of min(limbs, 2^class) limbs that
 // cycle through all L + K moduli (fp64 and integer limbs in the chain's
-// proportion); keeps the fastest mean of three runs.
+// proportion): the median of five runs each.  The earliest candidate within
+// 2% of the fastest wins, so near-ties resolve the same way run to run.
 static NttSchedule ntt_tune(pft_ctx* c, bool inverse, uint32_t cls) {
     const pft_params* P = c->P;
     NttSchedule cand[16];
@@ -538,8 +539,7 @@ static NttSchedule ntt_tune(pft_ctx* c, bool inverse, uint32_t cls) {
         hipFree(buf);
         return cand[0];
     }
-    NttSchedule best = cand[0];
-    float best_ms = 1e30f;
+    std::vector<float> med(nc, 1e30f);
     bool ok = hipMemsetAsync(buf, 0, bytes, c->stream) == hipSuccess;
     PolyBatch b{};
     for (uint32_t i = 0; i < np; ++i) {
@@ -554,14 +554,26 @@ static NttSchedule ntt_tune(pft_ctx* c, bool inverse, uint32_t cls) {
     b.off1 = P->L;
     for (int k = 0; ok && k < nc; ++k) {
         launch_ntt(b, c->tabs, P->log_n, inverse, cand[k], c->stream, nullptr);
-        ok = hipEventRecord(e0, c->stream) == hipSuccess;
-        for (int r = 0; r < 3; ++r) launch_ntt(b, c->tabs, P->log_n, inverse, cand[k], c->stream, nullptr);
-        ok = ok && hipEventRecord(e1, c->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
-        float ms = 0;
-        if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < best_ms) {
-            best_ms = ms;
-            best = cand[k];
+        float t[5];
+        for (int r = 0; ok && r < 5; ++r) {
+            ok = hipEventRecord(e0, c->stream) == hipSuccess;
+            launch_ntt(b, c->tabs, P->log_n, inverse, cand[k], c->stream, nullptr);
+            ok = ok && hipEventRecord(e1, c->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+                 hipEventElapsedTime(&t[r], e0, e1) == hipSuccess;
         }
+        if (ok) {
+            std::sort(t, t + 5);
+            med[k] = t[2];
+        }
+    }
+    NttSchedule best = cand[0];
+    if (ok) {
+        const float fastest = *std::min_element(med.begin(), med.end());
+        for (int k = 0; k < nc; ++k)
+            if (med[k] <= 1.02f * fastest) {
+                best = cand[k];
+                break;
+            }
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
@@ -1597,6 +1609,36 @@ extern "C" int pft_ntt_set_schedule(pft_ctx* c, int inverse, const uint32_t* sch
         if (!ntt_schedule_valid(c->P->log_n, s)) return fail(PFT_EINVAL, "not a candidate schedule for this ring");
     }
     c->ntt_pinned[inverse ? 1 : 0] = s;
+    return PFT_OK;
+}
+
+extern "C" int pft_ntt_tuning_export(pft_ctx* c, uint32_t* entries, uint32_t max_count) {
+    if (!c) return fail(PFT_EINVAL, "null context");
+    uint32_t i = 0;
+    for (const auto& kv : c->ntt_tuned) {
+        if (entries && i < max_count) {
+            entries[6 * i] = kv.first >= 64 ? 1u : 0u;
+            entries[6 * i + 1] = kv.first & 63u;
+            sched_words(kv.second, entries + 6 * i + 2);
+        }
+        ++i;
+    }
+    return (int)i;
+}
+
+extern "C" int pft_ntt_tuning_import(pft_ctx* c, const uint32_t* entries, uint32_t count) {
+    if (!c || (!entries && count)) return fail(PFT_EINVAL, "null argument");
+    std::map<uint32_t, NttSchedule> add;
+    for (uint32_t i = 0; i < count; ++i) {
+        const uint32_t* e = entries + 6 * i;
+        if (e[0] > 1 || e[1] > 10) return fail(PFT_EINVAL, "entry %u: bad direction or class", i);
+        NttSchedule s{};
+        for (uint32_t k = 0; k < 3 && e[2 + k]; ++k) s.radix[s.n_passes++] = (uint8_t)std::min<uint32_t>(e[2 + k], 255u);
+        s.flags = e[5];
+        if (!ntt_schedule_valid(c->P->log_n, s)) return fail(PFT_EINVAL, "entry %u: not a candidate schedule", i);
+        add[(e[0] ? 64u : 0u) + e[1]] = s;
+    }
+    for (const auto& kv : add) c->ntt_tuned[kv.first] = kv.second;
     return PFT_OK;
 }
 

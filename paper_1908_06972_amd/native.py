@@ -103,6 +103,8 @@ SIGNATURES = [
     ("pft_ntt_autotune", [_vp, ctypes.c_int], ctypes.c_int),
     ("pft_ntt_set_schedule", [_vp, ctypes.c_int, _u32p], ctypes.c_int),
     ("pft_ntt_get_schedule", [_vp, ctypes.c_int, ctypes.c_uint64, _u32p], ctypes.c_int),
+    ("pft_ntt_tuning_export", [_vp, _u32p, ctypes.c_uint32], ctypes.c_int),
+    ("pft_ntt_tuning_import", [_vp, _u32p, ctypes.c_uint32], ctypes.c_int),
     ("pft_exec_batch", [_vp, ctypes.POINTER(CtDesc), ctypes.c_uint32, ctypes.POINTER(OpDesc), ctypes.c_uint32],
      ctypes.c_int),
     ("pft_exec_plan", [ctypes.POINTER(OpDesc), ctypes.c_uint32, _u32p, ctypes.c_uint32, _u32p, _u32p], ctypes.c_int),
