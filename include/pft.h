@@ -159,6 +159,15 @@ int pft_mod_drop(pft_ctx* ctx, const pft_ct* in, uint32_t level, pft_ct* out);
  * result holds slot j+step of the input. */
 int pft_rotate(pft_ctx* ctx, const pft_ct* in, int32_t step, pft_ct* out);
 int pft_rotate_batch(pft_ctx* ctx, uint32_t n, const pft_ct* in, int32_t step, pft_ct* out);
+/* ROTATE by any step from power-of-two keys (the paper's cost model for
+ * ROTATE, Sec. 6.5: one automorphism and key switch per set bit of the step,
+ * so ROTATE_LHW is one key switch and ROTATE_HHW up to log2(N/2)): with
+ * r = step mod N/2, for every set bit k of r in ascending order the
+ * ciphertext is rotated by 2^k with the key for 2^k.  Same slots as a direct
+ * rotation by step (the residues differ: different key switches).  in and out
+ * may alias.  PFT_ENOKEY names the first missing power-of-two key. */
+int pft_rotate_pow2(pft_ctx* ctx, const pft_ct* in, int32_t step, pft_ct* out);
+int pft_rotate_pow2_batch(pft_ctx* ctx, uint32_t n, const pft_ct* in, int32_t step, pft_ct* out);
 /* TotalSum (Sec. 4.1, Alg. 2): ct += ROTATE(ct, 2^i) for i < log2(n_slots);
  * needs the rotation keys 1, 2, 4, ..., n_slots/2.  out may alias in. */
 int pft_total_sum(pft_ctx* ctx, const pft_ct* in, uint32_t n_slots, pft_ct* out);
@@ -241,6 +250,16 @@ int pft_ntt_get_schedule(pft_ctx* ctx, int inverse, uint64_t n_limbs, uint32_t* 
  * changed) and then sets them, so a later run can reuse earlier choices. */
 int pft_ntt_tuning_export(pft_ctx* ctx, uint32_t* entries, uint32_t max_count);
 int pft_ntt_tuning_import(pft_ctx* ctx, const uint32_t* entries, uint32_t count);
+
+/* ---- base conversion on the matrix cores ---------------------------------
+ * The ModUp and ModDown base conversions (sums of alpha or K products of
+ * residues below 2^60 by per-prime constants) run by default on MFMA: both
+ * operands are split into signed base-256 digits, the int8 x int8 products
+ * are summed exactly in int32 by v_mfma_i32_32x32x16_i8, and each target's
+ * 8 digit sums are folded back into a residue on the VALU.  mode 0 selects the
+ * 128-bit VALU multiply-accumulate kernels instead, 1 the matrix cores; the
+ * results are identical.  PFT_EINVAL for any other mode. */
+int pft_bconv_mode(pft_ctx* ctx, int mode);
 
 /* ---- op-list executor ---------------------------------------------------
  * pft_exec_batch runs n_ops operations on the ciphertexts cts[0..n_cts) with

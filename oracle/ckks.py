@@ -526,6 +526,21 @@ def rotate(params, x, step, key):
     return Ciphertext(add(c0, k0, mods), k1, x.scale)
 
 
+def rotate_pow2(params, x, step, rot_keys):
+    """ROTATE by `step` from power-of-two keys, the cost model of the paper's
+    ROTATE (Sec. 6.5: one automorphism and key switch per set bit of the step):
+    with r = step mod N/2, rotate by 2^k for every set bit k of r in ascending
+    order, each with rot_keys[2^k]."""
+    half = params.n // 2
+    r = step % half
+    k = 0
+    while (1 << k) < half:
+        if (r >> k) & 1:
+            x = rotate(params, x, 1 << k, rot_keys[1 << k])
+        k += 1
+    return x
+
+
 def total_sum(params, x, n_slots, rot_keys):
     """Alg. 2 (TotalSum): ct <- ct + ROTATE(ct, 2^i) for i = 0..log2(t)-1."""
     for i in range(int(math.log2(n_slots))):

@@ -274,6 +274,19 @@ class Context:
             c.sync_from(C[i])
         return cts
 
+    def rotate_pow2(self, a, step, out=None):
+        """Rotation by step from the power-of-two keys of its binary expansion."""
+        out = out or self.empty_ct(a.level)
+        da, do = a.desc(), out.desc()
+        N.check(self.lib.pft_rotate_pow2(self.handle, ctypes.byref(da), int(step), ctypes.byref(do)))
+        return out.sync_from(do)
+
+    def rotate_pow2_batch(self, a, step, out=None):
+        out = out or [self.empty_ct(x.level) for x in a]
+        A, O = self._arr(a), self._arr(out)
+        N.check(self.lib.pft_rotate_pow2_batch(self.handle, len(a), A, int(step), O))
+        return [o.sync_from(O[i]) for i, o in enumerate(out)]
+
     def rotate_batch(self, a, step, out=None):
         out = out or [self.empty_ct(x.level) for x in a]
         A, O = self._arr(a), self._arr(out)
@@ -350,6 +363,10 @@ class Context:
         buf = (ctypes.c_uint32 * (4 * n))()
         self.lib.pft_ntt_candidates(self.params.handle, buf, n)
         return [self._sched_from(buf[4 * i:4 * i + 4]) for i in range(n)]
+
+    def bconv_mode(self, mfma: bool):
+        """Base conversions on the matrix cores (True, the default) or the VALU."""
+        N.check(self.lib.pft_bconv_mode(self.handle, 1 if mfma else 0))
 
     def ntt_autotune(self, enable: bool):
         N.check(self.lib.pft_ntt_autotune(self.handle, int(bool(enable))))

@@ -217,6 +217,7 @@ struct pft_ctx {
     std::vector<void*> retired;
     // NTT pass schedules: pinned per direction, else tuned per (direction,
     // batch-size class) on first use when ntt_tune is set
+    bool bconv_mfma = true;  // base conversions on the matrix cores
     bool ntt_tune = true;
     NttSchedule ntt_pinned[2] = {};
     std::map<uint32_t, NttSchedule> ntt_tuned;
@@ -393,13 +394,88 @@ static int build_tables(pft_ctx* c) {
         for (uint32_t k = 0; k + 1 < lvl; ++k)
             rq[(size_t)(lvl - 1) * L + k] = pair(invmod(P->q[lvl - 1] % P->q[k], P->q[k]), P->q[k]);
 
+    // ---- MFMA base conversion operands (v_mfma_i32_32x32x16_i8).
+    // The contraction y_t = sum_i x_i h_{i,t} mod m_t is evaluated with both
+    // operands in signed base-256 digits: x_i = sum_a x_{i,a} 256^a and
+    // V_{(i,a),t} = 256^a h_{i,t} mod m_t = sum_b v_{(i,a),t,b} 256^b, so
+    // y_t = sum_b 256^b Z_{t,b} mod m_t with Z_{t,b} = sum_{i,a} x_{i,a}
+    // v_{(i,a),t,b}: exact int8 x int8 products summed in int32 (|Z| <=
+    // 12 * 8 * 128^2 < 2^21).  A 32 x 32 output tile holds 4 targets x 8 digit
+    // rows; row r is target (r/8)%2 + 2 ((r%8)/4), digit 4 (r/16) + r%4, so
+    // each lane receives all 8 digits of two targets.  Lane l of the A
+    // operand holds row l%32 and k = 8 (l/32) .. +7, k = 8 i_local + a.
+    auto digits = [](uint64_t v) { return v + 0x8080808080808080ull; };  // balanced digits, biased by 128
+    auto digit = [&](uint64_t v, uint32_t b) { return (int)((digits(v) >> (8 * b)) & 255u) - 128; };
+    auto row_t = [](uint32_t r) { return ((r / 8) % 2) + 2 * ((r % 8) / 4); };
+    auto row_b = [](uint32_t r) { return 4 * (r / 16) + (r % 4); };
+    auto pack_lane = [&](uint32_t lane, auto&& vmat /* (i_local, t_local, a) -> V or ~0 */) {
+        uint64_t w = 0;
+        const uint32_t r = lane % 32, half = lane / 32;
+        for (uint32_t a = 0; a < 8; ++a) {
+            const uint64_t v = vmat(half, row_t(r), a);
+            const int d = v == ~0ull ? 0 : digit(v, row_b(r));
+            w |= (uint64_t)(uint8_t)(int8_t)d << (8 * a);
+        }
+        return w;
+    };
+    const uint32_t up_rt = (L + K + 3) / 4, up_kb = (A + 1) / 2;
+    const uint32_t dn_rt = (L + 3) / 4, dn_kb = (K + 1) / 2;
+    std::vector<uint64_t> upa((size_t)L * dnum * up_rt * up_kb * 64, 0), dna((size_t)dn_rt * dn_kb * 64, 0);
+    std::vector<uint64_t> pw8(8);
+    for (uint32_t lvl = 1; lvl <= L; ++lvl) {
+        const uint32_t beta = (lvl + A - 1) / A;
+        for (uint32_t j = 0; j < beta; ++j) {
+            const uint32_t i0 = j * A, na = std::min(i0 + A, lvl) - i0, T = lvl + K - na;
+            for (uint32_t rt = 0; rt < (T + 3) / 4; ++rt)
+                for (uint32_t kb = 0; kb < (na + 1) / 2; ++kb)
+                    for (uint32_t lane = 0; lane < 64; ++lane) {
+                        auto vm = [&](uint32_t half, uint32_t tl, uint32_t a) -> uint64_t {
+                            const uint32_t ii = 2 * kb + half, tt = 4 * rt + tl;
+                            if (ii >= na || tt >= T) return ~0ull;
+                            const uint32_t t = tt < i0 ? tt : tt + na;
+                            const uint64_t m = t < lvl ? P->q[t] : P->p[t - lvl];
+                            uint64_t h = 1;  // (D_j / q_{i0+ii}) mod m
+                            for (uint32_t o = i0; o < i0 + na; ++o)
+                                if (o != i0 + ii) h = mulmod(h, P->q[o] % m, m);
+                            return mulmod(h, powmod(2 % m, 8 * a, m), m);
+                        };
+                        upa[((((size_t)(lvl - 1) * dnum + j) * up_rt + rt) * up_kb + kb) * 64 + lane] =
+                            pack_lane(lane, vm);
+                    }
+        }
+    }
+    for (uint32_t rt = 0; rt < dn_rt; ++rt)
+        for (uint32_t kb = 0; kb < dn_kb; ++kb)
+            for (uint32_t lane = 0; lane < 64; ++lane) {
+                auto vm = [&](uint32_t half, uint32_t tl, uint32_t a) -> uint64_t {
+                    const uint32_t k = 2 * kb + half, i = 4 * rt + tl;
+                    if (k >= K || i >= L) return ~0ull;
+                    const uint64_t m = P->q[i];
+                    uint64_t h = 1;  // (P / p_k) mod q_i
+                    for (uint32_t o = 0; o < K; ++o)
+                        if (o != k) h = mulmod(h, P->p[o] % m, m);
+                    return mulmod(h, powmod(2 % m, 8 * a, m), m);
+                };
+                dna[((size_t)rt * dn_kb + kb) * 64 + lane] = pack_lane(lane, vm);
+            }
+    std::vector<BconvRed> red(L + K);
+    for (uint32_t mi = 0; mi < L + K; ++mi) {
+        const uint64_t m = P->mods[mi];
+        red[mi].c32 = pair(powmod(2 % m, 32, m), m);
+        red[mi].one_p = shoup_companion(1 % m, m);
+        red[mi].cc = (powmod(2 % m, 45, m) + powmod(2 % m, 77, m)) % m;
+    }
+
     TwPair *d_hatinv, *d_phatinv, *d_pinv;
-    uint64_t *d_cmat, *d_downc;
+    uint64_t *d_cmat, *d_downc, *d_upa, *d_dna;
+    BconvRed* d_red;
+    if ((r = upload(c, &d_upa, upa)) || (r = upload(c, &d_dna, dna)) || (r = upload(c, &d_red, red))) return r;
     if ((r = upload(c, &d_hatinv, hatinv)) || (r = upload(c, &d_cmat, cmat)) || (r = upload(c, &d_phatinv, phatinv)) ||
         (r = upload(c, &d_downc, downc)) || (r = upload(c, &d_pinv, pinv)) || (r = upload(c, &c->rescale_qinv, rq)) ||
         (r = upload(c, &c->gadget, gadget)) || (r = upload(c, &c->to_mont, tomont)))
         return r;
-    c->kc = KsConsts{d_hatinv, d_cmat, d_phatinv, d_downc, d_pinv, L, K, dnum, A};
+    c->kc = KsConsts{d_hatinv, d_cmat, d_phatinv, d_downc, d_pinv, d_upa, d_dna, d_red,
+                     up_rt,    up_kb,  dn_rt,       dn_kb,   L,      K,     dnum,  A};
     return PFT_OK;
 }
 
@@ -1031,7 +1107,7 @@ static void key_switch_b(pft_ctx* c, uint32_t n, WsRef ws, const KsLayout& K, ui
             macs += (double)(rows - na) * na + na;
         }
         timed(c, PK_MODUP, 8.0 * N * (rd + wr) * n, N * macs * n,
-              [&] { launch_modup_b(n, ws, K.off_dcoef, K.off_ext, level, c->kc, c->tabs, lg, c->stream); });
+              [&] { launch_modup_b(n, ws, K.off_dcoef, K.off_ext, level, c->kc, c->tabs, lg, c->bconv_mfma, c->stream); });
     }
     // ModUp transforms: all digits of all items, full digits and the ragged
     // last digit in separate launches (different limb counts)
@@ -1061,7 +1137,9 @@ static void key_switch_b(pft_ctx* c, uint32_t n, WsRef ws, const KsLayout& K, ui
         ntt_jobs(c, jobs, P->K, level, true);
     }
     timed(c, PK_MODDOWN_CONV, 8.0 * N * (2.0 * P->K + 2.0 * level) * n, 2.0 * N * P->K * level * n,
-          [&] { launch_moddown_conv_b(n, ws, K.off_acc, K.off_conv, level, c->kc, c->tabs, lg, c->stream); });
+          [&] {
+              launch_moddown_conv_b(n, ws, K.off_acc, K.off_conv, level, c->kc, c->tabs, lg, c->bconv_mfma, c->stream);
+          });
     {
         std::vector<NttJob> jobs;
         for (uint32_t z = 0; z < n; ++z)
@@ -1234,6 +1312,64 @@ extern "C" int pft_rotate_batch(pft_ctx* c, uint32_t n, const pft_ct* in, int32_
 
 extern "C" int pft_total_sum(pft_ctx* c, const pft_ct* in, uint32_t n_slots, pft_ct* out) {
     return pft_total_sum_batch(c, 1, in, n_slots, out);
+}
+
+// Rotation by `step` built from power-of-two rotations (the cost model of the
+// paper's ROTATE: one automorphism and key switch per set bit of the step):
+// r = step mod N/2, then for every set bit k of r, ascending, ct <- ROTATE(ct,
+// 2^k) with the key for 2^k.  Two ciphertext regions of the workspace
+// alternate as source and destination.
+extern "C" int pft_rotate_pow2_batch(pft_ctx* c, uint32_t n, const pft_ct* in, int32_t step, pft_ct* out) {
+    if (!c || !in || !out) return fail(PFT_EINVAL, "null argument");
+    int r;
+    for (uint32_t i = 0; i < n; ++i) {
+        if ((r = check_ct(c, &in[i]))) return r;
+        if (!out[i].data) return fail(PFT_EINVAL, "null output");
+    }
+    const pft_params* P = c->P;
+    const uint32_t half = P->n / 2;
+    const uint32_t rr0 = (uint32_t)(((int64_t)step % (int64_t)half + half) % half);
+    for (uint32_t k = 0; (1u << k) < half; ++k)
+        if (((rr0 >> k) & 1u) && !find_rot(c, (int32_t)(1u << k)))
+            return fail(PFT_ENOKEY, "no rotation key for step %u", 1u << k);
+    const uint32_t lg = P->log_n;
+    return for_level_groups(n, in, [&](const std::vector<uint32_t>& g) -> int {
+        const uint32_t l = in[g[0]].level, cnt = (uint32_t)g.size();
+        const uint64_t nl = (uint64_t)l * P->n;
+        const uint64_t offs[2] = {0, 2 * nl};
+        const KsLayout K = ks_layout(P, l, 4 * nl);
+        int e;
+        if ((e = ensure_ws(c, (size_t)cnt * K.end * 8))) return e;
+        const WsRef ws{c->ws, K.end};
+        ItemPtrs I{}, O{};
+        for (uint32_t z = 0; z < cnt; ++z) {
+            I.p[z] = in[g[z]].data;
+            O.p[z] = out[g[z]].data;
+        }
+        launch_copy_rows_b(cnt, I, 0, ws_items(ws, cnt), offs[0], 2 * l, lg, c->stream);
+        uint32_t cur = 0;
+        for (uint32_t k = 0; (1u << k) < half; ++k) {
+            if (!((rr0 >> k) & 1u)) continue;
+            const uint64_t src = offs[cur], dst = offs[1 - cur];
+            const uint64_t kappa = galois_element((int32_t)(1u << k), P->n);
+            timed(c, PK_AUTOMORPHISM, 8.0 * 4 * nl * cnt, 0, [&] {
+                launch_automorphism_b(cnt, ws_items(ws, cnt, src), 2 * l, ws, dst, kappa, lg, c->stream);
+            });
+            key_switch_b(c, cnt, ws, K, dst + nl, *find_rot(c, (int32_t)(1u << k)), dst, PFT_NO_OFFSET,
+                         ws_items(ws, cnt, dst));
+            cur = 1 - cur;
+        }
+        launch_copy_rows_b(cnt, ws_items(ws, cnt, offs[cur]), 0, O, 0, 2 * l, lg, c->stream);
+        for (uint32_t z = 0; z < cnt; ++z) {
+            out[g[z]].level = l;
+            out[g[z]].scale = in[g[z]].scale;
+        }
+        return PFT_OK;
+    });
+}
+
+extern "C" int pft_rotate_pow2(pft_ctx* c, const pft_ct* in, int32_t step, pft_ct* out) {
+    return pft_rotate_pow2_batch(c, 1, in, step, out);
 }
 
 extern "C" int pft_total_sum_batch(pft_ctx* c, uint32_t n, const pft_ct* in, uint32_t n_slots, pft_ct* out) {
@@ -1588,6 +1724,13 @@ extern "C" int pft_ntt_candidates(const pft_params* p, uint32_t* scheds, uint32_
     if (scheds)
         for (uint32_t i = 0; i < std::min<uint32_t>((uint32_t)n, max_count); ++i) sched_words(cand[i], scheds + 4 * i);
     return n;
+}
+
+extern "C" int pft_bconv_mode(pft_ctx* c, int mode) {
+    if (!c) return fail(PFT_EINVAL, "null context");
+    if (mode != 0 && mode != 1) return fail(PFT_EINVAL, "mode must be 0 (VALU) or 1 (MFMA)");
+    c->bconv_mfma = mode == 1;
+    return PFT_OK;
 }
 
 extern "C" int pft_ntt_autotune(pft_ctx* c, int enable) {

@@ -150,6 +150,137 @@ __global__ __launch_bounds__(TB) void k_modup_b(WsRef ws, uint64_t off_d, uint64
     }
 }
 
+// ---- base conversion on the matrix cores -------------------------------
+// The contraction y_t = sum_i x_i h_{i,t} mod m_t in signed base-256 digits
+// (operand tables and the exactness bound are built on the host):
+// Z_{t,b} = sum_{i,a} x_{i,a} v_{(i,a),t,b} by v_mfma_i32_32x32x16_i8 with the
+// constant digits as A (32 rows = 4 targets x 8 digits b) and the input
+// digits as B (32 columns = 32 coefficients, k = 8 i_local + a), then
+// y_t = sum_b 256^b Z_{t,b} mod m_t on the VALU.
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+// balanced base-256 digits of v < 2^60 as packed int8: v + 0x80..80 carries
+// exactly as the balanced digits do, and each biased byte minus 128 is the
+// digit (the same bits as the byte XOR 0x80)
+__device__ __forceinline__ long split_digits(uint64_t v) {
+    return (long)((v + 0x8080808080808080ull) ^ 0x8080808080808080ull);
+}
+
+// sum_b 256^b Z_b mod m for the 8 digit sums of one target (|Z_b| < 2^21)
+__device__ __forceinline__ uint64_t fold_digits(const int (&z)[8], const BconvRed& rc, uint64_t m, uint32_t bits) {
+    int64_t lo = 0, hi = 0;
+#pragma unroll
+    for (int b = 3; b >= 0; --b) {
+        lo = lo * 256 + z[b];
+        hi = hi * 256 + z[4 + b];
+    }
+    uint64_t l = (uint64_t)(lo + (1ll << 45));  // in [0, 2^46)
+    const uint64_t h = (uint64_t)(hi + (1ll << 45));
+    if (bits <= 46) l = shoup(l, 1, rc.one_p, m);
+    uint64_t y = l + shoup(h, rc.c32.w, rc.c32.wp, m);  // < 2m
+    y = y >= m ? y - m : y;
+    return y >= rc.cc ? y - rc.cc : y + m - rc.cc;
+}
+
+// the two targets of this lane in accumulator tile acc: u = 0, 1
+template <int U>
+__device__ __forceinline__ void tile_digits(const v16i& acc, int (&z)[8]) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        z[b] = acc[4 * U + b];
+        z[4 + b] = acc[8 + 4 * U + b];
+    }
+}
+
+// ModUp on the matrix cores: same inputs and outputs as k_modup_b.  A wave
+// converts 32 coefficients of digit j = blockIdx.y to every target row.
+__global__ __launch_bounds__(TB) void k_modup_mfma_b(WsRef ws, uint64_t off_d, uint64_t off_ext, uint32_t level,
+                                                     KsConsts kc, const DevMod* __restrict__ mods, uint32_t log_n) {
+    const uint32_t lane = threadIdx.x & 63u, half = lane >> 5;
+    const uint32_t n = (blockIdx.x * (TB / 64) + (threadIdx.x >> 6)) * 32 + (lane & 31u);
+    const uint32_t j = blockIdx.y;
+    const uint32_t i0 = j * kc.alpha;
+    const uint32_t na = min(i0 + kc.alpha, level) - i0;
+    const uint32_t rows = level + kc.K, T = rows - na;
+    const uint32_t nkb = (na + 1) / 2;
+    const size_t cbase = ((size_t)(level - 1) * kc.dnum + j) * kc.alpha;
+    const uint64_t* __restrict__ d = ws_item(ws) + off_d;
+    long bop[PFT_MAX_ALPHA / 2];
+#pragma unroll
+    for (uint32_t kb = 0; kb < PFT_MAX_ALPHA / 2; ++kb) {
+        const uint32_t ii = 2 * kb + half;
+        uint64_t x = 0;
+        if (ii < na) {
+            const TwPair h = kc.modup_hatinv[cbase + ii];
+            x = shoup(d[at(i0 + ii, log_n, n)], h.w, h.wp, mods[i0 + ii].q);
+        }
+        bop[kb] = split_digits(x);
+    }
+    const uint64_t* __restrict__ aop =
+        kc.up_aop + ((size_t)(level - 1) * kc.dnum + j) * kc.up_rt * kc.up_kb * 64 + lane;
+    uint64_t* __restrict__ outj = ws_item(ws) + off_ext + ((size_t)j * rows << log_n);
+    for (uint32_t rt = 0; rt * 4 < T; ++rt) {
+        v16i acc = {};
+#pragma unroll
+        for (uint32_t kb = 0; kb < PFT_MAX_ALPHA / 2; ++kb)
+            if (kb < nkb)
+                acc = __builtin_amdgcn_mfma_i32_32x32x16_i8((long)aop[(rt * kc.up_kb + kb) * 64], bop[kb], acc, 0,
+                                                            0, 0);
+        int z[8];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (u == 0) tile_digits<0>(acc, z); else tile_digits<1>(acc, z);
+            const uint32_t tt = 4 * rt + 2 * half + u;
+            if (tt < T) {
+                const uint32_t t = tt < i0 ? tt : tt + na;
+                const uint32_t mi = t < level ? t : kc.L + (t - level);
+                outj[at(t, log_n, n)] = fold_digits(z, kc.red[mi], mods[mi].q, mods[mi].bits);
+            }
+        }
+    }
+}
+
+// ModDown conversion on the matrix cores: same inputs and outputs as
+// k_moddown_conv_b (poly b = blockIdx.y).
+__global__ __launch_bounds__(TB) void k_moddown_mfma_b(WsRef ws, uint64_t off_acc, uint64_t off_conv, uint32_t level,
+                                                       KsConsts kc, const DevMod* __restrict__ mods,
+                                                       uint32_t log_n) {
+    const uint32_t lane = threadIdx.x & 63u, half = lane >> 5;
+    const uint32_t n = (blockIdx.x * (TB / 64) + (threadIdx.x >> 6)) * 32 + (lane & 31u);
+    const uint32_t b = blockIdx.y;
+    const uint32_t rows = level + kc.K;
+    const uint32_t nkb = (kc.K + 1) / 2;
+    const uint64_t* __restrict__ acc_in = ws_item(ws) + off_acc;
+    long bop[PFT_MAX_K / 2];
+#pragma unroll
+    for (uint32_t kb = 0; kb < PFT_MAX_K / 2; ++kb) {
+        const uint32_t k = 2 * kb + half;
+        uint64_t x = 0;
+        if (k < kc.K) {
+            const TwPair h = kc.down_phatinv[k];
+            x = shoup(acc_in[at(b * rows + level + k, log_n, n)], h.w, h.wp, mods[kc.L + k].q);
+        }
+        bop[kb] = split_digits(x);
+    }
+    const uint64_t* __restrict__ aop = kc.down_aop + lane;
+    uint64_t* __restrict__ conv = ws_item(ws) + off_conv;
+    for (uint32_t rt = 0; rt * 4 < level; ++rt) {
+        v16i acc = {};
+#pragma unroll
+        for (uint32_t kb = 0; kb < PFT_MAX_K / 2; ++kb)
+            if (kb < nkb)
+                acc = __builtin_amdgcn_mfma_i32_32x32x16_i8((long)aop[(rt * kc.down_kb + kb) * 64], bop[kb], acc, 0,
+                                                            0, 0);
+        int z[8];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (u == 0) tile_digits<0>(acc, z); else tile_digits<1>(acc, z);
+            const uint32_t i = 4 * rt + 2 * half + u;
+            if (i < level) conv[at(b * level + i, log_n, n)] = fold_digits(z, kc.red[i], mods[i].q, mods[i].bits);
+        }
+    }
+}
+
 // acc_b[t] = sum_j x_j[t] key_{j,b}[row(t)], x_j = d (NTT domain, at off_d)
 // on digit j's own rows and ext_j elsewhere; keys hold key * 2^64 mod m
 // (Montgomery), so one REDC per output gives the plain residue.
@@ -175,6 +306,48 @@ __global__ __launch_bounds__(TB) void k_key_inner_b(WsRef ws, uint64_t off_d, ui
     uint64_t* __restrict__ acc = ws_item(ws) + off_acc;
     acc[at(t, log_n, k)] = mont_redc(a0.lo, a0.hi, md.q, md.mont_neg_qinv);
     acc[at(rows + t, log_n, k)] = mont_redc(a1.lo, a1.hi, md.q, md.mont_neg_qinv);
+}
+
+// The same inner product for all n_items ciphertexts of a launch, one thread
+// per (coefficient, row): the 2 beta key residues of the row are loaded once
+// and reused for every item (the key is shared by the batch), then each item
+// reads its beta inputs and writes its two outputs.  beta <= PFT_KEY_REGS.
+#define PFT_KEY_REGS 8
+__global__ __launch_bounds__(TB) void k_key_inner_items(WsRef ws, uint32_t n_items, uint64_t off_d, uint64_t off_ext,
+                                                        uint64_t off_acc, const uint64_t* __restrict__ key,
+                                                        uint32_t level, KsConsts kc, const DevMod* __restrict__ mods,
+                                                        uint32_t log_n) {
+    const uint32_t k = blockIdx.x * TB + threadIdx.x;
+    const uint32_t t = blockIdx.y;
+    const uint32_t rows = level + kc.K;
+    const uint32_t krow = t < level ? t : kc.L + (t - level);
+    const DevMod md = mods[krow];
+    const uint32_t beta = (level + kc.alpha - 1) / kc.alpha;
+    const uint32_t krows = kc.L + kc.K;
+    uint64_t k0[PFT_KEY_REGS], k1[PFT_KEY_REGS];
+    uint32_t own = PFT_KEY_REGS;  // the digit whose input is d itself on this row
+#pragma unroll
+    for (uint32_t j = 0; j < PFT_KEY_REGS; ++j) {
+        if (j < beta) {
+            k0[j] = key[at((2 * j) * krows + krow, log_n, k)];
+            k1[j] = key[at((2 * j + 1) * krows + krow, log_n, k)];
+            if (t >= j * kc.alpha && t < min(j * kc.alpha + kc.alpha, level)) own = j;
+        }
+    }
+    for (uint32_t z = 0; z < n_items; ++z) {
+        uint64_t* __restrict__ w = ws.base + (size_t)z * ws.stride;
+        Acc128 a0 = {0, 0}, a1 = {0, 0};
+#pragma unroll
+        for (uint32_t j = 0; j < PFT_KEY_REGS; ++j) {
+            if (j < beta) {
+                const uint64_t x = j == own ? w[off_d + at(t, log_n, k)] : w[off_ext + at(j * rows + t, log_n, k)];
+                mac128(a0, x, k0[j]);
+                mac128(a1, x, k1[j]);
+            }
+        }
+        w[off_acc + at(t, log_n, k)] = mont_redc(a0.lo, a0.hi, md.q, md.mont_neg_qinv);
+        w[off_acc + at(rows + t, log_n, k)] = mont_redc(a1.lo, a1.hi, md.q, md.mont_neg_qinv);
+    }
 }
 
 // ModDown conversion of the K special rows (coefficient form) of acc_b:
@@ -341,22 +514,35 @@ void launch_automorphism_b(uint32_t n, const ItemPtrs& in, uint32_t rows, WsRef 
 }
 
 void launch_modup_b(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, uint32_t level, const KsConsts& kc,
-                    const DevTables& t, uint32_t log_n, hipStream_t st) {
+                    const DevTables& t, uint32_t log_n, bool mfma, hipStream_t st) {
     const uint32_t beta = (level + kc.alpha - 1) / kc.alpha;
-    hipLaunchKernelGGL(k_modup_b, grid_nk(log_n, beta, n), dim3(TB), 0, st, ws, off_d, off_ext, level, kc, t.mods,
-                       log_n);
+    if (mfma)  // 32 coefficients per wave
+        hipLaunchKernelGGL(k_modup_mfma_b, dim3((1u << log_n) / (32 * (TB / 64)), beta, n), dim3(TB), 0, st, ws,
+                           off_d, off_ext, level, kc, t.mods, log_n);
+    else
+        hipLaunchKernelGGL(k_modup_b, grid_nk(log_n, beta, n), dim3(TB), 0, st, ws, off_d, off_ext, level, kc,
+                           t.mods, log_n);
 }
 
 void launch_key_inner_b(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, uint64_t off_acc, const uint64_t* key,
                         uint32_t level, const KsConsts& kc, const DevTables& t, uint32_t log_n, hipStream_t st) {
-    hipLaunchKernelGGL(k_key_inner_b, grid_nk(log_n, level + kc.K, n), dim3(TB), 0, st, ws, off_d, off_ext, off_acc,
-                       key, level, kc, t.mods, log_n);
+    const uint32_t beta = (level + kc.alpha - 1) / kc.alpha;
+    if (beta <= PFT_KEY_REGS)
+        hipLaunchKernelGGL(k_key_inner_items, grid_nk(log_n, level + kc.K, 1), dim3(TB), 0, st, ws, n, off_d, off_ext,
+                           off_acc, key, level, kc, t.mods, log_n);
+    else
+        hipLaunchKernelGGL(k_key_inner_b, grid_nk(log_n, level + kc.K, n), dim3(TB), 0, st, ws, off_d, off_ext,
+                           off_acc, key, level, kc, t.mods, log_n);
 }
 
 void launch_moddown_conv_b(uint32_t n, WsRef ws, uint64_t off_acc, uint64_t off_conv, uint32_t level,
-                           const KsConsts& kc, const DevTables& t, uint32_t log_n, hipStream_t st) {
-    hipLaunchKernelGGL(k_moddown_conv_b, grid_nk(log_n, 2, n), dim3(TB), 0, st, ws, off_acc, off_conv, level, kc,
-                       t.mods, log_n);
+                           const KsConsts& kc, const DevTables& t, uint32_t log_n, bool mfma, hipStream_t st) {
+    if (mfma)
+        hipLaunchKernelGGL(k_moddown_mfma_b, dim3((1u << log_n) / (32 * (TB / 64)), 2, n), dim3(TB), 0, st, ws,
+                           off_acc, off_conv, level, kc, t.mods, log_n);
+    else
+        hipLaunchKernelGGL(k_moddown_conv_b, grid_nk(log_n, 2, n), dim3(TB), 0, st, ws, off_acc, off_conv, level,
+                           kc, t.mods, log_n);
 }
 
 void launch_moddown_final_b(uint32_t n, WsRef ws, uint64_t off_acc, uint64_t off_conv, uint64_t off_add0,

@@ -68,12 +68,28 @@ struct WsRef {
 };
 #define PFT_NO_OFFSET (~0ull)
 
+// Per-modulus constants that fold the digit sums of the MFMA base
+// conversion back into a residue: y = S_lo + 2^32 S_hi with |S_lo|, |S_hi| <
+// 2^45 is reduced as (S_lo + 2^45) + (S_hi + 2^45) 2^32 - (2^45 + 2^77).
+struct BconvRed {
+    TwPair c32;    // 2^32 mod m with its Shoup companion
+    uint64_t one_p;  // floor(2^64 / m): Shoup companion of 1
+    uint64_t cc;     // (2^45 + 2^77) mod m
+};
+
 struct KsConsts {
     const TwPair* modup_hatinv;   // [L][dnum][alpha]   indexed by (level-1, j, ii)
     const uint64_t* modup_c;      // [L][dnum][alpha][L+K] Montgomery form, row = target row
     const TwPair* down_phatinv;   // [K]
     const uint64_t* down_c;       // [K][L] Montgomery form
     const TwPair* down_pinv;      // [L]
+    // MFMA base conversion: int8 digit operands, one 64-bit word per lane
+    // ModUp:   [L][dnum][up_rt][up_kb][64]   (level-1, digit, row tile, k block, lane)
+    // ModDown: [down_rt][down_kb][64]
+    const uint64_t* up_aop;
+    const uint64_t* down_aop;
+    const BconvRed* red;          // [L+K] by modulus index
+    uint32_t up_rt, up_kb, down_rt, down_kb;
     uint32_t L, K, dnum, alpha;
 };
 
@@ -86,14 +102,15 @@ void launch_copy_rows_b(uint32_t n, const ItemPtrs& src, uint64_t src_off, const
 void launch_automorphism_b(uint32_t n, const ItemPtrs& in, uint32_t rows, WsRef ws, uint64_t off_out, uint64_t kappa,
                            uint32_t log_n, hipStream_t st);
 // ModUp base conversion: d (coefficient form) -> ext [beta][level+K][N].
+// mfma: the contraction on the matrix cores (int8 digits), else 128-bit VALU MACs.
 void launch_modup_b(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, uint32_t level, const KsConsts& kc,
-                    const DevTables& t, uint32_t log_n, hipStream_t st);
+                    const DevTables& t, uint32_t log_n, bool mfma, hipStream_t st);
 // acc [2][level+K][N] = sum_j x_j * key_j  (key: [dnum][2][L+K][N], Montgomery form)
 void launch_key_inner_b(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, uint64_t off_acc, const uint64_t* key,
                         uint32_t level, const KsConsts& kc, const DevTables& t, uint32_t log_n, hipStream_t st);
 // acc special rows (coefficient form) -> conv [2][level][N] (coefficient form)
 void launch_moddown_conv_b(uint32_t n, WsRef ws, uint64_t off_acc, uint64_t off_conv, uint32_t level,
-                           const KsConsts& kc, const DevTables& t, uint32_t log_n, hipStream_t st);
+                           const KsConsts& kc, const DevTables& t, uint32_t log_n, bool mfma, hipStream_t st);
 // out_z[b][i] = (acc_b[i] - conv_b[i]) P^-1 (+ ws rows at off_add_b unless PFT_NO_OFFSET)
 void launch_moddown_final_b(uint32_t n, WsRef ws, uint64_t off_acc, uint64_t off_conv, uint64_t off_add0,
                             uint64_t off_add1, const ItemPtrs& out, uint32_t level, const KsConsts& kc,

@@ -84,6 +84,9 @@ SIGNATURES = [
     ("pft_rotate", [_vp, ctypes.POINTER(CtDesc), ctypes.c_int32, ctypes.POINTER(CtDesc)], ctypes.c_int),
     ("pft_rotate_batch", [_vp, ctypes.c_uint32, ctypes.POINTER(CtDesc), ctypes.c_int32, ctypes.POINTER(CtDesc)],
      ctypes.c_int),
+    ("pft_rotate_pow2", [_vp, ctypes.POINTER(CtDesc), ctypes.c_int32, ctypes.POINTER(CtDesc)], ctypes.c_int),
+    ("pft_rotate_pow2_batch", [_vp, ctypes.c_uint32, ctypes.POINTER(CtDesc), ctypes.c_int32, ctypes.POINTER(CtDesc)],
+     ctypes.c_int),
     ("pft_total_sum", [_vp, ctypes.POINTER(CtDesc), ctypes.c_uint32, ctypes.POINTER(CtDesc)], ctypes.c_int),
     ("pft_total_sum_batch", [_vp, ctypes.c_uint32, ctypes.POINTER(CtDesc), ctypes.c_uint32, ctypes.POINTER(CtDesc)],
      ctypes.c_int),
@@ -99,6 +102,7 @@ SIGNATURES = [
     ("pft_ptmatvec", [_vp, _vp, ctypes.c_uint32, ctypes.POINTER(CtDesc), ctypes.POINTER(CtDesc)], ctypes.c_int),
     ("pft_ntt_forward", [_vp, _vp, ctypes.c_uint32, ctypes.c_uint32], ctypes.c_int),
     ("pft_ntt_inverse", [_vp, _vp, ctypes.c_uint32, ctypes.c_uint32], ctypes.c_int),
+    ("pft_bconv_mode", [_vp, ctypes.c_int], ctypes.c_int),
     ("pft_ntt_candidates", [_vp, _u32p, ctypes.c_uint32], ctypes.c_int),
     ("pft_ntt_autotune", [_vp, ctypes.c_int], ctypes.c_int),
     ("pft_ntt_set_schedule", [_vp, ctypes.c_int, _u32p], ctypes.c_int),

@@ -170,6 +170,25 @@ def test_mul_relin_parity(request, name, levels):
         w.assert_same(w.ctx.mul_relin(ga, gb), C.hmul_relin(w.op, oa, ob, w.rlk))
 
 
+@pytest.mark.parametrize("name,levels", [("c1", (2, 1)), ("c2", (8, 5, 2)), ("c3", (24, 17, 6))])
+def test_bconv_modes_parity(request, name, levels):
+    """Key switching with the base conversions on the matrix cores (int8
+    digits, the default) and on the VALU (128-bit MACs): both equal the
+    oracle, at full, ragged-last-digit and low levels."""
+    w = _world(request, name)
+    for lvl in levels:
+        ga, oa = w.encrypt_pair(w.random_plain(23), lvl, 700 + lvl)
+        gb, ob = w.encrypt_pair(w.random_plain(24), lvl, 800 + lvl)
+        want = C.hmul_relin(w.op, oa, ob, w.rlk)
+        st = sorted(w.rot)[0]
+        want_rot = C.rotate(w.op, oa, st, w.rot[st])
+        for mfma in (True, False):
+            w.ctx.bconv_mode(mfma)
+            w.assert_same(w.ctx.mul_relin(ga, gb), want)
+            w.assert_same(w.ctx.rotate(ga, st), want_rot)
+    w.ctx.bconv_mode(True)
+
+
 @pytest.mark.parametrize("name,levels", [("c1", (2,)), ("c2", (8, 3, 2)), ("c3", (24, 13))])
 @pytest.mark.parametrize("mode", [0, 1])
 def test_rescale_parity(request, name, levels, mode):
@@ -187,6 +206,24 @@ def test_rotate_parity(request, name, steps, levels):
         g, o = w.encrypt_pair(w.random_plain(41), lvl, 500 + lvl)
         for st in steps:
             w.assert_same(w.ctx.rotate(g, st), C.rotate(w.op, o, st, w.rot[st]))
+
+
+def test_rotate_pow2_parity(c1):
+    """Rotation from power-of-two keys (low and high Hamming weight steps, a
+    negative step): bit-exact against the oracle's same decomposition."""
+    w = c1
+    for k in range(11):
+        if (1 << k) not in w.rot:
+            w.add_rotation(1 << k)
+    keys = {1 << k: w.rot[1 << k] for k in range(11)}
+    for lvl in (2, 1):
+        g, o = w.encrypt_pair(w.random_plain(42), lvl, 520 + lvl)
+        for st in (1, 11, -3, 2047):
+            w.assert_same(w.ctx.rotate_pow2(g, st), C.rotate_pow2(w.op, o, st, keys))
+        out = w.ctx.rotate_pow2_batch([g, g], 6)
+        want = C.rotate_pow2(w.op, o, 6, keys)
+        for x in out:
+            w.assert_same(x, want)
 
 
 def test_total_sum_parity(c1):

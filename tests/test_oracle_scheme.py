@@ -221,6 +221,24 @@ def test_c1_rotate(c1, step):
     assert np.max(np.abs(_dec(c1, r) - want)) <= c1["fresh"] + _ks_bound(P, r.scale)
 
 
+def test_c1_rotate_pow2(c1):
+    """Power-of-two decomposition: slots equal the direct rotation by the full
+    step (within one key-switch error per set bit), and a single-bit step is
+    exactly the direct rotation."""
+    P = c1["P"]
+    keys = {}
+    for k in range(4):
+        a, e = S.switch_key_draws(1, 200 + k, P.n, P.key_moduli(), P.dnum)
+        keys[1 << k] = C.rotation_key(P, c1["kd"].s, 1 << k, a, e)
+    for step, hw in ((11, 3), (13 - P.n // 2, 3)):   # 11 = 8 + 2 + 1; a negative step reduces mod N/2
+        r = C.rotate_pow2(P, c1["ct1"], step, keys)
+        want = np.roll(c1["z1"], -step)
+        assert np.max(np.abs(_dec(c1, r) - want)) <= c1["fresh"] + hw * _ks_bound(P, r.scale)
+    one = C.rotate_pow2(P, c1["ct1"], 4, keys)
+    direct = C.rotate(P, c1["ct1"], 4, keys[4])
+    assert np.array_equal(one.c0, direct.c0) and np.array_equal(one.c1, direct.c1)
+
+
 def test_c1_total_sum(c1):
     P = c1["P"]
     t = P.n // 2
