@@ -42,7 +42,8 @@ def kernel_name(kid, variant):
     if kid in (0, 1) and variant:
         v = variant - 1
         b = lambda x: "true" if x else "false"  # noqa: E731
-        return "k_ntt_pass<%d, %s, %s, %s, %s>" % (v & 31, b(kid == 1), b(v & 32), b(v & 64), b(v & 128))
+        return "k_ntt_pass<%d, %d, %s, %s, %s, %s>" % (v & 31, 3 if v & 256 else 4, b(kid == 1), b(v & 32), b(v & 64),
+                                                        b(v & 128))
     return KERNEL_NAMES.get(kid, FAMILIES[kid])
 CHAIN_DEPTH = 8
 ROT_SLOTS = 1 << 15
@@ -178,7 +179,7 @@ def summarize(trace_dir, fetch_dir, write_dir, kernel, kid, commands):
         kernel = max(per, key=lambda k: per[k][1])
         out[0] = "# %s: job steps of bench.py (large ring, N=2^16, L=24, batch 16)" % kernel
         if kernel.startswith("k_ntt_pass<"):
-            kid = 1 if kernel.split(",")[1].strip() == "true" else 0
+            kid = 1 if kernel.split(",")[2].strip() == "true" else 0
     short = kernel.replace("void ", "")
     tgt = [v for k, v in per.items() if k == short]
     avg_us = tgt[0][1] / tgt[0][0] if tgt else None
@@ -475,7 +476,7 @@ def main():
     sync = torch.cuda.synchronize
     if args.tuning_in:
         with open(args.tuning_in) as fh:
-            ctx.ntt_tuning_import([(e[0], e[1], (tuple(e[2]), e[3])) for e in json.load(fh)])
+            ctx.ntt_tuning_import([(e[0], e[1], (tuple(e[2]), int(e[3]))) for e in json.load(fh)])
         log("NTT schedules imported from %s" % args.tuning_in)
 
     def save_tuning():
@@ -633,8 +634,8 @@ def main():
         "config": {"workload": "large ring: N=2^16, L=24 (+K=6, dnum=4), scale 2^50, batch %d; depth-8 "
                                "HMult+relin+rescale chain then rotate-and-sum over 2^15 slots" % args.batch,
                    "global_batch": args.batch, "log_n": 16, "levels": lp.L, "special_primes": lp.K, "dnum": lp.dnum,
-                   "ntt_schedules": [{"inverse": bool(i), "class": c, "radices": r, "direct_rows": bool(d)}
-                                     for i, c, r, d in tuning]},
+                   "ntt_schedules": [{"inverse": bool(i), "class": c, "radices": r, "direct_rows": bool(f & 1),
+                                      "residues_per_thread": 8 if f & 2 else 16} for i, c, r, f in tuning]},
         "breakdown": breakdown,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -224,7 +224,9 @@ int pft_ntt_inverse(pft_ctx* ctx, uint64_t* data, uint32_t n_polys, uint32_t n_l
  * the window sizes (radices, log2 of each window's stage count) in forward
  * order, zero-filled to three entries and summing to log_n, then a flags word
  * (bit 0: the last window's pass accesses the side of its data that is not
- * coalesced directly, 16 bytes per lane, instead of staging it through LDS).
+ * coalesced directly, 16 bytes per lane, instead of staging it through LDS;
+ * bit 1: 8 residues per thread in 512-thread workgroups instead of 16 in 256,
+ * for more waves in flight).
  * Every schedule computes the same transform bit for bit; the choice only
  * changes speed.
  * pft_ntt_candidates writes the candidates for the ring of p (default first)
@@ -333,8 +335,9 @@ int pft_prof_read(pft_ctx* ctx, uint32_t kid, double* total_ms, uint64_t* launch
  * time first: up to max_count entries of (variant, ms, launches, algorithmic
  * bytes, ops); returns the number of distinct variants.  variant 0: the
  * family's single kernel; NTT passes (families 0 and 1): 1 + (radix | 32 if a
- * column pass | 64 if the transform's final pass | 128 if staged), naming
- * k_ntt_pass<radix, inverse, column, final, staged>.  Any output may be NULL. */
+ * column pass | 64 if the transform's final pass | 128 if staged | 256 if 8
+ * residues per thread), naming k_ntt_pass<radix, log2 residues per thread,
+ * inverse, column, final, staged>.  Any output may be NULL. */
 int pft_prof_read_variants(pft_ctx* ctx, uint32_t kid, uint32_t max_count, uint32_t* variants, double* total_ms,
                            uint64_t* launches, double* bytes, double* ops);
 

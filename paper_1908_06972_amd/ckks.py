@@ -345,16 +345,16 @@ class Context:
         N.check(self.lib.pft_ntt_inverse(self.handle, ctypes.c_void_p(data.data_ptr()), n_polys, n_limbs))
 
     # ---- NTT pass schedules (see pft_ntt_candidates): a schedule is
-    # (radices in forward order, direct) with direct = the last window's pass
-    # skips the LDS staging
+    # (radices in forward order, flags) with flag 1 = the last window's pass
+    # skips the LDS staging, flag 2 = 8 residues per thread instead of 16
     @staticmethod
     def _sched_from(words):
-        return tuple(int(r) for r in words[:3] if r), bool(words[3] & 1)
+        return tuple(int(r) for r in words[:3] if r), int(words[3])
 
     @staticmethod
     def _sched_to(sched):
-        radices, direct = sched
-        return (ctypes.c_uint32 * 4)(*(list(radices) + [0] * (3 - len(radices)) + [1 if direct else 0]))
+        radices, flags = sched
+        return (ctypes.c_uint32 * 4)(*(list(radices) + [0] * (3 - len(radices)) + [int(flags)]))
 
     def ntt_candidates(self):
         n = self.lib.pft_ntt_candidates(self.params.handle, None, 0)
@@ -372,12 +372,12 @@ class Context:
         N.check(self.lib.pft_ntt_autotune(self.handle, int(bool(enable))))
 
     def ntt_set_schedule(self, inverse: bool, sched):
-        """sched: (radices, direct), or None to unpin."""
+        """sched: (radices, flags), or None to unpin."""
         arr = None if sched is None else self._sched_to(sched)
         N.check(self.lib.pft_ntt_set_schedule(self.handle, int(bool(inverse)), arr))
 
     def ntt_tuning_export(self):
-        """Tuned choices: list of (inverse, class, (radices, direct))."""
+        """Tuned choices: list of (inverse, class, (radices, flags))."""
         n = self.lib.pft_ntt_tuning_export(self.handle, None, 0)
         if n < 0:
             N.check(n)

@@ -591,8 +591,8 @@ static NttSchedule ntt_default(const pft_params* P) {
 // 2% of the fastest wins, so near-ties resolve the same way run to run.
 static NttSchedule ntt_tune(pft_ctx* c, bool inverse, uint32_t cls) {
     const pft_params* P = c->P;
-    NttSchedule cand[16];
-    const int nc = ntt_candidates(P->log_n, cand, 16);
+    NttSchedule cand[32];
+    const int nc = ntt_candidates(P->log_n, cand, 32);
     if (nc <= 1) return cand[0];
     const uint32_t rows = P->L + P->K;
     const uint64_t want = 1ull << cls;
@@ -1719,8 +1719,8 @@ static void sched_words(const NttSchedule& s, uint32_t* w) {
 
 extern "C" int pft_ntt_candidates(const pft_params* p, uint32_t* scheds, uint32_t max_count) {
     if (!p) return fail(PFT_EINVAL, "null params");
-    NttSchedule cand[16];
-    const int n = ntt_candidates(p->log_n, cand, 16);
+    NttSchedule cand[32];
+    const int n = ntt_candidates(p->log_n, cand, 32);
     if (scheds)
         for (uint32_t i = 0; i < std::min<uint32_t>((uint32_t)n, max_count); ++i) sched_words(cand[i], scheds + 4 * i);
     return n;

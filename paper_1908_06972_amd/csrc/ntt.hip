@@ -30,6 +30,8 @@
 #include "pft_device.h"
 #include "pft_kernels.h"
 
+#include <type_traits>
+
 namespace {
 
 // ---- integer butterflies (any q < 2^60)
@@ -110,20 +112,24 @@ __device__ __forceinline__ uint64_t fp_to_u64(uint64_t v, double q, double qinv)
     return as_u(r + 4503599627370496.0) & 0x000FFFFFFFFFFFFFull;
 }
 
-template <int LOG_M, int PH>
+// Register phase PH of a radix-2^LOG_M pass with E = 2^EB residues per
+// thread: stage bits HB down to LB; element e of thread l is index r_of(l, e)
+// of its sub-problem (the EB window bits sit at WLO).
+template <int LOG_M, int PH, int EB>
 struct Phase {
-    static constexpr int HB = LOG_M - 1 - 4 * PH;           // highest stage bit of this phase
-    static constexpr int LB = (HB - 3 > 0) ? HB - 3 : 0;     // lowest stage bit
-    static constexpr int WLO = (HB - 3 >= 0) ? HB - 3 : 0;  // window of the 16 register elements
+    static constexpr int HB = LOG_M - 1 - EB * PH;                       // highest stage bit of this phase
+    static constexpr int LB = (HB - (EB - 1) > 0) ? HB - (EB - 1) : 0;   // lowest stage bit
+    static constexpr int WLO = (HB - (EB - 1) >= 0) ? HB - (EB - 1) : 0; // window of the register elements
     __device__ __forceinline__ static uint32_t r_of(uint32_t l, int e) {
-        return ((l >> WLO) << (WLO + 4)) | ((uint32_t)e << WLO) | (l & ((1u << WLO) - 1u));
+        return ((l >> WLO) << (WLO + EB)) | ((uint32_t)e << WLO) | (l & ((1u << WLO) - 1u));
     }
 };
 
-template <int LOG_M, int PH, bool INV, bool FP, bool FOLD>
-__device__ __forceinline__ void run_phase(uint64_t (&x)[16], uint32_t l, uint32_t high, uint32_t s0,
+template <int LOG_M, int PH, int EB, bool INV, bool FP, bool FOLD>
+__device__ __forceinline__ void run_phase(uint64_t (&x)[1 << EB], uint32_t l, uint32_t high, uint32_t s0,
                                           const TwPair* __restrict__ twt, const DevMod& md) {
-    using Ph = Phase<LOG_M, PH>;
+    using Ph = Phase<LOG_M, PH, EB>;
+    constexpr int E = 1 << EB;
     const uint64_t q = md.q, two_q = md.two_q;
     const double qd = md.qd, qinv = md.qinv;
     if constexpr (!INV) {
@@ -133,7 +139,7 @@ __device__ __forceinline__ void run_phase(uint64_t (&x)[16], uint32_t l, uint32_
             const uint32_t s = s0 + spp;
             const int pos = bit - Ph::WLO;
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
+            for (int e = 0; e < E; ++e) {
                 if (e & (1 << pos)) continue;
                 const uint32_t r = Ph::r_of(l, e);
                 const uint32_t i = (high << spp) | (r >> (bit + 1));
@@ -153,7 +159,7 @@ __device__ __forceinline__ void run_phase(uint64_t (&x)[16], uint32_t l, uint32_
             if (FOLD && PH == 0 && bit == Ph::HB) {
                 // stage 0 with N^-1 folded in (integer path: outputs fully reduced)
 #pragma unroll
-                for (int e = 0; e < 16; ++e) {
+                for (int e = 0; e < E; ++e) {
                     if (e & (1 << pos)) continue;
                     uint64_t X = x[e], Y = x[e | (1 << pos)];
                     if constexpr (FP) {
@@ -169,7 +175,7 @@ __device__ __forceinline__ void run_phase(uint64_t (&x)[16], uint32_t l, uint32_
                 }
             } else {
 #pragma unroll
-                for (int e = 0; e < 16; ++e) {
+                for (int e = 0; e < E; ++e) {
                     if (e & (1 << pos)) continue;
                     const uint32_t r = Ph::r_of(l, e);
                     const uint32_t i = (high << spp) | (r >> (bit + 1));
@@ -191,50 +197,55 @@ __device__ __forceinline__ void run_phase(uint64_t (&x)[16], uint32_t l, uint32_
 // phase's arrangement under either lane mapping, and the staging order --
 // puts each group of 16 consecutive lanes on distinct bank pairs (radix 6
 // and 7 keep a two-way conflict on one row-pass pattern).
-template <int LOG_M> struct LdsPad;
-template <> struct LdsPad<4> { static constexpr uint32_t S = 17, P = 0; };
-template <> struct LdsPad<6> { static constexpr uint32_t S = 69, P = 1; };
-template <> struct LdsPad<7> { static constexpr uint32_t S = 145, P = 2; };
-template <> struct LdsPad<8> { static constexpr uint32_t S = 273, P = 1; };
-template <> struct LdsPad<9> { static constexpr uint32_t S = 546, P = 1; };
-template <> struct LdsPad<10> { static constexpr uint32_t S = 1092, P = 1; };
-template <> struct LdsPad<12> { static constexpr uint32_t S = 4352, P = 1; };
-template <int LOG_M>
-constexpr uint32_t lds_words() { return (4096u >> LOG_M) * LdsPad<LOG_M>::S; }
-template <int LOG_M>
+// (8 residues per thread: radix 6 and 7 use their own (S, P); at most a
+// two-way conflict remains on one pattern of radix 4 and 6-10.)
+template <int LOG_M, int EB> struct LdsPad;
+template <int EB> struct LdsPad<4, EB> { static constexpr uint32_t S = 17, P = 0; };
+template <> struct LdsPad<6, 4> { static constexpr uint32_t S = 69, P = 1; };
+template <> struct LdsPad<6, 3> { static constexpr uint32_t S = 73, P = 2; };
+template <> struct LdsPad<7, 4> { static constexpr uint32_t S = 145, P = 2; };
+template <> struct LdsPad<7, 3> { static constexpr uint32_t S = 137, P = 1; };
+template <int EB> struct LdsPad<8, EB> { static constexpr uint32_t S = 273, P = 1; };
+template <int EB> struct LdsPad<9, EB> { static constexpr uint32_t S = 546, P = 1; };
+template <int EB> struct LdsPad<10, EB> { static constexpr uint32_t S = 1092, P = 1; };
+template <int EB> struct LdsPad<12, EB> { static constexpr uint32_t S = 4352, P = 1; };
+template <int LOG_M, int EB>
+constexpr uint32_t lds_words() { return (4096u >> LOG_M) * LdsPad<LOG_M, EB>::S; }
+template <int LOG_M, int EB>
 __device__ __forceinline__ uint32_t lds_at(uint32_t c, uint32_t r) {
-    return c * LdsPad<LOG_M>::S + r + LdsPad<LOG_M>::P * (r >> 4);
+    return c * LdsPad<LOG_M, EB>::S + r + LdsPad<LOG_M, EB>::P * (r >> 4);
 }
 
-template <int LOG_M, int PH>
-__device__ __forceinline__ void lds_read(uint64_t (&x)[16], const uint64_t* lds, uint32_t c, uint32_t l) {
+template <int LOG_M, int PH, int EB>
+__device__ __forceinline__ void lds_read(uint64_t (&x)[1 << EB], const uint64_t* lds, uint32_t c, uint32_t l) {
 #pragma unroll
-    for (int e = 0; e < 16; ++e) x[e] = lds[lds_at<LOG_M>(c, Phase<LOG_M, PH>::r_of(l, e))];
+    for (int e = 0; e < (1 << EB); ++e) x[e] = lds[lds_at<LOG_M, EB>(c, Phase<LOG_M, PH, EB>::r_of(l, e))];
 }
-template <int LOG_M, int PH>
-__device__ __forceinline__ void lds_write(const uint64_t (&x)[16], uint64_t* lds, uint32_t c, uint32_t l) {
+template <int LOG_M, int PH, int EB>
+__device__ __forceinline__ void lds_write(const uint64_t (&x)[1 << EB], uint64_t* lds, uint32_t c, uint32_t l) {
 #pragma unroll
-    for (int e = 0; e < 16; ++e) lds[lds_at<LOG_M>(c, Phase<LOG_M, PH>::r_of(l, e))] = x[e];
+    for (int e = 0; e < (1 << EB); ++e) lds[lds_at<LOG_M, EB>(c, Phase<LOG_M, PH, EB>::r_of(l, e))] = x[e];
 }
 
 // The register phases of one pass in execution order (forward: 0, 1, ...;
 // inverse: the reverse), with an LDS exchange between consecutive phases.
 // Each thread writes back to the words it read last, so one barrier per
 // exchange suffices.
-template <int LOG_M, bool INV, bool FP, bool FOLD, int K>
-__device__ __forceinline__ void run_phases(uint64_t (&x)[16], uint64_t* lds, uint32_t c, uint32_t l, uint32_t high,
-                                           uint32_t s0, const TwPair* __restrict__ twt, const DevMod& md) {
-    constexpr int NPH = (LOG_M + 3) / 4;
+template <int LOG_M, int EB, bool INV, bool FP, bool FOLD, int K>
+__device__ __forceinline__ void run_phases(uint64_t (&x)[1 << EB], uint64_t* lds, uint32_t c, uint32_t l,
+                                           uint32_t high, uint32_t s0, const TwPair* __restrict__ twt,
+                                           const DevMod& md) {
+    constexpr int NPH = (LOG_M + EB - 1) / EB;
     if constexpr (K < NPH) {
         constexpr int PH = INV ? NPH - 1 - K : K;
         if constexpr (K > 0) {
             constexpr int PREV = INV ? PH + 1 : PH - 1;
-            lds_write<LOG_M, PREV>(x, lds, c, l);
+            lds_write<LOG_M, PREV, EB>(x, lds, c, l);
             __syncthreads();
-            lds_read<LOG_M, PH>(x, lds, c, l);
+            lds_read<LOG_M, PH, EB>(x, lds, c, l);
         }
-        run_phase<LOG_M, PH, INV, FP, FOLD>(x, l, high, s0, twt, md);
-        run_phases<LOG_M, INV, FP, FOLD, K + 1>(x, lds, c, l, high, s0, twt, md);
+        run_phase<LOG_M, PH, EB, INV, FP, FOLD>(x, l, high, s0, twt, md);
+        run_phases<LOG_M, EB, INV, FP, FOLD, K + 1>(x, lds, c, l, high, s0, twt, md);
     }
 }
 
@@ -251,22 +262,26 @@ __device__ __forceinline__ void run_phases(uint64_t (&x)[16], uint64_t* lds, uin
 // Limbs with DevMod::fp run the fp64 butterflies: the first pass of a
 // transform converts its u64 input, later passes exchange the doubles through
 // HBM, and the final pass writes canonical u64.  Integer limbs keep u64.
-template <int LOG_M, bool INV, bool COL, bool FINAL, bool STAGE>
-__global__ __launch_bounds__(256) void k_ntt_pass(PolyBatch b, const DevMod* __restrict__ mods,
-                                                  const TwPair* __restrict__ tw, uint32_t log_n, uint32_t s0,
-                                                  uint32_t first_pass) {
+template <int LOG_M, int EB, bool INV, bool COL, bool FINAL, bool STAGE>
+__global__ __launch_bounds__(4096 >> EB) void k_ntt_pass(PolyBatch b, const DevMod* __restrict__ mods,
+                                                         const TwPair* __restrict__ tw, uint32_t log_n, uint32_t s0,
+                                                         uint32_t first_pass) {
     constexpr int M = 1 << LOG_M;
-    constexpr int T = M / 16;
-    constexpr int C = 256 / T;
-    constexpr int NPH = (LOG_M + 3) / 4;
+    constexpr int E = 1 << EB;          // residues per thread
+    constexpr uint32_t NT = 4096 >> EB;  // threads per workgroup
+    constexpr int T = M / E;             // threads per sub-problem
+    constexpr int C = NT / T;            // sub-problems per workgroup
+    constexpr int NPH = (LOG_M + EB - 1) / EB;
     constexpr int PH_IN = INV ? NPH - 1 : 0;
     constexpr int PH_OUT = INV ? 0 : NPH - 1;
-    constexpr bool DIRECT_IN = COL || !STAGE || Phase<LOG_M, PH_IN>::WLO >= 4;
-    constexpr bool DIRECT_OUT = COL || !STAGE || Phase<LOG_M, PH_OUT>::WLO >= 4;
-    // a row-pass arrangement where thread l owns words 16 l .. 16 l + 15
-    constexpr bool VEC_IN = !COL && Phase<LOG_M, PH_IN>::WLO == 0;
-    constexpr bool VEC_OUT = !COL && Phase<LOG_M, PH_OUT>::WLO == 0;
-    __shared__ uint64_t lds[lds_words<LOG_M>()];
+    using PIN = Phase<LOG_M, PH_IN, EB>;
+    using POUT = Phase<LOG_M, PH_OUT, EB>;
+    constexpr bool DIRECT_IN = COL || !STAGE || PIN::WLO >= 4;
+    constexpr bool DIRECT_OUT = COL || !STAGE || POUT::WLO >= 4;
+    // a row-pass arrangement where thread l owns words E l .. E l + E - 1
+    constexpr bool VEC_IN = !COL && PIN::WLO == 0;
+    constexpr bool VEC_OUT = !COL && POUT::WLO == 0;
+    __shared__ uint64_t lds[lds_words<LOG_M, EB>()];
 
     const uint32_t tid = threadIdx.x;
     const uint32_t job = blockIdx.y;
@@ -291,39 +306,39 @@ __global__ __launch_bounds__(256) void k_ntt_pass(PolyBatch b, const DevMod* __r
         return ((((size_t)(sp >> lbits) << LOG_M) | r) << lbits) | (sp & lmask);
     };
 
-    uint64_t x[16];
+    uint64_t x[E];
     const bool convert_in = fp && first_pass;
     if constexpr (DIRECT_IN && VEC_IN) {
-        const ulonglong2* __restrict__ src = reinterpret_cast<const ulonglong2*>(data + gidx(c, 16u * l));
+        const ulonglong2* __restrict__ src = reinterpret_cast<const ulonglong2*>(data + gidx(c, (uint32_t)E * l));
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
+        for (int e = 0; e < E / 2; ++e) {
             const ulonglong2 v = src[e];
             x[2 * e] = convert_in ? fp_from_u64(v.x) : v.x;
             x[2 * e + 1] = convert_in ? fp_from_u64(v.y) : v.y;
         }
     } else if constexpr (DIRECT_IN) {
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const uint64_t v = data[gidx(c, Phase<LOG_M, PH_IN>::r_of(l, e))];
+        for (int e = 0; e < E; ++e) {
+            const uint64_t v = data[gidx(c, PIN::r_of(l, e))];
             x[e] = convert_in ? fp_from_u64(v) : v;
         }
     } else {
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const uint32_t idx = tid + 256u * k;
+        for (int k = 0; k < E; ++k) {
+            const uint32_t idx = tid + NT * k;
             const uint32_t cc = idx / M, r = idx % M;
             const uint64_t v = data[gidx(cc, r)];
-            lds[lds_at<LOG_M>(cc, r)] = convert_in ? fp_from_u64(v) : v;
+            lds[lds_at<LOG_M, EB>(cc, r)] = convert_in ? fp_from_u64(v) : v;
         }
         __syncthreads();
-        lds_read<LOG_M, PH_IN>(x, lds, c, l);
+        lds_read<LOG_M, PH_IN, EB>(x, lds, c, l);
     }
 
     // the final inverse pass (s0 = 0) folds N^-1 into stage 0
     if (fp)
-        run_phases<LOG_M, INV, true, FINAL, 0>(x, lds, c, l, high, s0, twt, md);
+        run_phases<LOG_M, EB, INV, true, FINAL, 0>(x, lds, c, l, high, s0, twt, md);
     else
-        run_phases<LOG_M, INV, false, FINAL, 0>(x, lds, c, l, high, s0, twt, md);
+        run_phases<LOG_M, EB, INV, false, FINAL, 0>(x, lds, c, l, high, s0, twt, md);
 
     const uint64_t q = md.q, two_q = md.two_q;
     const double qd = md.qd, qinv = md.qinv;
@@ -339,9 +354,9 @@ __global__ __launch_bounds__(256) void k_ntt_pass(PolyBatch b, const DevMod* __r
         return v;
     };
     if constexpr (DIRECT_OUT && VEC_OUT) {
-        ulonglong2* __restrict__ dst = reinterpret_cast<ulonglong2*>(data + gidx(c, 16u * l));
+        ulonglong2* __restrict__ dst = reinterpret_cast<ulonglong2*>(data + gidx(c, (uint32_t)E * l));
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
+        for (int e = 0; e < E / 2; ++e) {
             ulonglong2 v;
             v.x = finish(x[2 * e]);
             v.y = finish(x[2 * e + 1]);
@@ -349,30 +364,30 @@ __global__ __launch_bounds__(256) void k_ntt_pass(PolyBatch b, const DevMod* __r
         }
     } else if constexpr (DIRECT_OUT) {
 #pragma unroll
-        for (int e = 0; e < 16; ++e) data[gidx(c, Phase<LOG_M, PH_OUT>::r_of(l, e))] = finish(x[e]);
+        for (int e = 0; e < E; ++e) data[gidx(c, POUT::r_of(l, e))] = finish(x[e]);
     } else {
-        lds_write<LOG_M, PH_OUT>(x, lds, c, l);
+        lds_write<LOG_M, PH_OUT, EB>(x, lds, c, l);
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const uint32_t idx = tid + 256u * k;
+        for (int k = 0; k < E; ++k) {
+            const uint32_t idx = tid + NT * k;
             const uint32_t cc = idx / M, r = idx % M;
-            data[gidx(cc, r)] = finish(lds[lds_at<LOG_M>(cc, r)]);
+            data[gidx(cc, r)] = finish(lds[lds_at<LOG_M, EB>(cc, r)]);
         }
     }
 }
 
-template <int LOG_M, bool INV, bool COL, bool FINAL>
+template <int LOG_M, int EB, bool INV, bool COL, bool FINAL>
 void launch_k(const PolyBatch& b, const DevTables& t, uint32_t log_n, uint32_t s0, uint32_t first_pass, bool stage,
               hipStream_t st) {
     const dim3 grid((1u << log_n) / 4096u, b.n_polys * b.n_limbs);
     const TwPair* tw = INV ? t.tw_inv : t.tw_fwd;
     if (COL || stage)
-        hipLaunchKernelGGL((k_ntt_pass<LOG_M, INV, COL, FINAL, true>), grid, dim3(256), 0, st, b, t.mods, tw, log_n,
-                           s0, first_pass);
+        hipLaunchKernelGGL((k_ntt_pass<LOG_M, EB, INV, COL, FINAL, true>), grid, dim3(4096 >> EB), 0, st, b, t.mods,
+                           tw, log_n, s0, first_pass);
     else if constexpr (!COL)
-        hipLaunchKernelGGL((k_ntt_pass<LOG_M, INV, COL, FINAL, false>), grid, dim3(256), 0, st, b, t.mods, tw,
-                           log_n, s0, first_pass);
+        hipLaunchKernelGGL((k_ntt_pass<LOG_M, EB, INV, COL, FINAL, false>), grid, dim3(4096 >> EB), 0, st, b, t.mods,
+                           tw, log_n, s0, first_pass);
 }
 
 // One pass.  A column pass (low index bits remain below the window) needs at
@@ -381,39 +396,47 @@ void launch_k(const PolyBatch& b, const DevTables& t, uint32_t log_n, uint32_t s
 // going back the s0 = 0 window is.
 template <int LOG_M, bool INV>
 void launch_pass(const PolyBatch& b, const DevTables& t, uint32_t log_n, uint32_t s0, bool final_pass, bool stage,
-                 hipStream_t st, ProfHook* g_prof) {
+                 bool e8, hipStream_t st, ProfHook* g_prof) {
     const int kid = INV ? PK_NTT_INV : PK_NTT_FWD;
     const uint32_t first_pass = INV ? (s0 + LOG_M == log_n) : (s0 == 0);
     const bool col = s0 + LOG_M < log_n;
     const bool staged = col || stage;
     if (g_prof) g_prof->begin(kid);
-    if (col) {
-        if constexpr (LOG_M <= 8) launch_k<LOG_M, INV, true, INV>(b, t, log_n, s0, first_pass, true, st);
-    } else if (final_pass) {
-        if constexpr (!INV || LOG_M == 12)
-            launch_k<LOG_M, INV, false, true>(b, t, log_n, s0, first_pass, stage, st);
-    } else {
-        if constexpr (INV) launch_k<LOG_M, INV, false, false>(b, t, log_n, s0, first_pass, stage, st);
-    }
+    auto go = [&](auto eb) {
+        constexpr int EB = decltype(eb)::value;
+        if (col) {
+            if constexpr (LOG_M <= 8) launch_k<LOG_M, EB, INV, true, INV>(b, t, log_n, s0, first_pass, true, st);
+        } else if (final_pass) {
+            if constexpr (!INV || LOG_M == 12)
+                launch_k<LOG_M, EB, INV, false, true>(b, t, log_n, s0, first_pass, stage, st);
+        } else {
+            if constexpr (INV) launch_k<LOG_M, EB, INV, false, false>(b, t, log_n, s0, first_pass, stage, st);
+        }
+    };
+    if (e8)
+        go(std::integral_constant<int, 3>{});
+    else
+        go(std::integral_constant<int, 4>{});
     if (g_prof) {
         const double elems = (double)b.n_polys * b.n_limbs * (double)(1u << log_n);
         // read + write every residue once; N/2 butterflies per stage
-        const uint32_t variant = 1u + (LOG_M | (col ? 32u : 0u) | (final_pass ? 64u : 0u) | (staged ? 128u : 0u));
+        const uint32_t variant =
+            1u + (LOG_M | (col ? 32u : 0u) | (final_pass ? 64u : 0u) | (staged ? 128u : 0u) | (e8 ? 256u : 0u));
         g_prof->end(kid, 16.0 * elems, 0.5 * elems * LOG_M, variant);
     }
 }
 
 template <bool INV>
 void launch_radix(uint32_t radix, const PolyBatch& b, const DevTables& t, uint32_t log_n, uint32_t s0, bool fin,
-                  bool stage, hipStream_t st, ProfHook* prof) {
+                  bool stage, bool e8, hipStream_t st, ProfHook* prof) {
     switch (radix) {
-        case 4: launch_pass<4, INV>(b, t, log_n, s0, fin, stage, st, prof); break;
-        case 6: launch_pass<6, INV>(b, t, log_n, s0, fin, stage, st, prof); break;
-        case 7: launch_pass<7, INV>(b, t, log_n, s0, fin, stage, st, prof); break;
-        case 8: launch_pass<8, INV>(b, t, log_n, s0, fin, stage, st, prof); break;
-        case 9: launch_pass<9, INV>(b, t, log_n, s0, fin, stage, st, prof); break;
-        case 10: launch_pass<10, INV>(b, t, log_n, s0, fin, stage, st, prof); break;
-        case 12: launch_pass<12, INV>(b, t, log_n, s0, fin, stage, st, prof); break;
+        case 4: launch_pass<4, INV>(b, t, log_n, s0, fin, stage, e8, st, prof); break;
+        case 6: launch_pass<6, INV>(b, t, log_n, s0, fin, stage, e8, st, prof); break;
+        case 7: launch_pass<7, INV>(b, t, log_n, s0, fin, stage, e8, st, prof); break;
+        case 8: launch_pass<8, INV>(b, t, log_n, s0, fin, stage, e8, st, prof); break;
+        case 9: launch_pass<9, INV>(b, t, log_n, s0, fin, stage, e8, st, prof); break;
+        case 10: launch_pass<10, INV>(b, t, log_n, s0, fin, stage, e8, st, prof); break;
+        case 12: launch_pass<12, INV>(b, t, log_n, s0, fin, stage, e8, st, prof); break;
         default: break;
     }
 }
@@ -423,7 +446,8 @@ void launch_radix(uint32_t radix, const PolyBatch& b, const DevTables& t, uint32
 bool ntt_supported(uint32_t log_n) { return log_n >= 12 && log_n <= 16; }
 
 // Candidate schedules per log2 N, the default first: every radix split
-// below, each with the row pass staged through LDS and direct.  Windows are
+// below, each with the row pass staged through LDS and direct, and each with
+// 16 and with 8 residues per thread.  Windows are
 // listed in forward order (stages 0.. first); every candidate has at most two
 // passes, so each moves every residue through HBM at most twice.
 int ntt_candidates(uint32_t log_n, NttSchedule* out, int max_out) {
@@ -443,22 +467,23 @@ int ntt_candidates(uint32_t log_n, NttSchedule* out, int max_out) {
         default: return 0;
     }
     int k = 0;
-    for (int direct = 0; direct < 2; ++direct)
-        for (int i = 0; i < n; ++i) {
-            if (k >= max_out) return k;
-            NttSchedule s{};
-            s.n_passes = c[i][1] ? 2 : 1;
-            s.radix[0] = c[i][0];
-            s.radix[1] = c[i][1];
-            s.flags = direct ? NTT_DIRECT_ROWS : 0;
-            out[k++] = s;
-        }
+    for (int e8 = 0; e8 < 2; ++e8)
+        for (int direct = 0; direct < 2; ++direct)
+            for (int i = 0; i < n; ++i) {
+                if (k >= max_out) return k;
+                NttSchedule s{};
+                s.n_passes = c[i][1] ? 2 : 1;
+                s.radix[0] = c[i][0];
+                s.radix[1] = c[i][1];
+                s.flags = (direct ? NTT_DIRECT_ROWS : 0u) | (e8 ? NTT_E8 : 0u);
+                out[k++] = s;
+            }
     return k;
 }
 
 bool ntt_schedule_valid(uint32_t log_n, const NttSchedule& s) {
-    NttSchedule c[16];
-    const int n = ntt_candidates(log_n, c, 16);
+    NttSchedule c[32];
+    const int n = ntt_candidates(log_n, c, 32);
     for (int i = 0; i < n; ++i)
         if (c[i].n_passes == s.n_passes && c[i].radix[0] == s.radix[0] && c[i].radix[1] == s.radix[1] &&
             c[i].flags == s.flags)
@@ -477,11 +502,12 @@ void launch_ntt(const PolyBatch& b, const DevTables& t, uint32_t log_n, bool inv
     }
     if (acc != log_n) return;
     const bool stage = (s.flags & NTT_DIRECT_ROWS) == 0;
+    const bool e8 = (s.flags & NTT_E8) != 0;
     if (!inverse) {
         for (uint32_t p = 0; p < s.n_passes; ++p)
-            launch_radix<false>(s.radix[p], b, t, log_n, s0[p], p + 1 == s.n_passes, stage, st, prof);
+            launch_radix<false>(s.radix[p], b, t, log_n, s0[p], p + 1 == s.n_passes, stage, e8, st, prof);
     } else {
         for (uint32_t p = s.n_passes; p-- > 0;)
-            launch_radix<true>(s.radix[p], b, t, log_n, s0[p], p == 0, stage, st, prof);
+            launch_radix<true>(s.radix[p], b, t, log_n, s0[p], p == 0, stage, e8, st, prof);
     }
 }

@@ -28,7 +28,10 @@ struct ProfHook {
 
 // An NTT pass schedule: the radices (log2 of the stage windows) in forward
 // order, summing to log2 N, and flags.
-enum : uint32_t { NTT_DIRECT_ROWS = 1 };  // row pass reads/writes its strided side directly
+enum : uint32_t {
+    NTT_DIRECT_ROWS = 1,  // row pass reads/writes its strided side directly
+    NTT_E8 = 2            // 8 residues per thread (512-thread workgroups) instead of 16
+};
 struct NttSchedule {
     uint32_t n_passes;
     uint8_t radix[4];

@@ -92,7 +92,8 @@ def test_library_decode_matches_oracle():
 def test_ntt_candidate_schedules():
     """Schedules cover log2 N exactly, default first, at most two passes, only
     the last window may exceed radix 8 (column passes need >= 16 sub-problems
-    per workgroup), and each radix split comes staged and direct."""
+    per workgroup), and each radix split comes staged and direct, with 16 and 8
+    residues per thread."""
     from paper_1908_06972_amd.ckks import Params
     lib = N.load()
     for log_n in range(12, 17):
@@ -106,8 +107,8 @@ def test_ntt_candidate_schedules():
         for radices, flags in scheds:
             assert sum(radices) == log_n and 1 <= len(radices) <= 2
             assert all(r <= 8 for r in radices[:-1])
-            assert flags in (0, 1)
-            assert (radices, 1 - flags) in scheds
+            assert flags in (0, 1, 2, 3)
+            assert all((radices, f) in scheds for f in (0, 1, 2, 3))
         assert scheds[0] == ({12: (12,), 13: (7, 6), 14: (7, 7), 15: (8, 7), 16: (8, 8)}[log_n], 0)
 
 

@@ -96,9 +96,11 @@ def test_ntt_autotune_picks_a_candidate(torch_cuda):
     ctx.ntt_autotune(False)
     assert ctx.ntt_get_schedule(False, 40) == cands[0]
     with pytest.raises(N.PftError):
-        ctx.ntt_set_schedule(False, ((7, 6, 1), False))
+        ctx.ntt_set_schedule(False, ((7, 6, 1), 0))
     with pytest.raises(N.PftError):
-        ctx.ntt_set_schedule(False, ((8, 8), False))
+        ctx.ntt_set_schedule(False, ((8, 8), 0))
+    with pytest.raises(N.PftError):
+        ctx.ntt_set_schedule(False, ((7, 7), 4))
     ctx.ntt_set_schedule(True, cands[-1])
     assert ctx.ntt_get_schedule(True, 7) == cands[-1]
     ctx.ntt_set_schedule(True, None)
