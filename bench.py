@@ -33,7 +33,8 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, AMD published
 ALU_PEAK_GOPS = 256 * 64 * 2.4  # int32 VALU lane-ops/s in G: 256 CUs x 64 lanes x 2.4 GHz
 FAMILIES = ["ntt_fwd_pass", "ntt_inv_pass", "modup_bconv", "key_inner_product", "moddown_bconv",
             "moddown_final", "tensor", "automorphism", "rescale", "elementwise"]
-KERNEL_NAMES = {2: "k_modup_b", 3: "k_key_inner_b", 4: "k_moddown_conv_b", 5: "k_moddown_final_b", 6: "k_tensor_b",
+KERNEL_NAMES = {2: "k_modup_mfma_b", 3: "k_key_inner_items", 4: "k_moddown_mfma_b", 5: "(fused into the forward NTT)",
+                6: "k_tensor_b",
                 7: "k_automorphism_b", 8: "k_rescale_expand_b/k_rescale_final_b"}
 
 
@@ -42,8 +43,8 @@ def kernel_name(kid, variant):
     if kid in (0, 1) and variant:
         v = variant - 1
         b = lambda x: "true" if x else "false"  # noqa: E731
-        return "k_ntt_pass<%d, %d, %s, %s, %s, %s>" % (v & 31, 3 if v & 256 else 4, b(kid == 1), b(v & 32), b(v & 64),
-                                                        b(v & 128))
+        return "k_ntt_pass<%d, %d, %s, %s, %s, %s, %s>" % (v & 31, 3 if v & 256 else 4, b(kid == 1), b(v & 32),
+                                                            b(v & 64), b(v & 128), b(v & 512))
     return KERNEL_NAMES.get(kid, FAMILIES[kid])
 CHAIN_DEPTH = 8
 ROT_SLOTS = 1 << 15
@@ -148,21 +149,36 @@ def _step_dispatches(rows, key_id, key_start):
     return [r for r in rows if int(r[key_id]) >= first]
 
 
-def summarize(trace_dir, fetch_dir, write_dir, kernel, kid, commands):
+def family_of(name):
+    """Kernel family index (see pft_prof_enable) of a kernel name."""
+    if name.startswith("k_ntt_pass<"):
+        return 1 if name.split(",")[2].strip() == "true" else 0
+    for prefix, k in (("k_modup", 2), ("k_key_inner", 3), ("k_moddown", 4), ("k_tensor", 6), ("k_automorphism", 7),
+                      ("k_rescale", 8)):
+        if name.startswith(prefix):
+            return k
+    return 9
+
+
+def summarize(trace_dir, fetch_dir, write_dir, kernel, kid, commands, n_top=6):
     """Markdown summary of three rocprofv3 runs of bench.py: a kernel trace
     (durations) and two counter runs (FETCH_SIZE with SQ_INSTS_VALU, then
-    WRITE_SIZE), each restricted to the dispatches of the job steps.  The
-    copy kernel k_copy_rows_b (8 bytes read and 8 written per work-item)
+    WRITE_SIZE), each restricted to the dispatches of the job steps, with
+    counter figures for the n_top longest kernels (or `kernel`).  The copy
+    kernel k_copy_rows_b (8 bytes read and 8 written per work-item)
     calibrates the byte counters."""
     trace = _step_dispatches(_csv_rows(_find(trace_dir, "kernel_trace.csv")), "Dispatch_Id", "Start_Timestamp")
+    short_name = lambda n: n.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "")  # noqa: E731
     per = {}
     for r in trace:
-        name = r["Kernel_Name"].replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "")
+        name = short_name(r["Kernel_Name"])
         d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
         c, t = per.get(name, (0, 0.0))
         per[name] = (c + 1, t + d)
     total = sum(t for _, t in per.values())
-    out = ["# %s: job steps of bench.py (large ring, N=2^16, L=24, batch 16)" % kernel, ""]
+    ranked = sorted(per.items(), key=lambda kv: -kv[1][1])
+    targets = [k for k, _ in ranked[:n_top]] if kernel == "auto" else [kernel]
+    out = ["# Kernels of the large-ring job step (N=2^16, L=24, batch 16): %s" % ", ".join(targets), ""]
     out.append("Commands (from the repository root on the GPU box, after `export TMPDIR=/tmp`):")
     out.append("")
     for c in commands:
@@ -173,64 +189,62 @@ def summarize(trace_dir, fetch_dir, write_dir, kernel, kid, commands):
     out.append("")
     out.append("| kernel | calls | total ms | avg us | share |")
     out.append("|---|---|---|---|---|")
-    for name, (c, t) in sorted(per.items(), key=lambda kv: -kv[1][1])[:14]:
+    for name, (c, t) in ranked[:14]:
         out.append("| %s | %d | %.2f | %.1f | %.1f%% |" % (name, c, t / 1e3, t / c, 100 * t / total))
-    if kernel == "auto":
-        kernel = max(per, key=lambda k: per[k][1])
-        out[0] = "# %s: job steps of bench.py (large ring, N=2^16, L=24, batch 16)" % kernel
-        if kernel.startswith("k_ntt_pass<"):
-            kid = 1 if kernel.split(",")[2].strip() == "true" else 0
-    short = kernel.replace("void ", "")
-    tgt = [v for k, v in per.items() if k == short]
-    avg_us = tgt[0][1] / tgt[0][0] if tgt else None
 
-    def per_dispatch(dirpath, counter):
-        rows = [r for r in _csv_rows(_find(dirpath, "counter_collection.csv"))]
-        rows = _step_dispatches(rows, "Dispatch_Id", "Start_Timestamp")
+    def per_dispatch(dirpath, counter, target):
+        rows = _step_dispatches(_csv_rows(_find(dirpath, "counter_collection.csv")), "Dispatch_Id", "Start_Timestamp")
         vals, cal = [], []
         for r in rows:
             if r.get("Counter_Name") != counter:
                 continue
             v = float(r["Counter_Value"])
-            if short in r["Kernel_Name"]:
+            name = short_name(r["Kernel_Name"])
+            if name == target:
                 vals.append(v)
-            elif "k_copy_rows_b" in r["Kernel_Name"]:
+            elif name == "k_copy_rows_b":
                 cal.append((v, 8.0 * float(r["Grid_Size"])))
         return vals, cal
 
-    fetch, fcal = per_dispatch(fetch_dir, "FETCH_SIZE")
-    valu, _ = per_dispatch(fetch_dir, "SQ_INSTS_VALU")
-    write, wcal = per_dispatch(write_dir, "WRITE_SIZE")
-    f_factor = sum(b for _, b in fcal) / (1024.0 * sum(v for v, _ in fcal)) if fcal else None
-    w_factor = sum(b for _, b in wcal) / (1024.0 * sum(v for v, _ in wcal)) if wcal else None
-    rec = {
-        "kernel": kernel,
-        "source_sha256": source_sha(kid),
-        "avg_launch_us": avg_us,
-        "fetch_kib_per_launch": sum(fetch) / len(fetch) if fetch else None,
-        "write_kib_per_launch": sum(write) / len(write) if write else None,
-        "fetch_calibration": f_factor,
-        "write_calibration": w_factor,
-        "valu_insts_per_launch": sum(valu) / len(valu) if valu else None,
-    }
-    if None not in (rec["fetch_kib_per_launch"], rec["write_kib_per_launch"], f_factor, w_factor):
-        rec["traffic_bytes_per_launch"] = 1024.0 * (rec["fetch_kib_per_launch"] * f_factor +
-                                                    rec["write_kib_per_launch"] * w_factor)
     out.append("")
-    out.append("Counters of %s over the same dispatches (%d with FETCH_SIZE, %d with WRITE_SIZE):" %
-               (kernel, len(fetch), len(write)))
+    out.append("Counters over the same dispatches, per launch (calibration factors: known bytes of k_copy_rows_b, a "
+               "plain copy of 8 bytes read and 8 written per work-item, divided by 1024 x its counted KiB; traffic = "
+               "1024 x (fetch x fetch factor + write x write factor); on this box FETCH_SIZE counts half the bytes "
+               "the copy reads, factor 2.0, and WRITE_SIZE is exact, factor 1.0):")
     out.append("")
-    for k in ("avg_launch_us", "fetch_kib_per_launch", "write_kib_per_launch", "fetch_calibration",
-              "write_calibration", "traffic_bytes_per_launch", "valu_insts_per_launch"):
-        if rec.get(k) is not None:
-            out.append("- %s: %.6g" % (k, rec[k]))
+    out.append("| kernel | avg us | fetch KiB | write KiB | traffic MB | VALU insts |")
+    out.append("|---|---|---|---|---|---|")
+    recs = []
+    for target in targets:
+        fetch, fcal = per_dispatch(fetch_dir, "FETCH_SIZE", target)
+        valu, _ = per_dispatch(fetch_dir, "SQ_INSTS_VALU", target)
+        write, wcal = per_dispatch(write_dir, "WRITE_SIZE", target)
+        f_factor = sum(b for _, b in fcal) / (1024.0 * sum(v for v, _ in fcal)) if fcal else None
+        w_factor = sum(b for _, b in wcal) / (1024.0 * sum(v for v, _ in wcal)) if wcal else None
+        c, t = per.get(target, (0, 0.0))
+        rec = {
+            "kernel": target,
+            "source_sha256": source_sha(family_of(target)),
+            "avg_launch_us": t / c if c else None,
+            "fetch_kib_per_launch": sum(fetch) / len(fetch) if fetch else None,
+            "write_kib_per_launch": sum(write) / len(write) if write else None,
+            "fetch_calibration": f_factor,
+            "write_calibration": w_factor,
+            "valu_insts_per_launch": sum(valu) / len(valu) if valu else None,
+        }
+        if None not in (rec["fetch_kib_per_launch"], rec["write_kib_per_launch"], f_factor, w_factor):
+            rec["traffic_bytes_per_launch"] = 1024.0 * (rec["fetch_kib_per_launch"] * f_factor +
+                                                        rec["write_kib_per_launch"] * w_factor)
+        fmt = lambda v, f: (f % v) if v is not None else "-"  # noqa: E731
+        out.append("| %s | %s | %s | %s | %s | %s |" % (
+            target, fmt(rec["avg_launch_us"], "%.1f"), fmt(rec["fetch_kib_per_launch"], "%.0f"),
+            fmt(rec["write_kib_per_launch"], "%.0f"),
+            fmt(rec.get("traffic_bytes_per_launch") and rec["traffic_bytes_per_launch"] / 1e6, "%.1f"),
+            fmt(rec["valu_insts_per_launch"], "%.4g")))
+        recs.append(rec)
     out.append("")
-    out.append("Calibration factors: known bytes of k_copy_rows_b (a plain copy, 8 bytes read and 8 written per "
-               "work-item) divided by 1024 x its counted KiB; traffic = 1024 x (fetch x fetch factor + write x "
-               "write factor).  On this box FETCH_SIZE counts half the bytes the copy reads (factor 2.0) while "
-               "WRITE_SIZE is exact (factor 1.0).")
-    out.append("")
-    out.append("pft-profile: " + json.dumps(rec))
+    for rec in recs:
+        out.append("pft-profile: " + json.dumps(rec))
     return "\n".join(out) + "\n"
 
 
@@ -252,17 +266,21 @@ def parse():
                     help="kernel the --summarize counters are collected for; auto = the longest in the trace")
     ap.add_argument("--family", type=int, default=0)
     ap.add_argument("--commands", nargs="*", default=[])
-    ap.add_argument("--tuning-in", help="JSON table of NTT schedules (from --tuning-out) to use instead of tuning")
+    ap.add_argument("--tuning-in", default=os.path.join(ROOT, "paper_1908_06972_amd", "tuning",
+                                                        "large_ring_n16_l24.json"),
+                    help="JSON table of NTT schedules (from --tuning-out) to use instead of tuning; the default is the "
+                         "table the autotuner produced for this workload, so kernel choices repeat run to run")
+    ap.add_argument("--retune", action="store_true", help="ignore --tuning-in and let the autotuner choose")
     ap.add_argument("--tuning-out", help="write the NTT schedules the run used (JSON)")
     return ap.parse_args()
 
 
-def prof_top_variant(ctx, kid):
-    """(variant, total ms, launches, bytes, ops) of the instantiation of
-    family kid with the largest total time since prof_enable."""
+def prof_variants(ctx, kid):
+    """[(variant, total ms, launches, bytes, ops)] of every instantiation of
+    family kid timed since prof_enable, largest total first."""
     import ctypes
     from paper_1908_06972_amd import native as N
-    n = 16
+    n = 64
     var = (ctypes.c_uint32 * n)()
     ms = (ctypes.c_double * n)()
     cnt = (ctypes.c_uint64 * n)()
@@ -271,9 +289,7 @@ def prof_top_variant(ctx, kid):
     k = ctx.lib.pft_prof_read_variants(ctx.handle, kid, n, var, ms, cnt, by, op)
     if k < 0:
         N.check(k)
-    if k == 0:
-        return 0, 0.0, 0, 0.0, 0.0
-    return var[0], ms[0], cnt[0], by[0], op[0]
+    return [(var[i], ms[i], cnt[i], by[i], op[i]) for i in range(min(k, n))]
 
 
 def prof_read(ctx, kid):
@@ -474,7 +490,7 @@ def main():
 
     lp, ctx, kd, cts = setup(args.batch)
     sync = torch.cuda.synchronize
-    if args.tuning_in:
+    if args.tuning_in and not args.retune and os.path.exists(args.tuning_in):
         with open(args.tuning_in) as fh:
             ctx.ntt_tuning_import([(e[0], e[1], (tuple(e[2]), int(e[3]))) for e in json.load(fh)])
         log("NTT schedules imported from %s" % args.tuning_in)
@@ -500,12 +516,20 @@ def main():
     job_step(ctx, cts)
     sync()
     totals = {k: prof_read(ctx, k) for k in range(len(FAMILIES))}
+    kernels = [(k,) + v for k in range(len(FAMILIES)) for v in prof_variants(ctx, k)]
     prof_enable(ctx, 0)
     step_total = sum(v[0] for v in totals.values())
-    dom = max(totals, key=lambda k: totals[k][0])
     log("kernel families over one step: " + ", ".join(
         "%s %.1fms (%d)" % (FAMILIES[k], v[0], v[1]) for k, v in sorted(totals.items(), key=lambda kv: -kv[1][0])
         if v[1]))
+    # the dominant kernel: the single instantiation with the largest total time
+    kernels.sort(key=lambda r: -r[2])
+    dom, dom_variant = kernels[0][0], kernels[0][1]
+    top_kernels = [{"kernel": kernel_name(k, v), "share_of_step": round(ms / step_total, 3), "launches": c,
+                    "avg_launch_us": round(1000.0 * ms / max(c, 1), 1),
+                    "alg_gbs": round(by / (ms * 1e-3) / 1e9, 1) if ms > 0 else None}
+                   for k, v, ms, c, by, op in kernels[:6]]
+    log("top kernels: " + ", ".join("%s %.1f%%" % (t["kernel"], 100 * t["share_of_step"]) for t in top_kernels))
 
     for i in range(args.warmup):
         job_step(ctx, cts)
@@ -527,7 +551,8 @@ def main():
     elapsed = time.perf_counter() - t0
     roctx.pause()
     dom_ms = prof_read(ctx, dom)[0]
-    variant, d_ms, d_cnt, d_bytes, d_ops = prof_top_variant(ctx, dom)
+    rows = [r for r in prof_variants(ctx, dom) if r[0] == dom_variant] or [(dom_variant, 0.0, 0, 0.0, 0.0)]
+    variant, d_ms, d_cnt, d_bytes, d_ops = rows[0]
     prof_enable(ctx, 0)
 
     hmults = args.batch * CHAIN_DEPTH * args.steps
@@ -604,9 +629,10 @@ def main():
         "launches": d_cnt,
         "alg_bytes_per_launch": d_bytes / max(d_cnt, 1),
         "alg_butterflies_per_launch": d_ops / max(d_cnt, 1),
-        "share_of_step": round(totals[dom][0] / step_total, 3) if step_total else None,
+        "family_share_of_step": round(totals[dom][0] / step_total, 3) if step_total else None,
         "kernel_share_of_family": round(d_ms / dom_ms, 3) if dom_ms else None,
         "alu": alu,
+        "top_kernels": top_kernels,
     }
 
     tuning = save_tuning()

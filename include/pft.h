@@ -327,8 +327,9 @@ void pft_graph_destroy(pft_graph* graph);
  * operations (butterflies for the transforms, 64-bit modular multiply-adds
  * otherwise) of those launches.  Families: 0 forward NTT pass, 1 inverse NTT
  * pass, 2 ModUp base conversion, 3 key inner product, 4 ModDown base
- * conversion, 5 ModDown final scaling, 6 HMUL tensor, 7 automorphism,
- * 8 rescale, 9 other elementwise. */
+ * conversion, 5 ModDown final scaling (kept as an index; it now runs as
+ * the epilogue of the forward NTT pass that produces it, family 0), 6 HMUL
+ * tensor, 7 automorphism, 8 rescale, 9 other elementwise. */
 int pft_prof_enable(pft_ctx* ctx, uint32_t mask);
 int pft_prof_read(pft_ctx* ctx, uint32_t kid, double* total_ms, uint64_t* launches, double* bytes, double* ops);
 /* Per-instantiation totals of family kid since pft_prof_enable, largest total
@@ -336,8 +337,9 @@ int pft_prof_read(pft_ctx* ctx, uint32_t kid, double* total_ms, uint64_t* launch
  * bytes, ops); returns the number of distinct variants.  variant 0: the
  * family's single kernel; NTT passes (families 0 and 1): 1 + (radix | 32 if a
  * column pass | 64 if the transform's final pass | 128 if staged | 256 if 8
- * residues per thread), naming k_ntt_pass<radix, log2 residues per thread,
- * inverse, column, final, staged>.  Any output may be NULL. */
+ * residues per thread | 512 if the pass finishes ModDown), naming
+ * k_ntt_pass<radix, log2 residues per thread, inverse, column, final, staged,
+ * ModDown epilogue>.  Any output may be NULL. */
 int pft_prof_read_variants(pft_ctx* ctx, uint32_t kid, uint32_t max_count, uint32_t* variants, double* total_ms,
                            uint64_t* launches, double* bytes, double* ops);
 

@@ -607,12 +607,12 @@ static NttSchedule ntt_tune(pft_ctx* c, bool inverse, uint32_t cls) {
     }
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) {
-        hipFree(buf);
+        (void)hipFree(buf);
         return cand[0];
     }
     if (hipEventCreate(&e1) != hipSuccess) {
-        hipEventDestroy(e0);
-        hipFree(buf);
+        (void)hipEventDestroy(e0);
+        (void)hipFree(buf);
         return cand[0];
     }
     std::vector<float> med(nc, 1e30f);
@@ -651,10 +651,10 @@ static NttSchedule ntt_tune(pft_ctx* c, bool inverse, uint32_t cls) {
                 break;
             }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    hipStreamSynchronize(c->stream);
-    hipFree(buf);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(buf);
     return best;
 }
 
@@ -670,8 +670,10 @@ static NttSchedule ntt_schedule(pft_ctx* c, bool inverse, uint64_t limbs) {
     return s;
 }
 
+// epi: forward transforms of (item, b) polynomial pairs whose final pass
+// finishes ModDown; epi->out lists every item, a launch gets its share.
 static void ntt_jobs(pft_ctx* c, const std::vector<NttJob>& jobs, uint32_t n_limbs, uint32_t split, bool inverse,
-                     uint32_t off0 = 0) {
+                     uint32_t off0 = 0, const NttEpilogue* epi = nullptr, int64_t src_delta = 0) {
     const pft_params* P = c->P;
     const NttSchedule sched = ntt_schedule(c, inverse, (uint64_t)jobs.size() * n_limbs);
     for (size_t s = 0; s < jobs.size(); s += PFT_MAX_POLYS) {
@@ -687,7 +689,15 @@ static void ntt_jobs(pft_ctx* c, const std::vector<NttJob>& jobs, uint32_t n_lim
         b.split = split;
         b.off0 = off0;
         b.off1 = P->L;
-        launch_ntt(b, c->tabs, P->log_n, inverse, sched, c->stream, hook(c));
+        b.src_delta = src_delta;
+        if (epi) {
+            NttEpilogue e = *epi;
+            for (uint32_t i = 0; i < PFT_MAX_POLYS / 2; ++i)
+                e.out[i] = s / 2 + i < PFT_MAX_POLYS / 2 ? epi->out[s / 2 + i] : nullptr;
+            launch_ntt(b, c->tabs, P->log_n, inverse, sched, c->stream, hook(c), &e);
+        } else {
+            launch_ntt(b, c->tabs, P->log_n, inverse, sched, c->stream, hook(c));
+        }
     }
 }
 
@@ -1090,12 +1100,12 @@ static void key_switch_b(pft_ctx* c, uint32_t n, WsRef ws, const KsLayout& K, ui
     const pft_params* P = c->P;
     const uint32_t lg = P->log_n, A = P->alpha, level = K.level, rows = K.rows, beta = K.beta;
     const double N = (double)P->n;
-    // d -> coefficient form
-    launch_copy_rows_b(n, ws_items(ws, n), off_d, ws_items(ws, n), K.off_dcoef, level, lg, c->stream);
+    // d -> coefficient form at off_dcoef (the first pass reads d in place;
+    // d itself stays in the NTT domain for the inner product)
     {
         std::vector<NttJob> jobs;
         for (uint32_t z = 0; z < n; ++z) jobs.push_back(NttJob{ws.base + z * ws.stride + K.off_dcoef, 255u, 0u});
-        ntt_jobs(c, jobs, level, ~0u, true);
+        ntt_jobs(c, jobs, level, ~0u, true, 0, nullptr, (int64_t)off_d - (int64_t)K.off_dcoef);
     }
     // ModUp base conversion
     {
@@ -1125,7 +1135,11 @@ static void key_switch_b(pft_ctx* c, uint32_t n, WsRef ws, const KsLayout& K, ui
         if (!last.empty()) ntt_jobs(c, last, rows - na_last, level, false);
     }
     // key inner product over level + K rows
-    timed(c, PK_KEY_INNER, 8.0 * N * ((double)beta * rows * 3 + 2.0 * rows) * n, 2.0 * N * beta * rows * n, [&] {
+    // the key is read once per launch (shared by the batch); each item reads
+    // beta inputs and writes two outputs per row
+    const double key_once = beta <= 8 ? 1.0 : (double)n;
+    timed(c, PK_KEY_INNER, 8.0 * N * ((double)beta * rows * n + 2.0 * beta * rows * key_once + 2.0 * rows * n),
+          2.0 * N * beta * rows * n, [&] {
         launch_key_inner_b(n, ws, off_d, K.off_ext, K.off_acc, key.data, level, c->kc, c->tabs, lg, c->stream);
     });
     // ModDown: special rows of both accumulators to coefficient form
@@ -1140,18 +1154,25 @@ static void key_switch_b(pft_ctx* c, uint32_t n, WsRef ws, const KsLayout& K, ui
           [&] {
               launch_moddown_conv_b(n, ws, K.off_acc, K.off_conv, level, c->kc, c->tabs, lg, c->bconv_mfma, c->stream);
           });
+    // the forward transform of conv finishes ModDown in its final pass:
+    // out_b[i] = (acc_b[i] - conv_b[i]) P^-1 (+ add_b)
     {
         std::vector<NttJob> jobs;
         for (uint32_t z = 0; z < n; ++z)
             for (uint32_t b = 0; b < 2; ++b)
                 jobs.push_back(NttJob{ws.base + z * ws.stride + K.off_conv + ((uint64_t)b * level << lg), 255u, 0u});
-        ntt_jobs(c, jobs, level, ~0u, false);
+        NttEpilogue epi{};
+        const uint64_t off_add[2] = {off_add0, off_add1};
+        for (uint32_t b = 0; b < 2; ++b) {
+            const int64_t conv0 = (int64_t)(K.off_conv + ((uint64_t)b * level << lg));
+            epi.d_acc[b] = (int64_t)(K.off_acc + ((uint64_t)b * K.rows << lg)) - conv0;
+            epi.d_add[b] = off_add[b] == PFT_NO_OFFSET ? PFT_EPI_NO_ADD : (int64_t)off_add[b] - conv0;
+        }
+        for (uint32_t z = 0; z < n; ++z) epi.out[z] = out.p[z];
+        epi.pinv = c->kc.down_pinv;
+        epi.level = level;
+        ntt_jobs(c, jobs, level, ~0u, false, 0, &epi);
     }
-    const double adds = (off_add0 != PFT_NO_OFFSET) + (off_add1 != PFT_NO_OFFSET);
-    timed(c, PK_MODDOWN_FINAL, 8.0 * N * level * (6.0 + adds) * n, 2.0 * N * level * n, [&] {
-        launch_moddown_final_b(n, ws, K.off_acc, K.off_conv, off_add0, off_add1, out, level, c->kc, c->tabs, lg,
-                               c->stream);
-    });
 }
 
 // Items of one batched call grouped into launches of at most PFT_MAX_ITEMS

@@ -378,26 +378,6 @@ __global__ __launch_bounds__(TB) void k_moddown_conv_b(WsRef ws, uint64_t off_ac
     }
 }
 
-// out_z[b][i] = (acc_b[i] - conv_b[i]) P^-1 mod q_i, plus (optionally) the
-// workspace rows at off_add0 / off_add1 ([level][N] each).
-__global__ __launch_bounds__(TB) void k_moddown_final_b(WsRef ws, uint64_t off_acc, uint64_t off_conv,
-                                                        uint64_t off_add0, uint64_t off_add1, ItemPtrs out,
-                                                        uint32_t level, KsConsts kc,
-                                                        const DevMod* __restrict__ mods, uint32_t log_n) {
-    const uint32_t k = blockIdx.x * TB + threadIdx.x;
-    const uint32_t b = blockIdx.y / level, i = blockIdx.y % level;
-    const uint32_t rows = level + kc.K;
-    const uint64_t q = mods[i].q;
-    const uint64_t* __restrict__ w = ws_item(ws);
-    const uint64_t x = w[off_acc + at(b * rows + i, log_n, k)];
-    const uint64_t c = w[off_conv + at(b * level + i, log_n, k)];
-    const TwPair pi = kc.down_pinv[i];
-    uint64_t r = shoup(x + q - c, pi.w, pi.wp, q);
-    const uint64_t off_add = b == 0 ? off_add0 : off_add1;
-    if (off_add != PFT_NO_OFFSET) r = add_mod(r, w[off_add + at(i, log_n, k)], q);
-    out.p[blockIdx.z][at(b * level + i, log_n, k)] = r;
-}
-
 // RESCALE, step 1: last_z ([2][N], coefficient form of limb level-1) ->
 // tmp_z [2][level-1][N] with ((r + h) mod q_last) - h reduced mod q_k,
 // h = (q_last - 1)/2 (mode 0, rounding) or 0 (mode 1, floor).
@@ -543,13 +523,6 @@ void launch_moddown_conv_b(uint32_t n, WsRef ws, uint64_t off_acc, uint64_t off_
     else
         hipLaunchKernelGGL(k_moddown_conv_b, grid_nk(log_n, 2, n), dim3(TB), 0, st, ws, off_acc, off_conv, level,
                            kc, t.mods, log_n);
-}
-
-void launch_moddown_final_b(uint32_t n, WsRef ws, uint64_t off_acc, uint64_t off_conv, uint64_t off_add0,
-                            uint64_t off_add1, const ItemPtrs& out, uint32_t level, const KsConsts& kc,
-                            const DevTables& t, uint32_t log_n, hipStream_t st) {
-    hipLaunchKernelGGL(k_moddown_final_b, grid_nk(log_n, 2 * level, n), dim3(TB), 0, st, ws, off_acc, off_conv,
-                       off_add0, off_add1, out, level, kc, t.mods, log_n);
 }
 
 void launch_rescale_expand_b(uint32_t n, WsRef ws, uint64_t off_last, uint64_t off_tmp, uint32_t level, uint32_t mode,

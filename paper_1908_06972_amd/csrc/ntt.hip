@@ -262,10 +262,10 @@ __device__ __forceinline__ void run_phases(uint64_t (&x)[1 << EB], uint64_t* lds
 // Limbs with DevMod::fp run the fp64 butterflies: the first pass of a
 // transform converts its u64 input, later passes exchange the doubles through
 // HBM, and the final pass writes canonical u64.  Integer limbs keep u64.
-template <int LOG_M, int EB, bool INV, bool COL, bool FINAL, bool STAGE>
+template <int LOG_M, int EB, bool INV, bool COL, bool FINAL, bool STAGE, bool EPI>
 __global__ __launch_bounds__(4096 >> EB) void k_ntt_pass(PolyBatch b, const DevMod* __restrict__ mods,
                                                          const TwPair* __restrict__ tw, uint32_t log_n, uint32_t s0,
-                                                         uint32_t first_pass) {
+                                                         uint32_t first_pass, NttEpilogue ep) {
     constexpr int M = 1 << LOG_M;
     constexpr int E = 1 << EB;          // residues per thread
     constexpr uint32_t NT = 4096 >> EB;  // threads per workgroup
@@ -308,18 +308,19 @@ __global__ __launch_bounds__(4096 >> EB) void k_ntt_pass(PolyBatch b, const DevM
 
     uint64_t x[E];
     const bool convert_in = fp && first_pass;
+    const uint64_t* src = first_pass ? data + b.src_delta : data;  // may alias data (in place)
     if constexpr (DIRECT_IN && VEC_IN) {
-        const ulonglong2* __restrict__ src = reinterpret_cast<const ulonglong2*>(data + gidx(c, (uint32_t)E * l));
+        const ulonglong2* __restrict__ srcv = reinterpret_cast<const ulonglong2*>(src + gidx(c, (uint32_t)E * l));
 #pragma unroll
         for (int e = 0; e < E / 2; ++e) {
-            const ulonglong2 v = src[e];
+            const ulonglong2 v = srcv[e];
             x[2 * e] = convert_in ? fp_from_u64(v.x) : v.x;
             x[2 * e + 1] = convert_in ? fp_from_u64(v.y) : v.y;
         }
     } else if constexpr (DIRECT_IN) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const uint64_t v = data[gidx(c, PIN::r_of(l, e))];
+            const uint64_t v = src[gidx(c, PIN::r_of(l, e))];
             x[e] = convert_in ? fp_from_u64(v) : v;
         }
     } else {
@@ -327,7 +328,7 @@ __global__ __launch_bounds__(4096 >> EB) void k_ntt_pass(PolyBatch b, const DevM
         for (int k = 0; k < E; ++k) {
             const uint32_t idx = tid + NT * k;
             const uint32_t cc = idx / M, r = idx % M;
-            const uint64_t v = data[gidx(cc, r)];
+            const uint64_t v = src[gidx(cc, r)];
             lds[lds_at<LOG_M, EB>(cc, r)] = convert_in ? fp_from_u64(v) : v;
         }
         __syncthreads();
@@ -353,7 +354,21 @@ __global__ __launch_bounds__(4096 >> EB) void k_ntt_pass(PolyBatch b, const DevM
         }
         return v;
     };
-    if constexpr (DIRECT_OUT && VEC_OUT) {
+    // store of transformed element j of this row (or the ModDown epilogue)
+    [[maybe_unused]] const uint32_t bsel = poly & 1u;
+    [[maybe_unused]] uint64_t* __restrict__ out_row =
+        EPI ? ep.out[poly >> 1] + ((size_t)(bsel * ep.level + row) << log_n) : nullptr;
+    [[maybe_unused]] const TwPair pinv = EPI ? ep.pinv[row] : TwPair{0, 0};
+    auto put = [&](size_t j, uint64_t v) {
+        if constexpr (EPI) {
+            uint64_t r = shoup(data[j + ep.d_acc[bsel]] + q - v, pinv.w, pinv.wp, q);
+            if (ep.d_add[bsel] != PFT_EPI_NO_ADD) r = add_mod(r, data[j + ep.d_add[bsel]], q);
+            out_row[j] = r;
+        } else {
+            data[j] = v;
+        }
+    };
+    if constexpr (DIRECT_OUT && VEC_OUT && !EPI) {
         ulonglong2* __restrict__ dst = reinterpret_cast<ulonglong2*>(data + gidx(c, (uint32_t)E * l));
 #pragma unroll
         for (int e = 0; e < E / 2; ++e) {
@@ -364,7 +379,7 @@ __global__ __launch_bounds__(4096 >> EB) void k_ntt_pass(PolyBatch b, const DevM
         }
     } else if constexpr (DIRECT_OUT) {
 #pragma unroll
-        for (int e = 0; e < E; ++e) data[gidx(c, POUT::r_of(l, e))] = finish(x[e]);
+        for (int e = 0; e < E; ++e) put(gidx(c, POUT::r_of(l, e)), finish(x[e]));
     } else {
         lds_write<LOG_M, PH_OUT, EB>(x, lds, c, l);
         __syncthreads();
@@ -372,22 +387,32 @@ __global__ __launch_bounds__(4096 >> EB) void k_ntt_pass(PolyBatch b, const DevM
         for (int k = 0; k < E; ++k) {
             const uint32_t idx = tid + NT * k;
             const uint32_t cc = idx / M, r = idx % M;
-            data[gidx(cc, r)] = finish(lds[lds_at<LOG_M, EB>(cc, r)]);
+            put(gidx(cc, r), finish(lds[lds_at<LOG_M, EB>(cc, r)]));
         }
     }
 }
 
 template <int LOG_M, int EB, bool INV, bool COL, bool FINAL>
 void launch_k(const PolyBatch& b, const DevTables& t, uint32_t log_n, uint32_t s0, uint32_t first_pass, bool stage,
-              hipStream_t st) {
+              const NttEpilogue* epi, hipStream_t st) {
     const dim3 grid((1u << log_n) / 4096u, b.n_polys * b.n_limbs);
     const TwPair* tw = INV ? t.tw_inv : t.tw_fwd;
+    const NttEpilogue ep = epi ? *epi : NttEpilogue{};
+    if constexpr (!INV && !COL && FINAL) {
+        // the epilogue reads acc and the addend and writes out beside the
+        // transformed value: always through the coalesced staged store
+        if (epi) {
+            hipLaunchKernelGGL((k_ntt_pass<LOG_M, EB, INV, COL, FINAL, true, true>), grid, dim3(4096 >> EB), 0, st, b,
+                               t.mods, tw, log_n, s0, first_pass, ep);
+            return;
+        }
+    }
     if (COL || stage)
-        hipLaunchKernelGGL((k_ntt_pass<LOG_M, EB, INV, COL, FINAL, true>), grid, dim3(4096 >> EB), 0, st, b, t.mods,
-                           tw, log_n, s0, first_pass);
+        hipLaunchKernelGGL((k_ntt_pass<LOG_M, EB, INV, COL, FINAL, true, false>), grid, dim3(4096 >> EB), 0, st, b,
+                           t.mods, tw, log_n, s0, first_pass, ep);
     else if constexpr (!COL)
-        hipLaunchKernelGGL((k_ntt_pass<LOG_M, EB, INV, COL, FINAL, false>), grid, dim3(4096 >> EB), 0, st, b, t.mods,
-                           tw, log_n, s0, first_pass);
+        hipLaunchKernelGGL((k_ntt_pass<LOG_M, EB, INV, COL, FINAL, false, false>), grid, dim3(4096 >> EB), 0, st, b,
+                           t.mods, tw, log_n, s0, first_pass, ep);
 }
 
 // One pass.  A column pass (low index bits remain below the window) needs at
@@ -396,21 +421,21 @@ void launch_k(const PolyBatch& b, const DevTables& t, uint32_t log_n, uint32_t s
 // going back the s0 = 0 window is.
 template <int LOG_M, bool INV>
 void launch_pass(const PolyBatch& b, const DevTables& t, uint32_t log_n, uint32_t s0, bool final_pass, bool stage,
-                 bool e8, hipStream_t st, ProfHook* g_prof) {
+                 bool e8, const NttEpilogue* epi, hipStream_t st, ProfHook* g_prof) {
     const int kid = INV ? PK_NTT_INV : PK_NTT_FWD;
     const uint32_t first_pass = INV ? (s0 + LOG_M == log_n) : (s0 == 0);
     const bool col = s0 + LOG_M < log_n;
-    const bool staged = col || stage;
+    const bool staged = col || stage || (epi && !INV && final_pass);
     if (g_prof) g_prof->begin(kid);
     auto go = [&](auto eb) {
         constexpr int EB = decltype(eb)::value;
         if (col) {
-            if constexpr (LOG_M <= 8) launch_k<LOG_M, EB, INV, true, INV>(b, t, log_n, s0, first_pass, true, st);
+            if constexpr (LOG_M <= 8) launch_k<LOG_M, EB, INV, true, INV>(b, t, log_n, s0, first_pass, true, nullptr, st);
         } else if (final_pass) {
             if constexpr (!INV || LOG_M == 12)
-                launch_k<LOG_M, EB, INV, false, true>(b, t, log_n, s0, first_pass, stage, st);
+                launch_k<LOG_M, EB, INV, false, true>(b, t, log_n, s0, first_pass, stage, epi, st);
         } else {
-            if constexpr (INV) launch_k<LOG_M, EB, INV, false, false>(b, t, log_n, s0, first_pass, stage, st);
+            if constexpr (INV) launch_k<LOG_M, EB, INV, false, false>(b, t, log_n, s0, first_pass, stage, nullptr, st);
         }
     };
     if (e8)
@@ -420,23 +445,29 @@ void launch_pass(const PolyBatch& b, const DevTables& t, uint32_t log_n, uint32_
     if (g_prof) {
         const double elems = (double)b.n_polys * b.n_limbs * (double)(1u << log_n);
         // read + write every residue once; N/2 butterflies per stage
-        const uint32_t variant =
-            1u + (LOG_M | (col ? 32u : 0u) | (final_pass ? 64u : 0u) | (staged ? 128u : 0u) | (e8 ? 256u : 0u));
-        g_prof->end(kid, 16.0 * elems, 0.5 * elems * LOG_M, variant);
+        const bool fused = epi && !INV && final_pass && !col;
+        const uint32_t variant = 1u + (LOG_M | (col ? 32u : 0u) | (final_pass ? 64u : 0u) | (staged ? 128u : 0u) |
+                                       (e8 ? 256u : 0u) | (fused ? 512u : 0u));
+        // the ModDown epilogue reads acc (and the addend) and writes out in
+        // place of the transform's own store
+        const double bytes = fused ? elems * (24.0 + (epi->d_add[0] != PFT_EPI_NO_ADD ? 4.0 : 0.0) +
+                                              (epi->d_add[1] != PFT_EPI_NO_ADD ? 4.0 : 0.0))
+                                   : 16.0 * elems;
+        g_prof->end(kid, bytes, 0.5 * elems * LOG_M, variant);
     }
 }
 
 template <bool INV>
 void launch_radix(uint32_t radix, const PolyBatch& b, const DevTables& t, uint32_t log_n, uint32_t s0, bool fin,
-                  bool stage, bool e8, hipStream_t st, ProfHook* prof) {
+                  bool stage, bool e8, const NttEpilogue* epi, hipStream_t st, ProfHook* prof) {
     switch (radix) {
-        case 4: launch_pass<4, INV>(b, t, log_n, s0, fin, stage, e8, st, prof); break;
-        case 6: launch_pass<6, INV>(b, t, log_n, s0, fin, stage, e8, st, prof); break;
-        case 7: launch_pass<7, INV>(b, t, log_n, s0, fin, stage, e8, st, prof); break;
-        case 8: launch_pass<8, INV>(b, t, log_n, s0, fin, stage, e8, st, prof); break;
-        case 9: launch_pass<9, INV>(b, t, log_n, s0, fin, stage, e8, st, prof); break;
-        case 10: launch_pass<10, INV>(b, t, log_n, s0, fin, stage, e8, st, prof); break;
-        case 12: launch_pass<12, INV>(b, t, log_n, s0, fin, stage, e8, st, prof); break;
+        case 4: launch_pass<4, INV>(b, t, log_n, s0, fin, stage, e8, epi, st, prof); break;
+        case 6: launch_pass<6, INV>(b, t, log_n, s0, fin, stage, e8, epi, st, prof); break;
+        case 7: launch_pass<7, INV>(b, t, log_n, s0, fin, stage, e8, epi, st, prof); break;
+        case 8: launch_pass<8, INV>(b, t, log_n, s0, fin, stage, e8, epi, st, prof); break;
+        case 9: launch_pass<9, INV>(b, t, log_n, s0, fin, stage, e8, epi, st, prof); break;
+        case 10: launch_pass<10, INV>(b, t, log_n, s0, fin, stage, e8, epi, st, prof); break;
+        case 12: launch_pass<12, INV>(b, t, log_n, s0, fin, stage, e8, epi, st, prof); break;
         default: break;
     }
 }
@@ -492,7 +523,7 @@ bool ntt_schedule_valid(uint32_t log_n, const NttSchedule& s) {
 }
 
 void launch_ntt(const PolyBatch& b, const DevTables& t, uint32_t log_n, bool inverse, const NttSchedule& s,
-                hipStream_t st, ProfHook* prof) {
+                hipStream_t st, ProfHook* prof, const NttEpilogue* epi) {
     if (b.n_polys == 0 || b.n_limbs == 0 || s.n_passes == 0 || s.n_passes > 3) return;
     uint32_t s0[4];
     uint32_t acc = 0;
@@ -505,9 +536,10 @@ void launch_ntt(const PolyBatch& b, const DevTables& t, uint32_t log_n, bool inv
     const bool e8 = (s.flags & NTT_E8) != 0;
     if (!inverse) {
         for (uint32_t p = 0; p < s.n_passes; ++p)
-            launch_radix<false>(s.radix[p], b, t, log_n, s0[p], p + 1 == s.n_passes, stage, e8, st, prof);
+            launch_radix<false>(s.radix[p], b, t, log_n, s0[p], p + 1 == s.n_passes, stage, e8,
+                                p + 1 == s.n_passes ? epi : nullptr, st, prof);
     } else {
         for (uint32_t p = s.n_passes; p-- > 0;)
-            launch_radix<true>(s.radix[p], b, t, log_n, s0[p], p == 0, stage, e8, st, prof);
+            launch_radix<true>(s.radix[p], b, t, log_n, s0[p], p == 0, stage, e8, nullptr, st, prof);
     }
 }

@@ -46,7 +46,9 @@ struct TwPair {
 // A set of RNS polynomials processed by one NTT launch.  Limb i (0 <= i <
 // n_limbs) of polynomial p sits at row r = i + (i >= gap_at[p] ? gap_len[p] : 0)
 // of ptr[p] (rows are N words apart); row r is reduced modulo modulus index
-// r < split ? off0 + r : off1 + (r - split).
+// r < split ? off0 + r : off1 + (r - split).  The first pass of a transform
+// reads each row from src_delta words past it (0: in place) and writes it in
+// place.
 struct PolyBatch {
     uint64_t* ptr[PFT_MAX_POLYS];
     uint8_t gap_at[PFT_MAX_POLYS];
@@ -54,6 +56,7 @@ struct PolyBatch {
     uint32_t n_polys;
     uint32_t n_limbs;
     uint32_t split, off0, off1;
+    int64_t src_delta;
 };
 
 __device__ __forceinline__ uint32_t pb_row(const PolyBatch& b, uint32_t p, uint32_t i) {

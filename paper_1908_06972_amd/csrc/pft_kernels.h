@@ -37,11 +37,26 @@ struct NttSchedule {
     uint8_t radix[4];
     uint32_t flags;
 };
+// Epilogue of a forward transform's final pass that finishes ModDown in
+// place of storing the transform: for transformed row i of polynomial p =
+// 2 z + b (z the item, b in {0, 1}) it writes
+//   out_z[b][i] = (acc - conv) P^-1 mod q_i (+ add)
+// where conv is the transformed value and acc / add sit at word offsets
+// d_acc[b] / d_add[b] from it (d_add[b] = PFT_EPI_NO_ADD: no addend).
+#define PFT_EPI_NO_ADD INT64_MIN
+struct NttEpilogue {
+    int64_t d_acc[2];
+    int64_t d_add[2];
+    uint64_t* out[PFT_MAX_POLYS / 2];  // per item of the launch: [2][level][N]
+    const TwPair* pinv;                // [L]: P^-1 mod q_i
+    uint32_t level;
+};
 bool ntt_supported(uint32_t log_n);
 int ntt_candidates(uint32_t log_n, NttSchedule* out, int max_out);
 bool ntt_schedule_valid(uint32_t log_n, const NttSchedule& s);
+// epi (forward only): finish ModDown in the final pass instead of storing.
 void launch_ntt(const PolyBatch& b, const DevTables& t, uint32_t log_n, bool inverse, const NttSchedule& s,
-                hipStream_t st, ProfHook* prof = nullptr);
+                hipStream_t st, ProfHook* prof = nullptr, const NttEpilogue* epi = nullptr);
 
 // ---- elementwise kernels (ckks.hip) --------------------------------------
 // Signed integer polynomials x ([n_polys][N] int64, device) reduced into
@@ -114,10 +129,6 @@ void launch_key_inner_b(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, 
 // acc special rows (coefficient form) -> conv [2][level][N] (coefficient form)
 void launch_moddown_conv_b(uint32_t n, WsRef ws, uint64_t off_acc, uint64_t off_conv, uint32_t level,
                            const KsConsts& kc, const DevTables& t, uint32_t log_n, bool mfma, hipStream_t st);
-// out_z[b][i] = (acc_b[i] - conv_b[i]) P^-1 (+ ws rows at off_add_b unless PFT_NO_OFFSET)
-void launch_moddown_final_b(uint32_t n, WsRef ws, uint64_t off_acc, uint64_t off_conv, uint64_t off_add0,
-                            uint64_t off_add1, const ItemPtrs& out, uint32_t level, const KsConsts& kc,
-                            const DevTables& t, uint32_t log_n, hipStream_t st);
 // RESCALE pieces (see ckks.hip)
 void launch_rescale_expand_b(uint32_t n, WsRef ws, uint64_t off_last, uint64_t off_tmp, uint32_t level, uint32_t mode,
                              const DevTables& t, uint32_t log_n, hipStream_t st);
