@@ -461,9 +461,16 @@ static int build_tables(pft_ctx* c) {
     std::vector<BconvRed> red(L + K);
     for (uint32_t mi = 0; mi < L + K; ++mi) {
         const uint64_t m = P->mods[mi];
-        red[mi].c32 = pair(powmod(2 % m, 32, m), m);
-        red[mi].one_p = shoup_companion(1 % m, m);
-        red[mi].cc = (powmod(2 % m, 45, m) + powmod(2 % m, 77, m)) % m;
+        const uint64_t c32 = powmod(2 % m, 32, m);
+        red[mi].m = m;
+        red[mi].negm = 0 - m;
+        red[mi].cq0 = m << 30;
+        red[mi].md = (double)m;
+        red[mi].minv = 1.0 / (double)m;
+        red[mi].c32 = (double)c32;
+        red[mi].c32q = (double)c32 / (double)m;
+        red[mi].fp = ntt_fp(m) ? 1u : 0u;
+        red[mi].pad = 0;
     }
 
     TwPair *d_hatinv, *d_phatinv, *d_pinv;
@@ -712,11 +719,11 @@ static void ntt_rows(pft_ctx* c, uint64_t* base, uint32_t n_polys, uint32_t rows
 
 // Runs f (one kernel launch) bracketed by profiling events when enabled.
 template <typename F>
-static void timed(pft_ctx* c, int kid, double bytes, double ops, F&& f) {
+static void timed(pft_ctx* c, int kid, double bytes, double ops, F&& f, uint32_t variant = 0) {
     ProfHook* h = hook(c);
     if (h) h->begin(kid);
     f();
-    if (h) h->end(kid, bytes, ops);
+    if (h) h->end(kid, bytes, ops, variant);
 }
 
 // ---------------------------------------------------------------------------
@@ -1117,7 +1124,8 @@ static void key_switch_b(pft_ctx* c, uint32_t n, WsRef ws, const KsLayout& K, ui
             macs += (double)(rows - na) * na + na;
         }
         timed(c, PK_MODUP, 8.0 * N * (rd + wr) * n, N * macs * n,
-              [&] { launch_modup_b(n, ws, K.off_dcoef, K.off_ext, level, c->kc, c->tabs, lg, c->bconv_mfma, c->stream); });
+              [&] { launch_modup_b(n, ws, K.off_dcoef, K.off_ext, level, c->kc, c->tabs, lg, c->bconv_mfma, c->stream); },
+              c->bconv_mfma ? (std::min(P->alpha, level) + 1) / 2 : 0);
     }
     // ModUp transforms: all digits of all items, full digits and the ragged
     // last digit in separate launches (different limb counts)
@@ -1153,7 +1161,8 @@ static void key_switch_b(pft_ctx* c, uint32_t n, WsRef ws, const KsLayout& K, ui
     timed(c, PK_MODDOWN_CONV, 8.0 * N * (2.0 * P->K + 2.0 * level) * n, 2.0 * N * P->K * level * n,
           [&] {
               launch_moddown_conv_b(n, ws, K.off_acc, K.off_conv, level, c->kc, c->tabs, lg, c->bconv_mfma, c->stream);
-          });
+          },
+          c->bconv_mfma ? (P->K + 1) / 2 : 0);
     // the forward transform of conv finishes ModDown in its final pass:
     // out_b[i] = (acc_b[i] - conv_b[i]) P^-1 (+ add_b)
     {

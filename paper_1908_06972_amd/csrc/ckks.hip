@@ -7,6 +7,8 @@
 // coalesced row segment of the limb-major [poly][limb][N] layout.  Batched
 // kernels take the ciphertext index from blockIdx.z; per-ciphertext
 // intermediates live in a workspace at base + z * stride (WsRef).
+#include <type_traits>
+
 #include "pft_device.h"
 #include "pft_kernels.h"
 
@@ -166,20 +168,31 @@ __device__ __forceinline__ long split_digits(uint64_t v) {
     return (long)((v + 0x8080808080808080ull) ^ 0x8080808080808080ull);
 }
 
-// sum_b 256^b Z_b mod m for the 8 digit sums of one target (|Z_b| < 2^21)
-__device__ __forceinline__ uint64_t fold_digits(const int (&z)[8], const BconvRed& rc, uint64_t m, uint32_t bits) {
-    int64_t lo = 0, hi = 0;
-#pragma unroll
-    for (int b = 3; b >= 0; --b) {
-        lo = lo * 256 + z[b];
-        hi = hi * 256 + z[4 + b];
+// sum_b 256^b Z_b mod m for the 8 digit sums of one target (|Z_b| < 2^21).
+// lo = sum_{b<4} 256^b Z_b and hi = sum_{b>=4} 256^(b-4) Z_b are integers
+// below 2^46 in magnitude, exact in fp64; the value is lo + 2^32 hi.
+//  m < 2^50: lo + fmulmod(hi, 2^32 mod m) and one fp64 reduction (the error
+//    analysis of fmulmod / freduce applies with |hi| < 2^46).
+//  m >= 2^50: the quotient k = round((lo + 2^32 hi) / m) has |k| < 2^29 and
+//    comes from fp64 (error below 2^-21); the remainder is formed exactly in
+//    integers mod 2^64 as (lo + 2^32 hi + 2^30 m) - (k + 2^30) m, which lies
+//    within (1/2 + 2^-21) m of zero, then one conditional add of m.
+__device__ __forceinline__ uint64_t fold_digits(const int (&z)[8], const BconvRed& rc) {
+#pragma clang fp contract(off)
+    const double lo = __builtin_fma((double)(z[3] * 256 + z[2]), 65536.0, (double)(z[1] * 256 + z[0]));
+    const double hi = __builtin_fma((double)(z[7] * 256 + z[6]), 65536.0, (double)(z[5] * 256 + z[4]));
+    if (rc.fp) {
+        double y = freduce(lo + fmulmod(hi, rc.c32, rc.c32q, rc.md), rc.md, rc.minv);
+        y = y < 0.0 ? y + rc.md : y;  // [0, m)
+        return as_u(y + 0x1p52) ^ 0x4330000000000000ull;
     }
-    uint64_t l = (uint64_t)(lo + (1ll << 45));  // in [0, 2^46)
-    const uint64_t h = (uint64_t)(hi + (1ll << 45));
-    if (bits <= 46) l = shoup(l, 1, rc.one_p, m);
-    uint64_t y = l + shoup(h, rc.c32.w, rc.c32.wp, m);  // < 2m
-    y = y >= m ? y - m : y;
-    return y >= rc.cc ? y - rc.cc : y + m - rc.cc;
+    const double s = __builtin_fma(hi, 0x1p32, lo);
+    const uint32_t k = (uint32_t)__builtin_fma(s, rc.minv, 0x1p30 + 0.5);  // floor: k + 2^30
+    // two's complement of an integer |v| < 2^51 in the low bits of v + 1.5 2^52
+    const uint64_t lo64 = as_u(lo + 0x1.8p52) - 0x4338000000000000ull;
+    const uint32_t hi32 = (uint32_t)as_u(hi + 0x1.8p52);
+    const uint64_t r = lo64 + ((uint64_t)hi32 << 32) + rc.cq0 + (uint64_t)k * rc.negm;
+    return (int64_t)r < 0 ? r + rc.m : r;
 }
 
 // the two targets of this lane in accumulator tile acc: u = 0, 1
@@ -192,8 +205,21 @@ __device__ __forceinline__ void tile_digits(const v16i& acc, int (&z)[8]) {
     }
 }
 
+// the fold constants of every modulus (at most 64) into LDS, so that the
+// per-target reads in the fold are short-latency
+__device__ __forceinline__ void stage_red(const KsConsts& kc, BconvRed* s_red) {
+    const uint32_t words = (kc.L + kc.K) * (uint32_t)(sizeof(BconvRed) / 8);
+    const uint64_t* src = reinterpret_cast<const uint64_t*>(kc.red);
+    uint64_t* dst = reinterpret_cast<uint64_t*>(s_red);
+    for (uint32_t w = threadIdx.x; w < words; w += TB) dst[w] = src[w];
+    __syncthreads();
+}
+
 // ModUp on the matrix cores: same inputs and outputs as k_modup_b.  A wave
-// converts 32 coefficients of digit j = blockIdx.y to every target row.
+// converts 32 coefficients of digit j = blockIdx.y to every target row.  NKB
+// = ceil(alpha' / 2) k-blocks of 16 for alpha' = min(alpha, level); a digit
+// with fewer limbs has zero input digits in the unused k positions.
+template <uint32_t NKB>
 __global__ __launch_bounds__(TB) void k_modup_mfma_b(WsRef ws, uint64_t off_d, uint64_t off_ext, uint32_t level,
                                                      KsConsts kc, const DevMod* __restrict__ mods, uint32_t log_n) {
     const uint32_t lane = threadIdx.x & 63u, half = lane >> 5;
@@ -202,12 +228,11 @@ __global__ __launch_bounds__(TB) void k_modup_mfma_b(WsRef ws, uint64_t off_d, u
     const uint32_t i0 = j * kc.alpha;
     const uint32_t na = min(i0 + kc.alpha, level) - i0;
     const uint32_t rows = level + kc.K, T = rows - na;
-    const uint32_t nkb = (na + 1) / 2;
     const size_t cbase = ((size_t)(level - 1) * kc.dnum + j) * kc.alpha;
     const uint64_t* __restrict__ d = ws_item(ws) + off_d;
-    long bop[PFT_MAX_ALPHA / 2];
+    long bop[NKB];
 #pragma unroll
-    for (uint32_t kb = 0; kb < PFT_MAX_ALPHA / 2; ++kb) {
+    for (uint32_t kb = 0; kb < NKB; ++kb) {
         const uint32_t ii = 2 * kb + half;
         uint64_t x = 0;
         if (ii < na) {
@@ -219,13 +244,21 @@ __global__ __launch_bounds__(TB) void k_modup_mfma_b(WsRef ws, uint64_t off_d, u
     const uint64_t* __restrict__ aop =
         kc.up_aop + ((size_t)(level - 1) * kc.dnum + j) * kc.up_rt * kc.up_kb * 64 + lane;
     uint64_t* __restrict__ outj = ws_item(ws) + off_ext + ((size_t)j * rows << log_n);
-    for (uint32_t rt = 0; rt * 4 < T; ++rt) {
-        v16i acc = {};
+    __shared__ BconvRed s_red[64];
+    stage_red(kc, s_red);
+    // the constant digits of tile rt + 1 load while tile rt is folded
+    long av[NKB];
 #pragma unroll
-        for (uint32_t kb = 0; kb < PFT_MAX_ALPHA / 2; ++kb)
-            if (kb < nkb)
-                acc = __builtin_amdgcn_mfma_i32_32x32x16_i8((long)aop[(rt * kc.up_kb + kb) * 64], bop[kb], acc, 0,
-                                                            0, 0);
+    for (uint32_t kb = 0; kb < NKB; ++kb) av[kb] = (long)aop[kb * 64];
+    for (uint32_t rt = 0; rt * 4 < T; ++rt) {
+        const v16i zero = {};
+        v16i acc = __builtin_amdgcn_mfma_i32_32x32x16_i8(av[0], bop[0], zero, 0, 0, 0);
+#pragma unroll
+        for (uint32_t kb = 1; kb < NKB; ++kb) acc = __builtin_amdgcn_mfma_i32_32x32x16_i8(av[kb], bop[kb], acc, 0, 0, 0);
+        if ((rt + 1) * 4 < T) {
+#pragma unroll
+            for (uint32_t kb = 0; kb < NKB; ++kb) av[kb] = (long)aop[((rt + 1) * kc.up_kb + kb) * 64];
+        }
         int z[8];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
@@ -234,14 +267,15 @@ __global__ __launch_bounds__(TB) void k_modup_mfma_b(WsRef ws, uint64_t off_d, u
             if (tt < T) {
                 const uint32_t t = tt < i0 ? tt : tt + na;
                 const uint32_t mi = t < level ? t : kc.L + (t - level);
-                outj[at(t, log_n, n)] = fold_digits(z, kc.red[mi], mods[mi].q, mods[mi].bits);
+                outj[at(t, log_n, n)] = fold_digits(z, s_red[mi]);
             }
         }
     }
 }
 
 // ModDown conversion on the matrix cores: same inputs and outputs as
-// k_moddown_conv_b (poly b = blockIdx.y).
+// k_moddown_conv_b (poly b = blockIdx.y); NKB = ceil(K / 2).
+template <uint32_t NKB>
 __global__ __launch_bounds__(TB) void k_moddown_mfma_b(WsRef ws, uint64_t off_acc, uint64_t off_conv, uint32_t level,
                                                        KsConsts kc, const DevMod* __restrict__ mods,
                                                        uint32_t log_n) {
@@ -249,11 +283,10 @@ __global__ __launch_bounds__(TB) void k_moddown_mfma_b(WsRef ws, uint64_t off_ac
     const uint32_t n = (blockIdx.x * (TB / 64) + (threadIdx.x >> 6)) * 32 + (lane & 31u);
     const uint32_t b = blockIdx.y;
     const uint32_t rows = level + kc.K;
-    const uint32_t nkb = (kc.K + 1) / 2;
     const uint64_t* __restrict__ acc_in = ws_item(ws) + off_acc;
-    long bop[PFT_MAX_K / 2];
+    long bop[NKB];
 #pragma unroll
-    for (uint32_t kb = 0; kb < PFT_MAX_K / 2; ++kb) {
+    for (uint32_t kb = 0; kb < NKB; ++kb) {
         const uint32_t k = 2 * kb + half;
         uint64_t x = 0;
         if (k < kc.K) {
@@ -264,19 +297,26 @@ __global__ __launch_bounds__(TB) void k_moddown_mfma_b(WsRef ws, uint64_t off_ac
     }
     const uint64_t* __restrict__ aop = kc.down_aop + lane;
     uint64_t* __restrict__ conv = ws_item(ws) + off_conv;
-    for (uint32_t rt = 0; rt * 4 < level; ++rt) {
-        v16i acc = {};
+    __shared__ BconvRed s_red[64];
+    stage_red(kc, s_red);
+    long av[NKB];
 #pragma unroll
-        for (uint32_t kb = 0; kb < PFT_MAX_K / 2; ++kb)
-            if (kb < nkb)
-                acc = __builtin_amdgcn_mfma_i32_32x32x16_i8((long)aop[(rt * kc.down_kb + kb) * 64], bop[kb], acc, 0,
-                                                            0, 0);
+    for (uint32_t kb = 0; kb < NKB; ++kb) av[kb] = (long)aop[kb * 64];
+    for (uint32_t rt = 0; rt * 4 < level; ++rt) {
+        const v16i zero = {};
+        v16i acc = __builtin_amdgcn_mfma_i32_32x32x16_i8(av[0], bop[0], zero, 0, 0, 0);
+#pragma unroll
+        for (uint32_t kb = 1; kb < NKB; ++kb) acc = __builtin_amdgcn_mfma_i32_32x32x16_i8(av[kb], bop[kb], acc, 0, 0, 0);
+        if ((rt + 1) * 4 < level) {
+#pragma unroll
+            for (uint32_t kb = 0; kb < NKB; ++kb) av[kb] = (long)aop[((rt + 1) * kc.down_kb + kb) * 64];
+        }
         int z[8];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             if (u == 0) tile_digits<0>(acc, z); else tile_digits<1>(acc, z);
             const uint32_t i = 4 * rt + 2 * half + u;
-            if (i < level) conv[at(b * level + i, log_n, n)] = fold_digits(z, kc.red[i], mods[i].q, mods[i].bits);
+            if (i < level) conv[at(b * level + i, log_n, n)] = fold_digits(z, s_red[i]);
         }
     }
 }
@@ -493,12 +533,23 @@ void launch_automorphism_b(uint32_t n, const ItemPtrs& in, uint32_t rows, WsRef 
     hipLaunchKernelGGL(k_automorphism_b, grid_nk(log_n, rows, n), dim3(TB), 0, st, in, ws, off_out, kappa, log_n);
 }
 
+// calls f(std::integral_constant<uint32_t, v>) for the runtime v in 1..MAX
+template <uint32_t MAX, uint32_t V = 1, class F>
+static void launch_kb(uint32_t v, F&& f) {
+    if constexpr (V <= MAX) {
+        if (v == V) f(std::integral_constant<uint32_t, V>{});
+        else launch_kb<MAX, V + 1>(v, f);
+    }
+}
+
 void launch_modup_b(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, uint32_t level, const KsConsts& kc,
                     const DevTables& t, uint32_t log_n, bool mfma, hipStream_t st) {
     const uint32_t beta = (level + kc.alpha - 1) / kc.alpha;
     if (mfma)  // 32 coefficients per wave
-        hipLaunchKernelGGL(k_modup_mfma_b, dim3((1u << log_n) / (32 * (TB / 64)), beta, n), dim3(TB), 0, st, ws,
-                           off_d, off_ext, level, kc, t.mods, log_n);
+        launch_kb<PFT_MAX_ALPHA / 2>((min(kc.alpha, level) + 1) / 2, [&](auto nkb) {
+            hipLaunchKernelGGL(k_modup_mfma_b<decltype(nkb)::value>, dim3((1u << log_n) / (32 * (TB / 64)), beta, n),
+                               dim3(TB), 0, st, ws, off_d, off_ext, level, kc, t.mods, log_n);
+        });
     else
         hipLaunchKernelGGL(k_modup_b, grid_nk(log_n, beta, n), dim3(TB), 0, st, ws, off_d, off_ext, level, kc,
                            t.mods, log_n);
@@ -518,8 +569,10 @@ void launch_key_inner_b(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, 
 void launch_moddown_conv_b(uint32_t n, WsRef ws, uint64_t off_acc, uint64_t off_conv, uint32_t level,
                            const KsConsts& kc, const DevTables& t, uint32_t log_n, bool mfma, hipStream_t st) {
     if (mfma)
-        hipLaunchKernelGGL(k_moddown_mfma_b, dim3((1u << log_n) / (32 * (TB / 64)), 2, n), dim3(TB), 0, st, ws,
-                           off_acc, off_conv, level, kc, t.mods, log_n);
+        launch_kb<PFT_MAX_K / 2>((kc.K + 1) / 2, [&](auto nkb) {
+            hipLaunchKernelGGL(k_moddown_mfma_b<decltype(nkb)::value>, dim3((1u << log_n) / (32 * (TB / 64)), 2, n),
+                               dim3(TB), 0, st, ws, off_acc, off_conv, level, kc, t.mods, log_n);
+        });
     else
         hipLaunchKernelGGL(k_moddown_conv_b, grid_nk(log_n, 2, n), dim3(TB), 0, st, ws, off_acc, off_conv, level,
                            kc, t.mods, log_n);

@@ -55,36 +55,7 @@ __device__ __forceinline__ void inv_bfly(uint64_t& X, uint64_t& Y, uint64_t w, u
     Y = v;
 }
 
-// ---- fp64 butterflies (q < 2^50)
-//
-// A residue is held as an integer-valued double of either sign; every value
-// stays an integer below 2^53 in magnitude, so sums and differences are exact.
-// fmulmod(a, w) returns a w - k q with k = rint(fl(a fl(w/q))): the product
-// a w is split exactly into hi + lo (hi = fl(a w), lo = fma(a, w, -hi)); then
-// fma(-k, q, hi) is exact because the true value is an integer of magnitude
-// below 2^53, and adding lo is exact for the same reason.  The quotient is off
-// from a w / q by at most 1/2 + |a| 2^-52 (two roundings), so with |a| <= c q
-// and q < 2^50 the result lies within (1/2 + c/4) q of zero.  freduce(x) =
-// x - rint(x/q) q lies within q/2 (+ a vanishing error) for the magnitudes
-// used here.  Forward: inputs within B q give outputs within (1 + B/4) q, so
-// B stays below 4/3 after the first stage (inputs below 4q are accepted).
-// Inverse: inputs within B q give outputs within max(1/2, 1/2 + B/2) q, so B
-// stays at most 1 (inputs below 4q accepted).  All magnitudes stay below
-// 8q < 2^53.
-__device__ __forceinline__ double as_f(uint64_t v) { return __builtin_bit_cast(double, v); }
-__device__ __forceinline__ uint64_t as_u(double v) { return __builtin_bit_cast(uint64_t, v); }
-
-__device__ __forceinline__ double fmulmod(double a, double w, double wq, double q) {
-#pragma clang fp contract(off)
-    const double hi = a * w;
-    const double lo = __builtin_fma(a, w, -hi);
-    const double k = __builtin_rint(a * wq);
-    return __builtin_fma(-k, q, hi) + lo;
-}
-__device__ __forceinline__ double freduce(double x, double q, double qinv) {
-#pragma clang fp contract(off)
-    return __builtin_fma(-__builtin_rint(x * qinv), q, x);
-}
+// ---- fp64 butterflies (q < 2^50): fmulmod / freduce in pft_device.h
 __device__ __forceinline__ void fwd_bfly_fp(uint64_t& X, uint64_t& Y, const TwPair& tp, double q, double qinv) {
 #pragma clang fp contract(off)
     const double x = freduce(as_f(X), q, qinv);

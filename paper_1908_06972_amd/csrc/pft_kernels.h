@@ -89,11 +89,19 @@ struct WsRef {
 // Per-modulus constants that fold the digit sums of the MFMA base
 // conversion back into a residue: y = S_lo + 2^32 S_hi with |S_lo|, |S_hi| <
 // 2^45 is reduced as (S_lo + 2^45) + (S_hi + 2^45) 2^32 - (2^45 + 2^77).
+// Per-target constants of the digit fold (sum_b 256^b Z_b mod m).
 struct BconvRed {
-    TwPair c32;    // 2^32 mod m with its Shoup companion
-    uint64_t one_p;  // floor(2^64 / m): Shoup companion of 1
-    uint64_t cc;     // (2^45 + 2^77) mod m
+    uint64_t m;
+    uint64_t negm;  // 2^64 - m                      (m >= 2^50)
+    uint64_t cq0;   // 2^30 m mod 2^64               (m >= 2^50)
+    double md;      // m                             (m < 2^50)
+    double minv;    // 1 / m
+    double c32;     // 2^32 mod m                    (m < 2^50)
+    double c32q;    // (2^32 mod m) / m              (m < 2^50)
+    uint32_t fp;    // 1 when m < 2^50
+    uint32_t pad;
 };
+static_assert(sizeof(BconvRed) == 64, "BconvRed is staged into LDS as 8 words");
 
 struct KsConsts {
     const TwPair* modup_hatinv;   // [L][dnum][alpha]   indexed by (level-1, j, ii)
