@@ -22,6 +22,7 @@ class Params:
         h = ctypes.c_void_p()
         N.check(lib.pft_params_create(ctypes.byref(spec), ctypes.byref(h)))
         self.handle = h
+        self._destroy = lib.pft_params_destroy  # bound now: usable during interpreter shutdown
         self.log_n = log_n
         self.n = 1 << log_n
         self.L = n_q
@@ -45,8 +46,8 @@ class Params:
         return self.q + self.p
 
     def __del__(self):
-        if getattr(self, "handle", None) is not None and N._lib is not None:
-            N._lib.pft_params_destroy(self.handle)
+        if getattr(self, "handle", None) is not None:
+            self._destroy(self.handle)
             self.handle = None
 
     # client-side ENCODE / DECODE on the host
@@ -409,8 +410,8 @@ class Graph:
         N.check(self.ctx.lib.pft_graph_launch(self.ctx.handle, self.handle))
 
     def close(self):
-        if getattr(self, "handle", None) is not None and N._lib is not None:
-            N._lib.pft_graph_destroy(self.handle)
+        if getattr(self, "handle", None) is not None:
+            self.ctx.lib.pft_graph_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -56,9 +56,15 @@ __device__ __forceinline__ void inv_bfly(uint64_t& X, uint64_t& Y, uint64_t w, u
 }
 
 // ---- fp64 butterflies (q < 2^50): fmulmod / freduce in pft_device.h
-__device__ __forceinline__ void fwd_bfly_fp(uint64_t& X, uint64_t& Y, const TwPair& tp, double q, double qinv) {
+// Forward: X is reduced only on the even stages of a pass (pass-local index).
+// With inputs within B q a reducing stage leaves (1 + B/4) q and a skipping
+// one (5B/4 + 1/2) q; a pass starts with a reducing stage and never has two
+// skipping ones in a row, so from inputs below 4q the bound stays at most 3q
+// (it settles at 1.64q / 2.55q), far inside the exact range of fmulmod.
+__device__ __forceinline__ void fwd_bfly_fp(uint64_t& X, uint64_t& Y, const TwPair& tp, double q, double qinv,
+                                            bool reduce_x) {
 #pragma clang fp contract(off)
-    const double x = freduce(as_f(X), q, qinv);
+    const double x = reduce_x ? freduce(as_f(X), q, qinv) : as_f(X);
     const double t = fmulmod(as_f(Y), as_f(tp.w), as_f(tp.wp), q);
     X = as_u(x + t);
     Y = as_u(x - t);
@@ -96,6 +102,18 @@ struct Phase {
     }
 };
 
+// Twiddle index (high << spp) | (r >> (bit + 1)) of the butterfly at stage
+// bit `bit` whose upper element is register e (r = r_of(l, e)).  The lane
+// bits below the window drop out of the shift; in the phase that holds the
+// window's top bits no lane bit is left, so the index is the same for every
+// lane of a sub-problem.
+template <int LOG_M, int PH, int EB>
+__device__ __forceinline__ uint32_t tw_index(uint32_t l, int e, int bit, uint32_t high, int spp) {
+    using Ph = Phase<LOG_M, PH, EB>;
+    const uint32_t lhi = (Ph::WLO + EB >= LOG_M) ? 0u : (l >> Ph::WLO);
+    return (high << spp) | (lhi << (Ph::WLO + EB - bit - 1)) | ((uint32_t)e >> (bit + 1 - Ph::WLO));
+}
+
 template <int LOG_M, int PH, int EB, bool INV, bool FP, bool FOLD>
 __device__ __forceinline__ void run_phase(uint64_t (&x)[1 << EB], uint32_t l, uint32_t high, uint32_t s0,
                                           const TwPair* __restrict__ twt, const DevMod& md) {
@@ -112,11 +130,9 @@ __device__ __forceinline__ void run_phase(uint64_t (&x)[1 << EB], uint32_t l, ui
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 if (e & (1 << pos)) continue;
-                const uint32_t r = Ph::r_of(l, e);
-                const uint32_t i = (high << spp) | (r >> (bit + 1));
-                const TwPair tp = twt[(1u << s) + i];
+                const TwPair tp = twt[(1u << s) + tw_index<LOG_M, PH, EB>(l, e, bit, high, spp)];
                 if constexpr (FP)
-                    fwd_bfly_fp(x[e], x[e | (1 << pos)], tp, qd, qinv);
+                    fwd_bfly_fp(x[e], x[e | (1 << pos)], tp, qd, qinv, (spp & 1) == 0);
                 else
                     fwd_bfly(x[e], x[e | (1 << pos)], tp.w, tp.wp, q, two_q);
             }
@@ -148,9 +164,7 @@ __device__ __forceinline__ void run_phase(uint64_t (&x)[1 << EB], uint32_t l, ui
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
                     if (e & (1 << pos)) continue;
-                    const uint32_t r = Ph::r_of(l, e);
-                    const uint32_t i = (high << spp) | (r >> (bit + 1));
-                    const TwPair tp = twt[(1u << s) + i];
+                    const TwPair tp = twt[(1u << s) + tw_index<LOG_M, PH, EB>(l, e, bit, high, spp)];
                     if constexpr (FP)
                         inv_bfly_fp(x[e], x[e | (1 << pos)], tp, qd, qinv);
                     else
@@ -265,11 +279,12 @@ __global__ __launch_bounds__(4096 >> EB) void k_ntt_pass(PolyBatch b, const DevM
     const bool fp = md.fp != 0;
     const TwPair* __restrict__ twt = tw + ((size_t)mi << log_n);
 
-    const uint32_t lbits = log_n - s0 - LOG_M;
+    // a row pass has no index bits below its window (s0 + LOG_M = log_n)
+    const uint32_t lbits = COL ? log_n - s0 - LOG_M : 0u;
     const uint32_t lmask = (1u << lbits) - 1u;
     const uint32_t sp0 = blockIdx.x * C;
-    const uint32_t c = COL ? tid % C : tid / T;
-    const uint32_t l = COL ? tid / C : tid % T;
+    const uint32_t c = C == 1 ? 0u : (COL ? tid % C : tid / T);
+    const uint32_t l = C == 1 ? tid : (COL ? tid / C : tid % T);
     const uint32_t high = (sp0 + c) >> lbits;
     // global index of element r of the workgroup's sub-problem cc
     auto gidx = [&](uint32_t cc, uint32_t r) -> size_t {

@@ -106,11 +106,10 @@ __device__ __forceinline__ uint64_t shoup(uint64_t a, uint64_t w, uint64_t wp, u
 // from a w / q by at most 1/2 + |a| 2^-52 (two roundings), so with |a| <= c q
 // and q < 2^50 the result lies within (1/2 + c/4) q of zero.  freduce(x) =
 // x - rint(x/q) q lies within q/2 (+ a vanishing error) for the magnitudes
-// used here.  Forward: inputs within B q give outputs within (1 + B/4) q, so
-// B stays below 4/3 after the first stage (inputs below 4q are accepted).
-// Inverse: inputs within B q give outputs within max(1/2, 1/2 + B/2) q, so B
-// stays at most 1 (inputs below 4q accepted).  All magnitudes stay below
-// 8q < 2^53.
+// used here.  Forward butterfly with X reduced: inputs within B q give outputs
+// within (1 + B/4) q (the lazy schedule of the NTT keeps B <= 3).  Inverse:
+// inputs within B q give outputs within max(1/2, 1/2 + B/2) q, so B stays at
+// most 1 (inputs below 4q accepted).  All magnitudes stay below 8q < 2^53.
 __device__ __forceinline__ double as_f(uint64_t v) { return __builtin_bit_cast(double, v); }
 __device__ __forceinline__ uint64_t as_u(double v) { return __builtin_bit_cast(uint64_t, v); }
 
