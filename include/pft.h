@@ -341,7 +341,8 @@ int pft_prof_read(pft_ctx* ctx, uint32_t kid, double* total_ms, uint64_t* launch
  * k_ntt_pass<radix, log2 residues per thread, inverse, column, final, staged,
  * ModDown epilogue>; base conversions on the matrix cores (families 2 and
  * 4): the number of 16-deep k-blocks, naming k_modup_mfma_b<kb> and
- * k_moddown_mfma_b<kb>.  Any output may be NULL. */
+ * k_moddown_mfma_b<kb>; the batched key inner product (family 3): the number
+ * of digits beta, naming k_key_inner_items<beta>.  Any output may be NULL. */
 int pft_prof_read_variants(pft_ctx* ctx, uint32_t kid, uint32_t max_count, uint32_t* variants, double* total_ms,
                            uint64_t* launches, double* bytes, double* ops);
 

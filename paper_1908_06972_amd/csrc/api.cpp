@@ -1149,7 +1149,7 @@ static void key_switch_b(pft_ctx* c, uint32_t n, WsRef ws, const KsLayout& K, ui
     timed(c, PK_KEY_INNER, 8.0 * N * ((double)beta * rows * n + 2.0 * beta * rows * key_once + 2.0 * rows * n),
           2.0 * N * beta * rows * n, [&] {
         launch_key_inner_b(n, ws, off_d, K.off_ext, K.off_acc, key.data, level, c->kc, c->tabs, lg, c->stream);
-    });
+    }, beta <= 8 ? beta : 0);
     // ModDown: special rows of both accumulators to coefficient form
     {
         std::vector<NttJob> jobs;

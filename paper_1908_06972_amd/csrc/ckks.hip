@@ -349,10 +349,15 @@ __global__ __launch_bounds__(TB) void k_key_inner_b(WsRef ws, uint64_t off_d, ui
 }
 
 // The same inner product for all n_items ciphertexts of a launch, one thread
-// per (coefficient, row): the 2 beta key residues of the row are loaded once
+// per (coefficient, row): the 2 BETA key residues of the row are loaded once
 // and reused for every item (the key is shared by the batch), then each item
-// reads its beta inputs and writes its two outputs.  beta <= PFT_KEY_REGS.
+// reads its BETA inputs and writes its two outputs.  The inputs of item z + 1
+// are in flight while item z is computed.  Rows with q < 2^50 work in fp64
+// (keys taken out of Montgomery form once per thread, each product by
+// fmulmod: |term| < 3q/4, the sum of at most 8 terms stays exact); the others
+// accumulate 128-bit products and finish with one REDC.
 #define PFT_KEY_REGS 8
+template <uint32_t BETA>
 __global__ __launch_bounds__(TB) void k_key_inner_items(WsRef ws, uint32_t n_items, uint64_t off_d, uint64_t off_ext,
                                                         uint64_t off_acc, const uint64_t* __restrict__ key,
                                                         uint32_t level, KsConsts kc, const DevMod* __restrict__ mods,
@@ -362,31 +367,71 @@ __global__ __launch_bounds__(TB) void k_key_inner_items(WsRef ws, uint32_t n_ite
     const uint32_t rows = level + kc.K;
     const uint32_t krow = t < level ? t : kc.L + (t - level);
     const DevMod md = mods[krow];
-    const uint32_t beta = (level + kc.alpha - 1) / kc.alpha;
     const uint32_t krows = kc.L + kc.K;
-    uint64_t k0[PFT_KEY_REGS], k1[PFT_KEY_REGS];
-    uint32_t own = PFT_KEY_REGS;  // the digit whose input is d itself on this row
+    // word offset of digit j's input on this row within an item's workspace:
+    // d itself on the digit's own rows, ext_j elsewhere
+    uint64_t src[BETA];
 #pragma unroll
-    for (uint32_t j = 0; j < PFT_KEY_REGS; ++j) {
-        if (j < beta) {
-            k0[j] = key[at((2 * j) * krows + krow, log_n, k)];
-            k1[j] = key[at((2 * j + 1) * krows + krow, log_n, k)];
-            if (t >= j * kc.alpha && t < min(j * kc.alpha + kc.alpha, level)) own = j;
-        }
+    for (uint32_t j = 0; j < BETA; ++j) {
+        const bool own = t >= j * kc.alpha && t < min(j * kc.alpha + kc.alpha, level);
+        src[j] = own ? off_d + at(t, log_n, k) : off_ext + at(j * rows + t, log_n, k);
     }
-    for (uint32_t z = 0; z < n_items; ++z) {
-        uint64_t* __restrict__ w = ws.base + (size_t)z * ws.stride;
-        Acc128 a0 = {0, 0}, a1 = {0, 0};
+    uint64_t k0[BETA], k1[BETA];
 #pragma unroll
-        for (uint32_t j = 0; j < PFT_KEY_REGS; ++j) {
-            if (j < beta) {
-                const uint64_t x = j == own ? w[off_d + at(t, log_n, k)] : w[off_ext + at(j * rows + t, log_n, k)];
-                mac128(a0, x, k0[j]);
-                mac128(a1, x, k1[j]);
-            }
+    for (uint32_t j = 0; j < BETA; ++j) {
+        k0[j] = key[at((2 * j) * krows + krow, log_n, k)];
+        k1[j] = key[at((2 * j + 1) * krows + krow, log_n, k)];
+    }
+    uint64_t xn[BETA];
+#pragma unroll
+    for (uint32_t j = 0; j < BETA; ++j) xn[j] = ws.base[src[j]];
+    const uint64_t o0 = off_acc + at(t, log_n, k), o1 = off_acc + at(rows + t, log_n, k);
+    if (md.fp) {
+        double w0[BETA], p0[BETA], w1[BETA], p1[BETA];
+#pragma unroll
+        for (uint32_t j = 0; j < BETA; ++j) {
+            w0[j] = (double)mont_redc(k0[j], 0, md.q, md.mont_neg_qinv);
+            w1[j] = (double)mont_redc(k1[j], 0, md.q, md.mont_neg_qinv);
+            p0[j] = w0[j] / md.qd;
+            p1[j] = w1[j] / md.qd;
         }
-        w[off_acc + at(t, log_n, k)] = mont_redc(a0.lo, a0.hi, md.q, md.mont_neg_qinv);
-        w[off_acc + at(rows + t, log_n, k)] = mont_redc(a1.lo, a1.hi, md.q, md.mont_neg_qinv);
+        for (uint32_t z = 0; z < n_items; ++z) {
+            uint64_t* __restrict__ w = ws.base + (size_t)z * ws.stride;
+            double x[BETA];
+#pragma unroll
+            for (uint32_t j = 0; j < BETA; ++j) x[j] = as_f(fp_from_u64(xn[j]));
+            if (z + 1 < n_items) {
+#pragma unroll
+                for (uint32_t j = 0; j < BETA; ++j) xn[j] = w[ws.stride + src[j]];
+            }
+            double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+            for (uint32_t j = 0; j < BETA; ++j) {
+                s0 += fmulmod(x[j], w0[j], p0[j], md.qd);
+                s1 += fmulmod(x[j], w1[j], p1[j], md.qd);
+            }
+            w[o0] = fp_to_u64(as_u(s0), md.qd, md.qinv);
+            w[o1] = fp_to_u64(as_u(s1), md.qd, md.qinv);
+        }
+    } else {
+        for (uint32_t z = 0; z < n_items; ++z) {
+            uint64_t* __restrict__ w = ws.base + (size_t)z * ws.stride;
+            uint64_t x[BETA];
+#pragma unroll
+            for (uint32_t j = 0; j < BETA; ++j) x[j] = xn[j];
+            if (z + 1 < n_items) {
+#pragma unroll
+                for (uint32_t j = 0; j < BETA; ++j) xn[j] = w[ws.stride + src[j]];
+            }
+            Acc128 a0 = {0, 0}, a1 = {0, 0};
+#pragma unroll
+            for (uint32_t j = 0; j < BETA; ++j) {
+                mac128(a0, x[j], k0[j]);
+                mac128(a1, x[j], k1[j]);
+            }
+            w[o0] = mont_redc(a0.lo, a0.hi, md.q, md.mont_neg_qinv);
+            w[o1] = mont_redc(a1.lo, a1.hi, md.q, md.mont_neg_qinv);
+        }
     }
 }
 
@@ -559,8 +604,10 @@ void launch_key_inner_b(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, 
                         uint32_t level, const KsConsts& kc, const DevTables& t, uint32_t log_n, hipStream_t st) {
     const uint32_t beta = (level + kc.alpha - 1) / kc.alpha;
     if (beta <= PFT_KEY_REGS)
-        hipLaunchKernelGGL(k_key_inner_items, grid_nk(log_n, level + kc.K, 1), dim3(TB), 0, st, ws, n, off_d, off_ext,
-                           off_acc, key, level, kc, t.mods, log_n);
+        launch_kb<PFT_KEY_REGS>(beta, [&](auto bc) {
+            hipLaunchKernelGGL(k_key_inner_items<decltype(bc)::value>, grid_nk(log_n, level + kc.K, 1), dim3(TB), 0,
+                               st, ws, n, off_d, off_ext, off_acc, key, level, kc, t.mods, log_n);
+        });
     else
         hipLaunchKernelGGL(k_key_inner_b, grid_nk(log_n, level + kc.K, n), dim3(TB), 0, st, ws, off_d, off_ext,
                            off_acc, key, level, kc, t.mods, log_n);

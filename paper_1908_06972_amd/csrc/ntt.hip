@@ -75,20 +75,6 @@ __device__ __forceinline__ void inv_bfly_fp(uint64_t& X, uint64_t& Y, const TwPa
     X = as_u(freduce(x + y, q, qinv));
     Y = as_u(fmulmod(x - y, as_f(tp.w), as_f(tp.wp), q));
 }
-// u64 below 2^52 -> double: the bits of 2^52 + v, minus 2^52.
-__device__ __forceinline__ uint64_t fp_from_u64(uint64_t v) {
-#pragma clang fp contract(off)
-    return as_u(as_f(v | 0x4330000000000000ull) - 4503599627370496.0);
-}
-// double residue -> canonical u64 in [0, q): reduce to within q/2, lift the
-// negative half by q, then read the mantissa of 2^52 + r.
-__device__ __forceinline__ uint64_t fp_to_u64(uint64_t v, double q, double qinv) {
-#pragma clang fp contract(off)
-    double r = freduce(as_f(v), q, qinv);
-    r = r < 0.0 ? r + q : r;
-    return as_u(r + 4503599627370496.0) & 0x000FFFFFFFFFFFFFull;
-}
-
 // Register phase PH of a radix-2^LOG_M pass with E = 2^EB residues per
 // thread: stage bits HB down to LB; element e of thread l is index r_of(l, e)
 // of its sub-problem (the EB window bits sit at WLO).

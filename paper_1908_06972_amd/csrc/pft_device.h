@@ -125,6 +125,20 @@ __device__ __forceinline__ double freduce(double x, double q, double qinv) {
     return __builtin_fma(-__builtin_rint(x * qinv), q, x);
 }
 
+// u64 below 2^52 -> double: the bits of 2^52 + v, minus 2^52.
+__device__ __forceinline__ uint64_t fp_from_u64(uint64_t v) {
+#pragma clang fp contract(off)
+    return as_u(as_f(v | 0x4330000000000000ull) - 4503599627370496.0);
+}
+// double residue -> canonical u64 in [0, q): reduce to within q/2, lift the
+// negative half by q, then read the mantissa of 2^52 + r.
+__device__ __forceinline__ uint64_t fp_to_u64(uint64_t v, double q, double qinv) {
+#pragma clang fp contract(off)
+    double r = freduce(as_f(v), q, qinv);
+    r = r < 0.0 ? r + q : r;
+    return as_u(r + 4503599627370496.0) & 0x000FFFFFFFFFFFFFull;
+}
+
 // (hi:lo) * 2^-64 mod q for hi:lo < q * 2^64; result in [0, q).
 __device__ __forceinline__ uint64_t mont_redc(uint64_t lo, uint64_t hi, uint64_t q, uint64_t neg_qinv) {
     uint64_t m = lo * neg_qinv;

@@ -86,9 +86,6 @@ struct WsRef {
 };
 #define PFT_NO_OFFSET (~0ull)
 
-// Per-modulus constants that fold the digit sums of the MFMA base
-// conversion back into a residue: y = S_lo + 2^32 S_hi with |S_lo|, |S_hi| <
-// 2^45 is reduced as (S_lo + 2^45) + (S_hi + 2^45) 2^32 - (2^45 + 2^77).
 // Per-target constants of the digit fold (sum_b 256^b Z_b mod m).
 struct BconvRed {
     uint64_t m;
