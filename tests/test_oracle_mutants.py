@@ -84,3 +84,40 @@ def test_mutant_decrypt_sign(monkeypatch):
         return C.sub(ct.c0, C.ring_mul(params, ct.c1, C.rns_from_int(s, mods), mods), mods)
     monkeypatch.setattr(C, "decrypt", bad)
     _expect_fail(TS.test_encrypt_decrypt_exact, _tiny())
+
+
+def test_mutant_ctmatvec_unrotated_giant_step(monkeypatch):
+    """A giant-step partial sum added without its rotation by g b."""
+    from oracle import training as T
+    from tests import test_oracle_training as TT
+    real_rotate = C.rotate
+    C.set_mul_mode(1)
+    fx = TT.make_train()
+
+    def bad_ctmatvec(params, inputs, diags, n_o, n_i, rlk, rot_keys):
+        b, G = T.bsgs_plan(n_o)
+        baby = [[v if r == 0 else real_rotate(params, v, r, rot_keys[r]) for r in range(b)] for v in inputs]
+        scale = diags[0][0][0].scale * inputs[0].scale
+        total = None
+        for g in range(G):
+            pairs = [(diags[c][g][r], baby[c][r]) for c in range(len(inputs)) for r in range(b)]
+            acc = T.relin_tensor(params, T._tensor_sum(params, pairs), rlk, scale)
+            total = acc if total is None else C.hadd(params, total, acc)
+        s = n_o
+        while s < n_i:
+            total = C.hadd(params, total, real_rotate(params, total, s, rot_keys[s]))
+            s *= 2
+        return total
+    monkeypatch.setattr(T, "ctmatvec", bad_ctmatvec)
+    _expect_fail(TT.test_encrypted_ctmatvec, fx)
+
+
+def test_mutant_softmax_wrong_shift(monkeypatch):
+    """(X + 1)^2 / 8 in place of (X + 2)^2 / 8 - 1/4."""
+    from oracle import training as T
+    from tests import test_oracle_training as TT
+    C.set_mul_mode(1)
+    fx = TT.make_train()
+    real = T.hadd_const
+    monkeypatch.setattr(T, "hadd_const", lambda P, x, v: real(P, x, 1.0 if v == 2.0 else v))
+    _expect_fail(TT.test_encrypted_softmax_approx, fx)
