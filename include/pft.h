@@ -181,6 +181,14 @@ int pft_total_sum_batch(pft_ctx* ctx, uint32_t n, const pft_ct* in, uint32_t n_s
  * Used for the 1/w average of Sec. 4.1.  Synchronizes (per-call constants). */
 int pft_mul_const(pft_ctx* ctx, const pft_ct* in, double value, pft_ct* out);
 int pft_mul_const_batch(pft_ctx* ctx, uint32_t n, const pft_ct* in, const double* values, pft_ct* out);
+/* HADDPLAIN of a constant (Sec. 3.4): out = in + m at X^0 with the integer
+ * m = round(value * in->scale) (half away from zero), i.e. every slot gains
+ * `value` at the ciphertext's own scale; out->scale = in->scale, level
+ * unchanged.  PFT_EINVAL if |value * scale| >= 2^62.  out may alias in.
+ * Used by the softmax approximation of Sec. 4.2.  Synchronizes (per-call
+ * constants); not capturable. */
+int pft_add_const(pft_ctx* ctx, const pft_ct* in, double value, pft_ct* out);
+int pft_add_const_batch(pft_ctx* ctx, uint32_t n, const pft_ct* in, const double* values, pft_ct* out);
 
 /* ---- PtMatVec: plaintext matrix x encrypted vector (Sec. 4.1, v H and h O)
  * Matrix M (n_o x n_in*n_i, row-major doubles) acting on an input split over
@@ -210,6 +218,23 @@ void pft_ptmat_destroy(pft_ptmat* m);
 /* in: n_docs * n_in ciphertexts, document-major, all at the matrix level;
  * out: n_docs ciphertexts (caller memory, 2*level*N each). */
 int pft_ptmatvec(pft_ctx* ctx, const pft_ptmat* m, uint32_t n_docs, const pft_ct* in, pft_ct* out);
+
+/* ---- CtMatVec: encrypted matrix x encrypted vector (Sec. 4.2) ------------
+ * The predict step of training with encrypted weights: the PtMatVec above
+ * with the pre-rotated diagonals E^c_{g,r} given as ciphertexts (so each
+ * diagonal product is HMUL instead of HMULPLAIN):
+ *   u = sum_g ROTATE(Relin(sum_c sum_r E^c_{g,r} (x) ROTATE(v_c, r)), g b),
+ *   y = u + ROTATE(u, n_o) + ... (steps n_o 2^s while n_o 2^s < n_i),
+ * where (x) is the HMUL tensor and the tensors of one giant step are summed
+ * before a single relinearisation.  Same plan rule and rotation keys as
+ * PtMatVec, plus the relinearisation key.  diags: n_in * G * b ciphertexts,
+ * layout [n_in][G][b], all at one level and scale (the caller's encrypted
+ * model, read only); in: n_docs * n_in ciphertexts, document-major, at the
+ * diagonals' level and of equal scales; out: n_docs ciphertexts (caller
+ * memory, 2*level*N each), out->scale = in scale * diagonal scale, no
+ * rescale.  PFT_EINVAL if n_in * b > 64. */
+int pft_ctmatvec(pft_ctx* ctx, uint32_t n_o, uint32_t n_i, uint32_t n_in, const pft_ct* diags, uint32_t n_docs,
+                 const pft_ct* in, pft_ct* out);
 
 /* ---- transforms on raw RNS polynomials ---------------------------------
  * data: device [n_polys][n_limbs][N], limb i of every polynomial mod q_i

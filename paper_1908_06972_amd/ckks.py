@@ -313,6 +313,23 @@ class Context:
         N.check(self.lib.pft_mul_const_batch(self.handle, len(a), A, N.dblp(vals), O))
         return [o.sync_from(O[i]) for i, o in enumerate(out)]
 
+    def add_const_batch(self, a, values, out=None):
+        out = out or [self.empty_ct(x.level) for x in a]
+        A, O = self._arr(a), self._arr(out)
+        vals = np.ascontiguousarray(values, dtype=np.float64)
+        N.check(self.lib.pft_add_const_batch(self.handle, len(a), A, N.dblp(vals), O))
+        return [o.sync_from(O[i]) for i, o in enumerate(out)]
+
+    def ctmatvec(self, diags, n_o, n_i, n_in, inputs, out=None):
+        """Encrypted matrix x encrypted vector.  diags: flat list of
+        n_in * G * b ciphertexts in [n_in][G][b] order; inputs: list over
+        documents of lists of n_in ciphertexts."""
+        flat = [c for doc in inputs for c in doc]
+        out = out or [self.empty_ct(doc[0].level) for doc in inputs]
+        D, A, O = self._arr(diags), self._arr(flat), self._arr(out)
+        N.check(self.lib.pft_ctmatvec(self.handle, n_o, n_i, n_in, D, len(inputs), A, O))
+        return [o.sync_from(O[i]) for i, o in enumerate(out)]
+
     def ptmat(self, M, n_o, n_i, n_in, level):
         """Plaintext matrix from doubles (library encoder)."""
         h = ctypes.c_void_p()

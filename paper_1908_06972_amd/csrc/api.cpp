@@ -1502,6 +1502,61 @@ extern "C" int pft_mul_const(pft_ctx* c, const pft_ct* in, double value, pft_ct*
     return pft_mul_const_batch(c, 1, in, &value, out);
 }
 
+// Per-call constants [n][level] (pairs) into the context's constant buffer.
+static int upload_consts(pft_ctx* c, const std::vector<TwPair>& consts) {
+    if (c->cbuf_n < consts.size()) {
+        HIPCK(hipStreamSynchronize(c->stream));
+        if (c->cbuf) HIPCK(hipFree(c->cbuf));
+        c->cbuf = nullptr;
+        HIPCK(hipMalloc(&c->cbuf, consts.size() * sizeof(TwPair)));
+        c->cbuf_n = consts.size();
+    }
+    HIPCK(hipMemcpyAsync(c->cbuf, consts.data(), consts.size() * sizeof(TwPair), hipMemcpyHostToDevice, c->stream));
+    return PFT_OK;
+}
+
+extern "C" int pft_add_const_batch(pft_ctx* c, uint32_t n, const pft_ct* in, const double* values, pft_ct* out) {
+    if (!c || !in || !values || !out) return fail(PFT_EINVAL, "null argument");
+    if (c->capturing) return fail(PFT_EINVAL, "add_const copies host constants and cannot be captured");
+    int r;
+    for (uint32_t i = 0; i < n; ++i) {
+        if ((r = check_ct(c, &in[i]))) return r;
+        if (!out[i].data) return fail(PFT_EINVAL, "null output");
+        if (!(std::fabs(values[i] * in[i].scale) < 4611686018427387904.0))
+            return fail(PFT_EINVAL, "constant times scale must stay below 2^62 in magnitude");
+    }
+    const pft_params* P = c->P;
+    return for_level_groups(n, in, [&](const std::vector<uint32_t>& g) -> int {
+        const uint32_t l = in[g[0]].level, cnt = (uint32_t)g.size();
+        std::vector<TwPair> consts((size_t)cnt * l);
+        for (uint32_t z = 0; z < cnt; ++z) {
+            const int64_t m = round_half_away(values[g[z]] * in[g[z]].scale);
+            for (uint32_t i = 0; i < l; ++i) {
+                const uint64_t q = P->q[i];
+                const uint64_t v = m >= 0 ? (uint64_t)m % q : (q - ((0ull - (uint64_t)m) % q)) % q;
+                consts[(size_t)z * l + i] = TwPair{v, 0};
+            }
+        }
+        int rr;
+        if ((rr = upload_consts(c, consts))) return rr;
+        ItemPtrs I{}, O{};
+        for (uint32_t z = 0; z < cnt; ++z) {
+            I.p[z] = in[g[z]].data;
+            O.p[z] = out[g[z]].data;
+        }
+        launch_add_const_b(cnt, I, O, c->cbuf, l, c->tabs, P->log_n, c->stream);
+        for (uint32_t z = 0; z < cnt; ++z) {
+            out[g[z]].level = l;
+            out[g[z]].scale = in[g[z]].scale;
+        }
+        return PFT_OK;
+    });
+}
+
+extern "C" int pft_add_const(pft_ctx* c, const pft_ct* in, double value, pft_ct* out) {
+    return pft_add_const_batch(c, 1, in, &value, out);
+}
+
 struct pft_ptmat {
     pft_ctx* ctx = nullptr;
     uint32_t n_o = 0, n_i = 0, n_in = 0, level = 0, b = 0, G = 0;
@@ -1719,6 +1774,128 @@ extern "C" int pft_ptmatvec(pft_ctx* c, const pft_ptmat* m, uint32_t n_docs, con
     for (uint32_t z = 0; z < n_docs; ++z) {
         out[z].level = l;
         out[z].scale = scale * m->pt_scale;
+    }
+    return PFT_OK;
+}
+
+// ---- encrypted-weight matrix-vector product (Sec. 4.2) --------------------
+extern "C" int pft_ctmatvec(pft_ctx* c, uint32_t n_o, uint32_t n_i, uint32_t n_in, const pft_ct* diags,
+                            uint32_t n_docs, const pft_ct* in, pft_ct* out) {
+    if (!c || !diags || !in || !out) return fail(PFT_EINVAL, "null argument");
+    if (!c->rlk.data) return fail(PFT_ENOKEY, "no relinearisation key");
+    const pft_params* P = c->P;
+    const uint32_t t = P->n / 2;
+    if (!n_o || (n_o & (n_o - 1)) || !n_i || (n_i & (n_i - 1)) || n_i > t || n_o > n_i)
+        return fail(PFT_EINVAL, "need powers of two n_o <= n_i <= N/2");
+    if (n_in < 1) return fail(PFT_EINVAL, "n_in must be at least 1");
+    pft_ptmat plan;  // only the plan fields, for the rotation steps
+    plan.n_o = n_o;
+    plan.n_i = n_i;
+    bsgs_plan(n_o, &plan.b, &plan.G);
+    const uint32_t b = plan.b, G = plan.G, J = n_in * b;
+    if (J > PFT_MAX_ITEMS) return fail(PFT_EINVAL, "n_in * b = %u exceeds %u diagonal terms per giant step", J,
+                                       (unsigned)PFT_MAX_ITEMS);
+    int r;
+    const uint32_t nd = n_in * G * b;
+    if ((r = check_ct(c, &diags[0]))) return r;
+    const uint32_t l = diags[0].level;
+    for (uint32_t j = 0; j < nd; ++j) {
+        if ((r = check_ct(c, &diags[j]))) return r;
+        if (diags[j].level != l) return fail(PFT_ELEVEL, "diagonals need equal levels");
+        if (!scales_match(diags[j].scale, diags[0].scale)) return fail(PFT_ESCALE, "diagonals need equal scales");
+    }
+    for (uint32_t z = 0; z < n_docs; ++z) {
+        if (!out[z].data) return fail(PFT_EINVAL, "null output");
+        for (uint32_t cc = 0; cc < n_in; ++cc) {
+            const pft_ct& x = in[(size_t)z * n_in + cc];
+            if ((r = check_ct(c, &x))) return r;
+            if (x.level != l) return fail(PFT_ELEVEL, "input level %u differs from the diagonals' level %u", x.level, l);
+            if (!scales_match(x.scale, in[0].scale)) return fail(PFT_ESCALE, "inputs need equal scales");
+        }
+    }
+    for (uint32_t st : ptmat_steps(&plan))
+        if (!find_rot(c, (int32_t)st)) return fail(PFT_ENOKEY, "no rotation key for step %u", st);
+    if (n_docs == 0) return PFT_OK;
+    const double scale = in[0].scale * diags[0].scale;
+    const uint32_t lg = P->log_n;
+    const uint64_t nl = (uint64_t)l * P->n, ct_words = 2 * nl;
+    // per document in aux: baby[n_in][b] | acc | tot | tmp
+    const uint64_t off_baby = 0, off_acc = (uint64_t)J * ct_words, off_tot = off_acc + ct_words,
+                   off_tmp = off_tot + ct_words, stride = off_tmp + ct_words;
+    if ((r = ensure_aux(c, (size_t)n_docs * stride * 8))) return r;
+    // per document in ws: the summed tensor [3][l][N], then key switching
+    const KsLayout K = ks_layout(P, l, 3 * nl);
+    const uint32_t chunk = PFT_MAX_ITEMS;
+    uint64_t* A = c->aux;
+    for (uint32_t z0 = 0; z0 < n_docs * n_in; z0 += PFT_MAX_ITEMS) {
+        const uint32_t cnt = std::min<uint32_t>(PFT_MAX_ITEMS, n_docs * n_in - z0);
+        ItemPtrs I{}, O{};
+        for (uint32_t u = 0; u < cnt; ++u) {
+            const uint32_t z = (z0 + u) / n_in, cc = (z0 + u) % n_in;
+            I.p[u] = in[z0 + u].data;
+            O.p[u] = A + z * stride + off_baby + (uint64_t)cc * b * ct_words;
+        }
+        launch_copy_rows_b(cnt, I, 0, O, 0, 2 * l, lg, c->stream);
+    }
+    const double in_scale = in[0].scale;
+    for (uint32_t rr = 1; rr < b; ++rr) {
+        std::vector<pft_ct> src, dst;
+        for (uint32_t z = 0; z < n_docs; ++z)
+            for (uint32_t cc = 0; cc < n_in; ++cc) {
+                const uint64_t base = z * stride + off_baby + (uint64_t)cc * b * ct_words;
+                src.push_back(pft_ct{A + base, l, 0, in_scale});
+                dst.push_back(pft_ct{A + base + rr * ct_words, l, 0, in_scale});
+            }
+        if ((r = pft_rotate_batch(c, (uint32_t)src.size(), src.data(), (int32_t)rr, dst.data()))) return r;
+    }
+    for (uint32_t g = 0; g < G; ++g) {
+        // the rotations of the previous giant step may have regrown ws
+        if ((r = ensure_ws(c, (size_t)std::min(n_docs, chunk) * K.end * 8))) return r;
+        const WsRef ws{c->ws, K.end};
+        ItemPtrs E{};
+        for (uint32_t cc = 0; cc < n_in; ++cc)
+            for (uint32_t rr = 0; rr < b; ++rr) E.p[cc * b + rr] = diags[((size_t)cc * G + g) * b + rr].data;
+        for (uint32_t z0 = 0; z0 < n_docs; z0 += chunk) {
+            const uint32_t cnt = std::min(chunk, n_docs - z0);
+            timed(c, PK_TENSOR, 8.0 * cnt * (2.0 * J * ct_words + 3.0 * nl) + 8.0 * J * ct_words,
+                  4.0 * cnt * J * nl, [&] {
+                      launch_ct_dot_b(cnt, E, J, WsRef{A + z0 * stride, stride}, off_baby, ct_words, ws, 0, l,
+                                      c->tabs, lg, c->stream);
+                  });
+            ItemPtrs O{};
+            for (uint32_t u = 0; u < cnt; ++u) O.p[u] = A + (z0 + u) * stride + (g == 0 ? off_tot : off_acc);
+            key_switch_b(c, cnt, ws, K, 2 * nl, c->rlk, 0, nl, O);
+        }
+        if (g == 0) continue;
+        std::vector<pft_ct> src = cts_at(A, stride, off_acc, n_docs, l, scale);
+        std::vector<pft_ct> dst = cts_at(A, stride, off_tmp, n_docs, l, scale);
+        if ((r = pft_rotate_batch(c, n_docs, src.data(), (int32_t)(g * b), dst.data()))) return r;
+        for (uint32_t z0 = 0; z0 < n_docs; z0 += 65535) {
+            const uint32_t cnt = std::min<uint32_t>(65535, n_docs - z0);
+            launch_add_ct_b(cnt, WsRef{A + z0 * stride, stride}, off_tot, off_tmp, off_tot, l, c->tabs, lg, c->stream);
+        }
+    }
+    for (uint32_t s = n_o; s < n_i; s <<= 1) {
+        std::vector<pft_ct> src = cts_at(A, stride, off_tot, n_docs, l, scale);
+        std::vector<pft_ct> dst = cts_at(A, stride, off_tmp, n_docs, l, scale);
+        if ((r = pft_rotate_batch(c, n_docs, src.data(), (int32_t)s, dst.data()))) return r;
+        for (uint32_t z0 = 0; z0 < n_docs; z0 += 65535) {
+            const uint32_t cnt = std::min<uint32_t>(65535, n_docs - z0);
+            launch_add_ct_b(cnt, WsRef{A + z0 * stride, stride}, off_tot, off_tmp, off_tot, l, c->tabs, lg, c->stream);
+        }
+    }
+    for (uint32_t z0 = 0; z0 < n_docs; z0 += PFT_MAX_ITEMS) {
+        const uint32_t cnt = std::min<uint32_t>(PFT_MAX_ITEMS, n_docs - z0);
+        ItemPtrs I{}, O{};
+        for (uint32_t u = 0; u < cnt; ++u) {
+            I.p[u] = A + (z0 + u) * stride + off_tot;
+            O.p[u] = out[z0 + u].data;
+        }
+        launch_copy_rows_b(cnt, I, 0, O, 0, 2 * l, lg, c->stream);
+    }
+    for (uint32_t z = 0; z < n_docs; ++z) {
+        out[z].level = l;
+        out[z].scale = scale;
     }
     return PFT_OK;
 }

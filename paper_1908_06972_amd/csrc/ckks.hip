@@ -530,6 +530,44 @@ __global__ __launch_bounds__(TB) void k_pt_dot_b(WsRef ws, uint64_t off_baby, ui
     w[off_acc + at(row, log_n, k)] = res;
 }
 
+// out_z = in_z + c_z at X^0: in the evaluation domain the constant c_z[i]
+// (mod q_i) is added to every entry of limb i of c0; c1 is copied.
+__global__ __launch_bounds__(TB) void k_add_const_b(ItemPtrs in, ItemPtrs out, const TwPair* __restrict__ consts,
+                                                    uint32_t level, const DevMod* __restrict__ mods, uint32_t log_n) {
+    const uint32_t k = blockIdx.x * TB + threadIdx.x;
+    const uint32_t row = blockIdx.y;
+    const size_t o = at(row, log_n, k);
+    uint64_t v = in.p[blockIdx.z][o];
+    if (row < level) v = add_mod(v, consts[(size_t)blockIdx.z * level + row].w, mods[row].q);
+    out.p[blockIdx.z][o] = v;
+}
+
+// HMUL tensors of one giant step of the encrypted-weight matrix-vector
+// product, summed over its J diagonal terms (Sec. 4.2, HMUL in place of
+// HMULPLAIN): d0 = sum e0 x0, d1 = sum (e0 x1 + e1 x0), d2 = sum e1 x1.
+__global__ __launch_bounds__(TB) void k_ct_dot_b(ItemPtrs e, uint32_t J, WsRef xs, uint64_t off_x, uint64_t ct_words,
+                                                 WsRef ws, uint64_t off_d, uint32_t level,
+                                                 const DevMod* __restrict__ mods, uint32_t log_n) {
+    const uint32_t k = blockIdx.x * TB + threadIdx.x;
+    const uint32_t i = blockIdx.y;
+    const DevMod md = mods[i];
+    const uint64_t* __restrict__ x = xs.base + (size_t)blockIdx.z * xs.stride + off_x;
+    const size_t o0 = at(i, log_n, k), o1 = at(level + i, log_n, k);
+    uint64_t d0 = 0, d1 = 0, d2 = 0;
+    for (uint32_t j = 0; j < J; ++j) {
+        const uint64_t* __restrict__ E = e.p[j];
+        const uint64_t e0 = E[o0], e1 = E[o1];
+        const uint64_t x0 = x[j * ct_words + o0], x1 = x[j * ct_words + o1];
+        d0 = add_mod(d0, mul_barrett(e0, x0, md), md.q);
+        d1 = add_mod(d1, add_mod(mul_barrett(e0, x1, md), mul_barrett(e1, x0, md), md.q), md.q);
+        d2 = add_mod(d2, mul_barrett(e1, x1, md), md.q);
+    }
+    uint64_t* __restrict__ d = ws_item(ws) + off_d;
+    d[o0] = d0;
+    d[o1] = d1;
+    d[at(2 * level + i, log_n, k)] = d2;
+}
+
 // out_z[b][i] = in_z[b][i] * c_z[i] (Shoup pairs, [n][level] on the device):
 // multiplication by an integer constant polynomial.
 __global__ __launch_bounds__(TB) void k_scale_const_b(ItemPtrs in, ItemPtrs out, const TwPair* __restrict__ consts,
@@ -647,6 +685,18 @@ void launch_pt_dot_b(uint32_t n, WsRef ws, uint64_t off_baby, uint64_t ct_words,
                      uint64_t off_acc, uint32_t level, const DevTables& t, uint32_t log_n, hipStream_t st) {
     hipLaunchKernelGGL(k_pt_dot_b, grid_nk(log_n, 2 * level, n), dim3(TB), 0, st, ws, off_baby, ct_words, pt, J,
                        off_acc, level, t.mods, log_n);
+}
+
+void launch_add_const_b(uint32_t n, const ItemPtrs& in, const ItemPtrs& out, const TwPair* consts, uint32_t level,
+                        const DevTables& t, uint32_t log_n, hipStream_t st) {
+    hipLaunchKernelGGL(k_add_const_b, grid_nk(log_n, 2 * level, n), dim3(TB), 0, st, in, out, consts, level, t.mods,
+                       log_n);
+}
+
+void launch_ct_dot_b(uint32_t n, const ItemPtrs& e, uint32_t J, WsRef xs, uint64_t off_x, uint64_t ct_words, WsRef ws,
+                     uint64_t off_d, uint32_t level, const DevTables& t, uint32_t log_n, hipStream_t st) {
+    hipLaunchKernelGGL(k_ct_dot_b, grid_nk(log_n, level, n), dim3(TB), 0, st, e, J, xs, off_x, ct_words, ws, off_d,
+                       level, t.mods, log_n);
 }
 
 void launch_scale_const_b(uint32_t n, const ItemPtrs& in, const ItemPtrs& out, const TwPair* consts, uint32_t level,

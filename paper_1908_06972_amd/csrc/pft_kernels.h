@@ -148,3 +148,12 @@ void launch_pt_dot_b(uint32_t n, WsRef ws, uint64_t off_baby, uint64_t ct_words,
 // out_z = in_z * consts[z][limb] (integer constant polynomial)
 void launch_scale_const_b(uint32_t n, const ItemPtrs& in, const ItemPtrs& out, const TwPair* consts, uint32_t level,
                           const DevTables& t, uint32_t log_n, hipStream_t st);
+// out_z = (in_z.c0 + consts[z][limb].w, in_z.c1): HADDPLAIN of a constant
+void launch_add_const_b(uint32_t n, const ItemPtrs& in, const ItemPtrs& out, const TwPair* consts, uint32_t level,
+                        const DevTables& t, uint32_t log_n, hipStream_t st);
+// Encrypted-weight products of one giant step: for item z, the HMUL tensor
+// sum_j E_j (x) X_{z,j} into ws_z + off_d as [3][level][N], with E_j =
+// e.p[j] (ciphertexts shared by all items, [2][level][N]) and X_{z,j} at
+// ws_z + off_x + j ct_words.  J <= PFT_MAX_ITEMS.
+void launch_ct_dot_b(uint32_t n, const ItemPtrs& e, uint32_t J, WsRef xs, uint64_t off_x, uint64_t ct_words, WsRef ws,
+                     uint64_t off_d, uint32_t level, const DevTables& t, uint32_t log_n, hipStream_t st);

@@ -100,6 +100,11 @@ SIGNATURES = [
     ("pft_ptmat_info", [_vp, _u32p], ctypes.c_int),
     ("pft_ptmat_destroy", [_vp], None),
     ("pft_ptmatvec", [_vp, _vp, ctypes.c_uint32, ctypes.POINTER(CtDesc), ctypes.POINTER(CtDesc)], ctypes.c_int),
+    ("pft_add_const", [_vp, ctypes.POINTER(CtDesc), ctypes.c_double, ctypes.POINTER(CtDesc)], ctypes.c_int),
+    ("pft_add_const_batch", [_vp, ctypes.c_uint32, ctypes.POINTER(CtDesc), _dblp, ctypes.POINTER(CtDesc)],
+     ctypes.c_int),
+    ("pft_ctmatvec", [_vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(CtDesc), ctypes.c_uint32,
+                      ctypes.POINTER(CtDesc), ctypes.POINTER(CtDesc)], ctypes.c_int),
     ("pft_ntt_forward", [_vp, _vp, ctypes.c_uint32, ctypes.c_uint32], ctypes.c_int),
     ("pft_ntt_inverse", [_vp, _vp, ctypes.c_uint32, ctypes.c_uint32], ctypes.c_int),
     ("pft_bconv_mode", [_vp, ctypes.c_int], ctypes.c_int),

@@ -1,0 +1,47 @@
+"""The predict step of PrivFT training with encrypted weights (Sec. 4.2) and
+its degree-2 softmax approximation, as a sequence of libpft calls; every
+step runs in the HIP kernels.
+
+Per batch of documents (client input: the count vector v split over n_in
+ciphertexts at level l, the word count w; model: the pre-rotated diagonals
+of H^T and O^T, encrypted by the model owner at scale q_{l-1} and
+q_{l-3}, levels l and l-2):
+  h = RESCALE(CtMatVec(E_H, v))        stage 1, v H with HMUL
+  h = RESCALE(h * (1/w))               the average (HMULPLAIN by a constant)
+  s = RESCALE(CtMatVec(E_O, h))        stage 2, h O with HMUL
+  y = (s + 2)^2 / 8 - 1/4              = s^2/8 + s/2 + 1/4, the softmax
+                                         approximation: two more levels
+Five levels in all; slot j of y holds the approximated softmax input of
+class j.
+"""
+
+from .inference import split_counts  # noqa: F401  (same client-side input layout)
+
+
+def softmax_approx(ctx, cts):
+    """X^2/8 + X/2 + 1/4 on a batch of ciphertexts, evaluated as
+    (X + 2)^2 / 8 - 1/4 so that only equal scales are added."""
+    n = len(cts)
+    a = ctx.add_const_batch(cts, [2.0] * n)
+    b = ctx.rescale_batch(ctx.mul_relin_batch(a, a))
+    c = ctx.rescale_batch(ctx.mul_const_batch(b, [0.125] * n))
+    return ctx.add_const_batch(c, [-0.25] * n)
+
+
+class EncryptedBowModel:
+    """Encrypted diagonals of H^T (dim x vocab) and O^T (classes x dim):
+    flat lists in [n_in][G][b] order, as pft_ctmatvec takes them."""
+
+    def __init__(self, stage1, stage2, dim, classes, n_in, t):
+        self.stage1, self.stage2 = stage1, stage2
+        self.dim, self.classes, self.n_in, self.t = dim, classes, n_in, t
+
+
+def predict_encrypted(ctx, model, inputs, words):
+    """inputs: per document a list of model.n_in ciphertexts; words: per
+    document the word count.  Returns one ciphertext per document."""
+    m = model
+    h = ctx.rescale_batch(ctx.ctmatvec(m.stage1, m.dim, m.t, m.n_in, inputs))
+    h = ctx.rescale_batch(ctx.mul_const_batch(h, [1.0 / float(w) for w in words]))
+    s = ctx.rescale_batch(ctx.ctmatvec(m.stage2, m.classes, m.dim, 1, [[x] for x in h]))
+    return softmax_approx(ctx, s)
