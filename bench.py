@@ -260,6 +260,7 @@ def parse():
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="run only this many untimed steps (for rocprofv3) and exit")
     ap.add_argument("--no-breakdown", action="store_true", help="skip the per-operation loops")
+    ap.add_argument("--no-predict", action="store_true", help="skip the encrypted-weight predict measurement")
     ap.add_argument("--serve-requests", type=int, default=1000,
                     help="requests of the serving measurement (0 skips it)")
     ap.add_argument("--summarize", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
@@ -414,6 +415,72 @@ def serving_bench(n_requests, rate=200.0, level=4, pool=16, budget_gib=16):
     for ctx, _, _ in sets.values():
         ctx.synchronize()
     return out
+
+
+def predict_bench(n_docs=32, level=6, reps=3):
+    """The predict step of training with encrypted weights (Sec. 4.2) at the
+    bag-of-words shapes (N = 2^15 prime chain, vocabulary 32768 = two input
+    ciphertexts, embedding 64, 8 classes): both weight matrices encrypted
+    (128 + 8 diagonal ciphertexts), a batch of documents at level `level`
+    (five levels consumed), then the degree-2 softmax approximation."""
+    import numpy as np
+
+    import synth as S
+    from paper_1908_06972_amd import ckks as L
+    from paper_1908_06972_amd import training as T
+
+    cfg = S.CONFIGS["C4"]
+    lp = L.Params.from_config(cfg)
+    ctx = L.Context(lp, 0)
+    n, t = lp.n, lp.n // 2
+    dim, classes, n_in = 64, 8, 2
+    kd = S.key_draws(61, n, lp.q)
+    ctx.set_secret(kd.s)
+    ctx.gen_public_key(kd.pk_a, kd.pk_e)
+    a, e = S.switch_key_draws(61, 0, n, lp.key_moduli(), lp.dnum)
+    ctx.gen_relin_key(a, e)
+    for st in sorted(set(T.rotation_steps(dim, t) + T.rotation_steps(classes, dim))):
+        a, e = S.switch_key_draws(61, 6000 + st, n, lp.key_moduli(), lp.dnum)
+        ctx.gen_rotation_key(st, a, e)
+    H, O = S.bow_weights(62, n_in * t, dim, classes)
+    seed = [7000]
+
+    def draws():
+        seed[0] += 1
+        d = S.enc_draws(seed[0], n)
+        return d.v, d.e0, d.e1
+
+    t0 = time.time()
+    model = T.EncryptedBowModel(T.encrypt_diagonals(ctx, H.T, dim, t, n_in, level, draws),
+                                T.encrypt_diagonals(ctx, O.T, classes, dim, 1, level - 2, draws),
+                                dim, classes, n_in, t)
+    counts, words = S.bow_documents(63, n_docs, n_in * t)
+    docs = []
+    for d in range(n_docs):
+        row = []
+        for c in range(n_in):
+            v, e0, e1 = draws()
+            row.append(ctx.encrypt(lp.encode(counts[d][c * t:(c + 1) * t].astype(np.float64), lp.scale), level,
+                                   lp.scale, v, e0, e1))
+        docs.append(row)
+    ctx.synchronize()
+    log("predict: model encrypted (%d + %d diagonals) and %d documents in %.1fs" % (
+        len(model.stage1), len(model.stage2), n_docs, time.time() - t0))
+    out = T.predict_encrypted(ctx, model, docs, list(words))
+    sec = timed(lambda: T.predict_encrypted(ctx, model, docs, list(words)), reps, ctx.synchronize)
+    err = 0.0
+    for d in range(2):
+        got = lp.decode(ctx.decrypt(out[d]), out[d].scale, classes).real
+        s = ((counts[d].astype(np.float64) @ H) / float(words[d])) @ O  # Alg. 1 steps 2-3 in fp64
+        err = max(err, float(np.max(np.abs(got - (s * s / 8 + s / 2 + 0.25)))))
+    res = {"docs_per_s": round(n_docs / sec, 2), "ms_per_batch": round(1000.0 * sec, 2), "batch": n_docs,
+           "level": level, "n": n, "limbs": lp.L, "vocab": n_in * t, "dim": dim, "classes": classes,
+           "max_abs_err_vs_fp64": err,
+           "note": "encrypted H and O (diagonal BSGS, HMUL + one relinearisation per giant step), 1/w, then "
+                   "X^2/8 + X/2 + 1/4; error of 2 documents against Alg. 1 steps 2-3 and the polynomial in fp64"}
+    log("predict: %s" % res)
+    ctx.close()
+    return res
 
 
 def timed(fn, reps, sync):
@@ -641,6 +708,9 @@ def main():
     serving = None
     if args.serve_requests > 0:
         serving = serving_bench(args.serve_requests)
+    predict = None
+    if not args.no_predict:
+        predict = predict_bench()
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample)...")
@@ -668,6 +738,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "serving": serving,
+        "predict": predict,
     }
     print(json.dumps(out), flush=True)
 

@@ -212,6 +212,12 @@ int pft_ptmat_create(pft_ctx* ctx, const double* M, uint32_t n_o, uint32_t n_i, 
                      pft_ptmat** out);
 int pft_ptmat_create_from_coeffs(pft_ctx* ctx, const int64_t* coeffs, uint32_t n_o, uint32_t n_i, uint32_t n_in,
                                  uint32_t level, double pt_scale, pft_ptmat** out);
+/* Client side (host only): the integer plaintexts of the pre-rotated
+ * diagonals P^c_{g,r} of M (same plan and layout as above), encoded with
+ * pft_encode at `scale`, written to out [n_in][G][b][N] (caller memory).
+ * Used to encrypt a model's diagonals for pft_ctmatvec (Sec. 4.2). */
+int pft_diagonals_encode(const pft_params* params, const double* M, uint32_t n_o, uint32_t n_i, uint32_t n_in,
+                         double scale, int64_t* out);
 /* n_o, n_i, n_in, level, b, G (host array of 6). */
 int pft_ptmat_info(const pft_ptmat* m, uint32_t* info);
 void pft_ptmat_destroy(pft_ptmat* m);

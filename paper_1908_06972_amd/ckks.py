@@ -60,6 +60,17 @@ class Params:
                                     float(self.scale if scale is None else scale), N.i64p(out)))
         return out
 
+    def diagonals_encode(self, M, n_o, n_i, n_in, scale) -> np.ndarray:
+        """Integer plaintexts [n_in][G][b][N] of the pre-rotated diagonals of
+        M (n_o x n_in*n_i) at `scale` (client side, host only)."""
+        Mc = np.ascontiguousarray(M, dtype=np.float64)
+        assert Mc.shape == (n_o, n_in * n_i)
+        b = 1 << ((int(n_o).bit_length() - 1 + 1) // 2)
+        G = n_o // b
+        out = np.empty((n_in, G, b, self.n), dtype=np.int64)
+        N.check(N.load().pft_diagonals_encode(self.handle, N.dblp(Mc), n_o, n_i, n_in, float(scale), N.i64p(out)))
+        return out
+
     def decode(self, residues, scale, n_slots=None) -> np.ndarray:
         res = np.ascontiguousarray(residues, dtype=np.uint64)
         n_slots = self.n // 2 if n_slots is None else n_slots

@@ -1628,18 +1628,17 @@ extern "C" int pft_ptmat_create_from_coeffs(pft_ctx* c, const int64_t* coeffs, u
     return PFT_OK;
 }
 
-extern "C" int pft_ptmat_create(pft_ctx* c, const double* M, uint32_t n_o, uint32_t n_i, uint32_t n_in,
-                                uint32_t level, pft_ptmat** out) {
-    if (!c || !M || !out) return fail(PFT_EINVAL, "null argument");
-    int r;
-    if ((r = ptmat_check(c, n_o, n_i, n_in, level))) return r;
-    const pft_params* P = c->P;
+extern "C" int pft_diagonals_encode(const pft_params* P, const double* M, uint32_t n_o, uint32_t n_i, uint32_t n_in,
+                                    double scale, int64_t* out) {
+    if (!P || !M || !out) return fail(PFT_EINVAL, "null argument");
     const uint32_t t = P->n / 2, cols = n_in * n_i;
+    if (!n_o || (n_o & (n_o - 1)) || !n_i || (n_i & (n_i - 1)) || n_i > t || n_o > n_i)
+        return fail(PFT_EINVAL, "need powers of two n_o <= n_i <= N/2");
+    if (n_in < 1) return fail(PFT_EINVAL, "n_in must be at least 1");
     uint32_t b, G;
     bsgs_plan(n_o, &b, &G);
-    const double pt_scale = (double)P->q[level - 1];
-    std::vector<int64_t> coeffs((size_t)n_in * G * b * P->n);
     std::vector<double> diag(t), zero(t, 0.0);
+    int r;
     for (uint32_t cc = 0; cc < n_in; ++cc)
         for (uint32_t g = 0; g < G; ++g)
             for (uint32_t rr = 0; rr < b; ++rr) {
@@ -1649,9 +1648,23 @@ extern "C" int pft_ptmat_create(pft_ctx* c, const double* M, uint32_t n_o, uint3
                     const uint32_t kk = (k + t - (g * b) % t) % t;
                     diag[k] = M[(size_t)(kk % n_o) * cols + (size_t)cc * n_i + (kk + i) % n_i];
                 }
-                int64_t* dst = coeffs.data() + (((size_t)cc * G + g) * b + rr) * P->n;
-                if ((r = pft_encode(P, diag.data(), zero.data(), t, pt_scale, dst))) return r;
+                int64_t* dst = out + (((size_t)cc * G + g) * b + rr) * P->n;
+                if ((r = pft_encode(P, diag.data(), zero.data(), t, scale, dst))) return r;
             }
+    return PFT_OK;
+}
+
+extern "C" int pft_ptmat_create(pft_ctx* c, const double* M, uint32_t n_o, uint32_t n_i, uint32_t n_in,
+                                uint32_t level, pft_ptmat** out) {
+    if (!c || !M || !out) return fail(PFT_EINVAL, "null argument");
+    int r;
+    if ((r = ptmat_check(c, n_o, n_i, n_in, level))) return r;
+    const pft_params* P = c->P;
+    uint32_t b, G;
+    bsgs_plan(n_o, &b, &G);
+    const double pt_scale = (double)P->q[level - 1];
+    std::vector<int64_t> coeffs((size_t)n_in * G * b * P->n);
+    if ((r = pft_diagonals_encode(P, M, n_o, n_i, n_in, pt_scale, coeffs.data()))) return r;
     return pft_ptmat_create_from_coeffs(c, coeffs.data(), n_o, n_i, n_in, level, pt_scale, out);
 }
 

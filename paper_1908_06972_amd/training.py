@@ -18,6 +18,39 @@ class j.
 from .inference import split_counts  # noqa: F401  (same client-side input layout)
 
 
+def bsgs_plan(n_o):
+    """(b, G): b = 2^ceil(log2(n_o)/2) baby steps, G = n_o / b giant steps
+    (the plan rule of pft_ptmatvec / pft_ctmatvec)."""
+    lg = int(n_o).bit_length() - 1
+    b = 1 << ((lg + 1) // 2)
+    return b, n_o // b
+
+
+def rotation_steps(n_o, n_i):
+    """Rotation keys a product with n_o outputs over period n_i needs."""
+    b, G = bsgs_plan(n_o)
+    steps = list(range(1, b)) + [g * b for g in range(1, G)]
+    s = n_o
+    while s < n_i:
+        steps.append(s)
+        s *= 2
+    return steps
+
+
+def encrypt_diagonals(ctx, M, n_o, n_i, n_in, level, draws):
+    """Client side: encode the pre-rotated diagonals of M at scale q_{level-1}
+    and encrypt each at `level`; draws() yields the encryption randomness
+    (v, e0, e1) of one ciphertext.  Flat list in [n_in][G][b] order."""
+    p = ctx.params
+    qs = float(p.q[level - 1])
+    plains = p.diagonals_encode(M, n_o, n_i, n_in, qs)
+    out = []
+    for m in plains.reshape(-1, p.n):
+        v, e0, e1 = draws()
+        out.append(ctx.encrypt(m, level, qs, v, e0, e1))
+    return out
+
+
 def softmax_approx(ctx, cts):
     """X^2/8 + X/2 + 1/4 on a batch of ciphertexts, evaluated as
     (X + 2)^2 / 8 - 1/4 so that only equal scales are added."""

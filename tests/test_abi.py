@@ -73,6 +73,26 @@ def test_library_encode_within_one_of_oracle(log_n):
     assert np.max(np.abs(sparse - C.encode(z[:5], P.n, P.scale))) <= 1
 
 
+@pytest.mark.parametrize("n_o,n_i,n_in", [(16, 2048, 2), (4, 16, 1), (8, 64, 3)])
+def test_library_diagonals_within_one_of_oracle(n_o, n_i, n_in):
+    """pft_diagonals_encode: the pre-rotated diagonals of the BSGS plan,
+    encoded, against the oracle's diagonals and encoder (Sec. 4.1/4.2)."""
+    from oracle import ptmatvec as PM
+    from paper_1908_06972_amd.ckks import Params
+    P = Params(12, 3, 60, 40, 1, 60, 1, 2 ** 40)
+    g = np.random.default_rng(n_o + n_i)
+    M = g.normal(0, 0.1, size=(n_o, n_in * n_i))
+    scale = 2.0 ** 38
+    lib = P.diagonals_encode(M, n_o, n_i, n_in, scale)
+    D = PM.prerotated_diagonals(M, n_o, n_i, n_in, P.n // 2)
+    b, G = PM.bsgs_plan(n_o)
+    assert lib.shape == (n_in, G, b, P.n)
+    for c in range(n_in):
+        for gg in range(G):
+            for r in range(b):
+                assert np.max(np.abs(lib[c, gg, r] - C.encode(D[c][gg][r], P.n, scale))) <= 1
+
+
 def test_library_decode_matches_oracle():
     from paper_1908_06972_amd.ckks import Params
     P = Params(12, 3, 60, 40, 1, 60, 1, 2 ** 40)

@@ -169,8 +169,16 @@ def test_predict_encrypted_values(world):
     V = 2 * t
     counts, words = S.bow_documents(91, 2, V, 20, 80)
     H, O = S.bow_weights(92, V, DIM, CLS)
-    model = GT.EncryptedBowModel(_lib_diags(w, H.T, DIM, t, 2, L, 9000), _lib_diags(w, O.T, CLS, DIM, 1, L - 2, 9500),
-                                 DIM, CLS, 2, t)
+    seed = [9500]
+
+    def draws():
+        seed[0] += 1
+        d = S.enc_draws(seed[0], w.n)
+        return d.v, d.e0, d.e1
+    # stage 1 through the oracle's diagonal layout and the library encoder,
+    # stage 2 through the library's own diagonal encoder
+    model = GT.EncryptedBowModel(_lib_diags(w, H.T, DIM, t, 2, L, 9000),
+                                 GT.encrypt_diagonals(w.ctx, O.T, CLS, DIM, 1, L - 2, draws), DIM, CLS, 2, t)
     docs = []
     for d in range(len(words)):
         v = counts[d].astype(np.float64)
