@@ -121,3 +121,13 @@ def test_mutant_softmax_wrong_shift(monkeypatch):
     real = T.hadd_const
     monkeypatch.setattr(T, "hadd_const", lambda P, x, v: real(P, x, 1.0 if v == 2.0 else v))
     _expect_fail(TT.test_encrypted_softmax_approx, fx)
+
+
+def test_mutant_colpack_half_totalsum(monkeypatch):
+    """TotalSum over half of the slots in the column-packed stage 1."""
+    from tests import test_oracle_colpack as TC
+    C.set_mul_mode(1)
+    fx = TC.make_small()
+    real = C.total_sum
+    monkeypatch.setattr(C, "total_sum", lambda P, x, n_slots, keys: real(P, x, n_slots // 2, keys))
+    _expect_fail(TC.test_stage1_replicates_column_dot, fx)
