@@ -225,6 +225,34 @@ void pft_ptmat_destroy(pft_ptmat* m);
  * out: n_docs ciphertexts (caller memory, 2*level*N each). */
 int pft_ptmatvec(pft_ctx* ctx, const pft_ptmat* m, uint32_t n_docs, const pft_ct* in, pft_ct* out);
 
+/* ---- plaintext dot products with TotalSum (Sec. 4.1, column packing) -----
+ * The paper's own packing of the inference: H packed vertically (plaintext
+ * H_{c,j} = rows c t .. c t + t - 1 of column j), one TotalSum per column
+ * (Alg. 2), and O packed horizontally (plaintext O_j = row j of O in slots
+ * 0 .. c-1).  A pft_ptdot holds n_out groups of J plaintexts P_{k,j}:
+ *   out[z][k] = TotalSum_{n_sum}( sum_j in[z][j] * P_{k,j} )
+ * (HMULPLAIN and HADD; TotalSum adds ROTATE by 1, 2, ..., n_sum/2, so with
+ * n_sum = t every slot holds the sum over all slots; n_sum = 1: no
+ * rotation).  Stage 1: n_out = n columns, J = ceil(m/t), n_sum = t; stage 2:
+ * n_out = 1, J = n, n_sum = 1.
+ * pft_ptdot_create encodes slot vectors [n_out][J][t] (doubles) with the
+ * encoder of pft_encode at scale q_{level-1}; ..._from_coeffs takes integer
+ * plaintexts [n_out][J][N] at pt_scale.  Device memory of the context,
+ * freed with it.
+ * pft_ptdot_apply: in n_docs * J ciphertexts (document-major) at the
+ * plaintexts' level with equal scales; out n_docs * n_out ciphertexts
+ * (caller memory); out scale = in scale * pt_scale, no rescale; needs the
+ * rotation keys 1, 2, ..., n_sum/2.  PFT_EINVAL if n_sum is not a power of
+ * two <= N/2. */
+typedef struct pft_ptdot pft_ptdot;
+int pft_ptdot_create(pft_ctx* ctx, const double* slots, uint32_t n_out, uint32_t J, uint32_t level,
+                     pft_ptdot** out);
+int pft_ptdot_create_from_coeffs(pft_ctx* ctx, const int64_t* coeffs, uint32_t n_out, uint32_t J, uint32_t level,
+                                 double pt_scale, pft_ptdot** out);
+void pft_ptdot_destroy(pft_ptdot* m);
+int pft_ptdot_apply(pft_ctx* ctx, const pft_ptdot* m, uint32_t n_docs, const pft_ct* in, uint32_t n_sum,
+                    pft_ct* out);
+
 /* ---- CtMatVec: encrypted matrix x encrypted vector (Sec. 4.2) ------------
  * The predict step of training with encrypted weights: the PtMatVec above
  * with the pre-rotated diagonals E^c_{g,r} given as ciphertexts (so each

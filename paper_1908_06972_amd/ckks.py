@@ -341,6 +341,36 @@ class Context:
         N.check(self.lib.pft_ctmatvec(self.handle, n_o, n_i, n_in, D, len(inputs), A, O))
         return [o.sync_from(O[i]) for i, o in enumerate(out)]
 
+    def ptdot(self, slots, level):
+        """Plaintexts P[k][j] from slot vectors [n_out][J][t] (library encoder,
+        scale q_{level-1})."""
+        sl = np.ascontiguousarray(slots, dtype=np.float64)
+        n_out, J, t = sl.shape
+        assert t == self.params.n // 2
+        h = ctypes.c_void_p()
+        N.check(self.lib.pft_ptdot_create(self.handle, N.dblp(sl), n_out, J, level, ctypes.byref(h)))
+        return PtDot(self, h, n_out, J, level)
+
+    def ptdot_from_coeffs(self, coeffs, level, pt_scale):
+        """Plaintexts P[k][j] from integer polynomials [n_out][J][N]."""
+        c = np.ascontiguousarray(coeffs, dtype=np.int64)
+        n_out, J, n = c.shape
+        assert n == self.params.n
+        h = ctypes.c_void_p()
+        N.check(self.lib.pft_ptdot_create_from_coeffs(self.handle, N.i64p(c), n_out, J, level, float(pt_scale),
+                                                      ctypes.byref(h)))
+        return PtDot(self, h, n_out, J, level)
+
+    def ptdot_apply(self, mat, inputs, n_sum=1, out=None):
+        """inputs: list over documents of lists of J ciphertexts; returns per
+        document a list of n_out ciphertexts."""
+        flat = [c for doc in inputs for c in doc]
+        outs = out or [self.empty_ct(mat.level) for _ in range(len(inputs) * mat.n_out)]
+        A, O = self._arr(flat), self._arr(outs)
+        N.check(self.lib.pft_ptdot_apply(self.handle, mat.handle, len(inputs), A, int(n_sum), O))
+        res = [o.sync_from(O[i]) for i, o in enumerate(outs)]
+        return [res[d * mat.n_out:(d + 1) * mat.n_out] for d in range(len(inputs))]
+
     def ptmat(self, M, n_o, n_i, n_in, level):
         """Plaintext matrix from doubles (library encoder)."""
         h = ctypes.c_void_p()
@@ -455,8 +485,21 @@ class PtMat:
         self.n_o, self.n_i, self.n_in, self.level, self.b, self.G = (int(x) for x in info)
 
     def __del__(self):
-        if getattr(self, "handle", None) is not None and N._lib is not None:
-            N._lib.pft_ptmat_destroy(self.handle)
+        if getattr(self, "handle", None) is not None:
+            self.ctx.lib.pft_ptmat_destroy(self.handle)
+            self.handle = None
+
+
+class PtDot:
+    """n_out groups of J plaintexts for pft_ptdot_apply."""
+
+    def __init__(self, ctx, handle, n_out, J, level):
+        self.ctx, self.handle = ctx, handle
+        self.n_out, self.J, self.level = n_out, J, level
+
+    def __del__(self):
+        if getattr(self, "handle", None) is not None:
+            self.ctx.lib.pft_ptdot_destroy(self.handle)
             self.handle = None
 
 

@@ -1913,6 +1913,139 @@ extern "C" int pft_ctmatvec(pft_ctx* c, uint32_t n_o, uint32_t n_i, uint32_t n_i
     return PFT_OK;
 }
 
+// ---- plaintext dot products with TotalSum (Sec. 4.1, column packing) ------
+struct pft_ptdot {
+    pft_ctx* ctx = nullptr;
+    uint32_t n_out = 0, J = 0, level = 0;
+    double pt_scale = 0;
+    uint64_t* pt = nullptr;  // [n_out][J][level][N], NTT domain, times 2^64 mod q
+};
+
+extern "C" int pft_ptdot_create_from_coeffs(pft_ctx* c, const int64_t* coeffs, uint32_t n_out, uint32_t J,
+                                            uint32_t level, double pt_scale, pft_ptdot** out) {
+    if (!c || !coeffs || !out) return fail(PFT_EINVAL, "null argument");
+    const pft_params* P = c->P;
+    if (!n_out || !J) return fail(PFT_EINVAL, "n_out and J must be positive");
+    if (level < 1 || level > P->L) return fail(PFT_ELEVEL, "plaintext level must be in 1..L");
+    const size_t N = P->n;
+    auto* m = new pft_ptdot();
+    m->ctx = c;
+    m->n_out = n_out;
+    m->J = J;
+    m->level = level;
+    m->pt_scale = pt_scale;
+    int r;
+    if ((r = dalloc(c, &m->pt, (size_t)n_out * J * level * N * 8))) {
+        delete m;
+        return r;
+    }
+    // stage PFT_SMALL_POLYS integer polynomials at a time through ws
+    if ((r = ensure_ws(c, (size_t)PFT_SMALL_POLYS * N * 8))) {
+        delete m;
+        return r;
+    }
+    const size_t total = (size_t)n_out * J;
+    for (size_t j0 = 0; j0 < total; j0 += PFT_SMALL_POLYS) {
+        const uint32_t nj = (uint32_t)std::min<size_t>(PFT_SMALL_POLYS, total - j0);
+        if ((r = upload_i64(c, (int64_t*)c->ws, coeffs + j0 * N, (size_t)nj * N))) {
+            delete m;
+            return r;
+        }
+        uint64_t* dst = m->pt + j0 * level * N;
+        SmallBatch sb = sb_rows(P, dst, nj, level, level);
+        launch_int_to_rns((const int64_t*)c->ws, sb, c->tabs, P->log_n, c->stream);
+        launch_mul_const(sb, sb, c->to_mont, c->tabs, P->log_n, c->stream);
+        ntt_rows(c, dst, nj, level, level, false);
+        HIPCK(hipStreamSynchronize(c->stream));  // the staged rows are reused next
+    }
+    *out = m;
+    return PFT_OK;
+}
+
+extern "C" int pft_ptdot_create(pft_ctx* c, const double* slots, uint32_t n_out, uint32_t J, uint32_t level,
+                                pft_ptdot** out) {
+    if (!c || !slots || !out) return fail(PFT_EINVAL, "null argument");
+    const pft_params* P = c->P;
+    if (level < 1 || level > P->L) return fail(PFT_ELEVEL, "plaintext level must be in 1..L");
+    const uint32_t t = P->n / 2;
+    const double pt_scale = (double)P->q[level - 1];
+    std::vector<int64_t> coeffs((size_t)n_out * J * P->n);
+    int r;
+    for (size_t u = 0; u < (size_t)n_out * J; ++u)
+        if ((r = pft_encode(P, slots + u * t, nullptr, t, pt_scale, coeffs.data() + u * P->n))) return r;
+    return pft_ptdot_create_from_coeffs(c, coeffs.data(), n_out, J, level, pt_scale, out);
+}
+
+extern "C" void pft_ptdot_destroy(pft_ptdot* m) { delete m; }  // device rows are freed with the context
+
+extern "C" int pft_ptdot_apply(pft_ctx* c, const pft_ptdot* m, uint32_t n_docs, const pft_ct* in, uint32_t n_sum,
+                               pft_ct* out) {
+    if (!c || !m || !in || !out) return fail(PFT_EINVAL, "null argument");
+    if (m->ctx != c) return fail(PFT_EINVAL, "plaintexts belong to another context");
+    const pft_params* P = c->P;
+    if (!n_sum || (n_sum & (n_sum - 1)) || n_sum > P->n / 2)
+        return fail(PFT_EINVAL, "n_sum must be a power of two <= N/2");
+    const uint32_t l = m->level, J = m->J, K = m->n_out, lg = P->log_n;
+    int r;
+    for (size_t u = 0; u < (size_t)n_docs * J; ++u) {
+        if ((r = check_ct(c, &in[u]))) return r;
+        if (in[u].level != l) return fail(PFT_ELEVEL, "input level %u differs from the plaintext level %u",
+                                          in[u].level, l);
+        if (!scales_match(in[u].scale, in[0].scale)) return fail(PFT_ESCALE, "inputs need equal scales");
+    }
+    for (size_t u = 0; u < (size_t)n_docs * K; ++u)
+        if (!out[u].data) return fail(PFT_EINVAL, "null output");
+    for (uint32_t s = 1; s < n_sum; s <<= 1)
+        if (!find_rot(c, (int32_t)s)) return fail(PFT_ENOKEY, "no rotation key for step %u", s);
+    if (n_docs == 0) return PFT_OK;
+    const double scale = in[0].scale * m->pt_scale;
+    const uint64_t ct_words = 2ull * l * P->n;
+    // per document in aux: inputs [J] | outputs [n_out]
+    const uint64_t off_out = (uint64_t)J * ct_words, stride = off_out + (uint64_t)K * ct_words;
+    if ((r = ensure_aux(c, (size_t)n_docs * stride * 8))) return r;
+    uint64_t* A = c->aux;
+    for (size_t z0 = 0; z0 < (size_t)n_docs * J; z0 += PFT_MAX_ITEMS) {
+        const uint32_t cnt = (uint32_t)std::min<size_t>(PFT_MAX_ITEMS, (size_t)n_docs * J - z0);
+        ItemPtrs I{}, O{};
+        for (uint32_t u = 0; u < cnt; ++u) {
+            const size_t z = (z0 + u) / J, j = (z0 + u) % J;
+            I.p[u] = in[z0 + u].data;
+            O.p[u] = A + z * stride + j * ct_words;
+        }
+        launch_copy_rows_b(cnt, I, 0, O, 0, 2 * l, lg, c->stream);
+    }
+    for (uint32_t k = 0; k < K; ++k) {
+        const uint64_t* ptk = m->pt + (size_t)k * J * l * P->n;
+        for (uint32_t z0 = 0; z0 < n_docs; z0 += 65535) {
+            const uint32_t cnt = std::min<uint32_t>(65535, n_docs - z0);
+            timed(c, PK_ELEMENTWISE, 8.0 * (double)cnt * ct_words * (J + 1) + 8.0 * J * l * P->n,
+                  (double)cnt * ct_words * J, [&] {
+                      launch_pt_dot_b(cnt, WsRef{A + z0 * stride, stride}, 0, ct_words, ptk, J,
+                                      off_out + (uint64_t)k * ct_words, l, c->tabs, lg, c->stream);
+                  });
+        }
+    }
+    std::vector<pft_ct> res;
+    res.reserve((size_t)n_docs * K);
+    for (uint32_t z = 0; z < n_docs; ++z)
+        for (uint32_t k = 0; k < K; ++k) res.push_back(pft_ct{A + z * stride + off_out + k * ct_words, l, 0, scale});
+    if (n_sum > 1 && (r = pft_total_sum_batch(c, (uint32_t)res.size(), res.data(), n_sum, res.data()))) return r;
+    for (size_t z0 = 0; z0 < res.size(); z0 += PFT_MAX_ITEMS) {
+        const uint32_t cnt = (uint32_t)std::min<size_t>(PFT_MAX_ITEMS, res.size() - z0);
+        ItemPtrs I{}, O{};
+        for (uint32_t u = 0; u < cnt; ++u) {
+            I.p[u] = res[z0 + u].data;
+            O.p[u] = out[z0 + u].data;
+        }
+        launch_copy_rows_b(cnt, I, 0, O, 0, 2 * l, lg, c->stream);
+    }
+    for (size_t u = 0; u < res.size(); ++u) {
+        out[u].level = l;
+        out[u].scale = scale;
+    }
+    return PFT_OK;
+}
+
 // ---------------------------------------------------------------------------
 // raw transforms
 // ---------------------------------------------------------------------------

@@ -1,0 +1,154 @@
+"""The paper's column-packed inference (Sec. 4.1 matrix packing) on the GPU.
+
+Bit-exact parity with the oracle uses integer plaintexts drawn by synth for
+the packed columns and rows and integer inputs (no encoder between the shared
+input and the compared residues): stage 1 (HMULPLAIN sums and one TotalSum
+per column) and the whole inference.  The library's encoder path is checked
+against Alg. 1 steps 2-3 in fp64 with argmax equality."""
+
+import math
+
+import numpy as np
+import pytest
+
+import synth as S
+from oracle import ckks as C
+from oracle import colpack as CP
+from oracle import ptmatvec as PM
+
+pytestmark = pytest.mark.gpu
+
+SMALL = dict(log_n=12, n_q=4, q0_bits=60, q_bits=40, n_p=2, p_bits=60, dnum=2, scale=2 ** 40)
+DIM, CLS = 8, 4
+
+
+class World:
+    def __init__(self):
+        import paper_1908_06972_amd.ckks as L
+        self.op = C.Params(**SMALL)
+        self.lp = L.Params(*SMALL.values())
+        assert self.op.q == self.lp.q and self.op.p == self.lp.p
+        C.set_mul_mode(1)
+        self.n = self.op.n
+        self.t = self.n // 2
+        self.ctx = L.Context(self.lp)
+        kd = S.key_draws(17, self.n, self.op.q)
+        self.kd = kd
+        self.ctx.set_secret(kd.s)
+        self.ctx.gen_public_key(kd.pk_a, kd.pk_e)
+        self.pk = C.public_key(self.op, kd.s, kd.pk_a, kd.pk_e)
+        self.keys = {}
+        for i in range(int(math.log2(self.t))):
+            st = 1 << i
+            a, e = S.switch_key_draws(17, 5000 + st, self.n, self.op.key_moduli(), self.op.dnum)
+            self.ctx.gen_rotation_key(st, a, e)
+            self.keys[st] = C.rotation_key(self.op, kd.s, st, a, e)
+
+    def enc_pair(self, m, level, seed):
+        d = S.enc_draws(seed, self.n)
+        return (self.ctx.encrypt(m, level, self.op.scale, d.v, d.e0, d.e1),
+                C.encrypt(self.op, self.pk, m, level, d.v, d.e0, d.e1, self.op.scale))
+
+    def assert_same(self, g, o):
+        host = self.ctx.export(g)
+        assert g.level == o.level and g.scale == o.scale
+        assert np.array_equal(host[0], o.c0) and np.array_equal(host[1], o.c1)
+
+
+@pytest.fixture(scope="module")
+def world():
+    import torch
+    assert torch.cuda.is_available()
+    return World()
+
+
+def _int_plains(seed, n_out, J, n, bound):
+    g = S.rng(seed)
+    return np.stack([np.stack([S.plaintext_coeffs(g, n, bound) for _ in range(J)]) for _ in range(n_out)])
+
+
+@pytest.mark.parametrize("n_in,n_sum,docs", [(3, 2048, 2), (1, 64, 1), (2, 1, 3)])
+def test_ptdot_parity(world, n_in, n_sum, docs):
+    """out[z][k] = TotalSum_{n_sum}(sum_j in[z][j] P_{k,j}) against the oracle."""
+    w = world
+    lvl = 4
+    plains = _int_plains(60 + n_in, DIM, n_in, w.n, 2 ** 20)
+    pt_scale = float(w.op.q[lvl - 1])
+    mat = w.ctx.ptdot_from_coeffs(plains, lvl, pt_scale)
+    ins = [[w.enc_pair(S.plaintext_coeffs(S.rng(610 + 3 * d + c), w.n, 2 ** 30), lvl, 620 + 3 * d + c)
+            for c in range(n_in)] for d in range(docs)]
+    outs = w.ctx.ptdot_apply(mat, [[x[0] for x in doc] for doc in ins], n_sum=n_sum)
+    for doc, gouts in zip(ins, outs):
+        for k, g in enumerate(gouts):
+            o = CP.dot_plain(w.op, [x[1] for x in doc], list(plains[k]), pt_scale)
+            if n_sum > 1:
+                o = C.total_sum(w.op, o, n_sum, w.keys)
+            w.assert_same(g, o)
+
+
+def test_colpack_inference_parity(world):
+    """The whole column-packed inference on integer plaintexts: bit-exact."""
+    from paper_1908_06972_amd import colpack as GC
+    w = world
+    L = w.op.L
+    n_in = 2
+    ph = _int_plains(71, DIM, n_in, w.n, 2 ** 20)
+    po = _int_plains(72, 1, DIM, w.n, 2 ** 20)
+    sh, so = float(w.op.q[L - 1]), float(w.op.q[L - 3])
+    model = GC.ColPackModel.__new__(GC.ColPackModel)
+    model.t, model.n_in, model.dim, model.classes = w.t, n_in, DIM, CLS
+    model.stage1 = w.ctx.ptdot_from_coeffs(ph, L, sh)
+    model.stage2 = w.ctx.ptdot_from_coeffs(po, L - 2, so)
+    ins = [[w.enc_pair(S.plaintext_coeffs(S.rng(730 + 2 * d + c), w.n, 2 ** 30), L, 740 + 2 * d + c)
+            for c in range(n_in)] for d in range(2)]
+    words = [45, 300]
+    outs = GC.encrypted_inference(w.ctx, model, [[x[0] for x in doc] for doc in ins], words)
+    for doc, wd, g in zip(ins, words, outs):
+        o = CP.inference(w.op, [x[1] for x in doc], [list(p) for p in ph], sh, list(po[0]), so, float(wd), w.keys,
+                         PM.constant_plain)
+        assert g.level == L - 3
+        w.assert_same(g, o)
+
+
+def test_colpack_inference_values(world):
+    """Library encoder end to end (ragged vocabulary): scores against Alg. 1
+    steps 2-3 in fp64, argmax equal."""
+    from paper_1908_06972_amd import colpack as GC
+    w = world
+    t, L = w.t, w.op.L
+    V = 3 * t - 77
+    counts, words = S.bow_documents(75, 3, V, 20, 80)
+    H, O = S.bow_weights(76, V, DIM, CLS)
+    model = GC.ColPackModel(w.ctx, H, O, L)
+    assert model.n_in == 3
+    docs = []
+    for d in range(len(words)):
+        v = np.zeros(3 * t)
+        v[:V] = counts[d]
+        row = []
+        for c in range(3):
+            dr = S.enc_draws(7600 + 3 * d + c, w.n)
+            row.append(w.ctx.encrypt(w.lp.encode(v[c * t:(c + 1) * t], w.op.scale), L, w.op.scale, dr.v, dr.e0,
+                                     dr.e1))
+        docs.append(row)
+    outs = GC.encrypted_inference(w.ctx, model, docs, list(words))
+    for d, g in enumerate(outs):
+        got = w.lp.decode(w.ctx.decrypt(g), g.scale, CLS).real
+        want = PM.inference_plain(counts[d].astype(np.float64), H, O, words[d])
+        assert np.max(np.abs(got - want)) <= 1e-5
+        srt = np.sort(want)
+        if srt[-1] - srt[-2] > 2e-5:
+            assert np.argmax(got) == np.argmax(want)
+
+
+def test_ptdot_errors(world):
+    w = world
+    mat = w.ctx.ptdot_from_coeffs(_int_plains(80, 2, 1, w.n, 2 ** 10), 3, float(w.op.q[2]))
+    x3 = w.enc_pair(S.plaintext_coeffs(S.rng(81), w.n, 2 ** 20), 3, 810)[0]
+    x2 = w.enc_pair(S.plaintext_coeffs(S.rng(82), w.n, 2 ** 20), 2, 820)[0]
+    with pytest.raises(RuntimeError):  # level differs from the plaintexts'
+        w.ctx.ptdot_apply(mat, [[x2]])
+    with pytest.raises(RuntimeError):  # n_sum not a power of two
+        w.ctx.ptdot_apply(mat, [[x3]], n_sum=3)
+    with pytest.raises(RuntimeError):  # n_sum beyond N/2
+        w.ctx.ptdot_apply(mat, [[x3]], n_sum=2 * w.t)
