@@ -261,6 +261,8 @@ def parse():
                     help="run only this many untimed steps (for rocprofv3) and exit")
     ap.add_argument("--no-breakdown", action="store_true", help="skip the per-operation loops")
     ap.add_argument("--no-predict", action="store_true", help="skip the encrypted-weight predict measurement")
+    ap.add_argument("--no-paper-inference", action="store_true",
+                    help="skip the inference at the paper's shapes (N=8192, 123 inputs)")
     ap.add_argument("--serve-requests", type=int, default=1000,
                     help="requests of the serving measurement (0 skips it)")
     ap.add_argument("--summarize", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
@@ -481,6 +483,79 @@ def predict_bench(n_docs=32, level=6, reps=3):
     log("predict: %s" % res)
     ctx.close()
     return res
+
+
+def paper_inference_bench(batch=8, classes=14):
+    """Encrypted fasttext inference at the paper's own inference shapes
+    (Sec. 6, Table 4: N = 8192, five 40-bit primes = log q 200, scale 2^40;
+    vocabulary m = 500000 -> 123 input ciphertexts, embedding n = 50), inputs
+    at the top level, three levels consumed.  Two packings of the same
+    products: the paper's column packing (one TotalSum per column of H,
+    n log2(t) rotations) and the diagonal BSGS form (rotations planned per
+    input count; H padded to 64 columns, O to 16 classes).  Per-example
+    latency (one document) and throughput over a batch."""
+    import numpy as np
+
+    import synth as S
+    from paper_1908_06972_amd import ckks as L
+    from paper_1908_06972_amd import colpack as CPK
+    from paper_1908_06972_amd.inference import BowModel, encrypted_inference
+    from paper_1908_06972_amd.training import bsgs_plan
+
+    lp = L.Params(13, 5, 40, 40, 1, 60, 5, 2 ** 40)
+    ctx = L.Context(lp, 0)
+    n, t = lp.n, lp.n // 2
+    vocab, dim = 500000, 50
+    n_in = -(-vocab // t)
+    kd = S.key_draws(81, n, lp.q)
+    ctx.set_secret(kd.s)
+    ctx.gen_public_key(kd.pk_a, kd.pk_e)
+    t0 = time.time()
+    H, O = S.bow_weights(82, vocab, dim, classes)
+    col = CPK.ColPackModel(ctx, H, O, lp.L)
+    Hp = np.zeros((vocab, 64))
+    Hp[:, :dim] = H
+    Op = np.zeros((64, classes))
+    Op[:dim] = O
+    diag = BowModel(ctx, Hp, Op, lp.L, n_in=n_in)
+    for st in sorted(set(col.rotation_steps()) | set(diag.rotation_steps())):
+        a, e = S.switch_key_draws(81, 8000 + st, n, lp.key_moduli(), lp.dnum)
+        ctx.gen_rotation_key(st, a, e)
+    counts, words = S.bow_documents(83, batch, vocab)
+    docs = []
+    for d in range(batch):
+        v = np.zeros(n_in * t)
+        v[:vocab] = counts[d]
+        row = []
+        for c in range(n_in):
+            dr = S.enc_draws(8300 + n_in * d + c, n)
+            row.append(ctx.encrypt(lp.encode(v[c * t:(c + 1) * t], lp.scale), lp.L, lp.scale, dr.v, dr.e0, dr.e1))
+        docs.append(row)
+    ctx.synchronize()
+    log("paper inference: models (%d column + %d diagonal plaintexts), keys and %d documents in %.1fs" % (
+        dim * n_in, 64 * n_in, batch, time.time() - t0))
+    b1, G1 = bsgs_plan(64, n_in)
+    b2, G2 = bsgs_plan(diag.c_pad, 1)
+    rot_diag = (n_in * (b1 - 1) + G1 - 1 + int(np.log2(t // 64))) + (b2 - 1 + G2 - 1 + int(np.log2(64 // diag.c_pad)))
+    out = {"n": n, "limbs": lp.L, "log_q": sum(int(q).bit_length() for q in lp.q), "vocab": vocab,
+           "input_ciphertexts": n_in, "dim": dim, "classes": classes, "batch": batch}
+    for name, run, rots in (("column", lambda ds: CPK.encrypted_inference(ctx, col, ds, list(words[:len(ds)])),
+                             dim * int(np.log2(t))),
+                            ("diagonal", lambda ds: encrypted_inference(ctx, diag, ds, list(words[:len(ds)])),
+                             rot_diag)):
+        res = run(docs[:1])
+        one = timed(lambda: run(docs[:1]), 3, ctx.synchronize)
+        many = timed(lambda: run(docs), 2, ctx.synchronize)
+        got = lp.decode(ctx.decrypt(res[0]), res[0].scale, classes).real
+        want = ((counts[0].astype(np.float64) @ H) / float(words[0])) @ O  # Alg. 1 steps 2-3 in fp64
+        out[name] = {"s_per_example": round(one, 5), "examples_per_s": round(batch / many, 2),
+                     "rotations_per_example": int(rots), "max_abs_err_vs_fp64": float(np.max(np.abs(got - want))),
+                     "argmax_equal": bool(np.argmax(got) == np.argmax(want))}
+        log("paper inference %s: %s" % (name, out[name]))
+    out["note"] = ("paper Table 4 (V100, same shapes): 0.23-0.66 s per example; column = the paper's packing "
+                   "(n TotalSums), diagonal = BSGS with %d baby x %d giant steps over %d inputs" % (b1, G1, n_in))
+    ctx.close()
+    return out
 
 
 def timed(fn, reps, sync):
@@ -711,6 +786,9 @@ def main():
     predict = None
     if not args.no_predict:
         predict = predict_bench()
+    paper_inf = None
+    if not args.no_paper_inference:
+        paper_inf = paper_inference_bench()
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample)...")
@@ -739,6 +817,7 @@ def main():
         "cpu_baseline": cpu,
         "serving": serving,
         "predict": predict,
+        "paper_inference": paper_inf,
     }
     print(json.dumps(out), flush=True)
 

@@ -192,9 +192,11 @@ int pft_add_const_batch(pft_ctx* ctx, uint32_t n, const pft_ct* in, const double
 
 /* ---- PtMatVec: plaintext matrix x encrypted vector (Sec. 4.1, v H and h O)
  * Matrix M (n_o x n_in*n_i, row-major doubles) acting on an input split over
- * n_in ciphertexts whose t = N/2 slots hold a vector periodic with period
+ * n_in ciphertexts (1 <= n_in <= 4096) whose t = N/2 slots hold a vector periodic with period
  * n_i (n_o | n_i | t, powers of two).  Diagonal method, baby-step/giant-step
- * form with b = 2^ceil(log2(n_o)/2) baby steps and G = n_o/b giant steps:
+ * form with b baby steps and G = n_o/b giant steps, b the power of two that
+ * minimises the rotations n_in (b - 1) + (G - 1) of one product (the larger
+ * b on ties; b = 2^ceil(log2(n_o)/2) for n_in = 1):
  *   D^c_i[k] = M[k mod n_o][c n_i + (k+i) mod n_i],   i = g b + r,
  *   P^c_{g,r} = D^c_{gb+r} rotated right by g b (pre-rotated, encoded at
  *               scale q_{level-1}),

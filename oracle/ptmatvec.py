@@ -22,9 +22,11 @@ P^c_{g,r} = rot(D^c_{g b + r}, -g b):
 
   u = sum_g rot( sum_c sum_r P^c_{g,r} * rot(v_c, r), g b ).
 
-Plan rule (shared convention, stated here and in the library header):
-b = 2^ceil(log2(n_o)/2), G = n_o / b.  Rotation steps used: 1..b-1,
-g b for 1 <= g < G, and n_o 2^s for s < log2(n_i/n_o).
+Plan rule (shared convention, stated here and in the library header): b
+minimises the rotations of one product, n_in (b - 1) + (G - 1) with
+G = n_o / b, the larger b on ties (b = 2^ceil(log2(n_o)/2) for one input
+ciphertext).  Rotation steps used: 1..b-1, g b for 1 <= g < G, and
+n_o 2^s for s < log2(n_i/n_o).
 """
 
 import math
@@ -34,16 +36,20 @@ import numpy as np
 from . import ckks as C
 
 
-def bsgs_plan(n_o: int):
-    """(b, G) for n_o diagonals, both powers of two, b * G = n_o."""
+def bsgs_plan(n_o: int, n_in: int = 1):
+    """(b, G) for n_o diagonals over n_in input ciphertexts, both powers of
+    two, b * G = n_o: the b that minimises the rotations of one product,
+    n_in (b - 1) + (G - 1), the larger b on ties (for n_in = 1,
+    b = 2^ceil(log2(n_o)/2))."""
     if n_o < 1 or n_o & (n_o - 1):
         raise ValueError("n_o must be a power of two")
-    b = 1 << ((int(math.log2(n_o)) + 1) // 2)
+    cands = [1 << k for k in range(int(math.log2(n_o)) + 1)]
+    b = min(cands, key=lambda bb: (n_in * (bb - 1) + n_o // bb - 1, -bb))
     return b, n_o // b
 
 
-def rotation_steps(n_o: int, n_i: int):
-    b, G = bsgs_plan(n_o)
+def rotation_steps(n_o: int, n_i: int, n_in: int = 1):
+    b, G = bsgs_plan(n_o, n_in)
     steps = list(range(1, b)) + [g * b for g in range(1, G)]
     s = n_o
     while s < n_i:
@@ -61,7 +67,7 @@ def diagonal(M, n_o, n_i, c, i, t):
 def prerotated_diagonals(M, n_o, n_i, n_in, t):
     """P[c][g][r] = rot(D^c_{g b + r}, -g b) as length-t real vectors, where
     rot(x, s)[k] = x[(k + s) mod t] (left rotation by s)."""
-    b, G = bsgs_plan(n_o)
+    b, G = bsgs_plan(n_o, n_in)
     out = []
     for c in range(n_in):
         per_c = []
@@ -78,7 +84,7 @@ def prerotated_diagonals(M, n_o, n_i, n_in, t):
 def slot_bsgs(P, vs, n_o, n_i):
     """The BSGS evaluation on plain slot vectors (numpy), the same sequence
     of rotations, products and sums as the encrypted evaluation."""
-    b, G = bsgs_plan(n_o)
+    b, G = bsgs_plan(n_o, len(vs))
     rot = lambda x, s: np.roll(x, -s)  # noqa: E731  (left rotation by s)
     baby = [[v if r == 0 else rot(v, r) for r in range(b)] for v in vs]
     total = None
@@ -98,7 +104,7 @@ def ptmatvec(params, inputs, plains, n_o, n_i, rot_keys, pt_scale):
     """Encrypted BSGS PtMatVec: inputs[c] ciphertexts, plains[c][g][r]
     integer plaintext polynomials (pre-rotated diagonals encoded at pt_scale),
     rot_keys {step: SwitchKey}.  No rescale."""
-    b, G = bsgs_plan(n_o)
+    b, G = bsgs_plan(n_o, len(inputs))
     baby = [[v if r == 0 else C.rotate(params, v, r, rot_keys[r]) for r in range(b)] for v in inputs]
     total = None
     for g in range(G):

@@ -81,7 +81,7 @@ def ctmatvec(params, inputs, diags, n_o, n_i, rlk, rot_keys):
     of the vector parts; diags[c][g][r]: ciphertexts of the pre-rotated
     diagonals, all at the inputs' level and of equal scale.  No rescale:
     the result has scale diag scale x input scale."""
-    b, G = bsgs_plan(n_o)
+    b, G = bsgs_plan(n_o, len(inputs))
     baby = [[v if r == 0 else C.rotate(params, v, r, rot_keys[r]) for r in range(b)] for v in inputs]
     scale = diags[0][0][0].scale * inputs[0].scale
     total = None

@@ -65,8 +65,8 @@ class Params:
         M (n_o x n_in*n_i) at `scale` (client side, host only)."""
         Mc = np.ascontiguousarray(M, dtype=np.float64)
         assert Mc.shape == (n_o, n_in * n_i)
-        b = 1 << ((int(n_o).bit_length() - 1 + 1) // 2)
-        G = n_o // b
+        from .training import bsgs_plan
+        b, G = bsgs_plan(n_o, n_in)
         out = np.empty((n_in, G, b, self.n), dtype=np.int64)
         N.check(N.load().pft_diagonals_encode(self.handle, N.dblp(Mc), n_o, n_i, n_in, float(scale), N.i64p(out)))
         return out

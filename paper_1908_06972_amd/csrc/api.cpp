@@ -1564,10 +1564,19 @@ struct pft_ptmat {
     uint64_t* pt = nullptr;  // [G][n_in * b][level][N], NTT domain, times 2^64 mod q
 };
 
-static void bsgs_plan(uint32_t n_o, uint32_t* b, uint32_t* G) {
-    uint32_t lg = 0;
-    while ((1u << lg) < n_o) ++lg;
-    *b = 1u << ((lg + 1) / 2);
+// Baby-step count b (a power of two dividing n_o) that minimises the key
+// switches of one product, n_in (b - 1) baby rotations of the inputs plus
+// G - 1 giant rotations of the partial sums (G = n_o / b); ties go to the
+// larger b.  For n_in = 1 this is b = 2^ceil(log2(n_o)/2).
+static void bsgs_plan(uint32_t n_o, uint32_t n_in, uint32_t* b, uint32_t* G) {
+    uint64_t best = ~0ull;
+    for (uint32_t bb = 1; bb <= n_o; bb <<= 1) {
+        const uint64_t cost = (uint64_t)n_in * (bb - 1) + (n_o / bb - 1);
+        if (cost <= best) {
+            best = cost;
+            *b = bb;
+        }
+    }
     *G = n_o / *b;
 }
 
@@ -1575,7 +1584,7 @@ static int ptmat_check(const pft_ctx* c, uint32_t n_o, uint32_t n_i, uint32_t n_
     const uint32_t t = c->P->n / 2;
     if (!n_o || (n_o & (n_o - 1)) || !n_i || (n_i & (n_i - 1)) || n_i > t || n_o > n_i)
         return fail(PFT_EINVAL, "need powers of two n_o <= n_i <= N/2");
-    if (n_in < 1 || n_in > 64) return fail(PFT_EINVAL, "n_in must be in 1..64");
+    if (n_in < 1 || n_in > 4096) return fail(PFT_EINVAL, "n_in must be in 1..4096");
     if (level < 2 || level > c->P->L) return fail(PFT_ELEVEL, "plaintext matrix level must be in 2..L");
     return PFT_OK;
 }
@@ -1619,7 +1628,7 @@ extern "C" int pft_ptmat_create_from_coeffs(pft_ctx* c, const int64_t* coeffs, u
     m->n_in = n_in;
     m->level = level;
     m->pt_scale = pt_scale;
-    bsgs_plan(n_o, &m->b, &m->G);
+    bsgs_plan(n_o, n_in, &m->b, &m->G);
     if ((r = ptmat_upload(c, m, coeffs))) {
         delete m;
         return r;
@@ -1636,7 +1645,7 @@ extern "C" int pft_diagonals_encode(const pft_params* P, const double* M, uint32
         return fail(PFT_EINVAL, "need powers of two n_o <= n_i <= N/2");
     if (n_in < 1) return fail(PFT_EINVAL, "n_in must be at least 1");
     uint32_t b, G;
-    bsgs_plan(n_o, &b, &G);
+    bsgs_plan(n_o, n_in, &b, &G);
     std::vector<double> diag(t), zero(t, 0.0);
     int r;
     for (uint32_t cc = 0; cc < n_in; ++cc)
@@ -1661,7 +1670,7 @@ extern "C" int pft_ptmat_create(pft_ctx* c, const double* M, uint32_t n_o, uint3
     if ((r = ptmat_check(c, n_o, n_i, n_in, level))) return r;
     const pft_params* P = c->P;
     uint32_t b, G;
-    bsgs_plan(n_o, &b, &G);
+    bsgs_plan(n_o, n_in, &b, &G);
     const double pt_scale = (double)P->q[level - 1];
     std::vector<int64_t> coeffs((size_t)n_in * G * b * P->n);
     if ((r = pft_diagonals_encode(P, M, n_o, n_i, n_in, pt_scale, coeffs.data()))) return r;
@@ -1804,7 +1813,7 @@ extern "C" int pft_ctmatvec(pft_ctx* c, uint32_t n_o, uint32_t n_i, uint32_t n_i
     pft_ptmat plan;  // only the plan fields, for the rotation steps
     plan.n_o = n_o;
     plan.n_i = n_i;
-    bsgs_plan(n_o, &plan.b, &plan.G);
+    bsgs_plan(n_o, n_in, &plan.b, &plan.G);
     const uint32_t b = plan.b, G = plan.G, J = n_in * b;
     if (J > PFT_MAX_ITEMS) return fail(PFT_EINVAL, "n_in * b = %u exceeds %u diagonal terms per giant step", J,
                                        (unsigned)PFT_MAX_ITEMS);

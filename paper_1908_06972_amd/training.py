@@ -18,17 +18,24 @@ class j.
 from .inference import split_counts  # noqa: F401  (same client-side input layout)
 
 
-def bsgs_plan(n_o):
-    """(b, G): b = 2^ceil(log2(n_o)/2) baby steps, G = n_o / b giant steps
-    (the plan rule of pft_ptmatvec / pft_ctmatvec)."""
-    lg = int(n_o).bit_length() - 1
-    b = 1 << ((lg + 1) // 2)
-    return b, n_o // b
+def bsgs_plan(n_o, n_in=1):
+    """(b, G), the plan rule of pft_ptmatvec / pft_ctmatvec: the power of two
+    b minimising n_in (b - 1) + (n_o / b - 1) rotations, larger b on ties;
+    G = n_o / b."""
+    best = None
+    bb = 1
+    while bb <= n_o:
+        cost = n_in * (bb - 1) + n_o // bb - 1
+        if best is None or cost <= best[0]:
+            best = (cost, bb)
+        bb *= 2
+    return best[1], n_o // best[1]
 
 
-def rotation_steps(n_o, n_i):
-    """Rotation keys a product with n_o outputs over period n_i needs."""
-    b, G = bsgs_plan(n_o)
+def rotation_steps(n_o, n_i, n_in=1):
+    """Rotation keys a product with n_o outputs over period n_i and n_in
+    input ciphertexts needs."""
+    b, G = bsgs_plan(n_o, n_in)
     steps = list(range(1, b)) + [g * b for g in range(1, G)]
     s = n_o
     while s < n_i:

@@ -85,7 +85,7 @@ def test_library_diagonals_within_one_of_oracle(n_o, n_i, n_in):
     scale = 2.0 ** 38
     lib = P.diagonals_encode(M, n_o, n_i, n_in, scale)
     D = PM.prerotated_diagonals(M, n_o, n_i, n_in, P.n // 2)
-    b, G = PM.bsgs_plan(n_o)
+    b, G = PM.bsgs_plan(n_o, n_in)
     assert lib.shape == (n_in, G, b, P.n)
     for c in range(n_in):
         for gg in range(G):

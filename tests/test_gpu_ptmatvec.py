@@ -58,7 +58,7 @@ def small():
 
 
 def _random_plains(seed, n_in, n_o, n, bound):
-    b, G = PM.bsgs_plan(n_o)
+    b, G = PM.bsgs_plan(n_o, n_in)
     g = S.rng(seed)
     arr = np.stack([np.stack([np.stack([S.plaintext_coeffs(g, n, bound) for _ in range(b)]) for _ in range(G)])
                     for _ in range(n_in)])
@@ -72,7 +72,7 @@ def test_ptmatvec_parity(small):
     plains = _random_plains(5, n_in, n_o, w.n, 2 ** 30)
     pt_scale = float(w.op.q[lvl - 1])
     mat = w.ctx.ptmat_from_coeffs(plains, n_o, n_i, n_in, lvl, pt_scale)
-    assert (mat.b, mat.G) == PM.bsgs_plan(n_o)
+    assert (mat.b, mat.G) == PM.bsgs_plan(n_o, n_in)
     docs = [[w.enc_pair(S.plaintext_coeffs(S.rng(100 + 2 * d + c), w.n, 2 ** 40), lvl, 200 + 2 * d + c)
              for c in range(n_in)] for d in range(3)]
     outs = w.ctx.ptmatvec(mat, [[x[0] for x in doc] for doc in docs])

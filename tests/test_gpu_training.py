@@ -60,7 +60,7 @@ class World:
 
     def enc_diag_pairs(self, n_o, n_in, level, seed, bound):
         """Encrypted integer diagonals, [n_in][G][b] on both sides."""
-        b, G = PM.bsgs_plan(n_o)
+        b, G = PM.bsgs_plan(n_o, n_in)
         qs = float(self.op.q[level - 1])
         g = S.rng(seed)
         gpu, orc, k = [], [], 0

@@ -23,8 +23,25 @@ def test_bsgs_plan(n_o):
     assert b == 2 ** math.ceil(math.log2(n_o) / 2)
 
 
+@pytest.mark.parametrize("n_o,n_in", [(n_o, n_in) for n_o in (1, 2, 4, 8, 16, 64, 256) for n_in in (1, 2, 3, 5, 17, 123)])
+def test_bsgs_plan_minimises_rotations(n_o, n_in):
+    """b minimises n_in (b - 1) + (n_o/b - 1) over powers of two (brute
+    force), the larger b on ties."""
+    b, G = PM.bsgs_plan(n_o, n_in)
+    cost = lambda bb: n_in * (bb - 1) + n_o // bb - 1  # noqa: E731
+    cands = [1 << k for k in range(int(math.log2(n_o)) + 1)]
+    best = min(cost(bb) for bb in cands)
+    assert cost(b) == best and b == max(bb for bb in cands if cost(bb) == best) and b * G == n_o
+
+
+def test_bsgs_plan_examples():
+    assert PM.bsgs_plan(64, 1) == (8, 8) and PM.bsgs_plan(64, 2) == (8, 8)
+    assert PM.bsgs_plan(64, 123) == (1, 64)  # many inputs: giant steps only
+    assert PM.bsgs_plan(16, 5) == (2, 8)
+
+
 @pytest.mark.parametrize("n_o,n_i,n_in,t", [(4, 16, 1, 16), (8, 64, 2, 64), (8, 64, 1, 512), (64, 1024, 2, 1024),
-                                            (16, 16, 1, 256), (1, 8, 3, 32)])
+                                            (16, 16, 1, 256), (1, 8, 3, 32), (16, 64, 5, 64), (64, 64, 9, 128)])
 def test_slot_bsgs_equals_matvec(n_o, n_i, n_in, t):
     """Slot k of the BSGS result equals (M v)_{k mod n_o}, where the input is
     n_in vectors of t slots, each periodic with period n_i."""
