@@ -113,6 +113,21 @@ int pft_gen_public_key(pft_ctx* ctx, const uint64_t* a, const int64_t* e);
  * (rotation of the slots by `step` to the left).  Keys stay in device memory. */
 int pft_gen_relin_key(pft_ctx* ctx, const uint64_t* a, const int64_t* e);
 int pft_gen_rotation_key(pft_ctx* ctx, int32_t step, const uint64_t* a, const int64_t* e);
+/* Rotation-key cache (keys beyond the HBM budget; Sec. 6.5 notes that at
+ * logN = 16 the rotation keys were kept in host memory and migrated per
+ * use).  max_resident = 0 (default): every rotation key stays in device
+ * memory.  max_resident = k > 0: each rotation key generated afterwards
+ * keeps a pinned host copy, and at most k keys occupy device slots; using a
+ * non-resident key copies it into a slot on the context stream, evicting
+ * the least recently used key (an eviction synchronizes the device first,
+ * so no queued kernel still reads the slot).  Must be set before the first
+ * rotation key is generated (PFT_EINVAL otherwise).  With a limited cache,
+ * rotations are refused during graph capture (PFT_EINVAL: a replay would
+ * read whatever key then occupies the slot).  The relinearisation key is never
+ * cached.  pft_key_cache_stats writes {max_resident, slots allocated, hits,
+ * misses, bytes copied to the device} to out[5]. */
+int pft_set_key_cache(pft_ctx* ctx, uint32_t max_resident);
+int pft_key_cache_stats(const pft_ctx* ctx, uint64_t* out);
 /* Number of device bytes held by keys and tables. */
 int pft_ctx_device_bytes(const pft_ctx* ctx, uint64_t* bytes);
 

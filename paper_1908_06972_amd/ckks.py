@@ -180,6 +180,16 @@ class Context:
     def gen_relin_key(self, a, e):
         N.check(self.lib.pft_gen_relin_key(self.handle, N.u64p(_u64(a)), N.i64p(_i64(e))))
 
+    def set_key_cache(self, max_resident: int):
+        """Keep at most max_resident rotation keys on the device (0: all);
+        the others live in pinned host memory and are copied in on use."""
+        N.check(self.lib.pft_set_key_cache(self.handle, int(max_resident)))
+
+    def key_cache_stats(self):
+        out = np.zeros(5, dtype=np.uint64)
+        N.check(self.lib.pft_key_cache_stats(self.handle, N.u64p(out)))
+        return dict(zip(("max_resident", "slots", "hits", "misses", "bytes_in"), (int(x) for x in out)))
+
     def gen_rotation_key(self, step, a, e):
         N.check(self.lib.pft_gen_rotation_key(self.handle, int(step), N.u64p(_u64(a)), N.i64p(_i64(e))))
 

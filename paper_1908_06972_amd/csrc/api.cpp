@@ -142,6 +142,11 @@ extern "C" int pft_params_dims(const pft_params* P, uint32_t* d) {
 // ---------------------------------------------------------------------------
 struct SwitchKeyDev {
     uint64_t* data = nullptr;  // [dnum][2][L+K][N], NTT domain, times 2^64 mod m
+    // rotation keys under a limited key cache: pinned host copy, and the
+    // cache slot that holds data while the key is resident
+    uint64_t* host = nullptr;
+    int slot = -1;
+    uint64_t last_use = 0;
 };
 
 // HIP-event bracketing of kernel families on the context stream.
@@ -206,6 +211,13 @@ struct pft_ctx {
     uint64_t* pk = nullptr;  // [2][L][N] (b, a), NTT domain
     SwitchKeyDev rlk;
     std::map<int32_t, SwitchKeyDev> rot;  // keyed by step mod N/2
+    // rotation-key cache (0 = every key resident): at most rot_cache_max keys
+    // in device slots, all keys in pinned host memory, least recently used
+    // key evicted on a miss
+    uint32_t rot_cache_max = 0;
+    std::vector<uint64_t*> rot_slots;
+    std::vector<int32_t> rot_slot_owner;  // normalised step, or -1
+    uint64_t rot_clock = 0, rot_hits = 0, rot_misses = 0, rot_bytes_in = 0;
     uint64_t* ws = nullptr;  // scratch of one operation (key switching etc.)
     size_t ws_bytes = 0;
     uint64_t* aux = nullptr;  // buffers of composite operations (PtMatVec) that call other operations
@@ -512,6 +524,8 @@ extern "C" void pft_ctx_destroy(pft_ctx* c) {
     if (c->aux) (void)hipFree(c->aux);
     if (c->cbuf) (void)hipFree(c->cbuf);
     for (void* p : c->retired) (void)hipFree(p);
+    for (auto& kv : c->rot)
+        if (kv.second.host) (void)hipHostFree(kv.second.host);
     for (hipStream_t st : c->side) {
         (void)hipStreamSynchronize(st);
         (void)hipStreamDestroy(st);
@@ -792,6 +806,49 @@ extern "C" int pft_gen_public_key(pft_ctx* c, const uint64_t* a, const int64_t* 
 }
 
 // s_prime: [L+K][N] NTT domain (device).  Builds the switching key into *dst.
+static size_t key_bytes(const pft_params* P) { return (size_t)P->dnum * 2 * (P->L + P->K) * P->n * 8; }
+
+// A device slot for rotation key `step` under the limited key cache: a free
+// slot, a new one below the limit, else the least recently used key's slot
+// (that key becomes non-resident; the device is synchronised first so no
+// queued kernel still reads the slot).  Sets the key's data and slot.
+static int key_slot(pft_ctx* c, int32_t step) {
+    int idx = -1;
+    for (size_t i = 0; i < c->rot_slot_owner.size(); ++i)
+        if (c->rot_slot_owner[i] < 0) {
+            idx = (int)i;
+            break;
+        }
+    if (idx < 0 && c->rot_slots.size() < c->rot_cache_max) {
+        uint64_t* p = nullptr;
+        int r;
+        if ((r = dalloc(c, &p, key_bytes(c->P)))) return r;
+        c->rot_slots.push_back(p);
+        c->rot_slot_owner.push_back(-1);
+        idx = (int)c->rot_slots.size() - 1;
+    }
+    if (idx < 0) {
+        uint64_t oldest = ~0ull;
+        for (size_t i = 0; i < c->rot_slots.size(); ++i) {
+            const SwitchKeyDev& o = c->rot[c->rot_slot_owner[i]];
+            if (o.last_use < oldest) {
+                oldest = o.last_use;
+                idx = (int)i;
+            }
+        }
+        HIPCK(hipDeviceSynchronize());
+        SwitchKeyDev& victim = c->rot[c->rot_slot_owner[idx]];
+        victim.data = nullptr;
+        victim.slot = -1;
+    }
+    SwitchKeyDev& k = c->rot[step];
+    c->rot_slot_owner[idx] = step;
+    k.data = c->rot_slots[idx];
+    k.slot = idx;
+    k.last_use = ++c->rot_clock;
+    return PFT_OK;
+}
+
 static int gen_switch_key(pft_ctx* c, const uint64_t* s_prime, const uint64_t* a, const int64_t* e,
                           SwitchKeyDev* dst) {
     const pft_params* P = c->P;
@@ -873,8 +930,42 @@ extern "C" int pft_gen_rotation_key(pft_ctx* c, int32_t step, const uint64_t* a,
     if (!c->s_prime && (r = dalloc(c, &c->s_prime, (size_t)R * P->n * 8))) return r;
     launch_automorphism_b(1, one_item(c->s), R, WsRef{c->s_prime, 0}, 0, galois_element(step, P->n), P->log_n,
                           c->stream);
-    SwitchKeyDev& k = c->rot[norm_step(step, P->n)];
-    return gen_switch_key(c, c->s_prime, a, e, &k);
+    const int32_t ns = norm_step(step, P->n);
+    SwitchKeyDev& k = c->rot[ns];
+    if (!c->rot_cache_max) return gen_switch_key(c, c->s_prime, a, e, &k);
+    // limited key cache: generate into a slot, keep the pinned host copy
+    const size_t bytes = key_bytes(P);
+    if (!k.host) {
+        void* h = nullptr;
+        if (hipHostMalloc(&h, bytes, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            c->rot.erase(ns);
+            return fail(PFT_ENOMEM, "pinned host memory for a rotation key (%zu bytes)", bytes);
+        }
+        k.host = (uint64_t*)h;
+    }
+    if (!k.data && (r = key_slot(c, ns))) return r;
+    if ((r = gen_switch_key(c, c->s_prime, a, e, &k))) return r;
+    HIPCK(hipMemcpyAsync(k.host, k.data, bytes, hipMemcpyDeviceToHost, c->stream));
+    HIPCK(hipStreamSynchronize(c->stream));
+    return PFT_OK;
+}
+
+extern "C" int pft_set_key_cache(pft_ctx* c, uint32_t max_resident) {
+    if (!c) return fail(PFT_EINVAL, "null ctx");
+    if (!c->rot.empty()) return fail(PFT_EINVAL, "set the key cache before generating rotation keys");
+    c->rot_cache_max = max_resident;
+    return PFT_OK;
+}
+
+extern "C" int pft_key_cache_stats(const pft_ctx* c, uint64_t* out) {
+    if (!c || !out) return fail(PFT_EINVAL, "null argument");
+    out[0] = c->rot_cache_max;
+    out[1] = c->rot_slots.size();
+    out[2] = c->rot_hits;
+    out[3] = c->rot_misses;
+    out[4] = c->rot_bytes_in;
+    return PFT_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -1296,9 +1387,43 @@ extern "C" int pft_rescale_batch(pft_ctx* c, uint32_t n, const pft_ct* in, uint3
     });
 }
 
-static const SwitchKeyDev* find_rot(pft_ctx* c, int32_t step) {
-    auto it = c->rot.find(norm_step(step, c->P->n));
-    return it == c->rot.end() ? nullptr : &it->second;
+static bool has_rot(pft_ctx* c, int32_t step) { return c->rot.count(norm_step(step, c->P->n)) != 0; }
+
+// The rotation key for `step`, made resident first under a limited key
+// cache (a miss copies the pinned host copy into a slot on the context
+// stream; with a limited cache nothing is captured).  Null with *err set if
+// the key is missing or cannot be made resident.
+static const SwitchKeyDev* use_rot(pft_ctx* c, int32_t step, int* err) {
+    const int32_t ns = norm_step(step, c->P->n);
+    auto it = c->rot.find(ns);
+    if (it == c->rot.end()) {
+        *err = fail(PFT_ENOKEY, "no rotation key for step %d", step);
+        return nullptr;
+    }
+    SwitchKeyDev& k = it->second;
+    if (c->capturing && c->rot_cache_max) {
+        // a replay would read whatever key then occupies the slot
+        *err = fail(PFT_EINVAL, "rotations cannot be captured while the rotation-key cache is limited");
+        return nullptr;
+    }
+    if (k.data) {
+        k.last_use = ++c->rot_clock;
+        if (c->rot_cache_max) ++c->rot_hits;
+        return &k;
+    }
+    int r;
+    if ((r = key_slot(c, ns))) {
+        *err = r;
+        return nullptr;
+    }
+    const size_t bytes = key_bytes(c->P);
+    if (hipMemcpyAsync(k.data, k.host, bytes, hipMemcpyHostToDevice, c->stream) != hipSuccess) {
+        *err = fail(PFT_EHIP, "rotation key upload: %s", hipGetErrorString(hipGetLastError()));
+        return nullptr;
+    }
+    ++c->rot_misses;
+    c->rot_bytes_in += bytes;
+    return &k;
 }
 
 extern "C" int pft_rotate(pft_ctx* c, const pft_ct* in, int32_t step, pft_ct* out) {
@@ -1307,14 +1432,15 @@ extern "C" int pft_rotate(pft_ctx* c, const pft_ct* in, int32_t step, pft_ct* ou
 
 extern "C" int pft_rotate_batch(pft_ctx* c, uint32_t n, const pft_ct* in, int32_t step, pft_ct* out) {
     if (!c || !in || !out) return fail(PFT_EINVAL, "null argument");
-    const SwitchKeyDev* key = find_rot(c, step);
-    if (!key) return fail(PFT_ENOKEY, "no rotation key for step %d", step);
+    if (!has_rot(c, step)) return fail(PFT_ENOKEY, "no rotation key for step %d", step);
     int r;
     for (uint32_t i = 0; i < n; ++i) {
         if ((r = check_ct(c, &in[i]))) return r;
         if (!out[i].data) return fail(PFT_EINVAL, "null output");
         if (out[i].data == in[i].data) return fail(PFT_EINVAL, "rotate output aliases its input");
     }
+    const SwitchKeyDev* key = use_rot(c, step, &r);
+    if (!key) return r;
     const pft_params* P = c->P;
     const uint64_t kappa = galois_element(step, P->n);
     return for_level_groups(n, in, [&](const std::vector<uint32_t>& g) -> int {
@@ -1360,7 +1486,7 @@ extern "C" int pft_rotate_pow2_batch(pft_ctx* c, uint32_t n, const pft_ct* in, i
     const uint32_t half = P->n / 2;
     const uint32_t rr0 = (uint32_t)(((int64_t)step % (int64_t)half + half) % half);
     for (uint32_t k = 0; (1u << k) < half; ++k)
-        if (((rr0 >> k) & 1u) && !find_rot(c, (int32_t)(1u << k)))
+        if (((rr0 >> k) & 1u) && !has_rot(c, (int32_t)(1u << k)))
             return fail(PFT_ENOKEY, "no rotation key for step %u", 1u << k);
     const uint32_t lg = P->log_n;
     return for_level_groups(n, in, [&](const std::vector<uint32_t>& g) -> int {
@@ -1385,8 +1511,10 @@ extern "C" int pft_rotate_pow2_batch(pft_ctx* c, uint32_t n, const pft_ct* in, i
             timed(c, PK_AUTOMORPHISM, 8.0 * 4 * nl * cnt, 0, [&] {
                 launch_automorphism_b(cnt, ws_items(ws, cnt, src), 2 * l, ws, dst, kappa, lg, c->stream);
             });
-            key_switch_b(c, cnt, ws, K, dst + nl, *find_rot(c, (int32_t)(1u << k)), dst, PFT_NO_OFFSET,
-                         ws_items(ws, cnt, dst));
+            int ke;
+            const SwitchKeyDev* rk = use_rot(c, (int32_t)(1u << k), &ke);
+            if (!rk) return ke;
+            key_switch_b(c, cnt, ws, K, dst + nl, *rk, dst, PFT_NO_OFFSET, ws_items(ws, cnt, dst));
             cur = 1 - cur;
         }
         launch_copy_rows_b(cnt, ws_items(ws, cnt, offs[cur]), 0, O, 0, 2 * l, lg, c->stream);
@@ -1412,7 +1540,7 @@ extern "C" int pft_total_sum_batch(pft_ctx* c, uint32_t n, const pft_ct* in, uin
     if (n_slots < 1 || n_slots > c->P->n / 2 || (n_slots & (n_slots - 1)))
         return fail(PFT_EINVAL, "n_slots must be a power of two <= N/2");
     for (uint32_t s = 1; s < n_slots; s <<= 1)
-        if (!find_rot(c, (int32_t)s)) return fail(PFT_ENOKEY, "no rotation key for step %u", s);
+        if (!has_rot(c, (int32_t)s)) return fail(PFT_ENOKEY, "no rotation key for step %u", s);
     const pft_params* P = c->P;
     const uint32_t lg = P->log_n;
     return for_level_groups(n, in, [&](const std::vector<uint32_t>& g) -> int {
@@ -1435,7 +1563,10 @@ extern "C" int pft_total_sum_batch(pft_ctx* c, uint32_t n, const pft_ct* in, uin
             const uint64_t kappa = galois_element((int32_t)s, P->n);
             timed(c, PK_AUTOMORPHISM, 8.0 * 4 * nl * cnt, 0,
                   [&] { launch_automorphism_b(cnt, CUR, 2 * l, ws, off_rot, kappa, lg, c->stream); });
-            key_switch_b(c, cnt, ws, K, off_rot + nl, *find_rot(c, (int32_t)s), off_rot, PFT_NO_OFFSET, ROT);
+            int ke;
+            const SwitchKeyDev* rk = use_rot(c, (int32_t)s, &ke);
+            if (!rk) return ke;
+            key_switch_b(c, cnt, ws, K, off_rot + nl, *rk, off_rot, PFT_NO_OFFSET, ROT);
             launch_add_ct_b(cnt, ws, off_cur, off_rot, off_cur, l, c->tabs, lg, c->stream);
         }
         launch_copy_rows_b(cnt, CUR, 0, O, 0, 2 * l, lg, c->stream);
@@ -1721,7 +1852,7 @@ extern "C" int pft_ptmatvec(pft_ctx* c, const pft_ptmat* m, uint32_t n_docs, con
         }
     }
     for (uint32_t st : ptmat_steps(m))
-        if (!find_rot(c, (int32_t)st)) return fail(PFT_ENOKEY, "no rotation key for step %u", st);
+        if (!has_rot(c, (int32_t)st)) return fail(PFT_ENOKEY, "no rotation key for step %u", st);
     if (n_docs == 0) return PFT_OK;
     const double scale = in[0].scale;
     const uint64_t ct_words = 2ull * l * P->n;
@@ -1836,7 +1967,7 @@ extern "C" int pft_ctmatvec(pft_ctx* c, uint32_t n_o, uint32_t n_i, uint32_t n_i
         }
     }
     for (uint32_t st : ptmat_steps(&plan))
-        if (!find_rot(c, (int32_t)st)) return fail(PFT_ENOKEY, "no rotation key for step %u", st);
+        if (!has_rot(c, (int32_t)st)) return fail(PFT_ENOKEY, "no rotation key for step %u", st);
     if (n_docs == 0) return PFT_OK;
     const double scale = in[0].scale * diags[0].scale;
     const uint32_t lg = P->log_n;
@@ -2005,7 +2136,7 @@ extern "C" int pft_ptdot_apply(pft_ctx* c, const pft_ptdot* m, uint32_t n_docs, 
     for (size_t u = 0; u < (size_t)n_docs * K; ++u)
         if (!out[u].data) return fail(PFT_EINVAL, "null output");
     for (uint32_t s = 1; s < n_sum; s <<= 1)
-        if (!find_rot(c, (int32_t)s)) return fail(PFT_ENOKEY, "no rotation key for step %u", s);
+        if (!has_rot(c, (int32_t)s)) return fail(PFT_ENOKEY, "no rotation key for step %u", s);
     if (n_docs == 0) return PFT_OK;
     const double scale = in[0].scale * m->pt_scale;
     const uint64_t ct_words = 2ull * l * P->n;
