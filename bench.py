@@ -416,6 +416,28 @@ def serving_bench(n_requests, rate=200.0, level=4, pool=16, budget_gib=16):
         log("serving %s: %s" % (mode, out[mode]))
     for ctx, _, _ in sets.values():
         ctx.synchronize()
+    # the same sets with a 2 GiB rotation-key budget: keys beyond each set's
+    # share live in pinned host memory and are copied in on use
+    kbudget = 2 << 30
+    t0 = time.time()
+    sets_c, policies_c, words_c, _ = build_sets(specs, H, O, pool_size=pool, level=level, draws=S,
+                                                key_budget_bytes=kbudget)
+    res_c = sum(ctx.device_bytes() for ctx, _, _ in sets_c.values())
+    log("serving: key-cache sets ready in %.1fs, %.2f GiB resident" % (time.time() - t0, res_c / 2 ** 30))
+    ex_c = GpuExecutor(sets_c)
+    n_c = min(n_requests, 300)
+    trace = poisson_trace(507, n_c, rate, SERVING_MIX, {k: pool for k in specs}, words_c)
+    st = Scheduler(ex_c, policies_c, budget_gib << 30, continuous=True).run(trace)
+    cache = {k: ctx.key_cache_stats() for k, (ctx, _, _) in sets_c.items()}
+    out["keys_over_budget"] = {
+        "rotation_key_budget_gib": kbudget / 2 ** 30, "resident_gib": round(res_c / 2 ** 30, 3), "requests": n_c,
+        "continuous": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.summary().items()},
+        "key_cache": {k: {"resident_keys": v["max_resident"], "misses": v["misses"], "hits": v["hits"],
+                          "gib_copied": round(v["bytes_in"] / 2 ** 30, 2)} for k, v in cache.items()}}
+    log("serving keys over budget: %s" % out["keys_over_budget"])
+    for ctx, _, _ in sets_c.values():
+        ctx.synchronize()
+        ctx.close()
     return out
 
 

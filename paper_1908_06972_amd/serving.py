@@ -258,11 +258,20 @@ def request_bytes(params, n_in, b, level):
     return (n_in + n_in * b + 3 + 4) * ct + ks
 
 
-def build_sets(specs, H, O, pool_size, level, draws, key_seed=77, doc_seed=78):
-    """One context (own HIP stream), resident keys, plaintext model and a
+def key_bytes(params):
+    """Device bytes of one switching key: [dnum][2][L+K][N] words."""
+    return params.dnum * 2 * (params.L + params.K) * params.n * 8
+
+
+def build_sets(specs, H, O, pool_size, level, draws, key_seed=77, doc_seed=78, key_budget_bytes=None):
+    """One context (own HIP stream), evaluation keys, plaintext model and a
     pool of encrypted documents per parameter set.
     specs: {name: WorkloadConfig-like}; draws: the seeded input module
     providing key_draws/switch_key_draws/enc_draws/bow_documents.
+    key_budget_bytes: device bytes for rotation keys across all sets (None:
+    every key resident); a set whose keys exceed its equal share keeps as
+    many as fit in device slots and the rest in pinned host memory (the
+    rotation-key cache), so it is still admitted.
     Returns (executor sets, policies, word counts, plain counts)."""
     import torch
 
@@ -279,7 +288,13 @@ def build_sets(specs, H, O, pool_size, level, draws, key_seed=77, doc_seed=78):
         ctx.set_secret(kd.s)
         ctx.gen_public_key(kd.pk_a, kd.pk_e)
         model = BowModel(ctx, H, O, level)
-        for st in model.rotation_steps():
+        steps = model.rotation_steps()
+        if key_budget_bytes is not None:
+            share = key_budget_bytes // len(specs)
+            kb = key_bytes(lp)
+            if len(steps) * kb > share:
+                ctx.set_key_cache(max(1, share // kb))
+        for st in steps:
             a, e = draws.switch_key_draws(key_seed, 5000 + st, n, lp.key_moduli(), lp.dnum)
             ctx.gen_rotation_key(st, a, e)
         counts, w = draws.bow_documents(doc_seed, pool_size, vocab)

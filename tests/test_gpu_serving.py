@@ -36,3 +36,30 @@ def test_mixed_stream_results_independent_of_batching():
         got = lp.decode(ctx.decrypt(mixed), mixed.scale, model.classes).real
         want = PM.inference_plain(counts[r.pset][r.doc].astype(np.float64), H, O, r.words)
         assert np.max(np.abs(got - want)) <= 1e-5
+
+
+def test_keys_beyond_budget_served_through_the_key_cache():
+    """With a rotation-key budget below the sets' keys, each set keeps a few
+    keys on the device and the rest in pinned host memory; every request
+    completes with the same result as with all keys resident."""
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1908_06972_amd.serving import GpuExecutor, Scheduler, build_sets, key_bytes, poisson_trace
+    specs = {"n12": WorkloadConfig("n12", 12, 4, 60, 40, 2, 60, 2, 40)}
+    H, O = S.bow_weights(9, 4096, 16, 4)
+    full, pol_f, words, _ = build_sets(specs, H, O, pool_size=4, level=4, draws=S)
+    from paper_1908_06972_amd.ckks import Params
+    kb = key_bytes(Params.from_config(specs["n12"]))
+    small, pol_s, words_s, _ = build_sets(specs, H, O, pool_size=4, level=4, draws=S, key_budget_bytes=3 * kb)
+    ctx_s = small["n12"][0]
+    assert ctx_s.key_cache_stats()["max_resident"] == 3
+    assert ctx_s.device_bytes() < full["n12"][0].device_bytes()
+    trace = poisson_trace(506, 12, 2000.0, {"n12": 1}, {"n12": 4}, words_s)
+    stats = Scheduler(GpuExecutor(small), pol_s, budget_bytes=8 << 30).run(trace)
+    assert stats.summary()["completed"] == len(trace)
+    assert ctx_s.key_cache_stats()["misses"] > 0
+    from paper_1908_06972_amd.inference import encrypted_inference
+    ctx_f, model_f, pool_f = full["n12"]
+    for r in trace:
+        ref = encrypted_inference(ctx_f, model_f, [pool_f[r.doc]], [r.words])[0]
+        assert np.array_equal(ctx_f.export(ref), ctx_s.export(r.result)), r.rid
