@@ -380,7 +380,7 @@ static int build_tables(pft_ctx* c) {
             }
         }
     }
-    std::vector<TwPair> phatinv(K), pinv(L), gadget(L), tomont(L + K);
+    std::vector<TwPair> phatinv(K), pinv(2 * L), gadget(L), tomont(L + K);
     std::vector<uint64_t> downc((size_t)K * L);
     for (uint32_t k = 0; k < K; ++k) {
         uint64_t h = 1;
@@ -398,6 +398,7 @@ static int build_tables(pft_ctx* c) {
         uint64_t pm = 1;
         for (uint32_t o = 0; o < K; ++o) pm = mulmod(pm, P->p[o] % P->q[i], P->q[i]);
         pinv[i] = pair(invmod(pm, P->q[i]), P->q[i]);
+        pinv[L + i] = twiddle(invmod(pm, P->q[i]), P->q[i]);  // fp64 form for q < 2^50
         gadget[i] = pair(pm, P->q[i]);
     }
     for (uint32_t m = 0; m < L + K; ++m) tomont[m] = pair(to_mont(1, P->mods[m]), P->mods[m]);
@@ -1270,6 +1271,7 @@ static void key_switch_b(pft_ctx* c, uint32_t n, WsRef ws, const KsLayout& K, ui
         }
         for (uint32_t z = 0; z < n; ++z) epi.out[z] = out.p[z];
         epi.pinv = c->kc.down_pinv;
+        epi.pinv_fp = c->kc.down_pinv + P->L;
         epi.level = level;
         ntt_jobs(c, jobs, level, ~0u, false, 0, &epi);
     }

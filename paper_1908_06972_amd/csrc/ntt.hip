@@ -330,14 +330,27 @@ __global__ __launch_bounds__(4096 >> EB) void k_ntt_pass(PolyBatch b, const DevM
     [[maybe_unused]] const uint32_t bsel = poly & 1u;
     [[maybe_unused]] uint64_t* __restrict__ out_row =
         EPI ? ep.out[poly >> 1] + ((size_t)(bsel * ep.level + row) << log_n) : nullptr;
-    [[maybe_unused]] const TwPair pinv = EPI ? ep.pinv[row] : TwPair{0, 0};
+    [[maybe_unused]] const TwPair pinv = EPI ? (fp ? ep.pinv_fp[row] : ep.pinv[row]) : TwPair{0, 0};
+    // store of element j from its register form v (integer-valued double
+    // within 3q for fp64 limbs; for integer limbs finish() reduces it)
     auto put = [&](size_t j, uint64_t v) {
         if constexpr (EPI) {
-            uint64_t r = shoup(data[j + ep.d_acc[bsel]] + q - v, pinv.w, pinv.wp, q);
-            if (ep.d_add[bsel] != PFT_EPI_NO_ADD) r = add_mod(r, data[j + ep.d_add[bsel]], q);
+            uint64_t r;
+            if (fp) {
+#pragma clang fp contract(off)
+                // (acc - conv) P^-1 with |acc - conv| < 4q: within 3q/2; the
+                // addend (< q) keeps it within 5q/2 before the final reduction
+                double y = fmulmod(as_f(fp_from_u64(data[j + ep.d_acc[bsel]])) - as_f(v), as_f(pinv.w),
+                                   as_f(pinv.wp), qd);
+                if (ep.d_add[bsel] != PFT_EPI_NO_ADD) y += as_f(fp_from_u64(data[j + ep.d_add[bsel]]));
+                r = fp_to_u64(as_u(y), qd, qinv);
+            } else {
+                r = shoup(data[j + ep.d_acc[bsel]] + q - finish(v), pinv.w, pinv.wp, q);
+                if (ep.d_add[bsel] != PFT_EPI_NO_ADD) r = add_mod(r, data[j + ep.d_add[bsel]], q);
+            }
             out_row[j] = r;
         } else {
-            data[j] = v;
+            data[j] = finish(v);
         }
     };
     if constexpr (DIRECT_OUT && VEC_OUT && !EPI) {
@@ -351,7 +364,7 @@ __global__ __launch_bounds__(4096 >> EB) void k_ntt_pass(PolyBatch b, const DevM
         }
     } else if constexpr (DIRECT_OUT) {
 #pragma unroll
-        for (int e = 0; e < E; ++e) put(gidx(c, POUT::r_of(l, e)), finish(x[e]));
+        for (int e = 0; e < E; ++e) put(gidx(c, POUT::r_of(l, e)), x[e]);
     } else {
         lds_write<LOG_M, PH_OUT, EB>(x, lds, c, l);
         __syncthreads();
@@ -359,7 +372,7 @@ __global__ __launch_bounds__(4096 >> EB) void k_ntt_pass(PolyBatch b, const DevM
         for (int k = 0; k < E; ++k) {
             const uint32_t idx = tid + NT * k;
             const uint32_t cc = idx / M, r = idx % M;
-            put(gidx(cc, r), finish(lds[lds_at<LOG_M, EB>(cc, r)]));
+            put(gidx(cc, r), lds[lds_at<LOG_M, EB>(cc, r)]);
         }
     }
 }

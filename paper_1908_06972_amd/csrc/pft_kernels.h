@@ -48,7 +48,8 @@ struct NttEpilogue {
     int64_t d_acc[2];
     int64_t d_add[2];
     uint64_t* out[PFT_MAX_POLYS / 2];  // per item of the launch: [2][level][N]
-    const TwPair* pinv;                // [L]: P^-1 mod q_i
+    const TwPair* pinv;                // [L]: P^-1 mod q_i (Shoup pairs)
+    const TwPair* pinv_fp;             // [L]: the same as (w, w/q) doubles, used where q_i < 2^50
     uint32_t level;
 };
 bool ntt_supported(uint32_t log_n);
@@ -105,7 +106,7 @@ struct KsConsts {
     const uint64_t* modup_c;      // [L][dnum][alpha][L+K] Montgomery form, row = target row
     const TwPair* down_phatinv;   // [K]
     const uint64_t* down_c;       // [K][L] Montgomery form
-    const TwPair* down_pinv;      // [L]
+    const TwPair* down_pinv;      // [2L]: Shoup pairs, then fp64 pairs
     // MFMA base conversion: int8 digit operands, one 64-bit word per lane
     // ModUp:   [L][dnum][up_rt][up_kb][64]   (level-1, digit, row tile, k block, lane)
     // ModDown: [down_rt][down_kb][64]
