@@ -56,11 +56,13 @@ __device__ __forceinline__ void inv_bfly(uint64_t& X, uint64_t& Y, uint64_t w, u
 }
 
 // ---- fp64 butterflies (q < 2^50): fmulmod / freduce in pft_device.h
-// Forward: X is reduced only on the even stages of a pass (pass-local index).
-// With inputs within B q a reducing stage leaves (1 + B/4) q and a skipping
-// one (5B/4 + 1/2) q; a pass starts with a reducing stage and never has two
-// skipping ones in a row, so from inputs below 4q the bound stays at most 3q
-// (it settles at 1.64q / 2.55q), far inside the exact range of fmulmod.
+// Forward: X is reduced on every third stage of a pass (pass-local stage
+// index = 0 mod 3).  With inputs within B q a reducing stage leaves
+// (1 + B/4) q and a skipping one (5B/4 + 1/2) q.  A pass starts with a
+// reducing stage, so at most two skipping stages follow one another; from
+// inputs below 4q the bound settles at 2.1q after a reducing stage and stays
+// below 4.5q (|values| < 2^53, and fmulmod's quotient is then off by at most
+// 1/2 + 4.5/4, so every step stays exact).
 __device__ __forceinline__ void fwd_bfly_fp(uint64_t& X, uint64_t& Y, const TwPair& tp, double q, double qinv,
                                             bool reduce_x) {
 #pragma clang fp contract(off)
@@ -69,10 +71,15 @@ __device__ __forceinline__ void fwd_bfly_fp(uint64_t& X, uint64_t& Y, const TwPa
     X = as_u(x + t);
     Y = as_u(x - t);
 }
-__device__ __forceinline__ void inv_bfly_fp(uint64_t& X, uint64_t& Y, const TwPair& tp, double q, double qinv) {
+// Inverse: X + Y is left unreduced on every third stage of a pass (stages in
+// execution order, index = 2 mod 3).  Inputs within B q give X within q/2
+// (reduced) or 2B q (not), Y within (1/2 + B/2) q; with two reducing stages
+// between skipping ones the bound settles at 1.5q and stays below 4q.
+__device__ __forceinline__ void inv_bfly_fp(uint64_t& X, uint64_t& Y, const TwPair& tp, double q, double qinv,
+                                            bool reduce_x) {
 #pragma clang fp contract(off)
     const double x = as_f(X), y = as_f(Y);
-    X = as_u(freduce(x + y, q, qinv));
+    X = as_u(reduce_x ? freduce(x + y, q, qinv) : x + y);
     Y = as_u(fmulmod(x - y, as_f(tp.w), as_f(tp.wp), q));
 }
 // Register phase PH of a radix-2^LOG_M pass with E = 2^EB residues per
@@ -118,7 +125,7 @@ __device__ __forceinline__ void run_phase(uint64_t (&x)[1 << EB], uint32_t l, ui
                 if (e & (1 << pos)) continue;
                 const TwPair tp = twt[(1u << s) + tw_index<LOG_M, PH, EB>(l, e, bit, high, spp)];
                 if constexpr (FP)
-                    fwd_bfly_fp(x[e], x[e | (1 << pos)], tp, qd, qinv, (spp & 1) == 0);
+                    fwd_bfly_fp(x[e], x[e | (1 << pos)], tp, qd, qinv, spp % 3 == 0);
                 else
                     fwd_bfly(x[e], x[e | (1 << pos)], tp.w, tp.wp, q, two_q);
             }
@@ -152,7 +159,7 @@ __device__ __forceinline__ void run_phase(uint64_t (&x)[1 << EB], uint32_t l, ui
                     if (e & (1 << pos)) continue;
                     const TwPair tp = twt[(1u << s) + tw_index<LOG_M, PH, EB>(l, e, bit, high, spp)];
                     if constexpr (FP)
-                        inv_bfly_fp(x[e], x[e | (1 << pos)], tp, qd, qinv);
+                        inv_bfly_fp(x[e], x[e | (1 << pos)], tp, qd, qinv, bit % 3 != 2);
                     else
                         inv_bfly(x[e], x[e | (1 << pos)], tp.w, tp.wp, q, two_q);
                 }
@@ -332,14 +339,14 @@ __global__ __launch_bounds__(4096 >> EB) void k_ntt_pass(PolyBatch b, const DevM
         EPI ? ep.out[poly >> 1] + ((size_t)(bsel * ep.level + row) << log_n) : nullptr;
     [[maybe_unused]] const TwPair pinv = EPI ? (fp ? ep.pinv_fp[row] : ep.pinv[row]) : TwPair{0, 0};
     // store of element j from its register form v (integer-valued double
-    // within 3q for fp64 limbs; for integer limbs finish() reduces it)
+    // within 4.5q for fp64 limbs; for integer limbs finish() reduces it)
     auto put = [&](size_t j, uint64_t v) {
         if constexpr (EPI) {
             uint64_t r;
             if (fp) {
 #pragma clang fp contract(off)
-                // (acc - conv) P^-1 with |acc - conv| < 4q: within 3q/2; the
-                // addend (< q) keeps it within 5q/2 before the final reduction
+                // (acc - conv) P^-1 with |acc - conv| < 5.5q: within 2q; the
+                // addend (< q) keeps it within 3q before the final reduction
                 double y = fmulmod(as_f(fp_from_u64(data[j + ep.d_acc[bsel]])) - as_f(v), as_f(pinv.w),
                                    as_f(pinv.wp), qd);
                 if (ep.d_add[bsel] != PFT_EPI_NO_ADD) y += as_f(fp_from_u64(data[j + ep.d_add[bsel]]));

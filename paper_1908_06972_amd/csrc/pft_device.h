@@ -107,9 +107,8 @@ __device__ __forceinline__ uint64_t shoup(uint64_t a, uint64_t w, uint64_t wp, u
 // and q < 2^50 the result lies within (1/2 + c/4) q of zero.  freduce(x) =
 // x - rint(x/q) q lies within q/2 (+ a vanishing error) for the magnitudes
 // used here.  Forward butterfly with X reduced: inputs within B q give outputs
-// within (1 + B/4) q (the lazy schedule of the NTT keeps B <= 3).  Inverse:
-// inputs within B q give outputs within max(1/2, 1/2 + B/2) q, so B stays at
-// most 1 (inputs below 4q accepted).  All magnitudes stay below 8q < 2^53.
+// within (1 + B/4) q; inverse with X + Y reduced: within max(1/2, 1/2 + B/2) q.
+// The lazy schedules of the NTT keep every magnitude below 4.5q < 2^53.
 __device__ __forceinline__ double as_f(uint64_t v) { return __builtin_bit_cast(double, v); }
 __device__ __forceinline__ uint64_t as_u(double v) { return __builtin_bit_cast(uint64_t, v); }
 
