@@ -181,7 +181,7 @@ def summarize(trace_dir, fetch_dir, write_dir, kernel, kid, commands, n_top=6):
     ranked = sorted(per.items(), key=lambda kv: -kv[1][1])
     targets = [k for k, _ in ranked[:n_top]] if kernel == "auto" else [kernel]
     out = ["# Kernels of the large-ring job step (N=2^16, L=24, batch 16): %s" % ", ".join(targets), ""]
-    out.append("Commands (from the repository root on the GPU box, after `export TMPDIR=/tmp`):")
+    out.append("Commands (from the repository root on the measuring MI355X host, after `export TMPDIR=/tmp`):")
     out.append("")
     for c in commands:
         out.append("    " + c)
@@ -211,7 +211,7 @@ def summarize(trace_dir, fetch_dir, write_dir, kernel, kid, commands, n_top=6):
     out.append("")
     out.append("Counters over the same dispatches, per launch (calibration factors: known bytes of k_copy_rows_b, a "
                "plain copy of 8 bytes read and 8 written per work-item, divided by 1024 x its counted KiB; traffic = "
-               "1024 x (fetch x fetch factor + write x write factor); on this box FETCH_SIZE counts half the bytes "
+               "1024 x (fetch x fetch factor + write x write factor); on the measured MI355X FETCH_SIZE counts half the bytes "
                "the copy reads, factor 2.0, and WRITE_SIZE is exact, factor 1.0):")
     out.append("")
     out.append("| kernel | avg us | fetch KiB | write KiB | traffic MB | VALU insts |")
