@@ -1193,9 +1193,12 @@ static ItemPtrs ws_items(WsRef ws, uint32_t n, uint64_t off = 0) {
 }
 
 // Key switching of d (NTT domain, [level][N] at ws_z + off_d) for n items:
-// out_z = ModDown(sum_j ModUp_j(d) key_j) + (ws rows at off_add0/off_add1).
+// out_z = ModDown(sum_j ModUp_j(d) key_j) + (ws rows at off_add0/off_add1),
+// plus, for the first polynomial, the rows at off_add0b (out may be those
+// rows: each element is read before it is written).
 static void key_switch_b(pft_ctx* c, uint32_t n, WsRef ws, const KsLayout& K, uint64_t off_d,
-                         const SwitchKeyDev& key, uint64_t off_add0, uint64_t off_add1, const ItemPtrs& out) {
+                         const SwitchKeyDev& key, uint64_t off_add0, uint64_t off_add1, const ItemPtrs& out,
+                         uint64_t off_add0b = PFT_NO_OFFSET) {
     const pft_params* P = c->P;
     const uint32_t lg = P->log_n, A = P->alpha, level = K.level, rows = K.rows, beta = K.beta;
     const double N = (double)P->n;
@@ -1264,10 +1267,12 @@ static void key_switch_b(pft_ctx* c, uint32_t n, WsRef ws, const KsLayout& K, ui
                 jobs.push_back(NttJob{ws.base + z * ws.stride + K.off_conv + ((uint64_t)b * level << lg), 255u, 0u});
         NttEpilogue epi{};
         const uint64_t off_add[2] = {off_add0, off_add1};
+        const uint64_t off_add2[2] = {off_add0b, PFT_NO_OFFSET};
         for (uint32_t b = 0; b < 2; ++b) {
             const int64_t conv0 = (int64_t)(K.off_conv + ((uint64_t)b * level << lg));
             epi.d_acc[b] = (int64_t)(K.off_acc + ((uint64_t)b * K.rows << lg)) - conv0;
             epi.d_add[b] = off_add[b] == PFT_NO_OFFSET ? PFT_EPI_NO_ADD : (int64_t)off_add[b] - conv0;
+            epi.d_add2[b] = off_add2[b] == PFT_NO_OFFSET ? PFT_EPI_NO_ADD : (int64_t)off_add2[b] - conv0;
         }
         for (uint32_t z = 0; z < n; ++z) epi.out[z] = out.p[z];
         epi.pinv = c->kc.down_pinv;
@@ -1568,8 +1573,9 @@ extern "C" int pft_total_sum_batch(pft_ctx* c, uint32_t n, const pft_ct* in, uin
             int ke;
             const SwitchKeyDev* rk = use_rot(c, (int32_t)s, &ke);
             if (!rk) return ke;
-            key_switch_b(c, cnt, ws, K, off_rot + nl, *rk, off_rot, PFT_NO_OFFSET, ROT);
-            launch_add_ct_b(cnt, ws, off_cur, off_rot, off_cur, l, c->tabs, lg, c->stream);
+            // cur + ROTATE(cur): (cur0 + kappa(cur0) + ks0, cur1 + ks1), finished in
+            // place by the ModDown epilogue
+            key_switch_b(c, cnt, ws, K, off_rot + nl, *rk, off_rot, off_cur + nl, CUR, off_cur);
         }
         launch_copy_rows_b(cnt, CUR, 0, O, 0, 2 * l, lg, c->stream);
         for (uint32_t z = 0; z < cnt; ++z) {

@@ -346,14 +346,16 @@ __global__ __launch_bounds__(4096 >> EB) void k_ntt_pass(PolyBatch b, const DevM
             if (fp) {
 #pragma clang fp contract(off)
                 // (acc - conv) P^-1 with |acc - conv| < 5.5q: within 2q; the
-                // addend (< q) keeps it within 3q before the final reduction
+                // addends (< q each) keep it within 4q before the final reduction
                 double y = fmulmod(as_f(fp_from_u64(data[j + ep.d_acc[bsel]])) - as_f(v), as_f(pinv.w),
                                    as_f(pinv.wp), qd);
                 if (ep.d_add[bsel] != PFT_EPI_NO_ADD) y += as_f(fp_from_u64(data[j + ep.d_add[bsel]]));
+                if (ep.d_add2[bsel] != PFT_EPI_NO_ADD) y += as_f(fp_from_u64(data[j + ep.d_add2[bsel]]));
                 r = fp_to_u64(as_u(y), qd, qinv);
             } else {
                 r = shoup(data[j + ep.d_acc[bsel]] + q - finish(v), pinv.w, pinv.wp, q);
                 if (ep.d_add[bsel] != PFT_EPI_NO_ADD) r = add_mod(r, data[j + ep.d_add[bsel]], q);
+                if (ep.d_add2[bsel] != PFT_EPI_NO_ADD) r = add_mod(r, data[j + ep.d_add2[bsel]], q);
             }
             out_row[j] = r;
         } else {
@@ -442,9 +444,11 @@ void launch_pass(const PolyBatch& b, const DevTables& t, uint32_t log_n, uint32_
                                        (e8 ? 256u : 0u) | (fused ? 512u : 0u));
         // the ModDown epilogue reads acc (and the addend) and writes out in
         // place of the transform's own store
-        const double bytes = fused ? elems * (24.0 + (epi->d_add[0] != PFT_EPI_NO_ADD ? 4.0 : 0.0) +
-                                              (epi->d_add[1] != PFT_EPI_NO_ADD ? 4.0 : 0.0))
-                                   : 16.0 * elems;
+        double extra = 0.0;  // addends: half of the rows (one polynomial) each
+        if (fused)
+            for (int bb = 0; bb < 2; ++bb)
+                extra += (epi->d_add[bb] != PFT_EPI_NO_ADD ? 4.0 : 0.0) + (epi->d_add2[bb] != PFT_EPI_NO_ADD ? 4.0 : 0.0);
+        const double bytes = fused ? elems * (24.0 + extra) : 16.0 * elems;
         g_prof->end(kid, bytes, 0.5 * elems * LOG_M, variant);
     }
 }

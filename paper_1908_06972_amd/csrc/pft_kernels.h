@@ -40,13 +40,16 @@ struct NttSchedule {
 // Epilogue of a forward transform's final pass that finishes ModDown in
 // place of storing the transform: for transformed row i of polynomial p =
 // 2 z + b (z the item, b in {0, 1}) it writes
-//   out_z[b][i] = (acc - conv) P^-1 mod q_i (+ add)
-// where conv is the transformed value and acc / add sit at word offsets
-// d_acc[b] / d_add[b] from it (d_add[b] = PFT_EPI_NO_ADD: no addend).
+//   out_z[b][i] = (acc - conv) P^-1 mod q_i (+ add) (+ add2)
+// where conv is the transformed value and acc / add / add2 sit at word
+// offsets d_acc[b] / d_add[b] / d_add2[b] from it (PFT_EPI_NO_ADD: no
+// addend).  out may coincide with an addend (each element is read before it
+// is written).
 #define PFT_EPI_NO_ADD INT64_MIN
 struct NttEpilogue {
     int64_t d_acc[2];
     int64_t d_add[2];
+    int64_t d_add2[2];  // a second addend, or PFT_EPI_NO_ADD
     uint64_t* out[PFT_MAX_POLYS / 2];  // per item of the launch: [2][level][N]
     const TwPair* pinv;                // [L]: P^-1 mod q_i (Shoup pairs)
     const TwPair* pinv_fp;             // [L]: the same as (w, w/q) doubles, used where q_i < 2^50
