@@ -35,7 +35,7 @@ FAMILIES = ["ntt_fwd_pass", "ntt_inv_pass", "modup_bconv", "key_inner_product", 
             "moddown_final", "tensor", "automorphism", "rescale", "elementwise"]
 KERNEL_NAMES = {2: "k_modup_mfma_b", 3: "k_key_inner_items", 4: "k_moddown_mfma_b", 5: "(fused into the forward NTT)",
                 6: "k_tensor_b",
-                7: "k_automorphism_b", 8: "k_rescale_expand_b/k_rescale_final_b"}
+                7: "k_automorphism_b", 8: "k_rescale_expand_b"}
 
 
 def kernel_name(kid, variant):

@@ -405,7 +405,9 @@ void pft_graph_destroy(pft_graph* graph);
  * pass, 2 ModUp base conversion, 3 key inner product, 4 ModDown base
  * conversion, 5 ModDown final scaling (kept as an index; it now runs as
  * the epilogue of the forward NTT pass that produces it, family 0), 6 HMUL
- * tensor, 7 automorphism, 8 rescale, 9 other elementwise. */
+ * tensor, 7 automorphism, 8 rescale (the spreading of the last limb; the
+ * final scaling runs as the epilogue of the forward NTT pass, family 0),
+ * 9 other elementwise. */
 int pft_prof_enable(pft_ctx* ctx, uint32_t mask);
 int pft_prof_read(pft_ctx* ctx, uint32_t kid, double* total_ms, uint64_t* launches, double* bytes, double* ops);
 /* Per-instantiation totals of family kid since pft_prof_enable, largest total

@@ -201,7 +201,7 @@ struct pft_ctx {
     hipStream_t stream = nullptr;
     DevTables tabs{};
     KsConsts kc{};
-    TwPair* rescale_qinv = nullptr;  // [L][L]: row l-1 holds q_{l-1}^-1 mod q_k
+    TwPair* rescale_qinv = nullptr;  // [2][L][L]: row l-1 holds q_{l-1}^-1 mod q_k (Shoup pairs, then fp64 pairs)
     TwPair* gadget = nullptr;        // [L]: (P mod q_i) as Shoup pairs
     TwPair* to_mont = nullptr;       // [L+K]: 2^64 mod m as Shoup pairs
     std::vector<void*> allocs;
@@ -402,10 +402,13 @@ static int build_tables(pft_ctx* c) {
         gadget[i] = pair(pm, P->q[i]);
     }
     for (uint32_t m = 0; m < L + K; ++m) tomont[m] = pair(to_mont(1, P->mods[m]), P->mods[m]);
-    std::vector<TwPair> rq((size_t)L * L, TwPair{0, 0});
+    std::vector<TwPair> rq(2 * (size_t)L * L, TwPair{0, 0});
     for (uint32_t lvl = 2; lvl <= L; ++lvl)
-        for (uint32_t k = 0; k + 1 < lvl; ++k)
-            rq[(size_t)(lvl - 1) * L + k] = pair(invmod(P->q[lvl - 1] % P->q[k], P->q[k]), P->q[k]);
+        for (uint32_t k = 0; k + 1 < lvl; ++k) {
+            const uint64_t v = invmod(P->q[lvl - 1] % P->q[k], P->q[k]);
+            rq[(size_t)(lvl - 1) * L + k] = pair(v, P->q[k]);
+            rq[(size_t)L * L + (size_t)(lvl - 1) * L + k] = twiddle(v, P->q[k]);  // fp64 form for q < 2^50
+        }
 
     // ---- MFMA base conversion operands (v_mfma_i32_32x32x16_i8).
     // The contraction y_t = sum_i x_i h_{i,t} mod m_t is evaluated with both
@@ -714,8 +717,10 @@ static void ntt_jobs(pft_ctx* c, const std::vector<NttJob>& jobs, uint32_t n_lim
         b.src_delta = src_delta;
         if (epi) {
             NttEpilogue e = *epi;
-            for (uint32_t i = 0; i < PFT_MAX_POLYS / 2; ++i)
+            for (uint32_t i = 0; i < PFT_MAX_POLYS / 2; ++i) {
                 e.out[i] = s / 2 + i < PFT_MAX_POLYS / 2 ? epi->out[s / 2 + i] : nullptr;
+                e.acc_item[i] = s / 2 + i < PFT_MAX_POLYS / 2 ? epi->acc_item[s / 2 + i] : nullptr;
+            }
             launch_ntt(b, c->tabs, P->log_n, inverse, sched, c->stream, hook(c), &e);
         } else {
             launch_ntt(b, c->tabs, P->log_n, inverse, sched, c->stream, hook(c));
@@ -1381,11 +1386,22 @@ extern "C" int pft_rescale_batch(pft_ctx* c, uint32_t n, const pft_ct* in, uint3
         const double nd = (double)N;
         timed(c, PK_RESCALE, 8.0 * nd * (2.0 + 2.0 * (l - 1)) * cnt, 0,
               [&] { launch_rescale_expand_b(cnt, ws, off_last, off_tmp, l, mode, c->tabs, lg, c->stream); });
-        ntt_jobs(c, jt, l - 1, ~0u, false);
-        timed(c, PK_RESCALE, 8.0 * nd * 6.0 * (l - 1) * cnt, 2.0 * nd * (l - 1) * cnt, [&] {
-            launch_rescale_final_b(cnt, I, ws, off_tmp, O, l, c->rescale_qinv + (size_t)(l - 1) * P->L, c->tabs, lg,
-                                   c->stream);
-        });
+        // the forward transform of tmp finishes in its final pass:
+        // out[b][k] = (c[b][k] - tmp[b][k]) q_last^-1 mod q_k
+        NttEpilogue epi{};
+        for (uint32_t b = 0; b < 2; ++b) {
+            epi.d_acc[b] = PFT_EPI_ITEM_ACC;
+            epi.d_add[b] = epi.d_add2[b] = PFT_EPI_NO_ADD;
+        }
+        for (uint32_t z = 0; z < cnt; ++z) {
+            epi.out[z] = O.p[z];
+            epi.acc_item[z] = I.p[z];
+        }
+        epi.acc_level = l;
+        epi.level = l - 1;
+        epi.pinv = c->rescale_qinv + (size_t)(l - 1) * P->L;
+        epi.pinv_fp = c->rescale_qinv + (size_t)P->L * P->L + (size_t)(l - 1) * P->L;
+        ntt_jobs(c, jt, l - 1, ~0u, false, 0, &epi);
         for (uint32_t z = 0; z < cnt; ++z) {
             out[g[z]].level = l - 1;
             out[g[z]].scale = in[g[z]].scale / (double)P->q[l - 1];

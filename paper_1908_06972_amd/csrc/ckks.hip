@@ -481,20 +481,6 @@ __global__ __launch_bounds__(TB) void k_rescale_expand_b(WsRef ws, uint64_t off_
     ws_item(ws)[off_tmp + at(b * nl + kq, log_n, k)] = r >= h ? r - h : r + qk - h;
 }
 
-// RESCALE, step 2: out_z[b][k] = (c_z[b][k] - tmp_z[b][k]) q_last^-1 mod q_k.
-__global__ __launch_bounds__(TB) void k_rescale_final_b(ItemPtrs c, WsRef ws, uint64_t off_tmp, ItemPtrs out,
-                                                        uint32_t level, const TwPair* __restrict__ qinv,
-                                                        const DevMod* __restrict__ mods, uint32_t log_n) {
-    const uint32_t k = blockIdx.x * TB + threadIdx.x;
-    const uint32_t nl = level - 1;
-    const uint32_t b = blockIdx.y / nl, kq = blockIdx.y % nl;
-    const uint64_t q = mods[kq].q;
-    const uint64_t x = c.p[blockIdx.z][at(b * level + kq, log_n, k)];
-    const uint64_t t = ws_item(ws)[off_tmp + at(b * nl + kq, log_n, k)];
-    const TwPair w = qinv[kq];
-    out.p[blockIdx.z][at(b * nl + kq, log_n, k)] = shoup(x + q - t, w.w, w.wp, q);
-}
-
 // ws_z[off_out] = ws_z[off_a] + ws_z[off_b] over [2][level][N]
 __global__ __launch_bounds__(TB) void k_add_ct_b(WsRef ws, uint64_t off_a, uint64_t off_b, uint64_t off_out,
                                                  uint32_t level, const DevMod* __restrict__ mods, uint32_t log_n) {
@@ -667,12 +653,6 @@ void launch_rescale_expand_b(uint32_t n, WsRef ws, uint64_t off_last, uint64_t o
                              const DevTables& t, uint32_t log_n, hipStream_t st) {
     hipLaunchKernelGGL(k_rescale_expand_b, grid_nk(log_n, 2 * (level - 1), n), dim3(TB), 0, st, ws, off_last,
                        off_tmp, level, mode, t.mods, log_n);
-}
-
-void launch_rescale_final_b(uint32_t n, const ItemPtrs& c, WsRef ws, uint64_t off_tmp, const ItemPtrs& out,
-                            uint32_t level, const TwPair* qinv, const DevTables& t, uint32_t log_n, hipStream_t st) {
-    hipLaunchKernelGGL(k_rescale_final_b, grid_nk(log_n, 2 * (level - 1), n), dim3(TB), 0, st, c, ws, off_tmp, out,
-                       level, qinv, t.mods, log_n);
 }
 
 void launch_add_ct_b(uint32_t n, WsRef ws, uint64_t off_a, uint64_t off_b, uint64_t off_out, uint32_t level,

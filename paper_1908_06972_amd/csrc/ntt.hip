@@ -338,6 +338,9 @@ __global__ __launch_bounds__(4096 >> EB) void k_ntt_pass(PolyBatch b, const DevM
     [[maybe_unused]] uint64_t* __restrict__ out_row =
         EPI ? ep.out[poly >> 1] + ((size_t)(bsel * ep.level + row) << log_n) : nullptr;
     [[maybe_unused]] const TwPair pinv = EPI ? (fp ? ep.pinv_fp[row] : ep.pinv[row]) : TwPair{0, 0};
+    [[maybe_unused]] const bool item_acc = EPI && ep.d_acc[bsel] == PFT_EPI_ITEM_ACC;
+    [[maybe_unused]] const uint64_t* __restrict__ acc_row =
+        item_acc ? ep.acc_item[poly >> 1] + ((size_t)(bsel * ep.acc_level + row) << log_n) : nullptr;
     // store of element j from its register form v (integer-valued double
     // within 4.5q for fp64 limbs; for integer limbs finish() reduces it)
     auto put = [&](size_t j, uint64_t v) {
@@ -347,13 +350,14 @@ __global__ __launch_bounds__(4096 >> EB) void k_ntt_pass(PolyBatch b, const DevM
 #pragma clang fp contract(off)
                 // (acc - conv) P^-1 with |acc - conv| < 5.5q: within 2q; the
                 // addends (< q each) keep it within 4q before the final reduction
-                double y = fmulmod(as_f(fp_from_u64(data[j + ep.d_acc[bsel]])) - as_f(v), as_f(pinv.w),
-                                   as_f(pinv.wp), qd);
+                const uint64_t a = item_acc ? acc_row[j] : data[j + ep.d_acc[bsel]];
+                double y = fmulmod(as_f(fp_from_u64(a)) - as_f(v), as_f(pinv.w), as_f(pinv.wp), qd);
                 if (ep.d_add[bsel] != PFT_EPI_NO_ADD) y += as_f(fp_from_u64(data[j + ep.d_add[bsel]]));
                 if (ep.d_add2[bsel] != PFT_EPI_NO_ADD) y += as_f(fp_from_u64(data[j + ep.d_add2[bsel]]));
                 r = fp_to_u64(as_u(y), qd, qinv);
             } else {
-                r = shoup(data[j + ep.d_acc[bsel]] + q - finish(v), pinv.w, pinv.wp, q);
+                const uint64_t a = item_acc ? acc_row[j] : data[j + ep.d_acc[bsel]];
+                r = shoup(a + q - finish(v), pinv.w, pinv.wp, q);
                 if (ep.d_add[bsel] != PFT_EPI_NO_ADD) r = add_mod(r, data[j + ep.d_add[bsel]], q);
                 if (ep.d_add2[bsel] != PFT_EPI_NO_ADD) r = add_mod(r, data[j + ep.d_add2[bsel]], q);
             }

@@ -43,14 +43,18 @@ struct NttSchedule {
 //   out_z[b][i] = (acc - conv) P^-1 mod q_i (+ add) (+ add2)
 // where conv is the transformed value and acc / add / add2 sit at word
 // offsets d_acc[b] / d_add[b] / d_add2[b] from it (PFT_EPI_NO_ADD: no
-// addend).  out may coincide with an addend (each element is read before it
-// is written).
+// addend), or acc is row i of polynomial b of an item's own ciphertext
+// (PFT_EPI_ITEM_ACC; RESCALE uses this with P^-1 replaced by q_last^-1).  out
+// may coincide with an addend (each element is read before it is written).
 #define PFT_EPI_NO_ADD INT64_MIN
+#define PFT_EPI_ITEM_ACC (INT64_MIN + 1)
 struct NttEpilogue {
-    int64_t d_acc[2];
+    int64_t d_acc[2];   // or PFT_EPI_ITEM_ACC: acc of item z at acc_item[z] + (b acc_level + i) N
     int64_t d_add[2];
     int64_t d_add2[2];  // a second addend, or PFT_EPI_NO_ADD
     uint64_t* out[PFT_MAX_POLYS / 2];  // per item of the launch: [2][level][N]
+    const uint64_t* acc_item[PFT_MAX_POLYS / 2];
+    uint32_t acc_level;
     const TwPair* pinv;                // [L]: P^-1 mod q_i (Shoup pairs)
     const TwPair* pinv_fp;             // [L]: the same as (w, w/q) doubles, used where q_i < 2^50
     uint32_t level;
@@ -141,8 +145,6 @@ void launch_moddown_conv_b(uint32_t n, WsRef ws, uint64_t off_acc, uint64_t off_
 // RESCALE pieces (see ckks.hip)
 void launch_rescale_expand_b(uint32_t n, WsRef ws, uint64_t off_last, uint64_t off_tmp, uint32_t level, uint32_t mode,
                              const DevTables& t, uint32_t log_n, hipStream_t st);
-void launch_rescale_final_b(uint32_t n, const ItemPtrs& c, WsRef ws, uint64_t off_tmp, const ItemPtrs& out,
-                            uint32_t level, const TwPair* qinv, const DevTables& t, uint32_t log_n, hipStream_t st);
 // ws_z[off_out] = ws_z[off_a] + ws_z[off_b] over [2][level][N]
 void launch_add_ct_b(uint32_t n, WsRef ws, uint64_t off_a, uint64_t off_b, uint64_t off_out, uint32_t level,
                      const DevTables& t, uint32_t log_n, hipStream_t st);
