@@ -67,7 +67,7 @@ def _int_plains(seed, n_out, J, n, bound):
     return np.stack([np.stack([S.plaintext_coeffs(g, n, bound) for _ in range(J)]) for _ in range(n_out)])
 
 
-@pytest.mark.parametrize("n_in,n_sum,docs", [(3, 2048, 2), (1, 64, 1), (2, 1, 3)])
+@pytest.mark.parametrize("n_in,n_sum,docs", [(3, 2048, 2), (1, 64, 1), (2, 1, 3), (70, 4, 1)])
 def test_ptdot_parity(world, n_in, n_sum, docs):
     """out[z][k] = TotalSum_{n_sum}(sum_j in[z][j] P_{k,j}) against the oracle."""
     w = world

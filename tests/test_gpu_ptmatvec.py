@@ -172,3 +172,19 @@ def test_bow_inference_c4(n_docs):
         srt = np.sort(want)
         if srt[-1] - srt[-2] > 2e-5:
             assert np.argmax(got) == np.argmax(want)
+
+
+def test_ptmatvec_many_inputs_giant_steps_only(small):
+    """70 input ciphertexts: the plan takes b = 1 (giant steps only) and the
+    inputs are staged in several batches; bit-exact with the oracle."""
+    w = small
+    n_o, n_i, n_in, lvl = 4, 16, 70, 3
+    assert PM.bsgs_plan(n_o, n_in) == (1, 4)
+    plains = _random_plains(7, n_in, n_o, w.n, 2 ** 20)
+    pt_scale = float(w.op.q[lvl - 1])
+    mat = w.ctx.ptmat_from_coeffs(plains, n_o, n_i, n_in, lvl, pt_scale)
+    assert (mat.b, mat.G) == (1, 4)
+    doc = [w.enc_pair(S.plaintext_coeffs(S.rng(900 + c), w.n, 2 ** 30), lvl, 1000 + c) for c in range(n_in)]
+    g = w.ctx.ptmatvec(mat, [[x[0] for x in doc]])[0]
+    o = PM.ptmatvec(w.op, [x[1] for x in doc], plains, n_o, n_i, w.keys, pt_scale)
+    w.assert_same(g, o)
