@@ -333,37 +333,64 @@ __global__ __launch_bounds__(4096 >> EB) void k_ntt_pass(PolyBatch b, const DevM
         }
         return v;
     };
-    // store of transformed element j of this row (or the ModDown epilogue)
+    // ModDown / RESCALE epilogue operands (uniform per workgroup)
     [[maybe_unused]] const uint32_t bsel = poly & 1u;
     [[maybe_unused]] uint64_t* __restrict__ out_row =
         EPI ? ep.out[poly >> 1] + ((size_t)(bsel * ep.level + row) << log_n) : nullptr;
     [[maybe_unused]] const TwPair pinv = EPI ? (fp ? ep.pinv_fp[row] : ep.pinv[row]) : TwPair{0, 0};
-    [[maybe_unused]] const bool item_acc = EPI && ep.d_acc[bsel] == PFT_EPI_ITEM_ACC;
-    [[maybe_unused]] const uint64_t* __restrict__ acc_row =
-        item_acc ? ep.acc_item[poly >> 1] + ((size_t)(bsel * ep.acc_level + row) << log_n) : nullptr;
-    // store of element j from its register form v (integer-valued double
-    // within 4.5q for fp64 limbs; for integer limbs finish() reduces it)
-    auto put = [&](size_t j, uint64_t v) {
-        if constexpr (EPI) {
-            uint64_t r;
-            if (fp) {
-#pragma clang fp contract(off)
-                // (acc - conv) P^-1 with |acc - conv| < 5.5q: within 2q; the
-                // addends (< q each) keep it within 4q before the final reduction
-                const uint64_t a = item_acc ? acc_row[j] : data[j + ep.d_acc[bsel]];
-                double y = fmulmod(as_f(fp_from_u64(a)) - as_f(v), as_f(pinv.w), as_f(pinv.wp), qd);
-                if (ep.d_add[bsel] != PFT_EPI_NO_ADD) y += as_f(fp_from_u64(data[j + ep.d_add[bsel]]));
-                if (ep.d_add2[bsel] != PFT_EPI_NO_ADD) y += as_f(fp_from_u64(data[j + ep.d_add2[bsel]]));
-                r = fp_to_u64(as_u(y), qd, qinv);
-            } else {
-                const uint64_t a = item_acc ? acc_row[j] : data[j + ep.d_acc[bsel]];
-                r = shoup(a + q - finish(v), pinv.w, pinv.wp, q);
-                if (ep.d_add[bsel] != PFT_EPI_NO_ADD) r = add_mod(r, data[j + ep.d_add[bsel]], q);
-                if (ep.d_add2[bsel] != PFT_EPI_NO_ADD) r = add_mod(r, data[j + ep.d_add2[bsel]], q);
+    [[maybe_unused]] const uint64_t* __restrict__ acc_src = nullptr;
+    [[maybe_unused]] const uint64_t* __restrict__ add_src = nullptr;
+    [[maybe_unused]] const uint64_t* __restrict__ add2_src = nullptr;
+    if constexpr (EPI) {
+        acc_src = ep.d_acc[bsel] == PFT_EPI_ITEM_ACC
+                      ? ep.acc_item[poly >> 1] + ((size_t)(bsel * ep.acc_level + row) << log_n)
+                      : data + ep.d_acc[bsel];
+        if (ep.d_add[bsel] != PFT_EPI_NO_ADD) add_src = data + ep.d_add[bsel];
+        if (ep.d_add2[bsel] != PFT_EPI_NO_ADD) add2_src = data + ep.d_add2[bsel];
+    }
+    // Epilogue stores of the E elements pos(k) with register forms val(k)
+    // (integer-valued doubles within 4.5q for fp64 limbs; finish() reduces
+    // integer limbs).  Every load of a chunk is issued before the first
+    // result is formed, so their latencies overlap.
+    [[maybe_unused]] auto epi_store = [&](auto pos, auto val) {
+        constexpr int CH = E < 8 ? E : 8;
+#pragma unroll
+        for (int k0 = 0; k0 < E; k0 += CH) {
+            uint32_t jj[CH];
+            uint64_t a[CH], u[CH], w[CH];
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+                jj[k] = pos(k0 + k);
+                a[k] = acc_src[jj[k]];
             }
-            out_row[j] = r;
-        } else {
-            data[j] = finish(v);
+            if (add_src) {
+#pragma unroll
+                for (int k = 0; k < CH; ++k) u[k] = add_src[jj[k]];
+            }
+            if (add2_src) {
+#pragma unroll
+                for (int k = 0; k < CH; ++k) w[k] = add2_src[jj[k]];
+            }
+            if (fp) {
+#pragma unroll
+                for (int k = 0; k < CH; ++k) {
+#pragma clang fp contract(off)
+                    // (acc - conv) P^-1 with |acc - conv| < 5.5q: within 2q; the
+                    // addends (< q each) keep it within 4q before the final reduction
+                    double y = fmulmod(as_f(fp_from_u64(a[k])) - as_f(val(k0 + k)), as_f(pinv.w), as_f(pinv.wp), qd);
+                    if (add_src) y += as_f(fp_from_u64(u[k]));
+                    if (add2_src) y += as_f(fp_from_u64(w[k]));
+                    out_row[jj[k]] = fp_to_u64(as_u(y), qd, qinv);
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < CH; ++k) {
+                    uint64_t r = shoup(a[k] + q - finish(val(k0 + k)), pinv.w, pinv.wp, q);
+                    if (add_src) r = add_mod(r, u[k], q);
+                    if (add2_src) r = add_mod(r, w[k], q);
+                    out_row[jj[k]] = r;
+                }
+            }
         }
     };
     if constexpr (DIRECT_OUT && VEC_OUT && !EPI) {
@@ -376,16 +403,27 @@ __global__ __launch_bounds__(4096 >> EB) void k_ntt_pass(PolyBatch b, const DevM
             dst[e] = v;
         }
     } else if constexpr (DIRECT_OUT) {
+        if constexpr (EPI)
+            epi_store([&](int e) { return (uint32_t)gidx(c, POUT::r_of(l, e)); }, [&](int e) { return x[e]; });
+        else
 #pragma unroll
-        for (int e = 0; e < E; ++e) put(gidx(c, POUT::r_of(l, e)), x[e]);
+            for (int e = 0; e < E; ++e) data[gidx(c, POUT::r_of(l, e))] = finish(x[e]);
     } else {
         lds_write<LOG_M, PH_OUT, EB>(x, lds, c, l);
         __syncthreads();
-#pragma unroll
-        for (int k = 0; k < E; ++k) {
+        auto at = [&](int k) {
             const uint32_t idx = tid + NT * k;
-            const uint32_t cc = idx / M, r = idx % M;
-            put(gidx(cc, r), lds[lds_at<LOG_M, EB>(cc, r)]);
+            return std::pair<uint32_t, uint32_t>(idx / M, idx % M);
+        };
+        if constexpr (EPI) {
+            epi_store([&](int k) { const auto p = at(k); return (uint32_t)gidx(p.first, p.second); },
+                      [&](int k) { const auto p = at(k); return lds[lds_at<LOG_M, EB>(p.first, p.second)]; });
+        } else {
+#pragma unroll
+            for (int k = 0; k < E; ++k) {
+                const auto p = at(k);
+                data[gidx(p.first, p.second)] = finish(lds[lds_at<LOG_M, EB>(p.first, p.second)]);
+            }
         }
     }
 }
