@@ -126,6 +126,25 @@ int pft_gen_rotation_key(pft_ctx* ctx, int32_t step, const uint64_t* a, const in
  * read whatever key then occupies the slot).  The relinearisation key is never
  * cached.  pft_key_cache_stats writes {max_resident, slots allocated, hits,
  * misses, bytes copied to the device} to out[5]. */
+/* Seeded KEYGEN (Sec. 3.4; X_key, the uniform masks and X_err of SETUP, sigma
+ * = 3.2 from Sec. 5): the secret, public key, relinearisation key and one
+ * rotation key per listed step, every draw taken on the device from the
+ * Philox4x64-10 counter-based generator (Salmon et al., SC 2011).  Stream
+ * key (seed, purpose 2^56 + key_id 2^8 + digit), counter (coefficient j,
+ * limb i, 0, 0); purposes 1 secret, 2/3 public-key mask/error, 4/5
+ * switching-key masks/errors (key_id 0 relinearisation, 1 + (step mod N/2)
+ * rotation), 6/7/8 ENC v/e0/e1.  From a block's words w0, w1: ternary
+ * (w0 mod 3) - 1; uniform floor((w1 2^64 + w0) q / 2^128); discrete Gaussian
+ * -19 + #{k : T_k <= w0} with T from pft_gaussian_cdt.  The result equals the
+ * caller-draws entry points above fed with the same draws.  A step that is 0
+ * mod N/2 is refused (PFT_EINVAL); the key-cache setting applies as above.
+ * Synchronizes the context stream. */
+int pft_keygen(pft_ctx* ctx, uint64_t seed, const int32_t* rot_steps, uint32_t n_steps);
+/* The 38 thresholds T_k = floor(2^64 F(k)), k = -19..18, of the cumulative
+ * distribution F of the discrete Gaussian of sigma 3.2 on -19..19, in
+ * increasing order.  Host only; table needs capacity >= 38 (PFT_EINVAL
+ * otherwise); *count receives 38. */
+int pft_gaussian_cdt(uint64_t* table, uint32_t capacity, uint32_t* count);
 int pft_set_key_cache(pft_ctx* ctx, uint32_t max_resident);
 int pft_key_cache_stats(const pft_ctx* ctx, uint64_t* out);
 /* Number of device bytes held by keys and tables. */
@@ -138,6 +157,10 @@ int pft_ctx_device_bytes(const pft_ctx* ctx, uint64_t* bytes);
  * the call sets out->level and out->scale. */
 int pft_encrypt(pft_ctx* ctx, const int64_t* m, uint32_t level, double scale,
                 const int64_t* v, const int64_t* e0, const int64_t* e1, pft_ct* out);
+/* ENC with v, e0, e1 drawn on the device from the streams of `seed`
+ * (purposes 6, 7, 8 of pft_keygen).  A seed must not be reused for two
+ * encryptions under one key (the masks would repeat).  Synchronizes. */
+int pft_encrypt_seeded(pft_ctx* ctx, const int64_t* m, uint32_t level, double scale, uint64_t seed, pft_ct* out);
 /* DEC: c0 + c1 s mod q_i, written to host memory [level][N] in coefficient
  * form.  Synchronizes the context stream. */
 int pft_decrypt(pft_ctx* ctx, const pft_ct* ct, uint64_t* out);

@@ -193,12 +193,26 @@ class Context:
     def gen_rotation_key(self, step, a, e):
         N.check(self.lib.pft_gen_rotation_key(self.handle, int(step), N.u64p(_u64(a)), N.i64p(_i64(e))))
 
+    def keygen(self, seed, rot_steps=()):
+        """Secret, public, relinearisation and rotation keys (one per step),
+        every draw taken on the device from the Philox streams of `seed`."""
+        steps = (ctypes.c_int32 * max(1, len(rot_steps)))(*[int(s) for s in rot_steps])
+        N.check(self.lib.pft_keygen(self.handle, ctypes.c_uint64(int(seed)), steps, len(rot_steps)))
+
     # ---- ENC / DEC
     def encrypt(self, m, level, scale, v, e0, e1) -> Ciphertext:
         ct = self.empty_ct(level)
         d = ct.desc()
         N.check(self.lib.pft_encrypt(self.handle, N.i64p(_i64(m)), level, float(scale), N.i64p(_i64(v)),
                                      N.i64p(_i64(e0)), N.i64p(_i64(e1)), ctypes.byref(d)))
+        return ct.sync_from(d)
+
+    def encrypt_seeded(self, m, level, scale, seed) -> Ciphertext:
+        """ENC with v, e0, e1 drawn on the device from the streams of `seed`."""
+        ct = self.empty_ct(level)
+        d = ct.desc()
+        N.check(self.lib.pft_encrypt_seeded(self.handle, N.i64p(_i64(m)), level, float(scale),
+                                            ctypes.c_uint64(int(seed)), ctypes.byref(d)))
         return ct.sync_from(d)
 
     def decrypt(self, ct: Ciphertext) -> np.ndarray:

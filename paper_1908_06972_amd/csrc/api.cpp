@@ -771,28 +771,79 @@ static bool check_uniform(const uint64_t* a, const std::vector<uint64_t>& mods, 
     return true;
 }
 
-extern "C" int pft_set_secret(pft_ctx* c, const int64_t* s) {
-    if (!c || !s) return fail(PFT_EINVAL, "null argument");
-    if (c->capturing) return fail(PFT_EINVAL, "host transfers cannot be captured in a graph");
+// Where KEYGEN and ENC take their random draws: caller arrays in host memory,
+// or the Philox4x64-10 streams of a seed (sampler.hip), keyed by
+// (seed, purpose 2^56 + key_id 2^8 + digit).
+enum : uint64_t {
+    DRAW_SECRET = 1, DRAW_PK_A = 2, DRAW_PK_E = 3, DRAW_KS_A = 4, DRAW_KS_E = 5, DRAW_ENC_V = 6, DRAW_ENC_E0 = 7,
+    DRAW_ENC_E1 = 8
+};
+struct Draws {
+    bool seeded;
+    uint64_t seed;
+    uint64_t key_id;     // switching keys: 0 relinearisation, 1 + step for rotation by step
+    const uint64_t* a;   // host masks (not seeded)
+    const int64_t* e;    // host errors (not seeded)
+};
+static Draws host_draws(const uint64_t* a, const int64_t* e) { return Draws{false, 0, 0, a, e}; }
+static Draws seeded_draws(uint64_t seed, uint64_t key_id) { return Draws{true, seed, key_id, nullptr, nullptr}; }
+static uint64_t stream_k1(uint64_t purpose, uint64_t key_id, uint32_t digit) {
+    return (purpose << 56) | (key_id << 8) | digit;
+}
+static const GaussianCdt& gaussian_cdt() {
+    static const GaussianCdt t = [] {
+        GaussianCdt g{};
+        const int k = gaussian_cdt_host(g.t, 2 * PFT_GAUSS_BOUND);
+        g.count = k > 0 ? (uint32_t)k : 0u;  // the kernel reads t[0 .. count)
+        return g;
+    }();
+    return t;
+}
+// rows x N uniform residues of stream (seed, purpose, key_id, digit) into dev
+static void sample_uniform(pft_ctx* c, const Draws& d, uint64_t purpose, uint32_t digit, const uint64_t* mods,
+                           uint32_t rows, uint64_t* dev) {
+    SampleModuli sm{};
+    for (uint32_t i = 0; i < rows; ++i) sm.q[i] = mods[i];
+    launch_sample_uniform(d.seed, stream_k1(purpose, d.key_id, digit), sm, rows, dev, c->P->n, c->stream);
+}
+// N ternary (kind 0) or discrete-Gaussian (kind 1) coefficients into dev
+static void sample_small(pft_ctx* c, const Draws& d, uint32_t kind, uint64_t purpose, uint32_t digit, int64_t* dev) {
+    launch_sample_small(kind, d.seed, stream_k1(purpose, d.key_id, digit), gaussian_cdt(), dev, c->P->n, c->stream);
+}
+
+extern "C" int pft_gaussian_cdt(uint64_t* table, uint32_t capacity, uint32_t* count) {
+    if (!table || !count) return fail(PFT_EINVAL, "null argument");
+    const int k = gaussian_cdt_host(table, capacity);
+    if (k < 0) return fail(PFT_EINVAL, "capacity below %u", 2u * PFT_GAUSS_BOUND);
+    *count = (uint32_t)k;
+    return PFT_OK;
+}
+
+static int set_secret_core(pft_ctx* c, const int64_t* s, const Draws& d) {
     const pft_params* P = c->P;
-    if (!check_ternary(s, P->n)) return fail(PFT_EINVAL, "secret must be ternary");
     const uint32_t R = P->L + P->K;
     int r;
     if (!c->s && (r = dalloc(c, &c->s, (size_t)R * P->n * 8))) return r;
     if ((r = ensure_ws(c, (size_t)P->n * 8))) return r;
-    if ((r = upload_i64(c, (int64_t*)c->ws, s, P->n))) return r;
+    if (d.seeded)
+        sample_small(c, d, 0, DRAW_SECRET, 0, (int64_t*)c->ws);
+    else if ((r = upload_i64(c, (int64_t*)c->ws, s, P->n)))
+        return r;
     launch_int_to_rns((const int64_t*)c->ws, sb(P, {c->s}, R, 0, P->L), c->tabs, P->log_n, c->stream);
     ntt_rows(c, c->s, 1, R, R, false, P->L);
     HIPCK(hipStreamSynchronize(c->stream));
     return PFT_OK;
 }
 
-extern "C" int pft_gen_public_key(pft_ctx* c, const uint64_t* a, const int64_t* e) {
-    if (!c || !a || !e) return fail(PFT_EINVAL, "null argument");
+extern "C" int pft_set_secret(pft_ctx* c, const int64_t* s) {
+    if (!c || !s) return fail(PFT_EINVAL, "null argument");
     if (c->capturing) return fail(PFT_EINVAL, "host transfers cannot be captured in a graph");
+    if (!check_ternary(s, c->P->n)) return fail(PFT_EINVAL, "secret must be ternary");
+    return set_secret_core(c, s, host_draws(nullptr, nullptr));
+}
+
+static int gen_public_key_core(pft_ctx* c, const Draws& d) {
     const pft_params* P = c->P;
-    if (!c->s) return fail(PFT_ENOKEY, "set the secret first");
-    if (!check_uniform(a, P->q, P->L, P->n)) return fail(PFT_EINVAL, "mask residues must be < q_i");
     int r;
     const size_t nL = (size_t)P->L * P->n;
     if (!c->pk && (r = dalloc(c, &c->pk, 2 * nL * 8))) return r;
@@ -800,7 +851,12 @@ extern "C" int pft_gen_public_key(pft_ctx* c, const uint64_t* a, const int64_t* 
     uint64_t* e_rns = c->ws;
     int64_t* e_raw = (int64_t*)(c->ws + nL);
     uint64_t* pa = c->pk + nL;
-    if ((r = upload_u64(c, pa, a, nL)) || (r = upload_i64(c, e_raw, e, P->n))) return r;
+    if (d.seeded) {
+        sample_uniform(c, d, DRAW_PK_A, 0, P->q.data(), P->L, pa);
+        sample_small(c, d, 1, DRAW_PK_E, 0, e_raw);
+    } else if ((r = upload_u64(c, pa, d.a, nL)) || (r = upload_i64(c, e_raw, d.e, P->n))) {
+        return r;
+    }
     ntt_rows(c, pa, 1, P->L, P->L, false);
     launch_int_to_rns(e_raw, sb(P, {e_rns}, P->L), c->tabs, P->log_n, c->stream);
     ntt_rows(c, e_rns, 1, P->L, P->L, false);
@@ -809,6 +865,14 @@ extern "C" int pft_gen_public_key(pft_ctx* c, const uint64_t* a, const int64_t* 
     launch_ew(EW_NEG_MULADD, B, A, &S, &E, c->tabs, P->log_n, c->stream);
     HIPCK(hipStreamSynchronize(c->stream));
     return PFT_OK;
+}
+
+extern "C" int pft_gen_public_key(pft_ctx* c, const uint64_t* a, const int64_t* e) {
+    if (!c || !a || !e) return fail(PFT_EINVAL, "null argument");
+    if (c->capturing) return fail(PFT_EINVAL, "host transfers cannot be captured in a graph");
+    if (!c->s) return fail(PFT_ENOKEY, "set the secret first");
+    if (!check_uniform(a, c->P->q, c->P->L, c->P->n)) return fail(PFT_EINVAL, "mask residues must be < q_i");
+    return gen_public_key_core(c, host_draws(a, e));
 }
 
 // s_prime: [L+K][N] NTT domain (device).  Builds the switching key into *dst.
@@ -855,14 +919,19 @@ static int key_slot(pft_ctx* c, int32_t step) {
     return PFT_OK;
 }
 
-static int gen_switch_key(pft_ctx* c, const uint64_t* s_prime, const uint64_t* a, const int64_t* e,
-                          SwitchKeyDev* dst) {
-    const pft_params* P = c->P;
+static int check_switch_draws(const pft_params* P, const uint64_t* a) {
     const uint32_t R = P->L + P->K;
     const size_t nR = (size_t)R * P->n;
     for (uint32_t j = 0; j < P->dnum; ++j)
         if (!check_uniform(a + (size_t)j * nR, P->mods, R, P->n))
             return fail(PFT_EINVAL, "mask residues must be < their modulus");
+    return PFT_OK;
+}
+
+static int gen_switch_key(pft_ctx* c, const uint64_t* s_prime, const Draws& d, SwitchKeyDev* dst) {
+    const pft_params* P = c->P;
+    const uint32_t R = P->L + P->K;
+    const size_t nR = (size_t)R * P->n;
     int r;
     if (!dst->data && (r = dalloc(c, &dst->data, (size_t)P->dnum * 2 * nR * 8))) return r;
     if ((r = ensure_ws(c, (nR + P->n + nR) * 8))) return r;
@@ -873,8 +942,13 @@ static int gen_switch_key(pft_ctx* c, const uint64_t* s_prime, const uint64_t* a
     for (uint32_t j = 0; j < P->dnum; ++j) {
         uint64_t* kb = dst->data + (size_t)(2 * j) * nR;
         uint64_t* ka = dst->data + (size_t)(2 * j + 1) * nR;
-        if ((r = upload_u64(c, ka, a + (size_t)j * nR, nR)) || (r = upload_i64(c, e_raw, e + (size_t)j * P->n, P->n)))
+        if (d.seeded) {
+            sample_uniform(c, d, DRAW_KS_A, j, P->mods.data(), R, ka);
+            sample_small(c, d, 1, DRAW_KS_E, j, e_raw);
+        } else if ((r = upload_u64(c, ka, d.a + (size_t)j * nR, nR)) ||
+                   (r = upload_i64(c, e_raw, d.e + (size_t)j * P->n, P->n))) {
             return r;
+        }
         ntt_rows(c, ka, 1, R, R, false, P->L);
         launch_int_to_rns(e_raw, sb(P, {e_rns}, R, 0, P->L), c->tabs, P->log_n, c->stream);
         ntt_rows(c, e_rns, 1, R, R, false, P->L);
@@ -896,17 +970,23 @@ static int gen_switch_key(pft_ctx* c, const uint64_t* s_prime, const uint64_t* a
     return PFT_OK;
 }
 
-extern "C" int pft_gen_relin_key(pft_ctx* c, const uint64_t* a, const int64_t* e) {
-    if (!c || !a || !e) return fail(PFT_EINVAL, "null argument");
-    if (c->capturing) return fail(PFT_EINVAL, "host transfers cannot be captured in a graph");
-    if (!c->s) return fail(PFT_ENOKEY, "set the secret first");
+static int gen_relin_key_core(pft_ctx* c, const Draws& d) {
     const pft_params* P = c->P;
     const uint32_t R = P->L + P->K;
     int r;
     if (!c->s_prime && (r = dalloc(c, &c->s_prime, (size_t)R * P->n * 8))) return r;
     const SmallBatch S = sb(P, {c->s}, R, 0, P->L), S2 = sb(P, {c->s_prime}, R, 0, P->L);
     launch_ew(EW_MUL, S2, S, &S, nullptr, c->tabs, P->log_n, c->stream);
-    return gen_switch_key(c, c->s_prime, a, e, &c->rlk);
+    return gen_switch_key(c, c->s_prime, d, &c->rlk);
+}
+
+extern "C" int pft_gen_relin_key(pft_ctx* c, const uint64_t* a, const int64_t* e) {
+    if (!c || !a || !e) return fail(PFT_EINVAL, "null argument");
+    if (c->capturing) return fail(PFT_EINVAL, "host transfers cannot be captured in a graph");
+    if (!c->s) return fail(PFT_ENOKEY, "set the secret first");
+    int r;
+    if ((r = check_switch_draws(c->P, a))) return r;
+    return gen_relin_key_core(c, host_draws(a, e));
 }
 
 static uint64_t galois_element(int32_t step, uint32_t n) {
@@ -926,10 +1006,7 @@ static ItemPtrs one_item(uint64_t* p) {
     return ip;
 }
 
-extern "C" int pft_gen_rotation_key(pft_ctx* c, int32_t step, const uint64_t* a, const int64_t* e) {
-    if (!c || !a || !e) return fail(PFT_EINVAL, "null argument");
-    if (c->capturing) return fail(PFT_EINVAL, "host transfers cannot be captured in a graph");
-    if (!c->s) return fail(PFT_ENOKEY, "set the secret first");
+static int gen_rotation_key_core(pft_ctx* c, int32_t step, const Draws& d) {
     const pft_params* P = c->P;
     const uint32_t R = P->L + P->K;
     int r;
@@ -938,7 +1015,7 @@ extern "C" int pft_gen_rotation_key(pft_ctx* c, int32_t step, const uint64_t* a,
                           c->stream);
     const int32_t ns = norm_step(step, P->n);
     SwitchKeyDev& k = c->rot[ns];
-    if (!c->rot_cache_max) return gen_switch_key(c, c->s_prime, a, e, &k);
+    if (!c->rot_cache_max) return gen_switch_key(c, c->s_prime, d, &k);
     // limited key cache: generate into a slot, keep the pinned host copy
     const size_t bytes = key_bytes(P);
     if (!k.host) {
@@ -951,9 +1028,34 @@ extern "C" int pft_gen_rotation_key(pft_ctx* c, int32_t step, const uint64_t* a,
         k.host = (uint64_t*)h;
     }
     if (!k.data && (r = key_slot(c, ns))) return r;
-    if ((r = gen_switch_key(c, c->s_prime, a, e, &k))) return r;
+    if ((r = gen_switch_key(c, c->s_prime, d, &k))) return r;
     HIPCK(hipMemcpyAsync(k.host, k.data, bytes, hipMemcpyDeviceToHost, c->stream));
     HIPCK(hipStreamSynchronize(c->stream));
+    return PFT_OK;
+}
+
+extern "C" int pft_gen_rotation_key(pft_ctx* c, int32_t step, const uint64_t* a, const int64_t* e) {
+    if (!c || !a || !e) return fail(PFT_EINVAL, "null argument");
+    if (c->capturing) return fail(PFT_EINVAL, "host transfers cannot be captured in a graph");
+    if (!c->s) return fail(PFT_ENOKEY, "set the secret first");
+    int r;
+    if ((r = check_switch_draws(c->P, a))) return r;
+    return gen_rotation_key_core(c, step, host_draws(a, e));
+}
+
+extern "C" int pft_keygen(pft_ctx* c, uint64_t seed, const int32_t* rot_steps, uint32_t n_steps) {
+    if (!c || (n_steps && !rot_steps)) return fail(PFT_EINVAL, "null argument");
+    if (c->capturing) return fail(PFT_EINVAL, "key generation cannot be captured in a graph");
+    const uint32_t half = c->P->n / 2;
+    int r;
+    if ((r = set_secret_core(c, nullptr, seeded_draws(seed, 0))) || (r = gen_public_key_core(c, seeded_draws(seed, 0))) ||
+        (r = gen_relin_key_core(c, seeded_draws(seed, 0))))
+        return r;
+    for (uint32_t i = 0; i < n_steps; ++i) {
+        const int32_t ns = norm_step(rot_steps[i], c->P->n);
+        if (ns == 0) return fail(PFT_EINVAL, "rotation step %d is 0 mod N/2 = %u", rot_steps[i], half);
+        if ((r = gen_rotation_key_core(c, rot_steps[i], seeded_draws(seed, 1u + (uint64_t)ns)))) return r;
+    }
     return PFT_OK;
 }
 
@@ -983,14 +1085,12 @@ static int check_ct(const pft_ctx* c, const pft_ct* ct) {
     return PFT_OK;
 }
 
-extern "C" int pft_encrypt(pft_ctx* c, const int64_t* m, uint32_t level, double scale, const int64_t* v,
-                           const int64_t* e0, const int64_t* e1, pft_ct* out) {
-    if (!c || !m || !v || !e0 || !e1 || !out || !out->data) return fail(PFT_EINVAL, "null argument");
-    if (c->capturing) return fail(PFT_EINVAL, "host transfers cannot be captured in a graph");
+// ENC with (v, e0, e1) from host arrays, or from the streams of d.seed
+static int encrypt_core(pft_ctx* c, const int64_t* m, uint32_t level, double scale, const int64_t* v,
+                        const int64_t* e0, const int64_t* e1, const Draws& d, pft_ct* out) {
     const pft_params* P = c->P;
     if (!c->pk) return fail(PFT_ENOKEY, "no public key");
     if (level < 1 || level > P->L) return fail(PFT_ELEVEL, "level %u out of range", level);
-    if (!check_ternary(v, P->n)) return fail(PFT_EINVAL, "v must be ternary");
     const uint32_t n = P->n;
     const size_t nl = (size_t)level * n;
     int r;
@@ -1000,9 +1100,15 @@ extern "C" int pft_encrypt(pft_ctx* c, const int64_t* m, uint32_t level, double 
     uint64_t* E0 = V + nl;
     uint64_t* E1 = E0 + nl;
     int64_t* raw = (int64_t*)(E1 + nl);
-    if ((r = upload_i64(c, raw, m, n)) || (r = upload_i64(c, raw + n, v, n)) || (r = upload_i64(c, raw + 2 * n, e0, n)) ||
-        (r = upload_i64(c, raw + 3 * n, e1, n)))
+    if ((r = upload_i64(c, raw, m, n))) return r;
+    if (d.seeded) {
+        sample_small(c, d, 0, DRAW_ENC_V, 0, raw + n);
+        sample_small(c, d, 1, DRAW_ENC_E0, 0, raw + 2 * n);
+        sample_small(c, d, 1, DRAW_ENC_E1, 0, raw + 3 * n);
+    } else if ((r = upload_i64(c, raw + n, v, n)) || (r = upload_i64(c, raw + 2 * n, e0, n)) ||
+               (r = upload_i64(c, raw + 3 * n, e1, n))) {
         return r;
+    }
     launch_int_to_rns(raw, sb(P, {M, V, E0, E1}, level), c->tabs, P->log_n, c->stream);
     ntt_rows(c, M, 4, level, level, false);
     const size_t nL = (size_t)P->L * n;
@@ -1016,6 +1122,21 @@ extern "C" int pft_encrypt(pft_ctx* c, const int64_t* m, uint32_t level, double 
     out->scale = scale;
     HIPCK(hipStreamSynchronize(c->stream));  // the raw host inputs were pageable copies
     return PFT_OK;
+}
+
+extern "C" int pft_encrypt(pft_ctx* c, const int64_t* m, uint32_t level, double scale, const int64_t* v,
+                           const int64_t* e0, const int64_t* e1, pft_ct* out) {
+    if (!c || !m || !v || !e0 || !e1 || !out || !out->data) return fail(PFT_EINVAL, "null argument");
+    if (c->capturing) return fail(PFT_EINVAL, "host transfers cannot be captured in a graph");
+    if (!check_ternary(v, c->P->n)) return fail(PFT_EINVAL, "v must be ternary");
+    return encrypt_core(c, m, level, scale, v, e0, e1, host_draws(nullptr, nullptr), out);
+}
+
+extern "C" int pft_encrypt_seeded(pft_ctx* c, const int64_t* m, uint32_t level, double scale, uint64_t seed,
+                                  pft_ct* out) {
+    if (!c || !m || !out || !out->data) return fail(PFT_EINVAL, "null argument");
+    if (c->capturing) return fail(PFT_EINVAL, "host transfers cannot be captured in a graph");
+    return encrypt_core(c, m, level, scale, nullptr, nullptr, nullptr, seeded_draws(seed, 0), out);
 }
 
 extern "C" int pft_decrypt(pft_ctx* c, const pft_ct* ct, uint64_t* out) {

@@ -163,3 +163,22 @@ void launch_add_const_b(uint32_t n, const ItemPtrs& in, const ItemPtrs& out, con
 // ws_z + off_x + j ct_words.  J <= PFT_MAX_ITEMS.
 void launch_ct_dot_b(uint32_t n, const ItemPtrs& e, uint32_t J, WsRef xs, uint64_t off_x, uint64_t ct_words, WsRef ws,
                      uint64_t off_d, uint32_t level, const DevTables& t, uint32_t log_n, hipStream_t st);
+
+// Seeded draws (sampler.hip): Philox4x64-10 streams keyed by (k0, k1).
+#define PFT_GAUSS_BOUND 19  // the discrete Gaussian's support is -19..19
+struct SampleModuli {
+    uint64_t q[64];  // modulus of output row i
+};
+struct GaussianCdt {
+    uint64_t t[2 * PFT_GAUSS_BOUND];  // floor(2^64 F(k)), k = -B .. B-1
+    uint32_t count;
+};
+// The thresholds of the discrete Gaussian of sigma 3.2; returns their count
+// (2 PFT_GAUSS_BOUND) or -1 if capacity is too small.  Host only.
+int gaussian_cdt_host(uint64_t* t, uint32_t capacity);
+// out[i][j], i < rows, j < n: uniform residues mod mods.q[i]
+void launch_sample_uniform(uint64_t k0, uint64_t k1, const SampleModuli& mods, uint32_t rows, uint64_t* out,
+                           uint32_t n, hipStream_t st);
+// out[j], j < n: kind 0 ternary, kind 1 discrete Gaussian
+void launch_sample_small(uint32_t kind, uint64_t k0, uint64_t k1, const GaussianCdt& cdt, int64_t* out, uint32_t n,
+                         hipStream_t st);

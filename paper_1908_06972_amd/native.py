@@ -101,6 +101,10 @@ SIGNATURES = [
     ("pft_ptmat_destroy", [_vp], None),
     ("pft_ptmatvec", [_vp, _vp, ctypes.c_uint32, ctypes.POINTER(CtDesc), ctypes.POINTER(CtDesc)], ctypes.c_int),
     ("pft_set_key_cache", [_vp, ctypes.c_uint32], ctypes.c_int),
+    ("pft_keygen", [_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32), ctypes.c_uint32], ctypes.c_int),
+    ("pft_gaussian_cdt", [_u64p, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32)], ctypes.c_int),
+    ("pft_encrypt_seeded", [_vp, _i64p, ctypes.c_uint32, ctypes.c_double, ctypes.c_uint64, ctypes.POINTER(CtDesc)],
+     ctypes.c_int),
     ("pft_key_cache_stats", [_vp, _u64p], ctypes.c_int),
     ("pft_ptdot_create", [_vp, _dblp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, _vp], ctypes.c_int),
     ("pft_ptdot_create_from_coeffs", [_vp, _i64p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_double,

@@ -175,3 +175,17 @@ def test_exec_plan_rejects_bad_lists():
     # a rescale chain: the simulated level drops, so the second rescale of a
     # level-2 input fails
     assert _plan([(RS, 0, 0, 1, 0, 0), (RS, 1, 0, 2, 0, 0)], [2, 0, 0])[0] == N.PFT_ELEVEL
+
+
+def test_library_gaussian_table_equals_oracle():
+    """pft_gaussian_cdt (120-bit fixed point in the library) against the
+    oracle's 60-digit decimal table: every threshold identical."""
+    from oracle import sampler as SP
+    lib = N.load()
+    t = np.zeros(64, dtype=np.uint64)
+    cnt = ctypes.c_uint32(0)
+    N.check(lib.pft_gaussian_cdt(N.u64p(t), 64, ctypes.byref(cnt)))
+    assert cnt.value == 2 * SP.BOUND
+    assert t[:cnt.value].tolist() == SP.gaussian_cdt()
+    with pytest.raises(N.PftError):
+        N.check(lib.pft_gaussian_cdt(N.u64p(t), 37, ctypes.byref(cnt)))
