@@ -447,9 +447,11 @@ class Context:
         self.lib.pft_ntt_candidates(self.params.handle, buf, n)
         return [self._sched_from(buf[4 * i:4 * i + 4]) for i in range(n)]
 
-    def bconv_mode(self, mfma: bool):
-        """Base conversions on the matrix cores (True, the default) or the VALU."""
-        N.check(self.lib.pft_bconv_mode(self.handle, 1 if mfma else 0))
+    def bconv_mode(self, mfma: bool, fused: bool = True):
+        """Base conversions on the matrix cores (True, the default) or the
+        VALU; with `fused` (the default) ModUp also applies the first pass of
+        the transform of its rows."""
+        N.check(self.lib.pft_bconv_mode(self.handle, (2 if fused else 1) if mfma else 0))
 
     def ntt_autotune(self, enable: bool):
         N.check(self.lib.pft_ntt_autotune(self.handle, int(bool(enable))))

@@ -230,6 +230,7 @@ struct pft_ctx {
     // NTT pass schedules: pinned per direction, else tuned per (direction,
     // batch-size class) on first use when ntt_tune is set
     bool bconv_mfma = true;  // base conversions on the matrix cores
+    bool modup_fuse = true;  // ModUp fused with the first forward transform pass (MFMA only)
     bool ntt_tune = true;
     NttSchedule ntt_pinned[2] = {};
     std::map<uint32_t, NttSchedule> ntt_tuned;
@@ -698,7 +699,7 @@ static NttSchedule ntt_schedule(pft_ctx* c, bool inverse, uint64_t limbs) {
 // epi: forward transforms of (item, b) polynomial pairs whose final pass
 // finishes ModDown; epi->out lists every item, a launch gets its share.
 static void ntt_jobs(pft_ctx* c, const std::vector<NttJob>& jobs, uint32_t n_limbs, uint32_t split, bool inverse,
-                     uint32_t off0 = 0, const NttEpilogue* epi = nullptr, int64_t src_delta = 0) {
+                     uint32_t off0 = 0, const NttEpilogue* epi = nullptr, int64_t src_delta = 0, uint32_t first = 0) {
     const pft_params* P = c->P;
     const NttSchedule sched = ntt_schedule(c, inverse, (uint64_t)jobs.size() * n_limbs);
     for (size_t s = 0; s < jobs.size(); s += PFT_MAX_POLYS) {
@@ -721,9 +722,9 @@ static void ntt_jobs(pft_ctx* c, const std::vector<NttJob>& jobs, uint32_t n_lim
                 e.out[i] = s / 2 + i < PFT_MAX_POLYS / 2 ? epi->out[s / 2 + i] : nullptr;
                 e.acc_item[i] = s / 2 + i < PFT_MAX_POLYS / 2 ? epi->acc_item[s / 2 + i] : nullptr;
             }
-            launch_ntt(b, c->tabs, P->log_n, inverse, sched, c->stream, hook(c), &e);
+            launch_ntt(b, c->tabs, P->log_n, inverse, sched, c->stream, hook(c), &e, first);
         } else {
-            launch_ntt(b, c->tabs, P->log_n, inverse, sched, c->stream, hook(c));
+            launch_ntt(b, c->tabs, P->log_n, inverse, sched, c->stream, hook(c), nullptr, first);
         }
     }
 }
@@ -1335,21 +1336,10 @@ static void key_switch_b(pft_ctx* c, uint32_t n, WsRef ws, const KsLayout& K, ui
         for (uint32_t z = 0; z < n; ++z) jobs.push_back(NttJob{ws.base + z * ws.stride + K.off_dcoef, 255u, 0u});
         ntt_jobs(c, jobs, level, ~0u, true, 0, nullptr, (int64_t)off_d - (int64_t)K.off_dcoef);
     }
-    // ModUp base conversion
-    {
-        double rd = 0, wr = 0, macs = 0;
-        for (uint32_t j = 0; j < beta; ++j) {
-            const uint32_t na = std::min(j * A + A, level) - j * A;
-            rd += na;
-            wr += rows - na;
-            macs += (double)(rows - na) * na + na;
-        }
-        timed(c, PK_MODUP, 8.0 * N * (rd + wr) * n, N * macs * n,
-              [&] { launch_modup_b(n, ws, K.off_dcoef, K.off_ext, level, c->kc, c->tabs, lg, c->bconv_mfma, c->stream); },
-              c->bconv_mfma ? (std::min(P->alpha, level) + 1) / 2 : 0);
-    }
-    // ModUp transforms: all digits of all items, full digits and the ragged
-    // last digit in separate launches (different limb counts)
+    // ModUp base conversion and the forward transforms of its rows: all
+    // digits of all items, full digits and the ragged last digit in separate
+    // transform launches (different limb counts).  Where both schedules start
+    // with a radix-16 column pass, ModUp applies that pass itself.
     {
         std::vector<NttJob> full, last;
         uint32_t na_last = 0;
@@ -1360,8 +1350,33 @@ static void key_switch_b(pft_ctx* c, uint32_t n, WsRef ws, const KsLayout& K, ui
                 (na == A ? full : last).push_back(job);
                 if (na != A) na_last = na;
             }
-        if (!full.empty()) ntt_jobs(c, full, rows - A, level, false);
-        if (!last.empty()) ntt_jobs(c, last, rows - na_last, level, false);
+        auto col16 = [&](const std::vector<NttJob>& jobs, uint32_t limbs) {
+            if (jobs.empty()) return true;
+            const NttSchedule s = ntt_schedule(c, false, (uint64_t)jobs.size() * limbs);
+            return s.n_passes >= 2 && s.radix[0] == 4;
+        };
+        const uint32_t nkb = (std::min(P->alpha, level) + 1) / 2;
+        const bool fuse = c->bconv_mfma && c->modup_fuse && lg >= 8 && nkb <= 6 && col16(full, rows - A) &&
+                          col16(last, rows - na_last);
+        double rd = 0, wr = 0, macs = 0;
+        for (uint32_t j = 0; j < beta; ++j) {
+            const uint32_t na = std::min(j * A + A, level) - j * A;
+            rd += na;
+            wr += rows - na;
+            macs += (double)(rows - na) * na + na;
+        }
+        if (fuse) {
+            timed(c, PK_MODUP, 8.0 * N * (rd + wr) * n, N * macs * n,
+                  [&] { launch_modup_col_b(n, ws, K.off_dcoef, K.off_ext, level, c->kc, c->tabs, lg, c->stream); },
+                  64u + nkb);
+        } else {
+            timed(c, PK_MODUP, 8.0 * N * (rd + wr) * n, N * macs * n, [&] {
+                launch_modup_b(n, ws, K.off_dcoef, K.off_ext, level, c->kc, c->tabs, lg, c->bconv_mfma, c->stream);
+            }, c->bconv_mfma ? nkb : 0);
+        }
+        const uint32_t first = fuse ? 1u : 0u;
+        if (!full.empty()) ntt_jobs(c, full, rows - A, level, false, 0, nullptr, 0, first);
+        if (!last.empty()) ntt_jobs(c, last, rows - na_last, level, false, 0, nullptr, 0, first);
     }
     // key inner product over level + K rows
     // the key is read once per launch (shared by the batch); each item reads
@@ -2366,8 +2381,9 @@ extern "C" int pft_ntt_candidates(const pft_params* p, uint32_t* scheds, uint32_
 
 extern "C" int pft_bconv_mode(pft_ctx* c, int mode) {
     if (!c) return fail(PFT_EINVAL, "null context");
-    if (mode != 0 && mode != 1) return fail(PFT_EINVAL, "mode must be 0 (VALU) or 1 (MFMA)");
-    c->bconv_mfma = mode == 1;
+    if (mode < 0 || mode > 2) return fail(PFT_EINVAL, "mode must be 0 (VALU), 1 (MFMA) or 2 (MFMA, fused ModUp)");
+    c->bconv_mfma = mode >= 1;
+    c->modup_fuse = mode == 2;
     return PFT_OK;
 }
 

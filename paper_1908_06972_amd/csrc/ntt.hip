@@ -27,9 +27,11 @@
 //   * otherwise (q < 2^60): 64-bit integer Shoup butterflies kept lazily
 //     reduced (forward in [0, 4q), inverse in [0, 2q)).
 // Inputs below 4q are accepted; outputs of a full transform are in [0, q).
+#include "bconv_device.h"
 #include "pft_device.h"
 #include "pft_kernels.h"
 
+#include <algorithm>
 #include <type_traits>
 
 namespace {
@@ -495,6 +497,115 @@ void launch_pass(const PolyBatch& b, const DevTables& t, uint32_t log_n, uint32_
     }
 }
 
+// ModUp (digit j = blockIdx.y of item z = blockIdx.z) fused with the first
+// pass (stages 0-3, a radix-16 column pass) of the forward transform of every
+// row it produces.  The workgroup converts the 256 coefficients
+// u0 + u + t N/16 (u, t < 16): the same exact contraction on the matrix cores
+// and fold as the stand-alone ModUp kernel, for up to 16 target rows at a
+// time, into LDS; then thread (target, u) takes the 16 values t of its
+// column through the four stages exactly as the first transform pass does
+// (fp64 rows converted on entry) and stores them in that pass's output form,
+// so the transform continues with its second pass.
+template <uint32_t NKB>
+__global__ __launch_bounds__(256) void k_modup_col_b(WsRef ws, uint64_t off_d, uint64_t off_ext, uint32_t level,
+                                                     KsConsts kc, const DevMod* __restrict__ mods,
+                                                     const TwPair* __restrict__ tw, uint32_t log_n) {
+    constexpr uint32_t ROWP = 272;  // LDS words per target row (256 coefficients + padding)
+    __shared__ uint64_t ybuf[16 * ROWP];
+    __shared__ BconvRed s_red[64];
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, half = lane >> 5, wave = tid >> 6;
+    const uint32_t S = 1u << (log_n - 4);
+    const uint32_t u0 = blockIdx.x * 16u;
+    const uint32_t j = blockIdx.y;
+    const uint32_t i0 = j * kc.alpha;
+    const uint32_t na = min(i0 + kc.alpha, level) - i0;
+    const uint32_t rows = level + kc.K, T = rows - na;
+    const size_t cbase = ((size_t)(level - 1) * kc.dnum + j) * kc.alpha;
+    uint64_t* item = ws.base + (size_t)blockIdx.z * ws.stride;
+    const uint64_t* __restrict__ d = item + off_d;
+    uint64_t* __restrict__ outj = item + off_ext + ((size_t)j * rows << log_n);
+    // input digits of this lane's coefficient in each of the wave's two
+    // 32-column blocks: column ci = 32 cb + (lane & 31) = 16 t + u
+    uint32_t ci[2];
+    long bop[2][NKB];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        ci[h] = 32u * (2u * wave + (uint32_t)h) + (lane & 31u);
+        const uint32_t pos = u0 + (ci[h] & 15u) + (ci[h] >> 4) * S;
+#pragma unroll
+        for (uint32_t kb = 0; kb < NKB; ++kb) {
+            const uint32_t ii = 2 * kb + half;
+            uint64_t x = 0;
+            if (ii < na) {
+                const TwPair hv = kc.modup_hatinv[cbase + ii];
+                x = shoup(d[((size_t)(i0 + ii) << log_n) + pos], hv.w, hv.wp, mods[i0 + ii].q);
+            }
+            bop[h][kb] = split_digits(x);
+        }
+    }
+    stage_red(kc, s_red);
+    const uint64_t* __restrict__ aop =
+        kc.up_aop + ((size_t)(level - 1) * kc.dnum + j) * kc.up_rt * kc.up_kb * 64 + lane;
+    const uint32_t tiles = (T + 3) / 4;
+    long av[NKB];
+#pragma unroll
+    for (uint32_t kb = 0; kb < NKB; ++kb) av[kb] = (long)aop[kb * 64];
+    for (uint32_t tb0 = 0; tb0 < T; tb0 += 16) {
+        const uint32_t nt = min(16u, T - tb0);
+        for (uint32_t rt = 0; rt * 4 < nt; ++rt) {
+            const uint32_t g = tb0 / 4 + rt;  // row tile of the digit's constant operands
+            const v16i zero = {};
+            v16i acc0 = __builtin_amdgcn_mfma_i32_32x32x16_i8(av[0], bop[0][0], zero, 0, 0, 0);
+            v16i acc1 = __builtin_amdgcn_mfma_i32_32x32x16_i8(av[0], bop[1][0], zero, 0, 0, 0);
+#pragma unroll
+            for (uint32_t kb = 1; kb < NKB; ++kb) {
+                acc0 = __builtin_amdgcn_mfma_i32_32x32x16_i8(av[kb], bop[0][kb], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_i32_32x32x16_i8(av[kb], bop[1][kb], acc1, 0, 0, 0);
+            }
+            if (g + 1 < tiles) {
+#pragma unroll
+                for (uint32_t kb = 0; kb < NKB; ++kb) av[kb] = (long)aop[((g + 1) * kc.up_kb + kb) * 64];
+            }
+#pragma unroll
+            for (int uu = 0; uu < 2; ++uu) {
+                const uint32_t tt = 4 * g + 2 * half + (uint32_t)uu;
+                if (tt < T) {
+                    const uint32_t t = tt < i0 ? tt : tt + na;
+                    const uint32_t mi = t < level ? t : kc.L + (t - level);
+                    int z[8];
+                    if (uu == 0) tile_digits<0>(acc0, z); else tile_digits<1>(acc0, z);
+                    ybuf[(tt - tb0) * ROWP + ci[0]] = fold_digits(z, s_red[mi]);
+                    if (uu == 0) tile_digits<0>(acc1, z); else tile_digits<1>(acc1, z);
+                    ybuf[(tt - tb0) * ROWP + ci[1]] = fold_digits(z, s_red[mi]);
+                }
+            }
+        }
+        __syncthreads();
+        const uint32_t tl = tid >> 4, u = tid & 15u;
+        if (tl < nt) {
+            const uint32_t tt = tb0 + tl;
+            const uint32_t t = tt < i0 ? tt : tt + na;
+            const uint32_t mi = t < level ? t : kc.L + (t - level);
+            const DevMod md = mods[mi];
+            const TwPair* __restrict__ twt = tw + ((size_t)mi << log_n);
+            uint64_t x[16];
+#pragma unroll
+            for (int e = 0; e < 16; ++e) x[e] = ybuf[tl * ROWP + 16u * e + u];
+            if (md.fp) {
+#pragma unroll
+                for (int e = 0; e < 16; ++e) x[e] = fp_from_u64(x[e]);
+                run_phase<4, 0, 4, false, true, false>(x, 0u, 0u, 0u, twt, md);
+            } else {
+                run_phase<4, 0, 4, false, false, false>(x, 0u, 0u, 0u, twt, md);
+            }
+            uint64_t* __restrict__ orow = outj + ((size_t)t << log_n) + u0 + u;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) orow[(size_t)e * S] = x[e];
+        }
+        __syncthreads();
+    }
+}
+
 template <bool INV>
 void launch_radix(uint32_t radix, const PolyBatch& b, const DevTables& t, uint32_t log_n, uint32_t s0, bool fin,
                   bool stage, bool e8, const NttEpilogue* epi, hipStream_t st, ProfHook* prof) {
@@ -560,8 +671,30 @@ bool ntt_schedule_valid(uint32_t log_n, const NttSchedule& s) {
     return false;
 }
 
+void launch_modup_col_b(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, uint32_t level, const KsConsts& kc,
+                        const DevTables& t, uint32_t log_n, hipStream_t st) {
+    const uint32_t beta = (level + kc.alpha - 1) / kc.alpha;
+    const uint32_t nkb = (std::min(kc.alpha, level) + 1) / 2;
+    const dim3 grid((1u << log_n) / 256, beta, n);
+#define PFT_MODUP_COL(K)                                                                                            \
+    case K:                                                                                                         \
+        hipLaunchKernelGGL(k_modup_col_b<K>, grid, dim3(256), 0, st, ws, off_d, off_ext, level, kc, t.mods, t.tw_fwd, \
+                           log_n);                                                                                  \
+        break;
+    switch (nkb) {
+        PFT_MODUP_COL(1)
+        PFT_MODUP_COL(2)
+        PFT_MODUP_COL(3)
+        PFT_MODUP_COL(4)
+        PFT_MODUP_COL(5)
+        PFT_MODUP_COL(6)
+        default: break;
+    }
+#undef PFT_MODUP_COL
+}
+
 void launch_ntt(const PolyBatch& b, const DevTables& t, uint32_t log_n, bool inverse, const NttSchedule& s,
-                hipStream_t st, ProfHook* prof, const NttEpilogue* epi) {
+                hipStream_t st, ProfHook* prof, const NttEpilogue* epi, uint32_t first) {
     if (b.n_polys == 0 || b.n_limbs == 0 || s.n_passes == 0 || s.n_passes > 3) return;
     uint32_t s0[4];
     uint32_t acc = 0;
@@ -573,7 +706,7 @@ void launch_ntt(const PolyBatch& b, const DevTables& t, uint32_t log_n, bool inv
     const bool stage = (s.flags & NTT_DIRECT_ROWS) == 0;
     const bool e8 = (s.flags & NTT_E8) != 0;
     if (!inverse) {
-        for (uint32_t p = 0; p < s.n_passes; ++p)
+        for (uint32_t p = first; p < s.n_passes; ++p)
             launch_radix<false>(s.radix[p], b, t, log_n, s0[p], p + 1 == s.n_passes, stage, e8,
                                 p + 1 == s.n_passes ? epi : nullptr, st, prof);
     } else {

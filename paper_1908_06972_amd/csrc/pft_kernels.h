@@ -63,8 +63,10 @@ bool ntt_supported(uint32_t log_n);
 int ntt_candidates(uint32_t log_n, NttSchedule* out, int max_out);
 bool ntt_schedule_valid(uint32_t log_n, const NttSchedule& s);
 // epi (forward only): finish ModDown in the final pass instead of storing.
+// first: a forward transform starts at pass `first` of the schedule (the
+// earlier passes already applied, e.g. by launch_modup_col_b).
 void launch_ntt(const PolyBatch& b, const DevTables& t, uint32_t log_n, bool inverse, const NttSchedule& s,
-                hipStream_t st, ProfHook* prof = nullptr, const NttEpilogue* epi = nullptr);
+                hipStream_t st, ProfHook* prof = nullptr, const NttEpilogue* epi = nullptr, uint32_t first = 0);
 
 // ---- elementwise kernels (ckks.hip) --------------------------------------
 // Signed integer polynomials x ([n_polys][N] int64, device) reduced into
@@ -136,6 +138,12 @@ void launch_automorphism_b(uint32_t n, const ItemPtrs& in, uint32_t rows, WsRef 
 // mfma: the contraction on the matrix cores (int8 digits), else 128-bit VALU MACs.
 void launch_modup_b(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, uint32_t level, const KsConsts& kc,
                     const DevTables& t, uint32_t log_n, bool mfma, hipStream_t st);
+// ModUp on the matrix cores fused with the first pass of the forward
+// transform (a radix-16 column pass, stages 0-3) of every converted row:
+// ext holds the output of that pass; the transform continues at pass 1 of a
+// schedule whose first radix is 4 (ntt.hip).  Needs log_n >= 8.
+void launch_modup_col_b(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, uint32_t level, const KsConsts& kc,
+                        const DevTables& t, uint32_t log_n, hipStream_t st);
 // acc [2][level+K][N] = sum_j x_j * key_j  (key: [dnum][2][L+K][N], Montgomery form)
 void launch_key_inner_b(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, uint64_t off_acc, const uint64_t* key,
                         uint32_t level, const KsConsts& kc, const DevTables& t, uint32_t log_n, hipStream_t st);

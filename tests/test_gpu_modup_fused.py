@@ -1,0 +1,109 @@
+"""ModUp fused with the first pass of the forward transform (k_modup_col_b):
+key switching bit-exact against the oracle with the forward schedule pinned
+to one that starts with a radix-16 column pass, so the fused path runs; full
+and ragged digits, one and several items, fp64 and integer rows; and the
+fused and unfused paths give the same ciphertexts."""
+
+import numpy as np
+import pytest
+
+import synth as S
+from oracle import ckks as C
+from oracle import sampler as SP
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    # alpha 2 (one k-block), 40-bit rows
+    "a2_n12": dict(log_n=12, n_q=4, q0_bits=60, q_bits=40, n_p=2, p_bits=60, dnum=2, scale=2 ** 40),
+    # alpha 6 (three k-blocks) as in the large ring: 50-bit fp64 rows, 60-bit integer rows
+    "a6_n12": dict(log_n=12, n_q=12, q0_bits=60, q_bits=50, n_p=6, p_bits=60, dnum=2, scale=2 ** 50),
+    # alpha 2 at N = 2^14 (column stride 1024)
+    "a2_n14": dict(log_n=14, n_q=8, q0_bits=60, q_bits=40, n_p=2, p_bits=60, dnum=4, scale=2 ** 40),
+}
+STEPS = [1, 5]
+
+
+class World:
+    def __init__(self, spec):
+        import paper_1908_06972_amd.ckks as L
+        self.op = C.Params(**spec)
+        self.lp = L.Params(*spec.values())
+        C.set_mul_mode(1)
+        n = self.n = self.op.n
+        self.ctx = L.Context(self.lp)
+        seed = 31
+        self.ctx.keygen(seed, STEPS)
+        self.s = SP.secret(seed, n)
+        self.pk = C.public_key(self.op, self.s, *SP.public_key_draws(seed, self.op.q, n))
+        mods = self.op.key_moduli()
+        self.rlk = C.relin_key(self.op, self.s, *SP.switch_key_draws(seed, 0, mods, self.op.dnum, n))
+        self.rot = {st: C.rotation_key(self.op, self.s, st,
+                                       *SP.switch_key_draws(seed, SP.rotation_key_id(st, n), mods, self.op.dnum, n))
+                    for st in STEPS}
+        cands = self.ctx.ntt_candidates()
+        self.col16 = [c for c in cands if c[0][0] == 4]
+        assert self.col16
+
+    def enc_pair(self, mseed, level):
+        m = S.plaintext_coeffs(S.rng(mseed), self.n, 2 ** 30)
+        g = self.ctx.encrypt_seeded(m, level, self.op.scale, 500 + mseed)
+        o = C.encrypt(self.op, self.pk, m, level, *SP.encryption_draws(500 + mseed, self.n), self.op.scale)
+        return g, o
+
+    def assert_same(self, g, o):
+        host = self.ctx.export(g)
+        assert np.array_equal(host[0], o.c0) and np.array_equal(host[1], o.c1)
+
+
+_worlds = {}
+
+
+def world(name):
+    import torch
+    assert torch.cuda.is_available()
+    if name not in _worlds:
+        _worlds[name] = World(CASES[name])
+    return _worlds[name]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("flags", [0, 3])
+def test_fused_modup_relin_and_rotation(name, flags):
+    w = world(name)
+    sched = [c for c in w.col16 if c[1] == flags][0]
+    w.ctx.ntt_set_schedule(False, sched)
+    w.ctx.bconv_mode(True, fused=True)
+    L = w.op.L
+    try:
+        for level in sorted({L, L - 1, 1}):
+            (ga, oa), (gb, ob) = w.enc_pair(10 + level, level), w.enc_pair(40 + level, level)
+            w.assert_same(w.ctx.mul_relin(ga, gb), C.hmul_relin(w.op, oa, ob, w.rlk))
+            for st in STEPS:
+                w.assert_same(w.ctx.rotate(ga, st), C.rotate(w.op, oa, st, w.rot[st]))
+    finally:
+        w.ctx.ntt_set_schedule(False, None)
+
+
+def test_fused_modup_batch_equals_unfused():
+    """Three items in one launch (grid z = 3): fused and unfused paths
+    produce the same ciphertexts, and both match the oracle."""
+    w = world("a6_n12")
+    sched = [c for c in w.col16 if c[1] == 0][0]
+    w.ctx.ntt_set_schedule(False, sched)
+    level = w.op.L - 1  # a ragged last digit (11 = 6 + 5)
+    pairs = [(w.enc_pair(70 + i, level), w.enc_pair(80 + i, level)) for i in range(3)]
+    try:
+        outs = {}
+        for fused in (True, False):
+            w.ctx.bconv_mode(True, fused=fused)
+            outs[fused] = [w.ctx.export(g) for g in
+                           w.ctx.mul_relin_batch([p[0][0] for p in pairs], [p[1][0] for p in pairs])]
+        for a, b in zip(outs[True], outs[False]):
+            assert np.array_equal(a, b)
+        for ((_, oa), (_, ob)), host in zip(pairs, outs[True]):
+            o = C.hmul_relin(w.op, oa, ob, w.rlk)
+            assert np.array_equal(host[0], o.c0) and np.array_equal(host[1], o.c1)
+    finally:
+        w.ctx.bconv_mode(True, fused=True)
+        w.ctx.ntt_set_schedule(False, None)
