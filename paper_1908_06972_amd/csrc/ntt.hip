@@ -507,7 +507,7 @@ void launch_pass(const PolyBatch& b, const DevTables& t, uint32_t log_n, uint32_
 // (fp64 rows converted on entry) and stores them in that pass's output form,
 // so the transform continues with its second pass.
 template <uint32_t NKB>
-__global__ __launch_bounds__(256) void k_modup_col_b(WsRef ws, uint64_t off_d, uint64_t off_ext, uint32_t level,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_modup_col_b(WsRef ws, uint64_t off_d, uint64_t off_ext, uint32_t level,
                                                      KsConsts kc, const DevMod* __restrict__ mods,
                                                      const TwPair* __restrict__ tw, uint32_t log_n) {
     constexpr uint32_t ROWP = 272;  // LDS words per target row (256 coefficients + padding)
@@ -554,29 +554,28 @@ __global__ __launch_bounds__(256) void k_modup_col_b(WsRef ws, uint64_t off_d, u
         const uint32_t nt = min(16u, T - tb0);
         for (uint32_t rt = 0; rt * 4 < nt; ++rt) {
             const uint32_t g = tb0 / 4 + rt;  // row tile of the digit's constant operands
-            const v16i zero = {};
-            v16i acc0 = __builtin_amdgcn_mfma_i32_32x32x16_i8(av[0], bop[0][0], zero, 0, 0, 0);
-            v16i acc1 = __builtin_amdgcn_mfma_i32_32x32x16_i8(av[0], bop[1][0], zero, 0, 0, 0);
+            // the two column blocks one after the other (one accumulator tile live)
 #pragma unroll
-            for (uint32_t kb = 1; kb < NKB; ++kb) {
-                acc0 = __builtin_amdgcn_mfma_i32_32x32x16_i8(av[kb], bop[0][kb], acc0, 0, 0, 0);
-                acc1 = __builtin_amdgcn_mfma_i32_32x32x16_i8(av[kb], bop[1][kb], acc1, 0, 0, 0);
-            }
-            if (g + 1 < tiles) {
+            for (int h = 0; h < 2; ++h) {
+                const v16i zero = {};
+                v16i acc = __builtin_amdgcn_mfma_i32_32x32x16_i8(av[0], bop[h][0], zero, 0, 0, 0);
 #pragma unroll
-                for (uint32_t kb = 0; kb < NKB; ++kb) av[kb] = (long)aop[((g + 1) * kc.up_kb + kb) * 64];
-            }
+                for (uint32_t kb = 1; kb < NKB; ++kb)
+                    acc = __builtin_amdgcn_mfma_i32_32x32x16_i8(av[kb], bop[h][kb], acc, 0, 0, 0);
+                if (h == 1 && g + 1 < tiles) {
 #pragma unroll
-            for (int uu = 0; uu < 2; ++uu) {
-                const uint32_t tt = 4 * g + 2 * half + (uint32_t)uu;
-                if (tt < T) {
-                    const uint32_t t = tt < i0 ? tt : tt + na;
-                    const uint32_t mi = t < level ? t : kc.L + (t - level);
-                    int z[8];
-                    if (uu == 0) tile_digits<0>(acc0, z); else tile_digits<1>(acc0, z);
-                    ybuf[(tt - tb0) * ROWP + ci[0]] = fold_digits(z, s_red[mi]);
-                    if (uu == 0) tile_digits<0>(acc1, z); else tile_digits<1>(acc1, z);
-                    ybuf[(tt - tb0) * ROWP + ci[1]] = fold_digits(z, s_red[mi]);
+                    for (uint32_t kb = 0; kb < NKB; ++kb) av[kb] = (long)aop[((g + 1) * kc.up_kb + kb) * 64];
+                }
+#pragma unroll
+                for (int uu = 0; uu < 2; ++uu) {
+                    const uint32_t tt = 4 * g + 2 * half + (uint32_t)uu;
+                    if (tt < T) {
+                        const uint32_t t = tt < i0 ? tt : tt + na;
+                        const uint32_t mi = t < level ? t : kc.L + (t - level);
+                        int z[8];
+                        if (uu == 0) tile_digits<0>(acc, z); else tile_digits<1>(acc, z);
+                        ybuf[(tt - tb0) * ROWP + ci[h]] = fold_digits(z, s_red[mi]);
+                    }
                 }
             }
         }
