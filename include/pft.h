@@ -359,11 +359,12 @@ int pft_ntt_tuning_import(pft_ctx* ctx, const uint32_t* entries, uint32_t count)
  * are summed exactly in int32 by v_mfma_i32_32x32x16_i8, and each target's
  * 8 digit sums are folded back into a residue on the VALU.  mode 0 selects the
  * 128-bit VALU multiply-accumulate kernels instead, 1 the matrix cores, 2 (the
- * default) the matrix cores with ModUp fused with the first pass of the
- * forward transform of its rows (used where that transform's schedule starts
- * with a radix-16 column pass and N >= 256; otherwise as mode 1): each
- * converted row is written once, already through stages 0-3.  The results
- * are identical in every mode.  PFT_EINVAL for any other mode. */
+ * default) the matrix cores with each conversion (ModUp and ModDown) fused
+ * with the first pass of the forward transform of its output rows (used
+ * where that transform's schedule starts with a radix-16 column pass and
+ * N >= 256; otherwise as mode 1): each converted row is written once, already
+ * through stages 0-3.  The results are identical in every mode.  PFT_EINVAL
+ * for any other mode. */
 int pft_bconv_mode(pft_ctx* ctx, int mode);
 
 /* ---- op-list executor ---------------------------------------------------

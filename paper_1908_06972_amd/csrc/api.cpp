@@ -1319,6 +1319,13 @@ static ItemPtrs ws_items(WsRef ws, uint32_t n, uint64_t off = 0) {
     return ip;
 }
 
+// Whether the forward schedule of `limbs` limbs starts with a radix-16
+// column pass (the pass the fused base-conversion kernels apply).
+static bool first_pass_col16(pft_ctx* c, uint64_t limbs) {
+    const NttSchedule s = ntt_schedule(c, false, limbs);
+    return s.n_passes >= 2 && s.radix[0] == 4;
+}
+
 // Key switching of d (NTT domain, [level][N] at ws_z + off_d) for n items:
 // out_z = ModDown(sum_j ModUp_j(d) key_j) + (ws rows at off_add0/off_add1),
 // plus, for the first polynomial, the rows at off_add0b (out may be those
@@ -1351,9 +1358,7 @@ static void key_switch_b(pft_ctx* c, uint32_t n, WsRef ws, const KsLayout& K, ui
                 if (na != A) na_last = na;
             }
         auto col16 = [&](const std::vector<NttJob>& jobs, uint32_t limbs) {
-            if (jobs.empty()) return true;
-            const NttSchedule s = ntt_schedule(c, false, (uint64_t)jobs.size() * limbs);
-            return s.n_passes >= 2 && s.radix[0] == 4;
+            return jobs.empty() || first_pass_col16(c, (uint64_t)jobs.size() * limbs);
         };
         const uint32_t nkb = (std::min(P->alpha, level) + 1) / 2;
         const bool fuse = c->bconv_mfma && c->modup_fuse && lg >= 8 && nkb <= 6 && col16(full, rows - A) &&
@@ -1394,13 +1399,22 @@ static void key_switch_b(pft_ctx* c, uint32_t n, WsRef ws, const KsLayout& K, ui
                 jobs.push_back(NttJob{ws.base + z * ws.stride + K.off_acc + ((uint64_t)b * rows << lg), 0u, level});
         ntt_jobs(c, jobs, P->K, level, true);
     }
-    timed(c, PK_MODDOWN_CONV, 8.0 * N * (2.0 * P->K + 2.0 * level) * n, 2.0 * N * P->K * level * n,
-          [&] {
-              launch_moddown_conv_b(n, ws, K.off_acc, K.off_conv, level, c->kc, c->tabs, lg, c->bconv_mfma, c->stream);
-          },
-          c->bconv_mfma ? (P->K + 1) / 2 : 0);
-    // the forward transform of conv finishes ModDown in its final pass:
+    // conversion of the special rows to the q-limbs (fused with the first
+    // pass of conv's forward transform where its schedule allows), then the
+    // forward transform of conv finishes ModDown in its final pass:
     // out_b[i] = (acc_b[i] - conv_b[i]) P^-1 (+ add_b)
+    const uint32_t down_kb = (P->K + 1) / 2;
+    const bool fuse_down = c->bconv_mfma && c->modup_fuse && lg >= 8 && down_kb <= 6 &&
+                           first_pass_col16(c, 2ull * n * level);
+    if (fuse_down) {
+        timed(c, PK_MODDOWN_CONV, 8.0 * N * (2.0 * P->K + 2.0 * level) * n, 2.0 * N * P->K * level * n,
+              [&] { launch_moddown_col_b(n, ws, K.off_acc, K.off_conv, level, c->kc, c->tabs, lg, c->stream); },
+              64u + down_kb);
+    } else {
+        timed(c, PK_MODDOWN_CONV, 8.0 * N * (2.0 * P->K + 2.0 * level) * n, 2.0 * N * P->K * level * n, [&] {
+            launch_moddown_conv_b(n, ws, K.off_acc, K.off_conv, level, c->kc, c->tabs, lg, c->bconv_mfma, c->stream);
+        }, c->bconv_mfma ? down_kb : 0);
+    }
     {
         std::vector<NttJob> jobs;
         for (uint32_t z = 0; z < n; ++z)
@@ -1419,7 +1433,7 @@ static void key_switch_b(pft_ctx* c, uint32_t n, WsRef ws, const KsLayout& K, ui
         epi.pinv = c->kc.down_pinv;
         epi.pinv_fp = c->kc.down_pinv + P->L;
         epi.level = level;
-        ntt_jobs(c, jobs, level, ~0u, false, 0, &epi);
+        ntt_jobs(c, jobs, level, ~0u, false, 0, &epi, 0, fuse_down ? 1u : 0u);
     }
 }
 

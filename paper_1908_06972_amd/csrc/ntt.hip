@@ -497,33 +497,39 @@ void launch_pass(const PolyBatch& b, const DevTables& t, uint32_t log_n, uint32_
     }
 }
 
-// ModUp (digit j = blockIdx.y of item z = blockIdx.z) fused with the first
-// pass (stages 0-3, a radix-16 column pass) of the forward transform of every
-// row it produces.  The workgroup converts the 256 coefficients
-// u0 + u + t N/16 (u, t < 16): the same exact contraction on the matrix cores
-// and fold as the stand-alone ModUp kernel, for up to 16 target rows at a
-// time, into LDS; then thread (target, u) takes the 16 values t of its
-// column through the four stages exactly as the first transform pass does
-// (fp64 rows converted on entry) and stores them in that pass's output form,
-// so the transform continues with its second pass.
-template <uint32_t NKB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_modup_col_b(WsRef ws, uint64_t off_d, uint64_t off_ext, uint32_t level,
-                                                     KsConsts kc, const DevMod* __restrict__ mods,
-                                                     const TwPair* __restrict__ tw, uint32_t log_n) {
+// A base conversion of hybrid key switching fused with the first pass
+// (stages 0-3, a radix-16 column pass) of the forward transform of every row
+// it produces.  ModUp (DOWN false): digit j = blockIdx.y of item z =
+// blockIdx.z, inputs the digit's rows of d, targets every row outside the
+// digit (q-limbs, then special primes), output ext_j.  ModDown (DOWN true):
+// polynomial b = blockIdx.y, inputs the K special rows of acc_b, targets the
+// q-limbs 0..level-1, output conv_b.  The workgroup converts the 256
+// coefficients u0 + u + t N/16 (u, t < 16): the same exact contraction on the
+// matrix cores and fold as the stand-alone conversion kernels, for up to 16
+// target rows at a time, into LDS; then thread (target, u) takes the 16
+// values t of its column through the four stages exactly as the first
+// transform pass does (fp64 rows converted on entry) and stores them in that
+// pass's output form, so the transform continues with its second pass.
+template <uint32_t NKB, bool DOWN>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_bconv_col_b(
+    WsRef ws, uint64_t off_in, uint64_t off_out, uint32_t level, KsConsts kc, const DevMod* __restrict__ mods,
+    const TwPair* __restrict__ tw, uint32_t log_n) {
     constexpr uint32_t ROWP = 272;  // LDS words per target row (256 coefficients + padding)
     __shared__ uint64_t ybuf[16 * ROWP];
     __shared__ BconvRed s_red[64];
     const uint32_t tid = threadIdx.x, lane = tid & 63u, half = lane >> 5, wave = tid >> 6;
     const uint32_t S = 1u << (log_n - 4);
     const uint32_t u0 = blockIdx.x * 16u;
-    const uint32_t j = blockIdx.y;
-    const uint32_t i0 = j * kc.alpha;
-    const uint32_t na = min(i0 + kc.alpha, level) - i0;
-    const uint32_t rows = level + kc.K, T = rows - na;
+    const uint32_t j = blockIdx.y;  // digit (ModUp) or polynomial (ModDown)
+    const uint32_t rows = level + kc.K;
+    // ModUp: the digit's limbs [i0, i0 + na) are the inputs and are skipped as targets
+    const uint32_t i0 = DOWN ? level : j * kc.alpha;
+    const uint32_t na = DOWN ? kc.K : min(i0 + kc.alpha, level) - i0;
+    const uint32_t T = DOWN ? level : rows - na;
     const size_t cbase = ((size_t)(level - 1) * kc.dnum + j) * kc.alpha;
     uint64_t* item = ws.base + (size_t)blockIdx.z * ws.stride;
-    const uint64_t* __restrict__ d = item + off_d;
-    uint64_t* __restrict__ outj = item + off_ext + ((size_t)j * rows << log_n);
+    const uint64_t* __restrict__ in = item + off_in + (DOWN ? ((size_t)j * rows << log_n) : 0);
+    uint64_t* __restrict__ out = item + off_out + ((size_t)j * (DOWN ? level : rows) << log_n);
     // input digits of this lane's coefficient in each of the wave's two
     // 32-column blocks: column ci = 32 cb + (lane & 31) = 16 t + u
     uint32_t ci[2];
@@ -537,23 +543,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             const uint32_t ii = 2 * kb + half;
             uint64_t x = 0;
             if (ii < na) {
-                const TwPair hv = kc.modup_hatinv[cbase + ii];
-                x = shoup(d[((size_t)(i0 + ii) << log_n) + pos], hv.w, hv.wp, mods[i0 + ii].q);
+                const TwPair hv = DOWN ? kc.down_phatinv[ii] : kc.modup_hatinv[cbase + ii];
+                const uint64_t qi = mods[DOWN ? kc.L + ii : i0 + ii].q;
+                x = shoup(in[((size_t)(i0 + ii) << log_n) + pos], hv.w, hv.wp, qi);
             }
             bop[h][kb] = split_digits(x);
         }
     }
     stage_red(kc, s_red);
+    const uint32_t kbs = DOWN ? kc.down_kb : kc.up_kb;
     const uint64_t* __restrict__ aop =
-        kc.up_aop + ((size_t)(level - 1) * kc.dnum + j) * kc.up_rt * kc.up_kb * 64 + lane;
+        (DOWN ? kc.down_aop : kc.up_aop + ((size_t)(level - 1) * kc.dnum + j) * kc.up_rt * kc.up_kb * 64) + lane;
     const uint32_t tiles = (T + 3) / 4;
+    // target tt: its row and modulus index
+    auto row_of = [&](uint32_t tt) { return DOWN ? tt : (tt < i0 ? tt : tt + na); };
+    auto mod_of = [&](uint32_t t) { return t < level ? t : kc.L + (t - level); };
     long av[NKB];
 #pragma unroll
     for (uint32_t kb = 0; kb < NKB; ++kb) av[kb] = (long)aop[kb * 64];
     for (uint32_t tb0 = 0; tb0 < T; tb0 += 16) {
         const uint32_t nt = min(16u, T - tb0);
         for (uint32_t rt = 0; rt * 4 < nt; ++rt) {
-            const uint32_t g = tb0 / 4 + rt;  // row tile of the digit's constant operands
+            const uint32_t g = tb0 / 4 + rt;  // row tile of the constant operands
             // the two column blocks one after the other (one accumulator tile live)
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
@@ -564,17 +575,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                     acc = __builtin_amdgcn_mfma_i32_32x32x16_i8(av[kb], bop[h][kb], acc, 0, 0, 0);
                 if (h == 1 && g + 1 < tiles) {
 #pragma unroll
-                    for (uint32_t kb = 0; kb < NKB; ++kb) av[kb] = (long)aop[((g + 1) * kc.up_kb + kb) * 64];
+                    for (uint32_t kb = 0; kb < NKB; ++kb) av[kb] = (long)aop[((g + 1) * kbs + kb) * 64];
                 }
 #pragma unroll
                 for (int uu = 0; uu < 2; ++uu) {
                     const uint32_t tt = 4 * g + 2 * half + (uint32_t)uu;
                     if (tt < T) {
-                        const uint32_t t = tt < i0 ? tt : tt + na;
-                        const uint32_t mi = t < level ? t : kc.L + (t - level);
                         int z[8];
                         if (uu == 0) tile_digits<0>(acc, z); else tile_digits<1>(acc, z);
-                        ybuf[(tt - tb0) * ROWP + ci[h]] = fold_digits(z, s_red[mi]);
+                        ybuf[(tt - tb0) * ROWP + ci[h]] = fold_digits(z, s_red[mod_of(row_of(tt))]);
                     }
                 }
             }
@@ -582,9 +591,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         __syncthreads();
         const uint32_t tl = tid >> 4, u = tid & 15u;
         if (tl < nt) {
-            const uint32_t tt = tb0 + tl;
-            const uint32_t t = tt < i0 ? tt : tt + na;
-            const uint32_t mi = t < level ? t : kc.L + (t - level);
+            const uint32_t t = row_of(tb0 + tl);
+            const uint32_t mi = mod_of(t);
             const DevMod md = mods[mi];
             const TwPair* __restrict__ twt = tw + ((size_t)mi << log_n);
             uint64_t x[16];
@@ -597,7 +605,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             } else {
                 run_phase<4, 0, 4, false, false, false>(x, 0u, 0u, 0u, twt, md);
             }
-            uint64_t* __restrict__ orow = outj + ((size_t)t << log_n) + u0 + u;
+            uint64_t* __restrict__ orow = out + ((size_t)t << log_n) + u0 + u;
 #pragma unroll
             for (int e = 0; e < 16; ++e) orow[(size_t)e * S] = x[e];
         }
@@ -670,26 +678,37 @@ bool ntt_schedule_valid(uint32_t log_n, const NttSchedule& s) {
     return false;
 }
 
+template <bool DOWN>
+static void launch_bconv_col(uint32_t nkb, dim3 grid, hipStream_t st, WsRef ws, uint64_t off_in, uint64_t off_out,
+                             uint32_t level, const KsConsts& kc, const DevTables& t, uint32_t log_n) {
+#define PFT_BCONV_COL(K)                                                                                          \
+    case K:                                                                                                       \
+        hipLaunchKernelGGL((k_bconv_col_b<K, DOWN>), grid, dim3(256), 0, st, ws, off_in, off_out, level, kc, t.mods, \
+                           t.tw_fwd, log_n);                                                                      \
+        break;
+    switch (nkb) {
+        PFT_BCONV_COL(1)
+        PFT_BCONV_COL(2)
+        PFT_BCONV_COL(3)
+        PFT_BCONV_COL(4)
+        PFT_BCONV_COL(5)
+        PFT_BCONV_COL(6)
+        default: break;
+    }
+#undef PFT_BCONV_COL
+}
+
 void launch_modup_col_b(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, uint32_t level, const KsConsts& kc,
                         const DevTables& t, uint32_t log_n, hipStream_t st) {
     const uint32_t beta = (level + kc.alpha - 1) / kc.alpha;
     const uint32_t nkb = (std::min(kc.alpha, level) + 1) / 2;
-    const dim3 grid((1u << log_n) / 256, beta, n);
-#define PFT_MODUP_COL(K)                                                                                            \
-    case K:                                                                                                         \
-        hipLaunchKernelGGL(k_modup_col_b<K>, grid, dim3(256), 0, st, ws, off_d, off_ext, level, kc, t.mods, t.tw_fwd, \
-                           log_n);                                                                                  \
-        break;
-    switch (nkb) {
-        PFT_MODUP_COL(1)
-        PFT_MODUP_COL(2)
-        PFT_MODUP_COL(3)
-        PFT_MODUP_COL(4)
-        PFT_MODUP_COL(5)
-        PFT_MODUP_COL(6)
-        default: break;
-    }
-#undef PFT_MODUP_COL
+    launch_bconv_col<false>(nkb, dim3((1u << log_n) / 256, beta, n), st, ws, off_d, off_ext, level, kc, t, log_n);
+}
+
+void launch_moddown_col_b(uint32_t n, WsRef ws, uint64_t off_acc, uint64_t off_conv, uint32_t level,
+                          const KsConsts& kc, const DevTables& t, uint32_t log_n, hipStream_t st) {
+    launch_bconv_col<true>((kc.K + 1) / 2, dim3((1u << log_n) / 256, 2, n), st, ws, off_acc, off_conv, level, kc, t,
+                           log_n);
 }
 
 void launch_ntt(const PolyBatch& b, const DevTables& t, uint32_t log_n, bool inverse, const NttSchedule& s,

@@ -144,6 +144,11 @@ void launch_modup_b(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, uint
 // schedule whose first radix is 4 (ntt.hip).  Needs log_n >= 8.
 void launch_modup_col_b(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, uint32_t level, const KsConsts& kc,
                         const DevTables& t, uint32_t log_n, hipStream_t st);
+// ModDown's conversion (conv_b = base conversion of the K special rows of
+// acc_b to the q-limbs 0..level-1) fused the same way: conv holds the output
+// of the first transform pass.
+void launch_moddown_col_b(uint32_t n, WsRef ws, uint64_t off_acc, uint64_t off_conv, uint32_t level,
+                          const KsConsts& kc, const DevTables& t, uint32_t log_n, hipStream_t st);
 // acc [2][level+K][N] = sum_j x_j * key_j  (key: [dnum][2][L+K][N], Montgomery form)
 void launch_key_inner_b(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, uint64_t off_acc, const uint64_t* key,
                         uint32_t level, const KsConsts& kc, const DevTables& t, uint32_t log_n, hipStream_t st);

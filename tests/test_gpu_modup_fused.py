@@ -1,8 +1,9 @@
-"""ModUp fused with the first pass of the forward transform (k_modup_col_b):
-key switching bit-exact against the oracle with the forward schedule pinned
-to one that starts with a radix-16 column pass, so the fused path runs; full
-and ragged digits, one and several items, fp64 and integer rows; and the
-fused and unfused paths give the same ciphertexts."""
+"""ModUp and ModDown conversions fused with the first pass of the forward
+transform of their rows (k_bconv_col_b): key switching bit-exact against the
+oracle with the forward schedule pinned to one that starts with a radix-16
+column pass, so both fused kernels run; full and ragged digits, one and
+several items, fp64 and integer rows; and the fused and unfused paths give
+the same ciphertexts."""
 
 import numpy as np
 import pytest
