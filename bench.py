@@ -45,6 +45,8 @@ def kernel_name(kid, variant):
         b = lambda x: "true" if x else "false"  # noqa: E731
         return "k_ntt_pass<%d, %d, %s, %s, %s, %s, %s>" % (v & 31, 3 if v & 256 else 4, b(kid == 1), b(v & 32),
                                                             b(v & 64), b(v & 128), b(v & 512))
+    if kid == 8 and variant == 1:  # RESCALE's expansion fused with the first transform pass
+        return "k_rescale_col_b"
     if kid in (2, 4) and variant >= 64:  # base conversion fused with the first transform pass
         return "k_bconv_col_b<%du, %s>" % (variant - 64, "true" if kid == 4 else "false")
     if kid in (2, 3, 4) and variant:  # templated on the k-block count / the number of digits

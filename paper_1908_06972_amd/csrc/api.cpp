@@ -1534,8 +1534,15 @@ extern "C" int pft_rescale_batch(pft_ctx* c, uint32_t n, const pft_ct* in, uint3
             }
         ntt_jobs(c, jl, 1, ~0u, true, l - 1);  // modulus of row 0 is q_{l-1}
         const double nd = (double)N;
-        timed(c, PK_RESCALE, 8.0 * nd * (2.0 + 2.0 * (l - 1)) * cnt, 0,
-              [&] { launch_rescale_expand_b(cnt, ws, off_last, off_tmp, l, mode, c->tabs, lg, c->stream); });
+        // the expansion applies the first pass of tmp's transform itself
+        // where that schedule starts with a radix-16 column pass
+        const bool fuse = lg >= 8 && first_pass_col16(c, (uint64_t)jt.size() * (l - 1));
+        if (fuse)
+            timed(c, PK_RESCALE, 8.0 * nd * (2.0 + 2.0 * (l - 1)) * cnt, 0,
+                  [&] { launch_rescale_col_b(cnt, ws, off_last, off_tmp, l, mode, c->tabs, lg, c->stream); }, 1u);
+        else
+            timed(c, PK_RESCALE, 8.0 * nd * (2.0 + 2.0 * (l - 1)) * cnt, 0,
+                  [&] { launch_rescale_expand_b(cnt, ws, off_last, off_tmp, l, mode, c->tabs, lg, c->stream); });
         // the forward transform of tmp finishes in its final pass:
         // out[b][k] = (c[b][k] - tmp[b][k]) q_last^-1 mod q_k
         NttEpilogue epi{};
@@ -1551,7 +1558,7 @@ extern "C" int pft_rescale_batch(pft_ctx* c, uint32_t n, const pft_ct* in, uint3
         epi.level = l - 1;
         epi.pinv = c->rescale_qinv + (size_t)(l - 1) * P->L;
         epi.pinv_fp = c->rescale_qinv + (size_t)P->L * P->L + (size_t)(l - 1) * P->L;
-        ntt_jobs(c, jt, l - 1, ~0u, false, 0, &epi);
+        ntt_jobs(c, jt, l - 1, ~0u, false, 0, &epi, 0, fuse ? 1u : 0u);
         for (uint32_t z = 0; z < cnt; ++z) {
             out[g[z]].level = l - 1;
             out[g[z]].scale = in[g[z]].scale / (double)P->q[l - 1];

@@ -613,6 +613,48 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     }
 }
 
+// RESCALE's expansion fused with the first pass (stages 0-3, a radix-16
+// column pass) of the forward transform of its rows: thread (row k, column u)
+// reads the 16 values t of column u0 + u + t N/16 of last_b (polynomial b's
+// limb level-1 in coefficient form), forms ((c + h) mod q_last) - h mod q_k
+// (h = (q_last - 1)/2 rounding, 0 floor; q_last < q_k) and takes the column
+// through the four stages exactly as the first transform pass does (fp64
+// rows converted on entry); row k of tmp_b continues at the second pass.
+__global__ __launch_bounds__(256) void k_rescale_col_b(WsRef ws, uint64_t off_last, uint64_t off_tmp, uint32_t level,
+                                                       uint32_t mode, const DevMod* __restrict__ mods,
+                                                       const TwPair* __restrict__ tw, uint32_t log_n) {
+    const uint32_t S = 1u << (log_n - 4);
+    const uint32_t u0 = blockIdx.x * 16u;
+    const uint32_t nl = level - 1;
+    const uint32_t groups = (nl + 15) / 16;
+    const uint32_t b = blockIdx.y / groups;
+    const uint32_t k = (blockIdx.y - b * groups) * 16u + (threadIdx.x >> 4), u = threadIdx.x & 15u;
+    if (k >= nl) return;  // no barrier in this kernel
+    const uint64_t ql = mods[level - 1].q;
+    const uint64_t h = mode == 0 ? (ql - 1) / 2 : 0;
+    uint64_t* item = ws.base + (size_t)blockIdx.z * ws.stride;
+    const uint64_t* __restrict__ last = item + off_last + ((size_t)b << log_n) + u0 + u;
+    const DevMod md = mods[k];
+    uint64_t x[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        uint64_t r = last[(size_t)e * S] + h;
+        r = r >= ql ? r - ql : r;
+        x[e] = r >= h ? r - h : r + md.q - h;
+    }
+    const TwPair* __restrict__ twt = tw + ((size_t)k << log_n);
+    if (md.fp) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) x[e] = fp_from_u64(x[e]);
+        run_phase<4, 0, 4, false, true, false>(x, 0u, 0u, 0u, twt, md);
+    } else {
+        run_phase<4, 0, 4, false, false, false>(x, 0u, 0u, 0u, twt, md);
+    }
+    uint64_t* __restrict__ orow = item + off_tmp + ((size_t)(b * nl + k) << log_n) + u0 + u;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) orow[(size_t)e * S] = x[e];
+}
+
 template <bool INV>
 void launch_radix(uint32_t radix, const PolyBatch& b, const DevTables& t, uint32_t log_n, uint32_t s0, bool fin,
                   bool stage, bool e8, const NttEpilogue* epi, hipStream_t st, ProfHook* prof) {
@@ -709,6 +751,13 @@ void launch_moddown_col_b(uint32_t n, WsRef ws, uint64_t off_acc, uint64_t off_c
                           const KsConsts& kc, const DevTables& t, uint32_t log_n, hipStream_t st) {
     launch_bconv_col<true>((kc.K + 1) / 2, dim3((1u << log_n) / 256, 2, n), st, ws, off_acc, off_conv, level, kc, t,
                            log_n);
+}
+
+void launch_rescale_col_b(uint32_t n, WsRef ws, uint64_t off_last, uint64_t off_tmp, uint32_t level, uint32_t mode,
+                          const DevTables& t, uint32_t log_n, hipStream_t st) {
+    const uint32_t groups = (level - 1 + 15) / 16;
+    hipLaunchKernelGGL(k_rescale_col_b, dim3((1u << log_n) / 256, 2 * groups, n), dim3(256), 0, st, ws, off_last,
+                       off_tmp, level, mode, t.mods, t.tw_fwd, log_n);
 }
 
 void launch_ntt(const PolyBatch& b, const DevTables& t, uint32_t log_n, bool inverse, const NttSchedule& s,

@@ -149,6 +149,10 @@ void launch_modup_col_b(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, 
 // of the first transform pass.
 void launch_moddown_col_b(uint32_t n, WsRef ws, uint64_t off_acc, uint64_t off_conv, uint32_t level,
                           const KsConsts& kc, const DevTables& t, uint32_t log_n, hipStream_t st);
+// RESCALE's expansion of last_z [2][N] into tmp_z [2][level-1][N] fused the
+// same way: tmp holds the output of the first transform pass.
+void launch_rescale_col_b(uint32_t n, WsRef ws, uint64_t off_last, uint64_t off_tmp, uint32_t level, uint32_t mode,
+                          const DevTables& t, uint32_t log_n, hipStream_t st);
 // acc [2][level+K][N] = sum_j x_j * key_j  (key: [dnum][2][L+K][N], Montgomery form)
 void launch_key_inner_b(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, uint64_t off_acc, const uint64_t* key,
                         uint32_t level, const KsConsts& kc, const DevTables& t, uint32_t log_n, hipStream_t st);

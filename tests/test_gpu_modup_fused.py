@@ -108,3 +108,23 @@ def test_fused_modup_batch_equals_unfused():
     finally:
         w.ctx.bconv_mode(True, fused=True)
         w.ctx.ntt_set_schedule(False, None)
+
+
+@pytest.mark.parametrize("name", ["a2_n12", "a6_n12"])
+@pytest.mark.parametrize("first16", [True, False])
+def test_rescale_fused_and_unfused(name, first16):
+    """RESCALE with its expansion fused with the first transform pass
+    (forward schedule starting with radix 16) and unfused (another first
+    radix): single and batched, top and lowest levels, against the oracle."""
+    w = world(name)
+    sched = [c for c in w.ctx.ntt_candidates() if (c[0][0] == 4) == first16][0]
+    w.ctx.ntt_set_schedule(False, sched)
+    try:
+        for level in sorted({w.op.L, 2}):
+            g, o = w.enc_pair(90 + level, level)
+            w.assert_same(w.ctx.rescale(g), C.rescale(w.op, o))
+            gs = [w.enc_pair(120 + 3 * level + i, level) for i in range(3)]
+            for (_, ox), out in zip(gs, w.ctx.rescale_batch([x[0] for x in gs])):
+                w.assert_same(out, C.rescale(w.op, ox))
+    finally:
+        w.ctx.ntt_set_schedule(False, None)
