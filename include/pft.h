@@ -187,7 +187,8 @@ int pft_mul_relin_batch(pft_ctx* ctx, uint32_t n, const pft_ct* a, const pft_ct*
 /* RESCALE by q_{level-1} (Sec. 5.1, Eq. (1) and Alg. 3).  mode 0 rounds
  * (adds (q-1)/2 before the exact division, the RESCALE of Sec. 3.4), mode 1
  * floors (Alg. 3 as printed).  out->data needs 2*(level-1)*N uint64 and must
- * not alias in. */
+ * not alias in.  (Where the forward schedule starts with a radix-16 column
+ * pass, the expansion of the last limb applies that pass itself.) */
 int pft_rescale(pft_ctx* ctx, const pft_ct* in, uint32_t mode, pft_ct* out);
 int pft_rescale_batch(pft_ctx* ctx, uint32_t n, const pft_ct* in, uint32_t mode, pft_ct* out);
 /* Keep limbs 0..level-1 (exact).  out may alias in. */
