@@ -94,17 +94,17 @@ class Roctx:
                 log("roctxProfilerPause returned %d" % rc)
 
 
-# kernel family -> source files whose text determines the kernel (for the
-# validity of stored counter figures)
-FAMILY_SOURCES = {0: ["ntt.hip", "pft_device.h"], 1: ["ntt.hip", "pft_device.h"]}
+# source files whose text determines the kernels (for the validity of stored
+# counter figures: any change to device code invalidates them all)
+KERNEL_SOURCES = ["ntt.hip", "ckks.hip", "sampler.hip", "pft_device.h", "bconv_device.h", "pft_kernels.h"]
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 CSRC = os.path.join(ROOT, "paper_1908_06972_amd", "csrc")
 
 
-def source_sha(kid):
+def source_sha(kid=None):
     import hashlib
     h = hashlib.sha256()
-    for f in FAMILY_SOURCES.get(kid, ["ckks.hip", "pft_device.h"]):
+    for f in KERNEL_SOURCES:
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()

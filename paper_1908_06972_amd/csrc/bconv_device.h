@@ -35,12 +35,17 @@ __device__ __forceinline__ long split_digits(uint64_t v) {
 //    comes from fp64 (error below 2^-21); the remainder is formed exactly in
 //    integers mod 2^64 as (lo + 2^32 hi + 2^30 m) - (k + 2^30) m, which lies
 //    within (1/2 + 2^-21) m of zero, then one conditional add of m.
+// RAW: for m < 2^50 return the bits of the reduced double itself (an
+// integer of magnitude at most m/2 + 1), the input form of the fp64
+// transform passes, instead of the canonical u64.
+template <bool RAW = false>
 __device__ __forceinline__ uint64_t fold_digits(const int (&z)[8], const BconvRed& rc) {
 #pragma clang fp contract(off)
     const double lo = __builtin_fma((double)(z[3] * 256 + z[2]), 65536.0, (double)(z[1] * 256 + z[0]));
     const double hi = __builtin_fma((double)(z[7] * 256 + z[6]), 65536.0, (double)(z[5] * 256 + z[4]));
     if (rc.fp) {
         double y = freduce(lo + fmulmod(hi, rc.c32, rc.c32q, rc.md), rc.md, rc.minv);
+        if (RAW) return as_u(y);
         y = y < 0.0 ? y + rc.md : y;  // [0, m)
         return as_u(y + 0x1p52) ^ 0x4330000000000000ull;
     }

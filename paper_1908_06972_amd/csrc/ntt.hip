@@ -583,7 +583,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                     if (tt < T) {
                         int z[8];
                         if (uu == 0) tile_digits<0>(acc, z); else tile_digits<1>(acc, z);
-                        ybuf[(tt - tb0) * ROWP + ci[h]] = fold_digits(z, s_red[mod_of(row_of(tt))]);
+                        // fp64 rows keep the fold's double (the pass's input form)
+                        ybuf[(tt - tb0) * ROWP + ci[h]] = fold_digits<true>(z, s_red[mod_of(row_of(tt))]);
                     }
                 }
             }
@@ -599,8 +600,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 #pragma unroll
             for (int e = 0; e < 16; ++e) x[e] = ybuf[tl * ROWP + 16u * e + u];
             if (md.fp) {
-#pragma unroll
-                for (int e = 0; e < 16; ++e) x[e] = fp_from_u64(x[e]);
                 run_phase<4, 0, 4, false, true, false>(x, 0u, 0u, 0u, twt, md);
             } else {
                 run_phase<4, 0, 4, false, false, false>(x, 0u, 0u, 0u, twt, md);
