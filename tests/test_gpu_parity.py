@@ -175,8 +175,9 @@ def test_mul_relin_parity(request, name, levels):
 @pytest.mark.parametrize("name,levels", [("c1", (2, 1)), ("c2", (8, 5, 2)), ("c3", (24, 17, 6))])
 def test_bconv_modes_parity(request, name, levels):
     """Key switching with the base conversions on the matrix cores (int8
-    digits, the default) and on the VALU (128-bit MACs): both equal the
-    oracle, at full, ragged-last-digit and low levels."""
+    digits; fused with the first transform pass, the default, and separate)
+    and on the VALU (128-bit MACs): all equal the oracle, at full,
+    ragged-last-digit and low levels."""
     w = _world(request, name)
     for lvl in levels:
         ga, oa = w.encrypt_pair(w.random_plain(23), lvl, 700 + lvl)
@@ -184,8 +185,8 @@ def test_bconv_modes_parity(request, name, levels):
         want = C.hmul_relin(w.op, oa, ob, w.rlk)
         st = sorted(w.rot)[0]
         want_rot = C.rotate(w.op, oa, st, w.rot[st])
-        for mfma in (True, False):
-            w.ctx.bconv_mode(mfma)
+        for mfma, fused in ((True, True), (True, False), (False, False)):
+            w.ctx.bconv_mode(mfma, fused=fused)
             w.assert_same(w.ctx.mul_relin(ga, gb), want)
             w.assert_same(w.ctx.rotate(ga, st), want_rot)
     w.ctx.bconv_mode(True)
@@ -408,3 +409,23 @@ def test_graph_replay_matches_eager(torch_cuda):
         assert np.array_equal(ctx.export(rot_out), eager), rep
     graph.close()
     ctx.close()
+
+
+@pytest.mark.parametrize("flags", [0, 1])
+def test_fused_first_pass_c3(c3, flags):
+    """At the large ring with the forward schedule pinned to (4, 12): the
+    base conversions and RESCALE's expansion apply the first transform pass
+    themselves; relinearisation, rotation and RESCALE equal the oracle at a
+    full and a ragged-last-digit level."""
+    w = c3
+    sched = [c for c in w.ctx.ntt_candidates() if tuple(c[0]) == (4, 12) and c[1] == flags][0]
+    w.ctx.ntt_set_schedule(False, sched)
+    try:
+        for lvl in (24, 19):
+            ga, oa = w.encrypt_pair(w.random_plain(41), lvl, 900 + lvl)
+            gb, ob = w.encrypt_pair(w.random_plain(42), lvl, 950 + lvl)
+            w.assert_same(w.ctx.mul_relin(ga, gb), C.hmul_relin(w.op, oa, ob, w.rlk))
+            w.assert_same(w.ctx.rotate(ga, 1), C.rotate(w.op, oa, 1, w.rot[1]))
+            w.assert_same(w.ctx.rescale(ga), C.rescale(w.op, oa))
+    finally:
+        w.ctx.ntt_set_schedule(False, None)
