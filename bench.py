@@ -47,8 +47,9 @@ def kernel_name(kid, variant):
                                                             b(v & 64), b(v & 128), b(v & 512))
     if kid == 8 and variant == 1:  # RESCALE's expansion fused with the first transform pass
         return "k_rescale_col_b"
-    if kid in (2, 4) and variant >= 64:  # base conversion fused with the first transform pass
-        return "k_bconv_col_b<%du, %s>" % (variant - 64, "true" if kid == 4 else "false")
+    if kid in (2, 4) and variant >= 64:  # base conversion fused with the first (and last inverse) pass
+        return "k_bconv_col_b<%du, %s, %s>" % ((variant - 64) & 15, "true" if kid == 4 else "false",
+                                               "true" if (variant - 64) & 16 else "false")
     if kid in (2, 3, 4) and variant:  # templated on the k-block count / the number of digits
         return "%s<%du>" % (KERNEL_NAMES[kid], variant)
     return KERNEL_NAMES.get(kid, FAMILIES[kid])

@@ -615,10 +615,17 @@ static NttSchedule ntt_default(const pft_params* P) {
 // cycle through all L + K moduli (fp64 and integer limbs in the chain's
 // proportion): the median of five runs each.  The earliest candidate within
 // 2% of the fastest wins, so near-ties resolve the same way run to run.
-static NttSchedule ntt_tune(pft_ctx* c, bool inverse, uint32_t cls) {
+// col16: only candidates whose first radix is 4 (a radix-16 column pass at
+// the start of a forward / the end of an inverse transform, the pass the
+// fused conversion kernels apply themselves).
+static NttSchedule ntt_tune(pft_ctx* c, bool inverse, uint32_t cls, bool col16 = false) {
     const pft_params* P = c->P;
-    NttSchedule cand[32];
-    const int nc = ntt_candidates(P->log_n, cand, 32);
+    NttSchedule all[32], cand[32];
+    const int na = ntt_candidates(P->log_n, all, 32);
+    int nc = 0;
+    for (int k = 0; k < na; ++k)
+        if (!col16 || (all[k].n_passes >= 2 && all[k].radix[0] == 4)) cand[nc++] = all[k];
+    if (nc == 0) return all[0];
     if (nc <= 1) return cand[0];
     const uint32_t rows = P->L + P->K;
     const uint64_t want = 1ull << cls;
@@ -684,14 +691,22 @@ static NttSchedule ntt_tune(pft_ctx* c, bool inverse, uint32_t cls) {
     return best;
 }
 
-static NttSchedule ntt_schedule(pft_ctx* c, bool inverse, uint64_t limbs) {
+// Tuned choices are keyed by direction (64), restriction to first radix 4
+// (32) and class.
+static NttSchedule ntt_schedule(pft_ctx* c, bool inverse, uint64_t limbs, bool col16 = false) {
     if (c->ntt_pinned[inverse].n_passes) return c->ntt_pinned[inverse];
-    const uint32_t key = (inverse ? 64u : 0u) + ntt_class(limbs);
+    const uint32_t key = (inverse ? 64u : 0u) + (col16 ? 32u : 0u) + ntt_class(limbs);
     auto it = c->ntt_tuned.find(key);
     if (it != c->ntt_tuned.end()) return it->second;
-    if (!c->ntt_tune) return ntt_default(c->P);
-    if (c->capturing) return ntt_default(c->P);  // no timing inside a capture
-    const NttSchedule s = ntt_tune(c, inverse, ntt_class(limbs));
+    if (!c->ntt_tune || c->capturing) {  // no timing inside a capture
+        if (!col16) return ntt_default(c->P);
+        NttSchedule all[32];
+        const int na = ntt_candidates(c->P->log_n, all, 32);
+        for (int k = 0; k < na; ++k)
+            if (all[k].n_passes >= 2 && all[k].radix[0] == 4) return all[k];
+        return ntt_default(c->P);
+    }
+    const NttSchedule s = ntt_tune(c, inverse, ntt_class(limbs), col16);
     c->ntt_tuned[key] = s;
     return s;
 }
@@ -699,9 +714,10 @@ static NttSchedule ntt_schedule(pft_ctx* c, bool inverse, uint64_t limbs) {
 // epi: forward transforms of (item, b) polynomial pairs whose final pass
 // finishes ModDown; epi->out lists every item, a launch gets its share.
 static void ntt_jobs(pft_ctx* c, const std::vector<NttJob>& jobs, uint32_t n_limbs, uint32_t split, bool inverse,
-                     uint32_t off0 = 0, const NttEpilogue* epi = nullptr, int64_t src_delta = 0, uint32_t first = 0) {
+                     uint32_t off0 = 0, const NttEpilogue* epi = nullptr, int64_t src_delta = 0, uint32_t first = 0,
+                     bool col16 = false) {
     const pft_params* P = c->P;
-    const NttSchedule sched = ntt_schedule(c, inverse, (uint64_t)jobs.size() * n_limbs);
+    const NttSchedule sched = ntt_schedule(c, inverse, (uint64_t)jobs.size() * n_limbs, col16);
     for (size_t s = 0; s < jobs.size(); s += PFT_MAX_POLYS) {
         PolyBatch b{};
         const uint32_t np = (uint32_t)std::min<size_t>(PFT_MAX_POLYS, jobs.size() - s);
@@ -1325,6 +1341,12 @@ static bool first_pass_col16(pft_ctx* c, uint64_t limbs) {
     const NttSchedule s = ntt_schedule(c, false, limbs);
     return s.n_passes >= 2 && s.radix[0] == 4;
 }
+// Whether an inverse transform of `limbs` limbs can end with a radix-16
+// column pass (the schedule chosen among such candidates, or the pinned one).
+static bool last_pass_col16(pft_ctx* c, uint64_t limbs) {
+    const NttSchedule s = ntt_schedule(c, true, limbs, true);
+    return s.n_passes >= 2 && s.radix[0] == 4;
+}
 
 // Key switching of d (NTT domain, [level][N] at ws_z + off_d) for n items:
 // out_z = ModDown(sum_j ModUp_j(d) key_j) + (ws rows at off_add0/off_add1),
@@ -1336,33 +1358,38 @@ static void key_switch_b(pft_ctx* c, uint32_t n, WsRef ws, const KsLayout& K, ui
     const pft_params* P = c->P;
     const uint32_t lg = P->log_n, A = P->alpha, level = K.level, rows = K.rows, beta = K.beta;
     const double N = (double)P->n;
+    // ModUp's rows: all digits of all items, full digits and the ragged last
+    // digit in separate transform launches (different limb counts)
+    std::vector<NttJob> full, last;
+    uint32_t na_last = 0;
+    for (uint32_t z = 0; z < n; ++z)
+        for (uint32_t j = 0; j < beta; ++j) {
+            const uint32_t i0 = j * A, na = std::min(i0 + A, level) - i0;
+            NttJob job{ws.base + z * ws.stride + K.off_ext + ((uint64_t)j * rows << lg), i0, na};
+            (na == A ? full : last).push_back(job);
+            if (na != A) na_last = na;
+        }
+    auto col16 = [&](const std::vector<NttJob>& jobs, uint32_t limbs) {
+        return jobs.empty() || first_pass_col16(c, (uint64_t)jobs.size() * limbs);
+    };
+    // Where the forward schedules start with a radix-16 column pass, ModUp
+    // applies that pass itself; then d's inverse transform also stops before
+    // its final radix-16 column pass (a schedule chosen among those ending
+    // with one) and ModUp applies that pass to its inputs.
+    const uint32_t nkb = (std::min(P->alpha, level) + 1) / 2;
+    const bool fuse = c->bconv_mfma && c->modup_fuse && lg >= 8 && nkb <= 6 && col16(full, rows - A) &&
+                      col16(last, rows - na_last);
+    const bool ifuse_up = fuse && last_pass_col16(c, (uint64_t)n * level);
     // d -> coefficient form at off_dcoef (the first pass reads d in place;
     // d itself stays in the NTT domain for the inner product)
     {
         std::vector<NttJob> jobs;
         for (uint32_t z = 0; z < n; ++z) jobs.push_back(NttJob{ws.base + z * ws.stride + K.off_dcoef, 255u, 0u});
-        ntt_jobs(c, jobs, level, ~0u, true, 0, nullptr, (int64_t)off_d - (int64_t)K.off_dcoef);
+        ntt_jobs(c, jobs, level, ~0u, true, 0, nullptr, (int64_t)off_d - (int64_t)K.off_dcoef, ifuse_up ? 1u : 0u,
+                 ifuse_up);
     }
-    // ModUp base conversion and the forward transforms of its rows: all
-    // digits of all items, full digits and the ragged last digit in separate
-    // transform launches (different limb counts).  Where both schedules start
-    // with a radix-16 column pass, ModUp applies that pass itself.
+    // ModUp base conversion and the forward transforms of its rows
     {
-        std::vector<NttJob> full, last;
-        uint32_t na_last = 0;
-        for (uint32_t z = 0; z < n; ++z)
-            for (uint32_t j = 0; j < beta; ++j) {
-                const uint32_t i0 = j * A, na = std::min(i0 + A, level) - i0;
-                NttJob job{ws.base + z * ws.stride + K.off_ext + ((uint64_t)j * rows << lg), i0, na};
-                (na == A ? full : last).push_back(job);
-                if (na != A) na_last = na;
-            }
-        auto col16 = [&](const std::vector<NttJob>& jobs, uint32_t limbs) {
-            return jobs.empty() || first_pass_col16(c, (uint64_t)jobs.size() * limbs);
-        };
-        const uint32_t nkb = (std::min(P->alpha, level) + 1) / 2;
-        const bool fuse = c->bconv_mfma && c->modup_fuse && lg >= 8 && nkb <= 6 && col16(full, rows - A) &&
-                          col16(last, rows - na_last);
         double rd = 0, wr = 0, macs = 0;
         for (uint32_t j = 0; j < beta; ++j) {
             const uint32_t na = std::min(j * A + A, level) - j * A;
@@ -1372,8 +1399,11 @@ static void key_switch_b(pft_ctx* c, uint32_t n, WsRef ws, const KsLayout& K, ui
         }
         if (fuse) {
             timed(c, PK_MODUP, 8.0 * N * (rd + wr) * n, N * macs * n,
-                  [&] { launch_modup_col_b(n, ws, K.off_dcoef, K.off_ext, level, c->kc, c->tabs, lg, c->stream); },
-                  64u + nkb);
+                  [&] {
+                      launch_modup_col_b(n, ws, K.off_dcoef, K.off_ext, level, c->kc, c->tabs, lg, ifuse_up,
+                                         c->stream);
+                  },
+                  64u + nkb + (ifuse_up ? 16u : 0u));
         } else {
             timed(c, PK_MODUP, 8.0 * N * (rd + wr) * n, N * macs * n, [&] {
                 launch_modup_b(n, ws, K.off_dcoef, K.off_ext, level, c->kc, c->tabs, lg, c->bconv_mfma, c->stream);
@@ -1391,25 +1421,30 @@ static void key_switch_b(pft_ctx* c, uint32_t n, WsRef ws, const KsLayout& K, ui
           2.0 * N * beta * rows * n, [&] {
         launch_key_inner_b(n, ws, off_d, K.off_ext, K.off_acc, key.data, level, c->kc, c->tabs, lg, c->stream);
     }, beta <= 8 ? beta : 0);
-    // ModDown: special rows of both accumulators to coefficient form
+    // ModDown: the conversion of the special rows to the q-limbs is fused
+    // with the first pass of conv's forward transform where its schedule
+    // allows, and then also with the final pass of the special rows' inverse
+    // transform (as for ModUp); the forward transform of conv finishes
+    // ModDown in its final pass: out_b[i] = (acc_b[i] - conv_b[i]) P^-1 (+ add_b)
+    const uint32_t down_kb = (P->K + 1) / 2;
+    const bool fuse_down = c->bconv_mfma && c->modup_fuse && lg >= 8 && down_kb <= 6 &&
+                           first_pass_col16(c, 2ull * n * level);
+    const bool ifuse_down = fuse_down && last_pass_col16(c, 2ull * n * P->K);
+    // special rows of both accumulators to coefficient form
     {
         std::vector<NttJob> jobs;
         for (uint32_t z = 0; z < n; ++z)
             for (uint32_t b = 0; b < 2; ++b)
                 jobs.push_back(NttJob{ws.base + z * ws.stride + K.off_acc + ((uint64_t)b * rows << lg), 0u, level});
-        ntt_jobs(c, jobs, P->K, level, true);
+        ntt_jobs(c, jobs, P->K, level, true, 0, nullptr, 0, ifuse_down ? 1u : 0u, ifuse_down);
     }
-    // conversion of the special rows to the q-limbs (fused with the first
-    // pass of conv's forward transform where its schedule allows), then the
-    // forward transform of conv finishes ModDown in its final pass:
-    // out_b[i] = (acc_b[i] - conv_b[i]) P^-1 (+ add_b)
-    const uint32_t down_kb = (P->K + 1) / 2;
-    const bool fuse_down = c->bconv_mfma && c->modup_fuse && lg >= 8 && down_kb <= 6 &&
-                           first_pass_col16(c, 2ull * n * level);
     if (fuse_down) {
         timed(c, PK_MODDOWN_CONV, 8.0 * N * (2.0 * P->K + 2.0 * level) * n, 2.0 * N * P->K * level * n,
-              [&] { launch_moddown_col_b(n, ws, K.off_acc, K.off_conv, level, c->kc, c->tabs, lg, c->stream); },
-              64u + down_kb);
+              [&] {
+                  launch_moddown_col_b(n, ws, K.off_acc, K.off_conv, level, c->kc, c->tabs, lg, ifuse_down,
+                                       c->stream);
+              },
+              64u + down_kb + (ifuse_down ? 16u : 0u));
     } else {
         timed(c, PK_MODDOWN_CONV, 8.0 * N * (2.0 * P->K + 2.0 * level) * n, 2.0 * N * P->K * level * n, [&] {
             launch_moddown_conv_b(n, ws, K.off_acc, K.off_conv, level, c->kc, c->tabs, lg, c->bconv_mfma, c->stream);
@@ -2436,7 +2471,7 @@ extern "C" int pft_ntt_tuning_export(pft_ctx* c, uint32_t* entries, uint32_t max
     for (const auto& kv : c->ntt_tuned) {
         if (entries && i < max_count) {
             entries[6 * i] = kv.first >= 64 ? 1u : 0u;
-            entries[6 * i + 1] = kv.first & 63u;
+            entries[6 * i + 1] = kv.first & 63u;  // class, + 32 for the first-radix-4 choices
             sched_words(kv.second, entries + 6 * i + 2);
         }
         ++i;
@@ -2449,11 +2484,13 @@ extern "C" int pft_ntt_tuning_import(pft_ctx* c, const uint32_t* entries, uint32
     std::map<uint32_t, NttSchedule> add;
     for (uint32_t i = 0; i < count; ++i) {
         const uint32_t* e = entries + 6 * i;
-        if (e[0] > 1 || e[1] > 10) return fail(PFT_EINVAL, "entry %u: bad direction or class", i);
+        if (e[0] > 1 || (e[1] & 31u) > 10 || e[1] > 42) return fail(PFT_EINVAL, "entry %u: bad direction or class", i);
         NttSchedule s{};
         for (uint32_t k = 0; k < 3 && e[2 + k]; ++k) s.radix[s.n_passes++] = (uint8_t)std::min<uint32_t>(e[2 + k], 255u);
         s.flags = e[5];
         if (!ntt_schedule_valid(c->P->log_n, s)) return fail(PFT_EINVAL, "entry %u: not a candidate schedule", i);
+        if (e[1] >= 32 && !(s.n_passes >= 2 && s.radix[0] == 4))
+            return fail(PFT_EINVAL, "entry %u: a first-radix-4 class needs a schedule starting with 4", i);
         add[(e[0] ? 64u : 0u) + e[1]] = s;
     }
     for (const auto& kv : add) c->ntt_tuned[kv.first] = kv.second;

@@ -510,10 +510,16 @@ void launch_pass(const PolyBatch& b, const DevTables& t, uint32_t log_n, uint32_
 // values t of its column through the four stages exactly as the first
 // transform pass does (fp64 rows converted on entry) and stores them in that
 // pass's output form, so the transform continues with its second pass.
-template <uint32_t NKB, bool DOWN>
+//
+// IFUSE: the input rows come from an inverse transform whose final pass (a
+// radix-16 column pass, stages 3-0 with N^-1 folded in) has not run; the
+// workgroup applies it to its 16 columns of each input row exactly as that
+// pass would (the same butterflies, the same conversion to canonical u64)
+// and stages the result in LDS before splitting the digits.
+template <uint32_t NKB, bool DOWN, bool IFUSE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_bconv_col_b(
     WsRef ws, uint64_t off_in, uint64_t off_out, uint32_t level, KsConsts kc, const DevMod* __restrict__ mods,
-    const TwPair* __restrict__ tw, uint32_t log_n) {
+    const TwPair* __restrict__ tw, const TwPair* __restrict__ tw_inv, uint32_t log_n) {
     constexpr uint32_t ROWP = 272;  // LDS words per target row (256 coefficients + padding)
     __shared__ uint64_t ybuf[16 * ROWP];
     __shared__ BconvRed s_red[64];
@@ -530,6 +536,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     uint64_t* item = ws.base + (size_t)blockIdx.z * ws.stride;
     const uint64_t* __restrict__ in = item + off_in + (DOWN ? ((size_t)j * rows << log_n) : 0);
     uint64_t* __restrict__ out = item + off_out + ((size_t)j * (DOWN ? level : rows) << log_n);
+    if constexpr (IFUSE) {
+        // the final inverse pass of each input row's 16 columns, into LDS
+        // rows 0..na-1 at column 16 t + u
+        const uint32_t ii = tid >> 4, u = tid & 15u;
+        if (ii < na) {
+            const uint32_t mi = DOWN ? kc.L + ii : i0 + ii;
+            const DevMod md = mods[mi];
+            const TwPair* __restrict__ twt = tw_inv + ((size_t)mi << log_n);
+            const uint64_t* __restrict__ irow = in + ((size_t)(i0 + ii) << log_n) + u0 + u;
+            uint64_t x[16];
+#pragma unroll
+            for (int e = 0; e < 16; ++e) x[e] = irow[(size_t)e * S];
+            if (md.fp) {
+                run_phase<4, 0, 4, true, true, true>(x, 0u, 0u, 0u, twt, md);
+#pragma unroll
+                for (int e = 0; e < 16; ++e) x[e] = fp_to_u64(x[e], md.qd, md.qinv);
+            } else {
+                run_phase<4, 0, 4, true, false, true>(x, 0u, 0u, 0u, twt, md);
+            }
+#pragma unroll
+            for (int e = 0; e < 16; ++e) ybuf[ii * ROWP + 16u * e + u] = x[e];
+        }
+        __syncthreads();
+    }
     // input digits of this lane's coefficient in each of the wave's two
     // 32-column blocks: column ci = 32 cb + (lane & 31) = 16 t + u
     uint32_t ci[2];
@@ -545,11 +575,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             if (ii < na) {
                 const TwPair hv = DOWN ? kc.down_phatinv[ii] : kc.modup_hatinv[cbase + ii];
                 const uint64_t qi = mods[DOWN ? kc.L + ii : i0 + ii].q;
-                x = shoup(in[((size_t)(i0 + ii) << log_n) + pos], hv.w, hv.wp, qi);
+                const uint64_t v = IFUSE ? ybuf[ii * ROWP + ci[h]] : in[((size_t)(i0 + ii) << log_n) + pos];
+                x = shoup(v, hv.w, hv.wp, qi);
             }
             bop[h][kb] = split_digits(x);
         }
     }
+    // (stage_red's barrier also orders the LDS input reads above before the
+    // first target batch overwrites those rows)
     stage_red(kc, s_red);
     const uint32_t kbs = DOWN ? kc.down_kb : kc.up_kb;
     const uint64_t* __restrict__ aop =
@@ -719,13 +752,13 @@ bool ntt_schedule_valid(uint32_t log_n, const NttSchedule& s) {
     return false;
 }
 
-template <bool DOWN>
+template <bool DOWN, bool IFUSE>
 static void launch_bconv_col(uint32_t nkb, dim3 grid, hipStream_t st, WsRef ws, uint64_t off_in, uint64_t off_out,
                              uint32_t level, const KsConsts& kc, const DevTables& t, uint32_t log_n) {
-#define PFT_BCONV_COL(K)                                                                                          \
-    case K:                                                                                                       \
-        hipLaunchKernelGGL((k_bconv_col_b<K, DOWN>), grid, dim3(256), 0, st, ws, off_in, off_out, level, kc, t.mods, \
-                           t.tw_fwd, log_n);                                                                      \
+#define PFT_BCONV_COL(K)                                                                                     \
+    case K:                                                                                                  \
+        hipLaunchKernelGGL((k_bconv_col_b<K, DOWN, IFUSE>), grid, dim3(256), 0, st, ws, off_in, off_out, level, \
+                           kc, t.mods, t.tw_fwd, t.tw_inv, log_n);                                           \
         break;
     switch (nkb) {
         PFT_BCONV_COL(1)
@@ -740,16 +773,23 @@ static void launch_bconv_col(uint32_t nkb, dim3 grid, hipStream_t st, WsRef ws, 
 }
 
 void launch_modup_col_b(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, uint32_t level, const KsConsts& kc,
-                        const DevTables& t, uint32_t log_n, hipStream_t st) {
+                        const DevTables& t, uint32_t log_n, bool ifuse, hipStream_t st) {
     const uint32_t beta = (level + kc.alpha - 1) / kc.alpha;
     const uint32_t nkb = (std::min(kc.alpha, level) + 1) / 2;
-    launch_bconv_col<false>(nkb, dim3((1u << log_n) / 256, beta, n), st, ws, off_d, off_ext, level, kc, t, log_n);
+    const dim3 grid((1u << log_n) / 256, beta, n);
+    if (ifuse)
+        launch_bconv_col<false, true>(nkb, grid, st, ws, off_d, off_ext, level, kc, t, log_n);
+    else
+        launch_bconv_col<false, false>(nkb, grid, st, ws, off_d, off_ext, level, kc, t, log_n);
 }
 
 void launch_moddown_col_b(uint32_t n, WsRef ws, uint64_t off_acc, uint64_t off_conv, uint32_t level,
-                          const KsConsts& kc, const DevTables& t, uint32_t log_n, hipStream_t st) {
-    launch_bconv_col<true>((kc.K + 1) / 2, dim3((1u << log_n) / 256, 2, n), st, ws, off_acc, off_conv, level, kc, t,
-                           log_n);
+                          const KsConsts& kc, const DevTables& t, uint32_t log_n, bool ifuse, hipStream_t st) {
+    const dim3 grid((1u << log_n) / 256, 2, n);
+    if (ifuse)
+        launch_bconv_col<true, true>((kc.K + 1) / 2, grid, st, ws, off_acc, off_conv, level, kc, t, log_n);
+    else
+        launch_bconv_col<true, false>((kc.K + 1) / 2, grid, st, ws, off_acc, off_conv, level, kc, t, log_n);
 }
 
 void launch_rescale_col_b(uint32_t n, WsRef ws, uint64_t off_last, uint64_t off_tmp, uint32_t level, uint32_t mode,
@@ -776,7 +816,7 @@ void launch_ntt(const PolyBatch& b, const DevTables& t, uint32_t log_n, bool inv
             launch_radix<false>(s.radix[p], b, t, log_n, s0[p], p + 1 == s.n_passes, stage, e8,
                                 p + 1 == s.n_passes ? epi : nullptr, st, prof);
     } else {
-        for (uint32_t p = s.n_passes; p-- > 0;)
+        for (uint32_t p = s.n_passes; p-- > first;)
             launch_radix<true>(s.radix[p], b, t, log_n, s0[p], p == 0, stage, e8, nullptr, st, prof);
     }
 }

@@ -64,7 +64,9 @@ int ntt_candidates(uint32_t log_n, NttSchedule* out, int max_out);
 bool ntt_schedule_valid(uint32_t log_n, const NttSchedule& s);
 // epi (forward only): finish ModDown in the final pass instead of storing.
 // first: a forward transform starts at pass `first` of the schedule (the
-// earlier passes already applied, e.g. by launch_modup_col_b).
+// earlier passes already applied, e.g. by launch_modup_col_b); an inverse
+// transform stops before pass `first` (the remaining passes applied by the
+// consumer, e.g. launch_modup_col_b with ifuse).
 void launch_ntt(const PolyBatch& b, const DevTables& t, uint32_t log_n, bool inverse, const NttSchedule& s,
                 hipStream_t st, ProfHook* prof = nullptr, const NttEpilogue* epi = nullptr, uint32_t first = 0);
 
@@ -141,14 +143,16 @@ void launch_modup_b(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, uint
 // ModUp on the matrix cores fused with the first pass of the forward
 // transform (a radix-16 column pass, stages 0-3) of every converted row:
 // ext holds the output of that pass; the transform continues at pass 1 of a
-// schedule whose first radix is 4 (ntt.hip).  Needs log_n >= 8.
+// schedule whose first radix is 4 (ntt.hip).  Needs log_n >= 8.  ifuse: d
+// comes from an inverse transform of such a schedule that stopped before its
+// final (radix-16 column) pass; the kernel applies that pass to its inputs.
 void launch_modup_col_b(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, uint32_t level, const KsConsts& kc,
-                        const DevTables& t, uint32_t log_n, hipStream_t st);
+                        const DevTables& t, uint32_t log_n, bool ifuse, hipStream_t st);
 // ModDown's conversion (conv_b = base conversion of the K special rows of
 // acc_b to the q-limbs 0..level-1) fused the same way: conv holds the output
 // of the first transform pass.
 void launch_moddown_col_b(uint32_t n, WsRef ws, uint64_t off_acc, uint64_t off_conv, uint32_t level,
-                          const KsConsts& kc, const DevTables& t, uint32_t log_n, hipStream_t st);
+                          const KsConsts& kc, const DevTables& t, uint32_t log_n, bool ifuse, hipStream_t st);
 // RESCALE's expansion of last_z [2][N] into tmp_z [2][level-1][N] fused the
 // same way: tmp holds the output of the first transform pass.
 void launch_rescale_col_b(uint32_t n, WsRef ws, uint64_t off_last, uint64_t off_tmp, uint32_t level, uint32_t mode,

@@ -128,3 +128,32 @@ def test_rescale_fused_and_unfused(name, first16):
                 w.assert_same(out, C.rescale(w.op, ox))
     finally:
         w.ctx.ntt_set_schedule(False, None)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("inv", ["col16_flags0", "col16_flags3", "other"])
+def test_inverse_fused_conversions(name, inv):
+    """The inverse transforms before ModUp and ModDown stop before their final
+    radix-16 column pass and the conversion kernels apply it to their inputs
+    (inverse schedule pinned to one ending with that pass, two flag sets), or
+    run whole (another schedule): relinearisation and rotation against the
+    oracle at full, ragged and lowest levels."""
+    w = world(name)
+    fwd = [c for c in w.col16 if c[1] == 0][0]
+    if inv == "other":
+        isched = [c for c in w.ctx.ntt_candidates() if c[0][0] != 4][0]
+    else:
+        isched = [c for c in w.col16 if c[1] == (0 if inv == "col16_flags0" else 3)][0]
+    w.ctx.ntt_set_schedule(False, fwd)
+    w.ctx.ntt_set_schedule(True, isched)
+    L = w.op.L
+    try:
+        for level in sorted({L, L - 1, 1}):
+            (ga, oa), (gb, ob) = w.enc_pair(150 + level, level), w.enc_pair(170 + level, level)
+            w.assert_same(w.ctx.mul_relin(ga, gb), C.hmul_relin(w.op, oa, ob, w.rlk))
+            for st in STEPS:
+                w.assert_same(w.ctx.rotate(ga, st), C.rotate(w.op, oa, st, w.rot[st]))
+            assert np.array_equal(w.ctx.decrypt(ga), C.decrypt(w.op, w.s, oa))
+    finally:
+        w.ctx.ntt_set_schedule(False, None)
+        w.ctx.ntt_set_schedule(True, None)
