@@ -837,7 +837,8 @@ def main():
         "config": {"workload": "large ring: N=2^16, L=24 (+K=6, dnum=4), scale 2^50, batch %d; depth-8 "
                                "HMult+relin+rescale chain then rotate-and-sum over 2^15 slots" % args.batch,
                    "global_batch": args.batch, "log_n": 16, "levels": lp.L, "special_primes": lp.K, "dnum": lp.dnum,
-                   "ntt_schedules": [{"inverse": bool(i), "class": c, "radices": r, "direct_rows": bool(f & 1),
+                   "ntt_schedules": [{"inverse": bool(i), "class": c & 31, "column16_only": bool(c & 32),
+                                      "radices": r, "direct_rows": bool(f & 1),
                                       "residues_per_thread": 8 if f & 2 else 16} for i, c, r, f in tuning]},
         "breakdown": breakdown,
         "roofline": roofline,
