@@ -347,7 +347,8 @@ int pft_ntt_autotune(pft_ctx* ctx, int enable);
 int pft_ntt_set_schedule(pft_ctx* ctx, int inverse, const uint32_t* sched);
 int pft_ntt_get_schedule(pft_ctx* ctx, int inverse, uint64_t n_limbs, uint32_t* sched);
 /* The tuned table as entries of six words (inverse 0/1, batch-size class
- * 0..10, the four schedule words): export writes up to max_count entries and
+ * 0..10, or 32 + class for a choice restricted to schedules whose first
+ * radix is 4 (made for the fused conversions), the four schedule words): export writes up to max_count entries and
  * returns how many exist; import validates every entry (PFT_EINVAL, nothing
  * changed) and then sets them, so a later run can reuse earlier choices. */
 int pft_ntt_tuning_export(pft_ctx* ctx, uint32_t* entries, uint32_t max_count);
@@ -364,7 +365,10 @@ int pft_ntt_tuning_import(pft_ctx* ctx, const uint32_t* entries, uint32_t count)
  * with the first pass of the forward transform of its output rows (used
  * where that transform's schedule starts with a radix-16 column pass and
  * N >= 256; otherwise as mode 1): each converted row is written once, already
- * through stages 0-3.  The results are identical in every mode.  PFT_EINVAL
+ * through stages 0-3.  In mode 2 the inverse transform of the conversion's
+ * inputs also stops before its final radix-16 column pass (its schedule is
+ * then chosen among those ending with one) and the conversion applies that
+ * pass while loading.  The results are identical in every mode.  PFT_EINVAL
  * for any other mode. */
 int pft_bconv_mode(pft_ctx* ctx, int mode);
 

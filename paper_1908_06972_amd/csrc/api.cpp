@@ -230,7 +230,7 @@ struct pft_ctx {
     // NTT pass schedules: pinned per direction, else tuned per (direction,
     // batch-size class) on first use when ntt_tune is set
     bool bconv_mfma = true;  // base conversions on the matrix cores
-    bool modup_fuse = true;  // ModUp fused with the first forward transform pass (MFMA only)
+    bool bconv_fuse = true;  // conversions fused with the adjacent transform passes (MFMA only)
     bool ntt_tune = true;
     NttSchedule ntt_pinned[2] = {};
     std::map<uint32_t, NttSchedule> ntt_tuned;
@@ -1377,7 +1377,7 @@ static void key_switch_b(pft_ctx* c, uint32_t n, WsRef ws, const KsLayout& K, ui
     // its final radix-16 column pass (a schedule chosen among those ending
     // with one) and ModUp applies that pass to its inputs.
     const uint32_t nkb = (std::min(P->alpha, level) + 1) / 2;
-    const bool fuse = c->bconv_mfma && c->modup_fuse && lg >= 8 && nkb <= 6 && col16(full, rows - A) &&
+    const bool fuse = c->bconv_mfma && c->bconv_fuse && lg >= 8 && nkb <= 6 && col16(full, rows - A) &&
                       col16(last, rows - na_last);
     const bool ifuse_up = fuse && last_pass_col16(c, (uint64_t)n * level);
     // d -> coefficient form at off_dcoef (the first pass reads d in place;
@@ -1427,7 +1427,7 @@ static void key_switch_b(pft_ctx* c, uint32_t n, WsRef ws, const KsLayout& K, ui
     // transform (as for ModUp); the forward transform of conv finishes
     // ModDown in its final pass: out_b[i] = (acc_b[i] - conv_b[i]) P^-1 (+ add_b)
     const uint32_t down_kb = (P->K + 1) / 2;
-    const bool fuse_down = c->bconv_mfma && c->modup_fuse && lg >= 8 && down_kb <= 6 &&
+    const bool fuse_down = c->bconv_mfma && c->bconv_fuse && lg >= 8 && down_kb <= 6 &&
                            first_pass_col16(c, 2ull * n * level);
     const bool ifuse_down = fuse_down && last_pass_col16(c, 2ull * n * P->K);
     // special rows of both accumulators to coefficient form
@@ -2439,7 +2439,7 @@ extern "C" int pft_bconv_mode(pft_ctx* c, int mode) {
     if (!c) return fail(PFT_EINVAL, "null context");
     if (mode < 0 || mode > 2) return fail(PFT_EINVAL, "mode must be 0 (VALU), 1 (MFMA) or 2 (MFMA, fused ModUp)");
     c->bconv_mfma = mode >= 1;
-    c->modup_fuse = mode == 2;
+    c->bconv_fuse = mode == 2;
     return PFT_OK;
 }
 
