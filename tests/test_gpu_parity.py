@@ -429,3 +429,20 @@ def test_fused_first_pass_c3(c3, flags):
             w.assert_same(w.ctx.rescale(ga), C.rescale(w.op, oa))
     finally:
         w.ctx.ntt_set_schedule(False, None)
+
+
+def test_tuning_table_restricted_classes(torch_cuda):
+    """Tuning entries of the first-radix-4 classes (32 + class): accepted with
+    a schedule starting with radix 4 and exported back, refused otherwise."""
+    import paper_1908_06972_amd.ckks as L
+    import paper_1908_06972_amd.native as N
+    lp = L.Params(16, 4, 60, 50, 1, 60, 2, 2 ** 40)
+    ctx = L.Context(lp)
+    ok = [(True, 40, ((4, 12), 3)), (False, 9, ((4, 12), 0))]
+    ctx.ntt_tuning_import(ok)
+    got = ctx.ntt_tuning_export()
+    for entry in ok:
+        assert entry in got
+    for bad in [(True, 40, ((8, 8), 0)), (True, 43, ((4, 12), 0)), (True, 11, ((4, 12), 0))]:
+        with pytest.raises(N.PftError):
+            ctx.ntt_tuning_import([bad])
