@@ -102,7 +102,7 @@ PROFILE_DIR = os.path.join(ROOT, "profiles")
 CSRC = os.path.join(ROOT, "paper_1908_06972_amd", "csrc")
 
 
-def source_sha(kid=None):
+def source_sha():
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
@@ -111,12 +111,12 @@ def source_sha(kid=None):
     return h.hexdigest()
 
 
-def stored_profile(kernel, kid):
+def stored_profile(kernel):
     """Counter figures of `kernel` recorded under profiles/ (a `pft-profile:`
     JSON line), if they were taken on the current kernel source."""
     if not os.path.isdir(PROFILE_DIR):
         return None
-    sha = source_sha(kid)
+    sha = source_sha()
     for f in sorted(os.listdir(PROFILE_DIR)):
         if not f.endswith(".md"):
             continue
@@ -154,17 +154,6 @@ def _step_dispatches(rows, key_id, key_start):
         return []
     first = tensors[CHAIN_DEPTH]
     return [r for r in rows if int(r[key_id]) >= first]
-
-
-def family_of(name):
-    """Kernel family index (see pft_prof_enable) of a kernel name."""
-    if name.startswith("k_ntt_pass<"):
-        return 1 if name.split(",")[2].strip() == "true" else 0
-    for prefix, k in (("k_modup", 2), ("k_key_inner", 3), ("k_moddown", 4), ("k_tensor", 6), ("k_automorphism", 7),
-                      ("k_rescale", 8)):
-        if name.startswith(prefix):
-            return k
-    return 9
 
 
 def summarize(trace_dir, fetch_dir, write_dir, kernel, kid, commands, n_top=6):
@@ -231,7 +220,7 @@ def summarize(trace_dir, fetch_dir, write_dir, kernel, kid, commands, n_top=6):
         c, t = per.get(target, (0, 0.0))
         rec = {
             "kernel": target,
-            "source_sha256": source_sha(family_of(target)),
+            "source_sha256": source_sha(),
             "avg_launch_us": t / c if c else None,
             "fetch_kib_per_launch": sum(fetch) / len(fetch) if fetch else None,
             "write_kib_per_launch": sum(write) / len(write) if write else None,
@@ -775,7 +764,7 @@ def main():
     avg_ms = d_ms / max(d_cnt, 1)
     gbs = d_bytes / (d_ms * 1e-3) / 1e9 if d_ms > 0 else 0.0
     kname = kernel_name(dom, variant)
-    stored = stored_profile(kname, dom)
+    stored = stored_profile(kname)
     traffic = None
     alu = None
     if stored:
