@@ -117,3 +117,25 @@ def test_keygen_refuses_step_zero():
     ctx = L.Context(L.Params(*SMALL.values()))
     with pytest.raises(RuntimeError):
         ctx.keygen(3, [op.n // 2])
+
+
+def test_keygen_twice_replaces_every_key():
+    """A second pft_keygen on the same context (another seed) regenerates the
+    secret, public, relinearisation and rotation keys in place: results then
+    match the oracle's keys for the second seed."""
+    import torch
+    assert torch.cuda.is_available()
+    w = World(SMALL, 5, [3])
+    w2 = World.__new__(World)
+    w2.__dict__.update(w.__dict__)
+    w.ctx.keygen(6, [3])
+    n, op = w.n, w.op
+    w2.s = SP.secret(6, n)
+    w2.pk = C.public_key(op, w2.s, *SP.public_key_draws(6, op.q, n))
+    mods = op.key_moduli()
+    w2.rlk = C.relin_key(op, w2.s, *SP.switch_key_draws(6, 0, mods, op.dnum, n))
+    w2.rot = {3: C.rotation_key(op, w2.s, 3, *SP.switch_key_draws(6, SP.rotation_key_id(3, n), mods, op.dnum, n))}
+    (ga, oa), (gb, ob) = w2.enc_pair(7, 307, op.L), w2.enc_pair(8, 308, op.L)
+    w2.assert_same(w2.ctx.mul_relin(ga, gb), C.hmul_relin(op, oa, ob, w2.rlk))
+    w2.assert_same(w2.ctx.rotate(ga, 3), C.rotate(op, oa, 3, w2.rot[3]))
+    assert np.array_equal(w2.ctx.decrypt(ga), C.decrypt(op, w2.s, oa))
