@@ -508,8 +508,9 @@ void launch_pass(const PolyBatch& b, const DevTables& t, uint32_t log_n, uint32_
 // matrix cores and fold as the stand-alone conversion kernels, for up to 16
 // target rows at a time, into LDS; then thread (target, u) takes the 16
 // values t of its column through the four stages exactly as the first
-// transform pass does (fp64 rows converted on entry) and stores them in that
-// pass's output form, so the transform continues with its second pass.
+// transform pass does (on fp64 rows the fold's reduced double is already the
+// butterflies' input form) and stores them in that pass's output form, so the
+// transform continues with its second pass.
 //
 // IFUSE: the input rows come from an inverse transform whose final pass (a
 // radix-16 column pass, stages 3-0 with N^-1 folded in) has not run; the
