@@ -306,8 +306,6 @@ def prof_enable(ctx, mask):
 
 
 def setup(batch):
-    import numpy as np
-
     import synth as S
     from paper_1908_06972_amd import ckks as L
 
@@ -317,25 +315,17 @@ def setup(batch):
     ctx = L.Context(lp, 0, stream=torch.cuda.Stream())  # a non-null stream: graphs can be captured on it
     n = lp.n
     t0 = time.time()
-    kd = S.key_draws(1, n, lp.q)
-    ctx.set_secret(kd.s)
-    ctx.gen_public_key(kd.pk_a, kd.pk_e)
-    a, e = S.switch_key_draws(1, 0, n, lp.key_moduli(), lp.dnum)
-    ctx.gen_relin_key(a, e)
+    # keys and encryption randomness drawn on the device from seeds
     steps = [1 << i for i in range(15)]
-    for st in steps:
-        a, e = S.switch_key_draws(1, 1000 + st, n, lp.key_moduli(), lp.dnum)
-        ctx.gen_rotation_key(st, a, e)
-    del a, e
-    log("keys: rlk + %d rotation keys resident, %.2f GiB device, %.1fs" % (len(steps), ctx.device_bytes() / 2 ** 30,
-                                                                            time.time() - t0))
+    ctx.keygen(1, steps)
+    log("keys from seed: rlk + %d rotation keys resident, %.2f GiB device, %.1fs" % (
+        len(steps), ctx.device_bytes() / 2 ** 30, time.time() - t0))
     cts = []
     for i in range(batch):
         z = S.slots_unit(S.rng(303 + i), n // 2)
-        d = S.enc_draws(3000 + i, n)
-        cts.append(ctx.encrypt(lp.encode(z), lp.L, lp.scale, d.v, d.e0, d.e1))
+        cts.append(ctx.encrypt_seeded(lp.encode(z), lp.L, lp.scale, 3000 + i))
     ctx.synchronize()
-    return lp, ctx, kd, cts
+    return lp, ctx, cts
 
 
 def job_step(ctx, cts):
@@ -648,7 +638,7 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
 
-    lp, ctx, kd, cts = setup(args.batch)
+    lp, ctx, cts = setup(args.batch)
     sync = torch.cuda.synchronize
     if args.tuning_in and not args.retune and os.path.exists(args.tuning_in):
         with open(args.tuning_in) as fh:
