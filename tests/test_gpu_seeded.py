@@ -139,3 +139,21 @@ def test_keygen_twice_replaces_every_key():
     w2.assert_same(w2.ctx.mul_relin(ga, gb), C.hmul_relin(op, oa, ob, w2.rlk))
     w2.assert_same(w2.ctx.rotate(ga, 3), C.rotate(op, oa, 3, w2.rot[3]))
     assert np.array_equal(w2.ctx.decrypt(ga), C.decrypt(op, w2.s, oa))
+
+
+def test_seeded_large_ring():
+    """The large-ring parameters (N = 2^16, 24 + 6 primes, dnum 4) as the
+    benchmark sets them up: seeded keys and encryption, then HMult+relin,
+    RESCALE and a rotation, bit-exact against the oracle's own draws."""
+    import torch
+    assert torch.cuda.is_available()
+    cfg = S.CONFIGS["C3"]
+    spec = dict(log_n=cfg.log_n, n_q=cfg.n_q, q0_bits=cfg.q0_bits, q_bits=cfg.q_bits, n_p=cfg.n_p,
+                p_bits=cfg.p_bits, dnum=cfg.dnum, scale=2 ** cfg.log_scale)
+    w = World(spec, 1, [1])
+    (ga, oa), (gb, ob) = w.enc_pair(303, 3000, w.op.L), w.enc_pair(304, 3001, w.op.L)
+    w.assert_same(ga, oa)
+    g = w.ctx.rescale(w.ctx.mul_relin(ga, gb))
+    o = C.rescale(w.op, C.hmul_relin(w.op, oa, ob, w.rlk))
+    w.assert_same(g, o)
+    w.assert_same(w.ctx.rotate(g, 1), C.rotate(w.op, o, 1, w.rot[1]))
