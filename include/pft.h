@@ -137,7 +137,8 @@ int pft_gen_rotation_key(pft_ctx* ctx, int32_t step, const uint64_t* a, const in
  * (w0 mod 3) - 1; uniform floor((w1 2^64 + w0) q / 2^128); discrete Gaussian
  * -19 + #{k : T_k <= w0} with T from pft_gaussian_cdt.  The result equals the
  * caller-draws entry points above fed with the same draws.  A step that is 0
- * mod N/2 is refused (PFT_EINVAL); the key-cache setting applies as above.
+ * mod N/2 is refused (PFT_EINVAL) before any key changes; the key-cache
+ * setting applies as above.
  * Synchronizes the context stream. */
 int pft_keygen(pft_ctx* ctx, uint64_t seed, const int32_t* rot_steps, uint32_t n_steps);
 /* The 38 thresholds T_k = floor(2^64 F(k)), k = -19..18, of the cumulative

@@ -1064,13 +1064,15 @@ extern "C" int pft_keygen(pft_ctx* c, uint64_t seed, const int32_t* rot_steps, u
     if (!c || (n_steps && !rot_steps)) return fail(PFT_EINVAL, "null argument");
     if (c->capturing) return fail(PFT_EINVAL, "key generation cannot be captured in a graph");
     const uint32_t half = c->P->n / 2;
+    for (uint32_t i = 0; i < n_steps; ++i)  // refuse before any key changes
+        if (norm_step(rot_steps[i], c->P->n) == 0)
+            return fail(PFT_EINVAL, "rotation step %d is 0 mod N/2 = %u", rot_steps[i], half);
     int r;
     if ((r = set_secret_core(c, nullptr, seeded_draws(seed, 0))) || (r = gen_public_key_core(c, seeded_draws(seed, 0))) ||
         (r = gen_relin_key_core(c, seeded_draws(seed, 0))))
         return r;
     for (uint32_t i = 0; i < n_steps; ++i) {
         const int32_t ns = norm_step(rot_steps[i], c->P->n);
-        if (ns == 0) return fail(PFT_EINVAL, "rotation step %d is 0 mod N/2 = %u", rot_steps[i], half);
         if ((r = gen_rotation_key_core(c, rot_steps[i], seeded_draws(seed, 1u + (uint64_t)ns)))) return r;
     }
     return PFT_OK;

@@ -117,6 +117,9 @@ def test_keygen_refuses_step_zero():
     ctx = L.Context(L.Params(*SMALL.values()))
     with pytest.raises(RuntimeError):
         ctx.keygen(3, [op.n // 2])
+    # nothing was generated: encryption still has no public key
+    with pytest.raises(RuntimeError):
+        ctx.encrypt_seeded(S.plaintext_coeffs(S.rng(1), op.n, 2 ** 20), op.L, op.scale, 1)
 
 
 def test_keygen_twice_replaces_every_key():
