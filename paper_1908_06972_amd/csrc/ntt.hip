@@ -354,25 +354,33 @@ __global__ __launch_bounds__(4096 >> EB) void k_ntt_pass(PolyBatch b, const DevM
     // (integer-valued doubles within 4.5q for fp64 limbs; finish() reduces
     // integer limbs).  Every load of a chunk is issued before the first
     // result is formed, so their latencies overlap.
-    [[maybe_unused]] auto epi_store = [&](auto pos, auto val) {
+    // PAIRS: positions come in adjacent pairs (pos(2m + 1) = pos(2m) + 1 with
+    // pos(2m) even), moved as 16-byte accesses.
+    [[maybe_unused]] auto epi_store = [&](auto pos, auto val, auto pairs) {
+        constexpr bool PAIRS = decltype(pairs)::value;
         constexpr int CH = E < 8 ? E : 8;
+        auto ld = [&](const uint64_t* __restrict__ p, const uint32_t (&jj)[CH], uint64_t (&v)[CH]) {
+            if constexpr (PAIRS) {
+#pragma unroll
+                for (int k = 0; k < CH; k += 2) {
+                    const ulonglong2 t = *reinterpret_cast<const ulonglong2*>(p + jj[k]);
+                    v[k] = t.x;
+                    v[k + 1] = t.y;
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < CH; ++k) v[k] = p[jj[k]];
+            }
+        };
 #pragma unroll
         for (int k0 = 0; k0 < E; k0 += CH) {
             uint32_t jj[CH];
-            uint64_t a[CH], u[CH], w[CH];
+            uint64_t a[CH], u[CH], w[CH], r[CH];
 #pragma unroll
-            for (int k = 0; k < CH; ++k) {
-                jj[k] = pos(k0 + k);
-                a[k] = acc_src[jj[k]];
-            }
-            if (add_src) {
-#pragma unroll
-                for (int k = 0; k < CH; ++k) u[k] = add_src[jj[k]];
-            }
-            if (add2_src) {
-#pragma unroll
-                for (int k = 0; k < CH; ++k) w[k] = add2_src[jj[k]];
-            }
+            for (int k = 0; k < CH; ++k) jj[k] = pos(k0 + k);
+            ld(acc_src, jj, a);
+            if (add_src) ld(add_src, jj, u);
+            if (add2_src) ld(add2_src, jj, w);
             if (fp) {
 #pragma unroll
                 for (int k = 0; k < CH; ++k) {
@@ -382,16 +390,28 @@ __global__ __launch_bounds__(4096 >> EB) void k_ntt_pass(PolyBatch b, const DevM
                     double y = fmulmod(as_f(fp_from_u64(a[k])) - as_f(val(k0 + k)), as_f(pinv.w), as_f(pinv.wp), qd);
                     if (add_src) y += as_f(fp_from_u64(u[k]));
                     if (add2_src) y += as_f(fp_from_u64(w[k]));
-                    out_row[jj[k]] = fp_to_u64(as_u(y), qd, qinv);
+                    r[k] = fp_to_u64(as_u(y), qd, qinv);
                 }
             } else {
 #pragma unroll
                 for (int k = 0; k < CH; ++k) {
-                    uint64_t r = shoup(a[k] + q - finish(val(k0 + k)), pinv.w, pinv.wp, q);
-                    if (add_src) r = add_mod(r, u[k], q);
-                    if (add2_src) r = add_mod(r, w[k], q);
-                    out_row[jj[k]] = r;
+                    uint64_t v = shoup(a[k] + q - finish(val(k0 + k)), pinv.w, pinv.wp, q);
+                    if (add_src) v = add_mod(v, u[k], q);
+                    if (add2_src) v = add_mod(v, w[k], q);
+                    r[k] = v;
                 }
+            }
+            if constexpr (PAIRS) {
+#pragma unroll
+                for (int k = 0; k < CH; k += 2) {
+                    ulonglong2 t;
+                    t.x = r[k];
+                    t.y = r[k + 1];
+                    *reinterpret_cast<ulonglong2*>(out_row + jj[k]) = t;
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < CH; ++k) out_row[jj[k]] = r[k];
             }
         }
     };
@@ -406,7 +426,8 @@ __global__ __launch_bounds__(4096 >> EB) void k_ntt_pass(PolyBatch b, const DevM
         }
     } else if constexpr (DIRECT_OUT) {
         if constexpr (EPI)
-            epi_store([&](int e) { return (uint32_t)gidx(c, POUT::r_of(l, e)); }, [&](int e) { return x[e]; });
+            epi_store([&](int e) { return (uint32_t)gidx(c, POUT::r_of(l, e)); }, [&](int e) { return x[e]; },
+                      std::false_type{});
         else
 #pragma unroll
             for (int e = 0; e < E; ++e) data[gidx(c, POUT::r_of(l, e))] = finish(x[e]);
@@ -418,8 +439,20 @@ __global__ __launch_bounds__(4096 >> EB) void k_ntt_pass(PolyBatch b, const DevM
             return std::pair<uint32_t, uint32_t>(idx / M, idx % M);
         };
         if constexpr (EPI) {
-            epi_store([&](int k) { const auto p = at(k); return (uint32_t)gidx(p.first, p.second); },
-                      [&](int k) { const auto p = at(k); return lds[lds_at<LOG_M, EB>(p.first, p.second)]; });
+            // element pairs 2 (tid + NT m) and its successor: adjacent in the
+            // row (a row pass has no index bits below its window)
+            auto at2 = [&](int k) {
+                const uint32_t idx = 2u * (tid + NT * (uint32_t)(k >> 1)) + (uint32_t)(k & 1);
+                return std::pair<uint32_t, uint32_t>(idx / M, idx % M);
+            };
+            if constexpr (!COL)
+                epi_store([&](int k) { const auto p = at2(k); return (uint32_t)gidx(p.first, p.second); },
+                          [&](int k) { const auto p = at2(k); return lds[lds_at<LOG_M, EB>(p.first, p.second)]; },
+                          std::true_type{});
+            else
+                epi_store([&](int k) { const auto p = at(k); return (uint32_t)gidx(p.first, p.second); },
+                          [&](int k) { const auto p = at(k); return lds[lds_at<LOG_M, EB>(p.first, p.second)]; },
+                          std::false_type{});
         } else {
 #pragma unroll
             for (int k = 0; k < E; ++k) {
