@@ -453,6 +453,17 @@ __global__ __launch_bounds__(4096 >> EB) void k_ntt_pass(PolyBatch b, const DevM
                 epi_store([&](int k) { const auto p = at(k); return (uint32_t)gidx(p.first, p.second); },
                           [&](int k) { const auto p = at(k); return lds[lds_at<LOG_M, EB>(p.first, p.second)]; },
                           std::false_type{});
+        } else if constexpr (!COL) {
+            // adjacent element pairs of the row as 16-byte stores
+#pragma unroll
+            for (int m = 0; m < E / 2; ++m) {
+                const uint32_t idx = 2u * (tid + NT * (uint32_t)m);
+                const uint32_t cc = idx / M, r = idx % M;
+                ulonglong2 v;
+                v.x = finish(lds[lds_at<LOG_M, EB>(cc, r)]);
+                v.y = finish(lds[lds_at<LOG_M, EB>(cc, r + 1)]);
+                *reinterpret_cast<ulonglong2*>(data + gidx(cc, r)) = v;
+            }
         } else {
 #pragma unroll
             for (int k = 0; k < E; ++k) {
