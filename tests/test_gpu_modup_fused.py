@@ -21,6 +21,8 @@ CASES = {
     "a6_n12": dict(log_n=12, n_q=12, q0_bits=60, q_bits=50, n_p=6, p_bits=60, dnum=2, scale=2 ** 50),
     # alpha 2 at N = 2^14 (column stride 1024)
     "a2_n14": dict(log_n=14, n_q=8, q0_bits=60, q_bits=40, n_p=2, p_bits=60, dnum=4, scale=2 ** 40),
+    # alpha 3 at N = 2^13 (schedule (4, 9), a 512-point row pass), odd K
+    "a3_n13": dict(log_n=13, n_q=6, q0_bits=60, q_bits=45, n_p=3, p_bits=60, dnum=2, scale=2 ** 45),
 }
 STEPS = [1, 5]
 
