@@ -630,8 +630,8 @@ def main():
         print(summarize(*args.summarize, args.kernel, args.family, args.commands), end="")
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (DESIGN.md describes how the "
-              "work would shard); rerun with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (requests would be sharded "
+              "one process per GPU); rerun with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
