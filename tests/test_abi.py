@@ -189,3 +189,26 @@ def test_library_gaussian_table_equals_oracle():
     assert t[:cnt.value].tolist() == SP.gaussian_cdt()
     with pytest.raises(N.PftError):
         N.check(lib.pft_gaussian_cdt(N.u64p(t), 37, ctypes.byref(cnt)))
+
+
+def test_shipped_tuning_table_is_valid():
+    """Every entry of the large-ring tuning table bench.py imports is a
+    candidate schedule at N = 2^16 (pft_ntt_candidates, host only), classes
+    are 0..10 or 32 + 0..10, and the first-radix-4 classes start with 4."""
+    import json
+    from paper_1908_06972_amd.ckks import Params
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1908_06972_amd",
+                        "tuning", "large_ring_n16_l24.json")
+    table = json.load(open(path))
+    lib = N.load()
+    p = Params(16, 24, 60, 50, 6, 60, 4, 2 ** 50)
+    n = lib.pft_ntt_candidates(p.handle, None, 0)
+    buf = (ctypes.c_uint32 * (4 * n))()
+    assert lib.pft_ntt_candidates(p.handle, buf, n) == n
+    cands = {(tuple(r for r in buf[4 * i:4 * i + 3] if r), buf[4 * i + 3]) for i in range(n)}
+    assert table
+    for inv, cls, radices, flags in table:
+        assert isinstance(inv, bool) and (0 <= cls <= 10 or 32 <= cls <= 42)
+        assert (tuple(radices), flags) in cands
+        if cls >= 32:
+            assert radices[0] == 4 and len(radices) >= 2
