@@ -131,3 +131,67 @@ def test_mutant_colpack_half_totalsum(monkeypatch):
     real = C.total_sum
     monkeypatch.setattr(C, "total_sum", lambda P, x, n_slots, keys: real(P, x, n_slots // 2, keys))
     _expect_fail(TC.test_stage1_replicates_column_dot, fx)
+
+
+# ---- the seeded sampler (oracle/sampler.py)
+
+def _philox_pins():
+    from tests import test_oracle_sampler as TSm
+    for key in TSm.KEYS:
+        for ctr in TSm.CTRS:
+            TSm.test_philox_matches_numpy(key, ctr)
+
+
+def test_mutant_philox_wrong_weyl_constant(monkeypatch):
+    from oracle import sampler as SP
+    monkeypatch.setattr(SP, "W1", SP.W1 ^ 1)
+    _expect_fail(_philox_pins)
+
+
+def test_mutant_philox_no_key_bump(monkeypatch):
+    from oracle import sampler as SP
+    monkeypatch.setattr(SP, "W0", 0)
+    monkeypatch.setattr(SP, "W1", 0)
+    _expect_fail(_philox_pins)
+
+
+def test_mutant_philox_swapped_round_outputs(monkeypatch):
+    from oracle import sampler as SP
+    real = SP.mulhilo
+    monkeypatch.setattr(SP, "mulhilo", lambda a, b: tuple(reversed(real(a, b))))
+    _expect_fail(_philox_pins)
+
+
+def test_mutant_gaussian_variance_sigma_not_2sigma(monkeypatch):
+    from decimal import Decimal, localcontext
+
+    from oracle import sampler as SP
+    from tests import test_oracle_sampler as TSm
+
+    def bad(sigma=SP.SIGMA, bound=SP.BOUND):
+        with localcontext() as ctx:
+            ctx.prec = 60
+            var = Decimal(sigma) * Decimal(sigma)  # exp(-x^2 / sigma^2): the factor 2 dropped
+            rho = [(Decimal(-x * x) / var).exp() for x in range(-bound, bound + 1)]
+            total, acc, out = sum(rho), Decimal(0), []
+            for r in rho[:-1]:
+                acc += r
+                out.append(int((acc * (1 << 64)) // total))
+        return out
+    monkeypatch.setattr(SP, "gaussian_cdt", bad)
+    _expect_fail(TSm.test_cdt_variance_is_sigma_squared, "3.2", 19)
+
+
+def test_mutant_uniform_off_by_one(monkeypatch):
+    from oracle import sampler as SP
+    from tests import test_oracle_sampler as TSm
+    real = SP.uniform
+    monkeypatch.setattr(SP, "uniform", lambda w0, w1, q: real(w0, w1, q) + np.uint64(1))
+    _expect_fail(TSm.test_uniform_is_its_definition_and_in_range)
+
+
+def test_mutant_ternary_unbalanced(monkeypatch):
+    from oracle import sampler as SP
+    from tests import test_oracle_sampler as TSm
+    monkeypatch.setattr(SP, "ternary", lambda w0: (w0 % np.uint64(4)).astype(np.int64) - 1)
+    _expect_fail(TSm.test_gaussian_and_ternary_draws)
