@@ -43,8 +43,11 @@ def kernel_name(kid, variant):
     if kid in (0, 1) and variant:
         v = variant - 1
         b = lambda x: "true" if x else "false"  # noqa: E731
-        return "k_ntt_pass<%d, %d, %s, %s, %s, %s, %s>" % (v & 31, 3 if v & 256 else 4, b(kid == 1), b(v & 32),
-                                                            b(v & 64), b(v & 128), b(v & 512))
+        name = "k_ntt_pass<%d, %d, %s, %s, %s, %s, %s" % (v & 31, 3 if v & 256 else 4, b(kid == 1), b(v & 32),
+                                                          b(v & 64), b(v & 128), b(v & 512))
+        return name + (", true>" if v & 1024 else ">")  # X -> X^kappa folded into the pass
+    if kid == 3 and variant >= 1024:  # inner product fused with the row pass of ModUp's rows
+        return "k_row_inner<%d, 3>" % (variant - 1024)
     if kid == 8 and variant == 1:  # RESCALE's expansion fused with the first transform pass
         return "k_rescale_col_b"
     if kid in (2, 4) and variant >= 64:  # base conversion fused with the first (and last inverse) pass
@@ -265,8 +268,7 @@ def parse():
                     help="kernel the --summarize counters are collected for; auto = the longest in the trace")
     ap.add_argument("--family", type=int, default=0)
     ap.add_argument("--commands", nargs="*", default=[])
-    ap.add_argument("--tuning-in", default=os.path.join(ROOT, "paper_1908_06972_amd", "tuning",
-                                                        "large_ring_n16_l24.json"),
+    ap.add_argument("--tuning-in", default=DEFAULT_TUNING,
                     help="JSON table of NTT schedules (from --tuning-out) to use instead of tuning; the default is the "
                          "table the autotuner produced for this workload, so kernel choices repeat run to run")
     ap.add_argument("--retune", action="store_true", help="ignore --tuning-in and let the autotuner choose")
@@ -305,27 +307,59 @@ def prof_enable(ctx, mask):
     N.check(ctx.lib.pft_prof_enable(ctx.handle, mask))
 
 
-def setup(batch):
+KEY_SEED = 1                                  # pft_keygen seed of the workload's keys
+ROT_STEPS = [1 << i for i in range(15)]       # rotation keys 2^0..2^14 (rotate-and-sum over 2^15 slots)
+SLOT_SEED0 = 303                              # slots of ciphertext i from rng(SLOT_SEED0 + i)
+ENC_SEED0 = 3000                              # encryption draws of ciphertext i from seed ENC_SEED0 + i
+DEFAULT_TUNING = os.path.join(ROOT, "paper_1908_06972_amd", "tuning", "large_ring_n16_l24.json")
+
+
+def make_context():
+    """Large-ring parameters, a context on a stream of its own (graphs can
+    be captured on it) and the workload's keys drawn on the device from
+    KEY_SEED: secret, public key, relinearisation key, rotation keys
+    2^0..2^14."""
     import synth as S
     from paper_1908_06972_amd import ckks as L
 
     import torch
-    cfg = S.CONFIGS["C3"]
-    lp = L.Params.from_config(cfg)
-    ctx = L.Context(lp, 0, stream=torch.cuda.Stream())  # a non-null stream: graphs can be captured on it
-    n = lp.n
+    lp = L.Params.from_config(S.CONFIGS["C3"])
+    ctx = L.Context(lp, 0, stream=torch.cuda.Stream())
     t0 = time.time()
-    # keys and encryption randomness drawn on the device from seeds
-    steps = [1 << i for i in range(15)]
-    ctx.keygen(1, steps)
+    ctx.keygen(KEY_SEED, ROT_STEPS)
     log("keys from seed: rlk + %d rotation keys resident, %.2f GiB device, %.1fs" % (
-        len(steps), ctx.device_bytes() / 2 ** 30, time.time() - t0))
-    cts = []
-    for i in range(batch):
-        z = S.slots_unit(S.rng(303 + i), n // 2)
-        cts.append(ctx.encrypt_seeded(lp.encode(z), lp.L, lp.scale, 3000 + i))
+        len(ROT_STEPS), ctx.device_bytes() / 2 ** 30, time.time() - t0))
+    return lp, ctx
+
+
+def batch_slots(n, batch):
+    """Unit-modulus complex slots of the batch's ciphertexts."""
+    import synth as S
+    return [S.slots_unit(S.rng(SLOT_SEED0 + i), n // 2) for i in range(batch)]
+
+
+def encrypt_batch(ctx, lp, plains):
+    """Seeded encryptions of the integer plaintexts at the top level."""
+    cts = [ctx.encrypt_seeded(m, lp.L, lp.scale, ENC_SEED0 + i) for i, m in enumerate(plains)]
     ctx.synchronize()
+    return cts
+
+
+def import_tuning(ctx, path):
+    """Load a JSON table of NTT schedules (written by --tuning-out)."""
+    with open(path) as fh:
+        ctx.ntt_tuning_import([(e[0], e[1], (tuple(e[2]), int(e[3]))) for e in json.load(fh)])
+
+
+def setup(batch):
+    lp, ctx = make_context()
+    cts = encrypt_batch(ctx, lp, [lp.encode(z) for z in batch_slots(lp.n, batch)])
     return lp, ctx, cts
+
+
+def chain_link(ctx, cur):
+    """One link of the chain on the whole batch: RESCALE(HMult+relin(c, c))."""
+    return ctx.rescale_batch(ctx.mul_relin_batch(cur, cur))
 
 
 def job_step(ctx, cts):
@@ -333,7 +367,7 @@ def job_step(ctx, cts):
     output buffers; returns the final ciphertexts."""
     cur = cts
     for _ in range(CHAIN_DEPTH):
-        cur = ctx.rescale_batch(ctx.mul_relin_batch(cur, cur))
+        cur = chain_link(ctx, cur)
     return ctx.total_sum_batch(cur, ROT_SLOTS)
 
 
@@ -641,8 +675,7 @@ def main():
     lp, ctx, cts = setup(args.batch)
     sync = torch.cuda.synchronize
     if args.tuning_in and not args.retune and os.path.exists(args.tuning_in):
-        with open(args.tuning_in) as fh:
-            ctx.ntt_tuning_import([(e[0], e[1], (tuple(e[2]), int(e[3]))) for e in json.load(fh)])
+        import_tuning(ctx, args.tuning_in)
         log("NTT schedules imported from %s" % args.tuning_in)
 
     def save_tuning():

@@ -24,9 +24,11 @@
  * Streams: a context enqueues all work on the HIP stream given at creation;
  *   calls that return host data synchronize that stream.  A context is not
  *   thread-safe; use one per host thread/stream.
- * Randomness: KEYGEN and ENC take their random polynomials as arguments
- *   (ternary secret, Gaussian errors, uniform masks), so results are a pure
- *   function of the inputs.
+ * Randomness: KEYGEN and ENC either take their random polynomials as
+ *   arguments (ternary secret, Gaussian errors, uniform masks) or, in the
+ *   seeded entry points pft_keygen and pft_encrypt_seeded, draw them on the
+ *   device from a counter-based generator keyed by a seed; either way results
+ *   are a pure function of the inputs.
  */
 #ifndef PFT_H
 #define PFT_H
@@ -99,7 +101,11 @@ typedef struct pft_pt {
 } pft_pt;
 
 /* ---- KEYGEN (Sec. 3.4), randomness supplied by the caller (host memory) --
- * s: ternary secret, N int64 in {-1,0,1}.  Must be called first. */
+ * s: ternary secret, N int64 in {-1,0,1}.  Must be called first.  Setting a
+ * secret (here or through pft_keygen) drops every key derived from an
+ * earlier one -- public, relinearisation and rotation keys -- so until they
+ * are generated again the calls that need them return PFT_ENOKEY.
+ * Synchronizes the context stream. */
 int pft_set_secret(pft_ctx* ctx, const int64_t* s);
 /* Public key b = -a s + e over q_0..q_{L-1}.  a: [L][N] uniform residues in
  * coefficient form (a[i][k] < q_i); e: [N] small errors. */
@@ -127,7 +133,7 @@ int pft_gen_rotation_key(pft_ctx* ctx, int32_t step, const uint64_t* a, const in
  * cached.  pft_key_cache_stats writes {max_resident, slots allocated, hits,
  * misses, bytes copied to the device} to out[5]. */
 /* Seeded KEYGEN (Sec. 3.4; X_key, the uniform masks and X_err of SETUP, sigma
- * = 3.2 from Sec. 5): the secret, public key, relinearisation key and one
+ * = 3.2 from Sec. 6.4, CKKS parameter selection): the secret, public key, relinearisation key and one
  * rotation key per listed step, every draw taken on the device from the
  * Philox4x64-10 counter-based generator (Salmon et al., SC 2011).  Stream
  * key (seed, purpose 2^56 + key_id 2^8 + digit), counter (coefficient j,
@@ -137,8 +143,9 @@ int pft_gen_rotation_key(pft_ctx* ctx, int32_t step, const uint64_t* a, const in
  * (w0 mod 3) - 1; uniform floor((w1 2^64 + w0) q / 2^128); discrete Gaussian
  * -19 + #{k : T_k <= w0} with T from pft_gaussian_cdt.  The result equals the
  * caller-draws entry points above fed with the same draws.  A step that is 0
- * mod N/2 is refused (PFT_EINVAL) before any key changes; the key-cache
- * setting applies as above.
+ * mod N/2 is refused (PFT_EINVAL) before any key changes.  Every key of an
+ * earlier secret is dropped first (rotation keys for steps missing from
+ * rot_steps then return PFT_ENOKEY); the key-cache setting applies as above.
  * Synchronizes the context stream. */
 int pft_keygen(pft_ctx* ctx, uint64_t seed, const int32_t* rot_steps, uint32_t n_steps);
 /* The 38 thresholds T_k = floor(2^64 F(k)), k = -19..18, of the cumulative
@@ -361,16 +368,22 @@ int pft_ntt_tuning_import(pft_ctx* ctx, const uint32_t* entries, uint32_t count)
  * operands are split into signed base-256 digits, the int8 x int8 products
  * are summed exactly in int32 by v_mfma_i32_32x32x16_i8, and each target's
  * 8 digit sums are folded back into a residue on the VALU.  mode 0 selects the
- * 128-bit VALU multiply-accumulate kernels instead, 1 the matrix cores, 2 (the
- * default) the matrix cores with each conversion (ModUp and ModDown) fused
+ * 128-bit VALU multiply-accumulate kernels instead, 1 the matrix cores, 2 the
+ * matrix cores with each conversion (ModUp and ModDown) fused
  * with the first pass of the forward transform of its output rows (used
  * where that transform's schedule starts with a radix-16 column pass and
  * N >= 256; otherwise as mode 1): each converted row is written once, already
  * through stages 0-3.  In mode 2 the inverse transform of the conversion's
  * inputs also stops before its final radix-16 column pass (its schedule is
  * then chosen among those ending with one) and the conversion applies that
- * pass while loading.  The results are identical in every mode.  PFT_EINVAL
- * for any other mode. */
+ * pass while loading.  Mode 3 (the default) is mode 2 with the key inner
+ * product fused into the remaining (row) pass of the forward transform of
+ * ModUp's rows: where that transform's schedule is (4, log_n - 4), log_n in
+ * {12, 13, 14, 16}, and at most 8 digits are active, one kernel takes each
+ * extended row through its row pass and accumulates its products with the
+ * key, so the extended digits are read once and only the accumulators are
+ * written (otherwise as mode 2).  The results are identical in every mode.
+ * PFT_EINVAL for any other mode. */
 int pft_bconv_mode(pft_ctx* ctx, int mode);
 
 /* ---- op-list executor ---------------------------------------------------

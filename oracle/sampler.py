@@ -1,11 +1,11 @@
 """Seeded draws of key generation and encryption -- TEST INFRASTRUCTURE ONLY
 (imported by tests/ and nothing else).
 
-SETUP (Sec. 3, the CKKS description) fixes the distributions the scheme
+SETUP (Sec. 3.4, the CKKS description) fixes the distributions the scheme
 draws from: X_key for the secret (ternary coefficients in this workload),
 the uniform distribution over R_q for the masks a and, for encryption, a
 ternary v, and the zero-centred discrete Gaussian X_err of standard
-deviation sigma = 3.2 (Sec. 5, parameter selection) for the errors.  Seeded
+deviation sigma = 3.2 (Sec. 6.4, CKKS parameter selection) for the errors.  Seeded
 KEYGEN and ENC take their draws from a counter-based generator, so one seed
 gives the same draws on every machine and in every order of evaluation.
 

@@ -19,15 +19,19 @@ FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
-    """Compile every source into one shared library (always recompiles)."""
-    objs = []
+    """Compile every source into one shared library (always recompiles; the
+    sources compile in parallel processes)."""
+    objs, procs = [], []
     for src in SOURCES:
         obj = os.path.join(CSRC, src + ".o")
         cmd = [HIPCC] + [f for f in FLAGS if f != "-shared"] + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
+        procs.append((src, subprocess.Popen(cmd)))
         objs.append(obj)
+    failed = [src for src, p in procs if p.wait() != 0]
+    if failed:
+        raise RuntimeError("hipcc failed on " + ", ".join(failed))
     tmp = LIB + ".tmp%d" % os.getpid()
     subprocess.check_call([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs)
     os.replace(tmp, LIB)

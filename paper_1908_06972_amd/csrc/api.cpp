@@ -210,6 +210,10 @@ struct pft_ctx {
     uint64_t* s_prime = nullptr;  // [L+K][N] scratch for s^2 / s(X^kappa) during key generation
     uint64_t* pk = nullptr;  // [2][L][N] (b, a), NTT domain
     SwitchKeyDev rlk;
+    // pk and rlk hold keys of the current secret (false after the secret
+    // changed and until they are generated again)
+    bool pk_ok = false, rlk_ok = false;
+    std::vector<uint64_t*> key_pool;  // device memory of dropped switching keys, reused by new ones
     std::map<int32_t, SwitchKeyDev> rot;  // keyed by step mod N/2
     // rotation-key cache (0 = every key resident): at most rot_cache_max keys
     // in device slots, all keys in pinned host memory, least recently used
@@ -231,6 +235,8 @@ struct pft_ctx {
     // batch-size class) on first use when ntt_tune is set
     bool bconv_mfma = true;  // base conversions on the matrix cores
     bool bconv_fuse = true;  // conversions fused with the adjacent transform passes (MFMA only)
+    bool inner_fuse = true;  // key inner product fused with the row pass of ModUp's rows (needs bconv_fuse)
+    std::vector<uint32_t> fp_rows;  // [L+K]: 1 where the modulus runs fp64 arithmetic (below 2^50)
     bool ntt_tune = true;
     NttSchedule ntt_pinned[2] = {};
     std::map<uint32_t, NttSchedule> ntt_tuned;
@@ -511,6 +517,7 @@ extern "C" int pft_ctx_create(const pft_params* P, int device, void* stream, pft
     c->device = device;
     c->stream = (hipStream_t)stream;
     c->prof.st = c->stream;
+    for (uint64_t m : P->mods) c->fp_rows.push_back(ntt_fp(m) ? 1u : 0u);
     int r = build_tables(c);
     if (r) {
         pft_ctx_destroy(c);
@@ -737,6 +744,9 @@ static void ntt_jobs(pft_ctx* c, const std::vector<NttJob>& jobs, uint32_t n_lim
             for (uint32_t i = 0; i < PFT_MAX_POLYS / 2; ++i) {
                 e.out[i] = s / 2 + i < PFT_MAX_POLYS / 2 ? epi->out[s / 2 + i] : nullptr;
                 e.acc_item[i] = s / 2 + i < PFT_MAX_POLYS / 2 ? epi->acc_item[s / 2 + i] : nullptr;
+                // perm_src is per item for a forward epilogue, per polynomial for an inverse transform
+                const size_t pi = inverse ? s + i : s / 2 + i;
+                e.perm_src[i] = pi < PFT_MAX_POLYS / 2 ? epi->perm_src[pi] : nullptr;
             }
             launch_ntt(b, c->tabs, P->log_n, inverse, sched, c->stream, hook(c), &e, first);
         } else {
@@ -836,6 +846,25 @@ extern "C" int pft_gaussian_cdt(uint64_t* table, uint32_t capacity, uint32_t* co
     return PFT_OK;
 }
 
+// Every key derived from the secret (public, relinearisation and rotation
+// keys) is dropped when the secret changes, so that no key of an earlier
+// secret stays usable; the device memory of dropped rotation keys is reused
+// by the keys generated next.  Queued work may still read the old keys, so
+// the stream is drained first.
+static int drop_derived_keys(pft_ctx* c) {
+    HIPCK(hipStreamSynchronize(c->stream));
+    c->pk_ok = false;
+    c->rlk_ok = false;
+    for (auto& kv : c->rot) {
+        SwitchKeyDev& k = kv.second;
+        if (k.slot < 0 && k.data) c->key_pool.push_back(k.data);
+        if (k.host) (void)hipHostFree(k.host);
+    }
+    c->rot.clear();
+    for (auto& o : c->rot_slot_owner) o = -1;
+    return PFT_OK;
+}
+
 static int set_secret_core(pft_ctx* c, const int64_t* s, const Draws& d) {
     const pft_params* P = c->P;
     const uint32_t R = P->L + P->K;
@@ -856,6 +885,8 @@ extern "C" int pft_set_secret(pft_ctx* c, const int64_t* s) {
     if (!c || !s) return fail(PFT_EINVAL, "null argument");
     if (c->capturing) return fail(PFT_EINVAL, "host transfers cannot be captured in a graph");
     if (!check_ternary(s, c->P->n)) return fail(PFT_EINVAL, "secret must be ternary");
+    int r;
+    if ((r = drop_derived_keys(c))) return r;
     return set_secret_core(c, s, host_draws(nullptr, nullptr));
 }
 
@@ -881,6 +912,7 @@ static int gen_public_key_core(pft_ctx* c, const Draws& d) {
     SmallBatch A = sb(P, {pa}, P->L), S = sb(P, {c->s}, P->L), E = sb(P, {e_rns}, P->L), B = sb(P, {c->pk}, P->L);
     launch_ew(EW_NEG_MULADD, B, A, &S, &E, c->tabs, P->log_n, c->stream);
     HIPCK(hipStreamSynchronize(c->stream));
+    c->pk_ok = true;
     return PFT_OK;
 }
 
@@ -950,6 +982,10 @@ static int gen_switch_key(pft_ctx* c, const uint64_t* s_prime, const Draws& d, S
     const uint32_t R = P->L + P->K;
     const size_t nR = (size_t)R * P->n;
     int r;
+    if (!dst->data && !c->key_pool.empty()) {
+        dst->data = c->key_pool.back();
+        c->key_pool.pop_back();
+    }
     if (!dst->data && (r = dalloc(c, &dst->data, (size_t)P->dnum * 2 * nR * 8))) return r;
     if ((r = ensure_ws(c, (nR + P->n + nR) * 8))) return r;
     uint64_t* e_rns = c->ws;
@@ -979,9 +1015,8 @@ static int gen_switch_key(pft_ctx* c, const uint64_t* s_prime, const Draws& d, S
             const SmallBatch Bd = sb(P, {kb}, i1 - i0, i0);
             launch_ew(EW_ADD, Bd, Bd, &G, nullptr, c->tabs, P->log_n, c->stream);
         }
-        // store both halves times 2^64 (Montgomery form) for the inner product
-        launch_mul_const(B, B, c->to_mont, c->tabs, P->log_n, c->stream);
-        launch_mul_const(A, A, c->to_mont, c->tabs, P->log_n, c->stream);
+        // both halves in the inner product's storage form (launch_key_form)
+        launch_key_form(sb(P, {kb, ka}, R, 0, P->L), c->to_mont, c->tabs, P->log_n, c->stream);
     }
     HIPCK(hipStreamSynchronize(c->stream));
     return PFT_OK;
@@ -994,7 +1029,9 @@ static int gen_relin_key_core(pft_ctx* c, const Draws& d) {
     if (!c->s_prime && (r = dalloc(c, &c->s_prime, (size_t)R * P->n * 8))) return r;
     const SmallBatch S = sb(P, {c->s}, R, 0, P->L), S2 = sb(P, {c->s_prime}, R, 0, P->L);
     launch_ew(EW_MUL, S2, S, &S, nullptr, c->tabs, P->log_n, c->stream);
-    return gen_switch_key(c, c->s_prime, d, &c->rlk);
+    if ((r = gen_switch_key(c, c->s_prime, d, &c->rlk))) return r;
+    c->rlk_ok = true;
+    return PFT_OK;
 }
 
 extern "C" int pft_gen_relin_key(pft_ctx* c, const uint64_t* a, const int64_t* e) {
@@ -1011,6 +1048,10 @@ static uint64_t galois_element(int32_t step, uint32_t n) {
     int64_t r = ((int64_t)step % half + half) % half;
     return powmod(5, (uint64_t)r, 2ull * n);
 }
+
+// kappa^-1 modulo 2N: the units modulo 2N form a group of order N, so the
+// inverse is kappa^(N-1).
+static uint64_t galois_inverse(uint64_t kappa, uint32_t n) { return powmod(kappa, n - 1, 2ull * n); }
 
 static int32_t norm_step(int32_t step, uint32_t n) {
     const int64_t half = n / 2;
@@ -1068,6 +1109,7 @@ extern "C" int pft_keygen(pft_ctx* c, uint64_t seed, const int32_t* rot_steps, u
         if (norm_step(rot_steps[i], c->P->n) == 0)
             return fail(PFT_EINVAL, "rotation step %d is 0 mod N/2 = %u", rot_steps[i], half);
     int r;
+    if ((r = drop_derived_keys(c))) return r;
     if ((r = set_secret_core(c, nullptr, seeded_draws(seed, 0))) || (r = gen_public_key_core(c, seeded_draws(seed, 0))) ||
         (r = gen_relin_key_core(c, seeded_draws(seed, 0))))
         return r;
@@ -1108,7 +1150,7 @@ static int check_ct(const pft_ctx* c, const pft_ct* ct) {
 static int encrypt_core(pft_ctx* c, const int64_t* m, uint32_t level, double scale, const int64_t* v,
                         const int64_t* e0, const int64_t* e1, const Draws& d, pft_ct* out) {
     const pft_params* P = c->P;
-    if (!c->pk) return fail(PFT_ENOKEY, "no public key");
+    if (!c->pk_ok) return fail(PFT_ENOKEY, "no public key for the current secret");
     if (level < 1 || level > P->L) return fail(PFT_ELEVEL, "level %u out of range", level);
     const uint32_t n = P->n;
     const size_t nl = (size_t)level * n;
@@ -1350,16 +1392,32 @@ static bool last_pass_col16(pft_ctx* c, uint64_t limbs) {
     return s.n_passes >= 2 && s.radix[0] == 4;
 }
 
+// The input of a rotation's key switch: item z's ciphertext src[z]
+// ([2][level][N], NTT domain) under X -> X^kappa.  Its c1 image is d and
+// its c0 image is the addend of the first output polynomial.
+struct KsRot {
+    uint64_t kappa, kappa_inv;
+    ItemPtrs src;
+};
+
 // Key switching of d (NTT domain, [level][N] at ws_z + off_d) for n items:
 // out_z = ModDown(sum_j ModUp_j(d) key_j) + (ws rows at off_add0/off_add1),
 // plus, for the first polynomial, the rows at off_add0b (out may be those
 // rows: each element is read before it is written).
+// rot: d and the first addend are the X^kappa images of rot->src (out must
+// not overlap rot->src).  Where the inner product is fused with the row pass
+// of ModUp's rows, the permutation is folded into the loads of the kernels
+// that read them (the first pass of d's inverse transform, the own rows of
+// the inner product, the ModDown epilogue); otherwise both images are first
+// written to the workspace at off_add0 (c0) and off_d = off_add0 + level N
+// (c1).
 static void key_switch_b(pft_ctx* c, uint32_t n, WsRef ws, const KsLayout& K, uint64_t off_d,
                          const SwitchKeyDev& key, uint64_t off_add0, uint64_t off_add1, const ItemPtrs& out,
-                         uint64_t off_add0b = PFT_NO_OFFSET) {
+                         uint64_t off_add0b = PFT_NO_OFFSET, const KsRot* rot = nullptr) {
     const pft_params* P = c->P;
     const uint32_t lg = P->log_n, A = P->alpha, level = K.level, rows = K.rows, beta = K.beta;
     const double N = (double)P->n;
+    const uint64_t nl = (uint64_t)level * P->n;
     // ModUp's rows: all digits of all items, full digits and the ragged last
     // digit in separate transform launches (different limb counts)
     std::vector<NttJob> full, last;
@@ -1382,13 +1440,36 @@ static void key_switch_b(pft_ctx* c, uint32_t n, WsRef ws, const KsLayout& K, ui
     const bool fuse = c->bconv_mfma && c->bconv_fuse && lg >= 8 && nkb <= 6 && col16(full, rows - A) &&
                       col16(last, rows - na_last);
     const bool ifuse_up = fuse && last_pass_col16(c, (uint64_t)n * level);
-    // d -> coefficient form at off_dcoef (the first pass reads d in place;
-    // d itself stays in the NTT domain for the inner product)
+    // the remaining (row) pass of the rows' forward transform, and the key
+    // inner product: fused in one kernel where that pass is the row pass of
+    // a (4, log_n - 4) schedule, else a transform launch per digit group and
+    // the inner-product kernel
+    const NttSchedule rs = ntt_schedule(c, false, full.empty() ? (uint64_t)last.size() * (rows - na_last)
+                                                               : (uint64_t)full.size() * (rows - A));
+    const bool fuse_inner =
+        fuse && c->inner_fuse && beta <= 8 && row_inner_supported(lg) && rs.n_passes == 2 && rs.radix[0] == 4;
+    const bool fold = rot && fuse_inner;
+    if (rot && !fold) {
+        // both X^kappa images into the workspace
+        timed(c, PK_AUTOMORPHISM, 8.0 * 4 * nl * n, 0,
+              [&] { launch_automorphism_b(n, rot->src, 2 * level, ws, off_add0, rot->kappa, lg, c->stream); });
+    }
+    // d -> coefficient form at off_dcoef (the first pass reads d in place, or
+    // through the permutation from rot->src; d stays in the NTT domain for
+    // the inner product)
     {
         std::vector<NttJob> jobs;
         for (uint32_t z = 0; z < n; ++z) jobs.push_back(NttJob{ws.base + z * ws.stride + K.off_dcoef, 255u, 0u});
-        ntt_jobs(c, jobs, level, ~0u, true, 0, nullptr, (int64_t)off_d - (int64_t)K.off_dcoef, ifuse_up ? 1u : 0u,
-                 ifuse_up);
+        if (fold) {
+            NttEpilogue pe{};
+            for (uint32_t z = 0; z < n; ++z) pe.perm_src[z] = rot->src.p[z] + nl;
+            pe.kappa = rot->kappa;
+            pe.kappa_inv = rot->kappa_inv;
+            ntt_jobs(c, jobs, level, ~0u, true, 0, &pe, 0, ifuse_up ? 1u : 0u, ifuse_up);
+        } else {
+            ntt_jobs(c, jobs, level, ~0u, true, 0, nullptr, (int64_t)off_d - (int64_t)K.off_dcoef, ifuse_up ? 1u : 0u,
+                     ifuse_up);
+        }
     }
     // ModUp base conversion and the forward transforms of its rows
     {
@@ -1411,18 +1492,41 @@ static void key_switch_b(pft_ctx* c, uint32_t n, WsRef ws, const KsLayout& K, ui
                 launch_modup_b(n, ws, K.off_dcoef, K.off_ext, level, c->kc, c->tabs, lg, c->bconv_mfma, c->stream);
             }, c->bconv_mfma ? nkb : 0);
         }
-        const uint32_t first = fuse ? 1u : 0u;
-        if (!full.empty()) ntt_jobs(c, full, rows - A, level, false, 0, nullptr, 0, first);
-        if (!last.empty()) ntt_jobs(c, last, rows - na_last, level, false, 0, nullptr, 0, first);
+        if (fuse_inner) {
+            // method bytes: d's own rows and the accumulators per item, the
+            // key once per launch (the extended rows are the transform's
+            // pass boundary); butterflies of the row pass plus two products
+            // per digit input
+            double ext_rows = 0;
+            for (uint32_t j = 0; j < beta; ++j) ext_rows += rows - (std::min(j * A + A, level) - j * A);
+            const uint32_t lm = lg - 4;
+            timed(c, PK_KEY_INNER, 8.0 * N * ((double)level * n + 2.0 * rows * n + 2.0 * beta * rows),
+                  N * n * (0.5 * lm * ext_rows + 2.0 * beta * rows),
+                  [&] {
+                      const uint64_t* c1[PFT_MAX_ITEMS] = {};
+                      if (fold)
+                          for (uint32_t z = 0; z < n; ++z) c1[z] = rot->src.p[z] + nl;
+                      launch_row_inner(n, ws, off_d, K.off_ext, K.off_acc, key.data, level, c->kc, c->tabs,
+                                       c->fp_rows.data(), lg, c1, fold ? rot->kappa : 0, fold ? rot->kappa_inv : 0,
+                                       c->stream);
+                  },
+                  1024u + lm);
+        } else {
+            const uint32_t first = fuse ? 1u : 0u;
+            if (!full.empty()) ntt_jobs(c, full, rows - A, level, false, 0, nullptr, 0, first);
+            if (!last.empty()) ntt_jobs(c, last, rows - na_last, level, false, 0, nullptr, 0, first);
+            // key inner product over level + K rows: the key is read once per
+            // launch (shared by the batch); each item reads beta inputs and
+            // writes two outputs per row
+            const double key_once = beta <= 8 ? 1.0 : (double)n;
+            timed(c, PK_KEY_INNER,
+                  8.0 * N * ((double)beta * rows * n + 2.0 * beta * rows * key_once + 2.0 * rows * n),
+                  2.0 * N * beta * rows * n, [&] {
+                launch_key_inner_b(n, ws, off_d, K.off_ext, K.off_acc, key.data, level, c->kc, c->tabs, lg,
+                                   c->stream);
+            }, beta <= 8 ? beta : 0);
+        }
     }
-    // key inner product over level + K rows
-    // the key is read once per launch (shared by the batch); each item reads
-    // beta inputs and writes two outputs per row
-    const double key_once = beta <= 8 ? 1.0 : (double)n;
-    timed(c, PK_KEY_INNER, 8.0 * N * ((double)beta * rows * n + 2.0 * beta * rows * key_once + 2.0 * rows * n),
-          2.0 * N * beta * rows * n, [&] {
-        launch_key_inner_b(n, ws, off_d, K.off_ext, K.off_acc, key.data, level, c->kc, c->tabs, lg, c->stream);
-    }, beta <= 8 ? beta : 0);
     // ModDown: the conversion of the special rows to the q-limbs is fused
     // with the first pass of conv's forward transform where its schedule
     // allows, and then also with the final pass of the special rows' inverse
@@ -1470,6 +1574,13 @@ static void key_switch_b(pft_ctx* c, uint32_t n, WsRef ws, const KsLayout& K, ui
         epi.pinv = c->kc.down_pinv;
         epi.pinv_fp = c->kc.down_pinv + P->L;
         epi.level = level;
+        if (fold) {
+            // the c0 image comes through the permutation in place of off_add0
+            epi.d_add[0] = PFT_EPI_NO_ADD;
+            for (uint32_t z = 0; z < n; ++z) epi.perm_src[z] = rot->src.p[z];
+            epi.kappa = rot->kappa;
+            epi.kappa_inv = rot->kappa_inv;
+        }
         ntt_jobs(c, jobs, level, ~0u, false, 0, &epi, 0, fuse_down ? 1u : 0u);
     }
 }
@@ -1499,7 +1610,7 @@ extern "C" int pft_mul_relin(pft_ctx* c, const pft_ct* a, const pft_ct* b, pft_c
 
 extern "C" int pft_mul_relin_batch(pft_ctx* c, uint32_t n, const pft_ct* a, const pft_ct* b, pft_ct* out) {
     if (!c || !a || !b || !out) return fail(PFT_EINVAL, "null argument");
-    if (!c->rlk.data) return fail(PFT_ENOKEY, "no relinearisation key");
+    if (!c->rlk_ok) return fail(PFT_ENOKEY, "no relinearisation key for the current secret");
     int r;
     for (uint32_t i = 0; i < n; ++i) {
         if ((r = check_ct(c, &a[i])) || (r = check_ct(c, &b[i]))) return r;
@@ -1659,7 +1770,7 @@ extern "C" int pft_rotate_batch(pft_ctx* c, uint32_t n, const pft_ct* in, int32_
     const SwitchKeyDev* key = use_rot(c, step, &r);
     if (!key) return r;
     const pft_params* P = c->P;
-    const uint64_t kappa = galois_element(step, P->n);
+    const uint64_t kappa = galois_element(step, P->n), kappa_inv = galois_inverse(kappa, P->n);
     return for_level_groups(n, in, [&](const std::vector<uint32_t>& g) -> int {
         const uint32_t l = in[g[0]].level, cnt = (uint32_t)g.size();
         const uint64_t nl = (uint64_t)l * P->n;
@@ -1672,9 +1783,8 @@ extern "C" int pft_rotate_batch(pft_ctx* c, uint32_t n, const pft_ct* in, int32_
             I.p[z] = in[g[z]].data;
             O.p[z] = out[g[z]].data;
         }
-        timed(c, PK_AUTOMORPHISM, 8.0 * 4 * nl * cnt, 0,
-              [&] { launch_automorphism_b(cnt, I, 2 * l, ws, 0, kappa, P->log_n, c->stream); });
-        key_switch_b(c, cnt, ws, K, nl, *key, 0, PFT_NO_OFFSET, O);
+        KsRot kr{kappa, kappa_inv, I};
+        key_switch_b(c, cnt, ws, K, nl, *key, 0, PFT_NO_OFFSET, O, PFT_NO_OFFSET, &kr);
         for (uint32_t z = 0; z < cnt; ++z) {
             out[g[z]].level = l;
             out[g[z]].scale = in[g[z]].scale;
@@ -1725,13 +1835,11 @@ extern "C" int pft_rotate_pow2_batch(pft_ctx* c, uint32_t n, const pft_ct* in, i
             if (!((rr0 >> k) & 1u)) continue;
             const uint64_t src = offs[cur], dst = offs[1 - cur];
             const uint64_t kappa = galois_element((int32_t)(1u << k), P->n);
-            timed(c, PK_AUTOMORPHISM, 8.0 * 4 * nl * cnt, 0, [&] {
-                launch_automorphism_b(cnt, ws_items(ws, cnt, src), 2 * l, ws, dst, kappa, lg, c->stream);
-            });
             int ke;
             const SwitchKeyDev* rk = use_rot(c, (int32_t)(1u << k), &ke);
             if (!rk) return ke;
-            key_switch_b(c, cnt, ws, K, dst + nl, *rk, dst, PFT_NO_OFFSET, ws_items(ws, cnt, dst));
+            KsRot kr{kappa, galois_inverse(kappa, P->n), ws_items(ws, cnt, src)};
+            key_switch_b(c, cnt, ws, K, dst + nl, *rk, dst, PFT_NO_OFFSET, ws_items(ws, cnt, dst), PFT_NO_OFFSET, &kr);
             cur = 1 - cur;
         }
         launch_copy_rows_b(cnt, ws_items(ws, cnt, offs[cur]), 0, O, 0, 2 * l, lg, c->stream);
@@ -1774,20 +1882,21 @@ extern "C" int pft_total_sum_batch(pft_ctx* c, uint32_t n, const pft_ct* in, uin
             O.p[z] = out[g[z]].data;
         }
         launch_copy_rows_b(cnt, I, 0, ws_items(ws, cnt), off_cur, 2 * l, lg, c->stream);
-        const ItemPtrs CUR = ws_items(ws, cnt, off_cur), ROT = ws_items(ws, cnt, off_rot);
+        // the running sum alternates between the two regions: the step reads
+        // one (its X^kappa image and itself) and writes the other
+        uint64_t a = off_cur, b = off_rot;
         for (uint32_t s = 1; s < n_slots; s <<= 1) {
-            // rot = ROTATE(cur, s); cur = cur + rot   (Alg. 2)
+            // cur + ROTATE(cur, s)   (Alg. 2): (cur0 + kappa(cur0) + ks0, cur1 + ks1),
+            // finished by the ModDown epilogue into the other region
             const uint64_t kappa = galois_element((int32_t)s, P->n);
-            timed(c, PK_AUTOMORPHISM, 8.0 * 4 * nl * cnt, 0,
-                  [&] { launch_automorphism_b(cnt, CUR, 2 * l, ws, off_rot, kappa, lg, c->stream); });
             int ke;
             const SwitchKeyDev* rk = use_rot(c, (int32_t)s, &ke);
             if (!rk) return ke;
-            // cur + ROTATE(cur): (cur0 + kappa(cur0) + ks0, cur1 + ks1), finished in
-            // place by the ModDown epilogue
-            key_switch_b(c, cnt, ws, K, off_rot + nl, *rk, off_rot, off_cur + nl, CUR, off_cur);
+            KsRot kr{kappa, galois_inverse(kappa, P->n), ws_items(ws, cnt, a)};
+            key_switch_b(c, cnt, ws, K, b + nl, *rk, b, a + nl, ws_items(ws, cnt, b), a, &kr);
+            std::swap(a, b);
         }
-        launch_copy_rows_b(cnt, CUR, 0, O, 0, 2 * l, lg, c->stream);
+        launch_copy_rows_b(cnt, ws_items(ws, cnt, a), 0, O, 0, 2 * l, lg, c->stream);
         for (uint32_t z = 0; z < cnt; ++z) {
             out[g[z]].level = l;
             out[g[z]].scale = in[g[z]].scale;
@@ -2153,7 +2262,7 @@ extern "C" int pft_ptmatvec(pft_ctx* c, const pft_ptmat* m, uint32_t n_docs, con
 extern "C" int pft_ctmatvec(pft_ctx* c, uint32_t n_o, uint32_t n_i, uint32_t n_in, const pft_ct* diags,
                             uint32_t n_docs, const pft_ct* in, pft_ct* out) {
     if (!c || !diags || !in || !out) return fail(PFT_EINVAL, "null argument");
-    if (!c->rlk.data) return fail(PFT_ENOKEY, "no relinearisation key");
+    if (!c->rlk_ok) return fail(PFT_ENOKEY, "no relinearisation key for the current secret");
     const pft_params* P = c->P;
     const uint32_t t = P->n / 2;
     if (!n_o || (n_o & (n_o - 1)) || !n_i || (n_i & (n_i - 1)) || n_i > t || n_o > n_i)
@@ -2439,9 +2548,11 @@ extern "C" int pft_ntt_candidates(const pft_params* p, uint32_t* scheds, uint32_
 
 extern "C" int pft_bconv_mode(pft_ctx* c, int mode) {
     if (!c) return fail(PFT_EINVAL, "null context");
-    if (mode < 0 || mode > 2) return fail(PFT_EINVAL, "mode must be 0 (VALU), 1 (MFMA) or 2 (MFMA, fused ModUp)");
+    if (mode < 0 || mode > 3)
+        return fail(PFT_EINVAL, "mode must be 0 (VALU), 1 (MFMA), 2 (MFMA, fused passes) or 3 (2 + fused inner product)");
     c->bconv_mfma = mode >= 1;
-    c->bconv_fuse = mode == 2;
+    c->bconv_fuse = mode >= 2;
+    c->inner_fuse = mode == 3;
     return PFT_OK;
 }
 

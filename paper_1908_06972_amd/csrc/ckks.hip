@@ -77,6 +77,20 @@ __global__ __launch_bounds__(TB) void k_mul_const(SmallBatch out, SmallBatch a, 
     out.ptr[poly][at(row, log_n, k)] = shoup(x, w.w, w.wp, q);
 }
 
+// Switching-key storage form in place: rows whose modulus is below 2^50 hold
+// the residue as an integer-valued double, the others residue * 2^64 mod m.
+__global__ __launch_bounds__(TB) void k_key_form(SmallBatch out, const TwPair* __restrict__ to_mont,
+                                                 const DevMod* __restrict__ mods, uint32_t log_n) {
+    const uint32_t k = blockIdx.x * TB + threadIdx.x;
+    const uint32_t limb = blockIdx.y / out.n_polys, poly = blockIdx.y % out.n_polys;
+    const uint32_t row = out.first + limb;
+    const uint32_t mi = sb_mod(out, row);
+    const DevMod md = mods[mi];
+    uint64_t* p = out.ptr[poly] + at(row, log_n, k);
+    const uint64_t x = *p;
+    *p = md.fp ? fp_from_u64(x) : shoup(x, to_mont[mi].w, to_mont[mi].wp, md.q);
+}
+
 // ---- batched kernels of the homomorphic operations ------------------------
 
 // HMUL tensor of ciphertexts a_z, b_z ([2][level][N] each): d0 = a0 b0,
@@ -273,17 +287,47 @@ __global__ __launch_bounds__(TB) void k_key_inner_b(WsRef ws, uint64_t off_d, ui
     const uint32_t beta = (level + kc.alpha - 1) / kc.alpha;
     const uint32_t krows = kc.L + kc.K;
     const uint64_t* __restrict__ w = ws_item(ws);
+    uint64_t* __restrict__ acc = ws_item(ws) + off_acc;
+    if (md.fp) {
+        // keys are integer-valued doubles; each term lies within 3q/4 and the
+        // sums are brought back within q/2 every four terms (exact below 2^53)
+        double s0 = 0.0, s1 = 0.0;
+        for (uint32_t j = 0; j < beta; ++j) {
+            const uint32_t i0 = j * kc.alpha, i1 = min(i0 + kc.alpha, level);
+            const uint64_t x = (t >= i0 && t < i1) ? w[off_d + at(t, log_n, k)]
+                                                    : w[off_ext + at(j * rows + t, log_n, k)];
+            const double xd = as_f(fp_from_u64(x));
+            const double k0 = as_f(key[at((2 * j) * krows + krow, log_n, k)]);
+            const double k1 = as_f(key[at((2 * j + 1) * krows + krow, log_n, k)]);
+            s0 += fmulmod(xd, k0, k0 / md.qd, md.qd);
+            s1 += fmulmod(xd, k1, k1 / md.qd, md.qd);
+            if ((j & 3u) == 3u) {
+                s0 = freduce(s0, md.qd, md.qinv);
+                s1 = freduce(s1, md.qd, md.qinv);
+            }
+        }
+        acc[at(t, log_n, k)] = fp_to_u64(as_u(s0), md.qd, md.qinv);
+        acc[at(rows + t, log_n, k)] = fp_to_u64(as_u(s1), md.qd, md.qinv);
+        return;
+    }
+    // 128-bit sums of at most 8 products stay below q 2^64 (8 q < 2^63)
     Acc128 a0 = {0, 0}, a1 = {0, 0};
+    uint64_t r0 = 0, r1 = 0;
     for (uint32_t j = 0; j < beta; ++j) {
         const uint32_t i0 = j * kc.alpha, i1 = min(i0 + kc.alpha, level);
         const uint64_t x = (t >= i0 && t < i1) ? w[off_d + at(t, log_n, k)]
                                                 : w[off_ext + at(j * rows + t, log_n, k)];
         mac128(a0, x, key[at((2 * j) * krows + krow, log_n, k)]);
         mac128(a1, x, key[at((2 * j + 1) * krows + krow, log_n, k)]);
+        if ((j & 7u) == 7u || j + 1 == beta) {
+            r0 = add_mod(r0, mont_redc(a0.lo, a0.hi, md.q, md.mont_neg_qinv), md.q);
+            r1 = add_mod(r1, mont_redc(a1.lo, a1.hi, md.q, md.mont_neg_qinv), md.q);
+            a0 = {0, 0};
+            a1 = {0, 0};
+        }
     }
-    uint64_t* __restrict__ acc = ws_item(ws) + off_acc;
-    acc[at(t, log_n, k)] = mont_redc(a0.lo, a0.hi, md.q, md.mont_neg_qinv);
-    acc[at(rows + t, log_n, k)] = mont_redc(a1.lo, a1.hi, md.q, md.mont_neg_qinv);
+    acc[at(t, log_n, k)] = r0;
+    acc[at(rows + t, log_n, k)] = r1;
 }
 
 // The same inner product for all n_items ciphertexts of a launch, one thread
@@ -328,8 +372,8 @@ __global__ __launch_bounds__(TB) void k_key_inner_items(WsRef ws, uint32_t n_ite
         double w0[BETA], p0[BETA], w1[BETA], p1[BETA];
 #pragma unroll
         for (uint32_t j = 0; j < BETA; ++j) {
-            w0[j] = (double)mont_redc(k0[j], 0, md.q, md.mont_neg_qinv);
-            w1[j] = (double)mont_redc(k1[j], 0, md.q, md.mont_neg_qinv);
+            w0[j] = as_f(k0[j]);
+            w1[j] = as_f(k1[j]);
             p0[j] = w0[j] / md.qd;
             p1[j] = w1[j] / md.qd;
         }
@@ -517,6 +561,12 @@ void launch_ew(EwOp op, const SmallBatch& out, const SmallBatch& a, const SmallB
     SmallBatch bb = b ? *b : a, cc = c ? *c : a;
     hipLaunchKernelGGL(k_ew, grid_nk(log_n, out.n_polys * out.n_limbs), dim3(TB), 0, st, (uint32_t)op, out, a, bb,
                        cc, t.mods, log_n);
+}
+
+void launch_key_form(const SmallBatch& rows, const TwPair* to_mont, const DevTables& t, uint32_t log_n,
+                     hipStream_t st) {
+    hipLaunchKernelGGL(k_key_form, grid_nk(log_n, rows.n_polys * rows.n_limbs), dim3(TB), 0, st, rows, to_mont,
+                       t.mods, log_n);
 }
 
 void launch_mul_const(const SmallBatch& out, const SmallBatch& a, const TwPair* consts, const DevTables& t,

@@ -16,9 +16,11 @@
 // elements are exchanged through LDS.  Global memory is read and written in
 // a coalesced order through LDS (consecutive lanes touch consecutive
 // addresses: along the sub-problem index when low bits exist, else along
-// the sub-problem itself).
-//   N = 2^12: one pass of 12 stages.   N = 2^13: 7 + 6.   N = 2^14: 7 + 7.
-//   N = 2^15: 8 + 7.                   N = 2^16: 8 + 8.
+// the sub-problem itself).  The split of the stages into passes is a
+// schedule (ntt_candidates below lists them per N; the first is the default,
+// e.g. one pass of 12 stages at N = 2^12 and 8 + 8 at N = 2^16); a
+// context's autotuner or a tuning table picks one per direction and batch
+// size (the large-ring workload uses 4 + 12 for its forward transforms).
 // Arithmetic, chosen per limb (uniform within a workgroup):
 //   * q < 2^50: fp64.  A residue fits the 53-bit significand, and MI355X issues
 //     fp64 FMA at the full VALU rate, so an exact product modulo q costs six
@@ -32,6 +34,7 @@
 #include "pft_kernels.h"
 
 #include <algorithm>
+#include <vector>
 #include <type_traits>
 
 namespace {
@@ -229,6 +232,40 @@ __device__ __forceinline__ void run_phases(uint64_t (&x)[1 << EB], uint64_t* lds
     }
 }
 
+// X -> X^kappa on an NTT-domain row (entry k holds the evaluation at
+// psi^(2 brv(k) + 1)) is the gather out[k] = in[sigma(k)] with
+// sigma(k) = brv(((2 brv(k) + 1) kappa mod 2N - 1) / 2).  In natural order
+// the map is affine modulo N, so the low bits of the image depend only on
+// the low bits of the argument; in bit-reversed order the high bits of
+// sigma(k) depend only on the high bits of k: every aligned 4096-word tile
+// of the result comes from one aligned tile of the input.  This stages
+// destination tile `tile` of the result in LDS (in the pass's LDS layout):
+// the source tile is read coalesced and word k of it is written at
+// pi(k) = sigma^-1(k) (kappa_inv in place of kappa), converted to the fp64
+// form if to_fp.  Ends with a barrier.
+__device__ __forceinline__ uint32_t galois_index(uint32_t k, uint32_t kap, uint32_t log_n) {
+    const uint32_t e = 2u * brev_n(k, log_n) + 1u;
+    const uint32_t e2 = (e * kap) & ((2u << log_n) - 1u);  // 2N divides 2^32: the low product bits suffice
+    return brev_n((e2 - 1u) >> 1, log_n);
+}
+template <int LOG_M, int EB>
+__device__ __forceinline__ void galois_tile_to_lds(const uint64_t* __restrict__ src, uint32_t tile, uint32_t log_n,
+                                                   uint64_t kappa, uint64_t kappa_inv, uint64_t* lds, bool to_fp) {
+    constexpr uint32_t NT = 4096 >> EB;
+    constexpr int E = 1 << EB;
+    constexpr uint32_t M = 1u << LOG_M;
+    const uint32_t st = galois_index(tile << 12, (uint32_t)kappa, log_n) >> 12;
+    const uint64_t* __restrict__ s = src + ((size_t)st << 12);
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        const uint32_t idx = threadIdx.x + NT * (uint32_t)k;
+        const uint32_t d = galois_index((st << 12) + idx, (uint32_t)kappa_inv, log_n) - (tile << 12);
+        const uint64_t v = s[idx];
+        lds[lds_at<LOG_M, EB>(d / M, d % M)] = to_fp ? fp_from_u64(v) : v;
+    }
+    __syncthreads();
+}
+
 // One pass over stages s0 .. s0 + LOG_M - 1 of a 4096-element tile.
 // COL (stages below log_n - LOG_M leave low index bits: the M elements of a
 // sub-problem are 2^lbits apart): consecutive lanes take consecutive
@@ -242,10 +279,16 @@ __device__ __forceinline__ void run_phases(uint64_t (&x)[1 << EB], uint64_t* lds
 // Limbs with DevMod::fp run the fp64 butterflies: the first pass of a
 // transform converts its u64 input, later passes exchange the doubles through
 // HBM, and the final pass writes canonical u64.  Integer limbs keep u64.
-template <int LOG_M, int EB, bool INV, bool COL, bool FINAL, bool STAGE, bool EPI>
+// PERM (row passes only): X -> X^kappa of NttEpilogue folded in.  Inverse
+// (the transform's first pass): the input of polynomial p is row i of
+// ep.perm_src[p] through the permutation.  Forward with EPI: the first
+// polynomial of item z also adds row i of ep.perm_src[z] through the
+// permutation (the ROTATE's X^kappa image of c0).
+template <int LOG_M, int EB, bool INV, bool COL, bool FINAL, bool STAGE, bool EPI, bool PERM = false>
 __global__ __launch_bounds__(4096 >> EB) void k_ntt_pass(PolyBatch b, const DevMod* __restrict__ mods,
                                                          const TwPair* __restrict__ tw, uint32_t log_n, uint32_t s0,
                                                          uint32_t first_pass, NttEpilogue ep) {
+    static_assert(!PERM || (!COL && (INV || EPI)), "the permutation is folded into row passes");
     constexpr int M = 1 << LOG_M;
     constexpr int E = 1 << EB;          // residues per thread
     constexpr uint32_t NT = 4096 >> EB;  // threads per workgroup
@@ -290,7 +333,11 @@ __global__ __launch_bounds__(4096 >> EB) void k_ntt_pass(PolyBatch b, const DevM
     uint64_t x[E];
     const bool convert_in = fp && first_pass;
     const uint64_t* src = first_pass ? data + b.src_delta : data;  // may alias data (in place)
-    if constexpr (DIRECT_IN && VEC_IN) {
+    if constexpr (PERM && INV) {
+        galois_tile_to_lds<LOG_M, EB>(ep.perm_src[poly] + ((size_t)row << log_n), blockIdx.x, log_n, ep.kappa,
+                                      ep.kappa_inv, lds, convert_in);
+        lds_read<LOG_M, PH_IN, EB>(x, lds, c, l);
+    } else if constexpr (DIRECT_IN && VEC_IN) {
         const ulonglong2* __restrict__ srcv = reinterpret_cast<const ulonglong2*>(src + gidx(c, (uint32_t)E * l));
 #pragma unroll
         for (int e = 0; e < E / 2; ++e) {
@@ -356,7 +403,8 @@ __global__ __launch_bounds__(4096 >> EB) void k_ntt_pass(PolyBatch b, const DevM
     // result is formed, so their latencies overlap.
     // PAIRS: positions come in adjacent pairs (pos(2m + 1) = pos(2m) + 1 with
     // pos(2m) even), moved as 16-byte accesses.
-    [[maybe_unused]] auto epi_store = [&](auto pos, auto val, auto pairs) {
+    // padd / has_p: a further addend (the permuted one of PERM), uniform per workgroup.
+    [[maybe_unused]] auto epi_store = [&](auto pos, auto val, auto pairs, auto padd, bool has_p) {
         constexpr bool PAIRS = decltype(pairs)::value;
         constexpr int CH = E < 8 ? E : 8;
         auto ld = [&](const uint64_t* __restrict__ p, const uint32_t (&jj)[CH], uint64_t (&v)[CH]) {
@@ -375,21 +423,26 @@ __global__ __launch_bounds__(4096 >> EB) void k_ntt_pass(PolyBatch b, const DevM
 #pragma unroll
         for (int k0 = 0; k0 < E; k0 += CH) {
             uint32_t jj[CH];
-            uint64_t a[CH], u[CH], w[CH], r[CH];
+            uint64_t a[CH], u[CH], w[CH], r[CH], pv[CH];
 #pragma unroll
             for (int k = 0; k < CH; ++k) jj[k] = pos(k0 + k);
             ld(acc_src, jj, a);
             if (add_src) ld(add_src, jj, u);
             if (add2_src) ld(add2_src, jj, w);
+            if (has_p) {
+#pragma unroll
+                for (int k = 0; k < CH; ++k) pv[k] = padd(k0 + k);
+            }
             if (fp) {
 #pragma unroll
                 for (int k = 0; k < CH; ++k) {
 #pragma clang fp contract(off)
                     // (acc - conv) P^-1 with |acc - conv| < 5.5q: within 2q; the
-                    // addends (< q each) keep it within 4q before the final reduction
+                    // addends (< q each) keep it within 5q before the final reduction
                     double y = fmulmod(as_f(fp_from_u64(a[k])) - as_f(val(k0 + k)), as_f(pinv.w), as_f(pinv.wp), qd);
                     if (add_src) y += as_f(fp_from_u64(u[k]));
                     if (add2_src) y += as_f(fp_from_u64(w[k]));
+                    if (has_p) y += as_f(fp_from_u64(pv[k]));
                     r[k] = fp_to_u64(as_u(y), qd, qinv);
                 }
             } else {
@@ -398,6 +451,7 @@ __global__ __launch_bounds__(4096 >> EB) void k_ntt_pass(PolyBatch b, const DevM
                     uint64_t v = shoup(a[k] + q - finish(val(k0 + k)), pinv.w, pinv.wp, q);
                     if (add_src) v = add_mod(v, u[k], q);
                     if (add2_src) v = add_mod(v, w[k], q);
+                    if (has_p) v = add_mod(v, pv[k], q);
                     r[k] = v;
                 }
             }
@@ -427,7 +481,7 @@ __global__ __launch_bounds__(4096 >> EB) void k_ntt_pass(PolyBatch b, const DevM
     } else if constexpr (DIRECT_OUT) {
         if constexpr (EPI)
             epi_store([&](int e) { return (uint32_t)gidx(c, POUT::r_of(l, e)); }, [&](int e) { return x[e]; },
-                      std::false_type{});
+                      std::false_type{}, [](int) { return 0ull; }, false);
         else
 #pragma unroll
             for (int e = 0; e < E; ++e) data[gidx(c, POUT::r_of(l, e))] = finish(x[e]);
@@ -445,14 +499,34 @@ __global__ __launch_bounds__(4096 >> EB) void k_ntt_pass(PolyBatch b, const DevM
                 const uint32_t idx = 2u * (tid + NT * (uint32_t)(k >> 1)) + (uint32_t)(k & 1);
                 return std::pair<uint32_t, uint32_t>(idx / M, idx % M);
             };
-            if constexpr (!COL)
+            if constexpr (!COL && PERM) {
+                // the transform's values leave the LDS first, then the
+                // permuted addend (first polynomial of an item) is staged there
+                uint64_t v[E];
+#pragma unroll
+                for (int k = 0; k < E; ++k) {
+                    const auto p = at2(k);
+                    v[k] = lds[lds_at<LOG_M, EB>(p.first, p.second)];
+                }
+                const bool has_p = bsel == 0 && ep.kappa != 0;
+                if (has_p) {
+                    __syncthreads();
+                    galois_tile_to_lds<LOG_M, EB>(ep.perm_src[poly >> 1] + ((size_t)row << log_n), blockIdx.x, log_n,
+                                                  ep.kappa, ep.kappa_inv, lds, false);
+                }
+                epi_store([&](int k) { const auto p = at2(k); return (uint32_t)gidx(p.first, p.second); },
+                          [&](int k) { return v[k]; }, std::true_type{},
+                          [&](int k) { const auto p = at2(k); return lds[lds_at<LOG_M, EB>(p.first, p.second)]; },
+                          has_p);
+            } else if constexpr (!COL) {
                 epi_store([&](int k) { const auto p = at2(k); return (uint32_t)gidx(p.first, p.second); },
                           [&](int k) { const auto p = at2(k); return lds[lds_at<LOG_M, EB>(p.first, p.second)]; },
-                          std::true_type{});
-            else
+                          std::true_type{}, [](int) { return 0ull; }, false);
+            } else {
                 epi_store([&](int k) { const auto p = at(k); return (uint32_t)gidx(p.first, p.second); },
                           [&](int k) { const auto p = at(k); return lds[lds_at<LOG_M, EB>(p.first, p.second)]; },
-                          std::false_type{});
+                          std::false_type{}, [](int) { return 0ull; }, false);
+            }
         } else if constexpr (!COL) {
             // adjacent element pairs of the row as 16-byte stores
 #pragma unroll
@@ -484,8 +558,21 @@ void launch_k(const PolyBatch& b, const DevTables& t, uint32_t log_n, uint32_t s
         // the epilogue reads acc and the addend and writes out beside the
         // transformed value: always through the coalesced staged store
         if (epi) {
-            hipLaunchKernelGGL((k_ntt_pass<LOG_M, EB, INV, COL, FINAL, true, true>), grid, dim3(4096 >> EB), 0, st, b,
-                               t.mods, tw, log_n, s0, first_pass, ep);
+            if (epi->kappa)
+                hipLaunchKernelGGL((k_ntt_pass<LOG_M, EB, INV, COL, FINAL, true, true, true>), grid, dim3(4096 >> EB),
+                                   0, st, b, t.mods, tw, log_n, s0, first_pass, ep);
+            else
+                hipLaunchKernelGGL((k_ntt_pass<LOG_M, EB, INV, COL, FINAL, true, true>), grid, dim3(4096 >> EB), 0, st,
+                                   b, t.mods, tw, log_n, s0, first_pass, ep);
+            return;
+        }
+    }
+    if constexpr (INV && !COL) {
+        // the first pass of an inverse transform reading its input through
+        // X -> X^kappa (staged through LDS on its input side)
+        if (epi && epi->kappa && first_pass) {
+            hipLaunchKernelGGL((k_ntt_pass<LOG_M, EB, INV, COL, FINAL, true, false, true>), grid, dim3(4096 >> EB), 0,
+                               st, b, t.mods, tw, log_n, s0, first_pass, ep);
             return;
         }
     }
@@ -517,7 +604,7 @@ void launch_pass(const PolyBatch& b, const DevTables& t, uint32_t log_n, uint32_
             if constexpr (!INV || LOG_M == 12)
                 launch_k<LOG_M, EB, INV, false, true>(b, t, log_n, s0, first_pass, stage, epi, st);
         } else {
-            if constexpr (INV) launch_k<LOG_M, EB, INV, false, false>(b, t, log_n, s0, first_pass, stage, nullptr, st);
+            if constexpr (INV) launch_k<LOG_M, EB, INV, false, false>(b, t, log_n, s0, first_pass, stage, epi, st);
         }
     };
     if (e8)
@@ -528,14 +615,17 @@ void launch_pass(const PolyBatch& b, const DevTables& t, uint32_t log_n, uint32_
         const double elems = (double)b.n_polys * b.n_limbs * (double)(1u << log_n);
         // read + write every residue once; N/2 butterflies per stage
         const bool fused = epi && !INV && final_pass && !col;
+        const bool perm = epi && epi->kappa && !col && (INV ? first_pass != 0 : fused);
         const uint32_t variant = 1u + (LOG_M | (col ? 32u : 0u) | (final_pass ? 64u : 0u) | (staged ? 128u : 0u) |
-                                       (e8 ? 256u : 0u) | (fused ? 512u : 0u));
+                                       (e8 ? 256u : 0u) | (fused ? 512u : 0u) | (perm ? 1024u : 0u));
         // the ModDown epilogue reads acc (and the addend) and writes out in
         // place of the transform's own store
         double extra = 0.0;  // addends: half of the rows (one polynomial) each
-        if (fused)
+        if (fused) {
             for (int bb = 0; bb < 2; ++bb)
                 extra += (epi->d_add[bb] != PFT_EPI_NO_ADD ? 4.0 : 0.0) + (epi->d_add2[bb] != PFT_EPI_NO_ADD ? 4.0 : 0.0);
+            if (perm) extra += 4.0;  // the permuted addend of the first polynomial
+        }
         const double bytes = fused ? elems * (24.0 + extra) : 16.0 * elems;
         g_prof->end(kid, bytes, 0.5 * elems * LOG_M, variant);
     }
@@ -732,6 +822,159 @@ __global__ __launch_bounds__(256) void k_rescale_col_b(WsRef ws, uint64_t off_la
     for (int e = 0; e < 16; ++e) orow[(size_t)e * S] = x[e];
 }
 
+// The key inner product of hybrid key switching fused with the last pass of
+// the forward transform of ModUp's rows.  Where the conversion kernel has
+// already applied the first pass (a radix-16 column pass), each extended row
+// needs one row pass of LOG_M = log_n - 4 stages over 4096-word tiles.  A
+// workgroup takes one tile of row t of one item and every digit j in turn:
+// x_j is d itself where t is one of digit j's own rows (d is in the NTT
+// domain already) or ext_j[t] taken through the row pass in registers; the
+// product with the key tile is accumulated, and only the two accumulator
+// tiles acc_b[t] = sum_j x_j key_{j,b}[t] (b = 0, 1) are written.  The
+// extended digits are read once instead of being written back by the row
+// pass and read again by a separate inner-product kernel.  The products are
+// taken in the arrangement the pass ends in (each thread holds E
+// consecutive words of its sub-problem), so d, the key and the accumulators
+// move as 16-byte accesses per lane and no LDS staging is needed.
+//
+// Block order: blocks are issued to the eight XCDs round-robin; block id
+// 8 k + x runs item k mod n of the (row, tile) pair 8 floor(k / n) + x, so
+// the items sharing one key tile run on one XCD at about the same time and
+// the tile comes from HBM about once per launch, then from that XCD's L2.
+//
+// FP (rows with q < 2^50, the key holding integer-valued doubles): x is
+// brought within q/2, each product formed by fmulmod against the quotient
+// w (1/q) (|term| < 0.9q, so the sum over at most 8 digits stays below
+// 2^53), the sums converted to canonical residues.  Otherwise x is brought
+// below q and Montgomery products with the key (stored times 2^64) are
+// added modulo q.  The rows of one kind form one launch (ri.row).
+template <int LOG_M, int EB, bool FP>
+__global__ __launch_bounds__(4096 >> EB) __attribute__((amdgpu_waves_per_eu(4)))
+void k_row_inner(RowInner ri, const DevMod* __restrict__ mods, const TwPair* __restrict__ tw, uint32_t log_n) {
+    constexpr int M = 1 << LOG_M;
+    constexpr int E = 1 << EB;
+    constexpr uint32_t NT = 4096 >> EB;
+    constexpr int T = M / E;
+    constexpr int C = NT / T;
+    constexpr int NPH = (LOG_M + EB - 1) / EB;
+    using PIN = Phase<LOG_M, 0, EB>;
+    using POUT = Phase<LOG_M, NPH - 1, EB>;
+    static_assert(PIN::WLO >= 4, "the row pass reads its input directly");
+    static_assert(POUT::WLO == 0, "each thread ends with E consecutive words");
+    __shared__ uint64_t lds[lds_words<LOG_M, EB>()];
+
+    const uint32_t bid = blockIdx.x;
+    const uint32_t kx = bid >> 3;
+    const uint32_t z = kx % ri.n_items;
+    const uint32_t pair = (kx / ri.n_items) * 8u + (bid & 7u);
+    if (pair >= ri.tiles * ri.n_rows) return;  // whole workgroup, before any barrier
+    const uint32_t tile = pair % ri.tiles;
+    const uint32_t t = ri.row[pair / ri.tiles];
+
+    const uint32_t tid = threadIdx.x;
+    const uint32_t mi = t < ri.level ? t : ri.L + (t - ri.level);
+    const DevMod md = mods[mi];
+    const uint64_t q = md.q, two_q = md.two_q;
+    const double qd = md.qd, qinv = md.qinv;
+    const TwPair* __restrict__ twt = tw + ((size_t)mi << log_n);
+    const uint32_t s0 = log_n - LOG_M;
+    const uint32_t sp0 = tile * (uint32_t)C;
+    const uint32_t c = C == 1 ? 0u : tid / T;
+    const uint32_t l = C == 1 ? tid : tid % T;
+    uint64_t* __restrict__ item = ri.base + (size_t)z * ri.stride;
+    // this thread's E consecutive words of the row: [w0, w0 + E)
+    const size_t w0 = ((size_t)(sp0 + c) << LOG_M) + (size_t)l * E;
+
+    auto load_vec = [&](const uint64_t* __restrict__ p, uint64_t (&v)[E]) {
+        const ulonglong2* __restrict__ pv = reinterpret_cast<const ulonglong2*>(p + w0);
+#pragma unroll
+        for (int e = 0; e < E / 2; ++e) {
+            const ulonglong2 u = pv[e];
+            v[2 * e] = u.x;
+            v[2 * e + 1] = u.y;
+        }
+    };
+    uint64_t acc0[E], acc1[E];  // FP: doubles; otherwise residues below q
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc0[e] = acc1[e] = 0;  // also the bits of +0.0
+    for (uint32_t j = 0; j < ri.beta; ++j) {
+        const uint32_t i0 = j * ri.alpha;
+        const bool own = t >= i0 && t < min(i0 + ri.alpha, ri.level);
+        uint64_t x[E];
+        if (own && ri.kappa) {
+            // d = X^kappa image of the input's row t: its tile staged in LDS
+            galois_tile_to_lds<LOG_M, EB>(ri.perm_src[z] + ((size_t)t << log_n), tile, log_n, ri.kappa, ri.kappa_inv,
+                                          lds, FP);
+#pragma unroll
+            for (int e = 0; e < E; ++e) x[e] = lds[lds_at<LOG_M, EB>(c, l * (uint32_t)E + (uint32_t)e)];
+            __syncthreads();  // the next digit's exchanges reuse the LDS
+        } else if (own) {
+            load_vec(item + ri.off_d + ((size_t)t << log_n), x);
+            if constexpr (FP) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) x[e] = fp_from_u64(x[e]);
+            }
+        } else {
+            const uint64_t* __restrict__ src = item + ri.off_ext + ((size_t)(j * ri.rows + t) << log_n);
+#pragma unroll
+            for (int e = 0; e < E; ++e) x[e] = src[((size_t)(sp0 + c) << LOG_M) | PIN::r_of(l, e)];
+            // the twiddles and their addresses are the same for every digit;
+            // opaque copies of their base and of the lane indices keep the
+            // compiler from holding all of them in registers across the
+            // digit loop (they are recomputed and reloaded per digit)
+            const TwPair* twj = twt;
+            uint32_t lj = l, cj = c;
+            asm volatile("" : "+v"(twj), "+v"(lj), "+v"(cj));
+            run_phases<LOG_M, EB, false, FP, false, 0>(x, lds, cj, lj, sp0 + c, s0, twj, md);
+            __syncthreads();  // the next digit's exchanges reuse the LDS
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                if constexpr (FP) {
+                    x[e] = as_u(freduce(as_f(x[e]), qd, qinv));
+                } else {
+                    const uint64_t v = x[e] >= two_q ? x[e] - two_q : x[e];
+                    x[e] = v >= q ? v - q : v;
+                }
+            }
+        }
+        uint64_t k0[E], k1[E];
+        load_vec(ri.key + ((size_t)((2 * j) * ri.krows + mi) << log_n), k0);
+        load_vec(ri.key + ((size_t)((2 * j + 1) * ri.krows + mi) << log_n), k1);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            if constexpr (FP) {
+#pragma clang fp contract(off)
+                const double xv = as_f(x[e]), a = as_f(k0[e]), b = as_f(k1[e]);
+                acc0[e] = as_u(as_f(acc0[e]) + fmulmod(xv, a, a * qinv, qd));
+                acc1[e] = as_u(as_f(acc1[e]) + fmulmod(xv, b, b * qinv, qd));
+            } else {
+                acc0[e] = add_mod(acc0[e], mont_redc(x[e] * k0[e], mulhi64(x[e], k0[e]), q, md.mont_neg_qinv), q);
+                acc1[e] = add_mod(acc1[e], mont_redc(x[e] * k1[e], mulhi64(x[e], k1[e]), q, md.mont_neg_qinv), q);
+            }
+        }
+    }
+    ulonglong2* __restrict__ o0 = reinterpret_cast<ulonglong2*>(item + ri.off_acc + ((size_t)t << log_n) + w0);
+    ulonglong2* __restrict__ o1 =
+        reinterpret_cast<ulonglong2*>(item + ri.off_acc + ((size_t)(ri.rows + t) << log_n) + w0);
+#pragma unroll
+    for (int e = 0; e < E / 2; ++e) {
+        ulonglong2 u, v;
+        if constexpr (FP) {
+            u.x = fp_to_u64(acc0[2 * e], qd, qinv);
+            u.y = fp_to_u64(acc0[2 * e + 1], qd, qinv);
+            v.x = fp_to_u64(acc1[2 * e], qd, qinv);
+            v.y = fp_to_u64(acc1[2 * e + 1], qd, qinv);
+        } else {
+            u.x = acc0[2 * e];
+            u.y = acc0[2 * e + 1];
+            v.x = acc1[2 * e];
+            v.y = acc1[2 * e + 1];
+        }
+        o0[e] = u;
+        o1[e] = v;
+    }
+}
+
 template <bool INV>
 void launch_radix(uint32_t radix, const PolyBatch& b, const DevTables& t, uint32_t log_n, uint32_t s0, bool fin,
                   bool stage, bool e8, const NttEpilogue* epi, hipStream_t st, ProfHook* prof) {
@@ -844,6 +1087,70 @@ void launch_rescale_col_b(uint32_t n, WsRef ws, uint64_t off_last, uint64_t off_
                        off_tmp, level, mode, t.mods, t.tw_fwd, log_n);
 }
 
+bool row_inner_supported(uint32_t log_n) {
+    const uint32_t r = log_n - 4;
+    return r == 8 || r == 9 || r == 10 || r == 12;
+}
+
+void launch_row_inner(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, uint64_t off_acc, const uint64_t* key,
+                      uint32_t level, const KsConsts& kc, const DevTables& t, const uint32_t* fp_rows,
+                      uint32_t log_n, const uint64_t* const* perm_src, uint64_t kappa, uint64_t kappa_inv,
+                      hipStream_t st) {
+    RowInner ri{};
+    if (kappa) {
+        for (uint32_t z = 0; z < n; ++z) ri.perm_src[z] = perm_src[z];
+        ri.kappa = kappa;
+        ri.kappa_inv = kappa_inv;
+    }
+    ri.base = ws.base;
+    ri.stride = ws.stride;
+    ri.off_d = off_d;
+    ri.off_ext = off_ext;
+    ri.off_acc = off_acc;
+    ri.key = key;
+    ri.n_items = n;
+    ri.level = level;
+    ri.rows = level + kc.K;
+    ri.alpha = kc.alpha;
+    ri.beta = (level + kc.alpha - 1) / kc.alpha;
+    ri.L = kc.L;
+    ri.krows = kc.L + kc.K;
+    ri.tiles = (1u << log_n) >> 12;
+    for (int fp = 1; fp >= 0; --fp) {
+        // the rows of one arithmetic kind, in chunks that fit the row list
+        std::vector<uint16_t> rows;
+        for (uint32_t r = 0; r < ri.rows; ++r) {
+            const uint32_t mi = r < level ? r : kc.L + (r - level);
+            if ((int)fp_rows[mi] == fp) rows.push_back((uint16_t)r);
+        }
+        for (size_t r0 = 0; r0 < rows.size(); r0 += PFT_ROW_LIST) {
+            ri.n_rows = (uint32_t)std::min<size_t>(PFT_ROW_LIST, rows.size() - r0);
+            for (uint32_t i = 0; i < ri.n_rows; ++i) ri.row[i] = rows[r0 + i];
+            const uint32_t pairs = ri.tiles * ri.n_rows;
+            const dim3 grid(8u * n * ((pairs + 7u) / 8u));
+            auto go = [&](auto lm, auto eb) {
+                constexpr int LM = decltype(lm)::value, EB = decltype(eb)::value;
+                if (fp)
+                    hipLaunchKernelGGL((k_row_inner<LM, EB, true>), grid, dim3(4096 >> EB), 0, st, ri, t.mods,
+                                       t.tw_fwd, log_n);
+                else
+                    hipLaunchKernelGGL((k_row_inner<LM, EB, false>), grid, dim3(4096 >> EB), 0, st, ri, t.mods,
+                                       t.tw_fwd, log_n);
+            };
+            // 8 residues per thread: with 16 the two accumulators and the
+            // pass's registers exceed what four waves per SIMD allow
+            auto by_eb = [&](auto lm) { go(lm, std::integral_constant<int, 3>{}); };
+            switch (log_n - 4) {
+                case 8: by_eb(std::integral_constant<int, 8>{}); break;
+                case 9: by_eb(std::integral_constant<int, 9>{}); break;
+                case 10: by_eb(std::integral_constant<int, 10>{}); break;
+                case 12: by_eb(std::integral_constant<int, 12>{}); break;
+                default: break;
+            }
+        }
+    }
+}
+
 void launch_ntt(const PolyBatch& b, const DevTables& t, uint32_t log_n, bool inverse, const NttSchedule& s,
                 hipStream_t st, ProfHook* prof, const NttEpilogue* epi, uint32_t first) {
     if (b.n_polys == 0 || b.n_limbs == 0 || s.n_passes == 0 || s.n_passes > 3) return;
@@ -861,7 +1168,9 @@ void launch_ntt(const PolyBatch& b, const DevTables& t, uint32_t log_n, bool inv
             launch_radix<false>(s.radix[p], b, t, log_n, s0[p], p + 1 == s.n_passes, stage, e8,
                                 p + 1 == s.n_passes ? epi : nullptr, st, prof);
     } else {
+        // epi of an inverse transform: X -> X^kappa folded into its first pass
         for (uint32_t p = s.n_passes; p-- > first;)
-            launch_radix<true>(s.radix[p], b, t, log_n, s0[p], p == 0, stage, e8, nullptr, st, prof);
+            launch_radix<true>(s.radix[p], b, t, log_n, s0[p], p == 0, stage, e8,
+                               p + 1 == s.n_passes && epi && epi->kappa ? epi : nullptr, st, prof);
     }
 }

@@ -58,11 +58,20 @@ struct NttEpilogue {
     const TwPair* pinv;                // [L]: P^-1 mod q_i (Shoup pairs)
     const TwPair* pinv_fp;             // [L]: the same as (w, w/q) doubles, used where q_i < 2^50
     uint32_t level;
+    // X -> X^kappa (kappa = 0: none) folded into a row pass: the first pass
+    // of an inverse transform reads row i of polynomial p from perm_src[p]
+    // + i N through the permutation; a forward epilogue adds, for the first
+    // polynomial of item z, row i of perm_src[z] through the permutation.
+    // kappa_inv = kappa^-1 mod 2N.
+    const uint64_t* perm_src[PFT_MAX_POLYS / 2];
+    uint64_t kappa, kappa_inv;
 };
 bool ntt_supported(uint32_t log_n);
 int ntt_candidates(uint32_t log_n, NttSchedule* out, int max_out);
 bool ntt_schedule_valid(uint32_t log_n, const NttSchedule& s);
-// epi (forward only): finish ModDown in the final pass instead of storing.
+// epi, forward: finish ModDown in the final pass instead of storing (and
+// add the permuted addend when epi->kappa is set); inverse: only
+// epi->kappa / perm_src are used, by the first pass.
 // first: a forward transform starts at pass `first` of the schedule (the
 // earlier passes already applied, e.g. by launch_modup_col_b); an inverse
 // transform stops before pass `first` (the remaining passes applied by the
@@ -87,6 +96,13 @@ enum EwOp : uint32_t {
 };
 void launch_ew(EwOp op, const SmallBatch& out, const SmallBatch& a, const SmallBatch* b, const SmallBatch* c,
                const DevTables& t, uint32_t log_n, hipStream_t st);
+// Switching-key storage form, in place on the rows of `rows` (plain residues
+// in): rows whose modulus is below 2^50 hold each residue as an
+// integer-valued double (the inner product's fp64 products read it
+// directly), the other rows residue * 2^64 mod m (Montgomery form: one REDC
+// per 128-bit sum of products).  to_mont: [L+K] Shoup pairs of 2^64 mod m.
+void launch_key_form(const SmallBatch& rows, const TwPair* to_mont, const DevTables& t, uint32_t log_n,
+                     hipStream_t st);
 // out = a * consts[limb] (Shoup pairs on the device)
 void launch_mul_const(const SmallBatch& out, const SmallBatch& a, const TwPair* consts, const DevTables& t,
                       uint32_t log_n, hipStream_t st);
@@ -157,6 +173,33 @@ void launch_moddown_col_b(uint32_t n, WsRef ws, uint64_t off_acc, uint64_t off_c
 // same way: tmp holds the output of the first transform pass.
 void launch_rescale_col_b(uint32_t n, WsRef ws, uint64_t off_last, uint64_t off_tmp, uint32_t level, uint32_t mode,
                           const DevTables& t, uint32_t log_n, hipStream_t st);
+// The key inner product fused with the remaining (row) pass of the forward
+// transform of ModUp's rows, for the items of a batch (ntt.hip): ext holds
+// the rows after the first pass of a (4, log_n - 4) schedule (as
+// launch_modup_col_b leaves them), d the NTT-domain input; writes
+// acc [2][level+K][N].  Needs row_inner_supported(log_n) and at most 8
+// digits; fp_rows[m] (host, by modulus index) is 1 where modulus m runs
+// fp64 arithmetic (one launch per kind).  kappa != 0: d is not read; its
+// own rows are the X -> X^kappa image of the rows of perm_src[z] (host
+// array of n device pointers, item z's input polynomial [level][N], NTT
+// domain), taken through the permutation as they are loaded.
+#define PFT_ROW_LIST 64
+struct RowInner {
+    uint64_t* base;  // item z's workspace at base + z stride
+    uint64_t stride;
+    uint64_t off_d, off_ext, off_acc;
+    const uint64_t* key;  // [dnum][2][L+K][N] in the storage form of launch_key_form
+    uint32_t n_items, level, rows, alpha, beta, L, krows, tiles;
+    uint32_t n_rows;              // rows of this launch
+    uint16_t row[PFT_ROW_LIST];   // their indices (0..level+K-1)
+    const uint64_t* perm_src[PFT_MAX_ITEMS];
+    uint64_t kappa, kappa_inv;
+};
+bool row_inner_supported(uint32_t log_n);
+void launch_row_inner(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, uint64_t off_acc, const uint64_t* key,
+                      uint32_t level, const KsConsts& kc, const DevTables& t, const uint32_t* fp_rows,
+                      uint32_t log_n, const uint64_t* const* perm_src, uint64_t kappa, uint64_t kappa_inv,
+                      hipStream_t st);
 // acc [2][level+K][N] = sum_j x_j * key_j  (key: [dnum][2][L+K][N], Montgomery form)
 void launch_key_inner_b(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, uint64_t off_acc, const uint64_t* key,
                         uint32_t level, const KsConsts& kc, const DevTables& t, uint32_t log_n, hipStream_t st);

@@ -1,8 +1,8 @@
 // sampler.hip -- seeded draws of KEYGEN and ENC on the device.
 //
-// SETUP (Sec. 3, the CKKS description) draws the secret from X_key (ternary
+// SETUP (Sec. 3.4, the CKKS description) draws the secret from X_key (ternary
 // coefficients here), masks uniformly from R_q and errors from the
-// zero-centred discrete Gaussian X_err, sigma = 3.2 (Sec. 5, parameter
+// zero-centred discrete Gaussian X_err, sigma = 3.2 (Sec. 6.4, CKKS parameter
 // selection).  The seeded entry points take every draw from a counter-based
 // generator so that a seed fixes the keys and ciphertexts on any device and
 // in any launch order.

@@ -88,23 +88,26 @@ def test_fused_modup_relin_and_rotation(name, flags):
         w.ctx.ntt_set_schedule(False, None)
 
 
-def test_fused_modup_batch_equals_unfused():
-    """Three items in one launch (grid z = 3): fused and unfused paths
-    produce the same ciphertexts, and both match the oracle."""
-    w = world("a6_n12")
+@pytest.mark.parametrize("name", ["a6_n12", "a2_n14"])
+def test_fused_modup_batch_equals_unfused(name):
+    """Three items in one launch: the key inner product fused with the row
+    pass of ModUp's rows, the fused passes alone and the unfused path
+    produce the same ciphertexts, and all match the oracle."""
+    w = world(name)
     sched = [c for c in w.col16 if c[1] == 0][0]
     w.ctx.ntt_set_schedule(False, sched)
-    level = w.op.L - 1  # a ragged last digit (11 = 6 + 5)
+    level = w.op.L - 1  # a ragged last digit
     pairs = [(w.enc_pair(70 + i, level), w.enc_pair(80 + i, level)) for i in range(3)]
     try:
         outs = {}
-        for fused in (True, False):
-            w.ctx.bconv_mode(True, fused=fused)
-            outs[fused] = [w.ctx.export(g) for g in
-                           w.ctx.mul_relin_batch([p[0][0] for p in pairs], [p[1][0] for p in pairs])]
-        for a, b in zip(outs[True], outs[False]):
-            assert np.array_equal(a, b)
-        for ((_, oa), (_, ob)), host in zip(pairs, outs[True]):
+        for mode in ((True, True), (True, False), (False, False)):
+            w.ctx.bconv_mode(True, fused=mode[0], inner=mode[1])
+            outs[mode] = [w.ctx.export(g) for g in
+                          w.ctx.mul_relin_batch([p[0][0] for p in pairs], [p[1][0] for p in pairs])]
+        for mode in ((True, False), (False, False)):
+            for a, b in zip(outs[(True, True)], outs[mode]):
+                assert np.array_equal(a, b)
+        for ((_, oa), (_, ob)), host in zip(pairs, outs[(True, True)]):
             o = C.hmul_relin(w.op, oa, ob, w.rlk)
             assert np.array_equal(host[0], o.c0) and np.array_equal(host[1], o.c1)
     finally:

@@ -160,3 +160,27 @@ def test_seeded_large_ring():
     o = C.rescale(w.op, C.hmul_relin(w.op, oa, ob, w.rlk))
     w.assert_same(g, o)
     w.assert_same(w.ctx.rotate(g, 1), C.rotate(w.op, o, 1, w.rot[1]))
+
+
+def test_new_secret_drops_every_derived_key():
+    """A key of an earlier secret never stays usable: after keygen with
+    steps [1, 3] and then keygen with [3] alone, step 1 has no key; after
+    pft_set_secret the public, relinearisation and rotation keys are all
+    missing until generated again."""
+    import torch
+    from paper_1908_06972_amd.native import PFT_ENOKEY, PftError
+    assert torch.cuda.is_available()
+    w = World(SMALL, 11, [1, 3])
+    g, _ = w.enc_pair(9, 409, w.op.L)
+    w.ctx.rotate(g, 1)
+    w.ctx.keygen(12, [3])
+    with pytest.raises(PftError) as ei:
+        w.ctx.rotate(g, 1)
+    assert ei.value.code == PFT_ENOKEY
+    w.ctx.rotate(g, 3)
+    w.ctx.set_secret(SP.secret(13, w.n))
+    for call in (lambda: w.ctx.rotate(g, 3), lambda: w.ctx.mul_relin(g, g),
+                 lambda: w.ctx.encrypt_seeded(S.plaintext_coeffs(S.rng(1), w.n, 2 ** 20), w.op.L, w.op.scale, 5)):
+        with pytest.raises(PftError) as ei:
+            call()
+        assert ei.value.code == PFT_ENOKEY
