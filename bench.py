@@ -242,9 +242,113 @@ def summarize(trace_dir, fetch_dir, write_dir, kernel, kid, commands, n_top=6):
             fmt(rec["valu_insts_per_launch"], "%.4g")))
         recs.append(rec)
     out.append("")
+    # every kernel of the profiled steps: counted traffic per step
+    def step_total(dirpath, counter):
+        rows = _step_dispatches(_csv_rows(_find(dirpath, "counter_collection.csv")), "Dispatch_Id", "Start_Timestamp")
+        tensors = {int(r["Dispatch_Id"]) for r in rows if "k_tensor_b" in r["Kernel_Name"]}
+        steps = len(tensors) / float(CHAIN_DEPTH)
+        tot = sum(float(r["Counter_Value"]) for r in rows if r.get("Counter_Name") == counter)
+        return tot, steps
+    f_tot, f_steps = step_total(fetch_dir, "FETCH_SIZE")
+    w_tot, w_steps = step_total(write_dir, "WRITE_SIZE")
+    f_factor = recs[0]["fetch_calibration"] if recs else None
+    w_factor = recs[0]["write_calibration"] if recs else None
+    if f_steps and w_steps and f_factor and w_factor:
+        step_rec = {"source_sha256": source_sha(), "steps_profiled": f_steps,
+                    "fetch_bytes_per_step": 1024.0 * f_tot * f_factor / f_steps,
+                    "write_bytes_per_step": 1024.0 * w_tot * w_factor / w_steps}
+        step_rec["traffic_bytes_per_step"] = step_rec["fetch_bytes_per_step"] + step_rec["write_bytes_per_step"]
+        out.append("Every kernel of the profiled steps together (calibrated as above): %.2f GB fetched and %.2f GB "
+                   "written per step, %.2f GB in all." % (step_rec["fetch_bytes_per_step"] / 1e9,
+                                                          step_rec["write_bytes_per_step"] / 1e9,
+                                                          step_rec["traffic_bytes_per_step"] / 1e9))
+        out.append("")
+        recs.append(None)
     for rec in recs:
-        out.append("pft-profile: " + json.dumps(rec))
+        if rec is None:
+            out.append("pft-step: " + json.dumps(step_rec))
+        else:
+            out.append("pft-profile: " + json.dumps(rec))
     return "\n".join(out) + "\n"
+
+
+def stored_step():
+    """Counted traffic per job step recorded under profiles/ (a `pft-step:`
+    line), if taken on the current kernel source."""
+    if not os.path.isdir(PROFILE_DIR):
+        return None
+    sha = source_sha()
+    for f in sorted(os.listdir(PROFILE_DIR)):
+        if not f.endswith(".md"):
+            continue
+        for line in open(os.path.join(PROFILE_DIR, f)):
+            if line.startswith("pft-step: "):
+                rec = json.loads(line[len("pft-step: "):])
+                if rec.get("source_sha256") == sha:
+                    return rec
+    return None
+
+
+def ct_bytes(level, n):
+    """One ciphertext at `level`: 2 polynomials x level limbs x N residues x 8 bytes."""
+    return 2 * level * n * 8
+
+
+def key_bytes(lp, level):
+    """The part of one switching key a key switch at `level` reads: beta
+    digits x (b, a) x (level + K) rows."""
+    beta = -(-level // lp.alpha)
+    return 2 * beta * (level + lp.K) * lp.n * 8
+
+
+def op_alg_bytes(lp, batch):
+    """Algorithmic HBM bytes of one operation at the top level L: its
+    operands read and its result written once, 8 bytes per residue; the
+    switching key once per batch (every ciphertext of a batch uses it).
+    HMult+relin reads two operand ciphertexts."""
+    L, n = lp.L, lp.n
+    return {"hmult_relin": 3 * ct_bytes(L, n) + key_bytes(lp, L) / batch,
+            "rotate": 2 * ct_bytes(L, n) + key_bytes(lp, L) / batch,
+            "rescale": ct_bytes(L, n) + ct_bytes(L - 1, n),
+            "poly_ntt": ct_bytes(L, n)}  # one L-limb polynomial read and written: 2 L N 8 bytes
+
+
+def step_alg_bytes(lp, batch):
+    """Algorithmic HBM bytes of one job step over the batch: for each of the
+    CHAIN_DEPTH links (levels L .. L - CHAIN_DEPTH + 1) an HMult+relin (two
+    operands read, the product written, the key once) and a RESCALE (read,
+    write), then the rotate-and-sum: per rotation the running sum read and
+    written once (the addition folds into the rotation's last kernel) and
+    the rotation key once."""
+    n, tot = lp.n, 0
+    for lvl in range(lp.L, lp.L - CHAIN_DEPTH, -1):
+        tot += 3 * ct_bytes(lvl, n) * batch + key_bytes(lp, lvl)
+        tot += (ct_bytes(lvl, n) + ct_bytes(lvl - 1, n)) * batch
+    lvl = lp.L - CHAIN_DEPTH
+    rotations = ROT_SLOTS.bit_length() - 1
+    tot += rotations * (2 * ct_bytes(lvl, n) * batch + key_bytes(lp, lvl))
+    return tot
+
+
+def copy_bandwidth(gib=2, reps=5):
+    """Device-to-device copy rate (read + write bytes per second) of a
+    torch tensor copy of `gib` GiB: the practical HBM ceiling beside the
+    published peak."""
+    import torch
+    n = (gib << 30) // 8
+    a = torch.zeros(n, dtype=torch.int64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2.0 * n * 8 / (ms * 1e-3) / 1e9
 
 
 def parse():
@@ -254,6 +358,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-baseline-full", action="store_true",
+                    help="print the oracle's full CPU table (JSON) on this host and exit (no GPU needed)")
+    ap.add_argument("--reps", type=int, default=10, help="runs per median of the CPU baseline")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="run only this many untimed steps (for rocprofv3) and exit")
     ap.add_argument("--no-breakdown", action="store_true", help="skip the per-operation loops")
@@ -610,58 +717,188 @@ def timed(fn, reps, sync):
     return (time.perf_counter() - t) / reps
 
 
-def cpu_baseline():
-    """The oracle (never tuned) on a bounded sample of the same job: two
-    HMult+relin, two RESCALE and two ROTATE of one N = 2^16, L = 24
-    ciphertext, extrapolated to the job's operation counts."""
+def host_cpu():
+    """(logical CPUs, model name, OpenMP threads the oracle uses) of this host."""
+    import subprocess
+    nproc = os.cpu_count() or 1
+    model = None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return nproc, model, int(os.environ.get("OMP_NUM_THREADS", nproc))
+
+
+def median_seconds(fn, reps):
+    """Median wall time of reps calls of fn."""
+    import statistics
+    ts = []
+    for _ in range(reps):
+        t = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t)
+    return statistics.median(ts)
+
+
+class OracleWorld:
+    """The oracle's keys and one encrypted input for a parameter set (from the
+    shared seeded draws), for timing."""
+
+    def __init__(self, cfg_name, rot_steps=(1,)):
+        import synth as S
+        from oracle import ckks as C
+        self.C = C
+        self.P = P = C.Params.from_config(S.CONFIGS[cfg_name])
+        n = P.n
+        C.set_mul_mode(0 if n <= 4096 else 1)  # schoolbook at N = 4096, the oracle's transform above
+        kd = S.key_draws(1, n, P.q)
+        self.pk = C.public_key(P, kd.s, kd.pk_a, kd.pk_e)
+        a, e = S.switch_key_draws(1, 0, n, P.key_moduli(), P.dnum)
+        self.rlk = C.relin_key(P, kd.s, a, e)
+        self.rot = {}
+        for st in rot_steps:
+            a, e = S.switch_key_draws(1, 1000 + st, n, P.key_moduli(), P.dnum)
+            self.rot[st] = C.rotation_key(P, kd.s, st, a, e)
+        d = S.enc_draws(3000, n)
+        self.ct = C.encrypt(P, self.pk, S.plaintext_coeffs(S.rng(5), n, int(P.scale)), P.L, d.v, d.e0, d.e1, P.scale)
+
+    def hmult(self):
+        return self.C.hmul_relin(self.P, self.ct, self.ct, self.rlk)
+
+    def rescale(self):
+        return self.C.rescale(self.P, self.ct)
+
+    def rotate_add(self):
+        return self.C.hadd(self.P, self.ct, self.C.rotate(self.P, self.ct, 1, self.rot[1]))
+
+
+def limb_ntt_seconds(reps, threads):
+    """Median seconds of the oracle's transform of one N = 2^16 limb, and of
+    a 24-limb polynomial spread over `threads` host threads."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import numpy as np
 
     import synth as S
+    from oracle import _ring
     from oracle import ckks as C
+    P = C.Params.from_config(S.CONFIGS["C3"])
+    lib = _ring.lib()
+    g = S.rng(9)
+    rows = [_ring.u64(g.integers(0, q, P.n, dtype=np.uint64)) for q in P.q]
+    outs = [np.empty(P.n, dtype=np.uint64) for _ in P.q]
 
-    cfg = S.CONFIGS["C3"]
-    P = C.Params.from_config(cfg)
-    C.set_mul_mode(1)
-    n = P.n
-    kd = S.key_draws(1, n, P.q)
-    pk = C.public_key(P, kd.s, kd.pk_a, kd.pk_e)
-    a, e = S.switch_key_draws(1, 0, n, P.key_moduli(), P.dnum)
-    rlk = C.relin_key(P, kd.s, a, e)
-    a, e = S.switch_key_draws(1, 1001, n, P.key_moduli(), P.dnum)
-    rk = C.rotation_key(P, kd.s, 1, a, e)
-    m = S.plaintext_coeffs(S.rng(5), n, 2 ** 50)
-    d = S.enc_draws(3000, n)
-    ct = C.encrypt(P, pk, m, P.L, d.v, d.e0, d.e1, P.scale)
-    th = tr = tt = 0.0
-    for _ in range(2):
-        t = time.perf_counter()
-        pr = C.hmul_relin(P, ct, ct, rlk)
-        th += time.perf_counter() - t
-        t = time.perf_counter()
-        ct = C.rescale(P, pr)
-        tr += time.perf_counter() - t
-        t = time.perf_counter()
-        rot = C.rotate(P, ct, 1, rk)
-        C.hadd(P, ct, rot)
-        tt += time.perf_counter() - t
-    th, tr, tt = th / 2, tr / 2, tt / 2
+    def one(i):
+        lib.or_ntt_fast(_ring.ptr(rows[i]), _ring.ptr(outs[i]), P.n, int(P.q[i]), int(P.psi[int(P.q[i])]))
+
+    limb = median_seconds(lambda: one(1), reps)
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        poly = median_seconds(lambda: list(ex.map(one, range(P.L))), reps)
+    return limb, poly
+
+
+def cpu_baseline(reps=10):
+    """The oracle (never tuned) on a bounded sample of the same job, on this
+    host's cores: medians of `reps` runs of one HMult+relin, one RESCALE and
+    one ROTATE+HADD of one N = 2^16, L = 24 ciphertext (OpenMP over limbs),
+    combined into the job's rate; the oracle's one-limb transform beside it."""
+    nproc, model, threads = host_cpu()
+    w = OracleWorld("C3")
+    th = median_seconds(w.hmult, reps)
+    tr = median_seconds(w.rescale, reps)
+    tt = median_seconds(w.rotate_add, reps)
+    limb, poly = limb_ntt_seconds(reps, threads)
     per_ct = CHAIN_DEPTH * (th + tr) + 15 * tt
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {
         "value": CHAIN_DEPTH / per_ct,
         "unit": "HMult+relin/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": "2 HMult+relin, 2 RESCALE, 2 ROTATE+HADD of one N=2^16 L=24 ciphertext (oracle, %d OpenMP "
-                  "threads); whole-job rate = 8 / (8 (t_hmult + t_rescale) + 15 t_rotate_add) with t_hmult=%.3fs "
-                  "t_rescale=%.3fs t_rotate_add=%.3fs" % (threads, th, tr, tt),
+        "nproc": nproc,
+        "cpu_model": model,
+        "sample": "medians of %d runs each of one HMult+relin, one RESCALE and one ROTATE+HADD of one N=2^16 L=24 "
+                  "ciphertext (oracle, %d OpenMP threads); whole-job rate = 8 / (8 (t_hmult + t_rescale) + 15 "
+                  "t_rotate_add) with t_hmult=%.3fs t_rescale=%.3fs t_rotate_add=%.3fs" % (reps, threads, th, tr, tt),
+        "limb_ntt_per_s_1thread": round(1.0 / limb, 2),
+        "poly_ntt_per_s": round(1.0 / poly, 3),
     }
+
+
+def cpu_baseline_full(reps=10):
+    """The full CPU table of the oracle on this host (run once, stored under
+    profiles/): limb and 24-limb transforms, the single-op workload (N = 4096,
+    schoolbook products) and the large-ring operations, medians of `reps`
+    runs on all threads and on one thread (a child process with
+    OMP_NUM_THREADS=1), and one bag-of-words inference (N = 2^15, 16 limbs,
+    vocabulary 32768, 64 -> 8)."""
+    import subprocess
+    nproc, model, threads = host_cpu()
+    res = {"nproc": nproc, "cpu_model": model, "threads": threads, "reps": reps}
+    if threads > 1:
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        out = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-full", "--reps",
+                              str(reps)], env=env, capture_output=True, text=True, check=True).stdout
+        res["one_thread"] = json.loads(out.strip().splitlines()[-1])
+    limb, poly = limb_ntt_seconds(reps, threads)
+    res["limb_ntt_s"], res["poly_ntt_s"] = limb, poly
+    for name in ("C1", "C3"):
+        w = OracleWorld(name)
+        r = reps if name == "C1" or threads > 1 else max(3, reps // 3)
+        res[name] = {"hmult_relin_s": median_seconds(w.hmult, r), "rescale_s": median_seconds(w.rescale, r),
+                     "rotate_add_s": median_seconds(w.rotate_add, r), "runs": r}
+    if threads > 1:
+        res["C4_inference_s"] = oracle_inference_seconds()
+    return res
+
+
+def oracle_inference_seconds():
+    """One encrypted bag-of-words inference on the oracle at the bag-of-words
+    shapes (stage 1, 1/w, stage 2 with BSGS PtMatVec; the diagonals encoded by
+    the oracle's encoder), wall seconds of one run."""
+    import numpy as np
+
+    import synth as S
+    from oracle import ckks as C
+    from oracle import ptmatvec as PM
+    P = C.Params.from_config(S.CONFIGS["C4"])
+    C.set_mul_mode(1)
+    n, t, L = P.n, P.n // 2, P.L
+    kd = S.key_draws(1, n, P.q)
+    pk = C.public_key(P, kd.s, kd.pk_a, kd.pk_e)
+    steps = sorted(set(PM.rotation_steps(64, t, 2) + PM.rotation_steps(8, 64, 1)))
+    keys = {}
+    for st in steps:
+        a, e = S.switch_key_draws(1, 1000 + st, n, P.key_moduli(), P.dnum)
+        keys[st] = C.rotation_key(P, kd.s, st, a, e)
+    H, O = S.bow_weights(404, 2 * t, 64, 8)
+    s1, s2 = float(P.q[L - 1]), float(P.q[L - 3])
+    p1 = [[[C.encode(d, n, s1) for d in g] for g in c] for c in PM.prerotated_diagonals(H.T, 64, t, 2, t)]
+    p2 = [[[C.encode(d, n, s2) for d in g] for g in c] for c in PM.prerotated_diagonals(O.T, 8, 64, 1, t)]
+    counts, words = S.bow_documents(405, 1, 2 * t)
+    cts = []
+    for c in range(2):
+        d = S.enc_draws(4500 + c, n)
+        cts.append(C.encrypt(P, pk, C.encode(counts[0][c * t:(c + 1) * t].astype(np.float64), n, P.scale), L,
+                             d.v, d.e0, d.e1, P.scale))
+    t0 = time.perf_counter()
+    o = C.rescale(P, PM.ptmatvec(P, cts, p1, 64, t, keys, s1))
+    m, ms = PM.constant_plain(P, 1.0 / float(words[0]), o.level)
+    o = C.rescale(P, C.hmul_plain(P, o, m, ms))
+    C.rescale(P, PM.ptmatvec(P, [o], p2, 8, 64, keys, s2))
+    return time.perf_counter() - t0
 
 
 def main():
     args = parse()
     if args.summarize:
         print(summarize(*args.summarize, args.kernel, args.family, args.commands), end="")
+        return
+    if args.cpu_baseline_full:
+        print(json.dumps(cpu_baseline_full(args.reps)), flush=True)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path (requests would be sharded "
@@ -796,9 +1033,11 @@ def main():
             # one wave-level VALU instruction = 64 lane-ops; peak issue is one
             # wave instruction per CU per clock (4 SIMDs x 16 lanes)
             lane_ops = stored["valu_insts_per_launch"] * 64.0
-            alu = {"achieved_gops": round(lane_ops / (avg_ms * 1e-3) / 1e9, 1), "peak_gops": ALU_PEAK_GOPS,
+            alu = {"achieved": round(lane_ops / (avg_ms * 1e-3) / 1e9, 1), "peak": ALU_PEAK_GOPS,
+                   "unit": "G lane-op/s",
                    "frac": round(lane_ops / (avg_ms * 1e-3) / 1e9 / ALU_PEAK_GOPS, 4),
                    "source": "SQ_INSTS_VALU per launch from profiles/ over this launch time"}
+    hbm_frac = gbs / HBM_PEAK_GBS
     roofline = {
         "kernel": kname,
         "family": FAMILIES[dom],
@@ -806,17 +1045,45 @@ def main():
         "achieved": round(gbs, 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
-        "frac": round(gbs / HBM_PEAK_GBS, 4),
+        "frac": round(hbm_frac, 4),
         "traffic": traffic,
         "avg_launch_us": round(1000.0 * avg_ms, 2),
         "launches": d_cnt,
         "alg_bytes_per_launch": d_bytes / max(d_cnt, 1),
-        "alg_butterflies_per_launch": d_ops / max(d_cnt, 1),
+        "alg_ops_per_launch": d_ops / max(d_cnt, 1),
+        "alg_bytes_note": "method bytes: operands read and results written once, 8 B per residue; words a "
+                          "transform leaves between its passes are layout cost and not counted",
         "family_share_of_step": round(totals[dom][0] / step_total, 3) if step_total else None,
         "kernel_share_of_family": round(d_ms / dom_ms, 3) if dom_ms else None,
+        "hbm": {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(hbm_frac, 4)},
         "alu": alu,
         "top_kernels": top_kernels,
     }
+    if alu and alu["frac"] > hbm_frac:
+        # the kernel is further along its integer-ALU roof than its HBM roof
+        roofline.update({"bound": "alu", "achieved": alu["achieved"], "peak": alu["peak"], "unit": alu["unit"],
+                         "frac": alu["frac"]})
+    # whole operations and the whole step against the HBM peak
+    copy_gbs = copy_bandwidth()
+    ops = op_alg_bytes(lp, args.batch)
+    operations = None
+    if breakdown:
+        rates = {"hmult_relin": breakdown["hmult_relin_per_s"], "rotate": breakdown["rotate_per_s"],
+                 "rescale": breakdown["rescale_per_s"], "poly_ntt": breakdown["ntt_per_s"]}
+        operations = {k: {"rate_per_s": round(rates[k], 2), "alg_bytes": ops[k],
+                          "achieved_gbs": round(rates[k] * ops[k] / 1e9, 1),
+                          "frac": round(rates[k] * ops[k] / 1e9 / HBM_PEAK_GBS, 4)} for k in rates}
+    sb = step_alg_bytes(lp, args.batch)
+    st_rec = stored_step()
+    step = {"alg_bytes": sb, "achieved_gbs": round(sb / (ms_per_step * 1e-3) / 1e9, 1),
+            "frac": round(sb / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "counted_bytes": st_rec["traffic_bytes_per_step"] if st_rec else None,
+            "counted_over_alg": round(st_rec["traffic_bytes_per_step"] / sb, 3) if st_rec else None}
+    roofline["operations"] = operations
+    roofline["step"] = step
+    roofline["copy_gbs"] = round(copy_gbs, 1)
+    log("roofline: %s %.1f GB/s method (%.3f of HBM); step %.1f GB/s (%.4f); copy %.0f GB/s" % (
+        kname, gbs, hbm_frac, step["achieved_gbs"], step["frac"], copy_gbs))
 
     tuning = save_tuning()
     serving = None

@@ -56,8 +56,11 @@ typedef struct pft_ctx pft_ctx;       /* opaque, owns device tables and keys */
 /* SETUP (Sec. 3.4; parameter guidance Sec. 6.4).  Primes are the largest
  * primes = 1 mod 2N of the given bit sizes: q_0 has q0_bits bits, q_1..q_{L-1}
  * the next L-1 largest with q_bits bits (descending), the K special primes
- * the largest unused with p_bits bits.  All bit sizes must be <= 60.
- * 10 <= log_n <= 16, 1 <= dnum <= n_q, n_p >= 1. */
+ * the largest unused with p_bits bits.  Bit sizes must be in 20..60.
+ * 12 <= log_n <= 16, 1 <= n_q <= 64, 1 <= n_p <= 12, 1 <= dnum <= n_q,
+ * alpha = ceil(n_q / dnum) <= 12.  rescale_mode: the mode RESCALE uses when
+ * called with PFT_RESCALE_DEFAULT (0 rounds, the RESCALE of Sec. 3.4; 1
+ * floors, Alg. 3 as printed).  PFT_EPARAM otherwise. */
 typedef struct pft_param_spec {
     uint32_t log_n;
     uint32_t n_q;     /* L */
@@ -66,12 +69,33 @@ typedef struct pft_param_spec {
     uint32_t n_p;     /* K */
     uint32_t p_bits;
     uint32_t dnum;    /* digits of hybrid key switching, alpha = ceil(L/dnum) */
-    uint32_t reserved;
+    uint32_t rescale_mode;
     double scale;     /* default encoding scale Delta */
 } pft_param_spec;
 
 int pft_params_create(const pft_param_spec* spec, pft_params** out);
+/* SETUP with the caller's prime chain (the moduli of Sec. 3.4 given
+ * explicitly): q: host [n_q], the ciphertext primes, strictly descending
+ * (RESCALE drops the last and smallest, Sec. 5.1); p: host [n_p], the
+ * special primes.  Every modulus must be prime, = 1 mod 2N, in (2^20, 2^60)
+ * and distinct from every other; PFT_EPARAM names the first that is not
+ * (nothing is created).  Other fields and limits as pft_param_spec; the
+ * arrays are copied. */
+typedef struct pft_param_primes {
+    uint32_t log_n;
+    uint32_t n_q;
+    const uint64_t* q;
+    const uint64_t* p;
+    uint32_t n_p;
+    uint32_t dnum;
+    uint32_t rescale_mode;
+    uint32_t reserved;
+    double scale;
+} pft_param_primes;
+int pft_params_create_primes(const pft_param_primes* spec, pft_params** out);
 void pft_params_destroy(pft_params* params);
+/* The parameter set's rescale_mode (host, *mode receives 0 or 1). */
+int pft_params_rescale_mode(const pft_params* params, uint32_t* mode);
 /* Copies q_0..q_{L-1} and p_0..p_{K-1} (host arrays of L and K entries). */
 int pft_params_moduli(const pft_params* params, uint64_t* q, uint64_t* p);
 /* N, L, K, dnum, alpha in that order (host array of 5). */
@@ -83,6 +107,31 @@ const char* pft_last_error(void);
 int pft_ctx_create(const pft_params* params, int device, void* hip_stream, pft_ctx** out);
 void pft_ctx_destroy(pft_ctx* ctx);
 int pft_ctx_synchronize(pft_ctx* ctx);
+
+/* Device memory of the library's own buffers (tables, keys, plaintext
+ * matrices, per-operation scratch; never the caller's ciphertexts).
+ * alloc/free: the caller's allocator (e.g. a framework's caching allocator),
+ * both or neither (NULL: hipMalloc/hipFree); alloc(user, bytes, device)
+ * returns device memory aligned to 256 bytes or NULL, free(user, ptr) takes
+ * back what alloc returned; both are called on the host thread that calls
+ * the library.  budget_bytes (0: none): an allocation that would take the
+ * context's live bytes past it fails with PFT_ENOMEM, and so does the call
+ * that needed it (an admission controller can size work by this).
+ * pft_ctx_create_alloc: pft_ctx_create with that allocator and budget (NULL:
+ * defaults); PFT_ENOMEM if the parameter set's tables already exceed it.
+ * pft_ctx_set_budget changes the budget later (PFT_ENOMEM, unchanged, if the
+ * context already holds more).  pft_ctx_memory writes {bytes of tables and
+ * keys, bytes of scratch and other buffers, budget} to out[3]. */
+typedef struct pft_allocator {
+    void* (*alloc)(void* user, uint64_t bytes, int device);
+    void (*free)(void* user, void* ptr);
+    void* user;
+    uint64_t budget_bytes;
+} pft_allocator;
+int pft_ctx_create_alloc(const pft_params* params, int device, void* hip_stream, const pft_allocator* alloc,
+                         pft_ctx** out);
+int pft_ctx_set_budget(pft_ctx* ctx, uint64_t budget_bytes);
+int pft_ctx_memory(const pft_ctx* ctx, uint64_t* out);
 
 /* ---- ciphertexts ------------------------------------------------------- */
 typedef struct pft_ct {
@@ -194,9 +243,11 @@ int pft_mul_relin(pft_ctx* ctx, const pft_ct* a, const pft_ct* b, pft_ct* out);
 int pft_mul_relin_batch(pft_ctx* ctx, uint32_t n, const pft_ct* a, const pft_ct* b, pft_ct* out);
 /* RESCALE by q_{level-1} (Sec. 5.1, Eq. (1) and Alg. 3).  mode 0 rounds
  * (adds (q-1)/2 before the exact division, the RESCALE of Sec. 3.4), mode 1
- * floors (Alg. 3 as printed).  out->data needs 2*(level-1)*N uint64 and must
+ * floors (Alg. 3 as printed), PFT_RESCALE_DEFAULT takes the parameter set's
+ * rescale_mode.  out->data needs 2*(level-1)*N uint64 and must
  * not alias in.  (Where the forward schedule starts with a radix-16 column
  * pass, the expansion of the last limb applies that pass itself.) */
+#define PFT_RESCALE_DEFAULT 2u
 int pft_rescale(pft_ctx* ctx, const pft_ct* in, uint32_t mode, pft_ct* out);
 int pft_rescale_batch(pft_ctx* ctx, uint32_t n, const pft_ct* in, uint32_t mode, pft_ct* out);
 /* Keep limbs 0..level-1 (exact).  out may alias in. */
@@ -423,6 +474,27 @@ int pft_exec_batch(pft_ctx* ctx, pft_ct* cts, uint32_t n_cts, const pft_op* ops,
  * error pft_exec_batch would return for the list. */
 int pft_exec_plan(const pft_op* ops, uint32_t n_ops, const uint32_t* levels, uint32_t n_cts, uint32_t* wave,
                   uint32_t* group);
+/* The plan of PtMatVec (Sec. 4.1) as an op list another implementation can
+ * replay: the operations pft_ptmatvec applies to one document, in its order,
+ * over a register file of ciphertexts.  Registers 0..n_in-1 hold the inputs
+ * v_c; the baby-step rotations of input c by r go to n_in + c (b - 1) + r - 1;
+ * then come the registers PROD, ACC, TMP and TOT (next four indices), the
+ * result is TOT (the out of the last op).  Kinds:
+ *   PFT_OP_ROTATE     R[out] = ROTATE(R[a], step)
+ *   PFT_OP_MUL_PLAIN  R[out] = HMULPLAIN(R[a], P_b), P_b the pre-rotated
+ *                     diagonal b of the [n_in][G][b] layout above
+ *   PFT_OP_ADD        R[out] = R[a] + R[b]
+ * (the plan's own kinds: pft_exec_batch does not take PFT_OP_MUL_PLAIN).
+ * pft_ptmat_plan: for the shape alone (host only; PFT_EINVAL unless n_o and
+ * n_i are powers of two with n_o <= n_i and 1 <= n_in <= 4096).
+ * pft_ptmat_plan_export: for a matrix, and (diag_coeffs not NULL) its
+ * integer plaintexts P_b, [n_in][G][b][N] int64, as pft_ptmatvec multiplies
+ * by them (times q_{level-1} scale, see pft_ptmat_create).
+ * Both write min(max_ops, count) ops (ops may be NULL) and the count to
+ * *n_ops. */
+enum { PFT_OP_MUL_PLAIN = 7 };
+int pft_ptmat_plan(uint32_t n_o, uint32_t n_i, uint32_t n_in, pft_op* ops, uint32_t max_ops, uint32_t* n_ops);
+int pft_ptmat_plan_export(const pft_ptmat* m, pft_op* ops, uint32_t max_ops, uint32_t* n_ops, int64_t* diag_coeffs);
 
 /* ---- HIP graphs ----------------------------------------------------------
  * pft_graph_begin starts a capture on the context stream (which must not be
@@ -448,7 +520,11 @@ void pft_graph_destroy(pft_graph* graph);
  * synchronizes and returns, for family `kid`, the summed event time, the
  * number of launches, and the summed algorithmic HBM bytes and algorithmic
  * operations (butterflies for the transforms, 64-bit modular multiply-adds
- * otherwise) of those launches.  Families: 0 forward NTT pass, 1 inverse NTT
+ * otherwise) of those launches.  Algorithmic bytes are the method's: the
+ * operands a launch reads and the results it writes, 8 bytes per residue;
+ * the words a transform leaves between two of its passes are the layout's
+ * cost and are not counted (a pass that neither starts nor ends its
+ * transform counts none).  Families: 0 forward NTT pass, 1 inverse NTT
  * pass, 2 ModUp base conversion, 3 key inner product, 4 ModDown base
  * conversion, 5 ModDown final scaling (kept as an index; it now runs as
  * the epilogue of the forward NTT pass that produces it, family 0), 6 HMUL
@@ -462,12 +538,16 @@ int pft_prof_read(pft_ctx* ctx, uint32_t kid, double* total_ms, uint64_t* launch
  * bytes, ops); returns the number of distinct variants.  variant 0: the
  * family's single kernel; NTT passes (families 0 and 1): 1 + (radix | 32 if a
  * column pass | 64 if the transform's final pass | 128 if staged | 256 if 8
- * residues per thread | 512 if the pass finishes ModDown), naming
- * k_ntt_pass<radix, log2 residues per thread, inverse, column, final, staged,
- * ModDown epilogue>; base conversions on the matrix cores (families 2 and
- * 4): the number of 16-deep k-blocks, naming k_modup_mfma_b<kb> and
- * k_moddown_mfma_b<kb>; the batched key inner product (family 3): the number
- * of digits beta, naming k_key_inner_items<beta>.  Any output may be NULL. */
+ * residues per thread | 512 if the pass finishes ModDown | 1024 if X^kappa
+ * is folded into it), naming k_ntt_pass<radix, log2 residues per thread,
+ * inverse, column, final, staged, ModDown epilogue[, true]>; base
+ * conversions on the matrix cores (families 2 and 4): the number of 16-deep
+ * k-blocks, naming k_modup_mfma_b<kb> and k_moddown_mfma_b<kb>, or 64 + kb
+ * (+ 16 with the inverse pass folded in) for the conversions fused with
+ * transform passes, naming k_bconv_col_b<kb, ModDown, inverse pass>; the key
+ * inner product (family 3): the number of digits beta, naming
+ * k_key_inner_items<beta>, or 1024 + the radix of the row pass it is fused
+ * with, naming k_row_inner<radix, 3>.  Any output may be NULL. */
 int pft_prof_read_variants(pft_ctx* ctx, uint32_t kid, uint32_t max_count, uint32_t* variants, double* total_ms,
                            uint64_t* launches, double* bytes, double* ops);
 

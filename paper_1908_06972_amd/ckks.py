@@ -16,11 +16,15 @@ from . import native as N
 class Params:
     """SETUP (Sec. 3.4): ring degree, prime chain, special primes, dnum, scale."""
 
-    def __init__(self, log_n, n_q, q0_bits, q_bits, n_p, p_bits, dnum, scale):
+    def __init__(self, log_n, n_q, q0_bits, q_bits, n_p, p_bits, dnum, scale, rescale_mode=0):
         lib = N.load()
-        spec = N.ParamSpec(log_n, n_q, q0_bits, q_bits, n_p, p_bits, dnum, 0, float(scale))
+        spec = N.ParamSpec(log_n, n_q, q0_bits, q_bits, n_p, p_bits, dnum, rescale_mode, float(scale))
         h = ctypes.c_void_p()
         N.check(lib.pft_params_create(ctypes.byref(spec), ctypes.byref(h)))
+        self._adopt(h, log_n, n_q, n_p, dnum, scale)
+
+    def _adopt(self, h, log_n, n_q, n_p, dnum, scale):
+        lib = N.load()
         self.handle = h
         self._destroy = lib.pft_params_destroy  # bound now: usable during interpreter shutdown
         self.log_n = log_n
@@ -37,6 +41,21 @@ class Params:
         dims = np.zeros(5, dtype=np.uint32)
         N.check(lib.pft_params_dims(h, dims.ctypes.data_as(N._u32p)))
         self.alpha = int(dims[4])
+        mode = ctypes.c_uint32()
+        N.check(lib.pft_params_rescale_mode(h, ctypes.byref(mode)))
+        self.rescale_mode = mode.value
+
+    @classmethod
+    def from_primes(cls, log_n, q, p, dnum, scale, rescale_mode=0):
+        """SETUP with the caller's prime chain (pft_params_create_primes)."""
+        qa = np.ascontiguousarray(q, dtype=np.uint64)
+        pa = np.ascontiguousarray(p, dtype=np.uint64)
+        spec = N.ParamPrimes(log_n, len(qa), N.u64p(qa), N.u64p(pa), len(pa), dnum, rescale_mode, 0, float(scale))
+        h = ctypes.c_void_p()
+        N.check(N.load().pft_params_create_primes(ctypes.byref(spec), ctypes.byref(h)))
+        obj = cls.__new__(cls)
+        obj._adopt(h, log_n, len(qa), len(pa), dnum, scale)
+        return obj
 
     @classmethod
     def from_config(cls, cfg):
@@ -110,18 +129,64 @@ def _u64(a):
     return np.ascontiguousarray(a, dtype=np.uint64)
 
 
+class TorchAllocator:
+    """Device memory for the library's own buffers from torch's caching
+    allocator (pft_allocator callbacks), on the context's stream."""
+
+    def __init__(self, stream):
+        self.stream = stream
+        self.live = {}
+
+        def alloc(_user, nbytes, device):
+            try:
+                ptr = torch.cuda.caching_allocator_alloc(int(nbytes), device, self.stream)
+            except RuntimeError:
+                return None
+            self.live[ptr] = int(nbytes)
+            return ptr
+
+        def free(_user, ptr):
+            if ptr in self.live:
+                del self.live[ptr]
+                torch.cuda.caching_allocator_delete(ptr)
+
+        self.alloc_fn = N.ALLOC_FN(alloc)
+        self.free_fn = N.FREE_FN(free)
+
+
 class Context:
-    def __init__(self, params: Params, device: int = 0, stream=None):
+    def __init__(self, params: Params, device: int = 0, stream=None, budget_bytes=0, torch_memory=False):
         """stream: a torch.cuda.Stream to run on (default: torch's current
-        stream).  Graph capture needs a stream other than the null stream."""
+        stream).  Graph capture needs a stream other than the null stream.
+        budget_bytes: cap on the library's own device memory (0: none);
+        torch_memory: take that memory from torch's caching allocator."""
         self.params = params
         self.device = torch.device("cuda", device)
         self.lib = N.load()
         h = ctypes.c_void_p()
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         stream = self.stream.cuda_stream
-        N.check(self.lib.pft_ctx_create(params.handle, device, ctypes.c_void_p(stream), ctypes.byref(h)))
+        self._alloc = None
+        if budget_bytes or torch_memory:
+            spec = N.Allocator()
+            if torch_memory:
+                self._alloc = TorchAllocator(self.stream)
+                spec.alloc, spec.free = self._alloc.alloc_fn, self._alloc.free_fn
+            spec.budget_bytes = int(budget_bytes)
+            N.check(self.lib.pft_ctx_create_alloc(params.handle, device, ctypes.c_void_p(stream), ctypes.byref(spec),
+                                                  ctypes.byref(h)))
+        else:
+            N.check(self.lib.pft_ctx_create(params.handle, device, ctypes.c_void_p(stream), ctypes.byref(h)))
         self.handle = h
+
+    def set_budget(self, budget_bytes):
+        N.check(self.lib.pft_ctx_set_budget(self.handle, int(budget_bytes)))
+
+    def memory(self):
+        """{"tables_keys", "scratch", "budget"} device bytes of the library's own buffers."""
+        out = np.zeros(3, dtype=np.uint64)
+        N.check(self.lib.pft_ctx_memory(self.handle, N.u64p(out)))
+        return dict(zip(("tables_keys", "scratch", "budget"), (int(x) for x in out)))
 
     def close(self):
         if getattr(self, "handle", None) is not None:
@@ -505,6 +570,24 @@ class Graph:
         self.close()
 
 
+OP_NAMES = {N.PFT_OP_ROTATE: "rotate", N.PFT_OP_MUL_PLAIN: "mul_plain", N.PFT_OP_ADD: "add"}
+
+
+def _plan_list(buf, n):
+    return [(OP_NAMES[buf[i].kind], buf[i].a, buf[i].b, buf[i].out, buf[i].step) for i in range(n)]
+
+
+def ptmat_plan(n_o, n_i, n_in):
+    """The PtMatVec op list of a shape (pft_ptmat_plan): tuples
+    (kind, a, b, out, step) with kind 'rotate', 'mul_plain' or 'add'."""
+    lib = N.load()
+    cnt = ctypes.c_uint32()
+    N.check(lib.pft_ptmat_plan(n_o, n_i, n_in, None, 0, ctypes.byref(cnt)))
+    buf = (N.OpDesc * max(cnt.value, 1))()
+    N.check(lib.pft_ptmat_plan(n_o, n_i, n_in, buf, cnt.value, ctypes.byref(cnt)))
+    return _plan_list(buf, cnt.value)
+
+
 class PtMat:
     def __init__(self, ctx, handle):
         self.ctx = ctx
@@ -512,6 +595,16 @@ class PtMat:
         info = np.zeros(6, dtype=np.uint32)
         N.check(ctx.lib.pft_ptmat_info(handle, info.ctypes.data_as(N._u32p)))
         self.n_o, self.n_i, self.n_in, self.level, self.b, self.G = (int(x) for x in info)
+
+    def plan_export(self):
+        """(op list as ptmat_plan, integer plaintexts [n_in][G][b][N])."""
+        lib = self.ctx.lib
+        cnt = ctypes.c_uint32()
+        N.check(lib.pft_ptmat_plan_export(self.handle, None, 0, ctypes.byref(cnt), None))
+        buf = (N.OpDesc * max(cnt.value, 1))()
+        coeffs = np.empty((self.n_in, self.G, self.b, self.ctx.params.n), dtype=np.int64)
+        N.check(lib.pft_ptmat_plan_export(self.handle, buf, cnt.value, ctypes.byref(cnt), N.i64p(coeffs)))
+        return _plan_list(buf, cnt.value), coeffs
 
     def __del__(self):
         if getattr(self, "handle", None) is not None:

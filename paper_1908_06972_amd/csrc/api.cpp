@@ -11,6 +11,7 @@
 #include <cmath>
 #include <complex>
 #include <map>
+#include <unordered_map>
 #include <string>
 #include <vector>
 
@@ -48,6 +49,7 @@ extern "C" const char* pft_last_error(void) { return g_err.c_str(); }
 // ---------------------------------------------------------------------------
 struct pft_params {
     uint32_t log_n, n, L, K, dnum, alpha;
+    uint32_t rescale_mode = 0;  // mode of pft_rescale's PFT_RESCALE_DEFAULT
     double scale;
     std::vector<uint64_t> q, p, mods;  // mods = q then p
     std::vector<uint64_t> psi;         // per modulus
@@ -78,15 +80,67 @@ static uint64_t primitive_2n_root(uint64_t q, uint64_t n) {
     return powmod(g, (q - 1) / (2 * n), q);
 }
 
+// Limits shared by both forms of SETUP.
+static int check_shape(uint32_t log_n, uint32_t n_q, uint32_t n_p, uint32_t dnum, uint32_t rescale_mode) {
+    if (!ntt_supported(log_n)) return fail(PFT_EPARAM, "log_n %u unsupported (12..16)", log_n);
+    if (n_q < 1 || n_q > 64) return fail(PFT_EPARAM, "n_q must be in 1..64");
+    if (n_p < 1 || n_p > 12) return fail(PFT_EPARAM, "n_p must be in 1..12");
+    if (dnum < 1 || dnum > n_q) return fail(PFT_EPARAM, "dnum must be in 1..n_q");
+    if ((n_q + dnum - 1) / dnum > 12) return fail(PFT_EPARAM, "alpha = ceil(L/dnum) must be <= 12");
+    if ((n_q + n_p) * 2 > 128) return fail(PFT_EPARAM, "too many primes");
+    if (rescale_mode > 1) return fail(PFT_EPARAM, "rescale_mode must be 0 (round) or 1 (floor)");
+    return PFT_OK;
+}
+
+// The rest of SETUP once the primes are fixed: moduli list and roots.
+static pft_params* finish_params(pft_params* P) {
+    P->mods = P->q;
+    P->mods.insert(P->mods.end(), P->p.begin(), P->p.end());
+    for (uint64_t m : P->mods) P->psi.push_back(primitive_2n_root(m, P->n));
+    return P;
+}
+
+extern "C" int pft_params_create_primes(const pft_param_primes* s, pft_params** out) {
+    if (!s || !out || !s->q || !s->p) return fail(PFT_EINVAL, "null argument");
+    int r;
+    if ((r = check_shape(s->log_n, s->n_q, s->n_p, s->dnum, s->rescale_mode))) return r;
+    const uint64_t two_n = 2ull << s->log_n;
+    std::vector<uint64_t> all;
+    for (uint32_t i = 0; i < s->n_q + s->n_p; ++i) {
+        const bool is_q = i < s->n_q;
+        const uint64_t m = is_q ? s->q[i] : s->p[i - s->n_q];
+        const char* kind = is_q ? "q" : "p";
+        const uint32_t idx = is_q ? i : i - s->n_q;
+        if (m <= (1ull << 20) || m >= (1ull << 60))
+            return fail(PFT_EPARAM, "%s[%u] = %llu is not in (2^20, 2^60)", kind, idx, (unsigned long long)m);
+        if (m % two_n != 1) return fail(PFT_EPARAM, "%s[%u] = %llu is not 1 mod 2N", kind, idx, (unsigned long long)m);
+        if (!is_prime_u64(m)) return fail(PFT_EPARAM, "%s[%u] = %llu is not prime", kind, idx, (unsigned long long)m);
+        if (std::find(all.begin(), all.end(), m) != all.end())
+            return fail(PFT_EPARAM, "%s[%u] = %llu appears twice", kind, idx, (unsigned long long)m);
+        if (is_q && i > 0 && !(s->q[i - 1] > m))
+            return fail(PFT_EPARAM, "q must be strictly descending (q[%u] <= q[%u])", i - 1, i);
+        all.push_back(m);
+    }
+    auto* P = new pft_params();
+    P->log_n = s->log_n;
+    P->n = 1u << s->log_n;
+    P->L = s->n_q;
+    P->K = s->n_p;
+    P->dnum = s->dnum;
+    P->alpha = (s->n_q + s->dnum - 1) / s->dnum;
+    P->rescale_mode = s->rescale_mode;
+    P->scale = s->scale;
+    P->q.assign(s->q, s->q + s->n_q);
+    P->p.assign(s->p, s->p + s->n_p);
+    *out = finish_params(P);
+    return PFT_OK;
+}
+
 extern "C" int pft_params_create(const pft_param_spec* s, pft_params** out) {
     if (!s || !out) return fail(PFT_EINVAL, "null argument");
-    if (!ntt_supported(s->log_n)) return fail(PFT_EPARAM, "log_n %u unsupported (12..16)", s->log_n);
-    if (s->n_q < 1 || s->n_q > 64) return fail(PFT_EPARAM, "n_q must be in 1..64");
-    if (s->n_p < 1 || s->n_p > 12) return fail(PFT_EPARAM, "n_p must be in 1..12");
-    if (s->dnum < 1 || s->dnum > s->n_q) return fail(PFT_EPARAM, "dnum must be in 1..n_q");
+    int r0;
+    if ((r0 = check_shape(s->log_n, s->n_q, s->n_p, s->dnum, s->rescale_mode))) return r0;
     uint32_t alpha = (s->n_q + s->dnum - 1) / s->dnum;
-    if (alpha > 12) return fail(PFT_EPARAM, "alpha = ceil(L/dnum) must be <= 12");
-    if ((s->n_q + s->n_p) * 2 > 128) return fail(PFT_EPARAM, "too many primes");
     for (uint32_t b : {s->q0_bits, s->q_bits, s->p_bits})
         if (b < 20 || b > 60) return fail(PFT_EPARAM, "prime bit sizes must be in 20..60");
     if (s->q0_bits < s->q_bits) return fail(PFT_EPARAM, "q0_bits must be >= q_bits (descending chain)");
@@ -97,6 +151,7 @@ extern "C" int pft_params_create(const pft_param_spec* s, pft_params** out) {
     P->K = s->n_p;
     P->dnum = s->dnum;
     P->alpha = alpha;
+    P->rescale_mode = s->rescale_mode;
     P->scale = s->scale;
     const uint64_t two_n = 2ull * P->n;
     std::vector<uint64_t> none;
@@ -111,14 +166,17 @@ extern "C" int pft_params_create(const pft_param_spec* s, pft_params** out) {
             delete P;
             return fail(PFT_EPARAM, "prime chain is not strictly descending");
         }
-    P->mods = P->q;
-    P->mods.insert(P->mods.end(), P->p.begin(), P->p.end());
-    for (uint64_t m : P->mods) P->psi.push_back(primitive_2n_root(m, P->n));
-    *out = P;
+    *out = finish_params(P);
     return PFT_OK;
 }
 
 extern "C" void pft_params_destroy(pft_params* P) { delete P; }
+
+extern "C" int pft_params_rescale_mode(const pft_params* P, uint32_t* mode) {
+    if (!P || !mode) return fail(PFT_EINVAL, "null argument");
+    *mode = P->rescale_mode;
+    return PFT_OK;
+}
 
 extern "C" int pft_params_moduli(const pft_params* P, uint64_t* q, uint64_t* p) {
     if (!P || !q || !p) return fail(PFT_EINVAL, "null argument");
@@ -245,13 +303,55 @@ struct pft_ctx {
     std::vector<hipStream_t> side;
     std::vector<hipEvent_t> side_ev;
     std::vector<std::pair<uint64_t*, size_t>> side_ws;
+    // device memory of the library's own buffers: the caller's allocator (or
+    // hipMalloc/hipFree), the bytes of every live allocation, and the budget
+    // (0: none) that new allocations must fit under
+    pft_allocator alloc{};
+    std::unordered_map<void*, size_t> live;
+    uint64_t live_bytes = 0;
 };
+
+// Every device allocation of the library goes through here: refused with
+// PFT_ENOMEM (and a message naming `what`) if it would take the context's
+// live bytes past its budget or if the allocator fails.
+static int dev_alloc(pft_ctx* c, void** p, size_t bytes, const char* what) {
+    *p = nullptr;
+    if (c->alloc.budget_bytes && c->live_bytes + bytes > c->alloc.budget_bytes)
+        return fail(PFT_ENOMEM, "%s of %zu bytes exceeds the context's device-memory budget (%llu of %llu bytes in use)",
+                    what, bytes, (unsigned long long)c->live_bytes, (unsigned long long)c->alloc.budget_bytes);
+    if (c->alloc.alloc) {
+        *p = c->alloc.alloc(c->alloc.user, bytes, c->device);
+        if (!*p) return fail(PFT_ENOMEM, "%s: the caller's allocator returned no memory for %zu bytes", what, bytes);
+    } else {
+        hipError_t e = hipMalloc(p, bytes);
+        if (e != hipSuccess) {
+            *p = nullptr;
+            return fail(PFT_ENOMEM, "%s: hipMalloc(%zu): %s", what, bytes, hipGetErrorString(e));
+        }
+    }
+    c->live[*p] = bytes;
+    c->live_bytes += bytes;
+    return PFT_OK;
+}
+
+static void dev_free(pft_ctx* c, void* p) {
+    if (!p) return;
+    auto it = c->live.find(p);
+    if (it != c->live.end()) {
+        c->live_bytes -= it->second;
+        c->live.erase(it);
+    }
+    if (c->alloc.free)
+        c->alloc.free(c->alloc.user, p);
+    else
+        (void)hipFree(p);
+}
 
 template <typename T>
 static int dalloc(pft_ctx* c, T** p, size_t bytes) {
     void* v = nullptr;
-    hipError_t e = hipMalloc(&v, bytes);
-    if (e != hipSuccess) return fail(PFT_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    int r = dev_alloc(c, &v, bytes, "table or key storage");
+    if (r) return r;
     c->allocs.push_back(v);
     c->device_bytes += bytes;
     *p = (T*)v;
@@ -276,12 +376,14 @@ static int ensure_ws(pft_ctx* c, size_t bytes) {
         if (c->live_graphs)
             c->retired.push_back(c->ws);
         else
-            HIPCK(hipFree(c->ws));
+            dev_free(c, c->ws);
         c->ws = nullptr;
         c->ws_bytes = 0;
     }
-    hipError_t e = hipMalloc(&c->ws, bytes);
-    if (e != hipSuccess) return fail(PFT_ENOMEM, "workspace hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    void* v = nullptr;
+    int r = dev_alloc(c, &v, bytes, "workspace");
+    if (r) return r;
+    c->ws = (uint64_t*)v;
     c->ws_bytes = bytes;
     return PFT_OK;
 }
@@ -296,12 +398,14 @@ static int ensure_aux(pft_ctx* c, size_t bytes) {
         if (c->live_graphs)
             c->retired.push_back(c->aux);
         else
-            HIPCK(hipFree(c->aux));
+            dev_free(c, c->aux);
         c->aux = nullptr;
         c->aux_bytes = 0;
     }
-    hipError_t e = hipMalloc(&c->aux, bytes);
-    if (e != hipSuccess) return fail(PFT_ENOMEM, "aux hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    void* v = nullptr;
+    int r = dev_alloc(c, &v, bytes, "aux buffer");
+    if (r) return r;
+    c->aux = (uint64_t*)v;
     c->aux_bytes = bytes;
     return PFT_OK;
 }
@@ -510,9 +614,16 @@ static int build_tables(pft_ctx* c) {
 }
 
 extern "C" int pft_ctx_create(const pft_params* P, int device, void* stream, pft_ctx** out) {
+    return pft_ctx_create_alloc(P, device, stream, nullptr, out);
+}
+
+extern "C" int pft_ctx_create_alloc(const pft_params* P, int device, void* stream, const pft_allocator* alloc,
+                                    pft_ctx** out) {
     if (!P || !out) return fail(PFT_EINVAL, "null argument");
+    if (alloc && (!alloc->alloc) != (!alloc->free)) return fail(PFT_EINVAL, "allocator needs both alloc and free");
     HIPCK(hipSetDevice(device));
     auto* c = new pft_ctx();
+    if (alloc) c->alloc = *alloc;
     c->P = P;
     c->device = device;
     c->stream = (hipStream_t)stream;
@@ -531,11 +642,11 @@ extern "C" void pft_ctx_destroy(pft_ctx* c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
-    for (void* p : c->allocs) (void)hipFree(p);
-    if (c->ws) (void)hipFree(c->ws);
-    if (c->aux) (void)hipFree(c->aux);
-    if (c->cbuf) (void)hipFree(c->cbuf);
-    for (void* p : c->retired) (void)hipFree(p);
+    for (void* p : c->allocs) dev_free(c, p);
+    dev_free(c, c->ws);
+    dev_free(c, c->aux);
+    dev_free(c, c->cbuf);
+    for (void* p : c->retired) dev_free(c, p);
     for (auto& kv : c->rot)
         if (kv.second.host) (void)hipHostFree(kv.second.host);
     for (hipStream_t st : c->side) {
@@ -543,8 +654,7 @@ extern "C" void pft_ctx_destroy(pft_ctx* c) {
         (void)hipStreamDestroy(st);
     }
     for (hipEvent_t e : c->side_ev) (void)hipEventDestroy(e);
-    for (auto& w : c->side_ws)
-        if (w.first) (void)hipFree(w.first);
+    for (auto& w : c->side_ws) dev_free(c, w.first);
     delete c;
 }
 
@@ -552,6 +662,23 @@ extern "C" int pft_ctx_synchronize(pft_ctx* c) {
     if (!c) return fail(PFT_EINVAL, "null ctx");
     if (c->capturing) return fail(PFT_EINVAL, "cannot synchronize during graph capture");
     HIPCK(hipStreamSynchronize(c->stream));
+    return PFT_OK;
+}
+
+extern "C" int pft_ctx_set_budget(pft_ctx* c, uint64_t budget_bytes) {
+    if (!c) return fail(PFT_EINVAL, "null ctx");
+    if (budget_bytes && c->live_bytes > budget_bytes)
+        return fail(PFT_ENOMEM, "the context already holds %llu bytes, more than a budget of %llu",
+                    (unsigned long long)c->live_bytes, (unsigned long long)budget_bytes);
+    c->alloc.budget_bytes = budget_bytes;
+    return PFT_OK;
+}
+
+extern "C" int pft_ctx_memory(const pft_ctx* c, uint64_t* out) {
+    if (!c || !out) return fail(PFT_EINVAL, "null argument");
+    out[0] = c->device_bytes;
+    out[1] = c->live_bytes - c->device_bytes;
+    out[2] = c->alloc.budget_bytes;
     return PFT_OK;
 }
 
@@ -641,18 +768,18 @@ static NttSchedule ntt_tune(pft_ctx* c, bool inverse, uint32_t cls, bool col16 =
     const uint32_t nl = (uint32_t)std::min<uint64_t>(want, rows);
     const size_t bytes = (size_t)np * rows * P->n * 8;
     void* buf = nullptr;
-    if (hipMalloc(&buf, bytes) != hipSuccess) {
+    if (dev_alloc(c, &buf, bytes, "autotuner scratch") != PFT_OK) {
         (void)hipGetLastError();
         return cand[0];
     }
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) {
-        (void)hipFree(buf);
+        dev_free(c, buf);
         return cand[0];
     }
     if (hipEventCreate(&e1) != hipSuccess) {
         (void)hipEventDestroy(e0);
-        (void)hipFree(buf);
+        dev_free(c, buf);
         return cand[0];
     }
     std::vector<float> med(nc, 1e30f);
@@ -694,7 +821,7 @@ static NttSchedule ntt_tune(pft_ctx* c, bool inverse, uint32_t cls, bool col16 =
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipStreamSynchronize(c->stream);
-    (void)hipFree(buf);
+    dev_free(c, buf);
     return best;
 }
 
@@ -1480,8 +1607,11 @@ static void key_switch_b(pft_ctx* c, uint32_t n, WsRef ws, const KsLayout& K, ui
             wr += rows - na;
             macs += (double)(rows - na) * na + na;
         }
+        // method bytes: rows between two passes of a transform (the fused
+        // conversion's inputs when it applies the inverse's last pass, its
+        // outputs when it applies the forward's first) are layout cost
         if (fuse) {
-            timed(c, PK_MODUP, 8.0 * N * (rd + wr) * n, N * macs * n,
+            timed(c, PK_MODUP, 8.0 * N * (ifuse_up ? 0.0 : rd) * n, N * macs * n,
                   [&] {
                       launch_modup_col_b(n, ws, K.off_dcoef, K.off_ext, level, c->kc, c->tabs, lg, ifuse_up,
                                          c->stream);
@@ -1545,7 +1675,7 @@ static void key_switch_b(pft_ctx* c, uint32_t n, WsRef ws, const KsLayout& K, ui
         ntt_jobs(c, jobs, P->K, level, true, 0, nullptr, 0, ifuse_down ? 1u : 0u, ifuse_down);
     }
     if (fuse_down) {
-        timed(c, PK_MODDOWN_CONV, 8.0 * N * (2.0 * P->K + 2.0 * level) * n, 2.0 * N * P->K * level * n,
+        timed(c, PK_MODDOWN_CONV, 8.0 * N * (ifuse_down ? 0.0 : 2.0 * P->K) * n, 2.0 * N * P->K * level * n,
               [&] {
                   launch_moddown_col_b(n, ws, K.off_acc, K.off_conv, level, c->kc, c->tabs, lg, ifuse_down,
                                        c->stream);
@@ -1649,7 +1779,8 @@ extern "C" int pft_rescale(pft_ctx* c, const pft_ct* in, uint32_t mode, pft_ct* 
 
 extern "C" int pft_rescale_batch(pft_ctx* c, uint32_t n, const pft_ct* in, uint32_t mode, pft_ct* out) {
     if (!c || !in || !out) return fail(PFT_EINVAL, "null argument");
-    if (mode > 1) return fail(PFT_EINVAL, "mode must be 0 (round) or 1 (floor)");
+    if (mode == PFT_RESCALE_DEFAULT) mode = c->P->rescale_mode;
+    if (mode > 1) return fail(PFT_EINVAL, "mode must be 0 (round), 1 (floor) or PFT_RESCALE_DEFAULT");
     int r;
     for (uint32_t i = 0; i < n; ++i) {
         if ((r = check_ct(c, &in[i]))) return r;
@@ -1685,8 +1816,8 @@ extern "C" int pft_rescale_batch(pft_ctx* c, uint32_t n, const pft_ct* in, uint3
         // the expansion applies the first pass of tmp's transform itself
         // where that schedule starts with a radix-16 column pass
         const bool fuse = lg >= 8 && first_pass_col16(c, (uint64_t)jt.size() * (l - 1));
-        if (fuse)
-            timed(c, PK_RESCALE, 8.0 * nd * (2.0 + 2.0 * (l - 1)) * cnt, 0,
+        if (fuse)  // its rows leave after the first transform pass: layout cost
+            timed(c, PK_RESCALE, 8.0 * nd * 2.0 * cnt, 0,
                   [&] { launch_rescale_col_b(cnt, ws, off_last, off_tmp, l, mode, c->tabs, lg, c->stream); }, 1u);
         else
             timed(c, PK_RESCALE, 8.0 * nd * (2.0 + 2.0 * (l - 1)) * cnt, 0,
@@ -1935,9 +2066,13 @@ extern "C" int pft_mul_const_batch(pft_ctx* c, uint32_t n, const pft_ct* in, con
         }
         if (c->cbuf_n < consts.size()) {
             HIPCK(hipStreamSynchronize(c->stream));
-            if (c->cbuf) HIPCK(hipFree(c->cbuf));
+            dev_free(c, c->cbuf);
             c->cbuf = nullptr;
-            HIPCK(hipMalloc(&c->cbuf, consts.size() * sizeof(TwPair)));
+            c->cbuf_n = 0;
+            void* v = nullptr;
+            int rr = dev_alloc(c, &v, consts.size() * sizeof(TwPair), "constant buffer");
+            if (rr) return rr;
+            c->cbuf = (TwPair*)v;
             c->cbuf_n = consts.size();
         }
         HIPCK(hipMemcpyAsync(c->cbuf, consts.data(), consts.size() * sizeof(TwPair), hipMemcpyHostToDevice,
@@ -1964,9 +2099,13 @@ extern "C" int pft_mul_const(pft_ctx* c, const pft_ct* in, double value, pft_ct*
 static int upload_consts(pft_ctx* c, const std::vector<TwPair>& consts) {
     if (c->cbuf_n < consts.size()) {
         HIPCK(hipStreamSynchronize(c->stream));
-        if (c->cbuf) HIPCK(hipFree(c->cbuf));
+        dev_free(c, c->cbuf);
         c->cbuf = nullptr;
-        HIPCK(hipMalloc(&c->cbuf, consts.size() * sizeof(TwPair)));
+        c->cbuf_n = 0;
+        void* v = nullptr;
+        int r = dev_alloc(c, &v, consts.size() * sizeof(TwPair), "constant buffer");
+        if (r) return r;
+        c->cbuf = (TwPair*)v;
         c->cbuf_n = consts.size();
     }
     HIPCK(hipMemcpyAsync(c->cbuf, consts.data(), consts.size() * sizeof(TwPair), hipMemcpyHostToDevice, c->stream));
@@ -2020,6 +2159,7 @@ struct pft_ptmat {
     uint32_t n_o = 0, n_i = 0, n_in = 0, level = 0, b = 0, G = 0;
     double pt_scale = 0;
     uint64_t* pt = nullptr;  // [G][n_in * b][level][N], NTT domain, times 2^64 mod q
+    std::vector<int64_t> coeffs;  // host [n_in][G][b][N]: the integer plaintexts, for the plan export
 };
 
 // Baby-step count b (a power of two dividing n_o) that minimises the key
@@ -2091,8 +2231,65 @@ extern "C" int pft_ptmat_create_from_coeffs(pft_ctx* c, const int64_t* coeffs, u
         delete m;
         return r;
     }
+    m->coeffs.assign(coeffs, coeffs + (size_t)n_in * m->G * m->b * c->P->n);
     *out = m;
     return PFT_OK;
+}
+
+// The operations of one document's PtMatVec in the order pft_ptmatvec runs
+// them (see pft_ptmat_plan in pft.h for the register convention).
+static std::vector<pft_op> ptmat_plan_ops(uint32_t n_o, uint32_t n_i, uint32_t n_in) {
+    uint32_t b, G;
+    bsgs_plan(n_o, n_in, &b, &G);
+    std::vector<pft_op> ops;
+    auto baby = [&](uint32_t cc, uint32_t rr) { return rr == 0 ? cc : n_in + cc * (b - 1) + (rr - 1); };
+    const uint32_t prod = n_in + n_in * (b - 1), acc = prod + 1, tmp = prod + 2, tot = prod + 3;
+    auto op = [&](uint32_t kind, uint32_t a, uint32_t bb, uint32_t out, int32_t step) {
+        ops.push_back(pft_op{kind, a, bb, out, step, 0});
+    };
+    for (uint32_t rr = 1; rr < b; ++rr)
+        for (uint32_t cc = 0; cc < n_in; ++cc) op(PFT_OP_ROTATE, cc, 0, baby(cc, rr), (int32_t)rr);
+    for (uint32_t g = 0; g < G; ++g) {
+        const uint32_t sum = g == 0 ? tot : acc;
+        bool first = true;
+        for (uint32_t cc = 0; cc < n_in; ++cc)
+            for (uint32_t rr = 0; rr < b; ++rr) {
+                const uint32_t diag = (cc * G + g) * b + rr;
+                op(PFT_OP_MUL_PLAIN, baby(cc, rr), diag, first ? sum : prod, 0);
+                if (!first) op(PFT_OP_ADD, sum, prod, sum, 0);
+                first = false;
+            }
+        if (g == 0) continue;
+        op(PFT_OP_ROTATE, acc, 0, tmp, (int32_t)(g * b));
+        op(PFT_OP_ADD, tot, tmp, tot, 0);
+    }
+    for (uint32_t st = n_o; st < n_i; st <<= 1) {
+        op(PFT_OP_ROTATE, tot, 0, tmp, (int32_t)st);
+        op(PFT_OP_ADD, tot, tmp, tot, 0);
+    }
+    return ops;
+}
+
+static int copy_plan(const std::vector<pft_op>& ops, pft_op* out, uint32_t max_ops, uint32_t* n_ops) {
+    if (n_ops) *n_ops = (uint32_t)ops.size();
+    if (out)
+        for (size_t i = 0; i < ops.size() && i < max_ops; ++i) out[i] = ops[i];
+    return PFT_OK;
+}
+
+extern "C" int pft_ptmat_plan(uint32_t n_o, uint32_t n_i, uint32_t n_in, pft_op* ops, uint32_t max_ops,
+                              uint32_t* n_ops) {
+    if (!n_o || (n_o & (n_o - 1)) || !n_i || (n_i & (n_i - 1)) || n_o > n_i)
+        return fail(PFT_EINVAL, "need powers of two n_o <= n_i");
+    if (n_in < 1 || n_in > 4096) return fail(PFT_EINVAL, "n_in must be in 1..4096");
+    return copy_plan(ptmat_plan_ops(n_o, n_i, n_in), ops, max_ops, n_ops);
+}
+
+extern "C" int pft_ptmat_plan_export(const pft_ptmat* m, pft_op* ops, uint32_t max_ops, uint32_t* n_ops,
+                                     int64_t* diag_coeffs) {
+    if (!m) return fail(PFT_EINVAL, "null matrix");
+    if (diag_coeffs) std::copy(m->coeffs.begin(), m->coeffs.end(), diag_coeffs);
+    return copy_plan(ptmat_plan_ops(m->n_o, m->n_i, m->n_in), ops, max_ops, n_ops);
 }
 
 extern "C" int pft_diagonals_encode(const pft_params* P, const double* M, uint32_t n_o, uint32_t n_i, uint32_t n_in,

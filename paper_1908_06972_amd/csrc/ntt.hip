@@ -613,12 +613,15 @@ void launch_pass(const PolyBatch& b, const DevTables& t, uint32_t log_n, uint32_
         go(std::integral_constant<int, 4>{});
     if (g_prof) {
         const double elems = (double)b.n_polys * b.n_limbs * (double)(1u << log_n);
-        // read + write every residue once; N/2 butterflies per stage
+        // method bytes: the transform's input (read by its first pass) and
+        // output (written by its final pass), 8 bytes per residue each; the
+        // words between two passes are the layout's cost, not the method's.
+        // N/2 butterflies per stage.
         const bool fused = epi && !INV && final_pass && !col;
         const bool perm = epi && epi->kappa && !col && (INV ? first_pass != 0 : fused);
         const uint32_t variant = 1u + (LOG_M | (col ? 32u : 0u) | (final_pass ? 64u : 0u) | (staged ? 128u : 0u) |
                                        (e8 ? 256u : 0u) | (fused ? 512u : 0u) | (perm ? 1024u : 0u));
-        // the ModDown epilogue reads acc (and the addend) and writes out in
+        // the ModDown epilogue reads acc (and the addends) and writes out in
         // place of the transform's own store
         double extra = 0.0;  // addends: half of the rows (one polynomial) each
         if (fused) {
@@ -626,7 +629,8 @@ void launch_pass(const PolyBatch& b, const DevTables& t, uint32_t log_n, uint32_
                 extra += (epi->d_add[bb] != PFT_EPI_NO_ADD ? 4.0 : 0.0) + (epi->d_add2[bb] != PFT_EPI_NO_ADD ? 4.0 : 0.0);
             if (perm) extra += 4.0;  // the permuted addend of the first polynomial
         }
-        const double bytes = fused ? elems * (24.0 + extra) : 16.0 * elems;
+        const double in_b = first_pass ? 8.0 : 0.0, out_b = final_pass ? 8.0 : 0.0;
+        const double bytes = elems * (in_b + (fused ? 16.0 + extra : out_b));
         g_prof->end(kid, bytes, 0.5 * elems * LOG_M, variant);
     }
 }

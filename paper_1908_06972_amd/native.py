@@ -33,7 +33,21 @@ class PftError(RuntimeError):
 class ParamSpec(ctypes.Structure):
     _fields_ = [("log_n", ctypes.c_uint32), ("n_q", ctypes.c_uint32), ("q0_bits", ctypes.c_uint32),
                 ("q_bits", ctypes.c_uint32), ("n_p", ctypes.c_uint32), ("p_bits", ctypes.c_uint32),
-                ("dnum", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("scale", ctypes.c_double)]
+                ("dnum", ctypes.c_uint32), ("rescale_mode", ctypes.c_uint32), ("scale", ctypes.c_double)]
+
+
+class ParamPrimes(ctypes.Structure):
+    _fields_ = [("log_n", ctypes.c_uint32), ("n_q", ctypes.c_uint32), ("q", _u64p), ("p", _u64p),
+                ("n_p", ctypes.c_uint32), ("dnum", ctypes.c_uint32), ("rescale_mode", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("scale", ctypes.c_double)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", ctypes.c_void_p), ("budget_bytes", ctypes.c_uint64)]
 
 
 class CtDesc(ctypes.Structure):
@@ -49,6 +63,8 @@ class OpDesc(ctypes.Structure):
 
 
 PFT_OP_NTT, PFT_OP_INTT, PFT_OP_ADD, PFT_OP_MUL_RELIN, PFT_OP_RESCALE, PFT_OP_ROTATE = 1, 2, 3, 4, 5, 6
+PFT_OP_MUL_PLAIN = 7
+PFT_RESCALE_DEFAULT = 2
 
 # (name, argtypes, restype) of every exported symbol declared in include/pft.h
 SIGNATURES = [
@@ -57,7 +73,15 @@ SIGNATURES = [
     ("pft_params_moduli", [_vp, _u64p, _u64p], ctypes.c_int),
     ("pft_params_dims", [_vp, _u32p], ctypes.c_int),
     ("pft_last_error", [], ctypes.c_char_p),
+    ("pft_params_create_primes", [ctypes.POINTER(ParamPrimes), ctypes.POINTER(_vp)], ctypes.c_int),
+    ("pft_params_rescale_mode", [_vp, _u32p], ctypes.c_int),
     ("pft_ctx_create", [_vp, ctypes.c_int, _vp, ctypes.POINTER(_vp)], ctypes.c_int),
+    ("pft_ctx_create_alloc", [_vp, ctypes.c_int, _vp, ctypes.POINTER(Allocator), ctypes.POINTER(_vp)], ctypes.c_int),
+    ("pft_ctx_set_budget", [_vp, ctypes.c_uint64], ctypes.c_int),
+    ("pft_ctx_memory", [_vp, _u64p], ctypes.c_int),
+    ("pft_ptmat_plan", [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(OpDesc), ctypes.c_uint32,
+                        _u32p], ctypes.c_int),
+    ("pft_ptmat_plan_export", [_vp, ctypes.POINTER(OpDesc), ctypes.c_uint32, _u32p, _i64p], ctypes.c_int),
     ("pft_ctx_destroy", [_vp], None),
     ("pft_ctx_synchronize", [_vp], ctypes.c_int),
     ("pft_set_secret", [_vp, _i64p], ctypes.c_int),
