@@ -365,6 +365,7 @@ def parse():
                     help="run only this many untimed steps (for rocprofv3) and exit")
     ap.add_argument("--no-breakdown", action="store_true", help="skip the per-operation loops")
     ap.add_argument("--no-predict", action="store_true", help="skip the encrypted-weight predict measurement")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-primitives op-list measurement")
     ap.add_argument("--no-paper-inference", action="store_true",
                     help="skip the inference at the paper's shapes (N=8192, 123 inputs)")
     ap.add_argument("--serve-requests", type=int, default=1000,
@@ -507,10 +508,142 @@ class GraphStep:
         self.graph.launch()
 
 
+C2_PAIRS = 64
+C2_SEED = 202
+
+
+def c2_op_list(ctx, inputs, steps):
+    """The batched-primitives op list over pairs (a_i, b_i) of mixed levels:
+    m = HMult+relin(a, b), r = RESCALE(m), t = ROTATE(r, step_i), s = t + r;
+    every 4th pair also takes a copy of a through NTT and INTT.  Returns
+    (ciphertexts: inputs then outputs, ops)."""
+    cts = list(inputs)
+    ops = []
+    for i in range(len(inputs) // 2):
+        a, b = 2 * i, 2 * i + 1
+        lvl = inputs[a].level
+        m, r, t, s = len(cts), len(cts) + 1, len(cts) + 2, len(cts) + 3
+        cts += [ctx.empty_ct(lvl), ctx.empty_ct(lvl - 1), ctx.empty_ct(lvl - 1), ctx.empty_ct(lvl - 1)]
+        ops += [("mul_relin", a, b, m, 0, 0), ("rescale", m, 0, r, 0, 0),
+                ("rotate", r, 0, t, steps[i % len(steps)], 0), ("add", t, r, s, 0, 0)]
+        if i % 4 == 0:
+            x = len(cts)
+            cts.append(ctx.empty_ct(lvl))
+            cts[x].data.copy_(inputs[a].data)
+            cts[x].level, cts[x].scale = inputs[a].level, inputs[a].scale
+            ops += [("ntt", x, 0, 0, 0, 0), ("intt", x, 0, 0, 0, 0)]
+    return cts, ops
+
+
+def c2_per_op(ctx, cts, ops):
+    """The op list issued one library call per operation and ciphertext."""
+    for kind, a, b, out, step, mode in ops:
+        if kind == "mul_relin":
+            ctx.mul_relin(cts[a], cts[b], out=cts[out])
+        elif kind == "rescale":
+            ctx.rescale(cts[a], mode, out=cts[out])
+        elif kind == "rotate":
+            ctx.rotate(cts[a], step, out=cts[out])
+        elif kind == "add":
+            ctx.add(cts[a], cts[b], out=cts[out])
+        elif kind == "ntt":
+            ctx.ntt_forward(cts[a].data, cts[a].level)
+        elif kind == "intt":
+            ctx.ntt_inverse(cts[a].data, cts[a].level)
+
+
+def c2_bench(reps=5):
+    """The batched-primitives configuration: N = 2^14, 8 ciphertext primes +
+    2 special primes (dnum 4), scale 2^40; 64 ciphertext pairs at levels
+    drawn from U{3..8} with slots U[-1, 1]; 16 rotation steps drawn from
+    U{1..N/2-1}; the op list of c2_op_list.  Timed four ways on identical
+    inputs: one call per operation (eager, and captured in one HIP graph),
+    and the op-list executor (eager, and replayed from one HIP graph).  All
+    four leave bit-identical outputs (checked)."""
+    import numpy as np
+    import torch
+
+    import synth as S
+    from paper_1908_06972_amd import ckks as L
+
+    cfg = S.CONFIGS["C2"]
+    lp = L.Params.from_config(cfg)
+    side = torch.cuda.Stream()
+    ctx = L.Context(lp, 0, stream=side)
+    g = S.rng(C2_SEED + 1)
+    steps = [int(x) for x in g.integers(1, lp.n // 2, size=16)]
+    ctx.keygen(KEY_SEED, steps)
+    g = S.rng(C2_SEED)
+    levels = [int(x) for x in g.integers(3, lp.L + 1, size=C2_PAIRS)]
+    inputs = []
+    for i in range(C2_PAIRS):
+        for k in range(2):
+            z = S.slots_uniform(S.rng(C2_SEED * 1000 + 2 * i + k), lp.n // 2)
+            top = ctx.encrypt_seeded(lp.encode(z), lp.L, lp.scale, C2_SEED * 1000 + 2 * i + k)
+            inputs.append(ctx.mod_drop(top, levels[i]) if levels[i] < lp.L else top)
+    ctx.synchronize()
+
+    def fresh():
+        return c2_op_list(ctx, inputs, steps)
+
+    def reset(cts, ops, ref):
+        # the NTT -> INTT copies are transformed in place: restore them
+        for kind, a, *_ in ops:
+            if kind == "ntt":
+                with torch.cuda.stream(side):
+                    cts[a].data.copy_(ref[a].data)
+
+    def same(x, y):
+        return all(p.level == q.level and bool((p.data[:, :p.level] == q.data[:, :q.level]).all())
+                   for p, q in zip(x, y))
+
+    sync = ctx.synchronize
+    ref, ops = fresh()
+    c2_per_op(ctx, ref, ops)
+    sync()
+    out = {"pairs": C2_PAIRS, "levels": "U{3..8}", "rotation_steps": steps, "ops": len(ops),
+           "hmult_relin_per_list": C2_PAIRS}
+    # one call per operation, eager
+    po, _ = fresh()
+    t_po = timed(lambda: (reset(po, ops, ref), c2_per_op(ctx, po, ops)), reps, sync)
+    # one call per operation, captured
+    pg, _ = fresh()
+    c2_per_op(ctx, pg, ops)
+    sync()
+    gr_po = ctx.capture(lambda: c2_per_op(ctx, pg, ops))
+    t_pg = timed(lambda: (reset(pg, ops, ref), gr_po.launch()), reps, sync)
+    # the op-list executor, eager
+    ex, _ = fresh()
+    ctx.exec_batch(ex, ops)
+    sync()
+    t_ex = timed(lambda: (reset(ex, ops, ref), ctx.exec_batch(ex, ops)), reps, sync)
+    # the op-list executor, captured
+    eg, _ = fresh()
+    ctx.exec_batch(eg, ops)
+    sync()
+    gr_ex = ctx.capture(lambda: ctx.exec_batch(eg, ops))
+    t_eg = timed(lambda: (reset(eg, ops, ref), gr_ex.launch()), reps, sync)
+    identical = same(po, ref) and same(pg, ref) and same(ex, ref) and same(eg, ref)
+    if not identical:
+        print("batched op list: outputs differ between launch modes", file=sys.stderr)
+        sys.exit(1)
+    gr_po.close()
+    gr_ex.close()
+    for name, t in (("per_op", t_po), ("per_op_graph", t_pg), ("exec_batch", t_ex), ("exec_batch_graph", t_eg)):
+        out[name] = {"ms_per_list": round(1000.0 * t, 3), "hmult_relin_per_s": round(C2_PAIRS / t, 1)}
+    out["identical_outputs"] = identical
+    out["speedup_exec_graph_over_per_op"] = round(t_po / t_eg, 2)
+    out["note"] = ("times include the device-to-device copies restoring the NTT/INTT operands (one small copy "
+                   "per 4th pair, the same in every mode)")
+    log("batched op list: %s" % {k: v for k, v in out.items() if isinstance(v, dict)})
+    ctx.close()
+    return out
+
+
 SERVING_MIX = {"N=2^14": 3, "N=2^15": 2, "N=2^16": 1}
 
 
-def serving_bench(n_requests, rate=200.0, level=4, pool=16, budget_gib=16):
+def serving_bench(n_requests, rate=200.0, level=4, pool=16, budget_gib=16, saturate_rate=2000.0):
     """Poisson stream of encrypted bag-of-words inferences (vocabulary 32768,
     embedding 64, 8 classes) over three parameter sets in the ratio 3:2:1
     (N = 2^14 / 2^15 / 2^16 with the batched / bag-of-words / large-ring
@@ -539,6 +672,14 @@ def serving_bench(n_requests, rate=200.0, level=4, pool=16, budget_gib=16):
         st = Scheduler(ex, policies, budget_gib << 30, continuous=cont).run(trace)
         out[mode] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.summary().items()}
         log("serving %s: %s" % (mode, out[mode]))
+    # the same mix arriving faster than one-request-at-a-time serving keeps up with
+    sat = {"rate_req_per_s": saturate_rate, "requests": n_requests}
+    for mode, cont in (("continuous", True), ("per_op", False)):
+        trace = poisson_trace(506, n_requests, saturate_rate, SERVING_MIX, {k: pool for k in specs}, words)
+        st = Scheduler(ex, policies, budget_gib << 30, continuous=cont).run(trace)
+        sat[mode] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.summary().items()}
+        log("serving at %.0f req/s, %s: %s" % (saturate_rate, mode, sat[mode]))
+    out["saturated"] = sat
     for ctx, _, _ in sets.values():
         ctx.synchronize()
     # the same sets with a 2 GiB rotation-key budget: keys beyond each set's
@@ -558,7 +699,8 @@ def serving_bench(n_requests, rate=200.0, level=4, pool=16, budget_gib=16):
         "rotation_key_budget_gib": kbudget / 2 ** 30, "resident_gib": round(res_c / 2 ** 30, 3), "requests": n_c,
         "continuous": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.summary().items()},
         "key_cache": {k: {"resident_keys": v["max_resident"], "misses": v["misses"], "hits": v["hits"],
-                          "gib_copied": round(v["bytes_in"] / 2 ** 30, 2)} for k, v in cache.items()}}
+                          "copied_ahead": v["prefetches"], "gib_copied": round(v["bytes_in"] / 2 ** 30, 2)}
+                      for k, v in cache.items()}}
     log("serving keys over budget: %s" % out["keys_over_budget"])
     for ctx, _, _ in sets_c.values():
         ctx.synchronize()
@@ -1086,6 +1228,9 @@ def main():
         kname, gbs, hbm_frac, step["achieved_gbs"], step["frac"], copy_gbs))
 
     tuning = save_tuning()
+    batched = None
+    if not args.no_batched:
+        batched = c2_bench()
     serving = None
     if args.serve_requests > 0:
         serving = serving_bench(args.serve_requests)
@@ -1122,6 +1267,7 @@ def main():
         "breakdown": breakdown,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched": batched,
         "serving": serving,
         "predict": predict,
         "paper_inference": paper_inf,

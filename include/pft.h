@@ -173,14 +173,29 @@ int pft_gen_rotation_key(pft_ctx* ctx, int32_t step, const uint64_t* a, const in
  * use).  max_resident = 0 (default): every rotation key stays in device
  * memory.  max_resident = k > 0: each rotation key generated afterwards
  * keeps a pinned host copy, and at most k keys occupy device slots; using a
- * non-resident key copies it into a slot on the context stream, evicting
- * the least recently used key (an eviction synchronizes the device first,
- * so no queued kernel still reads the slot).  Must be set before the first
- * rotation key is generated (PFT_EINVAL otherwise).  With a limited cache,
- * rotations are refused during graph capture (PFT_EINVAL: a replay would
- * read whatever key then occupies the slot).  The relinearisation key is never
+ * non-resident key copies it into a slot on a copy stream of the library's
+ * (the context stream waits for the copy through an event).  A slot is
+ * refilled only after every stream that read it has reached the point where
+ * the refill was decided (events; no device-wide synchronisation, so other
+ * contexts' streams keep running).  Victim: the resident key whose next use
+ * in the plan set by pft_key_cache_plan lies farthest ahead (keys the plan
+ * does not use first; the optimal offline choice for a known order), or,
+ * without a plan, the least recently used key.  With a plan, each rotation
+ * also starts the copy of the plan's next key if it is not resident, so the
+ * transfer overlaps the rotation.  Must be set before the first rotation
+ * key is generated (PFT_EINVAL otherwise).  With a limited cache, rotations
+ * are refused during graph capture (PFT_EINVAL: a replay would read
+ * whatever key then occupies the slot).  The relinearisation key is never
  * cached.  pft_key_cache_stats writes {max_resident, slots allocated, hits,
- * misses, bytes copied to the device} to out[5]. */
+ * misses, bytes copied to the device, keys copied ahead of use} to out[6]
+ * (a use that finds its key resident is a hit, also after a copy ahead). */
+/* The expected order of rotation steps, repeated cyclically (e.g. the
+ * rotations of one inference): steps[n_steps] (host, copied), any sign, each
+ * non-zero mod N/2 (PFT_EINVAL otherwise); n_steps = 0 clears the plan.  A
+ * rotation by a step of the plan moves the plan position past its next
+ * occurrence; steps outside the plan leave it.  Only affects which key is
+ * evicted and copied ahead, never results. */
+int pft_key_cache_plan(pft_ctx* ctx, const int32_t* steps, uint32_t n_steps);
 /* Seeded KEYGEN (Sec. 3.4; X_key, the uniform masks and X_err of SETUP, sigma
  * = 3.2 from Sec. 6.4, CKKS parameter selection): the secret, public key, relinearisation key and one
  * rotation key per listed step, every draw taken on the device from the

@@ -250,10 +250,17 @@ class Context:
         the others live in pinned host memory and are copied in on use."""
         N.check(self.lib.pft_set_key_cache(self.handle, int(max_resident)))
 
+    def key_cache_plan(self, steps):
+        """Expected cyclic order of rotation steps (eviction and copy-ahead)."""
+        arr = np.ascontiguousarray(np.asarray(list(steps), dtype=np.int32))
+        N.check(self.lib.pft_key_cache_plan(self.handle, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                            int(arr.size)))
+
     def key_cache_stats(self):
-        out = np.zeros(5, dtype=np.uint64)
+        out = np.zeros(6, dtype=np.uint64)
         N.check(self.lib.pft_key_cache_stats(self.handle, N.u64p(out)))
-        return dict(zip(("max_resident", "slots", "hits", "misses", "bytes_in"), (int(x) for x in out)))
+        return dict(zip(("max_resident", "slots", "hits", "misses", "bytes_in", "prefetches"),
+                        (int(x) for x in out)))
 
     def gen_rotation_key(self, step, a, e):
         N.check(self.lib.pft_gen_rotation_key(self.handle, int(step), N.u64p(_u64(a)), N.i64p(_i64(e))))

@@ -274,12 +274,27 @@ struct pft_ctx {
     std::vector<uint64_t*> key_pool;  // device memory of dropped switching keys, reused by new ones
     std::map<int32_t, SwitchKeyDev> rot;  // keyed by step mod N/2
     // rotation-key cache (0 = every key resident): at most rot_cache_max keys
-    // in device slots, all keys in pinned host memory, least recently used
-    // key evicted on a miss
+    // in device slots, all keys in pinned host memory.  A slot is refilled
+    // only after every stream that read it has passed that point (events, no
+    // device-wide synchronisation); keys are copied in on a copy stream of
+    // their own.  Victim: the resident key whose next use in the caller's
+    // cyclic plan lies farthest ahead (keys outside the plan first), else
+    // the least recently used.  With a plan, the next key of the plan is
+    // copied in while the current rotation runs.
     uint32_t rot_cache_max = 0;
     std::vector<uint64_t*> rot_slots;
     std::vector<int32_t> rot_slot_owner;  // normalised step, or -1
-    uint64_t rot_clock = 0, rot_hits = 0, rot_misses = 0, rot_bytes_in = 0;
+    struct SlotSync {
+        std::vector<hipStream_t> readers;  // streams with queued reads since the last fill
+        hipEvent_t ready = nullptr;        // recorded on the copy stream after the last fill
+        bool ready_pending = false;        // a copy-stream fill the readers must still wait for
+    };
+    std::vector<SlotSync> rot_sync;
+    std::map<hipStream_t, hipEvent_t> stream_ev;  // one event per stream, recorded at each slot refill
+    hipStream_t copy_st = nullptr;
+    std::vector<int32_t> rot_plan;  // normalised steps, cyclic
+    size_t rot_plan_pos = 0;
+    uint64_t rot_clock = 0, rot_hits = 0, rot_misses = 0, rot_bytes_in = 0, rot_prefetches = 0;
     uint64_t* ws = nullptr;  // scratch of one operation (key switching etc.)
     size_t ws_bytes = 0;
     uint64_t* aux = nullptr;  // buffers of composite operations (PtMatVec) that call other operations
@@ -642,11 +657,18 @@ extern "C" void pft_ctx_destroy(pft_ctx* c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
+    for (hipStream_t st : c->side) (void)hipStreamSynchronize(st);
+    if (c->copy_st) (void)hipStreamSynchronize(c->copy_st);
     for (void* p : c->allocs) dev_free(c, p);
     dev_free(c, c->ws);
     dev_free(c, c->aux);
     dev_free(c, c->cbuf);
     for (void* p : c->retired) dev_free(c, p);
+    if (c->copy_st) (void)hipStreamDestroy(c->copy_st);
+    for (auto& ss : c->rot_sync)
+        if (ss.ready) (void)hipEventDestroy(ss.ready);
+    for (auto& kv : c->stream_ev)
+        if (kv.second) (void)hipEventDestroy(kv.second);
     for (auto& kv : c->rot)
         if (kv.second.host) (void)hipHostFree(kv.second.host);
     for (hipStream_t st : c->side) {
@@ -980,6 +1002,7 @@ extern "C" int pft_gaussian_cdt(uint64_t* table, uint32_t capacity, uint32_t* co
 // the stream is drained first.
 static int drop_derived_keys(pft_ctx* c) {
     HIPCK(hipStreamSynchronize(c->stream));
+    if (c->copy_st) HIPCK(hipStreamSynchronize(c->copy_st));  // no key copy still reads a host copy
     c->pk_ok = false;
     c->rlk_ok = false;
     for (auto& kv : c->rot) {
@@ -989,6 +1012,10 @@ static int drop_derived_keys(pft_ctx* c) {
     }
     c->rot.clear();
     for (auto& o : c->rot_slot_owner) o = -1;
+    for (auto& ss : c->rot_sync) {
+        ss.readers.clear();
+        ss.ready_pending = false;
+    }
     return PFT_OK;
 }
 
@@ -1054,12 +1081,44 @@ extern "C" int pft_gen_public_key(pft_ctx* c, const uint64_t* a, const int64_t* 
 // s_prime: [L+K][N] NTT domain (device).  Builds the switching key into *dst.
 static size_t key_bytes(const pft_params* P) { return (size_t)P->dnum * 2 * (P->L + P->K) * P->n * 8; }
 
+// Distance from the cache's plan position to the next use of rotation step
+// `ns` in the cyclic plan (0: the next rotation), or SIZE_MAX if the plan
+// does not use it (or there is no plan).
+static size_t plan_next_use(const pft_ctx* c, int32_t ns) {
+    const size_t n = c->rot_plan.size();
+    for (size_t d = 0; d < n; ++d)
+        if (c->rot_plan[(c->rot_plan_pos + d) % n] == ns) return d;
+    return SIZE_MAX;
+}
+
+// Makes `fill` wait until every queued read of slot `idx` has run: each
+// stream that read the slot since its last fill records its event now (its
+// reads were enqueued earlier) and `fill` waits for it; a fill still in
+// flight on the copy stream is waited for too.  Clears the reader list.
+static int slot_wait_readers(pft_ctx* c, int idx, hipStream_t fill) {
+    pft_ctx::SlotSync& ss = c->rot_sync[idx];
+    for (hipStream_t rs : ss.readers) {
+        if (rs == fill) continue;  // stream order suffices
+        hipEvent_t& ev = c->stream_ev[rs];
+        if (!ev) HIPCK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        HIPCK(hipEventRecord(ev, rs));
+        HIPCK(hipStreamWaitEvent(fill, ev, 0));
+    }
+    ss.readers.clear();
+    if (ss.ready_pending && fill != c->copy_st) HIPCK(hipStreamWaitEvent(fill, ss.ready, 0));
+    return PFT_OK;
+}
+
 // A device slot for rotation key `step` under the limited key cache: a free
-// slot, a new one below the limit, else the least recently used key's slot
-// (that key becomes non-resident; the device is synchronised first so no
-// queued kernel still reads the slot).  Sets the key's data and slot.
-static int key_slot(pft_ctx* c, int32_t step) {
+// slot, a new one below the limit, else a victim's (the resident key whose
+// next use in the plan is farthest ahead, without a plan the least recently
+// used; never `keep`).  The victim becomes non-resident; the slot is not
+// filled here (the caller orders the fill after the slot's readers with
+// slot_wait_readers).  Sets the key's data and slot; *idx_out = the slot, or
+// -1 if every slot holds `keep`.
+static int key_slot(pft_ctx* c, int32_t step, int32_t keep, int* idx_out) {
     int idx = -1;
+    *idx_out = -1;
     for (size_t i = 0; i < c->rot_slot_owner.size(); ++i)
         if (c->rot_slot_owner[i] < 0) {
             idx = (int)i;
@@ -1071,18 +1130,25 @@ static int key_slot(pft_ctx* c, int32_t step) {
         if ((r = dalloc(c, &p, key_bytes(c->P)))) return r;
         c->rot_slots.push_back(p);
         c->rot_slot_owner.push_back(-1);
+        c->rot_sync.emplace_back();
+        HIPCK(hipEventCreateWithFlags(&c->rot_sync.back().ready, hipEventDisableTiming));
         idx = (int)c->rot_slots.size() - 1;
     }
     if (idx < 0) {
+        size_t far = 0;
         uint64_t oldest = ~0ull;
         for (size_t i = 0; i < c->rot_slots.size(); ++i) {
-            const SwitchKeyDev& o = c->rot[c->rot_slot_owner[i]];
-            if (o.last_use < oldest) {
+            const int32_t owner = c->rot_slot_owner[i];
+            if (owner == keep) continue;
+            const SwitchKeyDev& o = c->rot[owner];
+            const size_t d = plan_next_use(c, owner);
+            if (idx < 0 || d > far || (d == far && o.last_use < oldest)) {
+                far = d;
                 oldest = o.last_use;
                 idx = (int)i;
             }
         }
-        HIPCK(hipDeviceSynchronize());
+        if (idx < 0) return PFT_OK;
         SwitchKeyDev& victim = c->rot[c->rot_slot_owner[idx]];
         victim.data = nullptr;
         victim.slot = -1;
@@ -1092,6 +1158,29 @@ static int key_slot(pft_ctx* c, int32_t step) {
     k.data = c->rot_slots[idx];
     k.slot = idx;
     k.last_use = ++c->rot_clock;
+    *idx_out = idx;
+    return PFT_OK;
+}
+
+// Copies the pinned host copy of rotation key `ns` into a slot on the copy
+// stream (after the slot's readers); readers wait for the slot's `ready`
+// event.  `keep` is never evicted.  *copied = false if no slot could be
+// freed.
+static int key_fill(pft_ctx* c, int32_t ns, int32_t keep, bool* copied) {
+    *copied = false;
+    int r, idx;
+    if ((r = key_slot(c, ns, keep, &idx))) return r;
+    if (idx < 0) return PFT_OK;
+    if (!c->copy_st) HIPCK(hipStreamCreateWithFlags(&c->copy_st, hipStreamNonBlocking));
+    if ((r = slot_wait_readers(c, idx, c->copy_st))) return r;
+    SwitchKeyDev& k = c->rot[ns];
+    const size_t bytes = key_bytes(c->P);
+    HIPCK(hipMemcpyAsync(k.data, k.host, bytes, hipMemcpyHostToDevice, c->copy_st));
+    pft_ctx::SlotSync& ss = c->rot_sync[idx];
+    HIPCK(hipEventRecord(ss.ready, c->copy_st));
+    ss.ready_pending = true;
+    c->rot_bytes_in += bytes;
+    *copied = true;
     return PFT_OK;
 }
 
@@ -1212,7 +1301,14 @@ static int gen_rotation_key_core(pft_ctx* c, int32_t step, const Draws& d) {
         }
         k.host = (uint64_t*)h;
     }
-    if (!k.data && (r = key_slot(c, ns))) return r;
+    if (!k.data) {
+        int idx;
+        if ((r = key_slot(c, ns, ns, &idx))) return r;
+        if (idx < 0) return fail(PFT_ENOMEM, "no rotation-key slot");
+        // the key is written on the context stream
+        if ((r = slot_wait_readers(c, idx, c->stream))) return r;
+        c->rot_sync[idx].ready_pending = false;
+    }
     if ((r = gen_switch_key(c, c->s_prime, d, &k))) return r;
     HIPCK(hipMemcpyAsync(k.host, k.data, bytes, hipMemcpyDeviceToHost, c->stream));
     HIPCK(hipStreamSynchronize(c->stream));
@@ -1254,6 +1350,19 @@ extern "C" int pft_set_key_cache(pft_ctx* c, uint32_t max_resident) {
     return PFT_OK;
 }
 
+extern "C" int pft_key_cache_plan(pft_ctx* c, const int32_t* steps, uint32_t n_steps) {
+    if (!c || (n_steps && !steps)) return fail(PFT_EINVAL, "null argument");
+    std::vector<int32_t> plan;
+    for (uint32_t i = 0; i < n_steps; ++i) {
+        const int32_t ns = norm_step(steps[i], c->P->n);
+        if (ns == 0) return fail(PFT_EINVAL, "rotation step %d is 0 mod N/2", steps[i]);
+        plan.push_back(ns);
+    }
+    c->rot_plan.swap(plan);
+    c->rot_plan_pos = 0;
+    return PFT_OK;
+}
+
 extern "C" int pft_key_cache_stats(const pft_ctx* c, uint64_t* out) {
     if (!c || !out) return fail(PFT_EINVAL, "null argument");
     out[0] = c->rot_cache_max;
@@ -1261,6 +1370,7 @@ extern "C" int pft_key_cache_stats(const pft_ctx* c, uint64_t* out) {
     out[2] = c->rot_hits;
     out[3] = c->rot_misses;
     out[4] = c->rot_bytes_in;
+    out[5] = c->rot_prefetches;
     return PFT_OK;
 }
 
@@ -1849,9 +1959,11 @@ extern "C" int pft_rescale_batch(pft_ctx* c, uint32_t n, const pft_ct* in, uint3
 static bool has_rot(pft_ctx* c, int32_t step) { return c->rot.count(norm_step(step, c->P->n)) != 0; }
 
 // The rotation key for `step`, made resident first under a limited key
-// cache (a miss copies the pinned host copy into a slot on the context
-// stream; with a limited cache nothing is captured).  Null with *err set if
-// the key is missing or cannot be made resident.
+// cache (a miss copies the pinned host copy into a slot; the context stream
+// waits for it; with a limited cache nothing is captured).  With a plan, the
+// next key of the plan is then copied in ahead of its use.  The context
+// stream is noted as a reader of the key's slot.  Null with *err set if the
+// key is missing or cannot be made resident.
 static const SwitchKeyDev* use_rot(pft_ctx* c, int32_t step, int* err) {
     const int32_t ns = norm_step(step, c->P->n);
     auto it = c->rot.find(ns);
@@ -1860,28 +1972,46 @@ static const SwitchKeyDev* use_rot(pft_ctx* c, int32_t step, int* err) {
         return nullptr;
     }
     SwitchKeyDev& k = it->second;
-    if (c->capturing && c->rot_cache_max) {
+    if (!c->rot_cache_max) return &k;
+    if (c->capturing) {
         // a replay would read whatever key then occupies the slot
         *err = fail(PFT_EINVAL, "rotations cannot be captured while the rotation-key cache is limited");
         return nullptr;
     }
-    if (k.data) {
-        k.last_use = ++c->rot_clock;
-        if (c->rot_cache_max) ++c->rot_hits;
-        return &k;
-    }
+    const size_t d = plan_next_use(c, ns);
+    if (d != SIZE_MAX) c->rot_plan_pos = (c->rot_plan_pos + d + 1) % c->rot_plan.size();
     int r;
-    if ((r = key_slot(c, ns))) {
-        *err = r;
-        return nullptr;
+    if (k.data) {
+        ++c->rot_hits;
+    } else {
+        bool copied;
+        if ((r = key_fill(c, ns, INT32_MIN, &copied))) {
+            *err = r;
+            return nullptr;
+        }
+        ++c->rot_misses;
     }
-    const size_t bytes = key_bytes(c->P);
-    if (hipMemcpyAsync(k.data, k.host, bytes, hipMemcpyHostToDevice, c->stream) != hipSuccess) {
+    k.last_use = ++c->rot_clock;
+    pft_ctx::SlotSync& ss = c->rot_sync[k.slot];
+    if (ss.ready_pending && hipStreamWaitEvent(c->stream, ss.ready, 0) != hipSuccess) {
         *err = fail(PFT_EHIP, "rotation key upload: %s", hipGetErrorString(hipGetLastError()));
         return nullptr;
     }
-    ++c->rot_misses;
-    c->rot_bytes_in += bytes;
+    if (std::find(ss.readers.begin(), ss.readers.end(), c->stream) == ss.readers.end())
+        ss.readers.push_back(c->stream);
+    if (!c->rot_plan.empty()) {
+        // copy the plan's next key in while this rotation runs
+        const int32_t nxt = c->rot_plan[c->rot_plan_pos];
+        auto jt = c->rot.find(nxt);
+        if (jt != c->rot.end() && !jt->second.data) {
+            bool copied;
+            if ((r = key_fill(c, nxt, ns, &copied))) {
+                *err = r;
+                return nullptr;
+            }
+            if (copied) ++c->rot_prefetches;
+        }
+    }
     return &k;
 }
 

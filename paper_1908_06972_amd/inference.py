@@ -30,16 +30,24 @@ class BowModel:
         self.c_pad = O_pad.shape[1]
         self.stage2 = ctx.ptmat(O_pad.T, self.c_pad, dim, 1, level - 2)
 
+    @staticmethod
+    def _steps(m):
+        # the order pft_ptmatvec rotates in: baby steps, giant steps, then
+        # the rotate-and-sum over the n_i / n_o blocks
+        b, G = m.b, m.G
+        out = list(range(1, b)) + [g * b for g in range(1, G)]
+        s = m.n_o
+        while s < m.n_i:
+            out.append(s)
+            s *= 2
+        return out
+
     def rotation_steps(self):
-        def steps(m):
-            b, G = m.b, m.G
-            out = list(range(1, b)) + [g * b for g in range(1, G)]
-            s = m.n_o
-            while s < m.n_i:
-                out.append(s)
-                s *= 2
-            return out
-        return sorted(set(steps(self.stage1) + steps(self.stage2)))
+        return sorted(set(self._steps(self.stage1) + self._steps(self.stage2)))
+
+    def rotation_order(self):
+        """The rotation steps of one inference in the order they run."""
+        return self._steps(self.stage1) + self._steps(self.stage2)
 
 
 def encrypted_inference(ctx, model, inputs, words):

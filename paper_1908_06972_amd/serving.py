@@ -294,6 +294,7 @@ def build_sets(specs, H, O, pool_size, level, draws, key_seed=77, doc_seed=78, k
             kb = key_bytes(lp)
             if len(steps) * kb > share:
                 ctx.set_key_cache(max(1, share // kb))
+                ctx.key_cache_plan(model.rotation_order())
         for st in steps:
             a, e = draws.switch_key_draws(key_seed, 5000 + st, n, lp.key_moduli(), lp.dnum)
             ctx.gen_rotation_key(st, a, e)

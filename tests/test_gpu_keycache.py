@@ -100,3 +100,30 @@ def test_key_cache_refusals(two_slots):
     # the context still works after the refused capture
     w.ctx.rotate(g, 2, out=out)
     w.ctx.synchronize()
+
+
+def test_plan_eviction_and_copy_ahead():
+    """With the rotation order given as a plan, the cache evicts the key used
+    farthest ahead and copies the next key in while the current rotation
+    runs: a cyclic order over more keys than slots then hits, and every
+    result stays bit-exact."""
+    import torch
+    assert torch.cuda.is_available()
+    w = World(2)
+    w.ctx.key_cache_plan(STEPS)
+    g, o = w.enc_pair(90)
+    before = w.ctx.key_cache_stats()
+    for _ in range(3):
+        for st in STEPS:
+            g = w.ctx.rotate(g, st)
+            o = C.rotate(w.op, o, st, w.keys[st])
+    w.assert_same(g, o)
+    after = w.ctx.key_cache_stats()
+    assert after["prefetches"] > before["prefetches"]
+    assert after["hits"] - before["hits"] >= 10  # each key after the first is copied in ahead of its use
+    assert after["slots"] == 2
+    # a rotation outside the plan still works and leaves results exact
+    w.ctx.key_cache_plan([])
+    g = w.ctx.rotate(g, 4)
+    o = C.rotate(w.op, o, 4, w.keys[4])
+    w.assert_same(g, o)
