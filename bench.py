@@ -982,18 +982,23 @@ def cpu_baseline_full(reps=10):
     res = {"nproc": nproc, "cpu_model": model, "threads": threads, "reps": reps}
     if threads > 1:
         env = dict(os.environ, OMP_NUM_THREADS="1")
+        log("cpu baseline: one-thread child process")
         out = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-full", "--reps",
-                              str(reps)], env=env, capture_output=True, text=True, check=True).stdout
+                              str(reps)], env=env, stdout=subprocess.PIPE, text=True, check=True).stdout
         res["one_thread"] = json.loads(out.strip().splitlines()[-1])
     limb, poly = limb_ntt_seconds(reps, threads)
     res["limb_ntt_s"], res["poly_ntt_s"] = limb, poly
+    log("cpu baseline (%d threads): limb NTT %.4fs, 24-limb NTT %.4fs" % (threads, limb, poly))
     for name in ("C1", "C3"):
         w = OracleWorld(name)
         r = reps if name == "C1" or threads > 1 else max(3, reps // 3)
-        res[name] = {"hmult_relin_s": median_seconds(w.hmult, r), "rescale_s": median_seconds(w.rescale, r),
-                     "rotate_add_s": median_seconds(w.rotate_add, r), "runs": r}
+        res[name] = {"runs": r}
+        for op, fn in (("hmult_relin_s", w.hmult), ("rescale_s", w.rescale), ("rotate_add_s", w.rotate_add)):
+            res[name][op] = median_seconds(fn, r)
+            log("cpu baseline (%d threads): %s %s %.3fs (median of %d)" % (threads, name, op, res[name][op], r))
     if threads > 1:
         res["C4_inference_s"] = oracle_inference_seconds()
+        log("cpu baseline (%d threads): one bag-of-words inference %.1fs" % (threads, res["C4_inference_s"]))
     return res
 
 

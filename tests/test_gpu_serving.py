@@ -57,7 +57,10 @@ def test_keys_beyond_budget_served_through_the_key_cache():
     trace = poisson_trace(506, 12, 2000.0, {"n12": 1}, {"n12": 4}, words_s)
     stats = Scheduler(GpuExecutor(small), pol_s, budget_bytes=8 << 30).run(trace)
     assert stats.summary()["completed"] == len(trace)
-    assert ctx_s.key_cache_stats()["misses"] > 0
+    st = ctx_s.key_cache_stats()
+    # keys were copied in (on a miss or ahead of their use along the plan)
+    # and the plan's copy-ahead turned uses into hits
+    assert st["bytes_in"] > 0 and st["misses"] + st["prefetches"] > 0 and st["hits"] > 0
     from paper_1908_06972_amd.inference import encrypted_inference
     ctx_f, model_f, pool_f = full["n12"]
     for r in trace:
