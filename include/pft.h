@@ -256,6 +256,24 @@ int pft_mul_plain(pft_ctx* ctx, const pft_ct* a, const pft_pt* p, pft_ct* out); 
 /* HMUL followed by relinearisation (Table 2's HMUL+REL), no rescale. */
 int pft_mul_relin(pft_ctx* ctx, const pft_ct* a, const pft_ct* b, pft_ct* out);
 int pft_mul_relin_batch(pft_ctx* ctx, uint32_t n, const pft_ct* a, const pft_ct* b, pft_ct* out);
+/* pft_mul_relin_batch for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same kernels and results, with the key-switching
+ * workspace in a fixed device scratch of 64 MiB per GPU (a file-scope device
+ * array that each GPU holds until the process ends) instead of the
+ * context's growable workspace.  No hipMalloc, hipFree or other allocation
+ * happens in the call; the NTT autotuner is not run for new batch classes
+ * (their default schedule is used; results do not depend on it).  Each
+ * level group of the batch needs n_group * (3 level + level + beta (level +
+ * K) + 2 (level + K) + 2 level) * N * 8 bytes, beta = ceil(level / alpha);
+ * a batch with a group above 64 MiB is refused with PFT_ENOMEM before
+ * anything is enqueued (e.g. one ciphertext at N = 2^15 and 16 limbs fits;
+ * one at N = 2^16 and 24 limbs does not).  Calls on one GPU share its
+ * scratch: calls that overlap in time on different streams of the same GPU
+ * race and must be ordered by the caller.  The scratch needs no clearing
+ * (every word a call reads it has written first).  PFT_EHIP if the scratch's
+ * device address could not be resolved when the context was created. */
+int pft_mul_relin_batch_noalloc(pft_ctx* ctx, uint32_t n, const pft_ct* a, const pft_ct* b, pft_ct* out);
 /* RESCALE by q_{level-1} (Sec. 5.1, Eq. (1) and Alg. 3).  mode 0 rounds
  * (adds (q-1)/2 before the exact division, the RESCALE of Sec. 3.4), mode 1
  * floors (Alg. 3 as printed), PFT_RESCALE_DEFAULT takes the parameter set's

@@ -7,7 +7,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpft.so")
-SOURCES = ["ntt.hip", "ckks.hip", "sampler.hip", "api.cpp"]
+SOURCES = ["ntt.hip", "ckks.hip", "sampler.hip", "noalloc.hip", "api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -341,6 +341,13 @@ class Context:
         N.check(self.lib.pft_mul_relin_batch(self.handle, len(a), A, B, O))
         return [o.sync_from(O[i]) for i, o in enumerate(out)]
 
+    def mul_relin_batch_noalloc(self, a, b, out):
+        """mul_relin_batch with the workspace in the library's fixed device
+        scratch: no device allocation in the call (outputs must be given)."""
+        A, B, O = self._arr(a), self._arr(b), self._arr(out)
+        N.check(self.lib.pft_mul_relin_batch_noalloc(self.handle, len(a), A, B, O))
+        return [o.sync_from(O[i]) for i, o in enumerate(out)]
+
     def rescale(self, a, mode=0, out=None):
         out = out or self.empty_ct(a.level - 1)
         da, do = a.desc(), out.desc()

@@ -295,6 +295,7 @@ struct pft_ctx {
     std::vector<int32_t> rot_plan;  // normalised steps, cyclic
     size_t rot_plan_pos = 0;
     uint64_t rot_clock = 0, rot_hits = 0, rot_misses = 0, rot_bytes_in = 0, rot_prefetches = 0;
+    uint64_t* scratch = nullptr;  // this device's fixed scratch (noalloc.hip), resolved at creation
     uint64_t* ws = nullptr;  // scratch of one operation (key switching etc.)
     size_t ws_bytes = 0;
     uint64_t* aux = nullptr;  // buffers of composite operations (PtMatVec) that call other operations
@@ -644,6 +645,9 @@ extern "C" int pft_ctx_create_alloc(const pft_params* P, int device, void* strea
     c->stream = (hipStream_t)stream;
     c->prof.st = c->stream;
     for (uint64_t m : P->mods) c->fp_rows.push_back(ntt_fp(m) ? 1u : 0u);
+    // the device address of this GPU's fixed scratch (null if unavailable:
+    // then only the allocation-free entry point refuses)
+    if (noalloc_scratch_init(device, &c->scratch)) c->scratch = nullptr;
     int r = build_tables(c);
     if (r) {
         pft_ctx_destroy(c);
@@ -1848,7 +1852,26 @@ extern "C" int pft_mul_relin(pft_ctx* c, const pft_ct* a, const pft_ct* b, pft_c
     return pft_mul_relin_batch(c, 1, a, b, out);
 }
 
+// HMUL + relinearisation of n pairs.  fixed: null, the context workspace
+// (grown as needed); else a caller-provided device scratch of fixed_bytes:
+// every level group's workspace must fit in it (checked before anything is
+// enqueued; PFT_ENOMEM otherwise), and the NTT autotuner (which allocates)
+// is not consulted for new batch classes.
+static int mul_relin_core(pft_ctx* c, uint32_t n, const pft_ct* a, const pft_ct* b, pft_ct* out, uint64_t* fixed,
+                          size_t fixed_bytes);
+
 extern "C" int pft_mul_relin_batch(pft_ctx* c, uint32_t n, const pft_ct* a, const pft_ct* b, pft_ct* out) {
+    return mul_relin_core(c, n, a, b, out, nullptr, 0);
+}
+
+extern "C" int pft_mul_relin_batch_noalloc(pft_ctx* c, uint32_t n, const pft_ct* a, const pft_ct* b, pft_ct* out) {
+    if (!c) return fail(PFT_EINVAL, "null ctx");
+    if (!c->scratch) return fail(PFT_EHIP, "the fixed device scratch of device %d is not available", c->device);
+    return mul_relin_core(c, n, a, b, out, c->scratch, PFT_NOALLOC_SCRATCH_BYTES);
+}
+
+static int mul_relin_core(pft_ctx* c, uint32_t n, const pft_ct* a, const pft_ct* b, pft_ct* out, uint64_t* fixed,
+                          size_t fixed_bytes) {
     if (!c || !a || !b || !out) return fail(PFT_EINVAL, "null argument");
     if (!c->rlk_ok) return fail(PFT_ENOKEY, "no relinearisation key for the current secret");
     int r;
@@ -1859,13 +1882,33 @@ extern "C" int pft_mul_relin_batch(pft_ctx* c, uint32_t n, const pft_ct* a, cons
         if (out[i].data == a[i].data || out[i].data == b[i].data) return fail(PFT_EINVAL, "output aliases an input");
     }
     const pft_params* P = c->P;
+    if (fixed) {
+        // every level group must fit the fixed scratch: refuse before any launch
+        r = for_level_groups(n, a, [&](const std::vector<uint32_t>& g) -> int {
+            const uint32_t l = a[g[0]].level;
+            const size_t need = g.size() * ks_layout(P, l, 3ull * l * P->n).end * 8;
+            if (need > fixed_bytes)
+                return fail(PFT_ENOMEM,
+                            "HMUL+relin of %zu ciphertexts at level %u needs %zu bytes of scratch, more than the "
+                            "fixed %zu bytes",
+                            g.size(), l, need, fixed_bytes);
+            return PFT_OK;
+        });
+        if (r) return r;
+    }
+    struct NoTune {  // no autotuning (it allocates) while the fixed scratch is in use
+        pft_ctx* c;
+        bool was;
+        ~NoTune() { c->ntt_tune = was; }
+    } nt{c, c->ntt_tune};
+    if (fixed) c->ntt_tune = false;
     return for_level_groups(n, a, [&](const std::vector<uint32_t>& g) -> int {
         const uint32_t l = a[g[0]].level, cnt = (uint32_t)g.size();
         const uint64_t nl = (uint64_t)l * P->n;
         const KsLayout K = ks_layout(P, l, 3 * nl);
         int rr;
-        if ((rr = ensure_ws(c, (size_t)cnt * K.end * 8))) return rr;
-        const WsRef ws{c->ws, K.end};
+        if (!fixed && (rr = ensure_ws(c, (size_t)cnt * K.end * 8))) return rr;
+        const WsRef ws{fixed ? fixed : c->ws, K.end};
         ItemPtrs A{}, B{}, O{};
         for (uint32_t z = 0; z < cnt; ++z) {
             A.p[z] = a[g[z]].data;

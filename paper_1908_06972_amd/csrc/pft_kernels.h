@@ -228,6 +228,14 @@ void launch_add_const_b(uint32_t n, const ItemPtrs& in, const ItemPtrs& out, con
 void launch_ct_dot_b(uint32_t n, const ItemPtrs& e, uint32_t J, WsRef xs, uint64_t off_x, uint64_t ct_words, WsRef ws,
                      uint64_t off_d, uint32_t level, const DevTables& t, uint32_t log_n, hipStream_t st);
 
+// The fixed scratch of the allocation-free entry point (noalloc.hip): a
+// file-scope device array of PFT_NOALLOC_SCRATCH_BYTES per GPU.  Resolves
+// (once per device, with `device` current) and returns its device address;
+// 0 on success, -1 if the device is not current or the symbol lookup fails.
+#define PFT_NOALLOC_SCRATCH_BYTES (64ull << 20)
+#define PFT_NOALLOC_MAX_DEVICES 64
+int noalloc_scratch_init(int device, uint64_t** out);
+
 // Seeded draws (sampler.hip): Philox4x64-10 streams keyed by (k0, k1).
 #define PFT_GAUSS_BOUND 19  // the discrete Gaussian's support is -19..19
 struct SampleModuli {

@@ -131,6 +131,8 @@ SIGNATURES = [
      ctypes.c_int),
     ("pft_key_cache_stats", [_vp, _u64p], ctypes.c_int),
     ("pft_key_cache_plan", [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_uint32], ctypes.c_int),
+    ("pft_mul_relin_batch_noalloc", [_vp, ctypes.c_uint32, ctypes.POINTER(CtDesc), ctypes.POINTER(CtDesc),
+                                     ctypes.POINTER(CtDesc)], ctypes.c_int),
     ("pft_ptdot_create", [_vp, _dblp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, _vp], ctypes.c_int),
     ("pft_ptdot_create_from_coeffs", [_vp, _i64p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_double,
                                       _vp], ctypes.c_int),
