@@ -159,13 +159,15 @@ def _step_dispatches(rows, key_id, key_start):
     return [r for r in rows if int(r[key_id]) >= first]
 
 
-def summarize(trace_dir, fetch_dir, write_dir, kernel, kid, commands, n_top=6):
+def summarize(trace_dir, fetch_dir, write_dir, kernel, kid, commands, n_top=6, sq_dir=None):
     """Markdown summary of three rocprofv3 runs of bench.py: a kernel trace
     (durations) and two counter runs (FETCH_SIZE with SQ_INSTS_VALU, then
     WRITE_SIZE), each restricted to the dispatches of the job steps, with
     counter figures for the n_top longest kernels (or `kernel`).  The copy
     kernel k_copy_rows_b (8 bytes read and 8 written per work-item)
-    calibrates the byte counters."""
+    calibrates the byte counters.  sq_dir: an optional fourth run with the
+    SQ counters SQ_WAVE_CYCLES, SQ_WAIT_INST_ANY, SQ_ACTIVE_INST_VALU,
+    SQ_INSTS_LDS and SQ_LDS_BANK_CONFLICT, summarised per kernel."""
     trace = _step_dispatches(_csv_rows(_find(trace_dir, "kernel_trace.csv")), "Dispatch_Id", "Start_Timestamp")
     short_name = lambda n: n.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "")  # noqa: E731
     per = {}
@@ -242,6 +244,28 @@ def summarize(trace_dir, fetch_dir, write_dir, kernel, kid, commands, n_top=6):
             fmt(rec["valu_insts_per_launch"], "%.4g")))
         recs.append(rec)
     out.append("")
+    if sq_dir:
+        out.append("Issue counters over the same dispatches, per launch (wave cycles summed over waves; `wait` = "
+                   "SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES, the share of a wave's life spent waiting on a counter; `valu` "
+                   "= SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES per wave, times the waves resident per SIMD for the "
+                   "SIMD's VALU share; `conflict/LDS` = SQ_LDS_BANK_CONFLICT cycles per LDS instruction):")
+        out.append("")
+        out.append("| kernel | LDS insts | bank-conflict cycles | conflict/LDS | wait | valu |")
+        out.append("|---|---|---|---|---|---|")
+        for target in targets:
+            vals = {}
+            for ctr in ("SQ_WAVE_CYCLES", "SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_VALU", "SQ_INSTS_LDS",
+                        "SQ_LDS_BANK_CONFLICT"):
+                v, _ = per_dispatch(sq_dir, ctr, target)
+                vals[ctr] = sum(v) / len(v) if v else None
+            wc, lds, bc = vals["SQ_WAVE_CYCLES"], vals["SQ_INSTS_LDS"], vals["SQ_LDS_BANK_CONFLICT"]
+            fmt = lambda v, f: (f % v) if v is not None else "-"  # noqa: E731
+            out.append("| %s | %s | %s | %s | %s | %s |" % (
+                target, fmt(lds, "%.3g"), fmt(bc, "%.3g"), fmt(bc / lds if lds and bc is not None else None, "%.2f"),
+                fmt(vals["SQ_WAIT_INST_ANY"] / wc if wc and vals["SQ_WAIT_INST_ANY"] is not None else None, "%.2f"),
+                fmt(vals["SQ_ACTIVE_INST_VALU"] / wc if wc and vals["SQ_ACTIVE_INST_VALU"] is not None else None,
+                    "%.2f")))
+        out.append("")
     # every kernel of the profiled steps: counted traffic per step
     def step_total(dirpath, counter):
         rows = _step_dispatches(_csv_rows(_find(dirpath, "counter_collection.csv")), "Dispatch_Id", "Start_Timestamp")
@@ -376,6 +400,7 @@ def parse():
                     help="kernel the --summarize counters are collected for; auto = the longest in the trace")
     ap.add_argument("--family", type=int, default=0)
     ap.add_argument("--commands", nargs="*", default=[])
+    ap.add_argument("--sq", default=None, help="with --summarize: directory of the SQ counter run")
     ap.add_argument("--tuning-in", default=DEFAULT_TUNING,
                     help="JSON table of NTT schedules (from --tuning-out) to use instead of tuning; the default is the "
                          "table the autotuner produced for this workload, so kernel choices repeat run to run")
@@ -1042,7 +1067,7 @@ def oracle_inference_seconds():
 def main():
     args = parse()
     if args.summarize:
-        print(summarize(*args.summarize, args.kernel, args.family, args.commands), end="")
+        print(summarize(*args.summarize, args.kernel, args.family, args.commands, sq_dir=args.sq), end="")
         return
     if args.cpu_baseline_full:
         print(json.dumps(cpu_baseline_full(args.reps)), flush=True)

@@ -466,8 +466,10 @@ int pft_ntt_tuning_import(pft_ctx* ctx, const uint32_t* entries, uint32_t count)
  * {12, 13, 14, 16}, and at most 8 digits are active, one kernel takes each
  * extended row through its row pass and accumulates its products with the
  * key, so the extended digits are read once and only the accumulators are
- * written (otherwise as mode 2).  The results are identical in every mode.
- * PFT_EINVAL for any other mode. */
+ * written (otherwise as mode 2); its rows below 2^50 take two digits through
+ * each row pass together (one twiddle load and one LDS barrier serve both).
+ * Mode 4 is mode 3 with one digit per row pass.  The results are identical
+ * in every mode.  PFT_EINVAL for any other mode. */
 int pft_bconv_mode(pft_ctx* ctx, int mode);
 
 /* ---- op-list executor ---------------------------------------------------

@@ -526,13 +526,14 @@ class Context:
         self.lib.pft_ntt_candidates(self.params.handle, buf, n)
         return [self._sched_from(buf[4 * i:4 * i + 4]) for i in range(n)]
 
-    def bconv_mode(self, mfma: bool, fused: bool = True, inner: bool = True):
+    def bconv_mode(self, mfma: bool, fused: bool = True, inner: bool = True, pairs: bool = True):
         """Base conversions on the matrix cores (True, the default) or the
         VALU; with `fused` (the default) the conversions also apply the
         adjacent passes of the transforms, and with `inner` (the default,
         needs `fused`) the key inner product runs in the row pass of ModUp's
-        rows (pft_bconv_mode 3)."""
-        mode = (3 if inner else 2) if fused else 1
+        rows, two digits per row pass with `pairs` (pft_bconv_mode 3, the
+        default) or one (mode 4)."""
+        mode = ((3 if pairs else 4) if inner else 2) if fused else 1
         N.check(self.lib.pft_bconv_mode(self.handle, mode if mfma else 0))
 
     def ntt_autotune(self, enable: bool):

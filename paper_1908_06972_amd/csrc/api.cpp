@@ -310,6 +310,7 @@ struct pft_ctx {
     bool bconv_mfma = true;  // base conversions on the matrix cores
     bool bconv_fuse = true;  // conversions fused with the adjacent transform passes (MFMA only)
     bool inner_fuse = true;  // key inner product fused with the row pass of ModUp's rows (needs bconv_fuse)
+    bool inner_pairs = true;  // the fused inner product takes two digits through each row pass
     std::vector<uint32_t> fp_rows;  // [L+K]: 1 where the modulus runs fp64 arithmetic (below 2^50)
     bool ntt_tune = true;
     NttSchedule ntt_pinned[2] = {};
@@ -1752,7 +1753,7 @@ static void key_switch_b(pft_ctx* c, uint32_t n, WsRef ws, const KsLayout& K, ui
                           for (uint32_t z = 0; z < n; ++z) c1[z] = rot->src.p[z] + nl;
                       launch_row_inner(n, ws, off_d, K.off_ext, K.off_acc, key.data, level, c->kc, c->tabs,
                                        c->fp_rows.data(), lg, c1, fold ? rot->kappa : 0, fold ? rot->kappa_inv : 0,
-                                       c->stream);
+                                       c->inner_pairs, c->stream);
                   },
                   1024u + lm);
         } else {
@@ -2918,11 +2919,14 @@ extern "C" int pft_ntt_candidates(const pft_params* p, uint32_t* scheds, uint32_
 
 extern "C" int pft_bconv_mode(pft_ctx* c, int mode) {
     if (!c) return fail(PFT_EINVAL, "null context");
-    if (mode < 0 || mode > 3)
-        return fail(PFT_EINVAL, "mode must be 0 (VALU), 1 (MFMA), 2 (MFMA, fused passes) or 3 (2 + fused inner product)");
+    if (mode < 0 || mode > 4)
+        return fail(PFT_EINVAL,
+                    "mode must be 0 (VALU), 1 (MFMA), 2 (MFMA, fused passes), 3 (2 + fused inner product, digit "
+                    "pairs) or 4 (3 with one digit per row pass)");
     c->bconv_mfma = mode >= 1;
     c->bconv_fuse = mode >= 2;
-    c->inner_fuse = mode == 3;
+    c->inner_fuse = mode >= 3;
+    c->inner_pairs = mode == 3;
     return PFT_OK;
 }
 

@@ -173,30 +173,44 @@ __device__ __forceinline__ void run_phase(uint64_t (&x)[1 << EB], uint32_t l, ui
     }
 }
 
-// LDS word of element r of sub-problem c: c S + r + P (r >> 4).  The address
-// is affine in the register index e of every arrangement (so ds_read/ds_write
-// take immediate offsets).  (S, P) are chosen per M for the LDS serving 16
-// lanes x 8 bytes per cycle: every access pattern of the pass -- a register
-// phase's arrangement under either lane mapping, and the staging order --
-// puts each group of 16 consecutive lanes on distinct bank pairs (radix 6
-// and 7 keep a two-way conflict on one row-pass pattern).
-// (8 residues per thread: radix 6 and 7 use their own (S, P); at most a
-// two-way conflict remains on one pattern of radix 4 and 6-10.)
+// LDS word of element r of sub-problem c: c S + r + P (r >> 4), or, where
+// the 8-byte words of a 16-lane group cannot all be spread over distinct
+// bank pairs by a padding, c S + (r ^ h(r)) with h(r) = ((r >> XA) & 7) |
+// (((r >> XB) & 1) << 3): the low four bits of r are permuted by higher
+// ones (a bijection within each sub-problem).  The padded form is affine in
+// the register index e of every arrangement (so ds_read/ds_write take
+// immediate offsets).  The parameters are chosen per (M, residues per
+// thread) by an exhaustive model of the LDS serving 16 lanes x 8 bytes per
+// cycle over every access pattern of the pass -- each register phase's
+// arrangement under both lane mappings, the staging order and the
+// element-pair order of the staged store: with 16 residues per thread every
+// row-pass pattern is conflict-free (radix 6 and 7 keep a two-way conflict
+// on one), and with 8 the swizzled forms make the row passes of radix 7-12
+// conflict-free where any padding leaves two-way conflicts (radix 9 and 10
+// keep one two-way conflict pattern as column passes).
 template <int LOG_M, int EB> struct LdsPad;
-template <int EB> struct LdsPad<4, EB> { static constexpr uint32_t S = 17, P = 0; };
-template <> struct LdsPad<6, 4> { static constexpr uint32_t S = 69, P = 1; };
-template <> struct LdsPad<6, 3> { static constexpr uint32_t S = 73, P = 2; };
-template <> struct LdsPad<7, 4> { static constexpr uint32_t S = 145, P = 2; };
-template <> struct LdsPad<7, 3> { static constexpr uint32_t S = 137, P = 1; };
-template <int EB> struct LdsPad<8, EB> { static constexpr uint32_t S = 273, P = 1; };
-template <int EB> struct LdsPad<9, EB> { static constexpr uint32_t S = 546, P = 1; };
-template <int EB> struct LdsPad<10, EB> { static constexpr uint32_t S = 1092, P = 1; };
-template <int EB> struct LdsPad<12, EB> { static constexpr uint32_t S = 4352, P = 1; };
+template <int EB> struct LdsPad<4, EB> { static constexpr uint32_t S = 17, P = 0, XA = 0, XB = 0; };
+template <> struct LdsPad<6, 4> { static constexpr uint32_t S = 69, P = 1, XA = 0, XB = 0; };
+template <> struct LdsPad<6, 3> { static constexpr uint32_t S = 73, P = 2, XA = 0, XB = 0; };
+template <> struct LdsPad<7, 4> { static constexpr uint32_t S = 145, P = 2, XA = 0, XB = 0; };
+template <> struct LdsPad<7, 3> { static constexpr uint32_t S = 129, P = 0, XA = 4, XB = 4; };
+template <int EB> struct LdsPad<8, EB> { static constexpr uint32_t S = 273, P = 1, XA = 0, XB = 0; };
+template <> struct LdsPad<8, 3> { static constexpr uint32_t S = 257, P = 0, XA = 4, XB = 5; };
+template <int EB> struct LdsPad<9, EB> { static constexpr uint32_t S = 546, P = 1, XA = 0, XB = 0; };
+template <> struct LdsPad<9, 3> { static constexpr uint32_t S = 514, P = 0, XA = 4, XB = 6; };
+template <int EB> struct LdsPad<10, EB> { static constexpr uint32_t S = 1092, P = 1, XA = 0, XB = 0; };
+template <> struct LdsPad<10, 3> { static constexpr uint32_t S = 1026, P = 0, XA = 4, XB = 4; };
+template <int EB> struct LdsPad<12, EB> { static constexpr uint32_t S = 4352, P = 1, XA = 0, XB = 0; };
+template <> struct LdsPad<12, 3> { static constexpr uint32_t S = 4096, P = 0, XA = 4, XB = 6; };
 template <int LOG_M, int EB>
 constexpr uint32_t lds_words() { return (4096u >> LOG_M) * LdsPad<LOG_M, EB>::S; }
 template <int LOG_M, int EB>
 __device__ __forceinline__ uint32_t lds_at(uint32_t c, uint32_t r) {
-    return c * LdsPad<LOG_M, EB>::S + r + LdsPad<LOG_M, EB>::P * (r >> 4);
+    using L = LdsPad<LOG_M, EB>;
+    if constexpr (L::XA != 0)
+        return c * L::S + (r ^ (((r >> L::XA) & 7u) | (((r >> L::XB) & 1u) << 3)));
+    else
+        return c * L::S + r + L::P * (r >> 4);
 }
 
 template <int LOG_M, int PH, int EB>
@@ -210,11 +224,59 @@ __device__ __forceinline__ void lds_write(const uint64_t (&x)[1 << EB], uint64_t
     for (int e = 0; e < (1 << EB); ++e) lds[lds_at<LOG_M, EB>(c, Phase<LOG_M, PH, EB>::r_of(l, e))] = x[e];
 }
 
+// Where thread-index bit b lands in the word index c M + r of register
+// phase PH (COL: c = tid mod C, l = tid / C; otherwise c = tid / T, l =
+// tid mod T; r = Phase::r_of(l, e)).
+template <int LOG_M, int EB, bool COL>
+constexpr int tid_bit_pos(int ph, int b) {
+    constexpr int LT = LOG_M - EB;  // log2 of the threads per sub-problem
+    constexpr int LC = 12 - LOG_M;  // log2 of the sub-problems per workgroup
+    const int hb = LOG_M - 1 - EB * ph;
+    const int wlo = hb - (EB - 1) >= 0 ? hb - (EB - 1) : 0;
+    int lb;
+    if (COL) {
+        if (b < LC) return LOG_M + b;
+        lb = b - LC;
+    } else {
+        if (b >= LT) return LOG_M + (b - LT);
+        lb = b;
+    }
+    return lb < wlo ? lb : lb + EB;
+}
+// Whether the exchange between register phases pa and pb stays inside each
+// wave: every wave reads back exactly the words it wrote (its wave-index
+// bits land on the same word-index bits in both phases, and its lane bits
+// and element window cover the same set).  Such an exchange needs no
+// workgroup barrier: a wave's LDS instructions execute in order, so its
+// reads see its own earlier writes, and no other wave touches those words.
+template <int LOG_M, int EB, bool COL>
+constexpr bool wave_local_exchange(int pa, int pb) {
+    constexpr int LNT = 12 - EB;  // log2 of the threads per workgroup
+    if (LNT <= 6) return true;
+    for (int b = 6; b < LNT; ++b)
+        if (tid_bit_pos<LOG_M, EB, COL>(pa, b) != tid_bit_pos<LOG_M, EB, COL>(pb, b)) return false;
+    auto varying = [](int ph) {
+        const int hb = LOG_M - 1 - EB * ph;
+        const int wlo = hb - (EB - 1) >= 0 ? hb - (EB - 1) : 0;
+        uint32_t m = ((1u << EB) - 1u) << wlo;
+        for (int b = 0; b < 6; ++b) m |= 1u << tid_bit_pos<LOG_M, EB, COL>(ph, b);
+        return m;
+    };
+    return varying(pa) == varying(pb);
+}
+// Orders a wave's LDS writes before its following reads without a
+// workgroup barrier (the compiler must not move memory accesses across it).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // The register phases of one pass in execution order (forward: 0, 1, ...;
 // inverse: the reverse), with an LDS exchange between consecutive phases.
 // Each thread writes back to the words it read last, so one barrier per
-// exchange suffices.
-template <int LOG_M, int EB, bool INV, bool FP, bool FOLD, int K>
+// exchange suffices; an exchange that stays inside each wave needs none.
+template <int LOG_M, int EB, bool INV, bool FP, bool FOLD, int K, bool COL = false>
 __device__ __forceinline__ void run_phases(uint64_t (&x)[1 << EB], uint64_t* lds, uint32_t c, uint32_t l,
                                            uint32_t high, uint32_t s0, const TwPair* __restrict__ twt,
                                            const DevMod& md) {
@@ -224,11 +286,14 @@ __device__ __forceinline__ void run_phases(uint64_t (&x)[1 << EB], uint64_t* lds
         if constexpr (K > 0) {
             constexpr int PREV = INV ? PH + 1 : PH - 1;
             lds_write<LOG_M, PREV, EB>(x, lds, c, l);
-            __syncthreads();
+            if constexpr (wave_local_exchange<LOG_M, EB, COL>(PREV, PH))
+                wave_lds_sync();
+            else
+                __syncthreads();
             lds_read<LOG_M, PH, EB>(x, lds, c, l);
         }
         run_phase<LOG_M, PH, EB, INV, FP, FOLD>(x, l, high, s0, twt, md);
-        run_phases<LOG_M, EB, INV, FP, FOLD, K + 1>(x, lds, c, l, high, s0, twt, md);
+        run_phases<LOG_M, EB, INV, FP, FOLD, K + 1, COL>(x, lds, c, l, high, s0, twt, md);
     }
 }
 
@@ -365,9 +430,9 @@ __global__ __launch_bounds__(4096 >> EB) void k_ntt_pass(PolyBatch b, const DevM
 
     // the final inverse pass (s0 = 0) folds N^-1 into stage 0
     if (fp)
-        run_phases<LOG_M, EB, INV, true, FINAL, 0>(x, lds, c, l, high, s0, twt, md);
+        run_phases<LOG_M, EB, INV, true, FINAL, 0, COL>(x, lds, c, l, high, s0, twt, md);
     else
-        run_phases<LOG_M, EB, INV, false, FINAL, 0>(x, lds, c, l, high, s0, twt, md);
+        run_phases<LOG_M, EB, INV, false, FINAL, 0, COL>(x, lds, c, l, high, s0, twt, md);
 
     const uint64_t q = md.q, two_q = md.two_q;
     const double qd = md.qd, qinv = md.qinv;
@@ -852,7 +917,89 @@ __global__ __launch_bounds__(256) void k_rescale_col_b(WsRef ws, uint64_t off_la
 // 2^53), the sums converted to canonical residues.  Otherwise x is brought
 // below q and Montgomery products with the key (stored times 2^64) are
 // added modulo q.  The rows of one kind form one launch (ri.row).
-template <int LOG_M, int EB, bool FP>
+// Forward register phase PH applied to G independent tiles at once: each
+// twiddle is loaded once and serves the butterflies of every tile.
+template <int LOG_M, int PH, int EB, int G, bool FP>
+__device__ __forceinline__ void run_phase_g(uint64_t (&x)[G][1 << EB], uint32_t l, uint32_t high, uint32_t s0,
+                                            const TwPair* __restrict__ twt, const DevMod& md) {
+    using Ph = Phase<LOG_M, PH, EB>;
+    constexpr int E = 1 << EB;
+    const uint64_t q = md.q, two_q = md.two_q;
+    const double qd = md.qd, qinv = md.qinv;
+#pragma unroll
+    for (int bit = Ph::HB; bit >= Ph::LB; --bit) {
+        const int spp = LOG_M - 1 - bit;
+        const uint32_t s = s0 + spp;
+        const int pos = bit - Ph::WLO;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            if (e & (1 << pos)) continue;
+            const TwPair tp = twt[(1u << s) + tw_index<LOG_M, PH, EB>(l, e, bit, high, spp)];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                if constexpr (FP)
+                    fwd_bfly_fp(x[g][e], x[g][e | (1 << pos)], tp, qd, qinv, spp % 3 == 0);
+                else
+                    fwd_bfly(x[g][e], x[g][e | (1 << pos)], tp.w, tp.wp, q, two_q);
+            }
+        }
+    }
+}
+// The forward register phases of one pass for G tiles, each exchanging
+// through its own LDS region (one barrier per exchange for all of them).
+template <int LOG_M, int EB, int G, bool FP, int K>
+__device__ __forceinline__ void run_phases_g(uint64_t (&x)[G][1 << EB], uint64_t* lds, uint32_t c, uint32_t l,
+                                             uint32_t high, uint32_t s0, const TwPair* __restrict__ twt,
+                                             const DevMod& md) {
+    constexpr int NPH = (LOG_M + EB - 1) / EB;
+    constexpr uint32_t W = lds_words<LOG_M, EB>();
+    if constexpr (K < NPH) {
+        if constexpr (K > 0) {
+#pragma unroll
+            for (int g = 0; g < G; ++g) lds_write<LOG_M, K - 1, EB>(x[g], lds + g * W, c, l);
+            if constexpr (wave_local_exchange<LOG_M, EB, false>(K - 1, K))
+                wave_lds_sync();
+            else
+                __syncthreads();
+#pragma unroll
+            for (int g = 0; g < G; ++g) lds_read<LOG_M, K, EB>(x[g], lds + g * W, c, l);
+        }
+        run_phase_g<LOG_M, K, EB, G, FP>(x, l, high, s0, twt, md);
+        run_phases_g<LOG_M, EB, G, FP, K + 1>(x, lds, c, l, high, s0, twt, md);
+    }
+}
+
+// The key inner product of hybrid key switching fused with the last pass of
+// the forward transform of ModUp's rows.  Where the conversion kernel has
+// already applied the first pass (a radix-16 column pass), each extended row
+// needs one row pass of LOG_M = log_n - 4 stages over 4096-word tiles.  A
+// workgroup takes one tile of row t of one item and every digit j: x_j is d
+// itself where t is one of digit j's own rows (d is in the NTT domain
+// already) or ext_j[t] taken through the row pass in registers; the product
+// with the key tile is accumulated, and only the two accumulator tiles
+// acc_b[t] = sum_j x_j key_{j,b}[t] (b = 0, 1) are written.  The extended
+// digits are read once instead of being written back by the row pass and
+// read again by a separate inner-product kernel.  The products are taken in
+// the arrangement the pass ends in (each thread holds E consecutive words of
+// its sub-problem), so d, the key and the accumulators move as 16-byte
+// accesses per lane and no LDS staging is needed.
+//
+// G digits go through the row pass together (G = 2: each twiddle load and
+// each LDS barrier serves two tiles, and the two tiles' butterflies are
+// independent instruction streams); a leftover digit takes the pass alone.
+//
+// Block order: blocks are issued to the eight XCDs round-robin; block id
+// 8 k + x runs item k mod n of the (row, tile) pair 8 floor(k / n) + x, so
+// the items sharing one key tile run on one XCD at about the same time and
+// the tile comes from HBM about once per launch, then from that XCD's L2.
+//
+// FP (rows with q < 2^50, the key holding integer-valued doubles): x is
+// brought within q/2, each product formed by fmulmod against the quotient
+// w (1/q) (|term| < 0.9q, so the sum over at most 8 digits stays below
+// 2^53), the sums converted to canonical residues.  Otherwise x is brought
+// below q and Montgomery products with the key (stored times 2^64) are
+// added modulo q.  The rows of one kind form one launch (ri.row).
+template <int LOG_M, int EB, bool FP, int G>
 __global__ __launch_bounds__(4096 >> EB) __attribute__((amdgpu_waves_per_eu(4)))
 void k_row_inner(RowInner ri, const DevMod* __restrict__ mods, const TwPair* __restrict__ tw, uint32_t log_n) {
     constexpr int M = 1 << LOG_M;
@@ -865,7 +1012,8 @@ void k_row_inner(RowInner ri, const DevMod* __restrict__ mods, const TwPair* __r
     using POUT = Phase<LOG_M, NPH - 1, EB>;
     static_assert(PIN::WLO >= 4, "the row pass reads its input directly");
     static_assert(POUT::WLO == 0, "each thread ends with E consecutive words");
-    __shared__ uint64_t lds[lds_words<LOG_M, EB>()];
+    static_assert(G == 1 || G == 2, "one or two tiles per row pass");
+    __shared__ uint64_t lds[G * lds_words<LOG_M, EB>()];
 
     const uint32_t bid = blockIdx.x;
     const uint32_t kx = bid >> 3;
@@ -901,46 +1049,8 @@ void k_row_inner(RowInner ri, const DevMod* __restrict__ mods, const TwPair* __r
     uint64_t acc0[E], acc1[E];  // FP: doubles; otherwise residues below q
 #pragma unroll
     for (int e = 0; e < E; ++e) acc0[e] = acc1[e] = 0;  // also the bits of +0.0
-    for (uint32_t j = 0; j < ri.beta; ++j) {
-        const uint32_t i0 = j * ri.alpha;
-        const bool own = t >= i0 && t < min(i0 + ri.alpha, ri.level);
-        uint64_t x[E];
-        if (own && ri.kappa) {
-            // d = X^kappa image of the input's row t: its tile staged in LDS
-            galois_tile_to_lds<LOG_M, EB>(ri.perm_src[z] + ((size_t)t << log_n), tile, log_n, ri.kappa, ri.kappa_inv,
-                                          lds, FP);
-#pragma unroll
-            for (int e = 0; e < E; ++e) x[e] = lds[lds_at<LOG_M, EB>(c, l * (uint32_t)E + (uint32_t)e)];
-            __syncthreads();  // the next digit's exchanges reuse the LDS
-        } else if (own) {
-            load_vec(item + ri.off_d + ((size_t)t << log_n), x);
-            if constexpr (FP) {
-#pragma unroll
-                for (int e = 0; e < E; ++e) x[e] = fp_from_u64(x[e]);
-            }
-        } else {
-            const uint64_t* __restrict__ src = item + ri.off_ext + ((size_t)(j * ri.rows + t) << log_n);
-#pragma unroll
-            for (int e = 0; e < E; ++e) x[e] = src[((size_t)(sp0 + c) << LOG_M) | PIN::r_of(l, e)];
-            // the twiddles and their addresses are the same for every digit;
-            // opaque copies of their base and of the lane indices keep the
-            // compiler from holding all of them in registers across the
-            // digit loop (they are recomputed and reloaded per digit)
-            const TwPair* twj = twt;
-            uint32_t lj = l, cj = c;
-            asm volatile("" : "+v"(twj), "+v"(lj), "+v"(cj));
-            run_phases<LOG_M, EB, false, FP, false, 0>(x, lds, cj, lj, sp0 + c, s0, twj, md);
-            __syncthreads();  // the next digit's exchanges reuse the LDS
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-                if constexpr (FP) {
-                    x[e] = as_u(freduce(as_f(x[e]), qd, qinv));
-                } else {
-                    const uint64_t v = x[e] >= two_q ? x[e] - two_q : x[e];
-                    x[e] = v >= q ? v - q : v;
-                }
-            }
-        }
+    // acc_b += x key_{j,b}[t]
+    auto accumulate = [&](const uint64_t (&x)[E], uint32_t j) {
         uint64_t k0[E], k1[E];
         load_vec(ri.key + ((size_t)((2 * j) * ri.krows + mi) << log_n), k0);
         load_vec(ri.key + ((size_t)((2 * j + 1) * ri.krows + mi) << log_n), k1);
@@ -956,7 +1066,93 @@ void k_row_inner(RowInner ri, const DevMod* __restrict__ mods, const TwPair* __r
                 acc1[e] = add_mod(acc1[e], mont_redc(x[e] * k1[e], mulhi64(x[e], k1[e]), q, md.mont_neg_qinv), q);
             }
         }
+    };
+    // ext_j[t] (after the conversion kernel's column pass) into x
+    auto load_ext = [&](uint32_t j, uint64_t (&x)[E]) {
+        const uint64_t* __restrict__ src = item + ri.off_ext + ((size_t)(j * ri.rows + t) << log_n);
+#pragma unroll
+        for (int e = 0; e < E; ++e) x[e] = src[((size_t)(sp0 + c) << LOG_M) | PIN::r_of(l, e)];
+    };
+    // the row pass's output brought within q/2 (FP) or below q
+    auto settle = [&](uint64_t (&x)[E]) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            if constexpr (FP) {
+                x[e] = as_u(freduce(as_f(x[e]), qd, qinv));
+            } else {
+                const uint64_t v = x[e] >= two_q ? x[e] - two_q : x[e];
+                x[e] = v >= q ? v - q : v;
+            }
+        }
+    };
+    // the twiddles and their addresses are the same for every digit; opaque
+    // copies of their base and of the lane indices keep the compiler from
+    // holding all of them in registers across the digit loop (they are
+    // recomputed and reloaded per digit)
+    auto row_pass_1 = [&](uint32_t j) {
+        uint64_t x[E];
+        load_ext(j, x);
+        const TwPair* twj = twt;
+        uint32_t lj = l, cj = c;
+        asm volatile("" : "+v"(twj), "+v"(lj), "+v"(cj));
+        run_phases<LOG_M, EB, false, FP, false, 0>(x, lds, cj, lj, sp0 + c, s0, twj, md);
+        __syncthreads();  // the next digit's exchanges reuse the LDS
+        settle(x);
+        accumulate(x, j);
+    };
+    [[maybe_unused]] auto row_pass_2 = [&](uint32_t j1, uint32_t j2) {
+        uint64_t x[2][E];
+        load_ext(j1, x[0]);
+        load_ext(j2, x[1]);
+        const TwPair* twj = twt;
+        uint32_t lj = l, cj = c;
+        asm volatile("" : "+v"(twj), "+v"(lj), "+v"(cj));
+        run_phases_g<LOG_M, EB, 2, FP, 0>(x, lds, cj, lj, sp0 + c, s0, twj, md);
+        __syncthreads();  // the next digits' exchanges reuse the LDS
+        settle(x[0]);
+        accumulate(x[0], j1);
+        settle(x[1]);
+        accumulate(x[1], j2);
+    };
+
+    // the digit whose own rows include t: d itself (no transform needed)
+    if (t < ri.level) {
+        const uint32_t jo = t / ri.alpha;
+        uint64_t x[E];
+        if (ri.kappa) {
+            // d = X^kappa image of the input's row t: its tile staged in LDS
+            galois_tile_to_lds<LOG_M, EB>(ri.perm_src[z] + ((size_t)t << log_n), tile, log_n, ri.kappa, ri.kappa_inv,
+                                          lds, FP);
+#pragma unroll
+            for (int e = 0; e < E; ++e) x[e] = lds[lds_at<LOG_M, EB>(c, l * (uint32_t)E + (uint32_t)e)];
+            __syncthreads();  // the digits' exchanges reuse the LDS
+        } else {
+            load_vec(item + ri.off_d + ((size_t)t << log_n), x);
+            if constexpr (FP) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) x[e] = fp_from_u64(x[e]);
+            }
+        }
+        accumulate(x, jo);
     }
+    // every other digit through the row pass, G at a time (uniform control
+    // flow: t, level, alpha and beta are the same for the whole workgroup)
+    uint32_t pend = ~0u;
+    for (uint32_t j = 0; j < ri.beta; ++j) {
+        if (t < ri.level && j == t / ri.alpha) continue;
+        if constexpr (G == 1) {
+            row_pass_1(j);
+        } else {
+            if (pend == ~0u) {
+                pend = j;
+                continue;
+            }
+            row_pass_2(pend, j);
+            pend = ~0u;
+        }
+    }
+    if (pend != ~0u) row_pass_1(pend);
+
     ulonglong2* __restrict__ o0 = reinterpret_cast<ulonglong2*>(item + ri.off_acc + ((size_t)t << log_n) + w0);
     ulonglong2* __restrict__ o1 =
         reinterpret_cast<ulonglong2*>(item + ri.off_acc + ((size_t)(ri.rows + t) << log_n) + w0);
@@ -1099,7 +1295,7 @@ bool row_inner_supported(uint32_t log_n) {
 void launch_row_inner(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, uint64_t off_acc, const uint64_t* key,
                       uint32_t level, const KsConsts& kc, const DevTables& t, const uint32_t* fp_rows,
                       uint32_t log_n, const uint64_t* const* perm_src, uint64_t kappa, uint64_t kappa_inv,
-                      hipStream_t st) {
+                      bool pair_digits, hipStream_t st) {
     RowInner ri{};
     if (kappa) {
         for (uint32_t z = 0; z < n; ++z) ri.perm_src[z] = perm_src[z];
@@ -1134,11 +1330,14 @@ void launch_row_inner(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, ui
             const dim3 grid(8u * n * ((pairs + 7u) / 8u));
             auto go = [&](auto lm, auto eb) {
                 constexpr int LM = decltype(lm)::value, EB = decltype(eb)::value;
-                if (fp)
-                    hipLaunchKernelGGL((k_row_inner<LM, EB, true>), grid, dim3(4096 >> EB), 0, st, ri, t.mods,
+                if (fp && pair_digits)
+                    hipLaunchKernelGGL((k_row_inner<LM, EB, true, 2>), grid, dim3(4096 >> EB), 0, st, ri, t.mods,
+                                       t.tw_fwd, log_n);
+                else if (fp)
+                    hipLaunchKernelGGL((k_row_inner<LM, EB, true, 1>), grid, dim3(4096 >> EB), 0, st, ri, t.mods,
                                        t.tw_fwd, log_n);
                 else
-                    hipLaunchKernelGGL((k_row_inner<LM, EB, false>), grid, dim3(4096 >> EB), 0, st, ri, t.mods,
+                    hipLaunchKernelGGL((k_row_inner<LM, EB, false, 1>), grid, dim3(4096 >> EB), 0, st, ri, t.mods,
                                        t.tw_fwd, log_n);
             };
             // 8 residues per thread: with 16 the two accumulators and the

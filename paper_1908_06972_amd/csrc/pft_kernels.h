@@ -182,7 +182,9 @@ void launch_rescale_col_b(uint32_t n, WsRef ws, uint64_t off_last, uint64_t off_
 // fp64 arithmetic (one launch per kind).  kappa != 0: d is not read; its
 // own rows are the X -> X^kappa image of the rows of perm_src[z] (host
 // array of n device pointers, item z's input polynomial [level][N], NTT
-// domain), taken through the permutation as they are loaded.
+// domain), taken through the permutation as they are loaded.  pair_digits:
+// the fp64 rows take two digits through each row pass together (same
+// results).
 #define PFT_ROW_LIST 64
 struct RowInner {
     uint64_t* base;  // item z's workspace at base + z stride
@@ -199,7 +201,7 @@ bool row_inner_supported(uint32_t log_n);
 void launch_row_inner(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, uint64_t off_acc, const uint64_t* key,
                       uint32_t level, const KsConsts& kc, const DevTables& t, const uint32_t* fp_rows,
                       uint32_t log_n, const uint64_t* const* perm_src, uint64_t kappa, uint64_t kappa_inv,
-                      hipStream_t st);
+                      bool pair_digits, hipStream_t st);
 // acc [2][level+K][N] = sum_j x_j * key_j  (key: [dnum][2][L+K][N], Montgomery form)
 void launch_key_inner_b(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, uint64_t off_acc, const uint64_t* key,
                         uint32_t level, const KsConsts& kc, const DevTables& t, uint32_t log_n, hipStream_t st);

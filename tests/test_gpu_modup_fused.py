@@ -100,14 +100,14 @@ def test_fused_modup_batch_equals_unfused(name):
     pairs = [(w.enc_pair(70 + i, level), w.enc_pair(80 + i, level)) for i in range(3)]
     try:
         outs = {}
-        for mode in ((True, True), (True, False), (False, False)):
-            w.ctx.bconv_mode(True, fused=mode[0], inner=mode[1])
+        for mode in ((True, True, True), (True, True, False), (True, False, False), (False, False, False)):
+            w.ctx.bconv_mode(True, fused=mode[0], inner=mode[1], pairs=mode[2])
             outs[mode] = [w.ctx.export(g) for g in
                           w.ctx.mul_relin_batch([p[0][0] for p in pairs], [p[1][0] for p in pairs])]
-        for mode in ((True, False), (False, False)):
-            for a, b in zip(outs[(True, True)], outs[mode]):
+        for mode in ((True, True, False), (True, False, False), (False, False, False)):
+            for a, b in zip(outs[(True, True, True)], outs[mode]):
                 assert np.array_equal(a, b)
-        for ((_, oa), (_, ob)), host in zip(pairs, outs[(True, True)]):
+        for ((_, oa), (_, ob)), host in zip(pairs, outs[(True, True, True)]):
             o = C.hmul_relin(w.op, oa, ob, w.rlk)
             assert np.array_equal(host[0], o.c0) and np.array_equal(host[1], o.c1)
     finally:

@@ -176,9 +176,10 @@ def test_mul_relin_parity(request, name, levels):
 def test_bconv_modes_parity(request, name, levels):
     """Key switching with the base conversions on the matrix cores (int8
     digits; fused with the adjacent transform passes and the key inner
-    product fused with the row pass of ModUp's rows, the default; fused
-    passes only; separate) and on the VALU (128-bit MACs): all equal the
-    oracle, at full, ragged-last-digit and low levels."""
+    product fused with the row pass of ModUp's rows, two digits per row pass
+    (the default) or one; fused passes only; separate) and on the VALU
+    (128-bit MACs): all equal the oracle, at full, ragged-last-digit and low
+    levels."""
     w = _world(request, name)
     for lvl in levels:
         ga, oa = w.encrypt_pair(w.random_plain(23), lvl, 700 + lvl)
@@ -186,9 +187,10 @@ def test_bconv_modes_parity(request, name, levels):
         want = C.hmul_relin(w.op, oa, ob, w.rlk)
         st = sorted(w.rot)[0]
         want_rot = C.rotate(w.op, oa, st, w.rot[st])
-        for mfma, fused, inner in ((True, True, True), (True, True, False), (True, False, False),
-                                   (False, False, False)):
-            w.ctx.bconv_mode(mfma, fused=fused, inner=inner)
+        for mfma, fused, inner, pairs in ((True, True, True, True), (True, True, True, False),
+                                          (True, True, False, False), (True, False, False, False),
+                                          (False, False, False, False)):
+            w.ctx.bconv_mode(mfma, fused=fused, inner=inner, pairs=pairs)
             w.assert_same(w.ctx.mul_relin(ga, gb), want)
             w.assert_same(w.ctx.rotate(ga, st), want_rot)
     w.ctx.bconv_mode(True)
