@@ -1085,16 +1085,17 @@ void k_row_inner(RowInner ri, const DevMod* __restrict__ mods, const TwPair* __r
             }
         }
     };
-    // the twiddles and their addresses are the same for every digit; opaque
-    // copies of their base and of the lane indices keep the compiler from
-    // holding all of them in registers across the digit loop (they are
-    // recomputed and reloaded per digit)
+    // the twiddles and their addresses are the same for every digit; an
+    // opaque zero offset of their base and opaque copies of the lane indices
+    // keep the compiler from holding all of them in registers across the
+    // digit loop (they are recomputed and reloaded per digit).  The offset,
+    // not the pointer, is hidden, so the loads stay global (not flat) loads.
     auto row_pass_1 = [&](uint32_t j) {
         uint64_t x[E];
         load_ext(j, x);
-        const TwPair* twj = twt;
-        uint32_t lj = l, cj = c;
-        asm volatile("" : "+v"(twj), "+v"(lj), "+v"(cj));
+        uint32_t zoff = 0, lj = l, cj = c;
+        asm volatile("" : "+v"(zoff), "+v"(lj), "+v"(cj));
+        const TwPair* __restrict__ twj = twt + zoff;
         run_phases<LOG_M, EB, false, FP, false, 0>(x, lds, cj, lj, sp0 + c, s0, twj, md);
         __syncthreads();  // the next digit's exchanges reuse the LDS
         settle(x);
@@ -1104,9 +1105,9 @@ void k_row_inner(RowInner ri, const DevMod* __restrict__ mods, const TwPair* __r
         uint64_t x[2][E];
         load_ext(j1, x[0]);
         load_ext(j2, x[1]);
-        const TwPair* twj = twt;
-        uint32_t lj = l, cj = c;
-        asm volatile("" : "+v"(twj), "+v"(lj), "+v"(cj));
+        uint32_t zoff = 0, lj = l, cj = c;
+        asm volatile("" : "+v"(zoff), "+v"(lj), "+v"(cj));
+        const TwPair* __restrict__ twj = twt + zoff;
         run_phases_g<LOG_M, EB, 2, FP, 0>(x, lds, cj, lj, sp0 + c, s0, twj, md);
         __syncthreads();  // the next digits' exchanges reuse the LDS
         settle(x[0]);
