@@ -47,7 +47,8 @@ def kernel_name(kid, variant):
                                                           b(v & 64), b(v & 128), b(v & 512))
         return name + (", true>" if v & 1024 else ">")  # X -> X^kappa folded into the pass
     if kid == 3 and variant >= 1024:  # inner product fused with the row pass of ModUp's rows
-        return "k_row_inner<%d, 3>" % (variant - 1024)
+        v = variant - 1024
+        return "k_row_inner<%d, 3, %s, %d>" % (v & 63, "true" if v & 64 else "false", 2 if v & 128 else 1)
     if kid == 8 and variant == 1:  # RESCALE's expansion fused with the first transform pass
         return "k_rescale_col_b"
     if kid in (2, 4) and variant >= 64:  # base conversion fused with the first (and last inverse) pass
@@ -390,6 +391,7 @@ def parse():
     ap.add_argument("--no-breakdown", action="store_true", help="skip the per-operation loops")
     ap.add_argument("--no-predict", action="store_true", help="skip the encrypted-weight predict measurement")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-primitives op-list measurement")
+    ap.add_argument("--no-bow", action="store_true", help="skip the bag-of-words inference measurement")
     ap.add_argument("--no-paper-inference", action="store_true",
                     help="skip the inference at the paper's shapes (N=8192, 123 inputs)")
     ap.add_argument("--serve-requests", type=int, default=1000,
@@ -795,6 +797,64 @@ def predict_bench(n_docs=32, level=6, reps=3):
            "note": "encrypted H and O (diagonal BSGS, HMUL + one relinearisation per giant step), 1/w, then "
                    "X^2/8 + X/2 + 1/4; error of 2 documents against Alg. 1 steps 2-3 and the polynomial in fp64"}
     log("predict: %s" % res)
+    ctx.close()
+    return res
+
+
+def bow_bench(n_docs=32, reps=3, singles=8):
+    """The bag-of-words inference workload: N = 2^15, 16 ciphertext primes
+    (+4 special, dnum 4), scale 2^40; vocabulary 32768 (two input
+    ciphertexts per document), plaintext embedding 32768 x 64 and classifier
+    64 x 8 with N(0, 0.1^2) weights; documents of Zipf-distributed counts,
+    50-500 tokens each, encrypted at the top level; Alg. 1 steps 2-3 as
+    diagonal BSGS PtMatVec + 1/w + PtMatVec, three levels.  Reports the
+    batch of n_docs (documents/s), single-document latencies (median and
+    worst of `singles`), the error against fp64 and argmax agreement."""
+    import statistics
+
+    import numpy as np
+    import torch
+
+    import synth as S
+    from paper_1908_06972_amd import ckks as L
+    from paper_1908_06972_amd.inference import BowModel, encrypted_inference, split_counts
+
+    lp = L.Params.from_config(S.CONFIGS["C4"])
+    ctx = L.Context(lp, 0, stream=torch.cuda.Stream())
+    t0 = time.time()
+    H, O = S.bow_weights(404, 32768, 64, 8)
+    model = BowModel(ctx, H, O, lp.L)
+    ctx.keygen(KEY_SEED, model.rotation_steps())
+    counts, words = S.bow_documents(405, n_docs, 32768)
+    docs = [[ctx.encrypt_seeded(lp.encode(v), lp.L, lp.scale, 40500 + 4 * d + c)
+             for c, v in enumerate(split_counts(counts[d], model.n_in, model.t))] for d in range(n_docs)]
+    ctx.synchronize()
+    log("bag of words: model (%d + %d diagonals), keys and %d documents in %.1fs" % (
+        model.stage1.b * model.stage1.G * model.n_in, model.stage2.b * model.stage2.G, n_docs, time.time() - t0))
+    out = encrypted_inference(ctx, model, docs, list(words))
+    sec = timed(lambda: encrypted_inference(ctx, model, docs, list(words)), reps, ctx.synchronize)
+    lat = []
+    for d in range(singles):
+        ctx.synchronize()
+        t1 = time.perf_counter()
+        encrypted_inference(ctx, model, [docs[d]], [words[d]])
+        ctx.synchronize()
+        lat.append(time.perf_counter() - t1)
+    err, agree = 0.0, 0
+    for d in range(n_docs):
+        got = lp.decode(ctx.decrypt(out[d]), out[d].scale, 8).real
+        ref = ((counts[d].astype(np.float64) @ H) / float(words[d])) @ O  # Alg. 1 steps 2-3 in fp64
+        err = max(err, float(np.max(np.abs(got - ref))))
+        agree += int(np.argmax(got) == np.argmax(ref))
+    res = {"docs_per_s": round(n_docs / sec, 2), "ms_per_batch": round(1000.0 * sec, 2), "batch": n_docs,
+           "single_doc_ms_p50": round(1000.0 * statistics.median(lat), 2),
+           "single_doc_ms_max": round(1000.0 * max(lat), 2),
+           "rotations_per_doc": len(model.rotation_order()) + (model.stage1.b - 1) * (model.n_in - 1),
+           "n": lp.n, "limbs": lp.L, "vocab": 32768, "dim": 64, "classes": 8,
+           "max_abs_err_vs_fp64": err, "argmax_agree": "%d/%d" % (agree, n_docs),
+           "note": "plaintext weights, diagonal BSGS PtMatVec (Sec. 4.1); rotations per document: the baby steps of "
+                   "each input ciphertext, giant steps and the sum steps of both stages"}
+    log("bag of words: %s" % res)
     ctx.close()
     return res
 
@@ -1264,6 +1324,9 @@ def main():
     serving = None
     if args.serve_requests > 0:
         serving = serving_bench(args.serve_requests)
+    bow = None
+    if not args.no_bow:
+        bow = bow_bench()
     predict = None
     if not args.no_predict:
         predict = predict_bench()
@@ -1298,6 +1361,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "batched": batched,
+        "bag_of_words": bow,
         "serving": serving,
         "predict": predict,
         "paper_inference": paper_inf,

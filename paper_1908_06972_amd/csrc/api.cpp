@@ -1738,24 +1738,13 @@ static void key_switch_b(pft_ctx* c, uint32_t n, WsRef ws, const KsLayout& K, ui
             }, c->bconv_mfma ? nkb : 0);
         }
         if (fuse_inner) {
-            // method bytes: d's own rows and the accumulators per item, the
-            // key once per launch (the extended rows are the transform's
-            // pass boundary); butterflies of the row pass plus two products
-            // per digit input
-            double ext_rows = 0;
-            for (uint32_t j = 0; j < beta; ++j) ext_rows += rows - (std::min(j * A + A, level) - j * A);
-            const uint32_t lm = lg - 4;
-            timed(c, PK_KEY_INNER, 8.0 * N * ((double)level * n + 2.0 * rows * n + 2.0 * beta * rows),
-                  N * n * (0.5 * lm * ext_rows + 2.0 * beta * rows),
-                  [&] {
-                      const uint64_t* c1[PFT_MAX_ITEMS] = {};
-                      if (fold)
-                          for (uint32_t z = 0; z < n; ++z) c1[z] = rot->src.p[z] + nl;
-                      launch_row_inner(n, ws, off_d, K.off_ext, K.off_acc, key.data, level, c->kc, c->tabs,
-                                       c->fp_rows.data(), lg, c1, fold ? rot->kappa : 0, fold ? rot->kappa_inv : 0,
-                                       c->inner_pairs, c->stream);
-                  },
-                  1024u + lm);
+            // each launch (one per arithmetic kind of row) is timed on its own
+            const uint64_t* c1[PFT_MAX_ITEMS] = {};
+            if (fold)
+                for (uint32_t z = 0; z < n; ++z) c1[z] = rot->src.p[z] + nl;
+            launch_row_inner(n, ws, off_d, K.off_ext, K.off_acc, key.data, level, c->kc, c->tabs, c->fp_rows.data(),
+                             lg, c1, fold ? rot->kappa : 0, fold ? rot->kappa_inv : 0, c->inner_pairs, c->stream,
+                             hook(c));
         } else {
             const uint32_t first = fuse ? 1u : 0u;
             if (!full.empty()) ntt_jobs(c, full, rows - A, level, false, 0, nullptr, 0, first);

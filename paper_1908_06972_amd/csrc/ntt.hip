@@ -1296,7 +1296,7 @@ bool row_inner_supported(uint32_t log_n) {
 void launch_row_inner(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, uint64_t off_acc, const uint64_t* key,
                       uint32_t level, const KsConsts& kc, const DevTables& t, const uint32_t* fp_rows,
                       uint32_t log_n, const uint64_t* const* perm_src, uint64_t kappa, uint64_t kappa_inv,
-                      bool pair_digits, hipStream_t st) {
+                      bool pair_digits, hipStream_t st, ProfHook* prof) {
     RowInner ri{};
     if (kappa) {
         for (uint32_t z = 0; z < n; ++z) ri.perm_src[z] = perm_src[z];
@@ -1329,9 +1329,21 @@ void launch_row_inner(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, ui
             for (uint32_t i = 0; i < ri.n_rows; ++i) ri.row[i] = rows[r0 + i];
             const uint32_t pairs = ri.tiles * ri.n_rows;
             const dim3 grid(8u * n * ((pairs + 7u) / 8u));
+            // method bytes: d's own rows and both accumulators per item, the
+            // key rows once (the extended rows are the pass boundary); work:
+            // the row pass's butterflies and two products per digit input
+            double bytes = 0.0, ops = 0.0;
+            const double N = (double)(1u << log_n), lm = (double)(log_n - 4);
+            for (uint32_t i = 0; i < ri.n_rows; ++i) {
+                const double own = ri.row[i] < level ? 1.0 : 0.0;
+                bytes += 8.0 * N * (n * (own + 2.0) + 2.0 * ri.beta);
+                ops += N * n * (0.5 * lm * (ri.beta - own) + 2.0 * ri.beta);
+            }
+            const bool g2 = fp && pair_digits;
+            if (prof) prof->begin(PK_KEY_INNER);
             auto go = [&](auto lm, auto eb) {
                 constexpr int LM = decltype(lm)::value, EB = decltype(eb)::value;
-                if (fp && pair_digits)
+                if (g2)
                     hipLaunchKernelGGL((k_row_inner<LM, EB, true, 2>), grid, dim3(4096 >> EB), 0, st, ri, t.mods,
                                        t.tw_fwd, log_n);
                 else if (fp)
@@ -1351,6 +1363,8 @@ void launch_row_inner(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, ui
                 case 12: by_eb(std::integral_constant<int, 12>{}); break;
                 default: break;
             }
+            // variant: 1024 + radix, + 64 for the fp64 rows, + 128 with two digits per pass
+            if (prof) prof->end(PK_KEY_INNER, bytes, ops, 1024u + (log_n - 4) + (fp ? 64u : 0u) + (g2 ? 128u : 0u));
         }
     }
 }

@@ -184,7 +184,8 @@ void launch_rescale_col_b(uint32_t n, WsRef ws, uint64_t off_last, uint64_t off_
 // array of n device pointers, item z's input polynomial [level][N], NTT
 // domain), taken through the permutation as they are loaded.  pair_digits:
 // the fp64 rows take two digits through each row pass together (same
-// results).
+// results).  prof: each launch (one per arithmetic kind) is timed as a
+// PK_KEY_INNER variant 1024 + (log_n - 4) (+ 64 fp64 rows, + 128 digit pairs).
 #define PFT_ROW_LIST 64
 struct RowInner {
     uint64_t* base;  // item z's workspace at base + z stride
@@ -201,7 +202,7 @@ bool row_inner_supported(uint32_t log_n);
 void launch_row_inner(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, uint64_t off_acc, const uint64_t* key,
                       uint32_t level, const KsConsts& kc, const DevTables& t, const uint32_t* fp_rows,
                       uint32_t log_n, const uint64_t* const* perm_src, uint64_t kappa, uint64_t kappa_inv,
-                      bool pair_digits, hipStream_t st);
+                      bool pair_digits, hipStream_t st, ProfHook* prof = nullptr);
 // acc [2][level+K][N] = sum_j x_j * key_j  (key: [dnum][2][L+K][N], Montgomery form)
 void launch_key_inner_b(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, uint64_t off_acc, const uint64_t* key,
                         uint32_t level, const KsConsts& kc, const DevTables& t, uint32_t log_n, hipStream_t st);
