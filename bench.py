@@ -160,7 +160,7 @@ def _step_dispatches(rows, key_id, key_start):
     return [r for r in rows if int(r[key_id]) >= first]
 
 
-def summarize(trace_dir, fetch_dir, write_dir, kernel, kid, commands, n_top=6, sq_dir=None):
+def summarize(trace_dir, fetch_dir, write_dir, kernel, kid, commands, n_top=6, sq_dir=None, mix_dir=None):
     """Markdown summary of three rocprofv3 runs of bench.py: a kernel trace
     (durations) and two counter runs (FETCH_SIZE with SQ_INSTS_VALU, then
     WRITE_SIZE), each restricted to the dispatches of the job steps, with
@@ -168,7 +168,11 @@ def summarize(trace_dir, fetch_dir, write_dir, kernel, kid, commands, n_top=6, s
     kernel k_copy_rows_b (8 bytes read and 8 written per work-item)
     calibrates the byte counters.  sq_dir: an optional fourth run with the
     SQ counters SQ_WAVE_CYCLES, SQ_WAIT_INST_ANY, SQ_ACTIVE_INST_VALU,
-    SQ_INSTS_LDS and SQ_LDS_BANK_CONFLICT, summarised per kernel."""
+    SQ_INSTS_LDS and SQ_LDS_BANK_CONFLICT, summarised per kernel; mix_dir:
+    an optional fifth run with the instruction mix (SQ_INSTS_VALU_INT32,
+    SQ_INSTS_VALU_INT64, SQ_INSTS_VALU_FMA_F64, SQ_INSTS_MFMA) and the
+    matrix-core busy cycles (SQ_VALU_MFMA_BUSY_CYCLES over GRBM_GUI_ACTIVE
+    times the 1024 SIMDs)."""
     trace = _step_dispatches(_csv_rows(_find(trace_dir, "kernel_trace.csv")), "Dispatch_Id", "Start_Timestamp")
     short_name = lambda n: n.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "")  # noqa: E731
     per = {}
@@ -266,6 +270,26 @@ def summarize(trace_dir, fetch_dir, write_dir, kernel, kid, commands, n_top=6, s
                 fmt(vals["SQ_WAIT_INST_ANY"] / wc if wc and vals["SQ_WAIT_INST_ANY"] is not None else None, "%.2f"),
                 fmt(vals["SQ_ACTIVE_INST_VALU"] / wc if wc and vals["SQ_ACTIVE_INST_VALU"] is not None else None,
                     "%.2f")))
+        out.append("")
+    if mix_dir:
+        out.append("Instruction mix and matrix cores over the same dispatches, per launch (wave instructions; "
+                   "`MFMA busy` = SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE x 1024 SIMDs)):")
+        out.append("")
+        out.append("| kernel | VALU int32 | VALU int64 | VALU fp64 FMA | MFMA insts | MFMA busy |")
+        out.append("|---|---|---|---|---|---|")
+        for target in targets:
+            vals = {}
+            for ctr in ("SQ_INSTS_VALU_INT32", "SQ_INSTS_VALU_INT64", "SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_MFMA",
+                        "SQ_VALU_MFMA_BUSY_CYCLES", "GRBM_GUI_ACTIVE"):
+                v, _ = per_dispatch(mix_dir, ctr, target)
+                vals[ctr] = sum(v) / len(v) if v else None
+            fmt = lambda v, f: (f % v) if v is not None else "-"  # noqa: E731
+            busy = vals["SQ_VALU_MFMA_BUSY_CYCLES"]
+            act = vals["GRBM_GUI_ACTIVE"]
+            out.append("| %s | %s | %s | %s | %s | %s |" % (
+                target, fmt(vals["SQ_INSTS_VALU_INT32"], "%.3g"), fmt(vals["SQ_INSTS_VALU_INT64"], "%.3g"),
+                fmt(vals["SQ_INSTS_VALU_FMA_F64"], "%.3g"), fmt(vals["SQ_INSTS_MFMA"], "%.3g"),
+                fmt(busy / (act * 1024.0) if busy is not None and act else None, "%.3f")))
         out.append("")
     # every kernel of the profiled steps: counted traffic per step
     def step_total(dirpath, counter):
@@ -403,6 +427,7 @@ def parse():
     ap.add_argument("--family", type=int, default=0)
     ap.add_argument("--commands", nargs="*", default=[])
     ap.add_argument("--sq", default=None, help="with --summarize: directory of the SQ counter run")
+    ap.add_argument("--mix", default=None, help="with --summarize: directory of the instruction-mix counter run")
     ap.add_argument("--tuning-in", default=DEFAULT_TUNING,
                     help="JSON table of NTT schedules (from --tuning-out) to use instead of tuning; the default is the "
                          "table the autotuner produced for this workload, so kernel choices repeat run to run")
@@ -1127,7 +1152,8 @@ def oracle_inference_seconds():
 def main():
     args = parse()
     if args.summarize:
-        print(summarize(*args.summarize, args.kernel, args.family, args.commands, sq_dir=args.sq), end="")
+        print(summarize(*args.summarize, args.kernel, args.family, args.commands, sq_dir=args.sq, mix_dir=args.mix),
+              end="")
         return
     if args.cpu_baseline_full:
         print(json.dumps(cpu_baseline_full(args.reps)), flush=True)
