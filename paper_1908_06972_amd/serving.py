@@ -7,7 +7,11 @@ plaintext model (Sec. 4.1: v H, x 1/w, h O).  The scheduler:
   * queues arrivals per parameter set (FIFO);
   * whenever a parameter set's stream has no batch in flight, admits the
     oldest waiting requests of that set as one batch, as many as fit in the
-    HBM budget for in-flight working sets and the batch cap;
+    HBM budget and the batch cap.  A set's device footprint beyond its keys
+    is the larger of its in-flight batch's working set and the scratch its
+    context keeps allocated from earlier batches (the library's workspace
+    only grows), so the sum over sets of that footprint stays within the
+    budget;
   * launches the batch asynchronously and polls completion, so batches of
     different parameter sets overlap on the device and requests that arrive
     meanwhile join the next batch (continuous batching);
@@ -85,13 +89,25 @@ class RealClock:
 class Scheduler:
     def __init__(self, executor, policies, budget_bytes, clock=None, continuous=True):
         """policies: {pset: PsetPolicy}.  continuous=False gives the plain
-        per-op server: one request at a time, in arrival order, no overlap."""
+        per-op server: one request at a time, in arrival order, no overlap.
+        The executor may provide retained(pset): device bytes the set keeps
+        allocated between batches (0 if absent)."""
         self.ex = executor
         self.policies = policies
         self.budget = budget_bytes
         self.clock = clock or RealClock()
         self.continuous = continuous
         self.used = 0
+        self.inflight_bytes = {}
+
+    def _retained(self, p):
+        f = getattr(self.ex, "retained", None)
+        return f(p) if f else 0
+
+    def _footprint(self, skip=None):
+        """Device bytes beyond keys over all sets (except `skip`): per set the
+        larger of its in-flight working set and its retained scratch."""
+        return sum(max(self._retained(p), self.inflight_bytes.get(p, 0)) for p in self.policies if p != skip)
 
     def run(self, trace):
         """Serve every request of `trace` (sorted by arrival); fills in
@@ -125,6 +141,7 @@ class Scheduler:
                         stats.latencies.append(r.done - r.arrival)
                         stats.completed += 1
                     self.used -= nbytes
+                    self.inflight_bytes.pop(p, None)
                     del inflight[p]
             # admissions
             if self.continuous:
@@ -132,7 +149,9 @@ class Scheduler:
                     if p in inflight or not queues[p]:
                         continue
                     pol = self.policies[p]
-                    fit = (self.budget - self.used) // pol.bytes_per_request
+                    # the set's scratch already allocated covers that much of a batch
+                    room = self.budget - self._footprint(skip=p)
+                    fit = room // pol.bytes_per_request
                     n = min(len(queues[p]), pol.max_batch, fit)
                     if n <= 0:
                         continue
@@ -152,6 +171,7 @@ class Scheduler:
     def _launch(self, p, batch, inflight, stats):
         nbytes = self.policies[p].bytes_per_request * len(batch)
         self.used += nbytes
+        self.inflight_bytes[p] = nbytes
         t = self.clock.now()
         for r in batch:
             r.admitted = t
@@ -208,14 +228,23 @@ class GpuExecutor:
     def results(self, h):
         return self.handles.pop(h)[1]
 
+    def retained(self, p):
+        """Scratch bytes (workspaces, buffers of composite operations) the
+        set's context keeps allocated between batches."""
+        return int(self.sets[p][0].memory()["scratch"])
+
 
 class SimExecutor:
     """Simulated device for CPU tests: a batch of n requests of set p takes
     cost(p, n) seconds of simulated time; sets run concurrently."""
 
-    def __init__(self, clock, cost):
+    def __init__(self, clock, cost, retain=None):
+        """retain(p, n): scratch a batch of n requests of set p leaves
+        allocated (the set keeps the largest so far); None: nothing."""
         self.clock = clock
         self.cost = cost
+        self.retain = retain
+        self.kept = {}
         self.jobs = {}
         self.next = 0
         self.log = []
@@ -225,7 +254,12 @@ class SimExecutor:
         self.next += 1
         self.jobs[h] = (self.clock.now() + self.cost(p, len(batch)), [("result", r.rid) for r in batch])
         self.log.append((self.clock.now(), p, [r.rid for r in batch]))
+        if self.retain:
+            self.kept[p] = max(self.kept.get(p, 0), self.retain(p, len(batch)))
         return h
+
+    def retained(self, p):
+        return self.kept.get(p, 0)
 
     def poll(self, h):
         return self.clock.now() >= self.jobs[h][0]

@@ -89,3 +89,26 @@ def test_poisson_trace_rate_and_mix():
     assert abs(gaps.mean() - 1 / 200.0) < 0.05 / 200
     frac = {k: sum(r.pset == k for r in tr) / len(tr) for k in "abc"}
     assert abs(frac["a"] - 0.5) < 0.02 and abs(frac["b"] - 1 / 3) < 0.02 and abs(frac["c"] - 1 / 6) < 0.02
+
+
+def test_retained_scratch_counts_against_the_budget():
+    """A set's context keeps the scratch of its largest batch allocated; that
+    scratch counts against the HBM budget while other sets admit work, so
+    the sum over sets of max(in-flight working set, retained scratch) stays
+    within the budget."""
+    pol = {"A": PsetPolicy(100, 8), "B": PsetPolicy(100, 8)}
+    trace = [Request(i, "A", 0.0, 0, 1) for i in range(4)] + [Request(4 + i, "B", 2.0, 0, 1) for i in range(3)]
+    clock = SimClock()
+    ex = SimExecutor(clock, lambda p, n: 1.0, retain=lambda p, n: 100 * n)
+    stats = Scheduler(ex, pol, 500, clock=clock).run(trace)
+    assert stats.completed == 7
+    sizes = [(p, len(b)) for _, p, b in ex.log]
+    assert sizes[0] == ("A", 4)
+    # A keeps 400 bytes after its batch: B fits one request at a time
+    assert [n for p, n in sizes if p == "B"] == [1, 1, 1]
+    # without retained scratch the three B requests go as one batch
+    clock2 = SimClock()
+    ex2 = SimExecutor(clock2, lambda p, n: 1.0)
+    trace2 = [Request(i, "A", 0.0, 0, 1) for i in range(4)] + [Request(4 + i, "B", 2.0, 0, 1) for i in range(3)]
+    Scheduler(ex2, pol, 500, clock=clock2).run(trace2)
+    assert [len(b) for _, p, b in ex2.log if p == "B"] == [3]
