@@ -287,7 +287,9 @@ int pft_rescale_batch(pft_ctx* ctx, uint32_t n, const pft_ct* in, uint32_t mode,
 int pft_mod_drop(pft_ctx* ctx, const pft_ct* in, uint32_t level, pft_ct* out);
 /* ROTATE (Sec. 3.4): X -> X^kappa, kappa = 5^step mod 2N, then key switching
  * with the rotation key of `step` (PFT_ENOKEY if absent).  Slot j of the
- * result holds slot j+step of the input. */
+ * result holds slot j+step of the input.  A step that is a multiple of N/2
+ * leaves every slot in place (kappa = 1): out is a copy of in, no key is
+ * needed or used. */
 int pft_rotate(pft_ctx* ctx, const pft_ct* in, int32_t step, pft_ct* out);
 int pft_rotate_batch(pft_ctx* ctx, uint32_t n, const pft_ct* in, int32_t step, pft_ct* out);
 /* ROTATE by any step from power-of-two keys (the paper's cost model for

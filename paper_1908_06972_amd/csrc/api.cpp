@@ -2054,12 +2054,31 @@ extern "C" int pft_rotate(pft_ctx* c, const pft_ct* in, int32_t step, pft_ct* ou
 
 extern "C" int pft_rotate_batch(pft_ctx* c, uint32_t n, const pft_ct* in, int32_t step, pft_ct* out) {
     if (!c || !in || !out) return fail(PFT_EINVAL, "null argument");
-    if (!has_rot(c, step)) return fail(PFT_ENOKEY, "no rotation key for step %d", step);
+    const bool identity = norm_step(step, c->P->n) == 0;
+    if (!identity && !has_rot(c, step)) return fail(PFT_ENOKEY, "no rotation key for step %d", step);
     int r;
     for (uint32_t i = 0; i < n; ++i) {
         if ((r = check_ct(c, &in[i]))) return r;
         if (!out[i].data) return fail(PFT_EINVAL, "null output");
         if (out[i].data == in[i].data) return fail(PFT_EINVAL, "rotate output aliases its input");
+    }
+    if (identity) {
+        // a rotation by a multiple of N/2 slots leaves every slot in place
+        // (kappa = 1): the input itself, no key switch
+        return for_level_groups(n, in, [&](const std::vector<uint32_t>& g) -> int {
+            const uint32_t l = in[g[0]].level, cnt = (uint32_t)g.size();
+            ItemPtrs I{}, O{};
+            for (uint32_t z = 0; z < cnt; ++z) {
+                I.p[z] = in[g[z]].data;
+                O.p[z] = out[g[z]].data;
+            }
+            launch_copy_rows_b(cnt, I, 0, O, 0, 2 * l, c->P->log_n, c->stream);
+            for (uint32_t z = 0; z < cnt; ++z) {
+                out[g[z]].level = l;
+                out[g[z]].scale = in[g[z]].scale;
+            }
+            return PFT_OK;
+        });
     }
     const SwitchKeyDev* key = use_rot(c, step, &r);
     if (!key) return r;

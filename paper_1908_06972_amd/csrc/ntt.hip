@@ -1049,23 +1049,29 @@ void k_row_inner(RowInner ri, const DevMod* __restrict__ mods, const TwPair* __r
     uint64_t acc0[E], acc1[E];  // FP: doubles; otherwise residues below q
 #pragma unroll
     for (int e = 0; e < E; ++e) acc0[e] = acc1[e] = 0;  // also the bits of +0.0
-    // acc_b += x key_{j,b}[t]
-    auto accumulate = [&](const uint64_t (&x)[E], uint32_t j) {
-        uint64_t k0[E], k1[E];
-        load_vec(ri.key + ((size_t)((2 * j) * ri.krows + mi) << log_n), k0);
-        load_vec(ri.key + ((size_t)((2 * j + 1) * ri.krows + mi) << log_n), k1);
+    // the key tile key_{j,b}[t] of this thread's words
+    auto load_key = [&](uint32_t j, int b, uint64_t (&k)[E]) {
+        load_vec(ri.key + ((size_t)((2 * j + b) * ri.krows + mi) << log_n), k);
+    };
+    // acc_b += x k
+    auto mac = [&](const uint64_t (&x)[E], const uint64_t (&k)[E], uint64_t (&acc)[E]) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             if constexpr (FP) {
 #pragma clang fp contract(off)
-                const double xv = as_f(x[e]), a = as_f(k0[e]), b = as_f(k1[e]);
-                acc0[e] = as_u(as_f(acc0[e]) + fmulmod(xv, a, a * qinv, qd));
-                acc1[e] = as_u(as_f(acc1[e]) + fmulmod(xv, b, b * qinv, qd));
+                const double a = as_f(k[e]);
+                acc[e] = as_u(as_f(acc[e]) + fmulmod(as_f(x[e]), a, a * qinv, qd));
             } else {
-                acc0[e] = add_mod(acc0[e], mont_redc(x[e] * k0[e], mulhi64(x[e], k0[e]), q, md.mont_neg_qinv), q);
-                acc1[e] = add_mod(acc1[e], mont_redc(x[e] * k1[e], mulhi64(x[e], k1[e]), q, md.mont_neg_qinv), q);
+                acc[e] = add_mod(acc[e], mont_redc(x[e] * k[e], mulhi64(x[e], k[e]), q, md.mont_neg_qinv), q);
             }
         }
+    };
+    auto accumulate = [&](const uint64_t (&x)[E], uint32_t j) {
+        uint64_t k0[E], k1[E];
+        load_key(j, 0, k0);
+        load_key(j, 1, k1);
+        mac(x, k0, acc0);
+        mac(x, k1, acc1);
     };
     // ext_j[t] (after the conversion kernel's column pass) into x
     auto load_ext = [&](uint32_t j, uint64_t (&x)[E]) {
@@ -1090,6 +1096,9 @@ void k_row_inner(RowInner ri, const DevMod* __restrict__ mods, const TwPair* __r
     // keep the compiler from holding all of them in registers across the
     // digit loop (they are recomputed and reloaded per digit).  The offset,
     // not the pointer, is hidden, so the loads stay global (not flat) loads.
+    // (Issuing the key loads ahead of the pass, to hide their latency behind
+    // it, was measured slower: the extra live registers spill or crowd the
+    // pass at four waves per SIMD.)
     auto row_pass_1 = [&](uint32_t j) {
         uint64_t x[E];
         load_ext(j, x);
