@@ -127,3 +127,26 @@ def test_plan_eviction_and_copy_ahead():
     g = w.ctx.rotate(g, 4)
     o = C.rotate(w.op, o, 4, w.keys[4])
     w.assert_same(g, o)
+
+
+def test_exec_batch_rotations_through_a_limited_cache():
+    """Rotations of ciphertexts at two levels in one op list run as
+    concurrent groups on the executor's side streams; with two key slots
+    for five keys, slots are refilled while other streams may still read
+    them (ordered by events).  Every output equals the oracle."""
+    import torch
+    assert torch.cuda.is_available()
+    w = World(2)
+    ins = [w.enc_pair(200 + 2 * i, level=3 if i % 2 == 0 else 2) for i in range(10)]
+    cts = [g for g, _ in ins]
+    ops = []
+    for i in range(10):
+        out = len(cts)
+        cts.append(w.ctx.empty_ct(ins[i][0].level))
+        ops.append(("rotate", i, 0, out, STEPS[i % len(STEPS)], 0))
+    w.ctx.exec_batch(cts, ops)
+    w.ctx.synchronize()
+    for i, (_, o) in enumerate(ins):
+        st = STEPS[i % len(STEPS)]
+        w.assert_same(cts[10 + i], C.rotate(w.op, o, st, w.keys[st]))
+    assert w.ctx.key_cache_stats()["slots"] == 2
