@@ -34,8 +34,10 @@
 #include "pft_kernels.h"
 
 #include <algorithm>
-#include <vector>
+#include <cstdio>
+#include <cstdlib>
 #include <type_traits>
+#include <vector>
 
 namespace {
 
@@ -112,9 +114,89 @@ __device__ __forceinline__ uint32_t tw_index(uint32_t l, int e, int bit, uint32_
     return (high << spp) | (lhi << (Ph::WLO + EB - bit - 1)) | ((uint32_t)e >> (bit + 1 - Ph::WLO));
 }
 
-template <int LOG_M, int PH, int EB, bool INV, bool FP, bool FOLD>
-__device__ __forceinline__ void run_phase(uint64_t (&x)[1 << EB], uint32_t l, uint32_t high, uint32_t s0,
-                                          const TwPair* __restrict__ twt, const DevMod& md) {
+// The twiddles of register phase PH for one thread.  At the stage whose
+// butterflies span window bit pos, the upper elements e that agree in
+// e >> (pos + 1) share one twiddle (tw_index drops the bits below), so the
+// stage needs E >> (pos + 1) of them.  The first stages in execution order,
+// up to eight twiddles, are loaded by the constructor: a pass builds the set
+// of its next phase before the LDS exchange that precedes that phase, so the
+// loads are in flight during the exchange and its barrier (the fences of
+// the exchange would keep the compiler from moving them there itself).  The
+// later stages load at use.  The inverse transform's final stage with N^-1
+// folded in (FOLD, phase 0, top bit) uses none.  PRE: at most that many
+// twiddles preloaded (the registers they hold compete with the pass's own).
+// Twiddles preloaded per phase ahead of an exchange: by the transform
+// passes with 8 or 16 residues per thread, and by the fused inner product.
+constexpr int TW_PRE_PASS3 = 8;
+constexpr int TW_PRE_PASS4 = 3;
+constexpr int TW_PRE_INNER_FP2 = 3;
+constexpr int TW_PRE_INNER_FP1 = 1;
+constexpr int TW_PRE_INNER_INT = 1;
+constexpr int tw_pre_pass(int eb) { return eb == 3 ? TW_PRE_PASS3 : eb == 4 ? TW_PRE_PASS4 : 0; }
+constexpr int tw_pre_inner(bool fp, int g) {
+    return fp ? (g == 2 ? TW_PRE_INNER_FP2 : TW_PRE_INNER_FP1) : TW_PRE_INNER_INT;
+}
+template <int LOG_M, int PH, int EB, bool INV, bool FOLD, int PRE = 8>
+struct PhaseTw {
+    using Ph = Phase<LOG_M, PH, EB>;
+    static constexpr int E = 1 << EB;
+    static constexpr int P_HI = Ph::HB - Ph::WLO;  // window positions 0 .. P_HI
+    static constexpr int MAXPRE = PRE;
+    static constexpr int cnt(int pos) { return (INV && FOLD && PH == 0 && pos == P_HI) ? 0 : E >> (pos + 1); }
+    struct Layout {
+        int base[8];
+        bool pre[8];
+        int total;
+    };
+    static constexpr Layout layout() {
+        Layout y{};
+        int n = 0;
+        bool open = true;
+        for (int k = 0; k <= P_HI; ++k) {
+            const int pos = INV ? k : P_HI - k;
+            const int c = cnt(pos);
+            if (open && n + c <= MAXPRE) {
+                y.base[pos] = n;
+                y.pre[pos] = true;
+                n += c;
+            } else {
+                open = false;
+                y.base[pos] = 0;
+                y.pre[pos] = false;
+            }
+        }
+        y.total = n;
+        return y;
+    }
+    static constexpr Layout LY = layout();
+    TwPair t[LY.total > 0 ? LY.total : 1];
+    const TwPair* __restrict__ twt;
+    uint32_t l, high, s0;
+
+    __device__ __forceinline__ PhaseTw(const TwPair* __restrict__ tw, uint32_t l_, uint32_t high_, uint32_t s0_)
+        : twt(tw), l(l_), high(high_), s0(s0_) {
+#pragma unroll
+        for (int pos = 0; pos <= P_HI; ++pos) {
+            if (!LY.pre[pos]) continue;
+#pragma unroll
+            for (int m = 0; m < cnt(pos); ++m) t[LY.base[pos] + m] = load(pos, m << (pos + 1));
+        }
+    }
+    __device__ __forceinline__ TwPair load(int pos, int e) const {
+        const int bit = pos + Ph::WLO;
+        const int spp = LOG_M - 1 - bit;
+        return twt[(1u << (s0 + (uint32_t)spp)) + tw_index<LOG_M, PH, EB>(l, e, bit, high, spp)];
+    }
+    // the twiddle of the butterfly at window bit pos whose upper element is e
+    __device__ __forceinline__ TwPair get(int pos, int e) const {
+        if (LY.pre[pos]) return t[LY.base[pos] + (e >> (pos + 1))];
+        return load(pos, e);
+    }
+};
+
+template <int LOG_M, int PH, int EB, bool INV, bool FP, bool FOLD, int PRE>
+__device__ __forceinline__ void run_phase(uint64_t (&x)[1 << EB], const PhaseTw<LOG_M, PH, EB, INV, FOLD, PRE>& tw,
+                                          const DevMod& md) {
     using Ph = Phase<LOG_M, PH, EB>;
     constexpr int E = 1 << EB;
     const uint64_t q = md.q, two_q = md.two_q;
@@ -123,12 +205,11 @@ __device__ __forceinline__ void run_phase(uint64_t (&x)[1 << EB], uint32_t l, ui
 #pragma unroll
         for (int bit = Ph::HB; bit >= Ph::LB; --bit) {
             const int spp = LOG_M - 1 - bit;
-            const uint32_t s = s0 + spp;
             const int pos = bit - Ph::WLO;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 if (e & (1 << pos)) continue;
-                const TwPair tp = twt[(1u << s) + tw_index<LOG_M, PH, EB>(l, e, bit, high, spp)];
+                const TwPair tp = tw.get(pos, e);
                 if constexpr (FP)
                     fwd_bfly_fp(x[e], x[e | (1 << pos)], tp, qd, qinv, spp % 3 == 0);
                 else
@@ -138,8 +219,6 @@ __device__ __forceinline__ void run_phase(uint64_t (&x)[1 << EB], uint32_t l, ui
     } else {
 #pragma unroll
         for (int bit = Ph::LB; bit <= Ph::HB; ++bit) {
-            const int spp = LOG_M - 1 - bit;
-            const uint32_t s = s0 + spp;
             const int pos = bit - Ph::WLO;
             if (FOLD && PH == 0 && bit == Ph::HB) {
                 // stage 0 with N^-1 folded in (integer path: outputs fully reduced)
@@ -162,7 +241,7 @@ __device__ __forceinline__ void run_phase(uint64_t (&x)[1 << EB], uint32_t l, ui
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
                     if (e & (1 << pos)) continue;
-                    const TwPair tp = twt[(1u << s) + tw_index<LOG_M, PH, EB>(l, e, bit, high, spp)];
+                    const TwPair tp = tw.get(pos, e);
                     if constexpr (FP)
                         inv_bfly_fp(x[e], x[e | (1 << pos)], tp, qd, qinv, bit % 3 != 2);
                     else
@@ -171,6 +250,15 @@ __device__ __forceinline__ void run_phase(uint64_t (&x)[1 << EB], uint32_t l, ui
             }
         }
     }
+}
+
+// One register phase loading each twiddle at its use (a single-phase pass:
+// with no exchange in the way the compiler schedules the loads itself).
+template <int LOG_M, int PH, int EB, bool INV, bool FP, bool FOLD>
+__device__ __forceinline__ void run_phase(uint64_t (&x)[1 << EB], uint32_t l, uint32_t high, uint32_t s0,
+                                          const TwPair* __restrict__ twt, const DevMod& md) {
+    const PhaseTw<LOG_M, PH, EB, INV, FOLD, 0> tw(twt, l, high, s0);
+    run_phase<LOG_M, PH, EB, INV, FP, FOLD, 0>(x, tw, md);
 }
 
 // LDS word of element r of sub-problem c: c S + r + P (r >> 4), or, where
@@ -233,7 +321,7 @@ constexpr int tid_bit_pos(int ph, int b) {
     constexpr int LC = 12 - LOG_M;  // log2 of the sub-problems per workgroup
     const int hb = LOG_M - 1 - EB * ph;
     const int wlo = hb - (EB - 1) >= 0 ? hb - (EB - 1) : 0;
-    int lb;
+    int lb = 0;
     if (COL) {
         if (b < LC) return LOG_M + b;
         lb = b - LC;
@@ -276,13 +364,15 @@ __device__ __forceinline__ void wave_lds_sync() {
 // inverse: the reverse), with an LDS exchange between consecutive phases.
 // Each thread writes back to the words it read last, so one barrier per
 // exchange suffices; an exchange that stays inside each wave needs none.
-template <int LOG_M, int EB, bool INV, bool FP, bool FOLD, int K, bool COL = false>
+template <int LOG_M, int EB, bool INV, bool FP, bool FOLD, int K, bool COL = false, int PRE = 0>
 __device__ __forceinline__ void run_phases(uint64_t (&x)[1 << EB], uint64_t* lds, uint32_t c, uint32_t l,
                                            uint32_t high, uint32_t s0, const TwPair* __restrict__ twt,
                                            const DevMod& md) {
     constexpr int NPH = (LOG_M + EB - 1) / EB;
     if constexpr (K < NPH) {
         constexpr int PH = INV ? NPH - 1 - K : K;
+        // the phase's twiddle loads go out before the exchange
+        const PhaseTw<LOG_M, PH, EB, INV, FOLD, PRE> tw(twt, l, high, s0);
         if constexpr (K > 0) {
             constexpr int PREV = INV ? PH + 1 : PH - 1;
             lds_write<LOG_M, PREV, EB>(x, lds, c, l);
@@ -292,8 +382,8 @@ __device__ __forceinline__ void run_phases(uint64_t (&x)[1 << EB], uint64_t* lds
                 __syncthreads();
             lds_read<LOG_M, PH, EB>(x, lds, c, l);
         }
-        run_phase<LOG_M, PH, EB, INV, FP, FOLD>(x, l, high, s0, twt, md);
-        run_phases<LOG_M, EB, INV, FP, FOLD, K + 1, COL>(x, lds, c, l, high, s0, twt, md);
+        run_phase<LOG_M, PH, EB, INV, FP, FOLD, PRE>(x, tw, md);
+        run_phases<LOG_M, EB, INV, FP, FOLD, K + 1, COL, PRE>(x, lds, c, l, high, s0, twt, md);
     }
 }
 
@@ -430,9 +520,9 @@ __global__ __launch_bounds__(4096 >> EB) void k_ntt_pass(PolyBatch b, const DevM
 
     // the final inverse pass (s0 = 0) folds N^-1 into stage 0
     if (fp)
-        run_phases<LOG_M, EB, INV, true, FINAL, 0, COL>(x, lds, c, l, high, s0, twt, md);
+        run_phases<LOG_M, EB, INV, true, FINAL, 0, COL, tw_pre_pass(EB)>(x, lds, c, l, high, s0, twt, md);
     else
-        run_phases<LOG_M, EB, INV, false, FINAL, 0, COL>(x, lds, c, l, high, s0, twt, md);
+        run_phases<LOG_M, EB, INV, false, FINAL, 0, COL, tw_pre_pass(EB)>(x, lds, c, l, high, s0, twt, md);
 
     const uint64_t q = md.q, two_q = md.two_q;
     const double qd = md.qd, qinv = md.qinv;
@@ -919,9 +1009,9 @@ __global__ __launch_bounds__(256) void k_rescale_col_b(WsRef ws, uint64_t off_la
 // added modulo q.  The rows of one kind form one launch (ri.row).
 // Forward register phase PH applied to G independent tiles at once: each
 // twiddle is loaded once and serves the butterflies of every tile.
-template <int LOG_M, int PH, int EB, int G, bool FP>
-__device__ __forceinline__ void run_phase_g(uint64_t (&x)[G][1 << EB], uint32_t l, uint32_t high, uint32_t s0,
-                                            const TwPair* __restrict__ twt, const DevMod& md) {
+template <int LOG_M, int PH, int EB, int G, bool FP, int PRE>
+__device__ __forceinline__ void run_phase_g(uint64_t (&x)[G][1 << EB],
+                                            const PhaseTw<LOG_M, PH, EB, false, false, PRE>& tw, const DevMod& md) {
     using Ph = Phase<LOG_M, PH, EB>;
     constexpr int E = 1 << EB;
     const uint64_t q = md.q, two_q = md.two_q;
@@ -929,12 +1019,11 @@ __device__ __forceinline__ void run_phase_g(uint64_t (&x)[G][1 << EB], uint32_t 
 #pragma unroll
     for (int bit = Ph::HB; bit >= Ph::LB; --bit) {
         const int spp = LOG_M - 1 - bit;
-        const uint32_t s = s0 + spp;
         const int pos = bit - Ph::WLO;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             if (e & (1 << pos)) continue;
-            const TwPair tp = twt[(1u << s) + tw_index<LOG_M, PH, EB>(l, e, bit, high, spp)];
+            const TwPair tp = tw.get(pos, e);
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 if constexpr (FP)
@@ -947,13 +1036,15 @@ __device__ __forceinline__ void run_phase_g(uint64_t (&x)[G][1 << EB], uint32_t 
 }
 // The forward register phases of one pass for G tiles, each exchanging
 // through its own LDS region (one barrier per exchange for all of them).
-template <int LOG_M, int EB, int G, bool FP, int K>
+template <int LOG_M, int EB, int G, bool FP, int K, int PRE>
 __device__ __forceinline__ void run_phases_g(uint64_t (&x)[G][1 << EB], uint64_t* lds, uint32_t c, uint32_t l,
                                              uint32_t high, uint32_t s0, const TwPair* __restrict__ twt,
                                              const DevMod& md) {
     constexpr int NPH = (LOG_M + EB - 1) / EB;
     constexpr uint32_t W = lds_words<LOG_M, EB>();
     if constexpr (K < NPH) {
+        // the phase's twiddle loads go out before the exchange
+        const PhaseTw<LOG_M, K, EB, false, false, PRE> tw(twt, l, high, s0);
         if constexpr (K > 0) {
 #pragma unroll
             for (int g = 0; g < G; ++g) lds_write<LOG_M, K - 1, EB>(x[g], lds + g * W, c, l);
@@ -964,8 +1055,8 @@ __device__ __forceinline__ void run_phases_g(uint64_t (&x)[G][1 << EB], uint64_t
 #pragma unroll
             for (int g = 0; g < G; ++g) lds_read<LOG_M, K, EB>(x[g], lds + g * W, c, l);
         }
-        run_phase_g<LOG_M, K, EB, G, FP>(x, l, high, s0, twt, md);
-        run_phases_g<LOG_M, EB, G, FP, K + 1>(x, lds, c, l, high, s0, twt, md);
+        run_phase_g<LOG_M, K, EB, G, FP, PRE>(x, tw, md);
+        run_phases_g<LOG_M, EB, G, FP, K + 1, PRE>(x, lds, c, l, high, s0, twt, md);
     }
 }
 
@@ -997,8 +1088,10 @@ __device__ __forceinline__ void run_phases_g(uint64_t (&x)[G][1 << EB], uint64_t
 // brought within q/2, each product formed by fmulmod against the quotient
 // w (1/q) (|term| < 0.9q, so the sum over at most 8 digits stays below
 // 2^53), the sums converted to canonical residues.  Otherwise x is brought
-// below q and Montgomery products with the key (stored times 2^64) are
-// added modulo q.  The rows of one kind form one launch (ri.row).
+// below q and the Montgomery products with the key (stored times 2^64) are
+// summed without REDC's final subtraction (terms below 2q, at most 8 of
+// them: below 16q < 2^64), the sums reduced below q once at the end.  The
+// rows of one kind form one launch (ri.row).
 template <int LOG_M, int EB, bool FP, int G>
 __global__ __launch_bounds__(4096 >> EB) __attribute__((amdgpu_waves_per_eu(4)))
 void k_row_inner(RowInner ri, const DevMod* __restrict__ mods, const TwPair* __restrict__ tw, uint32_t log_n) {
@@ -1062,7 +1155,9 @@ void k_row_inner(RowInner ri, const DevMod* __restrict__ mods, const TwPair* __r
                 const double a = as_f(k[e]);
                 acc[e] = as_u(as_f(acc[e]) + fmulmod(as_f(x[e]), a, a * qinv, qd));
             } else {
-                acc[e] = add_mod(acc[e], mont_redc(x[e] * k[e], mulhi64(x[e], k[e]), q, md.mont_neg_qinv), q);
+                // REDC without its final subtraction: each term lies in [0, 2q)
+                const uint64_t lo = x[e] * k[e], m = lo * md.mont_neg_qinv;
+                acc[e] += mulhi64(x[e], k[e]) + mulhi64(m, q) + (lo != 0 ? 1u : 0u);
             }
         }
     };
@@ -1078,6 +1173,16 @@ void k_row_inner(RowInner ri, const DevMod* __restrict__ mods, const TwPair* __r
         const uint64_t* __restrict__ src = item + ri.off_ext + ((size_t)(j * ri.rows + t) << log_n);
 #pragma unroll
         for (int e = 0; e < E; ++e) x[e] = src[((size_t)(sp0 + c) << LOG_M) | PIN::r_of(l, e)];
+    };
+    // an integer accumulator (at most 8 terms below 2q each: below 16q <
+    // 2^64) brought below q
+    [[maybe_unused]] auto settle_acc = [&](uint64_t v) -> uint64_t {
+#pragma unroll
+        for (int sh = 3; sh >= 0; --sh) {
+            const uint64_t m = q << sh;
+            v = v >= m ? v - m : v;
+        }
+        return v;
     };
     // the row pass's output brought within q/2 (FP) or below q
     auto settle = [&](uint64_t (&x)[E]) {
@@ -1105,7 +1210,7 @@ void k_row_inner(RowInner ri, const DevMod* __restrict__ mods, const TwPair* __r
         uint32_t zoff = 0, lj = l, cj = c;
         asm volatile("" : "+v"(zoff), "+v"(lj), "+v"(cj));
         const TwPair* __restrict__ twj = twt + zoff;
-        run_phases<LOG_M, EB, false, FP, false, 0>(x, lds, cj, lj, sp0 + c, s0, twj, md);
+        run_phases<LOG_M, EB, false, FP, false, 0, false, tw_pre_inner(FP, G)>(x, lds, cj, lj, sp0 + c, s0, twj, md);
         __syncthreads();  // the next digit's exchanges reuse the LDS
         settle(x);
         accumulate(x, j);
@@ -1117,7 +1222,7 @@ void k_row_inner(RowInner ri, const DevMod* __restrict__ mods, const TwPair* __r
         uint32_t zoff = 0, lj = l, cj = c;
         asm volatile("" : "+v"(zoff), "+v"(lj), "+v"(cj));
         const TwPair* __restrict__ twj = twt + zoff;
-        run_phases_g<LOG_M, EB, 2, FP, 0>(x, lds, cj, lj, sp0 + c, s0, twj, md);
+        run_phases_g<LOG_M, EB, 2, FP, 0, tw_pre_inner(FP, 2)>(x, lds, cj, lj, sp0 + c, s0, twj, md);
         __syncthreads();  // the next digits' exchanges reuse the LDS
         settle(x[0]);
         accumulate(x[0], j1);
@@ -1175,10 +1280,10 @@ void k_row_inner(RowInner ri, const DevMod* __restrict__ mods, const TwPair* __r
             v.x = fp_to_u64(acc1[2 * e], qd, qinv);
             v.y = fp_to_u64(acc1[2 * e + 1], qd, qinv);
         } else {
-            u.x = acc0[2 * e];
-            u.y = acc0[2 * e + 1];
-            v.x = acc1[2 * e];
-            v.y = acc1[2 * e + 1];
+            u.x = settle_acc(acc0[2 * e]);
+            u.y = settle_acc(acc0[2 * e + 1]);
+            v.x = settle_acc(acc1[2 * e]);
+            v.y = settle_acc(acc1[2 * e + 1]);
         }
         o0[e] = u;
         o1[e] = v;
@@ -1323,6 +1428,11 @@ void launch_row_inner(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, ui
     ri.rows = level + kc.K;
     ri.alpha = kc.alpha;
     ri.beta = (level + kc.alpha - 1) / kc.alpha;
+    // the integer accumulators hold at most 8 terms below 2q (callers check)
+    if (ri.beta > 8) {
+        fprintf(stderr, "launch_row_inner: %u digits, at most 8 supported\n", ri.beta);
+        abort();
+    }
     ri.L = kc.L;
     ri.krows = kc.L + kc.K;
     ri.tiles = (1u << log_n) >> 12;

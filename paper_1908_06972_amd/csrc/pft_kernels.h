@@ -199,6 +199,7 @@ struct RowInner {
     uint64_t kappa, kappa_inv;
 };
 bool row_inner_supported(uint32_t log_n);
+// at most 8 digits (ceil(level / alpha) <= 8; aborts otherwise)
 void launch_row_inner(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, uint64_t off_acc, const uint64_t* key,
                       uint32_t level, const KsConsts& kc, const DevTables& t, const uint32_t* fp_rows,
                       uint32_t log_n, const uint64_t* const* perm_src, uint64_t kappa, uint64_t kappa_inv,
