@@ -52,6 +52,15 @@ __device__ __forceinline__ void fwd_bfly(uint64_t& X, uint64_t& Y, uint64_t w, u
     Y = x - t + two_q;
 }
 
+// The same with X already below 2q (no reduction of X).
+__device__ __forceinline__ void fwd_bfly_low(uint64_t& X, uint64_t& Y, uint64_t w, uint64_t wp, uint64_t q,
+                                             uint64_t two_q) {
+    const uint64_t x = X;
+    const uint64_t t = shoup_lazy(Y, w, wp, q);
+    X = x + t;
+    Y = x - t + two_q;
+}
+
 // Gentleman-Sande inverse butterfly: X, Y in [0, 2q) -> X + Y, (X - Y) W in [0, 2q).
 __device__ __forceinline__ void inv_bfly(uint64_t& X, uint64_t& Y, uint64_t w, uint64_t wp, uint64_t q,
                                          uint64_t two_q) {
@@ -194,9 +203,13 @@ struct PhaseTw {
     }
 };
 
-template <int LOG_M, int PH, int EB, bool INV, bool FP, bool FOLD, int PRE>
+// LOW (forward only): the inputs are already reduced (fp64 within q/2 + 1
+// or below q; integers below 2q), so the first stage skips its reduction of
+// X; the bounds of the later stages are those of reduced inputs.
+template <int LOG_M, int PH, int EB, bool INV, bool FP, bool FOLD, int PRE, bool LOW = false>
 __device__ __forceinline__ void run_phase(uint64_t (&x)[1 << EB], const PhaseTw<LOG_M, PH, EB, INV, FOLD, PRE>& tw,
                                           const DevMod& md) {
+    static_assert(!LOW || (!INV && PH == 0), "reduced inputs enter the first forward phase");
     using Ph = Phase<LOG_M, PH, EB>;
     constexpr int E = 1 << EB;
     const uint64_t q = md.q, two_q = md.two_q;
@@ -210,8 +223,11 @@ __device__ __forceinline__ void run_phase(uint64_t (&x)[1 << EB], const PhaseTw<
             for (int e = 0; e < E; ++e) {
                 if (e & (1 << pos)) continue;
                 const TwPair tp = tw.get(pos, e);
+                const bool first = LOW && PH == 0 && spp == 0;  // folded after unrolling
                 if constexpr (FP)
-                    fwd_bfly_fp(x[e], x[e | (1 << pos)], tp, qd, qinv, spp % 3 == 0);
+                    fwd_bfly_fp(x[e], x[e | (1 << pos)], tp, qd, qinv, spp % 3 == 0 && !first);
+                else if (first)
+                    fwd_bfly_low(x[e], x[e | (1 << pos)], tp.w, tp.wp, q, two_q);
                 else
                     fwd_bfly(x[e], x[e | (1 << pos)], tp.w, tp.wp, q, two_q);
             }
@@ -254,11 +270,11 @@ __device__ __forceinline__ void run_phase(uint64_t (&x)[1 << EB], const PhaseTw<
 
 // One register phase loading each twiddle at its use (a single-phase pass:
 // with no exchange in the way the compiler schedules the loads itself).
-template <int LOG_M, int PH, int EB, bool INV, bool FP, bool FOLD>
+template <int LOG_M, int PH, int EB, bool INV, bool FP, bool FOLD, bool LOW = false>
 __device__ __forceinline__ void run_phase(uint64_t (&x)[1 << EB], uint32_t l, uint32_t high, uint32_t s0,
                                           const TwPair* __restrict__ twt, const DevMod& md) {
     const PhaseTw<LOG_M, PH, EB, INV, FOLD, 0> tw(twt, l, high, s0);
-    run_phase<LOG_M, PH, EB, INV, FP, FOLD, 0>(x, tw, md);
+    run_phase<LOG_M, PH, EB, INV, FP, FOLD, 0, LOW>(x, tw, md);
 }
 
 // LDS word of element r of sub-problem c: c S + r + P (r >> 4), or, where
@@ -926,10 +942,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             uint64_t x[16];
 #pragma unroll
             for (int e = 0; e < 16; ++e) x[e] = ybuf[tl * ROWP + 16u * e + u];
+            // the fold's values are reduced (within q/2 + 1, or below q)
             if (md.fp) {
-                run_phase<4, 0, 4, false, true, false>(x, 0u, 0u, 0u, twt, md);
+                run_phase<4, 0, 4, false, true, false, true>(x, 0u, 0u, 0u, twt, md);
             } else {
-                run_phase<4, 0, 4, false, false, false>(x, 0u, 0u, 0u, twt, md);
+                run_phase<4, 0, 4, false, false, false, true>(x, 0u, 0u, 0u, twt, md);
             }
             uint64_t* __restrict__ orow = out + ((size_t)t << log_n) + u0 + u;
 #pragma unroll
@@ -972,9 +989,9 @@ __global__ __launch_bounds__(256) void k_rescale_col_b(WsRef ws, uint64_t off_la
     if (md.fp) {
 #pragma unroll
         for (int e = 0; e < 16; ++e) x[e] = fp_from_u64(x[e]);
-        run_phase<4, 0, 4, false, true, false>(x, 0u, 0u, 0u, twt, md);
+        run_phase<4, 0, 4, false, true, false, true>(x, 0u, 0u, 0u, twt, md);  // canonical inputs
     } else {
-        run_phase<4, 0, 4, false, false, false>(x, 0u, 0u, 0u, twt, md);
+        run_phase<4, 0, 4, false, false, false, true>(x, 0u, 0u, 0u, twt, md);
     }
     uint64_t* __restrict__ orow = item + off_tmp + ((size_t)(b * nl + k) << log_n) + u0 + u;
 #pragma unroll
