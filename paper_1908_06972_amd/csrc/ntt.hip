@@ -891,9 +891,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             bop[h][kb] = split_digits(x);
         }
     }
-    // (stage_red's barrier also orders the LDS input reads above before the
-    // first target batch overwrites those rows)
-    stage_red(kc, s_red);
     const uint32_t kbs = DOWN ? kc.down_kb : kc.up_kb;
     const uint64_t* __restrict__ aop =
         (DOWN ? kc.down_aop : kc.up_aop + ((size_t)(level - 1) * kc.dnum + j) * kc.up_rt * kc.up_kb * 64) + lane;
@@ -901,6 +898,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     // target tt: its row and modulus index
     auto row_of = [&](uint32_t tt) { return DOWN ? tt : (tt < i0 ? tt : tt + na); };
     auto mod_of = [&](uint32_t t) { return t < level ? t : kc.L + (t - level); };
+    // the fold constants of every target (T <= L + K <= 64) into LDS in
+    // target order, so that a fold finds its own at s_red[tt]; the barrier
+    // also orders the LDS input reads above before the first target batch
+    // overwrites those rows
+    {
+        const uint64_t* src = reinterpret_cast<const uint64_t*>(kc.red);
+        uint64_t* dst = reinterpret_cast<uint64_t*>(s_red);
+        constexpr uint32_t WPR = sizeof(BconvRed) / 8;
+        for (uint32_t w = tid; w < T * WPR; w += blockDim.x) dst[w] = src[mod_of(row_of(w / WPR)) * WPR + w % WPR];
+        __syncthreads();
+    }
     long av[NKB];
 #pragma unroll
     for (uint32_t kb = 0; kb < NKB; ++kb) av[kb] = (long)aop[kb * 64];
@@ -927,7 +935,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                         int z[8];
                         if (uu == 0) tile_digits<0>(acc, z); else tile_digits<1>(acc, z);
                         // fp64 rows keep the fold's double (the pass's input form)
-                        ybuf[(tt - tb0) * ROWP + ci[h]] = fold_digits<true>(z, s_red[mod_of(row_of(tt))]);
+                        ybuf[(tt - tb0) * ROWP + ci[h]] = fold_digits<true>(z, s_red[tt]);
                     }
                 }
             }
