@@ -207,7 +207,10 @@ struct SwitchKeyDev {
     uint64_t last_use = 0;
 };
 
-// HIP-event bracketing of kernel families on the context stream.
+// HIP-event bracketing of kernel families on the context stream.  The
+// events only time work and are read after a stream synchronisation, so they
+// skip the system-scope fence (a cache writeback and invalidation each time
+// one is recorded) that the default event performs.
 struct EventProf : ProfHook {
     hipStream_t st = nullptr;
     uint32_t mask = 0;
@@ -224,7 +227,7 @@ struct EventProf : ProfHook {
     hipEvent_t get() {
         if (used == pool.size()) {
             hipEvent_t e;
-            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
             pool.push_back(e);
         }
         return pool[used++];
