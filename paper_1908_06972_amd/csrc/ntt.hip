@@ -27,7 +27,8 @@
 //     fp64 instructions instead of some twenty 32-bit integer ones (bounds at
 //     fmulmod below).
 //   * otherwise (q < 2^60): 64-bit integer Shoup butterflies kept lazily
-//     reduced (forward in [0, 4q), inverse in [0, 2q)).
+//     reduced (forward below 8q inside a pass and below 4q between passes,
+//     inverse in [0, 2q)).
 // Inputs below 4q are accepted; outputs of a full transform are in [0, q).
 #include "bconv_device.h"
 #include "pft_device.h"
@@ -43,16 +44,9 @@ namespace {
 
 // ---- integer butterflies (any q < 2^60)
 
-// Harvey forward butterfly: X, Y in [0, 4q) -> X + WY, X - WY in [0, 4q).
-__device__ __forceinline__ void fwd_bfly(uint64_t& X, uint64_t& Y, uint64_t w, uint64_t wp, uint64_t q,
-                                         uint64_t two_q) {
-    uint64_t x = X >= two_q ? X - two_q : X;
-    uint64_t t = shoup_lazy(Y, w, wp, q);
-    X = x + t;
-    Y = x - t + two_q;
-}
-
-// The same with X already below 2q (no reduction of X).
+// Harvey forward butterflies (WY by Shoup, below 2q for any Y < 2^64).
+// Without reducing X: X + WY and X - WY + 2q stay below B + 2q for X, Y
+// below B.
 __device__ __forceinline__ void fwd_bfly_low(uint64_t& X, uint64_t& Y, uint64_t w, uint64_t wp, uint64_t q,
                                              uint64_t two_q) {
     const uint64_t x = X;
@@ -60,6 +54,23 @@ __device__ __forceinline__ void fwd_bfly_low(uint64_t& X, uint64_t& Y, uint64_t 
     X = x + t;
     Y = x - t + two_q;
 }
+// The same with X below 8q reduced below 2q in two steps.
+__device__ __forceinline__ void fwd_bfly_r8(uint64_t& X, uint64_t& Y, uint64_t w, uint64_t wp, uint64_t q,
+                                            uint64_t two_q) {
+    const uint64_t four_q = two_q << 1;
+    uint64_t x = X >= four_q ? X - four_q : X;
+    x = x >= two_q ? x - two_q : x;
+    const uint64_t t = shoup_lazy(Y, w, wp, q);
+    X = x + t;
+    Y = x - t + two_q;
+}
+// Integer forward stages of a pass reduce X only at stages spp with
+// (LOG_M - 1 - spp) divisible by 3, counted from the pass's last stage so
+// that the last stage reduces: from inputs below 4q, the (at most two)
+// stages before a reducing one leave values below 6q and 8q (< 2^63 for q
+// < 2^60), the reducing stage brings X below 2q in two steps, and every
+// pass ends below 4q as with a reduction at every stage.
+__device__ __forceinline__ constexpr bool int_fwd_reduces(int log_m, int spp) { return (log_m - 1 - spp) % 3 == 0; }
 
 // Gentleman-Sande inverse butterfly: X, Y in [0, 2q) -> X + Y, (X - Y) W in [0, 2q).
 __device__ __forceinline__ void inv_bfly(uint64_t& X, uint64_t& Y, uint64_t w, uint64_t wp, uint64_t q,
@@ -226,10 +237,10 @@ __device__ __forceinline__ void run_phase(uint64_t (&x)[1 << EB], const PhaseTw<
                 const bool first = LOW && PH == 0 && spp == 0;  // folded after unrolling
                 if constexpr (FP)
                     fwd_bfly_fp(x[e], x[e | (1 << pos)], tp, qd, qinv, spp % 3 == 0 && !first);
-                else if (first)
+                else if (first || !int_fwd_reduces(LOG_M, spp))
                     fwd_bfly_low(x[e], x[e | (1 << pos)], tp.w, tp.wp, q, two_q);
                 else
-                    fwd_bfly(x[e], x[e | (1 << pos)], tp.w, tp.wp, q, two_q);
+                    fwd_bfly_r8(x[e], x[e | (1 << pos)], tp.w, tp.wp, q, two_q);
             }
         }
     } else {
@@ -1053,8 +1064,10 @@ __device__ __forceinline__ void run_phase_g(uint64_t (&x)[G][1 << EB],
             for (int g = 0; g < G; ++g) {
                 if constexpr (FP)
                     fwd_bfly_fp(x[g][e], x[g][e | (1 << pos)], tp, qd, qinv, spp % 3 == 0);
+                else if (!int_fwd_reduces(LOG_M, spp))
+                    fwd_bfly_low(x[g][e], x[g][e | (1 << pos)], tp.w, tp.wp, q, two_q);
                 else
-                    fwd_bfly(x[g][e], x[g][e | (1 << pos)], tp.w, tp.wp, q, two_q);
+                    fwd_bfly_r8(x[g][e], x[g][e | (1 << pos)], tp.w, tp.wp, q, two_q);
             }
         }
     }
