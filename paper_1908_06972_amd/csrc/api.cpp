@@ -1624,10 +1624,21 @@ static ItemPtrs ws_items(WsRef ws, uint32_t n, uint64_t off = 0) {
     return ip;
 }
 
-// Whether the forward schedule of `limbs` limbs starts with a radix-16
-// column pass (the pass the fused base-conversion kernels apply).
+// Forward transforms whose first pass a fused kernel applies (the base
+// conversions, RESCALE's expansion) take their schedule among those that
+// start with a radix-16 column pass where the ring is large (N >= 2^15) and
+// so is the batch (a class above 256 limbs): there the fused path beats any
+// unfused schedule (bag-of-words batch at N = 2^15: 450 -> 530 documents/s),
+// while with smaller rings or batches the tuner's unrestricted choice is
+// kept (it fuses only when that choice starts with radix 16 anyway; a forced
+// fusion was 10-17% slower on the N = 2^14 op list).
+static bool fwd_col16_restricted(const pft_ctx* c, uint64_t limbs) {
+    return c->P->log_n >= 15 && ntt_class(limbs) >= 9;
+}
+// Whether a forward transform of `limbs` limbs starts with a radix-16 column
+// pass under that choice (or the pinned schedule).
 static bool first_pass_col16(pft_ctx* c, uint64_t limbs) {
-    const NttSchedule s = ntt_schedule(c, false, limbs);
+    const NttSchedule s = ntt_schedule(c, false, limbs, fwd_col16_restricted(c, limbs));
     return s.n_passes >= 2 && s.radix[0] == 4;
 }
 // Whether an inverse transform of `limbs` limbs can end with a radix-16
@@ -1689,8 +1700,9 @@ static void key_switch_b(pft_ctx* c, uint32_t n, WsRef ws, const KsLayout& K, ui
     // inner product: fused in one kernel where that pass is the row pass of
     // a (4, log_n - 4) schedule, else a transform launch per digit group and
     // the inner-product kernel
-    const NttSchedule rs = ntt_schedule(c, false, full.empty() ? (uint64_t)last.size() * (rows - na_last)
-                                                               : (uint64_t)full.size() * (rows - A));
+    const uint64_t rs_limbs =
+        full.empty() ? (uint64_t)last.size() * (rows - na_last) : (uint64_t)full.size() * (rows - A);
+    const NttSchedule rs = ntt_schedule(c, false, rs_limbs, fuse && fwd_col16_restricted(c, rs_limbs));
     const bool fuse_inner =
         fuse && c->inner_fuse && beta <= 8 && row_inner_supported(lg) && rs.n_passes == 2 && rs.radix[0] == 4;
     const bool fold = rot && fuse_inner;
@@ -1750,8 +1762,12 @@ static void key_switch_b(pft_ctx* c, uint32_t n, WsRef ws, const KsLayout& K, ui
                              hook(c));
         } else {
             const uint32_t first = fuse ? 1u : 0u;
-            if (!full.empty()) ntt_jobs(c, full, rows - A, level, false, 0, nullptr, 0, first);
-            if (!last.empty()) ntt_jobs(c, last, rows - na_last, level, false, 0, nullptr, 0, first);
+            if (!full.empty())
+                ntt_jobs(c, full, rows - A, level, false, 0, nullptr, 0, first,
+                         fuse && fwd_col16_restricted(c, (uint64_t)full.size() * (rows - A)));
+            if (!last.empty())
+                ntt_jobs(c, last, rows - na_last, level, false, 0, nullptr, 0, first,
+                         fuse && fwd_col16_restricted(c, (uint64_t)last.size() * (rows - na_last)));
             // key inner product over level + K rows: the key is read once per
             // launch (shared by the batch); each item reads beta inputs and
             // writes two outputs per row
@@ -1818,7 +1834,8 @@ static void key_switch_b(pft_ctx* c, uint32_t n, WsRef ws, const KsLayout& K, ui
             epi.kappa = rot->kappa;
             epi.kappa_inv = rot->kappa_inv;
         }
-        ntt_jobs(c, jobs, level, ~0u, false, 0, &epi, 0, fuse_down ? 1u : 0u);
+        ntt_jobs(c, jobs, level, ~0u, false, 0, &epi, 0, fuse_down ? 1u : 0u,
+                 fuse_down && fwd_col16_restricted(c, 2ull * n * level));
     }
 }
 
@@ -1983,7 +2000,8 @@ extern "C" int pft_rescale_batch(pft_ctx* c, uint32_t n, const pft_ct* in, uint3
         epi.level = l - 1;
         epi.pinv = c->rescale_qinv + (size_t)(l - 1) * P->L;
         epi.pinv_fp = c->rescale_qinv + (size_t)P->L * P->L + (size_t)(l - 1) * P->L;
-        ntt_jobs(c, jt, l - 1, ~0u, false, 0, &epi, 0, fuse ? 1u : 0u);
+        ntt_jobs(c, jt, l - 1, ~0u, false, 0, &epi, 0, fuse ? 1u : 0u,
+                 fuse && fwd_col16_restricted(c, (uint64_t)jt.size() * (l - 1)));
         for (uint32_t z = 0; z < cnt; ++z) {
             out[g[z]].level = l - 1;
             out[g[z]].scale = in[g[z]].scale / (double)P->q[l - 1];

@@ -315,6 +315,8 @@ template <int EB> struct LdsPad<9, EB> { static constexpr uint32_t S = 546, P = 
 template <> struct LdsPad<9, 3> { static constexpr uint32_t S = 514, P = 0, XA = 4, XB = 6; };
 template <int EB> struct LdsPad<10, EB> { static constexpr uint32_t S = 1092, P = 1, XA = 0, XB = 0; };
 template <> struct LdsPad<10, 3> { static constexpr uint32_t S = 1026, P = 0, XA = 4, XB = 4; };
+template <int EB> struct LdsPad<11, EB> { static constexpr uint32_t S = 2176, P = 1, XA = 0, XB = 0; };
+template <> struct LdsPad<11, 3> { static constexpr uint32_t S = 2048, P = 0, XA = 4, XB = 5; };
 template <int EB> struct LdsPad<12, EB> { static constexpr uint32_t S = 4352, P = 1, XA = 0, XB = 0; };
 template <> struct LdsPad<12, 3> { static constexpr uint32_t S = 4096, P = 0, XA = 4, XB = 6; };
 template <int LOG_M, int EB>
@@ -1338,6 +1340,7 @@ void launch_radix(uint32_t radix, const PolyBatch& b, const DevTables& t, uint32
         case 8: launch_pass<8, INV>(b, t, log_n, s0, fin, stage, e8, epi, st, prof); break;
         case 9: launch_pass<9, INV>(b, t, log_n, s0, fin, stage, e8, epi, st, prof); break;
         case 10: launch_pass<10, INV>(b, t, log_n, s0, fin, stage, e8, epi, st, prof); break;
+        case 11: launch_pass<11, INV>(b, t, log_n, s0, fin, stage, e8, epi, st, prof); break;
         case 12: launch_pass<12, INV>(b, t, log_n, s0, fin, stage, e8, epi, st, prof); break;
         default: break;
     }
@@ -1356,7 +1359,7 @@ int ntt_candidates(uint32_t log_n, NttSchedule* out, int max_out) {
     static const uint8_t c12[][2] = {{12, 0}, {8, 4}, {6, 6}, {4, 8}};
     static const uint8_t c13[][2] = {{7, 6}, {6, 7}, {4, 9}};
     static const uint8_t c14[][2] = {{7, 7}, {8, 6}, {6, 8}, {4, 10}};
-    static const uint8_t c15[][2] = {{8, 7}, {7, 8}, {6, 9}};
+    static const uint8_t c15[][2] = {{8, 7}, {7, 8}, {6, 9}, {4, 11}};
     static const uint8_t c16[][2] = {{8, 8}, {7, 9}, {6, 10}, {4, 12}};
     const uint8_t(*c)[2] = nullptr;
     int n = 0;
@@ -1364,7 +1367,7 @@ int ntt_candidates(uint32_t log_n, NttSchedule* out, int max_out) {
         case 12: c = c12; n = 4; break;
         case 13: c = c13; n = 3; break;
         case 14: c = c14; n = 4; break;
-        case 15: c = c15; n = 3; break;
+        case 15: c = c15; n = 4; break;
         case 16: c = c16; n = 4; break;
         default: return 0;
     }
@@ -1442,7 +1445,7 @@ void launch_rescale_col_b(uint32_t n, WsRef ws, uint64_t off_last, uint64_t off_
 
 bool row_inner_supported(uint32_t log_n) {
     const uint32_t r = log_n - 4;
-    return r == 8 || r == 9 || r == 10 || r == 12;
+    return r >= 8 && r <= 12;
 }
 
 void launch_row_inner(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, uint64_t off_acc, const uint64_t* key,
@@ -1517,6 +1520,7 @@ void launch_row_inner(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, ui
                 case 8: by_eb(std::integral_constant<int, 8>{}); break;
                 case 9: by_eb(std::integral_constant<int, 9>{}); break;
                 case 10: by_eb(std::integral_constant<int, 10>{}); break;
+                case 11: by_eb(std::integral_constant<int, 11>{}); break;
                 case 12: by_eb(std::integral_constant<int, 12>{}); break;
                 default: break;
             }

@@ -23,6 +23,9 @@ CASES = {
     "a2_n14": dict(log_n=14, n_q=8, q0_bits=60, q_bits=40, n_p=2, p_bits=60, dnum=4, scale=2 ** 40),
     # alpha 3 at N = 2^13 (schedule (4, 9), a 512-point row pass), odd K
     "a3_n13": dict(log_n=13, n_q=6, q0_bits=60, q_bits=45, n_p=3, p_bits=60, dnum=2, scale=2 ** 45),
+    # alpha 4 at N = 2^15 as in the bag-of-words ring (schedule (4, 11), a
+    # 2048-point row pass, two sub-problems per workgroup)
+    "a4_n15": dict(log_n=15, n_q=8, q0_bits=60, q_bits=40, n_p=4, p_bits=60, dnum=2, scale=2 ** 40),
 }
 STEPS = [1, 5]
 
@@ -88,7 +91,7 @@ def test_fused_modup_relin_and_rotation(name, flags):
         w.ctx.ntt_set_schedule(False, None)
 
 
-@pytest.mark.parametrize("name", ["a6_n12", "a2_n14"])
+@pytest.mark.parametrize("name", ["a6_n12", "a2_n14", "a4_n15"])
 def test_fused_modup_batch_equals_unfused(name):
     """Three items in one launch: the key inner product fused with the row
     pass of ModUp's rows, the fused passes alone and the unfused path
