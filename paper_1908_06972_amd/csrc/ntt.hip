@@ -1019,32 +1019,6 @@ __global__ __launch_bounds__(256) void k_rescale_col_b(WsRef ws, uint64_t off_la
     for (int e = 0; e < 16; ++e) orow[(size_t)e * S] = x[e];
 }
 
-// The key inner product of hybrid key switching fused with the last pass of
-// the forward transform of ModUp's rows.  Where the conversion kernel has
-// already applied the first pass (a radix-16 column pass), each extended row
-// needs one row pass of LOG_M = log_n - 4 stages over 4096-word tiles.  A
-// workgroup takes one tile of row t of one item and every digit j in turn:
-// x_j is d itself where t is one of digit j's own rows (d is in the NTT
-// domain already) or ext_j[t] taken through the row pass in registers; the
-// product with the key tile is accumulated, and only the two accumulator
-// tiles acc_b[t] = sum_j x_j key_{j,b}[t] (b = 0, 1) are written.  The
-// extended digits are read once instead of being written back by the row
-// pass and read again by a separate inner-product kernel.  The products are
-// taken in the arrangement the pass ends in (each thread holds E
-// consecutive words of its sub-problem), so d, the key and the accumulators
-// move as 16-byte accesses per lane and no LDS staging is needed.
-//
-// Block order: blocks are issued to the eight XCDs round-robin; block id
-// 8 k + x runs item k mod n of the (row, tile) pair 8 floor(k / n) + x, so
-// the items sharing one key tile run on one XCD at about the same time and
-// the tile comes from HBM about once per launch, then from that XCD's L2.
-//
-// FP (rows with q < 2^50, the key holding integer-valued doubles): x is
-// brought within q/2, each product formed by fmulmod against the quotient
-// w (1/q) (|term| < 0.9q, so the sum over at most 8 digits stays below
-// 2^53), the sums converted to canonical residues.  Otherwise x is brought
-// below q and Montgomery products with the key (stored times 2^64) are
-// added modulo q.  The rows of one kind form one launch (ri.row).
 // Forward register phase PH applied to G independent tiles at once: each
 // twiddle is loaded once and serves the butterflies of every tile.
 template <int LOG_M, int PH, int EB, int G, bool FP, int PRE>
