@@ -134,19 +134,10 @@ __device__ __forceinline__ uint32_t tw_index(uint32_t l, int e, int bit, uint32_
     return (high << spp) | (lhi << (Ph::WLO + EB - bit - 1)) | ((uint32_t)e >> (bit + 1 - Ph::WLO));
 }
 
-// The twiddles of register phase PH for one thread.  At the stage whose
-// butterflies span window bit pos, the upper elements e that agree in
-// e >> (pos + 1) share one twiddle (tw_index drops the bits below), so the
-// stage needs E >> (pos + 1) of them.  The first stages in execution order,
-// up to eight twiddles, are loaded by the constructor: a pass builds the set
-// of its next phase before the LDS exchange that precedes that phase, so the
-// loads are in flight during the exchange and its barrier (the fences of
-// the exchange would keep the compiler from moving them there itself).  The
-// later stages load at use.  The inverse transform's final stage with N^-1
-// folded in (FOLD, phase 0, top bit) uses none.  PRE: at most that many
-// twiddles preloaded (the registers they hold compete with the pass's own).
-// Twiddles preloaded per phase ahead of an exchange: by the transform
-// passes with 8 or 16 residues per thread, and by the fused inner product.
+// Twiddles preloaded per register phase ahead of the exchange before it
+// (PhaseTw below): by the transform passes with 8 or 16 residues per
+// thread, and by the fused inner product (fp64 rows two digits or one per
+// pass, 60-bit rows); larger budgets spill or cost waves per SIMD.
 constexpr int TW_PRE_PASS3 = 8;
 constexpr int TW_PRE_PASS4 = 3;
 constexpr int TW_PRE_INNER_FP2 = 3;
@@ -156,6 +147,16 @@ constexpr int tw_pre_pass(int eb) { return eb == 3 ? TW_PRE_PASS3 : eb == 4 ? TW
 constexpr int tw_pre_inner(bool fp, int g) {
     return fp ? (g == 2 ? TW_PRE_INNER_FP2 : TW_PRE_INNER_FP1) : TW_PRE_INNER_INT;
 }
+// The twiddles of register phase PH for one thread.  At the stage whose
+// butterflies span window bit pos, the upper elements e that agree in
+// e >> (pos + 1) share one twiddle (tw_index drops the bits below), so the
+// stage needs E >> (pos + 1) of them.  The first stages in execution order,
+// up to PRE twiddles, are loaded by the constructor: a pass builds the set
+// of its next phase before the LDS exchange that precedes that phase, so the
+// loads are in flight during the exchange and its barrier (the fences of
+// the exchange would keep the compiler from moving them there itself).  The
+// later stages load at use.  The inverse transform's final stage with N^-1
+// folded in (FOLD, phase 0, top bit) uses none.
 template <int LOG_M, int PH, int EB, bool INV, bool FOLD, int PRE = 8>
 struct PhaseTw {
     using Ph = Phase<LOG_M, PH, EB>;
