@@ -1326,6 +1326,12 @@ def main():
         # the kernel is further along its integer-ALU roof than its HBM roof
         roofline.update({"bound": "alu", "achieved": alu["achieved"], "peak": alu["peak"], "unit": alu["unit"],
                          "frac": alu["frac"]})
+    elif not alu and d_bytes == 0:
+        # no method bytes (it only reads and writes the middle of transforms)
+        # and no stored counters taken on this kernel source: its roof is
+        # unknown here, not an HBM fraction of zero
+        roofline.update({"bound": "alu", "achieved": None, "peak": ALU_PEAK_GOPS, "unit": "G lane-op/s",
+                         "frac": None, "note": "no counters under profiles/ for this kernel source"})
     # whole operations and the whole step against the HBM peak
     copy_gbs = copy_bandwidth()
     ops = op_alg_bytes(lp, args.batch)
