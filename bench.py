@@ -1181,7 +1181,11 @@ def main():
         return table
 
     if args.profile_steps:
-        # one settling step (autotuner), then the profiled steps
+        # one settling step (autotuner), then the profiled steps.  Timing the
+        # key inner product's launches (HIP events) keeps its two row kinds
+        # on one stream, one after the other, so that the trace gives each
+        # launch its own duration (the timed steps run them concurrently).
+        prof_enable(ctx, 1 << FAMILIES.index("key_inner_product"))
         for i in range(1 + args.profile_steps):
             job_step(ctx, cts)
             sync()

@@ -103,7 +103,11 @@ int pft_params_dims(const pft_params* params, uint32_t* dims);
 
 const char* pft_last_error(void);
 
-/* One context per device and stream.  stream may be NULL (the null stream). */
+/* One context per device and stream.  stream may be NULL (the null stream).
+ * Every call enqueues its work on that stream; within a call the library may
+ * fork work onto a helper stream of its own (created with the context) and
+ * always joins it back into the context stream before the call returns, so
+ * the context stream's order (and a graph captured from it) covers it. */
 int pft_ctx_create(const pft_params* params, int device, void* hip_stream, pft_ctx** out);
 void pft_ctx_destroy(pft_ctx* ctx);
 int pft_ctx_synchronize(pft_ctx* ctx);

@@ -233,16 +233,16 @@ struct EventProf : ProfHook {
         return pool[used++];
     }
     bool on(int kid) const { return (mask >> kid) & 1u; }
-    void begin(int kid) override {
+    void begin(int kid, hipStream_t s) override {
         if (!on(kid)) return;
         open[kid] = get();
-        if (open[kid]) (void)hipEventRecord(open[kid], st);
+        if (open[kid]) (void)hipEventRecord(open[kid], s ? s : st);
     }
-    void end(int kid, double bytes, double ops, uint32_t variant) override {
+    void end(int kid, double bytes, double ops, uint32_t variant, hipStream_t s) override {
         if (!on(kid) || !open[kid]) return;
         hipEvent_t b = get();
         if (!b) return;
-        (void)hipEventRecord(b, st);
+        (void)hipEventRecord(b, s ? s : st);
         recs.push_back(Rec{kid, variant, open[kid], b, bytes, ops});
         open[kid] = nullptr;
     }
@@ -318,6 +318,12 @@ struct pft_ctx {
     bool ntt_tune = true;
     NttSchedule ntt_pinned[2] = {};
     std::map<uint32_t, NttSchedule> ntt_tuned;
+    // the stream the context was created with, and a helper stream beside
+    // it: the fused inner product's 60-bit rows run there concurrently with
+    // its fp64 rows (forked from and joined back into the context stream)
+    hipStream_t home = nullptr;
+    hipStream_t inner_st = nullptr;
+    hipEvent_t inner_fork = nullptr, inner_join = nullptr;
     // op-list executor: side streams and their workspaces (branch k > 0;
     // branch 0 is the context stream with ws)
     std::vector<hipStream_t> side;
@@ -647,7 +653,20 @@ extern "C" int pft_ctx_create_alloc(const pft_params* P, int device, void* strea
     c->P = P;
     c->device = device;
     c->stream = (hipStream_t)stream;
+    c->home = c->stream;
     c->prof.st = c->stream;
+    // the inner product's helper stream (default priority); without it the
+    // two kinds of rows run one after the other on the context stream
+    if (hipStreamCreateWithFlags(&c->inner_st, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->inner_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->inner_join, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        if (c->inner_st) (void)hipStreamDestroy(c->inner_st);
+        if (c->inner_fork) (void)hipEventDestroy(c->inner_fork);
+        if (c->inner_join) (void)hipEventDestroy(c->inner_join);
+        c->inner_st = nullptr;
+        c->inner_fork = c->inner_join = nullptr;
+    }
     for (uint64_t m : P->mods) c->fp_rows.push_back(ntt_fp(m) ? 1u : 0u);
     // the device address of this GPU's fixed scratch (null if unavailable:
     // then only the allocation-free entry point refuses)
@@ -667,6 +686,7 @@ extern "C" void pft_ctx_destroy(pft_ctx* c) {
     (void)hipStreamSynchronize(c->stream);
     for (hipStream_t st : c->side) (void)hipStreamSynchronize(st);
     if (c->copy_st) (void)hipStreamSynchronize(c->copy_st);
+    if (c->inner_st) (void)hipStreamSynchronize(c->inner_st);
     for (void* p : c->allocs) dev_free(c, p);
     dev_free(c, c->ws);
     dev_free(c, c->aux);
@@ -685,6 +705,9 @@ extern "C" void pft_ctx_destroy(pft_ctx* c) {
     }
     for (hipEvent_t e : c->side_ev) (void)hipEventDestroy(e);
     for (auto& w : c->side_ws) dev_free(c, w.first);
+    if (c->inner_st) (void)hipStreamDestroy(c->inner_st);
+    if (c->inner_fork) (void)hipEventDestroy(c->inner_fork);
+    if (c->inner_join) (void)hipEventDestroy(c->inner_join);
     delete c;
 }
 
@@ -1757,9 +1780,29 @@ static void key_switch_b(pft_ctx* c, uint32_t n, WsRef ws, const KsLayout& K, ui
             const uint64_t* c1[PFT_MAX_ITEMS] = {};
             if (fold)
                 for (uint32_t z = 0; z < n; ++z) c1[z] = rot->src.p[z] + nl;
-            launch_row_inner(n, ws, off_d, K.off_ext, K.off_acc, key.data, level, c->kc, c->tabs, c->fp_rows.data(),
-                             lg, c1, fold ? rot->kappa : 0, fold ? rot->kappa_inv : 0, c->inner_pairs, c->stream,
-                             hook(c));
+            auto inner = [&](hipStream_t st, uint32_t rows_sel) {
+                launch_row_inner(n, ws, off_d, K.off_ext, K.off_acc, key.data, level, c->kc, c->tabs,
+                                 c->fp_rows.data(), lg, c1, fold ? rot->kappa : 0, fold ? rot->kappa_inv : 0,
+                                 c->inner_pairs, st, hook(c), rows_sel);
+            };
+            // on the context's own stream the 60-bit rows run on the helper
+            // stream beside the fp64 rows, so that each launch fills the
+            // other's tail; the helper's work is joined back before ModDown
+            // (and before anything later reads the accumulators or the key).
+            // While this family is being timed per launch the two run one
+            // after the other, so that each launch's time is its own.
+            const bool split = c->inner_st && c->stream == c->home && !c->prof.on(PK_KEY_INNER) &&
+                               hipEventRecord(c->inner_fork, c->stream) == hipSuccess &&
+                               hipStreamWaitEvent(c->inner_st, c->inner_fork, 0) == hipSuccess;
+            if (split) {
+                inner(c->inner_st, ROW_INNER_INT);
+                inner(c->stream, ROW_INNER_FP);
+                if (hipEventRecord(c->inner_join, c->inner_st) != hipSuccess ||
+                    hipStreamWaitEvent(c->stream, c->inner_join, 0) != hipSuccess)
+                    (void)hipStreamSynchronize(c->inner_st);  // last resort: never read unfinished rows
+            } else {
+                inner(c->stream, ROW_INNER_ALL);
+            }
         } else {
             const uint32_t first = fuse ? 1u : 0u;
             if (!full.empty())

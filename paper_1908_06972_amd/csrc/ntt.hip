@@ -1426,7 +1426,7 @@ bool row_inner_supported(uint32_t log_n) {
 void launch_row_inner(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, uint64_t off_acc, const uint64_t* key,
                       uint32_t level, const KsConsts& kc, const DevTables& t, const uint32_t* fp_rows,
                       uint32_t log_n, const uint64_t* const* perm_src, uint64_t kappa, uint64_t kappa_inv,
-                      bool pair_digits, hipStream_t st, ProfHook* prof) {
+                      bool pair_digits, hipStream_t st, ProfHook* prof, uint32_t rows_sel) {
     RowInner ri{};
     if (kappa) {
         for (uint32_t z = 0; z < n; ++z) ri.perm_src[z] = perm_src[z];
@@ -1453,6 +1453,7 @@ void launch_row_inner(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, ui
     ri.krows = kc.L + kc.K;
     ri.tiles = (1u << log_n) >> 12;
     for (int fp = 1; fp >= 0; --fp) {
+        if (!(rows_sel & (fp ? ROW_INNER_FP : ROW_INNER_INT))) continue;
         // the rows of one arithmetic kind, in chunks that fit the row list
         std::vector<uint16_t> rows;
         for (uint32_t r = 0; r < ri.rows; ++r) {
@@ -1475,7 +1476,7 @@ void launch_row_inner(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, ui
                 ops += N * n * (0.5 * lm * (ri.beta - own) + 2.0 * ri.beta);
             }
             const bool g2 = fp && pair_digits;
-            if (prof) prof->begin(PK_KEY_INNER);
+            if (prof) prof->begin(PK_KEY_INNER, st);
             auto go = [&](auto lm, auto eb) {
                 constexpr int LM = decltype(lm)::value, EB = decltype(eb)::value;
                 if (g2)
@@ -1500,7 +1501,8 @@ void launch_row_inner(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, ui
                 default: break;
             }
             // variant: 1024 + radix, + 64 for the fp64 rows, + 128 with two digits per pass
-            if (prof) prof->end(PK_KEY_INNER, bytes, ops, 1024u + (log_n - 4) + (fp ? 64u : 0u) + (g2 ? 128u : 0u));
+            if (prof)
+                prof->end(PK_KEY_INNER, bytes, ops, 1024u + (log_n - 4) + (fp ? 64u : 0u) + (g2 ? 128u : 0u), st);
         }
     }
 }

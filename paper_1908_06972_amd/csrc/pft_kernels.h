@@ -21,8 +21,9 @@ enum ProfKernel : int {
 // variant: which instantiation of the family ran (0 for single-kernel
 // families; NTT passes: 1 + (radix | col << 5 | final << 6 | staged << 7)).
 struct ProfHook {
-    virtual void begin(int kid) = 0;
-    virtual void end(int kid, double bytes, double ops, uint32_t variant = 0) = 0;
+    // st: the stream the bracketed launch goes to (null: the context stream)
+    virtual void begin(int kid, hipStream_t st = nullptr) = 0;
+    virtual void end(int kid, double bytes, double ops, uint32_t variant = 0, hipStream_t st = nullptr) = 0;
     virtual ~ProfHook() {}
 };
 
@@ -199,11 +200,14 @@ struct RowInner {
     uint64_t kappa, kappa_inv;
 };
 bool row_inner_supported(uint32_t log_n);
-// at most 8 digits (ceil(level / alpha) <= 8; aborts otherwise)
+// at most 8 digits (ceil(level / alpha) <= 8; aborts otherwise).  rows:
+// which rows this call launches, ROW_INNER_FP (those with q < 2^50),
+// ROW_INNER_INT (the others) or both.
+enum : uint32_t { ROW_INNER_INT = 1, ROW_INNER_FP = 2, ROW_INNER_ALL = 3 };
 void launch_row_inner(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, uint64_t off_acc, const uint64_t* key,
                       uint32_t level, const KsConsts& kc, const DevTables& t, const uint32_t* fp_rows,
                       uint32_t log_n, const uint64_t* const* perm_src, uint64_t kappa, uint64_t kappa_inv,
-                      bool pair_digits, hipStream_t st, ProfHook* prof = nullptr);
+                      bool pair_digits, hipStream_t st, ProfHook* prof = nullptr, uint32_t rows = ROW_INNER_ALL);
 // acc [2][level+K][N] = sum_j x_j * key_j  (key: [dnum][2][L+K][N], Montgomery form)
 void launch_key_inner_b(uint32_t n, WsRef ws, uint64_t off_d, uint64_t off_ext, uint64_t off_acc, const uint64_t* key,
                         uint32_t level, const KsConsts& kc, const DevTables& t, uint32_t log_n, hipStream_t st);
