@@ -112,8 +112,8 @@ def test_library_decode_matches_oracle():
 def test_ntt_candidate_schedules():
     """Schedules cover log2 N exactly, default first, at most two passes, only
     the last window may exceed radix 8 (column passes need >= 16 sub-problems
-    per workgroup), and each radix split comes staged and direct, with 16 and 8
-    residues per thread."""
+    per workgroup), each radix split comes staged and direct, with 16 and 8
+    residues per thread, and every size has the (4, log2 N - 4) split."""
     from paper_1908_06972_amd.ckks import Params
     lib = N.load()
     for log_n in range(12, 17):
@@ -128,6 +128,10 @@ def test_ntt_candidate_schedules():
             assert sum(radices) == log_n and 1 <= len(radices) <= 2
             assert all(r <= 8 for r in radices[:-1])
             assert flags in (0, 1, 2, 3)
+        # every size offers the split the fused conversions need: a radix-16
+        # column pass, then one row pass, in all four variants
+        for flags in (0, 1, 2, 3):
+            assert ((4, log_n - 4), flags) in scheds, (log_n, flags)
             assert all((radices, f) in scheds for f in (0, 1, 2, 3))
         assert scheds[0] == ({12: (12,), 13: (7, 6), 14: (7, 7), 15: (8, 7), 16: (8, 8)}[log_n], 0)
 
