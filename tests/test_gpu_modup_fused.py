@@ -165,3 +165,36 @@ def test_inverse_fused_conversions(name, inv):
     finally:
         w.ctx.ntt_set_schedule(False, None)
         w.ctx.ntt_set_schedule(True, None)
+
+
+@pytest.mark.parametrize("name", ["a6_n12", "a4_n15"])
+def test_inner_product_row_kinds_concurrent_and_sequential(name):
+    """The fused inner product's 60-bit rows run on the context's helper
+    stream beside its fp64 rows, except while the family is timed per launch
+    (then one after the other): both orders give the oracle's ciphertexts,
+    for relinearisation and rotation of a batch."""
+    import paper_1908_06972_amd.native as N
+    w = world(name)
+    sched = [c for c in w.col16 if c[1] == 0][0]
+    w.ctx.ntt_set_schedule(False, sched)
+    level = w.op.L
+    pairs = [(w.enc_pair(200 + i, level), w.enc_pair(210 + i, level)) for i in range(2)]
+    try:
+        outs = []
+        for mask in (0, 1 << 3):  # key inner product family timed: sequential
+            N.check(w.ctx.lib.pft_prof_enable(w.ctx.handle, mask))
+            rel = w.ctx.mul_relin_batch([p[0][0] for p in pairs], [p[1][0] for p in pairs])
+            rot = w.ctx.rotate_batch([p[0][0] for p in pairs], STEPS[1])
+            outs.append([w.ctx.export(g) for g in rel + rot])
+        N.check(w.ctx.lib.pft_prof_enable(w.ctx.handle, 0))
+        for a, b in zip(outs[0], outs[1]):
+            assert np.array_equal(a, b)
+        for ((_, oa), (_, ob)), host in zip(pairs, outs[0][:2]):
+            o = C.hmul_relin(w.op, oa, ob, w.rlk)
+            assert np.array_equal(host[0], o.c0) and np.array_equal(host[1], o.c1)
+        for ((_, oa), _), host in zip(pairs, outs[0][2:]):
+            o = C.rotate(w.op, oa, STEPS[1], w.rot[STEPS[1]])
+            assert np.array_equal(host[0], o.c0) and np.array_equal(host[1], o.c1)
+    finally:
+        N.check(w.ctx.lib.pft_prof_enable(w.ctx.handle, 0))
+        w.ctx.ntt_set_schedule(False, None)
