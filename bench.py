@@ -403,7 +403,7 @@ def copy_bandwidth(gib=2, reps=5):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=int(os.environ.get("WORLD_SIZE", "1")))
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -1218,9 +1218,10 @@ def main():
         sync()
         log("warmup step %d done" % i)
 
-    # timed region: batched eager launches; the dominant kernel family is
-    # bracketed with HIP events (on the stream of each launch) during the
-    # last timed step only, so that the events' own cost touches one step
+    # timed region: batched eager launches, each step enqueued while the
+    # previous one runs; the dominant kernel family is bracketed with HIP
+    # events (on the stream of each launch) during the last timed step only,
+    # so that the events' own cost touches one step
     prof_enable(ctx, 0)
     roctx = Roctx()
     sync()
@@ -1228,11 +1229,13 @@ def main():
     t0 = time.perf_counter()
     for i in range(args.steps):
         if i == args.steps - 1:
-            prof_enable(ctx, 1 << dom)  # the stream is idle here (synchronised after each step)
+            sync()  # the stream idle before the events are switched on
+            if i:
+                log("timed steps 0..%d done" % (i - 1))
+            prof_enable(ctx, 1 << dom)
         job_step(ctx, cts)
-        sync()
-        log("timed step %d done" % i)
     sync()
+    log("timed step %d done" % (args.steps - 1))
     elapsed = time.perf_counter() - t0
     roctx.pause()
     dom_ms = prof_read(ctx, dom)[0]
