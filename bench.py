@@ -66,9 +66,11 @@ def log(msg):
 
 
 class Roctx:
-    """roctxProfilerResume/Pause around the timed region, so that a
-    `rocprofv3 --selected-regions` run profiles exactly the timed steps.
-    Without the profiler these calls do nothing."""
+    """roctxProfilerResume/Pause around the timed region, for a profiler
+    that limits itself to such regions (rocprofv3's --selected-regions; the
+    stored profiles do not rely on it: they trace whole runs of
+    --profile-steps / --profile-workload).  Without a profiler these calls
+    do nothing."""
 
     def __init__(self):
         import ctypes
@@ -412,6 +414,10 @@ def parse():
     ap.add_argument("--reps", type=int, default=10, help="runs per median of the CPU baseline")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="run only this many untimed steps (for rocprofv3) and exit")
+    ap.add_argument("--profile-workload", choices=["bow", "batched"],
+                    help="run only the bag-of-words inference or the batched-primitives op list, then one more "
+                         "batch / eager executor run set apart by idle time (1 s before, 3 s after; for a "
+                         "rocprofv3 kernel trace), and exit")
     ap.add_argument("--no-breakdown", action="store_true", help="skip the per-operation loops")
     ap.add_argument("--no-predict", action="store_true", help="skip the encrypted-weight predict measurement")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-primitives op-list measurement")
@@ -604,14 +610,15 @@ def c2_per_op(ctx, cts, ops):
             ctx.ntt_inverse(cts[a].data, cts[a].level)
 
 
-def c2_bench(reps=5):
+def c2_bench(reps=5, region=None):
     """The batched-primitives configuration: N = 2^14, 8 ciphertext primes +
     2 special primes (dnum 4), scale 2^40; 64 ciphertext pairs at levels
     drawn from U{3..8} with slots U[-1, 1]; 16 rotation steps drawn from
     U{1..N/2-1}; the op list of c2_op_list.  Timed four ways on identical
     inputs: one call per operation (eager, and captured in one HIP graph),
     and the op-list executor (eager, and replayed from one HIP graph).  All
-    four leave bit-identical outputs (checked)."""
+    four leave bit-identical outputs (checked).  region (with resume() and
+    pause()): one more eager executor run between them."""
     import numpy as np
     import torch
 
@@ -669,6 +676,13 @@ def c2_bench(reps=5):
     ctx.exec_batch(ex, ops)
     sync()
     t_ex = timed(lambda: (reset(ex, ops, ref), ctx.exec_batch(ex, ops)), reps, sync)
+    if region is not None:
+        reset(ex, ops, ref)
+        sync()
+        region.resume()
+        ctx.exec_batch(ex, ops)
+        sync()
+        region.pause()
     # the op-list executor, captured
     eg, _ = fresh()
     ctx.exec_batch(eg, ops)
@@ -826,7 +840,7 @@ def predict_bench(n_docs=32, level=6, reps=3):
     return res
 
 
-def bow_bench(n_docs=32, reps=3, singles=8):
+def bow_bench(n_docs=32, reps=3, singles=8, region=None):
     """The bag-of-words inference workload: N = 2^15, 16 ciphertext primes
     (+4 special, dnum 4), scale 2^40; vocabulary 32768 (two input
     ciphertexts per document), plaintext embedding 32768 x 64 and classifier
@@ -834,7 +848,8 @@ def bow_bench(n_docs=32, reps=3, singles=8):
     50-500 tokens each, encrypted at the top level; Alg. 1 steps 2-3 as
     diagonal BSGS PtMatVec + 1/w + PtMatVec, three levels.  Reports the
     batch of n_docs (documents/s), single-document latencies (median and
-    worst of `singles`), the error against fp64 and argmax agreement."""
+    worst of `singles`), the error against fp64 and argmax agreement.
+    region (with resume() and pause()): one more batch runs between them."""
     import statistics
 
     import numpy as np
@@ -858,6 +873,12 @@ def bow_bench(n_docs=32, reps=3, singles=8):
         model.stage1.b * model.stage1.G * model.n_in, model.stage2.b * model.stage2.G, n_docs, time.time() - t0))
     out = encrypted_inference(ctx, model, docs, list(words))
     sec = timed(lambda: encrypted_inference(ctx, model, docs, list(words)), reps, ctx.synchronize)
+    if region is not None:
+        ctx.synchronize()
+        region.resume()
+        encrypted_inference(ctx, model, docs, list(words))
+        ctx.synchronize()
+        region.pause()
     lat = []
     for d in range(singles):
         ctx.synchronize()
@@ -1166,6 +1187,28 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+
+    if args.profile_workload:
+        class Pause:
+            """Idle before (1 s) and after (3 s) the profiled run, so that its
+            dispatches stand apart in a kernel trace: they follow the last
+            gap of about a second before the first gap of three."""
+
+            def resume(self):
+                torch.cuda.synchronize()
+                time.sleep(1.0)
+                log("profiled run: start")
+
+            def pause(self):
+                torch.cuda.synchronize()
+                log("profiled run: end")
+                time.sleep(3.0)
+
+        if args.profile_workload == "bow":
+            bow_bench(reps=1, singles=1, region=Pause())
+        else:
+            c2_bench(reps=1, region=Pause())
+        return
 
     lp, ctx, cts = setup(args.batch)
     sync = torch.cuda.synchronize
