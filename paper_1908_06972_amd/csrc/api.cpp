@@ -2626,9 +2626,9 @@ extern "C" int pft_ptmatvec(pft_ctx* c, const pft_ptmat* m, uint32_t n_docs, con
     if (n_docs == 0) return PFT_OK;
     const double scale = in[0].scale;
     const uint64_t ct_words = 2ull * l * P->n;
-    // per document: baby[n_in][b] | acc | tot | tmp
-    const uint64_t off_baby = 0, off_acc = (uint64_t)J * ct_words, off_tot = off_acc + ct_words,
-                   off_tmp = off_tot + ct_words, stride = off_tmp + ct_words;
+    // per document: baby[n_in][b] | acc[G] (acc[0] collects the total) | tmp
+    const uint64_t off_baby = 0, off_acc = (uint64_t)J * ct_words, off_tot = off_acc,
+                   off_tmp = off_acc + (uint64_t)m->G * ct_words, stride = off_tmp + ct_words;
     if ((r = ensure_aux(c, (size_t)n_docs * stride * 8))) return r;
     uint64_t* A = c->aux;
     // inputs -> baby[c][0]
@@ -2653,21 +2653,26 @@ extern "C" int pft_ptmatvec(pft_ctx* c, const pft_ptmat* m, uint32_t n_docs, con
             }
         if ((r = pft_rotate_batch(c, (uint32_t)src.size(), src.data(), (int32_t)rr, dst.data()))) return r;
     }
-    // giant steps: tot = sum_g ROTATE(sum_{c,r} P_{g,c,r} baby[c][r], g b)
-    const WsRef ws{A, stride};
-    for (uint32_t g = 0; g < m->G; ++g) {
-        const uint64_t* ptg = m->pt + (size_t)g * J * l * P->n;
-        for (uint32_t z0 = 0; z0 < n_docs; z0 += 65535) {
-            const uint32_t cnt = std::min<uint32_t>(65535, n_docs - z0);
+    // giant steps: tot = sum_g ROTATE(acc[g], g b), acc[g] = sum_{c,r} P_{g,c,r}
+    // baby[c][r]; the inner sums of several giant steps come from one pass
+    // over the baby steps
+    const uint32_t gt = pt_dot_multi_steps();
+    for (uint32_t g0 = 0; g0 < m->G; g0 += gt) {
+        const uint32_t n_g = std::min(gt, m->G - g0);
+        const uint64_t* ptg = m->pt + (size_t)g0 * J * l * P->n;
+        for (uint32_t z0 = 0; z0 < n_docs; z0 += 1024) {
+            const uint32_t cnt = std::min<uint32_t>(1024, n_docs - z0);
             const WsRef w{A + z0 * stride, stride};
-            timed(c, PK_ELEMENTWISE, 8.0 * (double)cnt * ct_words * (J + 1) + 8.0 * J * l * P->n,
-                  (double)cnt * ct_words * J, [&] {
-                      launch_pt_dot_b(cnt, w, off_baby, ct_words, ptg, J, g == 0 ? off_tot : off_acc, l, c->tabs, lg,
-                                      c->stream);
+            timed(c, PK_ELEMENTWISE,
+                  8.0 * (double)cnt * ct_words * (J + n_g) + 8.0 * (double)n_g * J * l * P->n,
+                  (double)cnt * ct_words * J * n_g, [&] {
+                      launch_pt_dot_multi_b(cnt, w, off_baby, ct_words, ptg, J, n_g, off_acc + g0 * ct_words, l,
+                                            c->tabs, lg, c->stream);
                   });
         }
-        if (g == 0) continue;
-        std::vector<pft_ct> src = cts_at(A, stride, off_acc, n_docs, l, scale * m->pt_scale);
+    }
+    for (uint32_t g = 1; g < m->G; ++g) {
+        std::vector<pft_ct> src = cts_at(A, stride, off_acc + g * ct_words, n_docs, l, scale * m->pt_scale);
         std::vector<pft_ct> dst = cts_at(A, stride, off_tmp, n_docs, l, scale * m->pt_scale);
         if ((r = pft_rotate_batch(c, n_docs, src.data(), (int32_t)(g * m->b), dst.data()))) return r;
         for (uint32_t z0 = 0; z0 < n_docs; z0 += 65535) {

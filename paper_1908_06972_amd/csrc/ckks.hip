@@ -498,6 +498,54 @@ __global__ __launch_bounds__(TB) void k_pt_dot_b(WsRef ws, uint64_t off_baby, ui
     w[off_acc + at(row, log_n, k)] = res;
 }
 
+// The inner sums of up to PT_GT giant steps at once: for g < n_g,
+// acc_{z,g}[row] = sum_{j<J} baby_{z,j}[row] pt_{g,j}[row mod level], acc_{z,g}
+// at ws_z + off_acc + g ct_words, pt_{g,j} at pt + (g J + j) level N
+// (Montgomery form); each baby residue is read once for all n_g giant
+// steps.  One thread per (item, row, coefficient); the items of one
+// coefficient block are consecutive workgroups (items vary fastest), so the
+// plaintext tiles they share are fetched about once per launch.  Sums are
+// reduced every 8 terms as in k_pt_dot_b.
+constexpr uint32_t PT_GT = 8;
+__global__ __launch_bounds__(TB) void k_pt_dot_multi_b(WsRef ws, uint32_t n_items, uint64_t off_baby,
+                                                       uint64_t ct_words, const uint64_t* __restrict__ pt, uint32_t J,
+                                                       uint32_t n_g, uint64_t off_acc, uint32_t level,
+                                                       const DevMod* __restrict__ mods, uint32_t log_n) {
+    const uint32_t kblocks = (1u << log_n) / TB;
+    const uint32_t z = blockIdx.x % n_items;
+    const uint32_t rest = blockIdx.x / n_items;
+    const uint32_t k = (rest % kblocks) * TB + threadIdx.x;
+    const uint32_t row = rest / kblocks, i = row % level;
+    const DevMod md = mods[i];
+    uint64_t* __restrict__ w = ws.base + (size_t)z * ws.stride;
+    const size_t o = at(row, log_n, k);
+    const size_t pstep = ((size_t)J * level) << log_n;  // words between giant steps of pt
+    Acc128 a[PT_GT];
+    uint64_t res[PT_GT];
+#pragma unroll
+    for (uint32_t g = 0; g < PT_GT; ++g) {
+        a[g] = Acc128{0, 0};
+        res[g] = 0;
+    }
+    for (uint32_t j = 0; j < J; ++j) {
+        const uint64_t x = w[off_baby + j * ct_words + o];
+        const uint64_t* __restrict__ pj = pt + at(j * level + i, log_n, k);
+#pragma unroll
+        for (uint32_t g = 0; g < PT_GT; ++g)
+            if (g < n_g) mac128(a[g], x, pj[g * pstep]);
+        if ((j & 7u) == 7u) {
+#pragma unroll
+            for (uint32_t g = 0; g < PT_GT; ++g) {
+                res[g] = add_mod(res[g], mont_redc(a[g].lo, a[g].hi, md.q, md.mont_neg_qinv), md.q);
+                a[g] = Acc128{0, 0};
+            }
+        }
+    }
+#pragma unroll
+    for (uint32_t g = 0; g < PT_GT; ++g)
+        if (g < n_g) w[off_acc + g * ct_words + o] = add_mod(res[g], mont_redc(a[g].lo, a[g].hi, md.q, md.mont_neg_qinv), md.q);
+}
+
 // out_z = in_z + c_z at X^0: in the evaluation domain the constant c_z[i]
 // (mod q_i) is added to every entry of limb i of c0; c1 is copied.
 __global__ __launch_bounds__(TB) void k_add_const_b(ItemPtrs in, ItemPtrs out, const TwPair* __restrict__ consts,
@@ -652,6 +700,16 @@ void launch_add_ct_b(uint32_t n, WsRef ws, uint64_t off_a, uint64_t off_b, uint6
 void launch_pt_dot_b(uint32_t n, WsRef ws, uint64_t off_baby, uint64_t ct_words, const uint64_t* pt, uint32_t J,
                      uint64_t off_acc, uint32_t level, const DevTables& t, uint32_t log_n, hipStream_t st) {
     hipLaunchKernelGGL(k_pt_dot_b, grid_nk(log_n, 2 * level, n), dim3(TB), 0, st, ws, off_baby, ct_words, pt, J,
+                       off_acc, level, t.mods, log_n);
+}
+
+uint32_t pt_dot_multi_steps() { return PT_GT; }
+
+void launch_pt_dot_multi_b(uint32_t n, WsRef ws, uint64_t off_baby, uint64_t ct_words, const uint64_t* pt, uint32_t J,
+                           uint32_t n_g, uint64_t off_acc, uint32_t level, const DevTables& t, uint32_t log_n,
+                           hipStream_t st) {
+    const uint64_t blocks = (uint64_t)n * ((1u << log_n) / TB) * 2 * level;
+    hipLaunchKernelGGL(k_pt_dot_multi_b, dim3((uint32_t)blocks), dim3(TB), 0, st, ws, n, off_baby, ct_words, pt, J, n_g,
                        off_acc, level, t.mods, log_n);
 }
 

@@ -223,6 +223,13 @@ void launch_add_ct_b(uint32_t n, WsRef ws, uint64_t off_a, uint64_t off_b, uint6
 // PtMatVec inner sums: acc_z = sum_j baby_{z,j} * pt_j (pt in Montgomery form)
 void launch_pt_dot_b(uint32_t n, WsRef ws, uint64_t off_baby, uint64_t ct_words, const uint64_t* pt, uint32_t J,
                      uint64_t off_acc, uint32_t level, const DevTables& t, uint32_t log_n, hipStream_t st);
+// PtMatVec inner sums of n_g <= pt_dot_multi_steps() giant steps at once:
+// acc_{z,g} (at off_acc + g ct_words) = sum_j baby_{z,j} * pt_{g,j}, pt_{g,j}
+// at pt + (g J + j) level N; each baby_{z,j} is read once for all of them
+uint32_t pt_dot_multi_steps();
+void launch_pt_dot_multi_b(uint32_t n, WsRef ws, uint64_t off_baby, uint64_t ct_words, const uint64_t* pt, uint32_t J,
+                           uint32_t n_g, uint64_t off_acc, uint32_t level, const DevTables& t, uint32_t log_n,
+                           hipStream_t st);
 // out_z = in_z * consts[z][limb] (integer constant polynomial)
 void launch_scale_const_b(uint32_t n, const ItemPtrs& in, const ItemPtrs& out, const TwPair* consts, uint32_t level,
                           const DevTables& t, uint32_t log_n, hipStream_t st);

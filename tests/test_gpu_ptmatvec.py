@@ -53,7 +53,7 @@ class SmallWorld:
 def small():
     import torch
     assert torch.cuda.is_available()
-    steps = sorted(set(PM.rotation_steps(16, 2048) + PM.rotation_steps(4, 16)))
+    steps = sorted(set(PM.rotation_steps(16, 2048) + PM.rotation_steps(4, 16) + PM.rotation_steps(16, 16, 9)))
     return SmallWorld(steps)
 
 
@@ -188,3 +188,21 @@ def test_ptmatvec_many_inputs_giant_steps_only(small):
     g = w.ctx.ptmatvec(mat, [[x[0] for x in doc]])[0]
     o = PM.ptmatvec(w.op, [x[1] for x in doc], plains, n_o, n_i, w.keys, pt_scale)
     w.assert_same(g, o)
+
+
+def test_ptmatvec_sixteen_giant_steps(small):
+    """9 input ciphertexts and 16 outputs: the plan takes b = 1 and G = 16,
+    so the giant steps' inner sums come from two passes over the inputs
+    (eight giant steps each); two documents, bit-exact with the oracle."""
+    w = small
+    n_o, n_i, n_in, lvl = 16, 16, 9, 3
+    assert PM.bsgs_plan(n_o, n_in) == (1, 16)
+    plains = _random_plains(11, n_in, n_o, w.n, 2 ** 20)
+    pt_scale = float(w.op.q[lvl - 1])
+    mat = w.ctx.ptmat_from_coeffs(plains, n_o, n_i, n_in, lvl, pt_scale)
+    assert (mat.b, mat.G) == (1, 16)
+    docs = [[w.enc_pair(S.plaintext_coeffs(S.rng(1100 + n_in * d + c), w.n, 2 ** 30), lvl, 1200 + n_in * d + c)
+             for c in range(n_in)] for d in range(2)]
+    outs = w.ctx.ptmatvec(mat, [[x[0] for x in doc] for doc in docs])
+    for doc, g in zip(docs, outs):
+        w.assert_same(g, PM.ptmatvec(w.op, [x[1] for x in doc], plains, n_o, n_i, w.keys, pt_scale))
