@@ -2929,14 +2929,17 @@ extern "C" int pft_ptdot_apply(pft_ctx* c, const pft_ptdot* m, uint32_t n_docs, 
         }
         launch_copy_rows_b(cnt, I, 0, O, 0, 2 * l, lg, c->stream);
     }
-    for (uint32_t k = 0; k < K; ++k) {
-        const uint64_t* ptk = m->pt + (size_t)k * J * l * P->n;
-        for (uint32_t z0 = 0; z0 < n_docs; z0 += 65535) {
-            const uint32_t cnt = std::min<uint32_t>(65535, n_docs - z0);
-            timed(c, PK_ELEMENTWISE, 8.0 * (double)cnt * ct_words * (J + 1) + 8.0 * J * l * P->n,
-                  (double)cnt * ct_words * J, [&] {
-                      launch_pt_dot_b(cnt, WsRef{A + z0 * stride, stride}, 0, ct_words, ptk, J,
-                                      off_out + (uint64_t)k * ct_words, l, c->tabs, lg, c->stream);
+    // several outputs' sums from one pass over the inputs
+    const uint32_t kt = pt_dot_multi_steps();
+    for (uint32_t k0 = 0; k0 < K; k0 += kt) {
+        const uint32_t nk = std::min(kt, K - k0);
+        const uint64_t* ptk = m->pt + (size_t)k0 * J * l * P->n;
+        for (uint32_t z0 = 0; z0 < n_docs; z0 += 1024) {
+            const uint32_t cnt = std::min<uint32_t>(1024, n_docs - z0);
+            timed(c, PK_ELEMENTWISE, 8.0 * (double)cnt * ct_words * (J + nk) + 8.0 * (double)nk * J * l * P->n,
+                  (double)cnt * ct_words * J * nk, [&] {
+                      launch_pt_dot_multi_b(cnt, WsRef{A + z0 * stride, stride}, 0, ct_words, ptk, J, nk,
+                                            off_out + (uint64_t)k0 * ct_words, l, c->tabs, lg, c->stream);
                   });
         }
     }

@@ -474,38 +474,14 @@ __global__ __launch_bounds__(TB) void k_add_ct_b(WsRef ws, uint64_t off_a, uint6
     w[off_out + o] = add_mod(w[off_a + o], w[off_b + o], q);
 }
 
-// acc_z[row] = sum_{j<J} baby_{z,j}[row] pt_j[row mod level]  for the 2*level
-// rows of a ciphertext; baby_{z,j} at ws_z + off_baby + j ct_words, pt_j at
-// pt + j level N holding plaintext * 2^64 mod q (Montgomery form).  The
-// 128-bit sum is reduced every 8 terms, which keeps it below q 2^64.
-__global__ __launch_bounds__(TB) void k_pt_dot_b(WsRef ws, uint64_t off_baby, uint64_t ct_words,
-                                                 const uint64_t* __restrict__ pt, uint32_t J, uint64_t off_acc,
-                                                 uint32_t level, const DevMod* __restrict__ mods, uint32_t log_n) {
-    const uint32_t k = blockIdx.x * TB + threadIdx.x;
-    const uint32_t row = blockIdx.y, i = row % level;
-    const DevMod md = mods[i];
-    uint64_t* __restrict__ w = ws_item(ws);
-    Acc128 a = {0, 0};
-    uint64_t res = 0;
-    for (uint32_t j = 0; j < J; ++j) {
-        mac128(a, w[off_baby + j * ct_words + at(row, log_n, k)], pt[at(j * level + i, log_n, k)]);
-        if ((j & 7u) == 7u) {
-            res = add_mod(res, mont_redc(a.lo, a.hi, md.q, md.mont_neg_qinv), md.q);
-            a.lo = a.hi = 0;
-        }
-    }
-    res = add_mod(res, mont_redc(a.lo, a.hi, md.q, md.mont_neg_qinv), md.q);
-    w[off_acc + at(row, log_n, k)] = res;
-}
-
 // The inner sums of up to PT_GT giant steps at once: for g < n_g,
 // acc_{z,g}[row] = sum_{j<J} baby_{z,j}[row] pt_{g,j}[row mod level], acc_{z,g}
-// at ws_z + off_acc + g ct_words, pt_{g,j} at pt + (g J + j) level N
-// (Montgomery form); each baby residue is read once for all n_g giant
-// steps.  One thread per (item, row, coefficient); the items of one
+// at ws_z + off_acc + g ct_words, pt_{g,j} at pt + (g J + j) level N; each
+// baby residue is read once for all n_g giant steps (or outputs).  One thread per (item, row, coefficient); the items of one
 // coefficient block are consecutive workgroups (items vary fastest), so the
-// plaintext tiles they share are fetched about once per launch.  Sums are
-// reduced every 8 terms as in k_pt_dot_b.
+// plaintext tiles they share are fetched about once per launch.  The plaintext
+// rows hold plaintext * 2^64 mod q (Montgomery form); each 128-bit sum is
+// reduced every 8 terms, which keeps it below q 2^64.
 constexpr uint32_t PT_GT = 8;
 __global__ __launch_bounds__(TB) void k_pt_dot_multi_b(WsRef ws, uint32_t n_items, uint64_t off_baby,
                                                        uint64_t ct_words, const uint64_t* __restrict__ pt, uint32_t J,
@@ -695,12 +671,6 @@ void launch_add_ct_b(uint32_t n, WsRef ws, uint64_t off_a, uint64_t off_b, uint6
                      const DevTables& t, uint32_t log_n, hipStream_t st) {
     hipLaunchKernelGGL(k_add_ct_b, grid_nk(log_n, 2 * level, n), dim3(TB), 0, st, ws, off_a, off_b, off_out, level,
                        t.mods, log_n);
-}
-
-void launch_pt_dot_b(uint32_t n, WsRef ws, uint64_t off_baby, uint64_t ct_words, const uint64_t* pt, uint32_t J,
-                     uint64_t off_acc, uint32_t level, const DevTables& t, uint32_t log_n, hipStream_t st) {
-    hipLaunchKernelGGL(k_pt_dot_b, grid_nk(log_n, 2 * level, n), dim3(TB), 0, st, ws, off_baby, ct_words, pt, J,
-                       off_acc, level, t.mods, log_n);
 }
 
 uint32_t pt_dot_multi_steps() { return PT_GT; }

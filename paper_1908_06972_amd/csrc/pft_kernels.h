@@ -220,12 +220,10 @@ void launch_rescale_expand_b(uint32_t n, WsRef ws, uint64_t off_last, uint64_t o
 // ws_z[off_out] = ws_z[off_a] + ws_z[off_b] over [2][level][N]
 void launch_add_ct_b(uint32_t n, WsRef ws, uint64_t off_a, uint64_t off_b, uint64_t off_out, uint32_t level,
                      const DevTables& t, uint32_t log_n, hipStream_t st);
-// PtMatVec inner sums: acc_z = sum_j baby_{z,j} * pt_j (pt in Montgomery form)
-void launch_pt_dot_b(uint32_t n, WsRef ws, uint64_t off_baby, uint64_t ct_words, const uint64_t* pt, uint32_t J,
-                     uint64_t off_acc, uint32_t level, const DevTables& t, uint32_t log_n, hipStream_t st);
-// PtMatVec inner sums of n_g <= pt_dot_multi_steps() giant steps at once:
-// acc_{z,g} (at off_acc + g ct_words) = sum_j baby_{z,j} * pt_{g,j}, pt_{g,j}
-// at pt + (g J + j) level N; each baby_{z,j} is read once for all of them
+// PtMatVec inner sums of n_g <= pt_dot_multi_steps() giant steps (or
+// outputs) at once: acc_{z,g} (at off_acc + g ct_words) = sum_j baby_{z,j} *
+// pt_{g,j}, pt_{g,j} at pt + (g J + j) level N in Montgomery form; each
+// baby_{z,j} is read once for all of them
 uint32_t pt_dot_multi_steps();
 void launch_pt_dot_multi_b(uint32_t n, WsRef ws, uint64_t off_baby, uint64_t ct_words, const uint64_t* pt, uint32_t J,
                            uint32_t n_g, uint64_t off_acc, uint32_t level, const DevTables& t, uint32_t log_n,
