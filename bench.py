@@ -414,10 +414,10 @@ def parse():
     ap.add_argument("--reps", type=int, default=10, help="runs per median of the CPU baseline")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="run only this many untimed steps (for rocprofv3) and exit")
-    ap.add_argument("--profile-workload", choices=["bow", "batched"],
-                    help="run only the bag-of-words inference or the batched-primitives op list, then one more "
-                         "batch / eager executor run set apart by idle time (1 s before, 3 s after; for a "
-                         "rocprofv3 kernel trace), and exit")
+    ap.add_argument("--profile-workload", choices=["bow", "predict", "batched"],
+                    help="run only the bag-of-words inference, the encrypted-weight predict step or the "
+                         "batched-primitives op list, then one more batch / eager executor run set apart by idle "
+                         "time (1 s before, 3 s after; for a rocprofv3 kernel trace), and exit")
     ap.add_argument("--no-breakdown", action="store_true", help="skip the per-operation loops")
     ap.add_argument("--no-predict", action="store_true", help="skip the encrypted-weight predict measurement")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-primitives op-list measurement")
@@ -774,12 +774,13 @@ def serving_bench(n_requests, rate=200.0, level=4, pool=16, budget_gib=16, satur
     return out
 
 
-def predict_bench(n_docs=32, level=6, reps=3):
+def predict_bench(n_docs=32, level=6, reps=3, region=None):
     """The predict step of training with encrypted weights (Sec. 4.2) at the
     bag-of-words shapes (N = 2^15 prime chain, vocabulary 32768 = two input
     ciphertexts, embedding 64, 8 classes): both weight matrices encrypted
     (128 + 8 diagonal ciphertexts), a batch of documents at level `level`
-    (five levels consumed), then the degree-2 softmax approximation."""
+    (five levels consumed), then the degree-2 softmax approximation.
+    region (with resume() and pause()): one more batch runs between them."""
     import numpy as np
 
     import synth as S
@@ -825,6 +826,12 @@ def predict_bench(n_docs=32, level=6, reps=3):
         len(model.stage1), len(model.stage2), n_docs, time.time() - t0))
     out = T.predict_encrypted(ctx, model, docs, list(words))
     sec = timed(lambda: T.predict_encrypted(ctx, model, docs, list(words)), reps, ctx.synchronize)
+    if region is not None:
+        ctx.synchronize()
+        region.resume()
+        T.predict_encrypted(ctx, model, docs, list(words))
+        ctx.synchronize()
+        region.pause()
     err = 0.0
     for d in range(2):
         got = lp.decode(ctx.decrypt(out[d]), out[d].scale, classes).real
@@ -1206,6 +1213,8 @@ def main():
 
         if args.profile_workload == "bow":
             bow_bench(reps=1, singles=1, region=Pause())
+        elif args.profile_workload == "predict":
+            predict_bench(reps=1, region=Pause())
         else:
             c2_bench(reps=1, region=Pause())
         return

@@ -2788,7 +2788,7 @@ extern "C" int pft_ctmatvec(pft_ctx* c, uint32_t n_o, uint32_t n_i, uint32_t n_i
             timed(c, PK_TENSOR, 8.0 * cnt * (2.0 * J * ct_words + 3.0 * nl) + 8.0 * J * ct_words,
                   4.0 * cnt * J * nl, [&] {
                       launch_ct_dot_b(cnt, E, J, WsRef{A + z0 * stride, stride}, off_baby, ct_words, ws, 0, l,
-                                      c->tabs, lg, c->stream);
+                                      c->to_mont, c->tabs, lg, c->stream);
                   });
             ItemPtrs O{};
             for (uint32_t u = 0; u < cnt; ++u) O.p[u] = A + (z0 + u) * stride + (g == 0 ? off_tot : off_acc);

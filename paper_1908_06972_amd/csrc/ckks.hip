@@ -536,28 +536,49 @@ __global__ __launch_bounds__(TB) void k_add_const_b(ItemPtrs in, ItemPtrs out, c
 
 // HMUL tensors of one giant step of the encrypted-weight matrix-vector
 // product, summed over its J diagonal terms (Sec. 4.2, HMUL in place of
-// HMULPLAIN): d0 = sum e0 x0, d1 = sum (e0 x1 + e1 x0), d2 = sum e1 x1.
+// HMULPLAIN): d0 = sum e0 x0, d1 = sum (e0 x1 + e1 x0), d2 = sum e1 x1.  The
+// full 128-bit products are summed and brought back by a Montgomery
+// reduction every 8 diagonal terms (at most 16 products below q^2 each:
+// below q 2^64 for q < 2^60); the reductions' factor 2^-64 is undone once at
+// the end by a Shoup product with 2^64 mod q (to_mont).
 __global__ __launch_bounds__(TB) void k_ct_dot_b(ItemPtrs e, uint32_t J, WsRef xs, uint64_t off_x, uint64_t ct_words,
                                                  WsRef ws, uint64_t off_d, uint32_t level,
-                                                 const DevMod* __restrict__ mods, uint32_t log_n) {
+                                                 const DevMod* __restrict__ mods, const TwPair* __restrict__ to_mont,
+                                                 uint32_t log_n) {
+    using u128 = unsigned __int128;
     const uint32_t k = blockIdx.x * TB + threadIdx.x;
     const uint32_t i = blockIdx.y;
     const DevMod md = mods[i];
+    const uint64_t q = md.q;
     const uint64_t* __restrict__ x = xs.base + (size_t)blockIdx.z * xs.stride + off_x;
     const size_t o0 = at(i, log_n, k), o1 = at(level + i, log_n, k);
+    u128 s0 = 0, s1 = 0, s2 = 0;
     uint64_t d0 = 0, d1 = 0, d2 = 0;
+    auto fold = [&](u128& sv, uint64_t& dv) {
+        dv = add_mod(dv, mont_redc((uint64_t)sv, (uint64_t)(sv >> 64), q, md.mont_neg_qinv), q);
+        sv = 0;
+    };
     for (uint32_t j = 0; j < J; ++j) {
         const uint64_t* __restrict__ E = e.p[j];
         const uint64_t e0 = E[o0], e1 = E[o1];
         const uint64_t x0 = x[j * ct_words + o0], x1 = x[j * ct_words + o1];
-        d0 = add_mod(d0, mul_barrett(e0, x0, md), md.q);
-        d1 = add_mod(d1, add_mod(mul_barrett(e0, x1, md), mul_barrett(e1, x0, md), md.q), md.q);
-        d2 = add_mod(d2, mul_barrett(e1, x1, md), md.q);
+        s0 += (u128)e0 * x0;
+        s1 += (u128)e0 * x1 + (u128)e1 * x0;
+        s2 += (u128)e1 * x1;
+        if ((j & 7u) == 7u) {
+            fold(s0, d0);
+            fold(s1, d1);
+            fold(s2, d2);
+        }
     }
+    fold(s0, d0);
+    fold(s1, d1);
+    fold(s2, d2);
+    const TwPair r = to_mont[i];
     uint64_t* __restrict__ d = ws_item(ws) + off_d;
-    d[o0] = d0;
-    d[o1] = d1;
-    d[at(2 * level + i, log_n, k)] = d2;
+    d[o0] = shoup(d0, r.w, r.wp, q);
+    d[o1] = shoup(d1, r.w, r.wp, q);
+    d[at(2 * level + i, log_n, k)] = shoup(d2, r.w, r.wp, q);
 }
 
 // out_z[b][i] = in_z[b][i] * c_z[i] (Shoup pairs, [n][level] on the device):
@@ -690,9 +711,10 @@ void launch_add_const_b(uint32_t n, const ItemPtrs& in, const ItemPtrs& out, con
 }
 
 void launch_ct_dot_b(uint32_t n, const ItemPtrs& e, uint32_t J, WsRef xs, uint64_t off_x, uint64_t ct_words, WsRef ws,
-                     uint64_t off_d, uint32_t level, const DevTables& t, uint32_t log_n, hipStream_t st) {
+                     uint64_t off_d, uint32_t level, const TwPair* to_mont, const DevTables& t, uint32_t log_n,
+                     hipStream_t st) {
     hipLaunchKernelGGL(k_ct_dot_b, grid_nk(log_n, level, n), dim3(TB), 0, st, e, J, xs, off_x, ct_words, ws, off_d,
-                       level, t.mods, log_n);
+                       level, t.mods, to_mont, log_n);
 }
 
 void launch_scale_const_b(uint32_t n, const ItemPtrs& in, const ItemPtrs& out, const TwPair* consts, uint32_t level,

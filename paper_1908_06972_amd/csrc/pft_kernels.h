@@ -237,9 +237,11 @@ void launch_add_const_b(uint32_t n, const ItemPtrs& in, const ItemPtrs& out, con
 // Encrypted-weight products of one giant step: for item z, the HMUL tensor
 // sum_j E_j (x) X_{z,j} into ws_z + off_d as [3][level][N], with E_j =
 // e.p[j] (ciphertexts shared by all items, [2][level][N]) and X_{z,j} at
-// ws_z + off_x + j ct_words.  J <= PFT_MAX_ITEMS.
+// ws_z + off_x + j ct_words.  J <= PFT_MAX_ITEMS.  to_mont: [L+K] 2^64 mod q
+// as Shoup pairs.
 void launch_ct_dot_b(uint32_t n, const ItemPtrs& e, uint32_t J, WsRef xs, uint64_t off_x, uint64_t ct_words, WsRef ws,
-                     uint64_t off_d, uint32_t level, const DevTables& t, uint32_t log_n, hipStream_t st);
+                     uint64_t off_d, uint32_t level, const TwPair* to_mont, const DevTables& t, uint32_t log_n,
+                     hipStream_t st);
 
 // The fixed scratch of the allocation-free entry point (noalloc.hip): a
 // file-scope device array of PFT_NOALLOC_SCRATCH_BYTES per GPU.  Resolves
