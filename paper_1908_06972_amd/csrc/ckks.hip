@@ -477,16 +477,18 @@ __global__ __launch_bounds__(TB) void k_add_ct_b(WsRef ws, uint64_t off_a, uint6
 // The inner sums of up to PT_GT giant steps at once: for g < n_g,
 // acc_{z,g}[row] = sum_{j<J} baby_{z,j}[row] pt_{g,j}[row mod level], acc_{z,g}
 // at ws_z + off_acc + g ct_words, pt_{g,j} at pt + (g J + j) level N; each
-// baby residue is read once for all n_g giant steps (or outputs).  One thread per (item, row, coefficient); the items of one
-// coefficient block are consecutive workgroups (items vary fastest), so the
-// plaintext tiles they share are fetched about once per launch.  The plaintext
-// rows hold plaintext * 2^64 mod q (Montgomery form); each 128-bit sum is
-// reduced every 8 terms, which keeps it below q 2^64.
+// baby residue is read once for all n_g giant steps (or outputs).  One thread
+// per (item, row, coefficient); the items of one coefficient block are
+// consecutive workgroups (items vary fastest), so the plaintext tiles they
+// share are fetched about once per launch.  The plaintext rows hold
+// plaintext * 2^64 mod q (Montgomery form); each 128-bit sum of full products
+// is reduced every 8 terms, which keeps it below q 2^64.
 constexpr uint32_t PT_GT = 8;
 __global__ __launch_bounds__(TB) void k_pt_dot_multi_b(WsRef ws, uint32_t n_items, uint64_t off_baby,
                                                        uint64_t ct_words, const uint64_t* __restrict__ pt, uint32_t J,
                                                        uint32_t n_g, uint64_t off_acc, uint32_t level,
                                                        const DevMod* __restrict__ mods, uint32_t log_n) {
+    using u128 = unsigned __int128;
     const uint32_t kblocks = (1u << log_n) / TB;
     const uint32_t z = blockIdx.x % n_items;
     const uint32_t rest = blockIdx.x / n_items;
@@ -496,30 +498,35 @@ __global__ __launch_bounds__(TB) void k_pt_dot_multi_b(WsRef ws, uint32_t n_item
     uint64_t* __restrict__ w = ws.base + (size_t)z * ws.stride;
     const size_t o = at(row, log_n, k);
     const size_t pstep = ((size_t)J * level) << log_n;  // words between giant steps of pt
-    Acc128 a[PT_GT];
+    u128 a[PT_GT];
     uint64_t res[PT_GT];
 #pragma unroll
     for (uint32_t g = 0; g < PT_GT; ++g) {
-        a[g] = Acc128{0, 0};
+        a[g] = 0;
         res[g] = 0;
     }
+    auto fold = [&](uint32_t g) {
+        res[g] = add_mod(res[g], mont_redc((uint64_t)a[g], (uint64_t)(a[g] >> 64), md.q, md.mont_neg_qinv), md.q);
+        a[g] = 0;
+    };
     for (uint32_t j = 0; j < J; ++j) {
         const uint64_t x = w[off_baby + j * ct_words + o];
         const uint64_t* __restrict__ pj = pt + at(j * level + i, log_n, k);
 #pragma unroll
         for (uint32_t g = 0; g < PT_GT; ++g)
-            if (g < n_g) mac128(a[g], x, pj[g * pstep]);
+            if (g < n_g) a[g] += (u128)x * pj[g * pstep];
         if ((j & 7u) == 7u) {
 #pragma unroll
-            for (uint32_t g = 0; g < PT_GT; ++g) {
-                res[g] = add_mod(res[g], mont_redc(a[g].lo, a[g].hi, md.q, md.mont_neg_qinv), md.q);
-                a[g] = Acc128{0, 0};
-            }
+            for (uint32_t g = 0; g < PT_GT; ++g)
+                if (g < n_g) fold(g);
         }
     }
 #pragma unroll
     for (uint32_t g = 0; g < PT_GT; ++g)
-        if (g < n_g) w[off_acc + g * ct_words + o] = add_mod(res[g], mont_redc(a[g].lo, a[g].hi, md.q, md.mont_neg_qinv), md.q);
+        if (g < n_g) {
+            fold(g);
+            w[off_acc + g * ct_words + o] = res[g];
+        }
 }
 
 // out_z = in_z + c_z at X^0: in the evaluation domain the constant c_z[i]
