@@ -361,7 +361,10 @@ int pft_diagonals_encode(const pft_params* params, const double* M, uint32_t n_o
 int pft_ptmat_info(const pft_ptmat* m, uint32_t* info);
 void pft_ptmat_destroy(pft_ptmat* m);
 /* in: n_docs * n_in ciphertexts, document-major, all at the matrix level;
- * out: n_docs ciphertexts (caller memory, 2*level*N each). */
+ * out: n_docs ciphertexts (caller memory, 2*level*N each).  Scratch: the
+ * context's auxiliary device buffer grows to n_docs (n_in b + G + 1)
+ * ciphertexts at the matrix level (PFT_ENOMEM if it cannot, or if it would
+ * have to grow during graph capture). */
 int pft_ptmatvec(pft_ctx* ctx, const pft_ptmat* m, uint32_t n_docs, const pft_ct* in, pft_ct* out);
 
 /* ---- plaintext dot products with TotalSum (Sec. 4.1, column packing) -----
