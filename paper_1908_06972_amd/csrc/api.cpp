@@ -2747,9 +2747,9 @@ extern "C" int pft_ctmatvec(pft_ctx* c, uint32_t n_o, uint32_t n_i, uint32_t n_i
     const double scale = in[0].scale * diags[0].scale;
     const uint32_t lg = P->log_n;
     const uint64_t nl = (uint64_t)l * P->n, ct_words = 2 * nl;
-    // per document in aux: baby[n_in][b] | acc | tot | tmp
-    const uint64_t off_baby = 0, off_acc = (uint64_t)J * ct_words, off_tot = off_acc + ct_words,
-                   off_tmp = off_tot + ct_words, stride = off_tmp + ct_words;
+    // per document in aux: baby[n_in][b] | acc[G] (acc[0] collects the total) | tmp
+    const uint64_t off_baby = 0, off_acc = (uint64_t)J * ct_words, off_tot = off_acc,
+                   off_tmp = off_acc + (uint64_t)G * ct_words, stride = off_tmp + ct_words;
     if ((r = ensure_aux(c, (size_t)n_docs * stride * 8))) return r;
     // per document in ws: the summed tensor [3][l][N], then key switching
     const KsLayout K = ks_layout(P, l, 3 * nl);
@@ -2776,26 +2776,36 @@ extern "C" int pft_ctmatvec(pft_ctx* c, uint32_t n_o, uint32_t n_i, uint32_t n_i
             }
         if ((r = pft_rotate_batch(c, (uint32_t)src.size(), src.data(), (int32_t)rr, dst.data()))) return r;
     }
-    for (uint32_t g = 0; g < G; ++g) {
-        // the rotations of the previous giant step may have regrown ws
-        if ((r = ensure_ws(c, (size_t)std::min(n_docs, chunk) * K.end * 8))) return r;
-        const WsRef ws{c->ws, K.end};
+    // the tensor sums of several giant steps from one pass over the baby
+    // steps, each giant step then relinearised into acc[g]
+    const uint32_t gt = std::max(1u, std::min(ct_dot_multi_steps(), (uint32_t)PFT_MAX_ITEMS / J));
+    for (uint32_t g0 = 0; g0 < G; g0 += gt) {
+        const uint32_t n_g = std::min(gt, G - g0);
         ItemPtrs E{};
-        for (uint32_t cc = 0; cc < n_in; ++cc)
-            for (uint32_t rr = 0; rr < b; ++rr) E.p[cc * b + rr] = diags[((size_t)cc * G + g) * b + rr].data;
-        for (uint32_t z0 = 0; z0 < n_docs; z0 += chunk) {
-            const uint32_t cnt = std::min(chunk, n_docs - z0);
-            timed(c, PK_TENSOR, 8.0 * cnt * (2.0 * J * ct_words + 3.0 * nl) + 8.0 * J * ct_words,
-                  4.0 * cnt * J * nl, [&] {
-                      launch_ct_dot_b(cnt, E, J, WsRef{A + z0 * stride, stride}, off_baby, ct_words, ws, 0, l,
-                                      c->to_mont, c->tabs, lg, c->stream);
+        for (uint32_t g = 0; g < n_g; ++g)
+            for (uint32_t cc = 0; cc < n_in; ++cc)
+                for (uint32_t rr = 0; rr < b; ++rr)
+                    E.p[g * J + cc * b + rr] = diags[((size_t)cc * G + g0 + g) * b + rr].data;
+        // at most `chunk` key-switch items in the workspace, as one giant step at a time
+        const uint32_t zc = std::max(1u, chunk / n_g);
+        for (uint32_t z0 = 0; z0 < n_docs; z0 += zc) {
+            const uint32_t cnt = std::min(zc, n_docs - z0);
+            if ((r = ensure_ws(c, (size_t)n_g * cnt * K.end * 8))) return r;
+            const WsRef ws{c->ws, K.end};
+            timed(c, PK_TENSOR, 8.0 * cnt * (2.0 * J * ct_words + 3.0 * n_g * nl) + 8.0 * n_g * J * ct_words,
+                  4.0 * cnt * n_g * J * nl, [&] {
+                      launch_ct_dot_multi_b(cnt, E, J, n_g, WsRef{A + z0 * stride, stride}, off_baby, ct_words, ws, 0,
+                                            l, c->to_mont, c->tabs, lg, c->stream);
                   });
-            ItemPtrs O{};
-            for (uint32_t u = 0; u < cnt; ++u) O.p[u] = A + (z0 + u) * stride + (g == 0 ? off_tot : off_acc);
-            key_switch_b(c, cnt, ws, K, 2 * nl, c->rlk, 0, nl, O);
+            for (uint32_t g = 0; g < n_g; ++g) {
+                ItemPtrs O{};
+                for (uint32_t u = 0; u < cnt; ++u) O.p[u] = A + (z0 + u) * stride + off_acc + (g0 + g) * ct_words;
+                key_switch_b(c, cnt, WsRef{c->ws + (size_t)g * cnt * K.end, K.end}, K, 2 * nl, c->rlk, 0, nl, O);
+            }
         }
-        if (g == 0) continue;
-        std::vector<pft_ct> src = cts_at(A, stride, off_acc, n_docs, l, scale);
+    }
+    for (uint32_t g = 1; g < G; ++g) {
+        std::vector<pft_ct> src = cts_at(A, stride, off_acc + g * ct_words, n_docs, l, scale);
         std::vector<pft_ct> dst = cts_at(A, stride, off_tmp, n_docs, l, scale);
         if ((r = pft_rotate_batch(c, n_docs, src.data(), (int32_t)(g * b), dst.data()))) return r;
         for (uint32_t z0 = 0; z0 < n_docs; z0 += 65535) {

@@ -541,17 +541,20 @@ __global__ __launch_bounds__(TB) void k_add_const_b(ItemPtrs in, ItemPtrs out, c
     out.p[blockIdx.z][o] = v;
 }
 
-// HMUL tensors of one giant step of the encrypted-weight matrix-vector
-// product, summed over its J diagonal terms (Sec. 4.2, HMUL in place of
-// HMULPLAIN): d0 = sum e0 x0, d1 = sum (e0 x1 + e1 x0), d2 = sum e1 x1.  The
-// full 128-bit products are summed and brought back by a Montgomery
-// reduction every 8 diagonal terms (at most 16 products below q^2 each:
-// below q 2^64 for q < 2^60); the reductions' factor 2^-64 is undone once at
-// the end by a Shoup product with 2^64 mod q (to_mont).
-__global__ __launch_bounds__(TB) void k_ct_dot_b(ItemPtrs e, uint32_t J, WsRef xs, uint64_t off_x, uint64_t ct_words,
-                                                 WsRef ws, uint64_t off_d, uint32_t level,
-                                                 const DevMod* __restrict__ mods, const TwPair* __restrict__ to_mont,
-                                                 uint32_t log_n) {
+// HMUL tensors of the encrypted-weight matrix-vector product, summed over the
+// J diagonal terms of each of n_g <= CT_GT giant steps (Sec. 4.2, HMUL in
+// place of HMULPLAIN): d0 = sum e0 x0, d1 = sum (e0 x1 + e1 x0), d2 = sum
+// e1 x1.  Giant step g takes its diagonals from e.p[g J + j] and writes
+// [3][level][N] at item g n_items + z of ws + off_d; each baby residue is read
+// once for all of them.  The full 128-bit products are summed and brought
+// back by a Montgomery reduction every 8 diagonal terms (at most 16 products
+// below q^2 each: below q 2^64 for q < 2^60); the reductions' factor 2^-64
+// is undone once at the end by a Shoup product with 2^64 mod q (to_mont).
+constexpr uint32_t CT_GT = 4;
+__global__ __launch_bounds__(TB) void k_ct_dot_multi_b(ItemPtrs e, uint32_t J, uint32_t n_g, WsRef xs, uint64_t off_x,
+                                                       uint64_t ct_words, WsRef ws, uint32_t n_items, uint64_t off_d,
+                                                       uint32_t level, const DevMod* __restrict__ mods,
+                                                       const TwPair* __restrict__ to_mont, uint32_t log_n) {
     using u128 = unsigned __int128;
     const uint32_t k = blockIdx.x * TB + threadIdx.x;
     const uint32_t i = blockIdx.y;
@@ -559,33 +562,49 @@ __global__ __launch_bounds__(TB) void k_ct_dot_b(ItemPtrs e, uint32_t J, WsRef x
     const uint64_t q = md.q;
     const uint64_t* __restrict__ x = xs.base + (size_t)blockIdx.z * xs.stride + off_x;
     const size_t o0 = at(i, log_n, k), o1 = at(level + i, log_n, k);
-    u128 s0 = 0, s1 = 0, s2 = 0;
-    uint64_t d0 = 0, d1 = 0, d2 = 0;
-    auto fold = [&](u128& sv, uint64_t& dv) {
-        dv = add_mod(dv, mont_redc((uint64_t)sv, (uint64_t)(sv >> 64), q, md.mont_neg_qinv), q);
-        sv = 0;
+    u128 s[CT_GT][3];
+    uint64_t d[CT_GT][3];
+#pragma unroll
+    for (uint32_t g = 0; g < CT_GT; ++g)
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            s[g][t] = 0;
+            d[g][t] = 0;
+        }
+    auto fold = [&](uint32_t g) {
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            d[g][t] = add_mod(d[g][t], mont_redc((uint64_t)s[g][t], (uint64_t)(s[g][t] >> 64), q, md.mont_neg_qinv), q);
+            s[g][t] = 0;
+        }
     };
     for (uint32_t j = 0; j < J; ++j) {
-        const uint64_t* __restrict__ E = e.p[j];
-        const uint64_t e0 = E[o0], e1 = E[o1];
         const uint64_t x0 = x[j * ct_words + o0], x1 = x[j * ct_words + o1];
-        s0 += (u128)e0 * x0;
-        s1 += (u128)e0 * x1 + (u128)e1 * x0;
-        s2 += (u128)e1 * x1;
+#pragma unroll
+        for (uint32_t g = 0; g < CT_GT; ++g)
+            if (g < n_g) {
+                const uint64_t* __restrict__ E = e.p[g * J + j];
+                const uint64_t e0 = E[o0], e1 = E[o1];
+                s[g][0] += (u128)e0 * x0;
+                s[g][1] += (u128)e0 * x1 + (u128)e1 * x0;
+                s[g][2] += (u128)e1 * x1;
+            }
         if ((j & 7u) == 7u) {
-            fold(s0, d0);
-            fold(s1, d1);
-            fold(s2, d2);
+#pragma unroll
+            for (uint32_t g = 0; g < CT_GT; ++g)
+                if (g < n_g) fold(g);
         }
     }
-    fold(s0, d0);
-    fold(s1, d1);
-    fold(s2, d2);
     const TwPair r = to_mont[i];
-    uint64_t* __restrict__ d = ws_item(ws) + off_d;
-    d[o0] = shoup(d0, r.w, r.wp, q);
-    d[o1] = shoup(d1, r.w, r.wp, q);
-    d[at(2 * level + i, log_n, k)] = shoup(d2, r.w, r.wp, q);
+#pragma unroll
+    for (uint32_t g = 0; g < CT_GT; ++g)
+        if (g < n_g) {
+            fold(g);
+            uint64_t* __restrict__ dd = ws.base + (size_t)(g * n_items + blockIdx.z) * ws.stride + off_d;
+            dd[o0] = shoup(d[g][0], r.w, r.wp, q);
+            dd[o1] = shoup(d[g][1], r.w, r.wp, q);
+            dd[at(2 * level + i, log_n, k)] = shoup(d[g][2], r.w, r.wp, q);
+        }
 }
 
 // out_z[b][i] = in_z[b][i] * c_z[i] (Shoup pairs, [n][level] on the device):
@@ -717,11 +736,13 @@ void launch_add_const_b(uint32_t n, const ItemPtrs& in, const ItemPtrs& out, con
                        log_n);
 }
 
-void launch_ct_dot_b(uint32_t n, const ItemPtrs& e, uint32_t J, WsRef xs, uint64_t off_x, uint64_t ct_words, WsRef ws,
-                     uint64_t off_d, uint32_t level, const TwPair* to_mont, const DevTables& t, uint32_t log_n,
-                     hipStream_t st) {
-    hipLaunchKernelGGL(k_ct_dot_b, grid_nk(log_n, level, n), dim3(TB), 0, st, e, J, xs, off_x, ct_words, ws, off_d,
-                       level, t.mods, to_mont, log_n);
+uint32_t ct_dot_multi_steps() { return CT_GT; }
+
+void launch_ct_dot_multi_b(uint32_t n, const ItemPtrs& e, uint32_t J, uint32_t n_g, WsRef xs, uint64_t off_x,
+                           uint64_t ct_words, WsRef ws, uint64_t off_d, uint32_t level, const TwPair* to_mont,
+                           const DevTables& t, uint32_t log_n, hipStream_t st) {
+    hipLaunchKernelGGL(k_ct_dot_multi_b, grid_nk(log_n, level, n), dim3(TB), 0, st, e, J, n_g, xs, off_x, ct_words, ws,
+                       n, off_d, level, t.mods, to_mont, log_n);
 }
 
 void launch_scale_const_b(uint32_t n, const ItemPtrs& in, const ItemPtrs& out, const TwPair* consts, uint32_t level,

@@ -234,14 +234,16 @@ void launch_scale_const_b(uint32_t n, const ItemPtrs& in, const ItemPtrs& out, c
 // out_z = (in_z.c0 + consts[z][limb].w, in_z.c1): HADDPLAIN of a constant
 void launch_add_const_b(uint32_t n, const ItemPtrs& in, const ItemPtrs& out, const TwPair* consts, uint32_t level,
                         const DevTables& t, uint32_t log_n, hipStream_t st);
-// Encrypted-weight products of one giant step: for item z, the HMUL tensor
-// sum_j E_j (x) X_{z,j} into ws_z + off_d as [3][level][N], with E_j =
-// e.p[j] (ciphertexts shared by all items, [2][level][N]) and X_{z,j} at
-// ws_z + off_x + j ct_words.  J <= PFT_MAX_ITEMS.  to_mont: [L+K] 2^64 mod q
-// as Shoup pairs.
-void launch_ct_dot_b(uint32_t n, const ItemPtrs& e, uint32_t J, WsRef xs, uint64_t off_x, uint64_t ct_words, WsRef ws,
-                     uint64_t off_d, uint32_t level, const TwPair* to_mont, const DevTables& t, uint32_t log_n,
-                     hipStream_t st);
+// Encrypted-weight products of n_g <= ct_dot_multi_steps() giant steps (n_g
+// J <= PFT_MAX_ITEMS): for item z and giant step g, the HMUL tensor sum_j
+// E_{g,j} (x) X_{z,j} into ws item g n + z at off_d as [3][level][N], with
+// E_{g,j} = e.p[g J + j] (ciphertexts shared by all items, [2][level][N]) and
+// X_{z,j} at xs_z + off_x + j ct_words; each X_{z,j} is read once for all of
+// them.  to_mont: [L+K] 2^64 mod q as Shoup pairs.
+uint32_t ct_dot_multi_steps();
+void launch_ct_dot_multi_b(uint32_t n, const ItemPtrs& e, uint32_t J, uint32_t n_g, WsRef xs, uint64_t off_x,
+                           uint64_t ct_words, WsRef ws, uint64_t off_d, uint32_t level, const TwPair* to_mont,
+                           const DevTables& t, uint32_t log_n, hipStream_t st);
 
 // The fixed scratch of the allocation-free entry point (noalloc.hip): a
 // file-scope device array of PFT_NOALLOC_SCRATCH_BYTES per GPU.  Resolves
